@@ -1,0 +1,29 @@
+"""FP64 CPU oracle for incremental matrix-power views.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+link anything in this package: only the tests, the smoke check and the
+benchmark's CPU-baseline leg use it.  It shares no code with the HIP path;
+both sides take their inputs from the separate `synth` generators.
+
+Every function cites the passage of the LINVIEW paper (Nikolic, ElSeidy,
+Koch, "LINVIEW: Incremental View Maintenance for Complex Analytical
+Queries", arXiv 1403.6968) that it follows.  All arithmetic is float64.
+
+Pins (what fixes each function other than itself) are in
+`tests/test_oracle_pins.py`; every function here is pinned, none is
+"parity unpinned".
+"""
+
+from .linview_oracle import (  # noqa: F401
+    levels,
+    reeval,
+    incr_factors,
+    incr_update,
+    apply_updates,
+    power_rows,
+    power_cols,
+    brute_power,
+    maxrel,
+    deltarel,
+    OpCounter,
+)
