@@ -1,0 +1,175 @@
+/*
+ * linview.h -- C ABI of an MI355X (gfx950) library that keeps matrix-power
+ * views P = A^k current under low-rank updates of A.
+ *
+ * Method (LINVIEW, Nikolic, ElSeidy, Koch, arXiv 1403.6968):
+ *  - A view of A^k, k = 2^m, stores every power of the exponential model,
+ *    P_1 = A, P_2, P_4, ..., P_k with P_i = P_{i/2} P_{i/2}
+ *    (Table 1, "Exponential"; Sec. 5.2).  The library numbers them by level
+ *    j = 0..m, level j holding A^(2^j).
+ *  - An update Delta A = U V^T (Sec. 4.2, factored form) is propagated with
+ *    the compact two-block factors of Sec. 4.3 / App. A (exponential model):
+ *        U_{2i} = [U_i, P_i U_i + U_i (V_i^T U_i)],   V_{2i} = [P_i^T V_i, V_i]
+ *    computed from the OLD powers, after which every stored power takes
+ *    P_i += U_i V_i^T (the trigger of Sec. 4.4 assigns all factors first and
+ *    then applies all updates).
+ *  - Re-evaluation (ReevalExp, Sec. 5.2.2 "Re-evaluation") applies Delta A
+ *    and recomputes the m squarings with dense products.
+ *
+ * Conventions for every entry point:
+ *  - Matrices are dense, row-major, with a leading dimension (elements per
+ *    row) ld >= n.  Element type: double in LV_FP64 mode, float in LV_FP32
+ *    mode.  A, U, V and outputs use the view's element type.
+ *  - Device pointers unless stated otherwise.  `stream` is a hipStream_t
+ *    (NULL = the default stream).  All device work is enqueued on `stream`
+ *    and is asynchronous: the caller keeps inputs unchanged and outputs
+ *    unread until the stream has passed the call.
+ *  - Ownership: the caller owns A, U, V, every output buffer and the device
+ *    `workspace`; a view borrows its workspace for its lifetime.  The
+ *    library never allocates device memory.  The lv_view handle itself is
+ *    host memory owned by the library and freed by lv_view_destroy.
+ *  - Errors: every call returns an lv_status; no exception crosses the ABI.
+ *    On failure nothing has been enqueued unless the status is LV_EDEVICE.
+ *    lv_last_error() returns a message for the last failure on the calling
+ *    host thread.
+ *  - A view is not thread-safe; distinct views are independent.
+ */
+#ifndef LINVIEW_H
+#define LINVIEW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LV_OK = 0,
+  LV_EINVAL = 1,  /* bad argument: k not a power of two, n or r out of range,
+                     null pointer, ld < n, power not stored, ...            */
+  LV_ENOMEM = 2,  /* workspace too small or misaligned                       */
+  LV_EDEVICE = 3, /* a HIP runtime call or kernel launch failed              */
+  LV_ESTATE = 4   /* operation not valid for this view                       */
+} lv_status;
+
+typedef enum {
+  LV_FP64 = 0, /* double storage and arithmetic                           */
+  LV_FP32 = 1  /* float storage and arithmetic; creation and re-anchoring
+                  square in double and round once; Gram V^T U and the
+                  factor assembly are accumulated in double                */
+} lv_mode;
+
+typedef struct lv_view lv_view;
+
+typedef struct {
+  int64_t n;          /* matrix order                                      */
+  int64_t n_pad;      /* padded order used on the device                   */
+  int64_t ld;         /* leading dimension of the stored powers            */
+  int32_t k;          /* view power                                        */
+  int32_t levels;     /* m + 1 stored powers                               */
+  int32_t r_max;      /* largest update rank accepted                      */
+  int32_t mode;       /* lv_mode                                           */
+  int64_t updates;    /* updates applied since creation                    */
+  int64_t reanchors;  /* re-evaluations from the current A                 */
+  size_t footprint;   /* workspace bytes in use                            */
+} lv_stats;
+
+/* Human-readable name of a status code (static string). */
+const char* lv_status_str(lv_status s);
+
+/* Message for the last failed call on this host thread ("" if none). */
+const char* lv_last_error(void);
+
+/* Exact workspace size in bytes for a view of order n, power k and largest
+ * update rank r_max.  Returns 0 if the arguments are invalid (same rules as
+ * lv_view_create).  The layout is: the m + 1 stored powers (padded order),
+ * m + 1 factor slabs (U_j, V_j of every level), per-level reduction
+ * partials, and a double-precision squaring scratch (LV_FP32 only). */
+size_t lv_view_footprint(int64_t n, int k, int r_max, lv_mode mode);
+
+/* Create a view of A^k (Table 1 exponential model; ReevalExp).
+ *  A         n x n, leading dimension lda >= n (device).
+ *  k         power of two, 1 <= k <= 1024 (the paper assumes log2 k
+ *            integral, Table 1 caption).
+ *  r_max     largest rank of later updates, 1 <= r_max, k * r_max <= 4096.
+ *  workspace device buffer of ws_bytes >= lv_view_footprint(...), 256-byte
+ *            aligned; borrowed until lv_view_destroy.
+ *  out       receives the new handle (host).
+ * All stored powers are computed by repeated squaring in double precision
+ * on the device (MFMA) and then rounded once to the storage type. */
+lv_status lv_view_create(const void* A, int64_t n, int64_t lda, int k, int r_max,
+                         lv_mode mode, void* workspace, size_t ws_bytes,
+                         void* stream, lv_view** out);
+
+/* Apply one update Delta A = U V^T (IncrExp, App. A exponential model; the
+ * trigger of Sec. 4.4).
+ *  U, V      n x r (device), leading dimensions ldu, ldv >= r.
+ *  r         1 <= r <= r_max.
+ * After the stream passes the call every stored power equals the
+ * corresponding power of the updated A (up to rounding). */
+lv_status lv_view_update(lv_view* v, const void* U, const void* V, int64_t r,
+                         int64_t ldu, int64_t ldv, void* stream);
+
+/* Apply `count` updates in order, (U_t, V_t) = (U + t*strideU, V + t*strideV)
+ * for t = 0..count-1 (strides in elements).  The result equals `count`
+ * calls of lv_view_update, bit for bit.  count >= 0. */
+lv_status lv_view_update_batch(lv_view* v, const void* U, const void* V, int64_t r,
+                               int64_t count, int64_t ldu, int64_t ldv,
+                               int64_t strideU, int64_t strideV, void* stream);
+
+/* Copy stored power A^power (power in {1, 2, 4, ..., k}) to out (n x n,
+ * leading dimension ldo >= n, device). */
+lv_status lv_view_read(const lv_view* v, int power, void* out, int64_t ldo, void* stream);
+
+/* Borrowed device pointer to stored power A^power and its leading
+ * dimension (written to *ld if ld is non-null); NULL if power is not
+ * stored.  Valid until the next update, re-anchor or destroy. */
+const void* lv_view_data(const lv_view* v, int power, int64_t* ld);
+
+/* Recompute every stored power from the current A (= the stored P_1) by
+ * repeated squaring in double precision, discarding accumulated rounding. */
+lv_status lv_view_reanchor(lv_view* v, void* stream);
+
+/* Per-kernel timing of a view's updates (diagnostics).  While enabled, the
+ * library brackets every level-pass launch with HIP events recorded on the
+ * update's stream; lv_view_timing waits for those events, returns the
+ * accumulated device time per kernel kind and clears the accumulators.
+ * Enabling adds one event pair per launch to the stream. */
+typedef struct {
+  double fused_ms;        /* fused level passes (levels 0..m-1)            */
+  int64_t fused_launches;
+  double tail_ms;         /* reductions and factor assembly                */
+  int64_t tail_launches;
+  double top_ms;          /* update-only pass of the top stored power      */
+  int64_t top_launches;
+} lv_timing;
+
+lv_status lv_view_set_timing(lv_view* v, int enable);
+lv_status lv_view_timing(lv_view* v, lv_timing* out);
+
+/* Counters and shape of a view (host). */
+lv_status lv_view_stats(const lv_view* v, lv_stats* out);
+
+/* Release the handle (the caller frees the workspace afterwards, once the
+ * stream has drained).  NULL is ignored. */
+void lv_view_destroy(lv_view* v);
+
+/* Workspace bytes for lv_reeval at order n; 0 if invalid. */
+size_t lv_reeval_footprint(int64_t n, int r_max, lv_mode mode);
+
+/* Re-evaluation baseline (ReevalExp, Sec. 5.2.2): out = (A + U V^T)^k
+ * computed as one rank-r update and m = log2 k dense squarings in the
+ * mode's own precision (MFMA).  A: n x n (lda); U, V: n x r (ldu, ldv);
+ * out: n x n (ldo).  A is not modified.  r = 0 skips the update (U, V
+ * may then be NULL). */
+lv_status lv_reeval(const void* A, int64_t n, int64_t lda, int k,
+                    const void* U, const void* V, int64_t r, int64_t ldu, int64_t ldv,
+                    lv_mode mode, void* out, int64_t ldo,
+                    void* workspace, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LINVIEW_H */

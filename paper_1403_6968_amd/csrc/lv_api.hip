@@ -1,0 +1,473 @@
+// C ABI of liblinview: argument validation, workspace layout, and the order
+// of kernel launches for view creation, updates, re-anchoring and the
+// re-evaluation baseline.
+#include "linview.h"
+#include "lv_internal.h"
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+using namespace lv;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+lv_status fail(lv_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+int ilog2(int64_t x) { int m = 0; while ((int64_t(1) << m) < x) ++m; return m; }
+int64_t next_pow2(int64_t x) { int64_t p = 1; while (p < x) p <<= 1; return p; }
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kMaxOrder = 65536;
+constexpr int kMaxK = 1024;
+constexpr int kMaxWidth = 256;   // k * r_pad: width of the top-level factors
+constexpr int kTileRows = 512;   // rows per tile of the fused level pass
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  int64_t n_pad = 0, ldp = 0;
+  int m = 0, r_pad = 0, W = 0, elem = 0, nct = 0, nrt = 0, tile_rows = 0;
+  size_t P[kMaxLevel + 1] = {};
+  size_t slabU[kMaxLevel + 1] = {};
+  size_t slabV[kMaxLevel + 1] = {};
+  size_t partX[kMaxLevel] = {};
+  size_t partY[kMaxLevel] = {};
+  size_t partG[kMaxLevel] = {};
+  size_t scratch[2] = {};
+  size_t total = 0;
+};
+
+lv_status check_shape(int64_t n, int k, int r_max, lv_mode mode) {
+  if (mode != LV_FP64 && mode != LV_FP32) return fail(LV_EINVAL, "unknown mode %d", (int)mode);
+  if (n < 1 || n > kMaxOrder) return fail(LV_EINVAL, "n = %lld outside [1, %lld]", (long long)n, (long long)kMaxOrder);
+  if (!is_pow2(k) || k > kMaxK) return fail(LV_EINVAL, "k = %d is not a power of two in [1, %d]", k, kMaxK);
+  if (r_max < 1) return fail(LV_EINVAL, "r_max = %d < 1", r_max);
+  const int64_t width = (int64_t)k * next_pow2(r_max);
+  if (width > kMaxWidth)
+    return fail(LV_EINVAL, "k * r_max (rounded up to a power of two) = %lld exceeds %d", (long long)width, kMaxWidth);
+  if (k > 1 && width / 2 > kMaxFusedRank)
+    return fail(LV_EINVAL, "level rank %lld exceeds the fused pass limit %d", (long long)(width / 2), kMaxFusedRank);
+  return LV_OK;
+}
+
+Layout make_layout(int64_t n, int k, int r_max, lv_mode mode) {
+  Layout L;
+  L.elem = mode == LV_FP64 ? 8 : 4;
+  L.n_pad = round_up(n, kPadOrder);
+  L.ldp = L.n_pad;
+  L.m = ilog2(k);
+  L.r_pad = (int)next_pow2(r_max);
+  L.W = k * L.r_pad;
+  L.tile_rows = kTileRows;
+  L.nct = (int)(L.n_pad / tile_cols_bytes(L.elem));
+  L.nrt = (int)((L.n_pad + L.tile_rows - 1) / L.tile_rows);
+  size_t off = 0;
+  const size_t mat = (size_t)L.n_pad * L.ldp * L.elem;
+  for (int j = 0; j <= L.m; ++j) { L.P[j] = off; off = align_up(off + mat); }
+  const size_t slab = (size_t)L.n_pad * L.W * L.elem;
+  for (int j = 0; j <= L.m; ++j) {
+    L.slabU[j] = off; off = align_up(off + slab);
+    L.slabV[j] = off; off = align_up(off + slab);
+  }
+  for (int j = 0; j < L.m; ++j) {
+    const size_t R = (size_t)L.r_pad << j;
+    L.partX[j] = off; off = align_up(off + (size_t)L.nct * L.n_pad * R * L.elem);
+    L.partY[j] = off; off = align_up(off + (size_t)L.nrt * L.n_pad * R * L.elem);
+    L.partG[j] = off; off = align_up(off + (size_t)L.nrt * R * R * sizeof(double));
+  }
+  if (mode == LV_FP32 && L.m > 0) {
+    const size_t dmat = (size_t)L.n_pad * L.n_pad * sizeof(double);
+    L.scratch[0] = off; off = align_up(off + dmat);
+    L.scratch[1] = off; off = align_up(off + dmat);
+  }
+  L.total = off;
+  return L;
+}
+
+lv_status hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return LV_OK;
+  return fail(LV_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace
+
+struct lv_view {
+  int64_t n;
+  int k;
+  int r_max;
+  lv_mode mode;
+  Layout L;
+  char* base;
+  size_t ws_bytes;
+  int64_t updates;
+  int64_t reanchors;
+
+  // Kernel timing (diagnostics): event pairs per launch kind, resolved by
+  // lv_view_timing.
+  bool timing = false;
+  struct Pair { hipEvent_t a, b; int kind; };
+  std::vector<Pair> pending;
+  std::vector<hipEvent_t> pool;
+
+  template <typename T> T* P(int j) const { return reinterpret_cast<T*>(base + L.P[j]); }
+  template <typename T> T* slabU(int s) const { return reinterpret_cast<T*>(base + L.slabU[s]); }
+  template <typename T> T* slabV(int s) const { return reinterpret_cast<T*>(base + L.slabV[s]); }
+  template <typename T> T* partX(int j) const { return reinterpret_cast<T*>(base + L.partX[j]); }
+  template <typename T> T* partY(int j) const { return reinterpret_cast<T*>(base + L.partY[j]); }
+  double* partG(int j) const { return reinterpret_cast<double*>(base + L.partG[j]); }
+  double* scratch(int i) const { return reinterpret_cast<double*>(base + L.scratch[i]); }
+};
+
+namespace {
+
+// Stored powers P_1..P_m from P_0 by repeated squaring in double precision
+// (Table 1, exponential model), then one rounding to the storage type.
+template <typename T>
+lv_status build_chain(lv_view* v, hipStream_t s) {
+  const Layout& L = v->L;
+  if (L.m == 0) return LV_OK;
+  if constexpr (sizeof(T) == 8) {
+    for (int j = 1; j <= L.m; ++j) {
+      lv_status st = hip_check(launch_gemm<double>(v->P<double>(j - 1), L.ldp, v->P<double>(j - 1), L.ldp,
+                                                   v->P<double>(j), L.ldp, L.n_pad, s), "gemm f64");
+      if (st != LV_OK) return st;
+    }
+  } else {
+    lv_status st = hip_check(launch_copy_pad<float, double>(v->P<float>(0), L.ldp, L.n_pad, v->scratch(0),
+                                                            L.n_pad, L.n_pad, s), "widen P_1");
+    if (st != LV_OK) return st;
+    for (int j = 1; j <= L.m; ++j) {
+      double* src = v->scratch((j - 1) & 1);
+      double* dst = v->scratch(j & 1);
+      st = hip_check(launch_gemm<double>(src, L.n_pad, src, L.n_pad, dst, L.n_pad, L.n_pad, s), "gemm f64");
+      if (st != LV_OK) return st;
+      st = hip_check(launch_copy_pad<double, float>(dst, L.n_pad, L.n_pad, v->P<float>(j), L.ldp, L.n_pad, s),
+                     "round P");
+      if (st != LV_OK) return st;
+    }
+  }
+  return LV_OK;
+}
+
+hipEvent_t take_event(lv_view* v) {
+  if (!v->pool.empty()) { hipEvent_t e = v->pool.back(); v->pool.pop_back(); return e; }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Runs `launch` and, when timing is on, brackets it with an event pair of
+// the given kind (0 fused, 1 tail, 2 top update).
+template <typename F>
+lv_status timed(lv_view* v, int kind, hipStream_t s, const char* what, F&& launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (v->timing) {
+    a = take_event(v);
+    b = take_event(v);
+    if (!a || !b) return fail(LV_EDEVICE, "hipEventCreate failed");
+    if (hipEventRecord(a, s) != hipSuccess) return fail(LV_EDEVICE, "hipEventRecord failed");
+  }
+  lv_status st = hip_check(launch(), what);
+  if (st != LV_OK) return st;
+  if (v->timing) {
+    if (hipEventRecord(b, s) != hipSuccess) return fail(LV_EDEVICE, "hipEventRecord failed");
+    v->pending.push_back({a, b, kind});
+  }
+  return LV_OK;
+}
+
+// One update through every level, factors in slab `sl` (App. A exponential
+// model; trigger of Sec. 4.4): levels 0..m-1 run the fused pass and the tail,
+// the top level the update-only pass.
+template <typename T>
+lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int64_t ldv, int sl,
+                     hipStream_t s) {
+  const Layout& L = v->L;
+  const int r_pad = (int)next_pow2(r);
+  T* sU = v->slabU<T>(sl);
+  T* sV = v->slabV<T>(sl);
+  lv_status st = hip_check(launch_prep<T>(U, ldu, V, ldv, v->n, r, r_pad, sU, sV, L.W, L.n_pad, s), "prep");
+  if (st != LV_OK) return st;
+  for (int j = 0; j < L.m; ++j) {
+    const int R = r_pad << j;
+    st = timed(v, 0, s, "level pass", [&] {
+      return launch_level_fused<T>(R, v->P<T>(j), L.ldp, L.n_pad, L.tile_rows, sU, sV, L.W, v->partX<T>(j),
+                                   v->partY<T>(j), v->partG(j), s);
+    });
+    if (st != LV_OK) return st;
+    st = timed(v, 1, s, "level tail", [&] {
+      return launch_level_tail<T>(R, v->partX<T>(j), v->partY<T>(j), v->partG(j), L.nct, L.nrt, L.n_pad, sU,
+                                  sV, L.W, s);
+    });
+    if (st != LV_OK) return st;
+  }
+  const int Rm = r_pad << L.m;
+  return timed(v, 2, s, "top update", [&] {
+    return launch_level_update<T>(Rm, v->P<T>(L.m), L.ldp, L.n_pad, sU, sV, L.W, s);
+  });
+}
+
+// ---------------------------------------------------------------- re-evaluation
+//
+// Workspace: two n_pad x n_pad ping-pong matrices and one factor slab pair
+// (n_pad x r_pad each).
+
+size_t reeval_bytes(int64_t n_pad, int r_pad, int elem) {
+  return 2 * align_up((size_t)n_pad * n_pad * elem) + 2 * align_up((size_t)n_pad * r_pad * elem);
+}
+
+template <typename T>
+lv_status reeval_impl(const T* A, int64_t n, int64_t lda, int k, const T* U, const T* V, int r,
+                             int64_t ldu, int64_t ldv, T* out, int64_t ldo, char* ws, hipStream_t s) {
+  const int64_t n_pad = round_up(n, kPadOrder);
+  const int r_pad = (int)next_pow2(r < 1 ? 1 : r);
+  const size_t mat = align_up((size_t)n_pad * n_pad * sizeof(T));
+  T* buf[2] = {reinterpret_cast<T*>(ws), reinterpret_cast<T*>(ws + mat)};
+  T* sU = reinterpret_cast<T*>(ws + 2 * mat);
+  T* sV = reinterpret_cast<T*>(ws + 2 * mat + align_up((size_t)n_pad * r_pad * sizeof(T)));
+  lv_status st = hip_check(launch_copy_pad<T, T>(A, lda, n, buf[0], n_pad, n_pad, s), "copy A");
+  if (st != LV_OK) return st;
+  if (r > 0) {
+    st = hip_check(launch_prep<T>(U, ldu, V, ldv, n, r, r_pad, sU, sV, r_pad, n_pad, s), "prep");
+    if (st != LV_OK) return st;
+    st = hip_check(launch_level_update<T>(r_pad, buf[0], n_pad, n_pad, sU, sV, r_pad, s), "A += U V^T");
+    if (st != LV_OK) return st;
+  }
+  int cur = 0;
+  for (int j = 1; (1 << j) <= k; ++j) {
+    st = hip_check(launch_gemm<T>(buf[cur], n_pad, buf[cur], n_pad, buf[cur ^ 1], n_pad, n_pad, s), "gemm");
+    if (st != LV_OK) return st;
+    cur ^= 1;
+  }
+  return hip_check(hipMemcpy2DAsync(out, ldo * sizeof(T), buf[cur], n_pad * sizeof(T), n * sizeof(T), n,
+                                    hipMemcpyDeviceToDevice, s), "copy out");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lv_status_str(lv_status s) {
+  switch (s) {
+    case LV_OK: return "LV_OK";
+    case LV_EINVAL: return "LV_EINVAL";
+    case LV_ENOMEM: return "LV_ENOMEM";
+    case LV_EDEVICE: return "LV_EDEVICE";
+    case LV_ESTATE: return "LV_ESTATE";
+  }
+  return "LV_UNKNOWN";
+}
+
+const char* lv_last_error(void) { return g_err; }
+
+size_t lv_view_footprint(int64_t n, int k, int r_max, lv_mode mode) {
+  if (check_shape(n, k, r_max, mode) != LV_OK) return 0;
+  return make_layout(n, k, r_max, mode).total;
+}
+
+lv_status lv_view_create(const void* A, int64_t n, int64_t lda, int k, int r_max, lv_mode mode,
+                         void* workspace, size_t ws_bytes, void* stream, lv_view** out) {
+  g_err[0] = 0;
+  if (!out) return fail(LV_EINVAL, "out is NULL");
+  *out = nullptr;
+  lv_status st = check_shape(n, k, r_max, mode);
+  if (st != LV_OK) return st;
+  if (!A || !workspace) return fail(LV_EINVAL, "A or workspace is NULL");
+  if (lda < n) return fail(LV_EINVAL, "lda = %lld < n = %lld", (long long)lda, (long long)n);
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+    return fail(LV_ENOMEM, "workspace is not %zu-byte aligned", kAlign);
+  const Layout L = make_layout(n, k, r_max, mode);
+  if (ws_bytes < L.total)
+    return fail(LV_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+  lv_view* v = new (std::nothrow) lv_view();
+  if (!v) return fail(LV_ENOMEM, "host allocation of the view handle failed");
+  v->n = n; v->k = k; v->r_max = r_max; v->mode = mode; v->L = L;
+  v->base = static_cast<char*>(workspace); v->ws_bytes = ws_bytes;
+  v->updates = 0; v->reanchors = 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (mode == LV_FP64) {
+    st = hip_check(launch_copy_pad<double, double>(static_cast<const double*>(A), lda, n, v->P<double>(0),
+                                                   L.ldp, L.n_pad, s), "copy A");
+    if (st == LV_OK) st = build_chain<double>(v, s);
+  } else {
+    st = hip_check(launch_copy_pad<float, float>(static_cast<const float*>(A), lda, n, v->P<float>(0),
+                                                 L.ldp, L.n_pad, s), "copy A");
+    if (st == LV_OK) st = build_chain<float>(v, s);
+  }
+  if (st != LV_OK) { delete v; return st; }
+  *out = v;
+  return LV_OK;
+}
+
+static lv_status check_update_args(const lv_view* v, const void* U, const void* V, int64_t r,
+                                   int64_t ldu, int64_t ldv) {
+  if (!v) return fail(LV_EINVAL, "view is NULL");
+  if (!U || !V) return fail(LV_EINVAL, "U or V is NULL");
+  if (r < 1 || r > v->r_max) return fail(LV_EINVAL, "rank r = %lld outside [1, %d]", (long long)r, v->r_max);
+  if (ldu < r || ldv < r) return fail(LV_EINVAL, "ldu/ldv smaller than r");
+  return LV_OK;
+}
+
+lv_status lv_view_update(lv_view* v, const void* U, const void* V, int64_t r, int64_t ldu,
+                         int64_t ldv, void* stream) {
+  g_err[0] = 0;
+  lv_status st = check_update_args(v, U, V, r, ldu, ldv);
+  if (st != LV_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  st = v->mode == LV_FP64
+           ? update_one<double>(v, static_cast<const double*>(U), static_cast<const double*>(V), (int)r, ldu, ldv, 0, s)
+           : update_one<float>(v, static_cast<const float*>(U), static_cast<const float*>(V), (int)r, ldu, ldv, 0, s);
+  if (st == LV_OK) v->updates += 1;
+  return st;
+}
+
+lv_status lv_view_update_batch(lv_view* v, const void* U, const void* V, int64_t r, int64_t count,
+                               int64_t ldu, int64_t ldv, int64_t strideU, int64_t strideV,
+                               void* stream) {
+  g_err[0] = 0;
+  if (count < 0) return fail(LV_EINVAL, "count < 0");
+  if (count == 0) return v ? LV_OK : fail(LV_EINVAL, "view is NULL");
+  lv_status st = check_update_args(v, U, V, r, ldu, ldv);
+  if (st != LV_OK) return st;
+  if (count > 1 && (strideU < v->n * ldu || strideV < v->n * ldv))
+    return fail(LV_EINVAL, "strides smaller than one n x r factor");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t es = v->L.elem;
+  for (int64_t t = 0; t < count; ++t) {
+    const char* Ut = static_cast<const char*>(U) + (size_t)(t * strideU) * es;
+    const char* Vt = static_cast<const char*>(V) + (size_t)(t * strideV) * es;
+    st = v->mode == LV_FP64
+             ? update_one<double>(v, reinterpret_cast<const double*>(Ut), reinterpret_cast<const double*>(Vt), (int)r, ldu, ldv, 0, s)
+             : update_one<float>(v, reinterpret_cast<const float*>(Ut), reinterpret_cast<const float*>(Vt), (int)r, ldu, ldv, 0, s);
+    if (st != LV_OK) return st;
+    v->updates += 1;
+  }
+  return LV_OK;
+}
+
+static int power_level(const lv_view* v, int power) {
+  if (!v || !is_pow2(power) || power > v->k) return -1;
+  return ilog2(power);
+}
+
+lv_status lv_view_read(const lv_view* v, int power, void* out, int64_t ldo, void* stream) {
+  g_err[0] = 0;
+  const int j = power_level(v, power);
+  if (j < 0) return fail(LV_EINVAL, "power %d is not stored", power);
+  if (!out) return fail(LV_EINVAL, "out is NULL");
+  if (ldo < v->n) return fail(LV_EINVAL, "ldo < n");
+  const size_t es = v->L.elem;
+  const char* src = v->base + v->L.P[j];
+  return hip_check(hipMemcpy2DAsync(out, ldo * es, src, v->L.ldp * es, v->n * es, v->n,
+                                    hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)),
+                   "read");
+}
+
+const void* lv_view_data(const lv_view* v, int power, int64_t* ld) {
+  const int j = power_level(v, power);
+  if (j < 0) return nullptr;
+  if (ld) *ld = v->L.ldp;
+  return v->base + v->L.P[j];
+}
+
+lv_status lv_view_reanchor(lv_view* v, void* stream) {
+  g_err[0] = 0;
+  if (!v) return fail(LV_EINVAL, "view is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  lv_status st = v->mode == LV_FP64 ? build_chain<double>(v, s) : build_chain<float>(v, s);
+  if (st == LV_OK) v->reanchors += 1;
+  return st;
+}
+
+lv_status lv_view_stats(const lv_view* v, lv_stats* out) {
+  if (!v || !out) return fail(LV_EINVAL, "view or out is NULL");
+  out->n = v->n;
+  out->n_pad = v->L.n_pad;
+  out->ld = v->L.ldp;
+  out->k = v->k;
+  out->levels = v->L.m + 1;
+  out->r_max = v->r_max;
+  out->mode = (int32_t)v->mode;
+  out->updates = v->updates;
+  out->reanchors = v->reanchors;
+  out->footprint = v->L.total;
+  return LV_OK;
+}
+
+lv_status lv_view_set_timing(lv_view* v, int enable) {
+  if (!v) return fail(LV_EINVAL, "view is NULL");
+  v->timing = enable != 0;
+  return LV_OK;
+}
+
+lv_status lv_view_timing(lv_view* v, lv_timing* out) {
+  if (!v || !out) return fail(LV_EINVAL, "view or out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  lv_status st = LV_OK;
+  for (auto& p : v->pending) {
+    float ms = 0.f;
+    if (st == LV_OK) {
+      if (hipEventSynchronize(p.b) != hipSuccess || hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess)
+        st = fail(LV_EDEVICE, "event timing failed");
+    }
+    if (p.kind == 0) { out->fused_ms += ms; out->fused_launches += 1; }
+    else if (p.kind == 1) { out->tail_ms += ms; out->tail_launches += 1; }
+    else { out->top_ms += ms; out->top_launches += 1; }
+    v->pool.push_back(p.a);
+    v->pool.push_back(p.b);
+  }
+  v->pending.clear();
+  return st;
+}
+
+void lv_view_destroy(lv_view* v) {
+  if (!v) return;
+  for (auto& p : v->pending) { v->pool.push_back(p.a); v->pool.push_back(p.b); }
+  for (hipEvent_t e : v->pool) hipEventDestroy(e);
+  delete v;
+}
+
+size_t lv_reeval_footprint(int64_t n, int r_max, lv_mode mode) {
+  if (mode != LV_FP64 && mode != LV_FP32) return 0;
+  if (n < 1 || n > kMaxOrder || r_max < 0 || r_max > kMaxWidth) return 0;
+  return reeval_bytes(round_up(n, kPadOrder), (int)next_pow2(r_max < 1 ? 1 : r_max), mode == LV_FP64 ? 8 : 4);
+}
+
+lv_status lv_reeval(const void* A, int64_t n, int64_t lda, int k, const void* U, const void* V, int64_t r,
+                    int64_t ldu, int64_t ldv, lv_mode mode, void* out, int64_t ldo, void* workspace,
+                    size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  if (mode != LV_FP64 && mode != LV_FP32) return fail(LV_EINVAL, "unknown mode %d", (int)mode);
+  if (n < 1 || n > kMaxOrder) return fail(LV_EINVAL, "n out of range");
+  if (!is_pow2(k) || k > kMaxK) return fail(LV_EINVAL, "k = %d is not a power of two in [1, %d]", k, kMaxK);
+  if (r < 0 || r > kMaxWidth) return fail(LV_EINVAL, "r out of range");
+  if (!A || !out || !workspace) return fail(LV_EINVAL, "NULL pointer");
+  if (r > 0 && (!U || !V || ldu < r || ldv < r)) return fail(LV_EINVAL, "bad U/V");
+  if (lda < n || ldo < n) return fail(LV_EINVAL, "lda/ldo < n");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(LV_ENOMEM, "workspace misaligned");
+  const size_t need = lv_reeval_footprint(n, (int)r, mode);
+  if (ws_bytes < need) return fail(LV_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  if (mode == LV_FP64)
+    return reeval_impl<double>(static_cast<const double*>(A), n, lda, k, static_cast<const double*>(U),
+                               static_cast<const double*>(V), (int)r, ldu, ldv, static_cast<double*>(out), ldo,
+                               ws, s);
+  return reeval_impl<float>(static_cast<const float*>(A), n, lda, k, static_cast<const float*>(U),
+                            static_cast<const float*>(V), (int)r, ldu, ldv, static_cast<float*>(out), ldo, ws,
+                            s);
+}
+
+}  // extern "C"

@@ -1,0 +1,71 @@
+// Internal declarations shared by the HIP translation units of liblinview.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace lv {
+
+// Every stored power is padded to a multiple of this order; the padding
+// rows and columns hold zeros and stay zero under every operation (a zero
+// row of P_j or U_j produces zero rows of every product), so no kernel needs
+// bounds checks.
+constexpr int kPadOrder = 256;
+// Rows per chunk in the fused level pass (one LDS-resident chunk of a tile).
+constexpr int kChunkRows = 64;
+// Rows handled by one tail work-group.
+constexpr int kTailRows = 64;
+// Largest rank handled by the register-resident fused pass.
+constexpr int kMaxFusedRank = 16;
+// Largest level of the exponential model (k <= 2^kMaxLevel).
+constexpr int kMaxLevel = 10;
+
+inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Columns covered by one tile of the level pass: a wave reads a 1 KiB row
+// segment with one 16-byte vector per lane.
+template <typename T> constexpr int tile_cols() { return 64 * (16 / (int)sizeof(T)); }
+inline int tile_cols_bytes(int elem) { return 64 * (16 / elem); }
+
+// ---- launchers (stream-ordered; return the launch status) ----
+
+// dst[i*ldd + j] = (i < n && j < n) ? src[i*lds + j] : 0 for i, j < n_pad.
+template <typename Tin, typename Tout>
+hipError_t launch_copy_pad(const Tin* src, int64_t lds, int64_t n, Tout* dst, int64_t ldd,
+                           int64_t n_pad, hipStream_t s);
+
+// Factor slab set-up: slab U columns [0, r_pad) and slab V columns
+// [W - r_pad, W) receive U and V (n x r), zero-filled up to r_pad columns and
+// n_pad rows.
+template <typename T>
+hipError_t launch_prep(const T* U, int64_t ldu, const T* V, int64_t ldv, int64_t n, int r,
+                       int r_pad, T* slabU, T* slabV, int W, int64_t n_pad, hipStream_t s);
+
+// Fused level pass for level rank R: partial X = P U_j, partial Y = P^T V_j,
+// partial Gram V_j^T U_j (column tile 0 only), and P += U_j V_j^T, in one
+// read and one write of P.
+template <typename T>
+hipError_t launch_level_fused(int R, T* P, int64_t ldp, int64_t n_pad, int tile_rows,
+                              const T* slabU, const T* slabV, int W, T* partX, T* partY,
+                              double* partG, hipStream_t s);
+
+// Tail of level j: reduce partials in a fixed order, G = sum of partial
+// Grams, U_{j+1} = [U_j, X + U_j G], V_{j+1} = [Y, V_j].
+template <typename T>
+hipError_t launch_level_tail(int R, const T* partX, const T* partY, const double* partG,
+                             int nct, int nrt, int64_t n_pad, T* slabU, T* slabV, int W,
+                             hipStream_t s);
+
+// Update-only pass: P += U_j V_j^T for rank R (the top stored power).
+template <typename T>
+hipError_t launch_level_update(int R, T* P, int64_t ldp, int64_t n_pad, const T* slabU,
+                               const T* slabV, int W, hipStream_t s);
+
+// C = A * B for n_pad x n_pad row-major matrices (n_pad a multiple of 256),
+// on MFMA (double: 16x16x4 f64; float: 32x32x2 f32).
+template <typename T>
+hipError_t launch_gemm(const T* A, int64_t lda, const T* B, int64_t ldb, T* C, int64_t ldc,
+                       int64_t n_pad, hipStream_t s);
+
+}  // namespace lv

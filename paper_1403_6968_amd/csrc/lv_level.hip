@@ -1,0 +1,402 @@
+// Level kernels of the IncrExp update (LINVIEW, App. A exponential model).
+//
+// For one level j of the exponential model the update needs, with the OLD
+// stored power P = A^(2^j) and the level factors U_j, V_j (n x R, R = 2^j r):
+//     X = P U_j,   Y = P^T V_j,   G = V_j^T U_j,   P += U_j V_j^T
+// and then U_{j+1} = [U_j, X + U_j G], V_{j+1} = [Y, V_j]  (Sec. 4.3, App. A).
+//
+// k_level_fused does the first four in ONE read and ONE write of P: a tile of
+// P is streamed through registers once; Y and the rank-R update use the
+// coalesced row-segment layout directly, and the old values go through LDS
+// so that X can be formed with one row per lane (no cross-lane reductions).
+// Each tile writes partial X / Y (and the column-tile-0 tiles partial Grams);
+// k_level_tail reduces them in a fixed order (deterministic, no float
+// atomics) and assembles the next level's factors.  k_level_update is the
+// update-only pass of the top stored power.
+//
+// Layouts (all row-major):
+//   P        n_pad x ldp, zero padding beyond n.
+//   slab U   n_pad x W; U_j = columns [0, R).
+//   slab V   n_pad x W; V_j = columns [W - R, W)  (callers pass the offset base).
+//   partX    [nct][n_pad][R]   (nct = n_pad / TC column tiles)
+//   partY    [nrt][n_pad][R]   (nrt row tiles)
+//   partG    [nrt][R][R] double
+#include "lv_internal.h"
+
+namespace lv {
+namespace {
+
+// 16-byte vector of T held as an array.
+template <typename T> struct alignas(16) V16 { T v[16 / sizeof(T)]; };
+
+template <typename T> __device__ __forceinline__ V16<T> ld16(const T* p) {
+  return *reinterpret_cast<const V16<T>*>(p);
+}
+template <typename T> __device__ __forceinline__ void st16(T* p, const V16<T>& x) {
+  *reinterpret_cast<V16<T>*>(p) = x;
+}
+
+__device__ __forceinline__ int wave_id() {
+  return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+// ---------------------------------------------------------------- fused pass
+//
+// Block: 256 threads (4 waves).  Tile: tile_rows x TC, TC = 64 lanes x 16 B.
+// Per 64-row chunk:
+//   Phase A  wave w takes rows w*16 .. w*16+15 of the chunk, one 16-byte
+//            vector per lane per row: Y partial (yacc, per-lane columns),
+//            old values to LDS, P + U_j V_j^T back to HBM.
+//   Phase B  wave w takes the w-th quarter of the tile's columns and lane l
+//            the l-th row of the chunk: x[c] = sum over the quarter of
+//            P_old[row][col] * U_j[col][c] with U_j rows broadcast through the
+//            scalar unit; the four quarters are summed in LDS and one partial
+//            per (row, tile column) is written.
+template <typename T, int R>
+__global__ void __launch_bounds__(256)
+k_level_fused(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
+              const T* __restrict__ Uj, const T* __restrict__ Vj, int W,
+              T* __restrict__ partX, T* __restrict__ partY, double* __restrict__ partG) {
+  constexpr int EPL = 16 / (int)sizeof(T);
+  constexpr int TC = 64 * EPL;
+  constexpr int CR = kChunkRows;
+  constexpr int RPW = CR / 4;
+  constexpr int QW = TC / 4;
+  constexpr int LDSW = TC + EPL;
+  static_assert(4 * TC * R <= CR * LDSW, "Y reduction buffer must fit in the tile buffer");
+
+  __shared__ __align__(16) T tileP[CR * LDSW];
+  __shared__ T xq[4 * CR * R];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = wave_id();
+  const int ct = blockIdx.x;
+  const int rt = blockIdx.y;
+  const int col0 = ct * TC;
+  const int row0 = rt * tile_rows;
+  const int nrows = min(tile_rows, n_pad - row0);
+  const int nchunks = nrows / CR;
+  const int lc = col0 + lane * EPL;
+
+  T vcol[EPL][R];
+#pragma unroll
+  for (int q = 0; q < EPL; ++q)
+#pragma unroll
+    for (int c = 0; c < R; ++c) vcol[q][c] = Vj[(int64_t)(lc + q) * W + c];
+
+  T yacc[EPL][R];
+#pragma unroll
+  for (int q = 0; q < EPL; ++q)
+#pragma unroll
+    for (int c = 0; c < R; ++c) yacc[q][c] = T(0);
+
+  for (int ch = 0; ch < nchunks; ++ch) {
+    const int cr0 = row0 + ch * CR;
+    const int wr0 = cr0 + wave * RPW;
+
+    V16<T> p[RPW];
+#pragma unroll
+    for (int t = 0; t < RPW; ++t) p[t] = ld16(P + (int64_t)(wr0 + t) * ldp + lc);
+
+#pragma unroll
+    for (int t = 0; t < RPW; ++t) {
+      const int64_t i = wr0 + t;
+      const T* urow = Uj + i * W;
+      const T* vrow = Vj + i * W;
+      T ui[R], vi[R];
+#pragma unroll
+      for (int c = 0; c < R; ++c) { ui[c] = urow[c]; vi[c] = vrow[c]; }
+#pragma unroll
+      for (int q = 0; q < EPL; ++q)
+#pragma unroll
+        for (int c = 0; c < R; ++c) yacc[q][c] = fma(p[t].v[q], vi[c], yacc[q][c]);
+      st16(tileP + (wave * RPW + t) * LDSW + lane * EPL, p[t]);
+#pragma unroll
+      for (int q = 0; q < EPL; ++q) {
+        T d = T(0);
+#pragma unroll
+        for (int c = 0; c < R; ++c) d = fma(ui[c], vcol[q][c], d);
+        p[t].v[q] += d;
+      }
+      st16(P + i * ldp + lc, p[t]);
+    }
+    __syncthreads();
+
+    T x[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) x[c] = T(0);
+    const int qc0 = wave * QW;
+#pragma unroll 4
+    for (int l = 0; l < QW; l += EPL) {
+      const V16<T> pv = ld16(tileP + lane * LDSW + qc0 + l);
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        const T* urow = Uj + (int64_t)(col0 + qc0 + l + e) * W;
+#pragma unroll
+        for (int c = 0; c < R; ++c) x[c] = fma(pv.v[e], urow[c], x[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < R; ++c) xq[(wave * CR + lane) * R + c] = x[c];
+    __syncthreads();
+    for (int idx = tid; idx < CR * R; idx += 256) {
+      const int rr = idx / R, c = idx % R;
+      const T s = ((xq[(0 * CR + rr) * R + c] + xq[(1 * CR + rr) * R + c]) +
+                   xq[(2 * CR + rr) * R + c]) + xq[(3 * CR + rr) * R + c];
+      partX[((int64_t)ct * n_pad + cr0 + rr) * R + c] = s;
+    }
+  }
+
+  // Y partial of this tile: sum the four waves' accumulators.
+  __syncthreads();
+  T* ybuf = tileP;
+#pragma unroll
+  for (int q = 0; q < EPL; ++q)
+#pragma unroll
+    for (int c = 0; c < R; ++c) ybuf[(wave * TC + lane * EPL + q) * R + c] = yacc[q][c];
+  __syncthreads();
+  for (int idx = tid; idx < TC * R; idx += 256) {
+    const int cc = idx / R, c = idx % R;
+    const T s = ((ybuf[(0 * TC + cc) * R + c] + ybuf[(1 * TC + cc) * R + c]) +
+                 ybuf[(2 * TC + cc) * R + c]) + ybuf[(3 * TC + cc) * R + c];
+    partY[((int64_t)rt * n_pad + col0 + cc) * R + c] = s;
+  }
+
+  // Partial Gram V_j^T U_j over this tile's rows (double accumulation).
+  if (ct == 0) {
+    for (int idx = tid; idx < R * R; idx += 256) {
+      const int a = idx / R, b = idx % R;
+      double g = 0.0;
+      for (int i = row0; i < row0 + nrows; ++i)
+        g = fma((double)Vj[(int64_t)i * W + a], (double)Uj[(int64_t)i * W + b], g);
+      partG[((int64_t)rt * R + a) * R + b] = g;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- tail
+template <typename T, int R>
+__global__ void __launch_bounds__(256)
+k_level_tail(const T* __restrict__ partX, const T* __restrict__ partY,
+             const double* __restrict__ partG, int nct, int nrt, int n_pad,
+             const T* Ucur, T* Unew, T* Vnew, int W) {
+  __shared__ double G[R * R];
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < R * R; idx += 256) {
+    double g = 0.0;
+    for (int t = 0; t < nrt; ++t) g += partG[(int64_t)t * R * R + idx];
+    G[idx] = g;
+  }
+  __syncthreads();
+  const int64_t row0 = (int64_t)blockIdx.x * kTailRows;
+  for (int idx = tid; idx < kTailRows * R; idx += 256) {
+    const int rr = idx / R, c = idx % R;
+    const int64_t i = row0 + rr;
+    double x = 0.0;
+    for (int t = 0; t < nct; ++t) x += (double)partX[((int64_t)t * n_pad + i) * R + c];
+    double ug = 0.0;
+#pragma unroll
+    for (int d = 0; d < R; ++d) ug = fma((double)Ucur[i * W + d], G[d * R + c], ug);
+    double y = 0.0;
+    for (int t = 0; t < nrt; ++t) y += (double)partY[((int64_t)t * n_pad + i) * R + c];
+    Unew[i * W + c] = (T)(x + ug);
+    Vnew[i * W + c] = (T)y;
+  }
+}
+
+// ---------------------------------------------------------------- update only
+// P += U_j V_j^T.  Lane holds a 16-byte column group; the wave walks batches
+// of 8 rows with U_j rows broadcast through the scalar unit; ranks above 16
+// are processed in groups of 16 columns of the factors.
+template <typename T, int R>
+__global__ void __launch_bounds__(256)
+k_level_update(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
+               const T* __restrict__ Uj, const T* __restrict__ Vj, int W) {
+  constexpr int EPL = 16 / (int)sizeof(T);
+  constexpr int TC = 64 * EPL;
+  constexpr int RG = R < 16 ? R : 16;
+  constexpr int NG = R / RG;
+  constexpr int RB = 8;
+  const int lane = threadIdx.x & 63;
+  const int wave = wave_id();
+  const int col0 = blockIdx.x * TC;
+  const int row0 = blockIdx.y * tile_rows;
+  const int nrows = min(tile_rows, n_pad - row0);
+  const int lc = col0 + lane * EPL;
+
+  for (int rb = wave * RB; rb < nrows; rb += 4 * RB) {
+    V16<T> p[RB];
+#pragma unroll
+    for (int t = 0; t < RB; ++t) p[t] = ld16(P + (int64_t)(row0 + rb + t) * ldp + lc);
+    T d[RB][EPL];
+#pragma unroll
+    for (int t = 0; t < RB; ++t)
+#pragma unroll
+      for (int q = 0; q < EPL; ++q) d[t][q] = T(0);
+    for (int g = 0; g < NG; ++g) {
+      T vcol[EPL][RG];
+#pragma unroll
+      for (int q = 0; q < EPL; ++q)
+#pragma unroll
+        for (int c = 0; c < RG; ++c) vcol[q][c] = Vj[(int64_t)(lc + q) * W + g * RG + c];
+#pragma unroll
+      for (int t = 0; t < RB; ++t) {
+        const T* urow = Uj + (int64_t)(row0 + rb + t) * W + g * RG;
+#pragma unroll
+        for (int q = 0; q < EPL; ++q)
+#pragma unroll
+          for (int c = 0; c < RG; ++c) d[t][q] = fma(urow[c], vcol[q][c], d[t][q]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < RB; ++t) {
+#pragma unroll
+      for (int q = 0; q < EPL; ++q) p[t].v[q] += d[t][q];
+      st16(P + (int64_t)(row0 + rb + t) * ldp + lc, p[t]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- small kernels
+template <typename Tin, typename Tout>
+__global__ void __launch_bounds__(256)
+k_copy_pad(const Tin* __restrict__ src, int64_t lds, int64_t n, Tout* __restrict__ dst,
+           int64_t ldd, int64_t n_pad) {
+  const int64_t i = blockIdx.x;
+  const int64_t j = (int64_t)blockIdx.y * 256 + threadIdx.x;
+  if (j >= n_pad) return;
+  const Tout v = (i < n && j < n) ? (Tout)src[i * lds + j] : Tout(0);
+  dst[i * ldd + j] = v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_prep(const T* __restrict__ U, int64_t ldu, const T* __restrict__ V, int64_t ldv, int64_t n,
+       int r, int r_pad, T* __restrict__ slabU, T* __restrict__ slabV, int W, int64_t n_pad) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= n_pad * r_pad) return;
+  const int64_t i = idx / r_pad;
+  const int c = (int)(idx % r_pad);
+  const bool in = i < n && c < r;
+  slabU[i * W + c] = in ? U[i * ldu + c] : T(0);
+  slabV[i * W + (W - r_pad) + c] = in ? V[i * ldv + c] : T(0);
+}
+
+template <typename T, int R>
+hipError_t fused_r(T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* Uj, const T* Vj,
+                   int W, T* partX, T* partY, double* partG, hipStream_t s) {
+  const dim3 grid((unsigned)(n_pad / tile_cols<T>()), (unsigned)((n_pad + tile_rows - 1) / tile_rows));
+  hipLaunchKernelGGL((k_level_fused<T, R>), grid, dim3(256), 0, s, P, ldp, (int)n_pad, tile_rows,
+                     Uj, Vj, W, partX, partY, partG);
+  return hipGetLastError();
+}
+
+template <typename T, int R>
+hipError_t tail_r(const T* partX, const T* partY, const double* partG, int nct, int nrt,
+                  int64_t n_pad, T* slabU, T* slabV, int W, hipStream_t s) {
+  const dim3 grid((unsigned)(n_pad / kTailRows));
+  // U_j = slab U columns [0, R): new block at [R, 2R).
+  // V_j = slab V columns [W-R, W): new block at [W-2R, W-R).
+  hipLaunchKernelGGL((k_level_tail<T, R>), grid, dim3(256), 0, s, partX, partY, partG, nct, nrt,
+                     (int)n_pad, (const T*)slabU, slabU + R, slabV + (W - 2 * R), W);
+  return hipGetLastError();
+}
+
+template <typename T, int R>
+hipError_t update_r(T* P, int64_t ldp, int64_t n_pad, const T* Uj, const T* Vj, int W,
+                    hipStream_t s) {
+  const int tile_rows = 256;
+  const dim3 grid((unsigned)(n_pad / tile_cols<T>()), (unsigned)((n_pad + tile_rows - 1) / tile_rows));
+  hipLaunchKernelGGL((k_level_update<T, R>), grid, dim3(256), 0, s, P, ldp, (int)n_pad, tile_rows,
+                     Uj, Vj, W);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename Tin, typename Tout>
+hipError_t launch_copy_pad(const Tin* src, int64_t lds, int64_t n, Tout* dst, int64_t ldd,
+                           int64_t n_pad, hipStream_t s) {
+  const dim3 grid((unsigned)n_pad, (unsigned)((n_pad + 255) / 256));
+  hipLaunchKernelGGL((k_copy_pad<Tin, Tout>), grid, dim3(256), 0, s, src, lds, n, dst, ldd, n_pad);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prep(const T* U, int64_t ldu, const T* V, int64_t ldv, int64_t n, int r,
+                       int r_pad, T* slabU, T* slabV, int W, int64_t n_pad, hipStream_t s) {
+  const int64_t total = n_pad * r_pad;
+  const dim3 grid((unsigned)((total + 255) / 256));
+  hipLaunchKernelGGL((k_prep<T>), grid, dim3(256), 0, s, U, ldu, V, ldv, n, r, r_pad, slabU, slabV,
+                     W, n_pad);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_level_fused(int R, T* P, int64_t ldp, int64_t n_pad, int tile_rows,
+                              const T* slabU, const T* slabV, int W, T* partX, T* partY,
+                              double* partG, hipStream_t s) {
+  const T* Uj = slabU;
+  const T* Vj = slabV + (W - R);
+  switch (R) {
+    case 1: return fused_r<T, 1>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s);
+    case 2: return fused_r<T, 2>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s);
+    case 4: return fused_r<T, 4>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s);
+    case 8: return fused_r<T, 8>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s);
+    case 16: return fused_r<T, 16>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_level_tail(int R, const T* partX, const T* partY, const double* partG, int nct,
+                             int nrt, int64_t n_pad, T* slabU, T* slabV, int W, hipStream_t s) {
+  switch (R) {
+    case 1: return tail_r<T, 1>(partX, partY, partG, nct, nrt, n_pad, slabU, slabV, W, s);
+    case 2: return tail_r<T, 2>(partX, partY, partG, nct, nrt, n_pad, slabU, slabV, W, s);
+    case 4: return tail_r<T, 4>(partX, partY, partG, nct, nrt, n_pad, slabU, slabV, W, s);
+    case 8: return tail_r<T, 8>(partX, partY, partG, nct, nrt, n_pad, slabU, slabV, W, s);
+    case 16: return tail_r<T, 16>(partX, partY, partG, nct, nrt, n_pad, slabU, slabV, W, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_level_update(int R, T* P, int64_t ldp, int64_t n_pad, const T* slabU,
+                               const T* slabV, int W, hipStream_t s) {
+  const T* Uj = slabU;
+  const T* Vj = slabV + (W - R);
+  switch (R) {
+    case 1: return update_r<T, 1>(P, ldp, n_pad, Uj, Vj, W, s);
+    case 2: return update_r<T, 2>(P, ldp, n_pad, Uj, Vj, W, s);
+    case 4: return update_r<T, 4>(P, ldp, n_pad, Uj, Vj, W, s);
+    case 8: return update_r<T, 8>(P, ldp, n_pad, Uj, Vj, W, s);
+    case 16: return update_r<T, 16>(P, ldp, n_pad, Uj, Vj, W, s);
+    case 32: return update_r<T, 32>(P, ldp, n_pad, Uj, Vj, W, s);
+    case 64: return update_r<T, 64>(P, ldp, n_pad, Uj, Vj, W, s);
+    case 128: return update_r<T, 128>(P, ldp, n_pad, Uj, Vj, W, s);
+    case 256: return update_r<T, 256>(P, ldp, n_pad, Uj, Vj, W, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+#define LV_INST(T)                                                                              \
+  template hipError_t launch_prep<T>(const T*, int64_t, const T*, int64_t, int64_t, int, int,     \
+                                     T*, T*, int, int64_t, hipStream_t);                          \
+  template hipError_t launch_level_fused<T>(int, T*, int64_t, int64_t, int, const T*, const T*,   \
+                                            int, T*, T*, double*, hipStream_t);                   \
+  template hipError_t launch_level_tail<T>(int, const T*, const T*, const double*, int, int,      \
+                                           int64_t, T*, T*, int, hipStream_t);                    \
+  template hipError_t launch_level_update<T>(int, T*, int64_t, int64_t, const T*, const T*, int,  \
+                                             hipStream_t);
+LV_INST(float)
+LV_INST(double)
+#undef LV_INST
+
+template hipError_t launch_copy_pad<float, float>(const float*, int64_t, int64_t, float*, int64_t, int64_t, hipStream_t);
+template hipError_t launch_copy_pad<double, double>(const double*, int64_t, int64_t, double*, int64_t, int64_t, hipStream_t);
+template hipError_t launch_copy_pad<float, double>(const float*, int64_t, int64_t, double*, int64_t, int64_t, hipStream_t);
+template hipError_t launch_copy_pad<double, float>(const double*, int64_t, int64_t, float*, int64_t, int64_t, hipStream_t);
+
+}  // namespace lv

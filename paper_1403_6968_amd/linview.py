@@ -1,0 +1,307 @@
+"""ctypes binding of liblinview (include/linview.h).
+
+Argument marshalling only: every step of view creation, update and
+re-evaluation runs in the library's HIP kernels.  PyTorch supplies device
+memory (the caller-owned workspace and outputs) and the current stream.
+The functions keep the C names; `View` is a small owner of a workspace and a
+handle on top of them.
+
+Loading fails loudly when the library has not been built: there is no
+fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblinview.so")
+
+LV_OK, LV_EINVAL, LV_ENOMEM, LV_EDEVICE, LV_ESTATE = 0, 1, 2, 3, 4
+LV_FP64, LV_FP32 = 0, 1
+
+_MODE_DTYPE = {LV_FP64: torch.float64, LV_FP32: torch.float32}
+
+EXPORTED = (
+    "lv_status_str", "lv_last_error", "lv_view_footprint", "lv_view_create",
+    "lv_view_update", "lv_view_update_batch", "lv_view_read", "lv_view_data",
+    "lv_view_reanchor", "lv_view_stats", "lv_view_destroy", "lv_reeval_footprint",
+    "lv_reeval", "lv_view_set_timing", "lv_view_timing",
+)
+
+
+class LinviewError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(message)
+        self.status = status
+
+
+class lv_stats(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("n_pad", ctypes.c_int64), ("ld", ctypes.c_int64),
+        ("k", ctypes.c_int32), ("levels", ctypes.c_int32), ("r_max", ctypes.c_int32),
+        ("mode", ctypes.c_int32), ("updates", ctypes.c_int64), ("reanchors", ctypes.c_int64),
+        ("footprint", ctypes.c_size_t),
+    ]
+
+
+class lv_timing(ctypes.Structure):
+    _fields_ = [
+        ("fused_ms", ctypes.c_double), ("fused_launches", ctypes.c_int64),
+        ("tail_ms", ctypes.c_double), ("tail_launches", ctypes.c_int64),
+        ("top_ms", ctypes.c_double), ("top_launches", ctypes.c_int64),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load liblinview.so (once).  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(path)
+    c = ctypes
+    P, I64, I32, SZ = c.c_void_p, c.c_int64, c.c_int, c.c_size_t
+    sig = {
+        "lv_status_str": (c.c_char_p, [I32]),
+        "lv_last_error": (c.c_char_p, []),
+        "lv_view_footprint": (SZ, [I64, I32, I32, I32]),
+        "lv_view_create": (I32, [P, I64, I64, I32, I32, I32, P, SZ, P, c.POINTER(P)]),
+        "lv_view_update": (I32, [P, P, P, I64, I64, I64, P]),
+        "lv_view_update_batch": (I32, [P, P, P, I64, I64, I64, I64, I64, I64, P]),
+        "lv_view_read": (I32, [P, I32, P, I64, P]),
+        "lv_view_data": (P, [P, I32, c.POINTER(I64)]),
+        "lv_view_reanchor": (I32, [P, P]),
+        "lv_view_stats": (I32, [P, c.POINTER(lv_stats)]),
+        "lv_view_destroy": (None, [P]),
+        "lv_reeval_footprint": (SZ, [I64, I32, I32]),
+        "lv_reeval": (I32, [P, I64, I64, I32, P, P, I64, I64, I64, I32, P, I64, P, SZ, P]),
+        "lv_view_set_timing": (I32, [P, I32]),
+        "lv_view_timing": (I32, [P, c.POINTER(lv_timing)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(st: int) -> None:
+    if st != LV_OK:
+        lib = load()
+        raise LinviewError(st, f"{lib.lv_status_str(st).decode()}: {lib.lv_last_error().decode()}")
+
+
+def _stream(stream, device) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _mat(x: torch.Tensor, dtype, name: str):
+    if not isinstance(x, torch.Tensor) or x.device.type != "cuda":
+        raise TypeError(f"{name} must be a device tensor")
+    if x.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {x.dtype}")
+    if x.dim() != 2 or (x.stride(1) != 1 and x.shape[1] > 1):
+        raise ValueError(f"{name} must be a row-major 2-D tensor")
+    ld = x.stride(0) if x.shape[0] > 1 else x.shape[1]
+    if ld < x.shape[1]:
+        raise ValueError(f"{name} rows overlap")
+    return x.data_ptr(), ld
+
+
+# ---------------------------------------------------------------- C names
+
+def lv_status_str(st: int) -> str:
+    return load().lv_status_str(st).decode()
+
+
+def lv_last_error() -> str:
+    return load().lv_last_error().decode()
+
+
+def lv_view_footprint(n: int, k: int, r_max: int, mode: int) -> int:
+    return int(load().lv_view_footprint(n, k, r_max, mode))
+
+
+def lv_view_create(A: torch.Tensor, k: int, r_max: int, mode: int, workspace: torch.Tensor,
+                   stream=None) -> ctypes.c_void_p:
+    lib = load()
+    a, lda = _mat(A, _MODE_DTYPE[mode], "A")
+    if A.shape[0] != A.shape[1]:
+        raise ValueError("A must be square")
+    if workspace.device.type != "cuda" or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous device tensor")
+    h = ctypes.c_void_p()
+    _check(lib.lv_view_create(a, A.shape[0], lda, k, r_max, mode, workspace.data_ptr(),
+                              workspace.numel() * workspace.element_size(),
+                              _stream(stream, A.device), ctypes.byref(h)))
+    return h
+
+
+def lv_view_update(view, U: torch.Tensor, V: torch.Tensor, dtype, stream=None) -> None:
+    u, ldu = _mat(U, dtype, "U")
+    v, ldv = _mat(V, dtype, "V")
+    if U.shape != V.shape:
+        raise ValueError("U and V must have the same shape")
+    _check(load().lv_view_update(view, u, v, U.shape[1], ldu, ldv, _stream(stream, U.device)))
+
+
+def lv_view_update_batch(view, U: torch.Tensor, V: torch.Tensor, dtype, stream=None) -> None:
+    """U, V: (count, n, r) device tensors, row-major per update."""
+    if U.dim() != 3 or U.shape != V.shape:
+        raise ValueError("U and V must be (count, n, r) tensors of one shape")
+    if U.dtype != dtype or V.dtype != dtype:
+        raise TypeError(f"U and V must be {dtype}")
+    if U.shape[2] > 1 and (U.stride(2) != 1 or V.stride(2) != 1):
+        raise ValueError("U and V must be row-major per update")
+    if U.shape[1] > 1 and (U.stride(1) < U.shape[2] or V.stride(1) < V.shape[2]):
+        raise ValueError("U and V rows overlap")
+    ldu = U.stride(1) if U.shape[1] > 1 else U.shape[2]
+    ldv = V.stride(1) if V.shape[1] > 1 else V.shape[2]
+    _check(load().lv_view_update_batch(view, U.data_ptr(), V.data_ptr(), U.shape[2], U.shape[0],
+                                       ldu, ldv, U.stride(0), V.stride(0),
+                                       _stream(stream, U.device)))
+
+
+def lv_view_read(view, power: int, out: torch.Tensor, dtype, stream=None) -> None:
+    o, ldo = _mat(out, dtype, "out")
+    _check(load().lv_view_read(view, power, o, ldo, _stream(stream, out.device)))
+
+
+def lv_view_data(view, power: int):
+    ld = ctypes.c_int64()
+    p = load().lv_view_data(view, power, ctypes.byref(ld))
+    return p, ld.value
+
+
+def lv_view_reanchor(view, stream=None, device=None) -> None:
+    _check(load().lv_view_reanchor(view, _stream(stream, device)))
+
+
+def lv_view_stats(view) -> dict:
+    s = lv_stats()
+    _check(load().lv_view_stats(view, ctypes.byref(s)))
+    return {f: getattr(s, f) for f, _ in lv_stats._fields_}
+
+
+def lv_view_set_timing(view, enable: bool) -> None:
+    _check(load().lv_view_set_timing(view, 1 if enable else 0))
+
+
+def lv_view_timing(view) -> dict:
+    t = lv_timing()
+    _check(load().lv_view_timing(view, ctypes.byref(t)))
+    return {f: getattr(t, f) for f, _ in lv_timing._fields_}
+
+
+def lv_view_destroy(view) -> None:
+    load().lv_view_destroy(view)
+
+
+def lv_reeval_footprint(n: int, r_max: int, mode: int) -> int:
+    return int(load().lv_reeval_footprint(n, r_max, mode))
+
+
+def lv_reeval(A: torch.Tensor, k: int, U, V, mode: int, out: torch.Tensor,
+              workspace: torch.Tensor, stream=None) -> None:
+    dtype = _MODE_DTYPE[mode]
+    a, lda = _mat(A, dtype, "A")
+    o, ldo = _mat(out, dtype, "out")
+    if U is None:
+        u = v = None
+        r = ldu = ldv = 0
+    else:
+        u, ldu = _mat(U, dtype, "U")
+        v, ldv = _mat(V, dtype, "V")
+        r = U.shape[1]
+    _check(load().lv_reeval(a, A.shape[0], lda, k, u, v, r, ldu, ldv, mode, o, ldo,
+                            workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+                            _stream(stream, A.device)))
+
+
+# ---------------------------------------------------------------- owner class
+
+class View:
+    """A view of A^k whose workspace is a torch device tensor."""
+
+    def __init__(self, A: torch.Tensor, k: int, r_max: int = 1, mode: int | None = None,
+                 stream=None):
+        if mode is None:
+            mode = LV_FP64 if A.dtype == torch.float64 else LV_FP32
+        self.mode = mode
+        self.dtype = _MODE_DTYPE[mode]
+        self.n = A.shape[0]
+        self.k = k
+        self.device = A.device
+        nbytes = lv_view_footprint(self.n, k, r_max, mode)
+        if nbytes == 0:
+            # Reproduce the library's validation message.
+            _check(load().lv_view_create(None, self.n, self.n, k, r_max, mode, None, 0, None,
+                                         ctypes.byref(ctypes.c_void_p())))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+        self.handle = lv_view_create(A, k, r_max, mode, self.workspace, stream)
+
+    def update(self, U: torch.Tensor, V: torch.Tensor, stream=None) -> None:
+        lv_view_update(self.handle, U, V, self.dtype, stream)
+
+    def update_batch(self, U: torch.Tensor, V: torch.Tensor, stream=None) -> None:
+        lv_view_update_batch(self.handle, U, V, self.dtype, stream)
+
+    def read(self, power: int | None = None, stream=None) -> torch.Tensor:
+        power = self.k if power is None else power
+        out = torch.empty(self.n, self.n, dtype=self.dtype, device=self.device)
+        lv_view_read(self.handle, power, out, self.dtype, stream)
+        return out
+
+    def reanchor(self, stream=None) -> None:
+        lv_view_reanchor(self.handle, stream, self.device)
+
+    def stats(self) -> dict:
+        return lv_view_stats(self.handle)
+
+    def set_timing(self, enable: bool) -> None:
+        lv_view_set_timing(self.handle, enable)
+
+    def timing(self) -> dict:
+        return lv_view_timing(self.handle)
+
+    def powers(self) -> list[int]:
+        out, p = [], 1
+        while p <= self.k:
+            out.append(p)
+            p *= 2
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None:
+            torch.cuda.synchronize(self.device)
+            lv_view_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def reeval(A: torch.Tensor, k: int, U=None, V=None, stream=None) -> torch.Tensor:
+    """(A + U V^T)^k by the library's re-evaluation path."""
+    mode = LV_FP64 if A.dtype == torch.float64 else LV_FP32
+    n = A.shape[0]
+    r = 0 if U is None else U.shape[1]
+    ws = torch.empty(lv_reeval_footprint(n, r, mode), dtype=torch.uint8, device=A.device)
+    out = torch.empty(n, n, dtype=A.dtype, device=A.device)
+    lv_reeval(A, k, U, V, mode, out, ws, stream)
+    return out

@@ -1,0 +1,109 @@
+"""The C ABI library loads and exports every symbol the header declares, and
+its host-side validation behaves as documented.  No call here reaches a
+device: every case returns before the first HIP call."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "linview.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1403_6968_amd import linview
+    if not os.path.exists(linview.LIB_PATH):
+        from paper_1403_6968_amd import build_lib
+        build_lib.build()
+    return linview.load()
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lv_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_symbols_exported(lib):
+    from paper_1403_6968_amd import linview
+    names = _declared()
+    assert len(names) >= 13
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in linview.h but not exported"
+    assert set(names) == set(linview.EXPORTED)
+
+
+def test_status_strings(lib):
+    from paper_1403_6968_amd import linview as L
+    assert L.lv_status_str(0) == "LV_OK"
+    assert L.lv_status_str(1) == "LV_EINVAL"
+    assert L.lv_status_str(3) == "LV_EDEVICE"
+
+
+def test_footprint_rules(lib):
+    from paper_1403_6968_amd import linview as L
+    f = L.lv_view_footprint
+    # the stored powers alone: (m + 1) padded float matrices
+    assert f(8192, 16, 1, L.LV_FP32) >= 5 * 8192 * 8192 * 4
+    assert f(8192, 16, 1, L.LV_FP64) >= 5 * 8192 * 8192 * 8
+    assert f(1000, 16, 1, L.LV_FP32) == f(1024, 16, 1, L.LV_FP32)     # padded to 256
+    assert f(1025, 16, 1, L.LV_FP32) > f(1024, 16, 1, L.LV_FP32)
+    assert f(1000, 1, 1, L.LV_FP64) >= 1024 * 1024 * 8
+    for bad in [(0, 16, 1, 1), (100, 3, 1, 1), (100, 12, 1, 1), (100, 16, 0, 1),
+                (100, 16, 1, 7), (100, 2048, 1, 1), (100, 16, 64, 1)]:
+        assert f(*bad) == 0, bad
+    assert L.lv_reeval_footprint(1000, 1, L.LV_FP32) >= 2 * 1024 * 1024 * 4
+    assert L.lv_reeval_footprint(0, 1, L.LV_FP32) == 0
+
+
+def test_create_validation_before_device(lib):
+    from paper_1403_6968_amd import linview as L
+    h = ctypes.c_void_p()
+    # NULL A / workspace
+    st = lib.lv_view_create(None, 64, 64, 4, 1, L.LV_FP32, None, 0, None, ctypes.byref(h))
+    assert st == L.LV_EINVAL and "NULL" in L.lv_last_error()
+    # k not a power of two
+    st = lib.lv_view_create(0x1000, 64, 64, 6, 1, L.LV_FP32, 0x1000, 1 << 30, None, ctypes.byref(h))
+    assert st == L.LV_EINVAL and "power of two" in L.lv_last_error()
+    # lda < n
+    st = lib.lv_view_create(0x1000, 64, 32, 4, 1, L.LV_FP32, 0x1000, 1 << 30, None, ctypes.byref(h))
+    assert st == L.LV_EINVAL
+    # misaligned workspace
+    st = lib.lv_view_create(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1001, 1 << 30, None, ctypes.byref(h))
+    assert st == L.LV_ENOMEM
+    # workspace too small
+    need = L.lv_view_footprint(64, 4, 1, L.LV_FP32)
+    st = lib.lv_view_create(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1000, need - 1, None, ctypes.byref(h))
+    assert st == L.LV_ENOMEM and str(need) in L.lv_last_error()
+    assert not h.value
+    # null out
+    st = lib.lv_view_create(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1000, need, None, None)
+    assert st == L.LV_EINVAL
+
+
+def test_null_view_calls(lib):
+    from paper_1403_6968_amd import linview as L
+    assert lib.lv_view_update(None, 0x1000, 0x1000, 1, 1, 1, None) == L.LV_EINVAL
+    assert lib.lv_view_update_batch(None, 0x1000, 0x1000, 1, 2, 1, 1, 64, 64, None) == L.LV_EINVAL
+    assert lib.lv_view_update_batch(None, 0x1000, 0x1000, 1, -1, 1, 1, 64, 64, None) == L.LV_EINVAL
+    assert lib.lv_view_read(None, 1, 0x1000, 1, None) == L.LV_EINVAL
+    assert lib.lv_view_reanchor(None, None) == L.LV_EINVAL
+    assert lib.lv_view_data(None, 1, None) is None
+    s = L.lv_stats()
+    assert lib.lv_view_stats(None, ctypes.byref(s)) == L.LV_EINVAL
+    lib.lv_view_destroy(None)
+
+
+def test_reeval_validation(lib):
+    from paper_1403_6968_amd import linview as L
+    st = lib.lv_reeval(0x1000, 64, 64, 5, None, None, 0, 0, 0, L.LV_FP32, 0x1000, 64, 0x1000, 1 << 30, None)
+    assert st == L.LV_EINVAL
+    st = lib.lv_reeval(0x1000, 64, 64, 4, None, None, 1, 1, 1, L.LV_FP32, 0x1000, 64, 0x1000, 1 << 30, None)
+    assert st == L.LV_EINVAL   # r = 1 with NULL U/V
+    st = lib.lv_reeval(0x1000, 64, 64, 4, None, None, 0, 0, 0, L.LV_FP32, 0x1000, 64, 0x1000, 16, None)
+    assert st == L.LV_ENOMEM
