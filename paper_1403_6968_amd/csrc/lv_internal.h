@@ -12,10 +12,12 @@ namespace lv {
 // row of P_j or U_j produces zero rows of every product), so no kernel needs
 // bounds checks.
 constexpr int kPadOrder = 256;
-// Rows per chunk in the fused level pass (one LDS-resident chunk of a tile).
-constexpr int kChunkRows = 64;
-// Rows handled by one tail work-group.
-constexpr int kTailRows = 64;
+// Rows of one wave's block in the fused level pass (a tile's row count and
+// the padded order must be multiples of 4 * kBlockRows).
+#ifndef LV_BLOCK_ROWS
+#define LV_BLOCK_ROWS 16
+#endif
+constexpr int kBlockRows = LV_BLOCK_ROWS;
 // Largest rank handled by the register-resident fused pass.
 constexpr int kMaxFusedRank = 16;
 // Largest level of the exponential model (k <= 2^kMaxLevel).

@@ -43,30 +43,35 @@ __device__ __forceinline__ int wave_id() {
 // ---------------------------------------------------------------- fused pass
 //
 // Block: 256 threads (4 waves).  Tile: tile_rows x TC, TC = 64 lanes x 16 B.
-// Per 64-row chunk:
-//   Phase A  wave w takes rows w*16 .. w*16+15 of the chunk, one 16-byte
-//            vector per lane per row: Y partial (yacc, per-lane columns),
-//            old values to LDS, P + U_j V_j^T back to HBM.
-//   Phase B  wave w takes the w-th quarter of the tile's columns and lane l
-//            the l-th row of the chunk: x[c] = sum over the quarter of
-//            P_old[row][col] * U_j[col][c] with U_j rows broadcast through the
-//            scalar unit; the four quarters are summed in LDS and one partial
-//            per (row, tile column) is written.
-template <typename T, int R>
+// The tile's rows are cut into blocks of RB rows; wave w owns blocks
+// w, w + 4, w + 8, ... and processes each one end to end with no block-wide
+// synchronisation:
+//   Phase A  one 16-byte vector per lane per row: Y partial (yacc, the
+//            lane's own columns, V_j rows broadcast through the scalar unit),
+//            the old values to the wave's private LDS block, and
+//            P + U_j V_j^T back to HBM; the next block's rows are then
+//            requested at once so that they are in flight during Phase B.
+//   Phase B  lane (rho, q) = (lane % RB, lane / RB) sums row rho of the block
+//            over the q-th of NQ = 64 / RB column slices with the tile's
+//            U_j rows read from LDS (staged once per tile); the NQ slice
+//            sums are combined with xor-shuffles and one partial per
+//            (row, tile column) is written.
+// The four waves' Y accumulators are summed once at the end of the tile.
+template <typename T, int R, int RB>
 __global__ void __launch_bounds__(256)
 k_level_fused(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
               const T* __restrict__ Uj, const T* __restrict__ Vj, int W,
               T* __restrict__ partX, T* __restrict__ partY, double* __restrict__ partG) {
   constexpr int EPL = 16 / (int)sizeof(T);
   constexpr int TC = 64 * EPL;
-  constexpr int CR = kChunkRows;
-  constexpr int RPW = CR / 4;
-  constexpr int QW = TC / 4;
-  constexpr int LDSW = TC + EPL;
-  static_assert(4 * TC * R <= CR * LDSW, "Y reduction buffer must fit in the tile buffer");
+  constexpr int NQ = 64 / RB;           // column slices in Phase B
+  constexpr int QW = TC / NQ;           // columns per slice
+  constexpr int LDSW = TC + EPL;        // padded LDS row (elements)
+  constexpr int UPAD = 4;               // LDS padding between U slices (elements)
+  static_assert(4 * TC * R <= 4 * RB * LDSW, "Y reduction buffer must fit in the tile buffer");
 
-  __shared__ __align__(16) T tileP[CR * LDSW];
-  __shared__ T xq[4 * CR * R];
+  __shared__ __align__(16) T tileP[4 * RB * LDSW];
+  __shared__ __align__(16) T utile[TC * R + NQ * UPAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -76,8 +81,15 @@ k_level_fused(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
   const int col0 = ct * TC;
   const int row0 = rt * tile_rows;
   const int nrows = min(tile_rows, n_pad - row0);
-  const int nchunks = nrows / CR;
+  const int nblocks = nrows / RB;
   const int lc = col0 + lane * EPL;
+  T* myP = tileP + wave * RB * LDSW;
+
+  // U_j rows of the tile's columns, slice-padded: (col, c) -> col*R + (col/QW)*UPAD + c.
+  for (int idx = tid; idx < TC * R; idx += 256) {
+    const int col = idx / R, c = idx % R;
+    utile[col * R + (col / QW) * UPAD + c] = Uj[(int64_t)(col0 + col) * W + c];
+  }
 
   T vcol[EPL][R];
 #pragma unroll
@@ -91,17 +103,25 @@ k_level_fused(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
 #pragma unroll
     for (int c = 0; c < R; ++c) yacc[q][c] = T(0);
 
-  for (int ch = 0; ch < nchunks; ++ch) {
-    const int cr0 = row0 + ch * CR;
-    const int wr0 = cr0 + wave * RPW;
+  __syncthreads();
 
-    V16<T> p[RPW];
+  const int rho = lane % RB;
+  const int qs = lane / RB;
+  const T* urow0 = utile + qs * (QW * R + UPAD);
+
+  V16<T> p[RB];
+  if (wave < nblocks) {
+    const int64_t r0 = row0 + wave * RB;
 #pragma unroll
-    for (int t = 0; t < RPW; ++t) p[t] = ld16(P + (int64_t)(wr0 + t) * ldp + lc);
+    for (int t = 0; t < RB; ++t) p[t] = ld16(P + (r0 + t) * ldp + lc);
+  }
+
+  for (int b = wave; b < nblocks; b += 4) {
+    const int64_t r0 = row0 + b * RB;
 
 #pragma unroll
-    for (int t = 0; t < RPW; ++t) {
-      const int64_t i = wr0 + t;
+    for (int t = 0; t < RB; ++t) {
+      const int64_t i = r0 + t;
       const T* urow = Uj + i * W;
       const T* vrow = Vj + i * W;
       T ui[R], vi[R];
@@ -111,7 +131,7 @@ k_level_fused(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
       for (int q = 0; q < EPL; ++q)
 #pragma unroll
         for (int c = 0; c < R; ++c) yacc[q][c] = fma(p[t].v[q], vi[c], yacc[q][c]);
-      st16(tileP + (wave * RPW + t) * LDSW + lane * EPL, p[t]);
+      st16(myP + t * LDSW + lane * EPL, p[t]);
 #pragma unroll
       for (int q = 0; q < EPL; ++q) {
         T d = T(0);
@@ -121,31 +141,40 @@ k_level_fused(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
       }
       st16(P + i * ldp + lc, p[t]);
     }
-    __syncthreads();
+    if (b + 4 < nblocks) {
+      const int64_t rn = r0 + 4 * RB;
+#pragma unroll
+      for (int t = 0; t < RB; ++t) p[t] = ld16(P + (rn + t) * ldp + lc);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
     T x[R];
 #pragma unroll
     for (int c = 0; c < R; ++c) x[c] = T(0);
-    const int qc0 = wave * QW;
+    const T* prow = myP + rho * LDSW + qs * QW;
 #pragma unroll 4
     for (int l = 0; l < QW; l += EPL) {
-      const V16<T> pv = ld16(tileP + lane * LDSW + qc0 + l);
+      const V16<T> pv = ld16(prow + l);
 #pragma unroll
       for (int e = 0; e < EPL; ++e) {
-        const T* urow = Uj + (int64_t)(col0 + qc0 + l + e) * W;
+        const T* ur = urow0 + (l + e) * R;
 #pragma unroll
-        for (int c = 0; c < R; ++c) x[c] = fma(pv.v[e], urow[c], x[c]);
+        for (int c = 0; c < R; ++c) x[c] = fma(pv.v[e], ur[c], x[c]);
       }
     }
 #pragma unroll
-    for (int c = 0; c < R; ++c) xq[(wave * CR + lane) * R + c] = x[c];
-    __syncthreads();
-    for (int idx = tid; idx < CR * R; idx += 256) {
-      const int rr = idx / R, c = idx % R;
-      const T s = ((xq[(0 * CR + rr) * R + c] + xq[(1 * CR + rr) * R + c]) +
-                   xq[(2 * CR + rr) * R + c]) + xq[(3 * CR + rr) * R + c];
-      partX[((int64_t)ct * n_pad + cr0 + rr) * R + c] = s;
+    for (int off = RB; off < 64; off <<= 1)
+#pragma unroll
+      for (int c = 0; c < R; ++c) x[c] += __shfl_xor(x[c], off);
+    if (qs == 0) {
+#pragma unroll
+      for (int c = 0; c < R; ++c) partX[((int64_t)ct * n_pad + r0 + rho) * R + c] = x[c];
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 
   // Y partial of this tile: sum the four waves' accumulators.
@@ -163,19 +192,42 @@ k_level_fused(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
     partY[((int64_t)rt * n_pad + col0 + cc) * R + c] = s;
   }
 
-  // Partial Gram V_j^T U_j over this tile's rows (double accumulation).
+  // Partial Gram V_j^T U_j over this tile's rows (double accumulation):
+  // thread (pair, group) sums every G-th row of the tile for one (a, b), the
+  // groups are then added in a fixed order.
   if (ct == 0) {
-    for (int idx = tid; idx < R * R; idx += 256) {
-      const int a = idx / R, b = idx % R;
+    constexpr int NP = R * R;
+    constexpr int G = NP >= 256 ? 1 : 256 / NP;
+    double* gbuf = reinterpret_cast<double*>(tileP);
+    __syncthreads();
+    for (int base = 0; base < NP; base += 256) {
+      const int pair = base + (tid % (NP < 256 ? NP : 256));
+      const int grp = tid / (NP < 256 ? NP : 256);
       double g = 0.0;
-      for (int i = row0; i < row0 + nrows; ++i)
-        g = fma((double)Vj[(int64_t)i * W + a], (double)Uj[(int64_t)i * W + b], g);
-      partG[((int64_t)rt * R + a) * R + b] = g;
+      if (grp < G && pair < NP) {
+        const int a = pair / R, bb = pair % R;
+        const T* vp = Vj + a;
+        const T* up = Uj + bb;
+#pragma unroll 8
+        for (int i = row0 + grp; i < row0 + nrows; i += G)
+          g = fma((double)vp[(int64_t)i * W], (double)up[(int64_t)i * W], g);
+      }
+      gbuf[tid] = g;
+      __syncthreads();
+      if (tid < (NP - base < 256 ? NP - base : 256)) {
+        double s = 0.0;
+        for (int q = 0; q < G; ++q) s += gbuf[q * (NP < 256 ? NP : 256) + tid];
+        partG[(int64_t)rt * NP + base + tid] = s;
+      }
+      __syncthreads();
     }
   }
 }
 
 // ---------------------------------------------------------------- tail
+// One thread per (row, c): the partials of the row tiles / column tiles are
+// loaded in batches of 8 (independent loads in flight) and added in index
+// order; the Gram partials are summed once per block into LDS.
 template <typename T, int R>
 __global__ void __launch_bounds__(256)
 k_level_tail(const T* __restrict__ partX, const T* __restrict__ partY,
@@ -189,20 +241,37 @@ k_level_tail(const T* __restrict__ partX, const T* __restrict__ partY,
     G[idx] = g;
   }
   __syncthreads();
-  const int64_t row0 = (int64_t)blockIdx.x * kTailRows;
-  for (int idx = tid; idx < kTailRows * R; idx += 256) {
-    const int rr = idx / R, c = idx % R;
-    const int64_t i = row0 + rr;
-    double x = 0.0;
-    for (int t = 0; t < nct; ++t) x += (double)partX[((int64_t)t * n_pad + i) * R + c];
-    double ug = 0.0;
+  const int64_t pairs = (int64_t)n_pad * R;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + tid;
+  if (idx >= pairs) return;
+  const int64_t i = idx / R;
+  const int c = (int)(idx % R);
+  const int64_t strideX = (int64_t)n_pad * R;
+  double x = 0.0;
+  int t = 0;
+  for (; t + 8 <= nct; t += 8) {
+    T v[8];
 #pragma unroll
-    for (int d = 0; d < R; ++d) ug = fma((double)Ucur[i * W + d], G[d * R + c], ug);
-    double y = 0.0;
-    for (int t = 0; t < nrt; ++t) y += (double)partY[((int64_t)t * n_pad + i) * R + c];
-    Unew[i * W + c] = (T)(x + ug);
-    Vnew[i * W + c] = (T)y;
+    for (int e = 0; e < 8; ++e) v[e] = partX[(t + e) * strideX + idx];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x += (double)v[e];
   }
+  for (; t < nct; ++t) x += (double)partX[t * strideX + idx];
+  double y = 0.0;
+  t = 0;
+  for (; t + 8 <= nrt; t += 8) {
+    T v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = partY[(t + e) * strideX + idx];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) y += (double)v[e];
+  }
+  for (; t < nrt; ++t) y += (double)partY[t * strideX + idx];
+  double ug = 0.0;
+#pragma unroll
+  for (int d = 0; d < R; ++d) ug = fma((double)Ucur[i * W + d], G[d * R + c], ug);
+  Unew[i * W + c] = (T)(x + ug);
+  Vnew[i * W + c] = (T)y;
 }
 
 // ---------------------------------------------------------------- update only
@@ -286,8 +355,9 @@ k_prep(const T* __restrict__ U, int64_t ldu, const T* __restrict__ V, int64_t ld
 template <typename T, int R>
 hipError_t fused_r(T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* Uj, const T* Vj,
                    int W, T* partX, T* partY, double* partG, hipStream_t s) {
+  constexpr int RB = kBlockRows;
   const dim3 grid((unsigned)(n_pad / tile_cols<T>()), (unsigned)((n_pad + tile_rows - 1) / tile_rows));
-  hipLaunchKernelGGL((k_level_fused<T, R>), grid, dim3(256), 0, s, P, ldp, (int)n_pad, tile_rows,
+  hipLaunchKernelGGL((k_level_fused<T, R, RB>), grid, dim3(256), 0, s, P, ldp, (int)n_pad, tile_rows,
                      Uj, Vj, W, partX, partY, partG);
   return hipGetLastError();
 }
@@ -295,7 +365,7 @@ hipError_t fused_r(T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* Uj,
 template <typename T, int R>
 hipError_t tail_r(const T* partX, const T* partY, const double* partG, int nct, int nrt,
                   int64_t n_pad, T* slabU, T* slabV, int W, hipStream_t s) {
-  const dim3 grid((unsigned)(n_pad / kTailRows));
+  const dim3 grid((unsigned)((n_pad * R + 255) / 256));
   // U_j = slab U columns [0, R): new block at [R, 2R).
   // V_j = slab V columns [W-R, W): new block at [W-2R, W-R).
   hipLaunchKernelGGL((k_level_tail<T, R>), grid, dim3(256), 0, s, partX, partY, partG, nct, nrt,
