@@ -189,6 +189,26 @@ def main():
         log(f"fused pass avg {fused_ms * 1e3:.1f} us -> {achieved:.0f} GB/s; "
             f"top update avg {top_ms * 1e3:.1f} us; per update {result['kernel_ms_per_update']}")
 
+    if not args.quick:
+        # measured streaming ceiling: a plain device copy of one stored power's size
+        src = torch.empty(n_pad * n_pad, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(10):
+            dst.copy_(src)
+        b.record(stream)
+        torch.cuda.synchronize()
+        copy_ms = a.elapsed_time(b) / 10
+        result["copy_ref"] = {"bytes": 2 * 4 * n_pad * n_pad, "ms": copy_ms,
+                              "GBps": 2 * 4 * n_pad * n_pad / (copy_ms * 1e-3) / 1e9}
+        if "roofline" in result:
+            result["roofline"]["frac_of_copy"] = result["roofline"]["achieved"] / result["copy_ref"]["GBps"]
+        log(f"copy reference: {result['copy_ref']['GBps']:.0f} GB/s")
+        del src, dst
+
     if not args.quick and not args.no_reeval:
         ws = torch.empty(lv.lv_reeval_footprint(n, r, lv.LV_FP32), dtype=torch.uint8, device=dev)
         out = torch.empty(n, n, dtype=torch.float32, device=dev)

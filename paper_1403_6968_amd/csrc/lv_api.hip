@@ -435,7 +435,7 @@ lv_status lv_view_timing(lv_view* v, lv_timing* out) {
 void lv_view_destroy(lv_view* v) {
   if (!v) return;
   for (auto& p : v->pending) { v->pool.push_back(p.a); v->pool.push_back(p.b); }
-  for (hipEvent_t e : v->pool) hipEventDestroy(e);
+  for (hipEvent_t e : v->pool) (void)hipEventDestroy(e);
   delete v;
 }
 

@@ -68,7 +68,6 @@ k_level_fused(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
   constexpr int QW = TC / NQ;           // columns per slice
   constexpr int LDSW = TC + EPL;        // padded LDS row (elements)
   constexpr int UPAD = 4;               // LDS padding between U slices (elements)
-  static_assert(4 * TC * R <= 4 * RB * LDSW, "Y reduction buffer must fit in the tile buffer");
 
   __shared__ __align__(16) T tileP[4 * RB * LDSW];
   __shared__ __align__(16) T utile[TC * R + NQ * UPAD];
@@ -177,19 +176,26 @@ k_level_fused(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 
-  // Y partial of this tile: sum the four waves' accumulators.
-  __syncthreads();
+  // Y partial of this tile: sum the four waves' accumulators (in column
+  // chunks of YC factor columns when the tile buffer cannot hold all R).
+  constexpr int YCAP = (RB * LDSW) / TC;
+  constexpr int YC = R < YCAP ? R : YCAP;
+  static_assert(YC >= 1 && R % YC == 0, "Y reduction chunking");
   T* ybuf = tileP;
 #pragma unroll
-  for (int q = 0; q < EPL; ++q)
+  for (int c0 = 0; c0 < R; c0 += YC) {
+    __syncthreads();
 #pragma unroll
-    for (int c = 0; c < R; ++c) ybuf[(wave * TC + lane * EPL + q) * R + c] = yacc[q][c];
-  __syncthreads();
-  for (int idx = tid; idx < TC * R; idx += 256) {
-    const int cc = idx / R, c = idx % R;
-    const T s = ((ybuf[(0 * TC + cc) * R + c] + ybuf[(1 * TC + cc) * R + c]) +
-                 ybuf[(2 * TC + cc) * R + c]) + ybuf[(3 * TC + cc) * R + c];
-    partY[((int64_t)rt * n_pad + col0 + cc) * R + c] = s;
+    for (int q = 0; q < EPL; ++q)
+#pragma unroll
+      for (int c = 0; c < YC; ++c) ybuf[(wave * TC + lane * EPL + q) * YC + c] = yacc[q][c0 + c];
+    __syncthreads();
+    for (int idx = tid; idx < TC * YC; idx += 256) {
+      const int cc = idx / YC, c = idx % YC;
+      const T s = ((ybuf[(0 * TC + cc) * YC + c] + ybuf[(1 * TC + cc) * YC + c]) +
+                   ybuf[(2 * TC + cc) * YC + c]) + ybuf[(3 * TC + cc) * YC + c];
+      partY[((int64_t)rt * n_pad + col0 + cc) * R + c0 + c] = s;
+    }
   }
 
   // Partial Gram V_j^T U_j over this tile's rows (double accumulation):
