@@ -57,8 +57,6 @@ lv_status check_shape(int64_t n, int k, int r_max, lv_mode mode) {
   const int64_t width = (int64_t)k * next_pow2(r_max);
   if (width > kMaxWidth)
     return fail(LV_EINVAL, "k * r_max (rounded up to a power of two) = %lld exceeds %d", (long long)width, kMaxWidth);
-  if (k > 1 && width / 2 > kMaxFusedRank)
-    return fail(LV_EINVAL, "level rank %lld exceeds the fused pass limit %d", (long long)(width / 2), kMaxFusedRank);
   return LV_OK;
 }
 

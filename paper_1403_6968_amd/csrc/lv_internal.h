@@ -12,13 +12,10 @@ namespace lv {
 // row of P_j or U_j produces zero rows of every product), so no kernel needs
 // bounds checks.
 constexpr int kPadOrder = 256;
-// Rows of one wave's block in the fused level pass (a tile's row count and
-// the padded order must be multiples of 4 * kBlockRows).
-#ifndef LV_BLOCK_ROWS
-#define LV_BLOCK_ROWS 16
-#endif
-constexpr int kBlockRows = LV_BLOCK_ROWS;
-// Largest rank handled by the register-resident fused pass.
+// A tile's row count and the padded order are multiples of 4 waves x 16-row
+// blocks in the fused level pass.
+// Largest level rank handled by the register-resident fused pass; larger
+// ranks run the skinny products in chunks of this many factor columns.
 constexpr int kMaxFusedRank = 16;
 // Largest level of the exponential model (k <= 2^kMaxLevel).
 constexpr int kMaxLevel = 10;

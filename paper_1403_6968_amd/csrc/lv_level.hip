@@ -57,11 +57,16 @@ __device__ __forceinline__ int wave_id() {
 //            sums are combined with xor-shuffles and one partial per
 //            (row, tile column) is written.
 // The four waves' Y accumulators are summed once at the end of the tile.
-template <typename T, int R, int RB>
+//
+// UPD = false gives the read-only variant used for ranks above 16: the
+// skinny products of 16 factor columns at a time (partials written with row
+// stride pR at the chunk's column offset), the rank update and the Gram done
+// by k_level_update and k_gram.
+template <typename T, int R, int RB, bool UPD>
 __global__ void __launch_bounds__(256)
 k_level_fused(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
               const T* __restrict__ Uj, const T* __restrict__ Vj, int W,
-              T* __restrict__ partX, T* __restrict__ partY, double* __restrict__ partG) {
+              T* __restrict__ partX, T* __restrict__ partY, double* __restrict__ partG, int pR) {
   constexpr int EPL = 16 / (int)sizeof(T);
   constexpr int TC = 64 * EPL;
   constexpr int NQ = 64 / RB;           // column slices in Phase B
@@ -90,11 +95,13 @@ k_level_fused(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
     utile[col * R + (col / QW) * UPAD + c] = Uj[(int64_t)(col0 + col) * W + c];
   }
 
-  T vcol[EPL][R];
+  T vcol[EPL][UPD ? R : 1];
+  if constexpr (UPD) {
 #pragma unroll
-  for (int q = 0; q < EPL; ++q)
+    for (int q = 0; q < EPL; ++q)
 #pragma unroll
-    for (int c = 0; c < R; ++c) vcol[q][c] = Vj[(int64_t)(lc + q) * W + c];
+      for (int c = 0; c < R; ++c) vcol[q][c] = Vj[(int64_t)(lc + q) * W + c];
+  }
 
   T yacc[EPL][R];
 #pragma unroll
@@ -121,24 +128,29 @@ k_level_fused(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
 #pragma unroll
     for (int t = 0; t < RB; ++t) {
       const int64_t i = r0 + t;
-      const T* urow = Uj + i * W;
       const T* vrow = Vj + i * W;
-      T ui[R], vi[R];
+      T vi[R];
 #pragma unroll
-      for (int c = 0; c < R; ++c) { ui[c] = urow[c]; vi[c] = vrow[c]; }
+      for (int c = 0; c < R; ++c) vi[c] = vrow[c];
 #pragma unroll
       for (int q = 0; q < EPL; ++q)
 #pragma unroll
         for (int c = 0; c < R; ++c) yacc[q][c] = fma(p[t].v[q], vi[c], yacc[q][c]);
       st16(myP + t * LDSW + lane * EPL, p[t]);
+      if constexpr (UPD) {
+        const T* urow = Uj + i * W;
+        T ui[R];
 #pragma unroll
-      for (int q = 0; q < EPL; ++q) {
-        T d = T(0);
+        for (int c = 0; c < R; ++c) ui[c] = urow[c];
 #pragma unroll
-        for (int c = 0; c < R; ++c) d = fma(ui[c], vcol[q][c], d);
-        p[t].v[q] += d;
+        for (int q = 0; q < EPL; ++q) {
+          T d = ui[0] * vcol[q][0];
+#pragma unroll
+          for (int c = 1; c < R; ++c) d = fma(ui[c], vcol[q][c], d);
+          p[t].v[q] += d;
+        }
+        st16(P + i * ldp + lc, p[t]);
       }
-      st16(P + i * ldp + lc, p[t]);
     }
     if (b + 4 < nblocks) {
       const int64_t rn = r0 + 4 * RB;
@@ -169,7 +181,7 @@ k_level_fused(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
       for (int c = 0; c < R; ++c) x[c] += __shfl_xor(x[c], off);
     if (qs == 0) {
 #pragma unroll
-      for (int c = 0; c < R; ++c) partX[((int64_t)ct * n_pad + r0 + rho) * R + c] = x[c];
+      for (int c = 0; c < R; ++c) partX[((int64_t)ct * n_pad + r0 + rho) * pR + c] = x[c];
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -194,14 +206,14 @@ k_level_fused(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
       const int cc = idx / YC, c = idx % YC;
       const T s = ((ybuf[(0 * TC + cc) * YC + c] + ybuf[(1 * TC + cc) * YC + c]) +
                    ybuf[(2 * TC + cc) * YC + c]) + ybuf[(3 * TC + cc) * YC + c];
-      partY[((int64_t)rt * n_pad + col0 + cc) * R + c0 + c] = s;
+      partY[((int64_t)rt * n_pad + col0 + cc) * pR + c0 + c] = s;
     }
   }
 
   // Partial Gram V_j^T U_j over this tile's rows (double accumulation):
   // thread (pair, group) sums every G-th row of the tile for one (a, b), the
   // groups are then added in a fixed order.
-  if (ct == 0) {
+  if (UPD && ct == 0) {
     constexpr int NP = R * R;
     constexpr int G = NP >= 256 ? 1 : 256 / NP;
     double* gbuf = reinterpret_cast<double*>(tileP);
@@ -227,6 +239,55 @@ k_level_fused(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
       }
       __syncthreads();
     }
+  }
+}
+
+// ---------------------------------------------------------------- Gram (ranks > 16)
+// Partial V_j^T U_j over one row tile (double accumulation, rows in index
+// order): factor rows are staged in LDS 16 at a time; block (rt, pc) covers
+// pairs [pc * 256 * PPT, (pc + 1) * 256 * PPT) of the R x R result and thread
+// t owns the pairs base + t, base + t + 256, ...
+template <typename T, int R>
+constexpr int gram_ppt() { return (R * R + 255) / 256 < 16 ? (R * R + 255) / 256 : 16; }
+
+template <typename T, int R>
+__global__ void __launch_bounds__(256)
+k_gram(const T* __restrict__ Uj, const T* __restrict__ Vj, int W, int n_pad, int tile_rows,
+       double* __restrict__ partG) {
+  constexpr int RS = 16;
+  constexpr int PPT = gram_ppt<T, R>();
+  const int pbase = blockIdx.y * 256 * PPT;
+  __shared__ T su[RS][R];
+  __shared__ T sv[RS][R];
+  const int tid = threadIdx.x;
+  const int rt = blockIdx.x;
+  const int row0 = rt * tile_rows;
+  const int nrows = min(tile_rows, n_pad - row0);
+  double g[PPT];
+#pragma unroll
+  for (int e = 0; e < PPT; ++e) g[e] = 0.0;
+  for (int i0 = row0; i0 < row0 + nrows; i0 += RS) {
+    __syncthreads();
+    for (int idx = tid; idx < RS * R; idx += 256) {
+      const int rr = idx / R, c = idx % R;
+      su[rr][c] = Uj[(int64_t)(i0 + rr) * W + c];
+      sv[rr][c] = Vj[(int64_t)(i0 + rr) * W + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < PPT; ++e) {
+      const int pair = pbase + tid + 256 * e;
+      if (pair < R * R) {
+        const int a = pair / R, b = pair % R;
+#pragma unroll
+        for (int rr = 0; rr < RS; ++rr) g[e] = fma((double)sv[rr][a], (double)su[rr][b], g[e]);
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < PPT; ++e) {
+    const int pair = pbase + tid + 256 * e;
+    if (pair < R * R) partG[(int64_t)rt * R * R + pair] = g[e];
   }
 }
 
@@ -358,14 +419,44 @@ k_prep(const T* __restrict__ U, int64_t ldu, const T* __restrict__ V, int64_t ld
   slabV[i * W + (W - r_pad) + c] = in ? V[i * ldv + c] : T(0);
 }
 
+template <typename T, int R, int RB, bool UPD>
+hipError_t fused_launch(T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* Uj, const T* Vj,
+                        int W, T* partX, T* partY, double* partG, int pR, hipStream_t s) {
+  const dim3 grid((unsigned)(n_pad / tile_cols<T>()), (unsigned)((n_pad + tile_rows - 1) / tile_rows));
+  hipLaunchKernelGGL((k_level_fused<T, R, RB, UPD>), grid, dim3(256), 0, s, P, ldp, (int)n_pad, tile_rows,
+                     Uj, Vj, W, partX, partY, partG, pR);
+  return hipGetLastError();
+}
+
+template <typename T, int R>
+hipError_t update_r(T* P, int64_t ldp, int64_t n_pad, const T* Uj, const T* Vj, int W,
+                    hipStream_t s);
+
+// One level with rank R: for R <= 16 the fused pass; above, the skinny
+// products in 16-column chunks (read-only passes), the Gram, then the rank-R
+// update pass.
 template <typename T, int R>
 hipError_t fused_r(T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* Uj, const T* Vj,
                    int W, T* partX, T* partY, double* partG, hipStream_t s) {
-  constexpr int RB = kBlockRows;
-  const dim3 grid((unsigned)(n_pad / tile_cols<T>()), (unsigned)((n_pad + tile_rows - 1) / tile_rows));
-  hipLaunchKernelGGL((k_level_fused<T, R, RB>), grid, dim3(256), 0, s, P, ldp, (int)n_pad, tile_rows,
-                     Uj, Vj, W, partX, partY, partG);
-  return hipGetLastError();
+  if constexpr (R <= kMaxFusedRank) {
+    // 16-row blocks keep more rows in flight per wave; at R >= 8 the factor
+    // registers make 8-row blocks (more resident waves) faster.
+    constexpr int RB = R >= 8 ? 8 : 16;
+    return fused_launch<T, R, RB, true>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, R, s);
+  } else {
+    constexpr int RC = kMaxFusedRank;
+    for (int c0 = 0; c0 < R; c0 += RC) {
+      hipError_t e = fused_launch<T, RC, 8, false>(P, ldp, n_pad, tile_rows, Uj + c0, Vj + c0, W,
+                                                   partX + c0, partY + c0, nullptr, R, s);
+      if (e != hipSuccess) return e;
+    }
+    constexpr int per_block = 256 * gram_ppt<T, R>();
+    const dim3 ggrid((unsigned)((n_pad + tile_rows - 1) / tile_rows), (unsigned)((R * R + per_block - 1) / per_block));
+    hipLaunchKernelGGL((k_gram<T, R>), ggrid, dim3(256), 0, s, Uj, Vj, W, (int)n_pad, tile_rows, partG);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return update_r<T, R>(P, ldp, n_pad, Uj, Vj, W, s);
+  }
 }
 
 template <typename T, int R>
@@ -421,6 +512,9 @@ hipError_t launch_level_fused(int R, T* P, int64_t ldp, int64_t n_pad, int tile_
     case 4: return fused_r<T, 4>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s);
     case 8: return fused_r<T, 8>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s);
     case 16: return fused_r<T, 16>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s);
+    case 32: return fused_r<T, 32>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s);
+    case 64: return fused_r<T, 64>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s);
+    case 128: return fused_r<T, 128>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -434,6 +528,9 @@ hipError_t launch_level_tail(int R, const T* partX, const T* partY, const double
     case 4: return tail_r<T, 4>(partX, partY, partG, nct, nrt, n_pad, slabU, slabV, W, s);
     case 8: return tail_r<T, 8>(partX, partY, partG, nct, nrt, n_pad, slabU, slabV, W, s);
     case 16: return tail_r<T, 16>(partX, partY, partG, nct, nrt, n_pad, slabU, slabV, W, s);
+    case 32: return tail_r<T, 32>(partX, partY, partG, nct, nrt, n_pad, slabU, slabV, W, s);
+    case 64: return tail_r<T, 64>(partX, partY, partG, nct, nrt, n_pad, slabU, slabV, W, s);
+    case 128: return tail_r<T, 128>(partX, partY, partG, nct, nrt, n_pad, slabU, slabV, W, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -105,7 +105,10 @@ def test_fp32_ragged_n1000():
 
 @pytest.mark.parametrize("n,k,r,dtype", [(600, 8, 2, "f32"), (300, 4, 3, "f64"), (257, 2, 1, "f32"),
                                          (70, 16, 1, "f64"), (130, 1, 4, "f64"), (1024, 16, 1, "f32"),
-                                         (520, 4, 4, "f64"), (256, 2, 8, "f32")])
+                                         (520, 4, 4, "f64"), (256, 2, 8, "f32"),
+                                         # level ranks above 16: chunked skinny passes + Gram kernel
+                                         (600, 16, 4, "f32"), (520, 16, 8, "f64"), (300, 256, 1, "f64"),
+                                         (777, 32, 3, "f32")])
 def test_updates_shapes(n, k, r, dtype):
     lv = _lv()
     tol = 1e-10 if dtype == "f64" else 1e-4
