@@ -50,6 +50,27 @@ def parse():
     return p.parse_args()
 
 
+def counter_traffic(n, k, r):
+    """HBM bytes per fused launch from the committed rocprofv3 counter
+    summary, or None when the workload differs or the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "k_level_fused_n8192_k16_fp32_rank1_traffic.md")
+    src = os.path.join(ROOT, "paper_1403_6968_amd", "csrc", "lv_level.hip")
+    if (n, k, r) != (8192, 16, 1) or not os.path.exists(prof) or not os.path.exists(src):
+        return None
+    vals = {}
+    for line in open(prof):
+        if line.startswith("traffic_bytes_per_launch k_level_fused ="):
+            vals["bytes"] = float(line.split("=")[1].split()[0])
+        elif line.startswith("source_sha256_prefix ="):
+            vals["sha"] = line.split("=")[1].strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if vals.get("sha") != sha or "bytes" not in vals:
+        return None
+    return vals["bytes"]
+
+
 def cpu_baseline(A32, Us, Vs, k, budget_s):
     """The FP64 oracle (unchanged) timed on the host on a bounded sample of
     the same workload: as many of the first updates as fit in the budget."""
@@ -178,7 +199,7 @@ def main():
         bytes_launch = 2 * elem * n_pad * n_pad
         achieved = bytes_launch / (fused_ms * 1e-3) / 1e9
         result["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                              "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                              "frac": achieved / HBM_PEAK_GBPS, "traffic": counter_traffic(n, k, r),
                               "kernel": "k_level_fused (levels 0..m-1)",
                               "avg_launch_ms": fused_ms, "bytes_per_launch": bytes_launch}
         result["kernel_ms_per_update"] = {
@@ -189,8 +210,9 @@ def main():
         log(f"fused pass avg {fused_ms * 1e3:.1f} us -> {achieved:.0f} GB/s; "
             f"top update avg {top_ms * 1e3:.1f} us; per update {result['kernel_ms_per_update']}")
 
-    if not args.quick:
+    if True:
         # measured streaming ceiling: a plain device copy of one stored power's size
+        # (also the reference kernel for scaling HBM traffic counters)
         src = torch.empty(n_pad * n_pad, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         dst.copy_(src)
