@@ -71,8 +71,10 @@ typedef struct {
   int32_t r_max;      /* largest update rank accepted                      */
   int32_t mode;       /* lv_mode                                           */
   int64_t updates;    /* updates applied since creation                    */
-  int64_t reanchors;  /* re-evaluations from the current A                 */
+  int64_t reanchors;  /* re-evaluations requested by lv_view_reanchor       */
   size_t footprint;   /* workspace bytes in use                            */
+  int64_t drift_reanchors; /* re-evaluations triggered by lv_view_drift_check */
+  double last_residual;    /* max_j rho_j of the last drift check          */
 } lv_stats;
 
 /* Human-readable name of a status code (static string). */
@@ -131,6 +133,27 @@ const void* lv_view_data(const lv_view* v, int power, int64_t* ld);
  * repeated squaring in double precision, discarding accumulated rounding. */
 lv_status lv_view_reanchor(lv_view* v, void* stream);
 
+/* Copy out (n x n, leading dimension lds >= n, device) into stored power
+ * A^power: restores a checkpoint written with lv_view_read, or lets a test
+ * perturb a stored power.  The caller is responsible for consistency of the
+ * chain afterwards (see lv_view_drift_check). */
+lv_status lv_view_write(lv_view* v, int power, const void* src, int64_t lds, void* stream);
+
+/* Drift check of the stored chain (the exponential model defines
+ * P_{2i} = P_i P_i, Table 1; incremental updates keep it only up to
+ * accumulated rounding).  For z (n doubles, device) and every level
+ * j = 0..m-1 (level j stores A^(2^j)):
+ *     rho_j = max|P_{j+1} z - P_j (P_j z)| / max|P_{j+1} z|
+ * with double accumulation over the stored values.  When some rho_j > tau
+ * (or is not finite), every stored power is recomputed from the stored A by
+ * repeated squaring in double precision (as lv_view_reanchor); the decision
+ * is taken on the device, the host does not wait.  residuals (device, m
+ * doubles) receives rho_j if non-null.  tau >= 0.  For k = 1 there is nothing
+ * to check.  lv_view_stats reports the count of triggered re-evaluations and
+ * the last max_j rho_j (it waits for the device to read them). */
+lv_status lv_view_drift_check(lv_view* v, const void* z, double tau, double* residuals,
+                              void* stream);
+
 /* Per-kernel timing of a view's updates (diagnostics).  While enabled, the
  * library brackets every level-pass launch with HIP events recorded on the
  * update's stream; lv_view_timing waits for those events, returns the
@@ -148,7 +171,8 @@ typedef struct {
 lv_status lv_view_set_timing(lv_view* v, int enable);
 lv_status lv_view_timing(lv_view* v, lv_timing* out);
 
-/* Counters and shape of a view (host). */
+/* Counters and shape of a view.  Reads the drift counters from the device
+ * (a synchronous copy). */
 lv_status lv_view_stats(const lv_view* v, lv_stats* out);
 
 /* Release the handle (the caller frees the workspace afterwards, once the

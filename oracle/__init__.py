@@ -23,6 +23,7 @@ from .linview_oracle import (  # noqa: F401
     power_rows,
     power_cols,
     brute_power,
+    chain_residuals,
     maxrel,
     deltarel,
     OpCounter,

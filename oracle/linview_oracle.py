@@ -156,6 +156,21 @@ def brute_power(A, k: int):
     return R
 
 
+def chain_residuals(P: dict[int, np.ndarray], z: np.ndarray) -> list[float]:
+    """How far stored powers are from the exponential model's defining
+    relation P_{2i} = P_i P_i (Table 1), probed with a vector z:
+    rho_i = max|P_{2i} z - P_i (P_i z)| / max|P_{2i} z| for i = 1, 2, ..., k/2."""
+    out = []
+    z = np.asarray(z, dtype=np.float64)
+    for i in levels(max(P))[:-1]:
+        c = P[2 * i] @ z
+        b = P[i] @ (P[i] @ z)
+        den = float(np.max(np.abs(c)))
+        num = float(np.max(np.abs(c - b)))
+        out.append(num / den if den > 0 else (math.inf if num > 0 else 0.0))
+    return out
+
+
 def maxrel(X: np.ndarray, R: np.ndarray) -> float:
     """Normwise max-norm relative error max|X - R| / max|R|."""
     X = np.asarray(X, dtype=np.float64)

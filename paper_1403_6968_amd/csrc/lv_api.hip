@@ -46,6 +46,7 @@ struct Layout {
   size_t partY[kMaxLevel] = {};
   size_t partG[kMaxLevel] = {};
   size_t scratch[2] = {};
+  size_t probe = 0;  // zpad | Pz (m+1 vectors) | PPz (m vectors) | residuals | gate | counter
   size_t total = 0;
 };
 
@@ -90,6 +91,8 @@ Layout make_layout(int64_t n, int k, int r_max, lv_mode mode) {
     L.scratch[0] = off; off = align_up(off + dmat);
     L.scratch[1] = off; off = align_up(off + dmat);
   }
+  L.probe = off;
+  off = align_up(off + (size_t)(2 * L.m + 2) * L.n_pad * sizeof(double) + kMaxLevel * sizeof(double) + 256);
   L.total = off;
   return L;
 }
@@ -126,37 +129,66 @@ struct lv_view {
   template <typename T> T* partY(int j) const { return reinterpret_cast<T*>(base + L.partY[j]); }
   double* partG(int j) const { return reinterpret_cast<double*>(base + L.partG[j]); }
   double* scratch(int i) const { return reinterpret_cast<double*>(base + L.scratch[i]); }
+  double* zpad() const { return reinterpret_cast<double*>(base + L.probe); }
+  double* Pz(int j) const { return zpad() + (size_t)(1 + j) * L.n_pad; }
+  double* PPz(int j) const { return zpad() + (size_t)(L.m + 2 + j) * L.n_pad; }
+  double* residuals() const { return zpad() + (size_t)(2 * L.m + 2) * L.n_pad; }
+  int* gate() const { return reinterpret_cast<int*>(residuals() + kMaxLevel); }
+  unsigned long long* drift_counter() const {
+    return reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(residuals() + kMaxLevel) + 64);
+  }
 };
 
 namespace {
 
 // Stored powers P_1..P_m from P_0 by repeated squaring in double precision
 // (Table 1, exponential model), then one rounding to the storage type.
+// With a non-null gate every kernel of the chain runs only if *gate != 0.
 template <typename T>
-lv_status build_chain(lv_view* v, hipStream_t s) {
+lv_status build_chain(lv_view* v, hipStream_t s, const int* gate = nullptr) {
   const Layout& L = v->L;
   if (L.m == 0) return LV_OK;
   if constexpr (sizeof(T) == 8) {
     for (int j = 1; j <= L.m; ++j) {
       lv_status st = hip_check(launch_gemm<double>(v->P<double>(j - 1), L.ldp, v->P<double>(j - 1), L.ldp,
-                                                   v->P<double>(j), L.ldp, L.n_pad, s), "gemm f64");
+                                                   v->P<double>(j), L.ldp, L.n_pad, s, gate), "gemm f64");
       if (st != LV_OK) return st;
     }
   } else {
     lv_status st = hip_check(launch_copy_pad<float, double>(v->P<float>(0), L.ldp, L.n_pad, v->scratch(0),
-                                                            L.n_pad, L.n_pad, s), "widen P_1");
+                                                            L.n_pad, L.n_pad, s, gate), "widen P_1");
     if (st != LV_OK) return st;
     for (int j = 1; j <= L.m; ++j) {
       double* src = v->scratch((j - 1) & 1);
       double* dst = v->scratch(j & 1);
-      st = hip_check(launch_gemm<double>(src, L.n_pad, src, L.n_pad, dst, L.n_pad, L.n_pad, s), "gemm f64");
+      st = hip_check(launch_gemm<double>(src, L.n_pad, src, L.n_pad, dst, L.n_pad, L.n_pad, s, gate),
+                     "gemm f64");
       if (st != LV_OK) return st;
-      st = hip_check(launch_copy_pad<double, float>(dst, L.n_pad, L.n_pad, v->P<float>(j), L.ldp, L.n_pad, s),
+      st = hip_check(launch_copy_pad<double, float>(dst, L.n_pad, L.n_pad, v->P<float>(j), L.ldp, L.n_pad, s,
+                                                    gate),
                      "round P");
       if (st != LV_OK) return st;
     }
   }
   return LV_OK;
+}
+
+// Drift check: P_j z for every level, P_j (P_j z) below the top, the
+// residual kernel (gate + counter), then the gated squaring chain.
+template <typename T>
+lv_status drift_check(lv_view* v, const double* z, double tau, hipStream_t s) {
+  const Layout& L = v->L;
+  lv_status st = hip_check(launch_vec_pad(z, v->n, v->zpad(), L.n_pad, s), "pad z");
+  for (int j = 0; j <= L.m && st == LV_OK; ++j)
+    st = hip_check(launch_matvec<T>(v->P<T>(j), L.ldp, L.n_pad, v->zpad(), v->Pz(j), s), "P z");
+  for (int j = 0; j < L.m && st == LV_OK; ++j)
+    st = hip_check(launch_matvec<T>(v->P<T>(j), L.ldp, L.n_pad, v->Pz(j), v->PPz(j), s), "P P z");
+  if (st != LV_OK) return st;
+  st = hip_check(launch_drift_residual(v->zpad() + L.n_pad, v->zpad() + (size_t)(L.m + 2) * L.n_pad, L.m,
+                                       L.n_pad, tau, v->residuals(), v->gate(), v->drift_counter(), s),
+                 "residual");
+  if (st != LV_OK) return st;
+  return build_chain<T>(v, s, v->gate());
 }
 
 hipEvent_t take_event(lv_view* v) {
@@ -304,6 +336,8 @@ lv_status lv_view_create(const void* A, int64_t n, int64_t lda, int k, int r_max
                                                  L.ldp, L.n_pad, s), "copy A");
     if (st == LV_OK) st = build_chain<float>(v, s);
   }
+  if (st == LV_OK)
+    st = hip_check(hipMemsetAsync(v->gate(), 0, 128, s), "clear drift counters");
   if (st != LV_OK) { delete v; return st; }
   *out = v;
   return LV_OK;
@@ -389,6 +423,34 @@ lv_status lv_view_reanchor(lv_view* v, void* stream) {
   return st;
 }
 
+lv_status lv_view_drift_check(lv_view* v, const void* z, double tau, double* residuals, void* stream) {
+  g_err[0] = 0;
+  if (!v || !z) return fail(LV_EINVAL, "view or z is NULL");
+  if (!(tau >= 0.0)) return fail(LV_EINVAL, "tau must be >= 0");
+  if (v->L.m == 0) return LV_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  lv_status st = v->mode == LV_FP64 ? drift_check<double>(v, static_cast<const double*>(z), tau, s)
+                                    : drift_check<float>(v, static_cast<const double*>(z), tau, s);
+  if (st != LV_OK) return st;
+  if (residuals)
+    st = hip_check(hipMemcpyAsync(residuals, v->residuals(), sizeof(double) * v->L.m, hipMemcpyDeviceToDevice, s),
+                   "copy residuals");
+  return st;
+}
+
+lv_status lv_view_write(lv_view* v, int power, const void* src, int64_t lds, void* stream) {
+  g_err[0] = 0;
+  const int j = power_level(v, power);
+  if (j < 0) return fail(LV_EINVAL, "power %d is not stored", power);
+  if (!src) return fail(LV_EINVAL, "src is NULL");
+  if (lds < v->n) return fail(LV_EINVAL, "lds < n");
+  const size_t es = v->L.elem;
+  char* dst = v->base + v->L.P[j];
+  return hip_check(hipMemcpy2DAsync(dst, v->L.ldp * es, src, lds * es, v->n * es, v->n,
+                                    hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)),
+                   "write");
+}
+
 lv_status lv_view_stats(const lv_view* v, lv_stats* out) {
   if (!v || !out) return fail(LV_EINVAL, "view or out is NULL");
   out->n = v->n;
@@ -401,6 +463,15 @@ lv_status lv_view_stats(const lv_view* v, lv_stats* out) {
   out->updates = v->updates;
   out->reanchors = v->reanchors;
   out->footprint = v->L.total;
+  unsigned long long cnt = 0;
+  double res[kMaxLevel] = {};
+  if (hipMemcpy(&cnt, v->drift_counter(), sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(res, v->residuals(), sizeof(double) * (v->L.m > 0 ? v->L.m : 1), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(LV_EDEVICE, "reading drift counters failed");
+  out->drift_reanchors = (int64_t)cnt;
+  double mx = 0.0;
+  for (int j = 0; j < v->L.m; ++j) mx = res[j] > mx || res[j] != res[j] ? res[j] : mx;
+  out->last_residual = mx;
   return LV_OK;
 }
 

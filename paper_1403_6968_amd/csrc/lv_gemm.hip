@@ -49,7 +49,8 @@ constexpr int BM = 128, BN = 128, BK = 16;
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_gemm(const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ldb,
-       T* __restrict__ C, int64_t ldc, int n_pad) {
+       T* __restrict__ C, int64_t ldc, int n_pad, const int* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
   using F = Mfma<T>;
   constexpr int M = F::M;
   constexpr int NB = 64 / M;           // MFMA blocks per wave per dimension
@@ -128,16 +129,16 @@ k_gemm(const T* __restrict__ A, int64_t lda, const T* __restrict__ B, int64_t ld
 
 template <typename T>
 hipError_t launch_gemm(const T* A, int64_t lda, const T* B, int64_t ldb, T* C, int64_t ldc,
-                       int64_t n_pad, hipStream_t s) {
+                       int64_t n_pad, hipStream_t s, const int* gate) {
   if (n_pad % BM != 0) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(n_pad / BN), (unsigned)(n_pad / BM));
-  hipLaunchKernelGGL((k_gemm<T>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, (int)n_pad);
+  hipLaunchKernelGGL((k_gemm<T>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, (int)n_pad, gate);
   return hipGetLastError();
 }
 
 template hipError_t launch_gemm<double>(const double*, int64_t, const double*, int64_t, double*,
-                                        int64_t, int64_t, hipStream_t);
+                                        int64_t, int64_t, hipStream_t, const int*);
 template hipError_t launch_gemm<float>(const float*, int64_t, const float*, int64_t, float*,
-                                       int64_t, int64_t, hipStream_t);
+                                       int64_t, int64_t, hipStream_t, const int*);
 
 }  // namespace lv

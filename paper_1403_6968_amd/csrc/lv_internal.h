@@ -30,9 +30,11 @@ inline int tile_cols_bytes(int elem) { return 64 * (16 / elem); }
 // ---- launchers (stream-ordered; return the launch status) ----
 
 // dst[i*ldd + j] = (i < n && j < n) ? src[i*lds + j] : 0 for i, j < n_pad.
+// With a non-null `gate`, the kernel does nothing unless *gate != 0 (read on
+// the device, so a decision taken by an earlier kernel needs no host sync).
 template <typename Tin, typename Tout>
 hipError_t launch_copy_pad(const Tin* src, int64_t lds, int64_t n, Tout* dst, int64_t ldd,
-                           int64_t n_pad, hipStream_t s);
+                           int64_t n_pad, hipStream_t s, const int* gate = nullptr);
 
 // Factor slab set-up: slab U columns [0, r_pad) and slab V columns
 // [W - r_pad, W) receive U and V (n x r), zero-filled up to r_pad columns and
@@ -65,6 +67,23 @@ hipError_t launch_level_update(int R, T* P, int64_t ldp, int64_t n_pad, const T*
 // on MFMA (double: 16x16x4 f64; float: 32x32x2 f32).
 template <typename T>
 hipError_t launch_gemm(const T* A, int64_t lda, const T* B, int64_t ldb, T* C, int64_t ldc,
-                       int64_t n_pad, hipStream_t s);
+                       int64_t n_pad, hipStream_t s, const int* gate = nullptr);
+
+// ---- drift check (FP64 test of the stored chain P_{j+1} = P_j P_j)
+
+// x = z zero-padded to n_pad (double).
+hipError_t launch_vec_pad(const double* z, int64_t n, double* x, int64_t n_pad, hipStream_t s);
+
+// y = P x with double accumulation, P n_pad x n_pad (ld ldp) of type T.
+template <typename T>
+hipError_t launch_matvec(const T* P, int64_t ldp, int64_t n_pad, const double* x, double* y,
+                         hipStream_t s);
+
+// rho_j = max|Pz[j+1] - PPz[j]| / max|Pz[j+1]| for j < m (Pz, PPz: n_pad
+// doubles per level); *gate = (some rho_j > tau or not finite); the
+// counter is incremented when the gate opens.
+hipError_t launch_drift_residual(const double* Pz, const double* PPz, int m, int64_t n_pad,
+                                 double tau, double* residuals, int* gate,
+                                 unsigned long long* counter, hipStream_t s);
 
 }  // namespace lv

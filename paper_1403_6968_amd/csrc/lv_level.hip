@@ -398,7 +398,8 @@ k_level_update(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
 template <typename Tin, typename Tout>
 __global__ void __launch_bounds__(256)
 k_copy_pad(const Tin* __restrict__ src, int64_t lds, int64_t n, Tout* __restrict__ dst,
-           int64_t ldd, int64_t n_pad) {
+           int64_t ldd, int64_t n_pad, const int* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
   const int64_t i = blockIdx.x;
   const int64_t j = (int64_t)blockIdx.y * 256 + threadIdx.x;
   if (j >= n_pad) return;
@@ -484,9 +485,9 @@ hipError_t update_r(T* P, int64_t ldp, int64_t n_pad, const T* Uj, const T* Vj, 
 
 template <typename Tin, typename Tout>
 hipError_t launch_copy_pad(const Tin* src, int64_t lds, int64_t n, Tout* dst, int64_t ldd,
-                           int64_t n_pad, hipStream_t s) {
+                           int64_t n_pad, hipStream_t s, const int* gate) {
   const dim3 grid((unsigned)n_pad, (unsigned)((n_pad + 255) / 256));
-  hipLaunchKernelGGL((k_copy_pad<Tin, Tout>), grid, dim3(256), 0, s, src, lds, n, dst, ldd, n_pad);
+  hipLaunchKernelGGL((k_copy_pad<Tin, Tout>), grid, dim3(256), 0, s, src, lds, n, dst, ldd, n_pad, gate);
   return hipGetLastError();
 }
 
@@ -567,9 +568,9 @@ LV_INST(float)
 LV_INST(double)
 #undef LV_INST
 
-template hipError_t launch_copy_pad<float, float>(const float*, int64_t, int64_t, float*, int64_t, int64_t, hipStream_t);
-template hipError_t launch_copy_pad<double, double>(const double*, int64_t, int64_t, double*, int64_t, int64_t, hipStream_t);
-template hipError_t launch_copy_pad<float, double>(const float*, int64_t, int64_t, double*, int64_t, int64_t, hipStream_t);
-template hipError_t launch_copy_pad<double, float>(const double*, int64_t, int64_t, float*, int64_t, int64_t, hipStream_t);
+template hipError_t launch_copy_pad<float, float>(const float*, int64_t, int64_t, float*, int64_t, int64_t, hipStream_t, const int*);
+template hipError_t launch_copy_pad<double, double>(const double*, int64_t, int64_t, double*, int64_t, int64_t, hipStream_t, const int*);
+template hipError_t launch_copy_pad<float, double>(const float*, int64_t, int64_t, double*, int64_t, int64_t, hipStream_t, const int*);
+template hipError_t launch_copy_pad<double, float>(const double*, int64_t, int64_t, float*, int64_t, int64_t, hipStream_t, const int*);
 
 }  // namespace lv

@@ -29,7 +29,7 @@ EXPORTED = (
     "lv_status_str", "lv_last_error", "lv_view_footprint", "lv_view_create",
     "lv_view_update", "lv_view_update_batch", "lv_view_read", "lv_view_data",
     "lv_view_reanchor", "lv_view_stats", "lv_view_destroy", "lv_reeval_footprint",
-    "lv_reeval", "lv_view_set_timing", "lv_view_timing",
+    "lv_reeval", "lv_view_set_timing", "lv_view_timing", "lv_view_write", "lv_view_drift_check",
 )
 
 
@@ -44,7 +44,8 @@ class lv_stats(ctypes.Structure):
         ("n", ctypes.c_int64), ("n_pad", ctypes.c_int64), ("ld", ctypes.c_int64),
         ("k", ctypes.c_int32), ("levels", ctypes.c_int32), ("r_max", ctypes.c_int32),
         ("mode", ctypes.c_int32), ("updates", ctypes.c_int64), ("reanchors", ctypes.c_int64),
-        ("footprint", ctypes.c_size_t),
+        ("footprint", ctypes.c_size_t), ("drift_reanchors", ctypes.c_int64),
+        ("last_residual", ctypes.c_double),
     ]
 
 
@@ -85,6 +86,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "lv_reeval_footprint": (SZ, [I64, I32, I32]),
         "lv_reeval": (I32, [P, I64, I64, I32, P, P, I64, I64, I64, I32, P, I64, P, SZ, P]),
         "lv_view_set_timing": (I32, [P, I32]),
+        "lv_view_write": (I32, [P, I32, P, I64, P]),
+        "lv_view_drift_check": (I32, [P, P, c.c_double, P, P]),
         "lv_view_timing": (I32, [P, c.POINTER(lv_timing)]),
     }
     for name, (res, args) in sig.items():
@@ -179,6 +182,21 @@ def lv_view_read(view, power: int, out: torch.Tensor, dtype, stream=None) -> Non
     _check(load().lv_view_read(view, power, o, ldo, _stream(stream, out.device)))
 
 
+def lv_view_write(view, power: int, src: torch.Tensor, dtype, stream=None) -> None:
+    a, lds = _mat(src, dtype, "src")
+    _check(load().lv_view_write(view, power, a, lds, _stream(stream, src.device)))
+
+
+def lv_view_drift_check(view, z: torch.Tensor, tau: float, residuals=None, stream=None) -> None:
+    if z.dtype != torch.float64 or z.device.type != "cuda" or not z.is_contiguous():
+        raise TypeError("z must be a contiguous float64 device vector")
+    if residuals is not None and (residuals.dtype != torch.float64 or not residuals.is_contiguous()):
+        raise TypeError("residuals must be a contiguous float64 device vector")
+    _check(load().lv_view_drift_check(view, z.data_ptr(), float(tau),
+                                      None if residuals is None else residuals.data_ptr(),
+                                      _stream(stream, z.device)))
+
+
 def lv_view_data(view, power: int):
     ld = ctypes.c_int64()
     p = load().lv_view_data(view, power, ctypes.byref(ld))
@@ -266,6 +284,17 @@ class View:
 
     def reanchor(self, stream=None) -> None:
         lv_view_reanchor(self.handle, stream, self.device)
+
+    def write(self, power: int, src: torch.Tensor, stream=None) -> None:
+        lv_view_write(self.handle, power, src, self.dtype, stream)
+
+    def drift_check(self, z: torch.Tensor, tau: float, stream=None) -> torch.Tensor:
+        """Residuals rho_j (device tensor, one per level below the top);
+        re-anchors on the device when one exceeds tau."""
+        m = len(self.powers()) - 1
+        res = torch.zeros(max(m, 1), dtype=torch.float64, device=self.device)
+        lv_view_drift_check(self.handle, z, tau, res if m > 0 else None, stream)
+        return res[:m]
 
     def stats(self) -> dict:
         return lv_view_stats(self.handle)

@@ -93,6 +93,11 @@ def test_bench_workload_sampled_every_100_updates():
             assert mr < 1e-4, f"P_{i} maxrel {mr:.3e} after {t}"
             assert dr < dtol, f"P_{i} deltarel {dr:.3e} >= {dtol:.3e} after {t}"
         note(f"after {t0 + every}: maxrel/deltarel " + " ".join(msg))
+    # the stored chain after 1000 FP32 updates still satisfies P_{2i} = P_i P_i
+    z = dev(synth.rng(0, 2, 9).standard_normal(n), torch.float64)
+    res = view.drift_check(z, tau=1e-3).cpu().numpy()
+    note(f"drift residuals after {T} updates: {res}")
+    assert res.max() < 1e-3 and view.stats()["drift_reanchors"] == 0
     # a stale view (the last 100 updates missed) fails the bound
     for i in powers:
         ref = r[i][0].ravel()

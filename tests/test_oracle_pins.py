@@ -409,3 +409,29 @@ def test_pins_catch_planted_mistakes(kind):
 
 def test_unmutated_copy_passes():
     assert all(_exact_incr_check(_mutant("none"), n=4, k=8, r=1 + s % 2, seed=s) for s in range(4))
+
+
+# ----------------------------------------------------------------- chain residuals
+
+def test_chain_residuals_pins():
+    """Residuals of the defining relation P_{2i} = P_i P_i: zero (to rounding)
+    for a re-evaluated chain, exactly zero on integers, and for a
+    perturbation delta * e_a e_b^T of P_i probed with z = e_b the closed form
+    of the two residuals that see it."""
+    n, k = 30, 16
+    A = synth.gaussian_matrix(n, seed=14)
+    P = O.reeval(A, k)
+    assert max(O.chain_residuals(P, np.ones(n))) < 1e-14
+    Ai = synth.integer_matrix((6, 6), -1, 1, seed=15)
+    Pi = O.reeval(Ai, 8)
+    assert O.chain_residuals(Pi, np.arange(6.0)) == [0.0, 0.0, 0.0]
+    # perturb P_2 at (a, b) by delta; z = e_b
+    a, b, delta = 2, 5, 0.5
+    Q = {i: M.copy() for i, M in P.items()}
+    Q[2][a, b] += delta
+    z = np.zeros(n); z[b] = 1.0
+    res = O.chain_residuals(Q, z)
+    c0 = Q[2] @ z                       # rho_1: P_2' z vs A (A z)
+    assert res[0] == pytest.approx(delta / np.max(np.abs(c0)), rel=1e-12)
+    assert res[2] < 1e-13               # P_8 / P_4 relation untouched
+    assert res[1] > 1e-3                # P_4 vs P_2' P_2' sees it
