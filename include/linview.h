@@ -179,6 +179,48 @@ lv_status lv_view_stats(const lv_view* v, lv_stats* out);
  * stream has drained).  NULL is ignored. */
 void lv_view_destroy(lv_view* v);
 
+/* ---------------------------------------------------------------------
+ * Batched rounds over many views (one update per view per round).
+ *
+ * A batch is built over existing views of one mode (uneven n, k and r_max
+ * allowed).  Each round applies, to every view, the update staged in that
+ * view's input buffers (lv_batch_inputs): U, V of n rows and r_max columns,
+ * row-major with leading dimension r_max (a view without an update this
+ * round stages zeros, which leaves it unchanged bit for bit).  The round is
+ * one launch from the host: a HIP graph captured at lv_batch_create and
+ * replayed by lv_batch_update.  Inside it, every level step of all views
+ * runs as one multi-view launch per level rank (work-groups map to
+ * (view, tile) through descriptor tables in the workspace), so small views
+ * share the GPU instead of launching separately.  The per-view results equal
+ * lv_view_update bit for bit.
+ * --------------------------------------------------------------------- */
+typedef struct lv_batch lv_batch;
+
+/* Workspace bytes for a batch over `views` (count >= 1); 0 if invalid. */
+size_t lv_batch_footprint(lv_view* const* views, int count);
+
+/* Build the batch (descriptor tables, input staging, the captured round).
+ * workspace: device, >= lv_batch_footprint bytes, 256-byte aligned,
+ * borrowed until lv_batch_destroy.  The views must outlive the batch and
+ * must not be updated through other calls while the batch is used. */
+lv_status lv_batch_create(lv_view* const* views, int count, void* workspace, size_t ws_bytes,
+                          void* stream, lv_batch** out);
+
+/* Device input buffers of view i (U and V, n x r_max, leading dimension r_max). */
+lv_status lv_batch_inputs(const lv_batch* b, int i, void** U, void** V, int64_t* ld);
+
+/* Stage the next update of view i: U, V n x r (device, leading dimensions
+ * ldu, ldv >= r), 0 <= r <= r_max; columns r..r_max-1 of the staging are
+ * zeroed (r = 0 stages "no update"; U and V may then be NULL). */
+lv_status lv_batch_stage(lv_batch* b, int i, const void* U, const void* V, int64_t r, int64_t ldu,
+                         int64_t ldv, void* stream);
+
+/* One round: every view applies its staged update (stream-ordered). */
+lv_status lv_batch_update(lv_batch* b, void* stream);
+
+/* Release the batch (after the stream has drained).  NULL is ignored. */
+void lv_batch_destroy(lv_batch* b);
+
 /* Workspace bytes for lv_reeval at order n; 0 if invalid. */
 size_t lv_reeval_footprint(int64_t n, int r_max, lv_mode mode);
 

@@ -27,6 +27,44 @@ inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 template <typename T> constexpr int tile_cols() { return 64 * (16 / (int)sizeof(T)); }
 inline int tile_cols_bytes(int elem) { return 64 * (16 / elem); }
 
+// ---- work descriptors ----
+// One descriptor per (view, kernel) in a launch.  A single-view launch passes
+// one descriptor by value; a multi-view launch passes a device array sorted
+// by block_begin (the first work-group of each view) and the work-group
+// finds its view by binary search.
+
+template <typename T> struct FusedDesc {
+  T* P; int64_t ldp; int n_pad; int tile_rows;
+  const T* Uj; const T* Vj; int W;      // U_j = Uj[i*W + c], V_j = Vj[i*W + c]
+  T* partX; T* partY; double* partG; int pR;
+  int nct; int block_begin;             // blocks: nct x ceil(n_pad / tile_rows)
+};
+template <typename T> struct GramDesc {
+  const T* Uj; const T* Vj; int W; int n_pad; int tile_rows; double* partG;
+  int nrt; int block_begin;             // blocks: nrt x pair chunks
+};
+template <typename T> struct TailDesc {
+  const T* partX; const T* partY; const double* partG; int nct; int nrt; int n_pad;
+  T* slabU; T* slabV; int W; int block_begin;   // blocks: ceil(n_pad * R / 256)
+};
+template <typename T> struct UpdateDesc {
+  T* P; int64_t ldp; int n_pad; int tile_rows; const T* Uj; const T* Vj; int W;
+  int nct; int block_begin;             // blocks: nct x ceil(n_pad / tile_rows)
+};
+template <typename T> struct PrepDesc {
+  const T* U; int64_t ldu; const T* V; int64_t ldv; int64_t n; int r; int r_pad;
+  T* slabU; T* slabV; int W; int64_t n_pad; int block_begin;   // blocks: ceil(n_pad * r_pad / 256)
+};
+
+// Rows per tile of the update-only pass.
+constexpr int kUpdateTileRows = 256;
+// Work-groups of a tail launch / Gram pairs per work-group for rank R.
+inline int tail_blocks(int64_t n_pad, int R) { return (int)((n_pad * R + 255) / 256); }
+inline int gram_pairs_per_block(int R) {
+  const int ppt = (R * R + 255) / 256 < 16 ? (R * R + 255) / 256 : 16;
+  return 256 * ppt;
+}
+
 // ---- launchers (stream-ordered; return the launch status) ----
 
 // dst[i*ldd + j] = (i < n && j < n) ? src[i*lds + j] : 0 for i, j < n_pad.
@@ -62,6 +100,20 @@ hipError_t launch_level_tail(int R, const T* partX, const T* partY, const double
 template <typename T>
 hipError_t launch_level_update(int R, T* P, int64_t ldp, int64_t n_pad, const T* slabU,
                                const T* slabV, int W, hipStream_t s);
+
+// Multi-view launches over device descriptor arrays (nd descriptors,
+// `blocks` work-groups in total).  `chunk` selects the read-only skinny pass
+// over 16 factor columns used for level ranks above kMaxFusedRank.
+template <typename T>
+hipError_t launch_fused_multi(int R, bool chunk, const FusedDesc<T>* ds, int nd, int blocks, hipStream_t s);
+template <typename T>
+hipError_t launch_gram_multi(int R, const GramDesc<T>* ds, int nd, int blocks, hipStream_t s);
+template <typename T>
+hipError_t launch_tail_multi(int R, const TailDesc<T>* ds, int nd, int blocks, hipStream_t s);
+template <typename T>
+hipError_t launch_update_multi(int R, const UpdateDesc<T>* ds, int nd, int blocks, hipStream_t s);
+template <typename T>
+hipError_t launch_prep_multi(const PrepDesc<T>* ds, int nd, int blocks, hipStream_t s);
 
 // C = A * B for n_pad x n_pad row-major matrices (n_pad a multiple of 256),
 // on MFMA (double: 16x16x4 f64; float: 32x32x2 f32).

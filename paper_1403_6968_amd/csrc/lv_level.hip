@@ -40,6 +40,18 @@ __device__ __forceinline__ int wave_id() {
   return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
 
+// Index of the descriptor whose block range holds block `b` (descriptors are
+// sorted by block_begin, the first starts at 0): binary search, uniform.
+template <typename D>
+__device__ __forceinline__ int find_desc(const D* __restrict__ ds, int nd, int b) {
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ds[mid].block_begin <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 // ---------------------------------------------------------------- fused pass
 //
 // Block: 256 threads (4 waves).  Tile: tile_rows x TC, TC = 64 lanes x 16 B.
@@ -63,10 +75,11 @@ __device__ __forceinline__ int wave_id() {
 // stride pR at the chunk's column offset), the rank update and the Gram done
 // by k_level_update and k_gram.
 template <typename T, int R, int RB, bool UPD>
-__global__ void __launch_bounds__(256)
-k_level_fused(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
-              const T* __restrict__ Uj, const T* __restrict__ Vj, int W,
-              T* __restrict__ partX, T* __restrict__ partY, double* __restrict__ partG, int pR) {
+__device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp, const int n_pad,
+                                           const int tile_rows, const T* __restrict__ Uj,
+                                           const T* __restrict__ Vj, const int W, T* __restrict__ partX,
+                                           T* __restrict__ partY, double* __restrict__ partG, const int pR,
+                                           const int ct, const int rt) {
   constexpr int EPL = 16 / (int)sizeof(T);
   constexpr int TC = 64 * EPL;
   constexpr int NQ = 64 / RB;           // column slices in Phase B
@@ -80,8 +93,6 @@ k_level_fused(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = wave_id();
-  const int ct = blockIdx.x;
-  const int rt = blockIdx.y;
   const int col0 = ct * TC;
   const int row0 = rt * tile_rows;
   const int nrows = min(tile_rows, n_pad - row0);
@@ -242,6 +253,21 @@ k_level_fused(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
   }
 }
 
+template <typename T, int R, int RB, bool UPD>
+__global__ void __launch_bounds__(256) k_level_fused(const FusedDesc<T> d) {
+  fused_body<T, R, RB, UPD>(d.P, d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.partX, d.partY, d.partG, d.pR,
+                            blockIdx.x, blockIdx.y);
+}
+
+template <typename T, int R, int RB, bool UPD>
+__global__ void __launch_bounds__(256) k_level_fused_multi(const FusedDesc<T>* __restrict__ ds, int nd) {
+  const int v = find_desc(ds, nd, (int)blockIdx.x);
+  const FusedDesc<T> d = ds[v];
+  const int local = (int)blockIdx.x - d.block_begin;
+  fused_body<T, R, RB, UPD>(d.P, d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.partX, d.partY, d.partG, d.pR,
+                            local % d.nct, local / d.nct);
+}
+
 // ---------------------------------------------------------------- Gram (ranks > 16)
 // Partial V_j^T U_j over one row tile (double accumulation, rows in index
 // order): factor rows are staged in LDS 16 at a time; block (rt, pc) covers
@@ -251,16 +277,15 @@ template <typename T, int R>
 constexpr int gram_ppt() { return (R * R + 255) / 256 < 16 ? (R * R + 255) / 256 : 16; }
 
 template <typename T, int R>
-__global__ void __launch_bounds__(256)
-k_gram(const T* __restrict__ Uj, const T* __restrict__ Vj, int W, int n_pad, int tile_rows,
-       double* __restrict__ partG) {
+__device__ __forceinline__ void gram_body(const T* __restrict__ Uj, const T* __restrict__ Vj, const int W,
+                                          const int n_pad, const int tile_rows, double* __restrict__ partG,
+                                          const int rt, const int pc) {
   constexpr int RS = 16;
   constexpr int PPT = gram_ppt<T, R>();
-  const int pbase = blockIdx.y * 256 * PPT;
+  const int pbase = pc * 256 * PPT;
   __shared__ T su[RS][R];
   __shared__ T sv[RS][R];
   const int tid = threadIdx.x;
-  const int rt = blockIdx.x;
   const int row0 = rt * tile_rows;
   const int nrows = min(tile_rows, n_pad - row0);
   double g[PPT];
@@ -291,15 +316,30 @@ k_gram(const T* __restrict__ Uj, const T* __restrict__ Vj, int W, int n_pad, int
   }
 }
 
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_gram(const GramDesc<T> d) {
+  gram_body<T, R>(d.Uj, d.Vj, d.W, d.n_pad, d.tile_rows, d.partG, blockIdx.x, blockIdx.y);
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_gram_multi(const GramDesc<T>* __restrict__ ds, int nd) {
+  const int v = find_desc(ds, nd, (int)blockIdx.x);
+  const GramDesc<T> d = ds[v];
+  const int local = (int)blockIdx.x - d.block_begin;
+  gram_body<T, R>(d.Uj, d.Vj, d.W, d.n_pad, d.tile_rows, d.partG, local % d.nrt, local / d.nrt);
+}
+
 // ---------------------------------------------------------------- tail
 // One thread per (row, c): the partials of the row tiles / column tiles are
 // loaded in batches of 8 (independent loads in flight) and added in index
 // order; the Gram partials are summed once per block into LDS.
 template <typename T, int R>
-__global__ void __launch_bounds__(256)
-k_level_tail(const T* __restrict__ partX, const T* __restrict__ partY,
-             const double* __restrict__ partG, int nct, int nrt, int n_pad,
-             const T* Ucur, T* Unew, T* Vnew, int W) {
+__device__ __forceinline__ void tail_body(const T* __restrict__ partX, const T* __restrict__ partY,
+                                          const double* __restrict__ partG, const int nct, const int nrt,
+                                          const int n_pad, T* slabU, T* slabV, const int W, const int blk) {
+  const T* Ucur = slabU;
+  T* Unew = slabU + R;
+  T* Vnew = slabV + (W - 2 * R);
   __shared__ double G[R * R];
   const int tid = threadIdx.x;
   for (int idx = tid; idx < R * R; idx += 256) {
@@ -309,7 +349,7 @@ k_level_tail(const T* __restrict__ partX, const T* __restrict__ partY,
   }
   __syncthreads();
   const int64_t pairs = (int64_t)n_pad * R;
-  const int64_t idx = (int64_t)blockIdx.x * 256 + tid;
+  const int64_t idx = (int64_t)blk * 256 + tid;
   if (idx >= pairs) return;
   const int64_t i = idx / R;
   const int c = (int)(idx % R);
@@ -341,14 +381,27 @@ k_level_tail(const T* __restrict__ partX, const T* __restrict__ partY,
   Vnew[i * W + c] = (T)y;
 }
 
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_level_tail(const TailDesc<T> d) {
+  tail_body<T, R>(d.partX, d.partY, d.partG, d.nct, d.nrt, d.n_pad, d.slabU, d.slabV, d.W, blockIdx.x);
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_level_tail_multi(const TailDesc<T>* __restrict__ ds, int nd) {
+  const int v = find_desc(ds, nd, (int)blockIdx.x);
+  const TailDesc<T> d = ds[v];
+  tail_body<T, R>(d.partX, d.partY, d.partG, d.nct, d.nrt, d.n_pad, d.slabU, d.slabV, d.W,
+                  (int)blockIdx.x - d.block_begin);
+}
+
 // ---------------------------------------------------------------- update only
 // P += U_j V_j^T.  Lane holds a 16-byte column group; the wave walks batches
 // of 8 rows with U_j rows broadcast through the scalar unit; ranks above 16
 // are processed in groups of 16 columns of the factors.
 template <typename T, int R>
-__global__ void __launch_bounds__(256)
-k_level_update(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
-               const T* __restrict__ Uj, const T* __restrict__ Vj, int W) {
+__device__ __forceinline__ void update_body(T* __restrict__ P, const int64_t ldp, const int n_pad,
+                                            const int tile_rows, const T* __restrict__ Uj,
+                                            const T* __restrict__ Vj, const int W, const int ct, const int rt) {
   constexpr int EPL = 16 / (int)sizeof(T);
   constexpr int TC = 64 * EPL;
   constexpr int RG = R < 16 ? R : 16;
@@ -356,8 +409,8 @@ k_level_update(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
   constexpr int RB = 8;
   const int lane = threadIdx.x & 63;
   const int wave = wave_id();
-  const int col0 = blockIdx.x * TC;
-  const int row0 = blockIdx.y * tile_rows;
+  const int col0 = ct * TC;
+  const int row0 = rt * tile_rows;
   const int nrows = min(tile_rows, n_pad - row0);
   const int lc = col0 + lane * EPL;
 
@@ -394,6 +447,19 @@ k_level_update(T* __restrict__ P, int64_t ldp, int n_pad, int tile_rows,
   }
 }
 
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_level_update(const UpdateDesc<T> d) {
+  update_body<T, R>(d.P, d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, blockIdx.x, blockIdx.y);
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_level_update_multi(const UpdateDesc<T>* __restrict__ ds, int nd) {
+  const int v = find_desc(ds, nd, (int)blockIdx.x);
+  const UpdateDesc<T> d = ds[v];
+  const int local = (int)blockIdx.x - d.block_begin;
+  update_body<T, R>(d.P, d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, local % d.nct, local / d.nct);
+}
+
 // ---------------------------------------------------------------- small kernels
 template <typename Tin, typename Tout>
 __global__ void __launch_bounds__(256)
@@ -408,10 +474,11 @@ k_copy_pad(const Tin* __restrict__ src, int64_t lds, int64_t n, Tout* __restrict
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256)
-k_prep(const T* __restrict__ U, int64_t ldu, const T* __restrict__ V, int64_t ldv, int64_t n,
-       int r, int r_pad, T* __restrict__ slabU, T* __restrict__ slabV, int W, int64_t n_pad) {
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void prep_body(const T* __restrict__ U, const int64_t ldu, const T* __restrict__ V,
+                                          const int64_t ldv, const int64_t n, const int r, const int r_pad,
+                                          T* __restrict__ slabU, T* __restrict__ slabV, const int W,
+                                          const int64_t n_pad, const int blk) {
+  const int64_t idx = (int64_t)blk * 256 + threadIdx.x;
   if (idx >= n_pad * r_pad) return;
   const int64_t i = idx / r_pad;
   const int c = (int)(idx % r_pad);
@@ -420,18 +487,39 @@ k_prep(const T* __restrict__ U, int64_t ldu, const T* __restrict__ V, int64_t ld
   slabV[i * W + (W - r_pad) + c] = in ? V[i * ldv + c] : T(0);
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_prep(const PrepDesc<T> d) {
+  prep_body<T>(d.U, d.ldu, d.V, d.ldv, d.n, d.r, d.r_pad, d.slabU, d.slabV, d.W, d.n_pad, blockIdx.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_prep_multi(const PrepDesc<T>* __restrict__ ds, int nd) {
+  const int v = find_desc(ds, nd, (int)blockIdx.x);
+  const PrepDesc<T> d = ds[v];
+  prep_body<T>(d.U, d.ldu, d.V, d.ldv, d.n, d.r, d.r_pad, d.slabU, d.slabV, d.W, d.n_pad,
+               (int)blockIdx.x - d.block_begin);
+}
+
 template <typename T, int R, int RB, bool UPD>
 hipError_t fused_launch(T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* Uj, const T* Vj,
                         int W, T* partX, T* partY, double* partG, int pR, hipStream_t s) {
-  const dim3 grid((unsigned)(n_pad / tile_cols<T>()), (unsigned)((n_pad + tile_rows - 1) / tile_rows));
-  hipLaunchKernelGGL((k_level_fused<T, R, RB, UPD>), grid, dim3(256), 0, s, P, ldp, (int)n_pad, tile_rows,
-                     Uj, Vj, W, partX, partY, partG, pR);
+  const int nct = (int)(n_pad / tile_cols<T>());
+  const FusedDesc<T> d{P, ldp, (int)n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, pR, nct, 0};
+  const dim3 grid((unsigned)nct, (unsigned)((n_pad + tile_rows - 1) / tile_rows));
+  hipLaunchKernelGGL((k_level_fused<T, R, RB, UPD>), grid, dim3(256), 0, s, d);
   return hipGetLastError();
 }
 
 template <typename T, int R>
 hipError_t update_r(T* P, int64_t ldp, int64_t n_pad, const T* Uj, const T* Vj, int W,
-                    hipStream_t s);
+                    hipStream_t s) {
+  const int tile_rows = kUpdateTileRows;
+  const int nct = (int)(n_pad / tile_cols<T>());
+  const UpdateDesc<T> d{P, ldp, (int)n_pad, tile_rows, Uj, Vj, W, nct, 0};
+  const dim3 grid((unsigned)nct, (unsigned)((n_pad + tile_rows - 1) / tile_rows));
+  hipLaunchKernelGGL((k_level_update<T, R>), grid, dim3(256), 0, s, d);
+  return hipGetLastError();
+}
 
 // One level with rank R: for R <= 16 the fused pass; above, the skinny
 // products in 16-column chunks (read-only passes), the Gram, then the rank-R
@@ -451,9 +539,10 @@ hipError_t fused_r(T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* Uj,
                                                    partX + c0, partY + c0, nullptr, R, s);
       if (e != hipSuccess) return e;
     }
-    constexpr int per_block = 256 * gram_ppt<T, R>();
-    const dim3 ggrid((unsigned)((n_pad + tile_rows - 1) / tile_rows), (unsigned)((R * R + per_block - 1) / per_block));
-    hipLaunchKernelGGL((k_gram<T, R>), ggrid, dim3(256), 0, s, Uj, Vj, W, (int)n_pad, tile_rows, partG);
+    const int nrt = (int)((n_pad + tile_rows - 1) / tile_rows);
+    const GramDesc<T> g{Uj, Vj, W, (int)n_pad, tile_rows, partG, nrt, 0};
+    const dim3 ggrid((unsigned)nrt, (unsigned)((R * R + gram_pairs_per_block(R) - 1) / gram_pairs_per_block(R)));
+    hipLaunchKernelGGL((k_gram<T, R>), ggrid, dim3(256), 0, s, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return update_r<T, R>(P, ldp, n_pad, Uj, Vj, W, s);
@@ -463,23 +552,23 @@ hipError_t fused_r(T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* Uj,
 template <typename T, int R>
 hipError_t tail_r(const T* partX, const T* partY, const double* partG, int nct, int nrt,
                   int64_t n_pad, T* slabU, T* slabV, int W, hipStream_t s) {
-  const dim3 grid((unsigned)((n_pad * R + 255) / 256));
-  // U_j = slab U columns [0, R): new block at [R, 2R).
-  // V_j = slab V columns [W-R, W): new block at [W-2R, W-R).
-  hipLaunchKernelGGL((k_level_tail<T, R>), grid, dim3(256), 0, s, partX, partY, partG, nct, nrt,
-                     (int)n_pad, (const T*)slabU, slabU + R, slabV + (W - 2 * R), W);
+  const TailDesc<T> d{partX, partY, partG, nct, nrt, (int)n_pad, slabU, slabV, W, 0};
+  hipLaunchKernelGGL((k_level_tail<T, R>), dim3((unsigned)tail_blocks(n_pad, R)), dim3(256), 0, s, d);
   return hipGetLastError();
 }
 
-template <typename T, int R>
-hipError_t update_r(T* P, int64_t ldp, int64_t n_pad, const T* Uj, const T* Vj, int W,
-                    hipStream_t s) {
-  const int tile_rows = 256;
-  const dim3 grid((unsigned)(n_pad / tile_cols<T>()), (unsigned)((n_pad + tile_rows - 1) / tile_rows));
-  hipLaunchKernelGGL((k_level_update<T, R>), grid, dim3(256), 0, s, P, ldp, (int)n_pad, tile_rows,
-                     Uj, Vj, W);
-  return hipGetLastError();
-}
+#define LV_RANK_SWITCH(R, CALL)            \
+  switch (R) {                              \
+    case 1: { constexpr int RR = 1; CALL; }   \
+    case 2: { constexpr int RR = 2; CALL; }   \
+    case 4: { constexpr int RR = 4; CALL; }   \
+    case 8: { constexpr int RR = 8; CALL; }   \
+    case 16: { constexpr int RR = 16; CALL; } \
+    case 32: { constexpr int RR = 32; CALL; } \
+    case 64: { constexpr int RR = 64; CALL; } \
+    case 128: { constexpr int RR = 128; CALL; } \
+    default: return hipErrorInvalidValue;   \
+  }
 
 }  // namespace
 
@@ -494,10 +583,8 @@ hipError_t launch_copy_pad(const Tin* src, int64_t lds, int64_t n, Tout* dst, in
 template <typename T>
 hipError_t launch_prep(const T* U, int64_t ldu, const T* V, int64_t ldv, int64_t n, int r,
                        int r_pad, T* slabU, T* slabV, int W, int64_t n_pad, hipStream_t s) {
-  const int64_t total = n_pad * r_pad;
-  const dim3 grid((unsigned)((total + 255) / 256));
-  hipLaunchKernelGGL((k_prep<T>), grid, dim3(256), 0, s, U, ldu, V, ldv, n, r, r_pad, slabU, slabV,
-                     W, n_pad);
+  const PrepDesc<T> d{U, ldu, V, ldv, n, r, r_pad, slabU, slabV, W, n_pad, 0};
+  hipLaunchKernelGGL((k_prep<T>), dim3((unsigned)((n_pad * r_pad + 255) / 256)), dim3(256), 0, s, d);
   return hipGetLastError();
 }
 
@@ -507,33 +594,13 @@ hipError_t launch_level_fused(int R, T* P, int64_t ldp, int64_t n_pad, int tile_
                               double* partG, hipStream_t s) {
   const T* Uj = slabU;
   const T* Vj = slabV + (W - R);
-  switch (R) {
-    case 1: return fused_r<T, 1>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s);
-    case 2: return fused_r<T, 2>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s);
-    case 4: return fused_r<T, 4>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s);
-    case 8: return fused_r<T, 8>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s);
-    case 16: return fused_r<T, 16>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s);
-    case 32: return fused_r<T, 32>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s);
-    case 64: return fused_r<T, 64>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s);
-    case 128: return fused_r<T, 128>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s);
-    default: return hipErrorInvalidValue;
-  }
+  LV_RANK_SWITCH(R, return (fused_r<T, RR>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s)))
 }
 
 template <typename T>
 hipError_t launch_level_tail(int R, const T* partX, const T* partY, const double* partG, int nct,
                              int nrt, int64_t n_pad, T* slabU, T* slabV, int W, hipStream_t s) {
-  switch (R) {
-    case 1: return tail_r<T, 1>(partX, partY, partG, nct, nrt, n_pad, slabU, slabV, W, s);
-    case 2: return tail_r<T, 2>(partX, partY, partG, nct, nrt, n_pad, slabU, slabV, W, s);
-    case 4: return tail_r<T, 4>(partX, partY, partG, nct, nrt, n_pad, slabU, slabV, W, s);
-    case 8: return tail_r<T, 8>(partX, partY, partG, nct, nrt, n_pad, slabU, slabV, W, s);
-    case 16: return tail_r<T, 16>(partX, partY, partG, nct, nrt, n_pad, slabU, slabV, W, s);
-    case 32: return tail_r<T, 32>(partX, partY, partG, nct, nrt, n_pad, slabU, slabV, W, s);
-    case 64: return tail_r<T, 64>(partX, partY, partG, nct, nrt, n_pad, slabU, slabV, W, s);
-    case 128: return tail_r<T, 128>(partX, partY, partG, nct, nrt, n_pad, slabU, slabV, W, s);
-    default: return hipErrorInvalidValue;
-  }
+  LV_RANK_SWITCH(R, return (tail_r<T, RR>(partX, partY, partG, nct, nrt, n_pad, slabU, slabV, W, s)))
 }
 
 template <typename T>
@@ -541,18 +608,66 @@ hipError_t launch_level_update(int R, T* P, int64_t ldp, int64_t n_pad, const T*
                                const T* slabV, int W, hipStream_t s) {
   const T* Uj = slabU;
   const T* Vj = slabV + (W - R);
+  if (R == 256) return update_r<T, 256>(P, ldp, n_pad, Uj, Vj, W, s);
+  LV_RANK_SWITCH(R, return (update_r<T, RR>(P, ldp, n_pad, Uj, Vj, W, s)))
+}
+
+// ---- multi-view launchers
+
+template <typename T>
+hipError_t launch_fused_multi(int R, bool chunk, const FusedDesc<T>* ds, int nd, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  if (chunk) {
+    hipLaunchKernelGGL((k_level_fused_multi<T, kMaxFusedRank, 8, false>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       ds, nd);
+    return hipGetLastError();
+  }
   switch (R) {
-    case 1: return update_r<T, 1>(P, ldp, n_pad, Uj, Vj, W, s);
-    case 2: return update_r<T, 2>(P, ldp, n_pad, Uj, Vj, W, s);
-    case 4: return update_r<T, 4>(P, ldp, n_pad, Uj, Vj, W, s);
-    case 8: return update_r<T, 8>(P, ldp, n_pad, Uj, Vj, W, s);
-    case 16: return update_r<T, 16>(P, ldp, n_pad, Uj, Vj, W, s);
-    case 32: return update_r<T, 32>(P, ldp, n_pad, Uj, Vj, W, s);
-    case 64: return update_r<T, 64>(P, ldp, n_pad, Uj, Vj, W, s);
-    case 128: return update_r<T, 128>(P, ldp, n_pad, Uj, Vj, W, s);
-    case 256: return update_r<T, 256>(P, ldp, n_pad, Uj, Vj, W, s);
+    case 1: hipLaunchKernelGGL((k_level_fused_multi<T, 1, 16, true>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
+    case 2: hipLaunchKernelGGL((k_level_fused_multi<T, 2, 16, true>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
+    case 4: hipLaunchKernelGGL((k_level_fused_multi<T, 4, 16, true>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
+    case 8: hipLaunchKernelGGL((k_level_fused_multi<T, 8, 8, true>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
+    case 16: hipLaunchKernelGGL((k_level_fused_multi<T, 16, 8, true>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gram_multi(int R, const GramDesc<T>* ds, int nd, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  switch (R) {
+    case 32: hipLaunchKernelGGL((k_gram_multi<T, 32>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
+    case 64: hipLaunchKernelGGL((k_gram_multi<T, 64>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
+    case 128: hipLaunchKernelGGL((k_gram_multi<T, 128>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_tail_multi(int R, const TailDesc<T>* ds, int nd, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  LV_RANK_SWITCH(R, hipLaunchKernelGGL((k_level_tail_multi<T, RR>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd);
+                 return hipGetLastError())
+}
+
+template <typename T>
+hipError_t launch_update_multi(int R, const UpdateDesc<T>* ds, int nd, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  if (R == 256) {
+    hipLaunchKernelGGL((k_level_update_multi<T, 256>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd);
+    return hipGetLastError();
+  }
+  LV_RANK_SWITCH(R, hipLaunchKernelGGL((k_level_update_multi<T, RR>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd);
+                 return hipGetLastError())
+}
+
+template <typename T>
+hipError_t launch_prep_multi(const PrepDesc<T>* ds, int nd, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_prep_multi<T>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd);
+  return hipGetLastError();
 }
 
 #define LV_INST(T)                                                                              \
@@ -563,7 +678,12 @@ hipError_t launch_level_update(int R, T* P, int64_t ldp, int64_t n_pad, const T*
   template hipError_t launch_level_tail<T>(int, const T*, const T*, const double*, int, int,      \
                                            int64_t, T*, T*, int, hipStream_t);                    \
   template hipError_t launch_level_update<T>(int, T*, int64_t, int64_t, const T*, const T*, int,  \
-                                             hipStream_t);
+                                             hipStream_t);                                        \
+  template hipError_t launch_fused_multi<T>(int, bool, const FusedDesc<T>*, int, int, hipStream_t); \
+  template hipError_t launch_gram_multi<T>(int, const GramDesc<T>*, int, int, hipStream_t);        \
+  template hipError_t launch_tail_multi<T>(int, const TailDesc<T>*, int, int, hipStream_t);        \
+  template hipError_t launch_update_multi<T>(int, const UpdateDesc<T>*, int, int, hipStream_t);    \
+  template hipError_t launch_prep_multi<T>(const PrepDesc<T>*, int, int, hipStream_t);
 LV_INST(float)
 LV_INST(double)
 #undef LV_INST

@@ -1,0 +1,131 @@
+// Internal view state shared by the C-ABI translation units: workspace
+// layout of a view, the view handle, and error helpers.
+#pragma once
+
+#include "linview.h"
+#include "lv_internal.h"
+
+#include <cstdarg>
+#include <cstdio>
+#include <vector>
+
+namespace lv {
+
+// Message of the last failure on this host thread (set by fail()).
+extern thread_local char g_err[512];
+lv_status fail(lv_status st, const char* fmt, ...);
+
+inline bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+inline int ilog2(int64_t x) { int m = 0; while ((int64_t(1) << m) < x) ++m; return m; }
+inline int64_t next_pow2(int64_t x) { int64_t p = 1; while (p < x) p <<= 1; return p; }
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kMaxOrder = 65536;
+constexpr int kMaxK = 1024;
+constexpr int kMaxWidth = 256;   // k * r_pad: width of the top-level factors
+constexpr int kTileRows = 512;   // rows per tile of the fused level pass
+
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  int64_t n_pad = 0, ldp = 0;
+  int m = 0, r_pad = 0, W = 0, elem = 0, nct = 0, nrt = 0, tile_rows = 0;
+  size_t P[kMaxLevel + 1] = {};
+  size_t slabU[kMaxLevel + 1] = {};
+  size_t slabV[kMaxLevel + 1] = {};
+  size_t partX[kMaxLevel] = {};
+  size_t partY[kMaxLevel] = {};
+  size_t partG[kMaxLevel] = {};
+  size_t scratch[2] = {};
+  size_t probe = 0;  // zpad | Pz (m+1 vectors) | PPz (m vectors) | residuals | gate | counter
+  size_t total = 0;
+};
+
+inline lv_status check_shape(int64_t n, int k, int r_max, lv_mode mode) {
+  if (mode != LV_FP64 && mode != LV_FP32) return fail(LV_EINVAL, "unknown mode %d", (int)mode);
+  if (n < 1 || n > kMaxOrder) return fail(LV_EINVAL, "n = %lld outside [1, %lld]", (long long)n, (long long)kMaxOrder);
+  if (!is_pow2(k) || k > kMaxK) return fail(LV_EINVAL, "k = %d is not a power of two in [1, %d]", k, kMaxK);
+  if (r_max < 1) return fail(LV_EINVAL, "r_max = %d < 1", r_max);
+  const int64_t width = (int64_t)k * next_pow2(r_max);
+  if (width > kMaxWidth)
+    return fail(LV_EINVAL, "k * r_max (rounded up to a power of two) = %lld exceeds %d", (long long)width, kMaxWidth);
+  return LV_OK;
+}
+
+inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode) {
+  lv::Layout L;
+  L.elem = mode == LV_FP64 ? 8 : 4;
+  L.n_pad = round_up(n, kPadOrder);
+  L.ldp = L.n_pad;
+  L.m = ilog2(k);
+  L.r_pad = (int)next_pow2(r_max);
+  L.W = k * L.r_pad;
+  L.tile_rows = kTileRows;
+  L.nct = (int)(L.n_pad / tile_cols_bytes(L.elem));
+  L.nrt = (int)((L.n_pad + L.tile_rows - 1) / L.tile_rows);
+  size_t off = 0;
+  const size_t mat = (size_t)L.n_pad * L.ldp * L.elem;
+  for (int j = 0; j <= L.m; ++j) { L.P[j] = off; off = align_up(off + mat); }
+  const size_t slab = (size_t)L.n_pad * L.W * L.elem;
+  for (int j = 0; j <= L.m; ++j) {
+    L.slabU[j] = off; off = align_up(off + slab);
+    L.slabV[j] = off; off = align_up(off + slab);
+  }
+  for (int j = 0; j < L.m; ++j) {
+    const size_t R = (size_t)L.r_pad << j;
+    L.partX[j] = off; off = align_up(off + (size_t)L.nct * L.n_pad * R * L.elem);
+    L.partY[j] = off; off = align_up(off + (size_t)L.nrt * L.n_pad * R * L.elem);
+    L.partG[j] = off; off = align_up(off + (size_t)L.nrt * R * R * sizeof(double));
+  }
+  if (mode == LV_FP32 && L.m > 0) {
+    const size_t dmat = (size_t)L.n_pad * L.n_pad * sizeof(double);
+    L.scratch[0] = off; off = align_up(off + dmat);
+    L.scratch[1] = off; off = align_up(off + dmat);
+  }
+  L.probe = off;
+  off = align_up(off + (size_t)(2 * L.m + 2) * L.n_pad * sizeof(double) + kMaxLevel * sizeof(double) + 256);
+  L.total = off;
+  return L;
+}
+
+inline lv_status hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return LV_OK;
+  return fail(LV_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace lv
+
+struct lv_view {
+  int64_t n;
+  int k;
+  int r_max;
+  lv_mode mode;
+  lv::Layout L;
+  char* base;
+  size_t ws_bytes;
+  int64_t updates;
+  int64_t reanchors;
+
+  // Kernel timing (diagnostics): event pairs per launch kind, resolved by
+  // lv_view_timing.
+  bool timing = false;
+  struct Pair { hipEvent_t a, b; int kind; };
+  std::vector<Pair> pending;
+  std::vector<hipEvent_t> pool;
+
+  template <typename T> T* P(int j) const { return reinterpret_cast<T*>(base + L.P[j]); }
+  template <typename T> T* slabU(int s) const { return reinterpret_cast<T*>(base + L.slabU[s]); }
+  template <typename T> T* slabV(int s) const { return reinterpret_cast<T*>(base + L.slabV[s]); }
+  template <typename T> T* partX(int j) const { return reinterpret_cast<T*>(base + L.partX[j]); }
+  template <typename T> T* partY(int j) const { return reinterpret_cast<T*>(base + L.partY[j]); }
+  double* partG(int j) const { return reinterpret_cast<double*>(base + L.partG[j]); }
+  double* scratch(int i) const { return reinterpret_cast<double*>(base + L.scratch[i]); }
+  double* zpad() const { return reinterpret_cast<double*>(base + L.probe); }
+  double* Pz(int j) const { return zpad() + (size_t)(1 + j) * L.n_pad; }
+  double* PPz(int j) const { return zpad() + (size_t)(L.m + 2 + j) * L.n_pad; }
+  double* residuals() const { return zpad() + (size_t)(2 * L.m + 2) * L.n_pad; }
+  int* gate() const { return reinterpret_cast<int*>(residuals() + lv::kMaxLevel); }
+  unsigned long long* drift_counter() const {
+    return reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(residuals() + lv::kMaxLevel) + 64);
+  }
+};

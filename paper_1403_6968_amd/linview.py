@@ -30,6 +30,8 @@ EXPORTED = (
     "lv_view_update", "lv_view_update_batch", "lv_view_read", "lv_view_data",
     "lv_view_reanchor", "lv_view_stats", "lv_view_destroy", "lv_reeval_footprint",
     "lv_reeval", "lv_view_set_timing", "lv_view_timing", "lv_view_write", "lv_view_drift_check",
+    "lv_batch_footprint", "lv_batch_create", "lv_batch_inputs", "lv_batch_stage", "lv_batch_update",
+    "lv_batch_destroy",
 )
 
 
@@ -88,6 +90,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "lv_view_set_timing": (I32, [P, I32]),
         "lv_view_write": (I32, [P, I32, P, I64, P]),
         "lv_view_drift_check": (I32, [P, P, c.c_double, P, P]),
+        "lv_batch_footprint": (SZ, [c.POINTER(P), I32]),
+        "lv_batch_create": (I32, [c.POINTER(P), I32, P, SZ, P, c.POINTER(P)]),
+        "lv_batch_inputs": (I32, [P, I32, c.POINTER(P), c.POINTER(P), c.POINTER(I64)]),
+        "lv_batch_stage": (I32, [P, I32, P, P, I64, I64, I64, P]),
+        "lv_batch_update": (I32, [P, P]),
+        "lv_batch_destroy": (None, [P]),
         "lv_view_timing": (I32, [P, c.POINTER(lv_timing)]),
     }
     for name, (res, args) in sig.items():
@@ -316,6 +324,73 @@ class View:
         if getattr(self, "handle", None) is not None:
             torch.cuda.synchronize(self.device)
             lv_view_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _handles(views):
+    arr = (ctypes.c_void_p * len(views))(*[v.handle.value for v in views])
+    return arr
+
+
+def lv_batch_footprint(views) -> int:
+    return int(load().lv_batch_footprint(_handles(views), len(views)))
+
+
+def lv_batch_create(views, workspace: torch.Tensor, stream=None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(load().lv_batch_create(_handles(views), len(views), workspace.data_ptr(),
+                                  workspace.numel() * workspace.element_size(),
+                                  _stream(stream, workspace.device), ctypes.byref(h)))
+    return h
+
+
+def lv_batch_stage(batch, i: int, U, V, dtype, stream=None, device=None) -> None:
+    if U is None:
+        _check(load().lv_batch_stage(batch, i, None, None, 0, 0, 0, _stream(stream, device)))
+        return
+    u, ldu = _mat(U, dtype, "U")
+    v, ldv = _mat(V, dtype, "V")
+    _check(load().lv_batch_stage(batch, i, u, v, U.shape[1], ldu, ldv, _stream(stream, U.device)))
+
+
+def lv_batch_update(batch, stream=None, device=None) -> None:
+    _check(load().lv_batch_update(batch, _stream(stream, device)))
+
+
+def lv_batch_destroy(batch) -> None:
+    load().lv_batch_destroy(batch)
+
+
+class Batch:
+    """One update per view per round for a list of `View`s of one mode; a
+    round is one replay of a HIP graph captured at construction."""
+
+    def __init__(self, views, stream=None):
+        self.views = list(views)
+        self.device = self.views[0].device
+        self.dtype = self.views[0].dtype
+        nbytes = lv_batch_footprint(self.views)
+        if nbytes == 0:
+            raise LinviewError(LV_EINVAL, lv_last_error())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.handle = lv_batch_create(self.views, self.workspace, stream)
+
+    def stage(self, i: int, U=None, V=None, stream=None) -> None:
+        lv_batch_stage(self.handle, i, U, V, self.dtype, stream, self.device)
+
+    def update(self, stream=None) -> None:
+        lv_batch_update(self.handle, stream, self.device)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None:
+            torch.cuda.synchronize(self.device)
+            lv_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -1,0 +1,94 @@
+"""Batched rounds (lv_batch_*): many views of uneven n, k and rank updated in
+one graph-replayed round must equal the same views updated one by one with
+lv_view_update, bit for bit, and the FP64 oracle within tolerance.
+
+A batch stages every update at its view's full width r_max (unused columns
+zero).  Zero columns leave every value exact but a different width selects
+a different reduction order, so the one-by-one twins receive the same
+zero-padded factors."""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from tests.gpu_util import dev, host, need_gpu, note, read_all
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    note(f"start {request.node.nodeid}")
+    yield
+
+
+# (n, k, r): ragged orders, k from 1 to 16, ranks 1..8 (level ranks up to 64)
+SHAPES = [(256, 16, 1), (300, 8, 3), (700, 16, 2), (513, 1, 2), (1100, 4, 5), (384, 16, 4),
+          (640, 2, 8), (256, 16, 8), (900, 16, 1), (128, 8, 7)]
+
+
+@pytest.mark.parametrize("dtype_name", ["f32", "f64"])
+def test_batch_rounds_match_single_views_and_oracle(dtype_name):
+    need_gpu()
+    import torch
+    from paper_1403_6968_amd import linview as lv
+    td, nd = (torch.float32, np.float32) if dtype_name == "f32" else (torch.float64, np.float64)
+    rounds = 4
+    views, twins, ref, staged = [], [], [], []
+    for v, (n, k, r) in enumerate(SHAPES):
+        A = synth.gaussian_matrix(n, seed=30, config=4, view=v).astype(nd).astype(np.float64)
+        views.append(lv.View(dev(A, td), k, r_max=r))
+        twins.append(lv.View(dev(A, td), k, r_max=r))
+        ref.append(O.reeval(A, k))
+    batch = lv.Batch(views)
+    for t in range(rounds):
+        for v, (n, k, r) in enumerate(SHAPES):
+            if (v + t) % 4 == 3:                      # some views sit a round out
+                batch.stage(v)
+                z = torch.zeros(n, r, dtype=td, device="cuda")
+                twins[v].update(z, z)
+                continue
+            rr = 1 + (v + t) % r                       # ranks vary between rounds
+            U, V = synth.update_factors(n, rr, 1, seed=31 + t, config=4, view=v)
+            U = U[0].astype(nd).astype(np.float64)
+            V = V[0].astype(nd).astype(np.float64)
+            Ud, Vd = dev(U, td), dev(V, td)
+            batch.stage(v, Ud, Vd)
+            Up = np.zeros((n, r)); Up[:, :rr] = U
+            Vp = np.zeros((n, r)); Vp[:, :rr] = V
+            twins[v].update(dev(Up, td), dev(Vp, td))
+            ref[v] = O.incr_update(ref[v], U, V)
+        batch.update()
+    tol = 1e-10 if dtype_name == "f64" else 1e-4
+    worst = 0.0
+    for v in range(len(SHAPES)):
+        got, twin = read_all(views[v]), read_all(twins[v])
+        for i in got:
+            np.testing.assert_array_equal(got[i], twin[i])
+            worst = max(worst, O.maxrel(got[i], ref[v][i]))
+    note(f"batch {dtype_name}: worst maxrel vs oracle {worst:.2e}")
+    assert worst < tol
+    assert views[0].stats()["updates"] == rounds
+    batch.close()
+    for x in views + twins:
+        x.close()
+
+
+def test_batch_errors():
+    need_gpu()
+    import torch
+    from paper_1403_6968_amd import linview as lv
+    a = lv.View(torch.zeros(64, 64, dtype=torch.float32, device="cuda"), 4)
+    b = lv.View(torch.zeros(64, 64, dtype=torch.float64, device="cuda"), 4)
+    with pytest.raises(lv.LinviewError):
+        lv.Batch([a, b])                               # mixed modes
+    batch = lv.Batch([a])
+    U = torch.zeros(64, 2, dtype=torch.float32, device="cuda")
+    with pytest.raises(lv.LinviewError):
+        batch.stage(0, U, U)                           # rank above r_max
+    with pytest.raises(lv.LinviewError):
+        batch.stage(1)                                 # no such view
+    batch.close(); a.close(); b.close()
