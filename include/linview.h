@@ -221,6 +221,65 @@ lv_status lv_batch_update(lv_batch* b, void* stream);
 /* Release the batch (after the stream has drained).  NULL is ignored. */
 void lv_batch_destroy(lv_batch* b);
 
+/* ---------------------------------------------------------------------
+ * Serving loop.  Views live inside one caller-provided HBM arena: each
+ * admitted view takes one block (its workspace and an input staging area)
+ * from a first-fit free list, so admission is by exact footprint and
+ * removing a view returns its block.  Rank-1 update requests arrive from
+ * host memory and queue per view; each step coalesces up to r_coalesce
+ * queued requests of a view into one rank-r update (the delta of U V^T is
+ * the sum of the rank-1 deltas, Sec. 4.1-4.2) and launches one multi-view
+ * round over exactly the views with pending requests, without waiting for
+ * earlier rounds (continuous batching: requests that arrive meanwhile join
+ * the next step).  Completion events give each request's latency from its
+ * arrival time to the end of the round that applied it.  Not thread-safe.
+ * --------------------------------------------------------------------- */
+typedef struct lv_server lv_server;
+
+typedef struct {
+  uint64_t submitted;         /* requests accepted                             */
+  uint64_t completed;         /* requests applied (their round has finished)    */
+  uint64_t rounds;            /* rounds launched                                */
+  uint64_t coalesced_updates; /* per-view rank-r updates launched               */
+  int32_t views;              /* views admitted                                 */
+  size_t arena_free;          /* free arena bytes                               */
+  double latency_p50_s;       /* arrival -> completion, over completed requests */
+  double latency_p99_s;
+  double latency_max_s;
+} lv_server_counters;
+
+/* arena: device, 256-byte aligned, >= 4 MiB (descriptor ring) plus the
+ * views; r_coalesce in [1, 64] is every view's r_max. */
+lv_status lv_server_create(void* arena, size_t arena_bytes, lv_mode mode, int r_coalesce,
+                           void* stream, lv_server** out);
+/* Arena bytes one view of order n and power k takes (0 if invalid). */
+size_t lv_server_view_bytes(const lv_server* s, int64_t n, int k);
+/* Admit a view of A^k (A: n x n device, lda >= n); LV_ENOMEM when no free
+ * block is large enough (the caller may retry after removals). */
+lv_status lv_server_add_view(lv_server* s, const void* A, int64_t n, int64_t lda, int k,
+                             int* view_id);
+/* Wait for in-flight rounds, then free the view and its block. */
+lv_status lv_server_remove_view(lv_server* s, int view_id);
+/* The view handle (for lv_view_read / lv_view_data); NULL if none. */
+lv_view* lv_server_view(lv_server* s, int view_id);
+/* Seconds on the server's clock (arrival times are on this clock). */
+double lv_server_now(const lv_server* s);
+/* Queue the rank-1 request u v^T (u, v: n elements of the view's type in
+ * host memory, copied before return).  arrival < 0 means now. */
+lv_status lv_server_submit(lv_server* s, int view_id, const void* u, const void* v, double arrival,
+                           uint64_t* ticket);
+/* Launch one round over the views with pending requests (non-blocking;
+ * *launched = requests in the round, 0 if none were pending). */
+lv_status lv_server_step(lv_server* s, int* launched);
+/* Retire finished rounds without waiting; *completed = total applied. */
+lv_status lv_server_poll(lv_server* s, uint64_t* completed);
+/* Wait for every launched round. */
+lv_status lv_server_drain(lv_server* s);
+lv_status lv_server_stats(const lv_server* s, lv_server_counters* out);
+/* Drain, destroy the views, release host resources (the caller frees the
+ * arena).  NULL is ignored. */
+void lv_server_destroy(lv_server* s);
+
 /* Workspace bytes for lv_reeval at order n; 0 if invalid. */
 size_t lv_reeval_footprint(int64_t n, int r_max, lv_mode mode);
 

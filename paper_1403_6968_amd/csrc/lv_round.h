@@ -1,0 +1,150 @@
+// Round planner shared by batched rounds and the serving loop: for a set of
+// views with one update each, the per-level-step multi-view launches
+//   prep (update -> factor slab 0, all views)
+//   for j = 0..max_m:
+//     fused passes (R <= 16), one launch per R
+//     read-only skinny chunks (R > 16), one launch for all views
+//     Gram (R > 16), one launch per R
+//     rank-R update of level j (R > 16) and top-level updates, one per R
+//     tails (reductions + next factors), one launch per R
+// Every view runs exactly the kernels of lv_view_update, so its result is
+// identical bit for bit to an update applied alone with the same factors.
+#pragma once
+
+#include "lv_view_impl.h"
+
+#include <cstring>
+#include <map>
+#include <vector>
+
+namespace lv {
+
+enum Kind { kPrep, kFused, kChunk, kGram, kUpdate, kTail };
+
+struct LaunchRec {
+  Kind kind;
+  int R;
+  size_t off;   // byte offset of the descriptor array in the descriptor area
+  int nd;
+  int blocks;
+};
+
+// Host-side plan of a round: descriptor bytes (to be copied to device
+// memory) and the launch list referring to offsets in them.
+struct Plan {
+  std::vector<char> bytes;
+  std::vector<LaunchRec> launches;
+
+  template <typename D, typename F>
+  void add(Kind kind, int R, std::vector<D>& ds, F blocks_of) {
+    if (ds.empty()) return;
+    int b = 0;
+    for (auto& d : ds) { d.block_begin = b; b += blocks_of(d); }
+    const size_t off = align_up(bytes.size());
+    bytes.resize(off + ds.size() * sizeof(D));
+    std::memcpy(bytes.data() + off, ds.data(), ds.size() * sizeof(D));
+    launches.push_back({kind, R, off, (int)ds.size(), b});
+  }
+};
+
+template <typename T> int fused_blocks(const FusedDesc<T>& d) {
+  return d.nct * ((d.n_pad + d.tile_rows - 1) / d.tile_rows);
+}
+template <typename T> int update_blocks(const UpdateDesc<T>& d) {
+  return d.nct * ((d.n_pad + d.tile_rows - 1) / d.tile_rows);
+}
+template <typename T> int prep_blocks(const PrepDesc<T>& d) {
+  return (int)((d.n_pad * d.r_pad + 255) / 256);
+}
+
+// The update source of one view in a round: U, V (n x r, leading dims
+// ldu, ldv) on the device; r may be below the view's r_max (the factor slab
+// is zero-filled up to the view's padded rank).
+struct RoundInput {
+  const void* U; int64_t ldu; const void* V; int64_t ldv; int r;
+};
+
+// Descriptors and launch list of one round over `views`.
+template <typename T>
+Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>& in) {
+  Plan pl;
+  std::vector<PrepDesc<T>> prep;
+  int max_m = 0;
+  for (size_t i = 0; i < views.size(); ++i) {
+    lv_view* v = views[i];
+    const Layout& L = v->L;
+    prep.push_back({static_cast<const T*>(in[i].U), in[i].ldu, static_cast<const T*>(in[i].V), in[i].ldv, v->n,
+                    in[i].r, L.r_pad, v->slabU<T>(0), v->slabV<T>(0), L.W, L.n_pad, 0});
+    max_m = L.m > max_m ? L.m : max_m;
+  }
+  pl.add(kPrep, 0, prep, &prep_blocks<T>);
+
+  for (int j = 0; j <= max_m; ++j) {
+    std::map<int, std::vector<FusedDesc<T>>> fused;
+    std::vector<FusedDesc<T>> chunks;
+    std::map<int, std::vector<GramDesc<T>>> gram;
+    std::map<int, std::vector<UpdateDesc<T>>> upd;
+    std::map<int, std::vector<TailDesc<T>>> tail;
+    for (lv_view* v : views) {
+      const Layout& L = v->L;
+      if (j > L.m) continue;
+      const int R = L.r_pad << j;
+      T* sU = v->slabU<T>(0);
+      T* sV = v->slabV<T>(0);
+      const T* Vj = sV + (L.W - R);
+      if (j == L.m) {
+        upd[R].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, kUpdateTileRows, sU, Vj, L.W,
+                          (int)(L.n_pad / tile_cols_bytes(L.elem)), 0});
+        continue;
+      }
+      if (R <= kMaxFusedRank) {
+        fused[R].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, L.tile_rows, sU, Vj, L.W, v->partX<T>(j),
+                            v->partY<T>(j), v->partG(j), R, L.nct, 0});
+      } else {
+        for (int c0 = 0; c0 < R; c0 += kMaxFusedRank)
+          chunks.push_back({v->P<T>(j), L.ldp, (int)L.n_pad, L.tile_rows, sU + c0, Vj + c0, L.W,
+                            v->partX<T>(j) + c0, v->partY<T>(j) + c0, nullptr, R, L.nct, 0});
+        gram[R].push_back({sU, Vj, L.W, (int)L.n_pad, L.tile_rows, v->partG(j), L.nrt, 0});
+        upd[R].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, kUpdateTileRows, sU, Vj, L.W,
+                          (int)(L.n_pad / tile_cols_bytes(L.elem)), 0});
+      }
+      tail[R].push_back({v->partX<T>(j), v->partY<T>(j), v->partG(j), L.nct, L.nrt, (int)L.n_pad, sU, sV, L.W, 0});
+    }
+    for (auto& kv : fused) pl.add(kFused, kv.first, kv.second, &fused_blocks<T>);
+    pl.add(kChunk, kMaxFusedRank, chunks, &fused_blocks<T>);
+    for (auto& kv : gram) {
+      const int R = kv.first;
+      const int chunks_per_tile = (R * R + gram_pairs_per_block(R) - 1) / gram_pairs_per_block(R);
+      pl.add(kGram, R, kv.second, [chunks_per_tile](const GramDesc<T>& d) { return d.nrt * chunks_per_tile; });
+    }
+    for (auto& kv : upd) pl.add(kUpdate, kv.first, kv.second, &update_blocks<T>);
+    for (auto& kv : tail) {
+      const int R = kv.first;
+      pl.add(kTail, R, kv.second, [R](const TailDesc<T>& d) { return tail_blocks(d.n_pad, R); });
+    }
+  }
+  return pl;
+}
+
+// Launch a round whose descriptors are at `dbase` on the device.
+template <typename T>
+lv_status enqueue_round(const Plan& pl, const char* dbase, hipStream_t s) {
+  for (const LaunchRec& l : pl.launches) {
+    const void* d = dbase + l.off;
+    hipError_t e = hipSuccess;
+    switch (l.kind) {
+      case kPrep: e = launch_prep_multi<T>(static_cast<const PrepDesc<T>*>(d), l.nd, l.blocks, s); break;
+      case kFused: e = launch_fused_multi<T>(l.R, false, static_cast<const FusedDesc<T>*>(d), l.nd, l.blocks, s); break;
+      case kChunk: e = launch_fused_multi<T>(l.R, true, static_cast<const FusedDesc<T>*>(d), l.nd, l.blocks, s); break;
+      case kGram: e = launch_gram_multi<T>(l.R, static_cast<const GramDesc<T>*>(d), l.nd, l.blocks, s); break;
+      case kUpdate: e = launch_update_multi<T>(l.R, static_cast<const UpdateDesc<T>*>(d), l.nd, l.blocks, s); break;
+      case kTail: e = launch_tail_multi<T>(l.R, static_cast<const TailDesc<T>*>(d), l.nd, l.blocks, s); break;
+    }
+    lv_status st = hip_check(e, "batch launch");
+    if (st != LV_OK) return st;
+  }
+  return LV_OK;
+}
+
+
+}  // namespace lv

@@ -31,7 +31,9 @@ EXPORTED = (
     "lv_view_reanchor", "lv_view_stats", "lv_view_destroy", "lv_reeval_footprint",
     "lv_reeval", "lv_view_set_timing", "lv_view_timing", "lv_view_write", "lv_view_drift_check",
     "lv_batch_footprint", "lv_batch_create", "lv_batch_inputs", "lv_batch_stage", "lv_batch_update",
-    "lv_batch_destroy",
+    "lv_batch_destroy", "lv_server_create", "lv_server_view_bytes", "lv_server_add_view",
+    "lv_server_remove_view", "lv_server_view", "lv_server_now", "lv_server_submit", "lv_server_step",
+    "lv_server_poll", "lv_server_drain", "lv_server_stats", "lv_server_destroy",
 )
 
 
@@ -56,6 +58,15 @@ class lv_timing(ctypes.Structure):
         ("fused_ms", ctypes.c_double), ("fused_launches", ctypes.c_int64),
         ("tail_ms", ctypes.c_double), ("tail_launches", ctypes.c_int64),
         ("top_ms", ctypes.c_double), ("top_launches", ctypes.c_int64),
+    ]
+
+
+class lv_server_counters(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rounds", ctypes.c_uint64),
+        ("coalesced_updates", ctypes.c_uint64), ("views", ctypes.c_int32),
+        ("arena_free", ctypes.c_size_t), ("latency_p50_s", ctypes.c_double),
+        ("latency_p99_s", ctypes.c_double), ("latency_max_s", ctypes.c_double),
     ]
 
 
@@ -96,6 +107,18 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "lv_batch_stage": (I32, [P, I32, P, P, I64, I64, I64, P]),
         "lv_batch_update": (I32, [P, P]),
         "lv_batch_destroy": (None, [P]),
+        "lv_server_create": (I32, [P, SZ, I32, I32, P, c.POINTER(P)]),
+        "lv_server_view_bytes": (SZ, [P, I64, I32]),
+        "lv_server_add_view": (I32, [P, P, I64, I64, I32, c.POINTER(I32)]),
+        "lv_server_remove_view": (I32, [P, I32]),
+        "lv_server_view": (P, [P, I32]),
+        "lv_server_now": (c.c_double, [P]),
+        "lv_server_submit": (I32, [P, I32, P, P, c.c_double, c.POINTER(c.c_uint64)]),
+        "lv_server_step": (I32, [P, c.POINTER(I32)]),
+        "lv_server_poll": (I32, [P, c.POINTER(c.c_uint64)]),
+        "lv_server_drain": (I32, [P]),
+        "lv_server_stats": (I32, [P, c.POINTER(lv_server_counters)]),
+        "lv_server_destroy": (None, [P]),
         "lv_view_timing": (I32, [P, c.POINTER(lv_timing)]),
     }
     for name, (res, args) in sig.items():
@@ -391,6 +414,96 @@ class Batch:
         if getattr(self, "handle", None) is not None:
             torch.cuda.synchronize(self.device)
             lv_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving loop over views kept in one device arena (see linview.h):
+    host-side rank-1 requests, per-view coalescing, continuous batching."""
+
+    def __init__(self, arena_bytes: int, mode: int = LV_FP32, r_coalesce: int = 8,
+                 device="cuda", stream=None):
+        import numpy as _np
+        self._np = _np
+        self.mode = mode
+        self.dtype = _MODE_DTYPE[mode]
+        self.np_dtype = _np.float64 if mode == LV_FP64 else _np.float32
+        self.device = torch.device(device)
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=self.device)
+        self._stream = _stream(stream, self.device)
+        h = ctypes.c_void_p()
+        _check(load().lv_server_create(self.arena.data_ptr(), arena_bytes, mode, r_coalesce,
+                                       self._stream, ctypes.byref(h)))
+        self.handle = h
+        self.n = {}
+        self.k = {}
+
+    def view_bytes(self, n: int, k: int) -> int:
+        return int(load().lv_server_view_bytes(self.handle, n, k))
+
+    def add_view(self, A: torch.Tensor, k: int) -> int:
+        a, lda = _mat(A, self.dtype, "A")
+        vid = ctypes.c_int()
+        _check(load().lv_server_add_view(self.handle, a, A.shape[0], lda, k, ctypes.byref(vid)))
+        self.n[vid.value] = A.shape[0]
+        self.k[vid.value] = k
+        return vid.value
+
+    def remove_view(self, vid: int) -> None:
+        _check(load().lv_server_remove_view(self.handle, vid))
+        self.n.pop(vid, None)
+        self.k.pop(vid, None)
+
+    def now(self) -> float:
+        return float(load().lv_server_now(self.handle))
+
+    def submit(self, vid: int, u, v, arrival: float = -1.0) -> int:
+        u = self._np.ascontiguousarray(u, dtype=self.np_dtype)
+        v = self._np.ascontiguousarray(v, dtype=self.np_dtype)
+        if u.shape != (self.n[vid],) or v.shape != (self.n[vid],):
+            raise ValueError("u and v must be vectors of the view's order")
+        t = ctypes.c_uint64()
+        _check(load().lv_server_submit(self.handle, vid, u.ctypes.data, v.ctypes.data, float(arrival),
+                                       ctypes.byref(t)))
+        return t.value
+
+    def step(self) -> int:
+        n = ctypes.c_int()
+        _check(load().lv_server_step(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def poll(self) -> int:
+        c = ctypes.c_uint64()
+        _check(load().lv_server_poll(self.handle, ctypes.byref(c)))
+        return c.value
+
+    def drain(self) -> None:
+        _check(load().lv_server_drain(self.handle))
+
+    def stats(self) -> dict:
+        st = lv_server_counters()
+        _check(load().lv_server_stats(self.handle, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in lv_server_counters._fields_}
+
+    def read(self, vid: int, power: int) -> torch.Tensor:
+        h = load().lv_server_view(self.handle, vid)
+        if not h:
+            raise LinviewError(LV_EINVAL, f"no view {vid}")
+        n = self.n[vid]
+        out = torch.empty(n, n, dtype=self.dtype, device=self.device)
+        lv_view_read(ctypes.c_void_p(h), power, out, self.dtype, self._stream)
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None:
+            load().lv_server_destroy(self.handle)
+            torch.cuda.synchronize(self.device)
             self.handle = None
 
     def __del__(self):
