@@ -47,7 +47,121 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-reeval", action="store_true")
     p.add_argument("--quick", action="store_true", help="timed region only (for profilers)")
+    p.add_argument("--no-secondary", action="store_true",
+                   help="skip the rank-4, batched and serving workloads")
+    p.add_argument("--serve-seconds", type=float, default=2.0)
     return p.parse_args()
+
+
+def bench_rank4(torch, lv, synth, dev, steps=40):
+    """A^16 view, n = 16384, FP32, rank-4 updates: updates/s."""
+    n, k, r = 16384, 16, 4
+    A = torch.from_numpy(synth.gaussian_matrix(n, seed=0, config=3).astype(np.float32)).to(dev)
+    U, V = synth.update_factors(n, r, steps + 5, seed=0, config=3)
+    Ud = torch.from_numpy(U.astype(np.float32)).to(dev)
+    Vd = torch.from_numpy(V.astype(np.float32)).to(dev)
+    view = lv.View(A, k, r_max=r)
+    del A
+    view.update_batch(Ud[:5], Vd[:5])
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    view.update_batch(Ud[5:], Vd[5:])
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    view.close()
+    return {"workload": "A^16, n=16384, FP32, rank-4 updates", "ms_per_update": ms,
+            "updates_per_s": 1000.0 / ms, "rank1_equiv_per_s": 4000.0 / ms,
+            "alg_GBps": 2 * 4 * 5 * n * n / (ms * 1e-3) / 1e9}
+
+
+def bench_batched(torch, lv, synth, dev, rounds=30):
+    """64 views, n in {512..4096}, k in {8, 16}, rank 1..8, FP32: one graph
+    replay per round (every view applies one update)."""
+    g = synth.rng(0, 4, 0)
+    ns = g.choice([512, 1024, 2048, 4096], size=64)
+    ks = g.choice([8, 16], size=64)
+    rs = g.integers(1, 9, size=64)
+    views = []
+    bytes_round = 0
+    for v in range(64):
+        n, k, r = int(ns[v]), int(ks[v]), int(rs[v])
+        A = torch.from_numpy(synth.gaussian_matrix(n, seed=0, config=4, view=v).astype(np.float32)).to(dev)
+        views.append(lv.View(A, k, r_max=r))
+        bytes_round += 2 * 4 * (int(np.log2(k)) + 1) * views[-1].stats()["n_pad"] ** 2
+    batch = lv.Batch(views)
+    for v in range(64):
+        n, r = int(ns[v]), int(rs[v])
+        U, V = synth.update_factors(n, r, 1, seed=0, config=4, view=v)
+        batch.stage(v, torch.from_numpy(U[0].astype(np.float32)).to(dev),
+                    torch.from_numpy(V[0].astype(np.float32)).to(dev))
+    batch.update()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(rounds):
+        batch.update()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / rounds
+    batch.close()
+    for x in views:
+        x.close()
+    return {"workload": "64 views, n in {512,1024,2048,4096}, k in {8,16}, rank 1..8, FP32",
+            "round_ms": ms, "view_updates_per_s": 64 * 1000.0 / ms,
+            "alg_bytes_per_round": bytes_round, "alg_GBps": bytes_round / (ms * 1e-3) / 1e9}
+
+
+def bench_serving(torch, lv, synth, dev, seconds=2.0, rate=20000.0, r_coalesce=16):
+    """32 views, n log-uniform in [2048, 16384], k = 16, FP32; Poisson
+    arrivals at `rate` requests/s over views with Zipf(1.1) popularity;
+    per-view coalescing, continuous batching."""
+    g = synth.rng(0, 5, 0)
+    ns = np.exp(g.uniform(np.log(2048), np.log(16384), size=32)).astype(int)
+    pop = np.arange(1, 33, dtype=np.float64) ** -1.1
+    pop /= pop.sum()
+    perm = g.permutation(32)
+    probe = lv.Server(16 << 20, r_coalesce=r_coalesce)
+    need = sum(probe.view_bytes(int(n), 16) for n in ns)
+    probe.close()
+    srv = lv.Server((16 << 20) + need, r_coalesce=r_coalesce)
+    ids = []
+    for v in range(32):
+        A = torch.from_numpy(synth.gaussian_matrix(int(ns[v]), seed=0, config=5, view=v).astype(np.float32)).to(dev)
+        ids.append(srv.add_view(A, 16))
+        del A
+    torch.cuda.synchronize()
+    pool = []
+    for v in range(32):
+        U, V = synth.update_factors(int(ns[v]), 1, 8, seed=0, config=5, view=v)
+        pool.append((U[:, :, 0].astype(np.float32), V[:, :, 0].astype(np.float32)))
+    count = int(rate * seconds)
+    gaps = g.exponential(1.0 / rate, size=count)
+    targets = perm[g.choice(32, size=count, p=pop)]
+    t0 = srv.now() + 0.05
+    arrivals = t0 + np.cumsum(gaps)
+    i = 0
+    while i < count:
+        now = srv.now()
+        while i < count and arrivals[i] <= now:
+            v = int(targets[i])
+            u, w = pool[v]
+            srv.submit(ids[v], u[i % 8], w[i % 8], float(arrivals[i]))
+            i += 1
+        srv.step()
+    while srv.step() > 0:
+        pass
+    srv.drain()
+    t_end = srv.now()
+    st = srv.stats()
+    srv.close()
+    return {"workload": "32 views, n log-uniform [2048,16384], k=16, FP32, Poisson %.0f req/s, Zipf(1.1)" % rate,
+            "offered_per_s": rate, "completed": int(st["completed"]),
+            "throughput_per_s": st["completed"] / (t_end - t0), "rounds": int(st["rounds"]),
+            "mean_coalesced_rank": st["completed"] / max(st["coalesced_updates"], 1),
+            "latency_p50_ms": st["latency_p50_s"] * 1e3, "latency_p99_ms": st["latency_p99_s"] * 1e3,
+            "arena_GB": need / 1e9}
 
 
 def counter_traffic(n, k, r):
@@ -268,6 +382,17 @@ def main():
         del ws, out
 
     view.close()
+    del Ad, Ud, Vd
+    torch.cuda.empty_cache()
+    if not args.quick and not args.no_secondary:
+        sec = {}
+        for name, fn in (("rank4_n16384", lambda: bench_rank4(torch, lv, synth, dev)),
+                         ("batched_64_views", lambda: bench_batched(torch, lv, synth, dev)),
+                         ("serving_32_views", lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds))):
+            sec[name] = fn()
+            torch.cuda.empty_cache()
+            log(f"{name}: {sec[name]}")
+        result["secondary"] = sec
     if not args.quick and not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(A32, Us, Vs, k, args.cpu_seconds)
         log(f"cpu oracle: {result['cpu_baseline']['value']:.3f} updates/s on "
