@@ -54,26 +54,34 @@ def parse():
 
 
 def bench_rank4(torch, lv, synth, dev, steps=40):
-    """A^16 view, n = 16384, FP32, rank-4 updates: updates/s."""
+    """A^16 view, n = 16384, rank-4 updates: plain FP32 and FP32 with
+    bfloat16 shadows (skinny products on the matrix cores), updates/s and the
+    per-kind kernel time of one update."""
     n, k, r = 16384, 16, 4
     A = torch.from_numpy(synth.gaussian_matrix(n, seed=0, config=3).astype(np.float32)).to(dev)
     U, V = synth.update_factors(n, r, steps + 5, seed=0, config=3)
     Ud = torch.from_numpy(U.astype(np.float32)).to(dev)
     Vd = torch.from_numpy(V.astype(np.float32)).to(dev)
-    view = lv.View(A, k, r_max=r)
+    out = {"workload": "A^16, n=16384, rank-4 updates"}
+    for tag, mode in (("fp32", lv.LV_FP32), ("bf16shadow", lv.LV_FP32_BF16SHADOW)):
+        view = lv.View(A, k, r_max=r, mode=mode)
+        view.update_batch(Ud[:5], Vd[:5])
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        view.update_batch(Ud[5:], Vd[5:])
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        view.set_timing(True)
+        view.update(Ud[0], Vd[0])
+        tm = view.timing()
+        view.set_timing(False)
+        view.close()
+        out[tag] = {"ms_per_update": ms, "updates_per_s": 1000.0 / ms, "rank1_equiv_per_s": 4000.0 / ms,
+                    "level_passes_ms": tm["fused_ms"], "tails_ms": tm["tail_ms"], "top_update_ms": tm["top_ms"]}
     del A
-    view.update_batch(Ud[:5], Vd[:5])
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    view.update_batch(Ud[5:], Vd[5:])
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / steps
-    view.close()
-    return {"workload": "A^16, n=16384, FP32, rank-4 updates", "ms_per_update": ms,
-            "updates_per_s": 1000.0 / ms, "rank1_equiv_per_s": 4000.0 / ms,
-            "alg_GBps": 2 * 4 * 5 * n * n / (ms * 1e-3) / 1e9}
+    return out
 
 
 def bench_batched(torch, lv, synth, dev, rounds=30):
@@ -113,19 +121,20 @@ def bench_batched(torch, lv, synth, dev, rounds=30):
             "alg_bytes_per_round": bytes_round, "alg_GBps": bytes_round / (ms * 1e-3) / 1e9}
 
 
-def bench_serving(torch, lv, synth, dev, seconds=2.0, rate=20000.0, r_coalesce=16):
-    """32 views, n log-uniform in [2048, 16384], k = 16, FP32; Poisson
-    arrivals at `rate` requests/s over views with Zipf(1.1) popularity;
-    per-view coalescing, continuous batching."""
+def bench_serving(torch, lv, synth, dev, seconds=2.0, rate=20000.0, r_coalesce=16, shadow=True):
+    """32 views, n log-uniform in [2048, 16384], k = 16, FP32 (with bfloat16
+    shadows by default); Poisson arrivals at `rate` requests/s over views with
+    Zipf(1.1) popularity; per-view coalescing, continuous batching."""
+    mode = lv.LV_FP32_BF16SHADOW if shadow else lv.LV_FP32
     g = synth.rng(0, 5, 0)
     ns = np.exp(g.uniform(np.log(2048), np.log(16384), size=32)).astype(int)
     pop = np.arange(1, 33, dtype=np.float64) ** -1.1
     pop /= pop.sum()
     perm = g.permutation(32)
-    probe = lv.Server(16 << 20, r_coalesce=r_coalesce)
+    probe = lv.Server(16 << 20, mode=mode, r_coalesce=r_coalesce)
     need = sum(probe.view_bytes(int(n), 16) for n in ns)
     probe.close()
-    srv = lv.Server((16 << 20) + need, r_coalesce=r_coalesce)
+    srv = lv.Server((16 << 20) + need, mode=mode, r_coalesce=r_coalesce)
     ids = []
     for v in range(32):
         A = torch.from_numpy(synth.gaussian_matrix(int(ns[v]), seed=0, config=5, view=v).astype(np.float32)).to(dev)
@@ -156,7 +165,8 @@ def bench_serving(torch, lv, synth, dev, seconds=2.0, rate=20000.0, r_coalesce=1
     t_end = srv.now()
     st = srv.stats()
     srv.close()
-    return {"workload": "32 views, n log-uniform [2048,16384], k=16, FP32, Poisson %.0f req/s, Zipf(1.1)" % rate,
+    return {"workload": "32 views, n log-uniform [2048,16384], k=16, %s, Poisson %.0f req/s, Zipf(1.1)"
+                        % ("FP32 + BF16 shadows" if shadow else "FP32", rate),
             "offered_per_s": rate, "completed": int(st["completed"]),
             "throughput_per_s": st["completed"] / (t_end - t0), "rounds": int(st["rounds"]),
             "mean_coalesced_rank": st["completed"] / max(st["coalesced_updates"], 1),
@@ -388,7 +398,9 @@ def main():
         sec = {}
         for name, fn in (("rank4_n16384", lambda: bench_rank4(torch, lv, synth, dev)),
                          ("batched_64_views", lambda: bench_batched(torch, lv, synth, dev)),
-                         ("serving_32_views", lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds))):
+                         ("serving_32_views", lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds)),
+                         ("serving_32_views_fp32",
+                          lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds, shadow=False))):
             sec[name] = fn()
             torch.cuda.empty_cache()
             log(f"{name}: {sec[name]}")

@@ -19,7 +19,8 @@
  * Conventions for every entry point:
  *  - Matrices are dense, row-major, with a leading dimension (elements per
  *    row) ld >= n.  Element type: double in LV_FP64 mode, float in LV_FP32
- *    mode.  A, U, V and outputs use the view's element type.
+ *    and LV_FP32_BF16SHADOW modes.  A, U, V and outputs use the view's
+ *    element type.
  *  - Device pointers unless stated otherwise.  `stream` is a hipStream_t
  *    (NULL = the default stream).  All device work is enqueued on `stream`
  *    and is asynchronous: the caller keeps inputs unchanged and outputs
@@ -55,9 +56,19 @@ typedef enum {
 
 typedef enum {
   LV_FP64 = 0, /* double storage and arithmetic                           */
-  LV_FP32 = 1  /* float storage and arithmetic; creation and re-anchoring
+  LV_FP32 = 1, /* float storage and arithmetic; creation and re-anchoring
                   square in double and round once; Gram V^T U and the
                   factor assembly are accumulated in double                */
+  LV_FP32_BF16SHADOW = 2
+               /* float storage as LV_FP32, plus a bfloat16 copy (shadow)
+                  of every stored power below the top, rewritten by the
+                  pass that applies the rank update.  The tall-skinny
+                  products P_j U_j and P_j^T V_j of the exponential model
+                  (App. A) read the shadow and multiply on the matrix cores
+                  (bfloat16 inputs, float accumulation); the rank update
+                  itself, the Gram V^T U (double) and the factor assembly
+                  are those of LV_FP32.  Element type at the API: float.
+                  Re-evaluation (lv_reeval) does not take this mode.      */
 } lv_mode;
 
 typedef struct lv_view lv_view;
@@ -87,7 +98,8 @@ const char* lv_last_error(void);
  * update rank r_max.  Returns 0 if the arguments are invalid (same rules as
  * lv_view_create).  The layout is: the m + 1 stored powers (padded order),
  * m + 1 factor slabs (U_j, V_j of every level), per-level reduction
- * partials, and a double-precision squaring scratch (LV_FP32 only). */
+ * partials, the bfloat16 shadows (LV_FP32_BF16SHADOW) and a double-precision
+ * squaring scratch (both float modes). */
 size_t lv_view_footprint(int64_t n, int k, int r_max, lv_mode mode);
 
 /* Create a view of A^k (Table 1 exponential model; ReevalExp).
@@ -130,13 +142,15 @@ lv_status lv_view_read(const lv_view* v, int power, void* out, int64_t ldo, void
 const void* lv_view_data(const lv_view* v, int power, int64_t* ld);
 
 /* Recompute every stored power from the current A (= the stored P_1) by
- * repeated squaring in double precision, discarding accumulated rounding. */
+ * repeated squaring in double precision, discarding accumulated rounding
+ * (bfloat16 shadows are rewritten from the new values). */
 lv_status lv_view_reanchor(lv_view* v, void* stream);
 
 /* Copy out (n x n, leading dimension lds >= n, device) into stored power
  * A^power: restores a checkpoint written with lv_view_read, or lets a test
- * perturb a stored power.  The caller is responsible for consistency of the
- * chain afterwards (see lv_view_drift_check). */
+ * perturb a stored power (its bfloat16 shadow, if any, is rewritten).  The
+ * caller is responsible for consistency of the chain afterwards (see
+ * lv_view_drift_check). */
 lv_status lv_view_write(lv_view* v, int power, const void* src, int64_t lds, void* stream);
 
 /* Drift check of the stored chain (the exponential model defines

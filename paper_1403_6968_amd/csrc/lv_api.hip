@@ -56,6 +56,11 @@ lv_status build_chain(lv_view* v, hipStream_t s, const int* gate = nullptr) {
                      "round P");
       if (st != LV_OK) return st;
     }
+    if (v->shadowed())
+      for (int j = 0; j < L.m; ++j) {
+        st = hip_check(launch_to_bf16(v->P<float>(j), v->shadow(j), L.n_pad * L.ldp, s, gate), "shadow");
+        if (st != LV_OK) return st;
+      }
   }
   return LV_OK;
 }
@@ -119,6 +124,31 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
   if (st != LV_OK) return st;
   for (int j = 0; j < L.m; ++j) {
     const int R = r_pad << j;
+    if constexpr (sizeof(T) == 4) {
+      if (v->shadowed()) {
+        // skinny products from the shadow, FP64 Gram, then the rank update
+        // that also rewrites the shadow (after the skinny pass has read it)
+        st = timed(v, 0, s, "skinny (bf16)", [&] {
+          return launch_skinny_bf16(R, v->shadow(j), L.ldp, L.n_pad, L.tile_rows, sU, sV, L.W, v->partX<float>(j),
+                                    v->partY<float>(j), s);
+        });
+        if (st == LV_OK)
+          st = timed(v, 0, s, "gram", [&] {
+            return launch_level_gram<float>(R, sU, sV, L.W, L.n_pad, L.tile_rows, v->partG(j), s);
+          });
+        if (st == LV_OK)
+          st = timed(v, 0, s, "update + shadow", [&] {
+            return launch_level_update<float>(R, v->P<float>(j), L.ldp, L.n_pad, sU, sV, L.W, s, v->shadow(j));
+          });
+        if (st == LV_OK)
+          st = timed(v, 1, s, "level tail", [&] {
+            return launch_level_tail<float>(R, v->partX<float>(j), v->partY<float>(j), v->partG(j), L.nct, L.nrt,
+                                            L.n_pad, sU, sV, L.W, s);
+          });
+        if (st != LV_OK) return st;
+        continue;
+      }
+    }
     st = timed(v, 0, s, "level pass", [&] {
       return launch_level_fused<T>(R, v->P<T>(j), L.ldp, L.n_pad, L.tile_rows, sU, sV, L.W, v->partX<T>(j),
                                    v->partY<T>(j), v->partG(j), s);
@@ -333,9 +363,13 @@ lv_status lv_view_write(lv_view* v, int power, const void* src, int64_t lds, voi
   if (lds < v->n) return fail(LV_EINVAL, "lds < n");
   const size_t es = v->L.elem;
   char* dst = v->base + v->L.P[j];
-  return hip_check(hipMemcpy2DAsync(dst, v->L.ldp * es, src, lds * es, v->n * es, v->n,
-                                    hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)),
-                   "write");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  lv_status st = hip_check(hipMemcpy2DAsync(dst, v->L.ldp * es, src, lds * es, v->n * es, v->n,
+                                            hipMemcpyDeviceToDevice, s),
+                           "write");
+  if (st == LV_OK && v->shadowed() && j < v->L.m)
+    st = hip_check(launch_to_bf16(v->P<float>(j), v->shadow(j), v->L.n_pad * v->L.ldp, s), "shadow");
+  return st;
 }
 
 lv_status lv_view_stats(const lv_view* v, lv_stats* out) {

@@ -22,6 +22,13 @@ constexpr int kMaxLevel = 10;
 
 inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
+// float -> bfloat16 bits, rounding to nearest even (finite x).
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  uint32_t u = __builtin_bit_cast(uint32_t, x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
 // Columns covered by one tile of the level pass: a wave reads a 1 KiB row
 // segment with one 16-byte vector per lane.
 template <typename T> constexpr int tile_cols() { return 64 * (16 / (int)sizeof(T)); }
@@ -49,6 +56,15 @@ template <typename T> struct TailDesc {
 };
 template <typename T> struct UpdateDesc {
   T* P; int64_t ldp; int n_pad; int tile_rows; const T* Uj; const T* Vj; int W;
+  int nct; int block_begin;             // blocks: nct x ceil(n_pad / tile_rows)
+  uint16_t* S;                          // bfloat16 shadow of P rewritten by the pass, or null
+};
+// Skinny products of a level from the bfloat16 shadow S of P (ld ldp):
+// X = S U_j and Y = S^T V_j, R <= 128, same partial layouts as FusedDesc.
+struct SkinnyDesc {
+  const uint16_t* S; int64_t ldp; int n_pad; int tile_rows;
+  const float* Uj; const float* Vj; int W; int R;
+  float* partX; float* partY; int pR;
   int nct; int block_begin;             // blocks: nct x ceil(n_pad / tile_rows)
 };
 template <typename T> struct PrepDesc {
@@ -96,10 +112,32 @@ hipError_t launch_level_tail(int R, const T* partX, const T* partY, const double
                              int nct, int nrt, int64_t n_pad, T* slabU, T* slabV, int W,
                              hipStream_t s);
 
-// Update-only pass: P += U_j V_j^T for rank R (the top stored power).
+// Update-only pass: P += U_j V_j^T for rank R (the top stored power).  With a
+// non-null shadow S (float only) the pass also writes S = bf16(P) of the new
+// values.
 template <typename T>
 hipError_t launch_level_update(int R, T* P, int64_t ldp, int64_t n_pad, const T* slabU,
-                               const T* slabV, int W, hipStream_t s);
+                               const T* slabV, int W, hipStream_t s, uint16_t* S = nullptr);
+
+// Partial Grams V_j^T U_j in double, one per row tile of tile_rows rows.
+template <typename T>
+hipError_t launch_level_gram(int R, const T* slabU, const T* slabV, int W, int64_t n_pad, int tile_rows,
+                             double* partG, hipStream_t s);
+
+// Skinny products of level rank R (<= 128) from the bfloat16 shadow S on the
+// matrix cores (bf16 x bf16 -> fp32): partial X = S U_j, partial Y = S^T V_j
+// over tiles of tile_rows x 256 (partials as for the fused pass, row stride R).
+hipError_t launch_skinny_bf16(int R, const uint16_t* S, int64_t ldp, int64_t n_pad, int tile_rows,
+                              const float* slabU, const float* slabV, int W, float* partX, float* partY,
+                              hipStream_t s);
+hipError_t launch_skinny_bf16_multi(int nb, const SkinnyDesc* ds, int nd, int blocks, hipStream_t s);
+// Factor blocks of 32 columns the skinny kernel needs for rank R.
+inline int skinny_blocks_for(int R) { return R <= 32 ? 1 : R <= 64 ? 2 : 4; }
+
+// S = bf16(P) for `count` consecutive floats (count a multiple of 4); with a
+// non-null gate only when *gate != 0.
+hipError_t launch_to_bf16(const float* P, uint16_t* S, int64_t count, hipStream_t s,
+                          const int* gate = nullptr);
 
 // Multi-view launches over device descriptor arrays (nd descriptors,
 // `blocks` work-groups in total).  `chunk` selects the read-only skinny pass
@@ -111,7 +149,7 @@ hipError_t launch_gram_multi(int R, const GramDesc<T>* ds, int nd, int blocks, h
 template <typename T>
 hipError_t launch_tail_multi(int R, const TailDesc<T>* ds, int nd, int blocks, hipStream_t s);
 template <typename T>
-hipError_t launch_update_multi(int R, const UpdateDesc<T>* ds, int nd, int blocks, hipStream_t s);
+hipError_t launch_update_multi(int R, bool shadow, const UpdateDesc<T>* ds, int nd, int blocks, hipStream_t s);
 template <typename T>
 hipError_t launch_prep_multi(const PrepDesc<T>* ds, int nd, int blocks, hipStream_t s);
 

@@ -397,11 +397,13 @@ __global__ void __launch_bounds__(256) k_level_tail_multi(const TailDesc<T>* __r
 // ---------------------------------------------------------------- update only
 // P += U_j V_j^T.  Lane holds a 16-byte column group; the wave walks batches
 // of 8 rows with U_j rows broadcast through the scalar unit; ranks above 16
-// are processed in groups of 16 columns of the factors.
-template <typename T, int R>
+// are processed in groups of 16 columns of the factors.  SH (float only):
+// the new values are also written to the bfloat16 shadow S (same ld).
+template <typename T, int R, bool SH>
 __device__ __forceinline__ void update_body(T* __restrict__ P, const int64_t ldp, const int n_pad,
                                             const int tile_rows, const T* __restrict__ Uj,
-                                            const T* __restrict__ Vj, const int W, const int ct, const int rt) {
+                                            const T* __restrict__ Vj, const int W, uint16_t* __restrict__ S,
+                                            const int ct, const int rt) {
   constexpr int EPL = 16 / (int)sizeof(T);
   constexpr int TC = 64 * EPL;
   constexpr int RG = R < 16 ? R : 16;
@@ -443,21 +445,28 @@ __device__ __forceinline__ void update_body(T* __restrict__ P, const int64_t ldp
 #pragma unroll
       for (int q = 0; q < EPL; ++q) p[t].v[q] += d[t][q];
       st16(P + (int64_t)(row0 + rb + t) * ldp + lc, p[t]);
+      if constexpr (SH) {
+        static_assert(EPL == 4, "shadows are kept for float storage only");
+        ushort4 sh;
+        sh.x = bf16_rne(p[t].v[0]); sh.y = bf16_rne(p[t].v[1]);
+        sh.z = bf16_rne(p[t].v[2]); sh.w = bf16_rne(p[t].v[3]);
+        *reinterpret_cast<ushort4*>(S + (int64_t)(row0 + rb + t) * ldp + lc) = sh;
+      }
     }
   }
 }
 
-template <typename T, int R>
+template <typename T, int R, bool SH>
 __global__ void __launch_bounds__(256) k_level_update(const UpdateDesc<T> d) {
-  update_body<T, R>(d.P, d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, blockIdx.x, blockIdx.y);
+  update_body<T, R, SH>(d.P, d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.S, blockIdx.x, blockIdx.y);
 }
 
-template <typename T, int R>
+template <typename T, int R, bool SH>
 __global__ void __launch_bounds__(256) k_level_update_multi(const UpdateDesc<T>* __restrict__ ds, int nd) {
   const int v = find_desc(ds, nd, (int)blockIdx.x);
   const UpdateDesc<T> d = ds[v];
   const int local = (int)blockIdx.x - d.block_begin;
-  update_body<T, R>(d.P, d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, local % d.nct, local / d.nct);
+  update_body<T, R, SH>(d.P, d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.S, local % d.nct, local / d.nct);
 }
 
 // ---------------------------------------------------------------- small kernels
@@ -512,12 +521,28 @@ hipError_t fused_launch(T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T
 
 template <typename T, int R>
 hipError_t update_r(T* P, int64_t ldp, int64_t n_pad, const T* Uj, const T* Vj, int W,
-                    hipStream_t s) {
+                    hipStream_t s, uint16_t* S = nullptr) {
   const int tile_rows = kUpdateTileRows;
   const int nct = (int)(n_pad / tile_cols<T>());
-  const UpdateDesc<T> d{P, ldp, (int)n_pad, tile_rows, Uj, Vj, W, nct, 0};
+  const UpdateDesc<T> d{P, ldp, (int)n_pad, tile_rows, Uj, Vj, W, nct, 0, S};
   const dim3 grid((unsigned)nct, (unsigned)((n_pad + tile_rows - 1) / tile_rows));
-  hipLaunchKernelGGL((k_level_update<T, R>), grid, dim3(256), 0, s, d);
+  if constexpr (sizeof(T) == 4) {
+    if (S != nullptr) {
+      hipLaunchKernelGGL((k_level_update<T, R, true>), grid, dim3(256), 0, s, d);
+      return hipGetLastError();
+    }
+  }
+  if (S != nullptr) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_level_update<T, R, false>), grid, dim3(256), 0, s, d);
+  return hipGetLastError();
+}
+
+template <typename T, int R>
+hipError_t gram_r(const T* Uj, const T* Vj, int W, int64_t n_pad, int tile_rows, double* partG, hipStream_t s) {
+  const int nrt = (int)((n_pad + tile_rows - 1) / tile_rows);
+  const GramDesc<T> g{Uj, Vj, W, (int)n_pad, tile_rows, partG, nrt, 0};
+  const dim3 ggrid((unsigned)nrt, (unsigned)((R * R + gram_pairs_per_block(R) - 1) / gram_pairs_per_block(R)));
+  hipLaunchKernelGGL((k_gram<T, R>), ggrid, dim3(256), 0, s, g);
   return hipGetLastError();
 }
 
@@ -539,11 +564,7 @@ hipError_t fused_r(T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* Uj,
                                                    partX + c0, partY + c0, nullptr, R, s);
       if (e != hipSuccess) return e;
     }
-    const int nrt = (int)((n_pad + tile_rows - 1) / tile_rows);
-    const GramDesc<T> g{Uj, Vj, W, (int)n_pad, tile_rows, partG, nrt, 0};
-    const dim3 ggrid((unsigned)nrt, (unsigned)((R * R + gram_pairs_per_block(R) - 1) / gram_pairs_per_block(R)));
-    hipLaunchKernelGGL((k_gram<T, R>), ggrid, dim3(256), 0, s, g);
-    hipError_t e = hipGetLastError();
+    hipError_t e = gram_r<T, R>(Uj, Vj, W, n_pad, tile_rows, partG, s);
     if (e != hipSuccess) return e;
     return update_r<T, R>(P, ldp, n_pad, Uj, Vj, W, s);
   }
@@ -605,11 +626,19 @@ hipError_t launch_level_tail(int R, const T* partX, const T* partY, const double
 
 template <typename T>
 hipError_t launch_level_update(int R, T* P, int64_t ldp, int64_t n_pad, const T* slabU,
-                               const T* slabV, int W, hipStream_t s) {
+                               const T* slabV, int W, hipStream_t s, uint16_t* S) {
   const T* Uj = slabU;
   const T* Vj = slabV + (W - R);
-  if (R == 256) return update_r<T, 256>(P, ldp, n_pad, Uj, Vj, W, s);
-  LV_RANK_SWITCH(R, return (update_r<T, RR>(P, ldp, n_pad, Uj, Vj, W, s)))
+  if (R == 256) return update_r<T, 256>(P, ldp, n_pad, Uj, Vj, W, s, S);
+  LV_RANK_SWITCH(R, return (update_r<T, RR>(P, ldp, n_pad, Uj, Vj, W, s, S)))
+}
+
+template <typename T>
+hipError_t launch_level_gram(int R, const T* slabU, const T* slabV, int W, int64_t n_pad, int tile_rows,
+                             double* partG, hipStream_t s) {
+  const T* Uj = slabU;
+  const T* Vj = slabV + (W - R);
+  LV_RANK_SWITCH(R, return (gram_r<T, RR>(Uj, Vj, W, n_pad, tile_rows, partG, s)))
 }
 
 // ---- multi-view launchers
@@ -636,13 +665,8 @@ hipError_t launch_fused_multi(int R, bool chunk, const FusedDesc<T>* ds, int nd,
 template <typename T>
 hipError_t launch_gram_multi(int R, const GramDesc<T>* ds, int nd, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  switch (R) {
-    case 32: hipLaunchKernelGGL((k_gram_multi<T, 32>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
-    case 64: hipLaunchKernelGGL((k_gram_multi<T, 64>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
-    case 128: hipLaunchKernelGGL((k_gram_multi<T, 128>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  LV_RANK_SWITCH(R, hipLaunchKernelGGL((k_gram_multi<T, RR>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd);
+                 return hipGetLastError())
 }
 
 template <typename T>
@@ -652,15 +676,25 @@ hipError_t launch_tail_multi(int R, const TailDesc<T>* ds, int nd, int blocks, h
                  return hipGetLastError())
 }
 
-template <typename T>
-hipError_t launch_update_multi(int R, const UpdateDesc<T>* ds, int nd, int blocks, hipStream_t s) {
-  if (blocks <= 0) return hipSuccess;
+template <typename T, bool SH>
+hipError_t update_multi_sh(int R, const UpdateDesc<T>* ds, int nd, int blocks, hipStream_t s) {
   if (R == 256) {
-    hipLaunchKernelGGL((k_level_update_multi<T, 256>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd);
+    hipLaunchKernelGGL((k_level_update_multi<T, 256, SH>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd);
     return hipGetLastError();
   }
-  LV_RANK_SWITCH(R, hipLaunchKernelGGL((k_level_update_multi<T, RR>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd);
+  LV_RANK_SWITCH(R, hipLaunchKernelGGL((k_level_update_multi<T, RR, SH>), dim3((unsigned)blocks), dim3(256), 0, s,
+                                       ds, nd);
                  return hipGetLastError())
+}
+
+template <typename T>
+hipError_t launch_update_multi(int R, bool shadow, const UpdateDesc<T>* ds, int nd, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  if constexpr (sizeof(T) == 4) {
+    if (shadow) return update_multi_sh<T, true>(R, ds, nd, blocks, s);
+  }
+  if (shadow) return hipErrorInvalidValue;
+  return update_multi_sh<T, false>(R, ds, nd, blocks, s);
 }
 
 template <typename T>
@@ -678,11 +712,13 @@ hipError_t launch_prep_multi(const PrepDesc<T>* ds, int nd, int blocks, hipStrea
   template hipError_t launch_level_tail<T>(int, const T*, const T*, const double*, int, int,      \
                                            int64_t, T*, T*, int, hipStream_t);                    \
   template hipError_t launch_level_update<T>(int, T*, int64_t, int64_t, const T*, const T*, int,  \
-                                             hipStream_t);                                        \
+                                             hipStream_t, uint16_t*);                             \
+  template hipError_t launch_level_gram<T>(int, const T*, const T*, int, int64_t, int, double*,   \
+                                           hipStream_t);                                          \
   template hipError_t launch_fused_multi<T>(int, bool, const FusedDesc<T>*, int, int, hipStream_t); \
   template hipError_t launch_gram_multi<T>(int, const GramDesc<T>*, int, int, hipStream_t);        \
   template hipError_t launch_tail_multi<T>(int, const TailDesc<T>*, int, int, hipStream_t);        \
-  template hipError_t launch_update_multi<T>(int, const UpdateDesc<T>*, int, int, hipStream_t);    \
+  template hipError_t launch_update_multi<T>(int, bool, const UpdateDesc<T>*, int, int, hipStream_t); \
   template hipError_t launch_prep_multi<T>(const PrepDesc<T>*, int, int, hipStream_t);
 LV_INST(float)
 LV_INST(double)

@@ -7,6 +7,9 @@
 //     Gram (R > 16), one launch per R
 //     rank-R update of level j (R > 16) and top-level updates, one per R
 //     tails (reductions + next factors), one launch per R
+// Views with bfloat16 shadows run, below their top level, the shadow skinny
+// pass (one launch per factor-block count), the Gram and the update that
+// rewrites the shadow (one launch per R) in place of the fused pass.
 // Every view runs exactly the kernels of lv_view_update, so its result is
 // identical bit for bit to an update applied alone with the same factors.
 #pragma once
@@ -19,7 +22,7 @@
 
 namespace lv {
 
-enum Kind { kPrep, kFused, kChunk, kGram, kUpdate, kTail };
+enum Kind { kPrep, kFused, kChunk, kSkinny, kGram, kUpdate, kUpdateShadow, kTail };
 
 struct LaunchRec {
   Kind kind;
@@ -53,6 +56,7 @@ template <typename T> int fused_blocks(const FusedDesc<T>& d) {
 template <typename T> int update_blocks(const UpdateDesc<T>& d) {
   return d.nct * ((d.n_pad + d.tile_rows - 1) / d.tile_rows);
 }
+inline int skinny_blocks(const SkinnyDesc& d) { return d.nct * ((d.n_pad + d.tile_rows - 1) / d.tile_rows); }
 template <typename T> int prep_blocks(const PrepDesc<T>& d) {
   return (int)((d.n_pad * d.r_pad + 255) / 256);
 }
@@ -82,8 +86,9 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
   for (int j = 0; j <= max_m; ++j) {
     std::map<int, std::vector<FusedDesc<T>>> fused;
     std::vector<FusedDesc<T>> chunks;
+    std::map<int, std::vector<SkinnyDesc>> skinny;
     std::map<int, std::vector<GramDesc<T>>> gram;
-    std::map<int, std::vector<UpdateDesc<T>>> upd;
+    std::map<int, std::vector<UpdateDesc<T>>> upd, updsh;
     std::map<int, std::vector<TailDesc<T>>> tail;
     for (lv_view* v : views) {
       const Layout& L = v->L;
@@ -96,6 +101,19 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
         upd[R].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, kUpdateTileRows, sU, Vj, L.W,
                           (int)(L.n_pad / tile_cols_bytes(L.elem)), 0});
         continue;
+      }
+      const int upd_nct = (int)(L.n_pad / tile_cols_bytes(L.elem));
+      if constexpr (sizeof(T) == 4) {
+        if (v->shadowed()) {
+          skinny[skinny_blocks_for(R)].push_back({v->shadow(j), L.ldp, (int)L.n_pad, L.tile_rows, sU, Vj, L.W, R,
+                                                  v->partX<T>(j), v->partY<T>(j), R, L.nct, 0});
+          gram[R].push_back({sU, Vj, L.W, (int)L.n_pad, L.tile_rows, v->partG(j), L.nrt, 0});
+          updsh[R].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, kUpdateTileRows, sU, Vj, L.W, upd_nct, 0,
+                              v->shadow(j)});
+          tail[R].push_back({v->partX<T>(j), v->partY<T>(j), v->partG(j), L.nct, L.nrt, (int)L.n_pad, sU, sV, L.W,
+                             0});
+          continue;
+        }
       }
       if (R <= kMaxFusedRank) {
         fused[R].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, L.tile_rows, sU, Vj, L.W, v->partX<T>(j),
@@ -112,12 +130,14 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
     }
     for (auto& kv : fused) pl.add(kFused, kv.first, kv.second, &fused_blocks<T>);
     pl.add(kChunk, kMaxFusedRank, chunks, &fused_blocks<T>);
+    for (auto& kv : skinny) pl.add(kSkinny, kv.first, kv.second, &skinny_blocks);
     for (auto& kv : gram) {
       const int R = kv.first;
       const int chunks_per_tile = (R * R + gram_pairs_per_block(R) - 1) / gram_pairs_per_block(R);
       pl.add(kGram, R, kv.second, [chunks_per_tile](const GramDesc<T>& d) { return d.nrt * chunks_per_tile; });
     }
     for (auto& kv : upd) pl.add(kUpdate, kv.first, kv.second, &update_blocks<T>);
+    for (auto& kv : updsh) pl.add(kUpdateShadow, kv.first, kv.second, &update_blocks<T>);
     for (auto& kv : tail) {
       const int R = kv.first;
       pl.add(kTail, R, kv.second, [R](const TailDesc<T>& d) { return tail_blocks(d.n_pad, R); });
@@ -137,7 +157,11 @@ lv_status enqueue_round(const Plan& pl, const char* dbase, hipStream_t s) {
       case kFused: e = launch_fused_multi<T>(l.R, false, static_cast<const FusedDesc<T>*>(d), l.nd, l.blocks, s); break;
       case kChunk: e = launch_fused_multi<T>(l.R, true, static_cast<const FusedDesc<T>*>(d), l.nd, l.blocks, s); break;
       case kGram: e = launch_gram_multi<T>(l.R, static_cast<const GramDesc<T>*>(d), l.nd, l.blocks, s); break;
-      case kUpdate: e = launch_update_multi<T>(l.R, static_cast<const UpdateDesc<T>*>(d), l.nd, l.blocks, s); break;
+      case kSkinny: e = launch_skinny_bf16_multi(l.R, static_cast<const SkinnyDesc*>(d), l.nd, l.blocks, s); break;
+      case kUpdate: e = launch_update_multi<T>(l.R, false, static_cast<const UpdateDesc<T>*>(d), l.nd, l.blocks, s); break;
+      case kUpdateShadow:
+        e = launch_update_multi<T>(l.R, true, static_cast<const UpdateDesc<T>*>(d), l.nd, l.blocks, s);
+        break;
       case kTail: e = launch_tail_multi<T>(l.R, static_cast<const TailDesc<T>*>(d), l.nd, l.blocks, s); break;
     }
     lv_status st = hip_check(e, "batch launch");

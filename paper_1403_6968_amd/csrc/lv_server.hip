@@ -246,7 +246,7 @@ lv_status lv_server_create(void* arena, size_t arena_bytes, lv_mode mode, int r_
   g_err[0] = 0;
   if (!out) return fail(LV_EINVAL, "out is NULL");
   *out = nullptr;
-  if (mode != LV_FP64 && mode != LV_FP32) return fail(LV_EINVAL, "unknown mode");
+  if (mode != LV_FP64 && mode != LV_FP32 && mode != LV_FP32_BF16SHADOW) return fail(LV_EINVAL, "unknown mode");
   if (r_coalesce < 1 || r_coalesce > 64) return fail(LV_EINVAL, "r_coalesce outside [1, 64]");
   if (!arena || reinterpret_cast<uintptr_t>(arena) % kAlign) return fail(LV_EINVAL, "arena NULL or misaligned");
   if (arena_bytes < kRingSlots * kSlotBytes) return fail(LV_ENOMEM, "arena smaller than the descriptor ring");

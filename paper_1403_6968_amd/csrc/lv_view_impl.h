@@ -36,13 +36,15 @@ struct Layout {
   size_t partX[kMaxLevel] = {};
   size_t partY[kMaxLevel] = {};
   size_t partG[kMaxLevel] = {};
+  size_t shadow[kMaxLevel] = {};   // bfloat16 copies of P_0..P_{m-1} (LV_FP32_BF16SHADOW)
   size_t scratch[2] = {};
   size_t probe = 0;  // zpad | Pz (m+1 vectors) | PPz (m vectors) | residuals | gate | counter
   size_t total = 0;
 };
 
 inline lv_status check_shape(int64_t n, int k, int r_max, lv_mode mode) {
-  if (mode != LV_FP64 && mode != LV_FP32) return fail(LV_EINVAL, "unknown mode %d", (int)mode);
+  if (mode != LV_FP64 && mode != LV_FP32 && mode != LV_FP32_BF16SHADOW)
+    return fail(LV_EINVAL, "unknown mode %d", (int)mode);
   if (n < 1 || n > kMaxOrder) return fail(LV_EINVAL, "n = %lld outside [1, %lld]", (long long)n, (long long)kMaxOrder);
   if (!is_pow2(k) || k > kMaxK) return fail(LV_EINVAL, "k = %d is not a power of two in [1, %d]", k, kMaxK);
   if (r_max < 1) return fail(LV_EINVAL, "r_max = %d < 1", r_max);
@@ -77,7 +79,9 @@ inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode) {
     L.partY[j] = off; off = align_up(off + (size_t)L.nrt * L.n_pad * R * L.elem);
     L.partG[j] = off; off = align_up(off + (size_t)L.nrt * R * R * sizeof(double));
   }
-  if (mode == LV_FP32 && L.m > 0) {
+  if (mode == LV_FP32_BF16SHADOW)
+    for (int j = 0; j < L.m; ++j) { L.shadow[j] = off; off = align_up(off + (size_t)L.n_pad * L.ldp * 2); }
+  if (mode != LV_FP64 && L.m > 0) {
     const size_t dmat = (size_t)L.n_pad * L.n_pad * sizeof(double);
     L.scratch[0] = off; off = align_up(off + dmat);
     L.scratch[1] = off; off = align_up(off + dmat);
@@ -119,6 +123,8 @@ struct lv_view {
   template <typename T> T* partX(int j) const { return reinterpret_cast<T*>(base + L.partX[j]); }
   template <typename T> T* partY(int j) const { return reinterpret_cast<T*>(base + L.partY[j]); }
   double* partG(int j) const { return reinterpret_cast<double*>(base + L.partG[j]); }
+  uint16_t* shadow(int j) const { return reinterpret_cast<uint16_t*>(base + L.shadow[j]); }
+  bool shadowed() const { return mode == LV_FP32_BF16SHADOW; }
   double* scratch(int i) const { return reinterpret_cast<double*>(base + L.scratch[i]); }
   double* zpad() const { return reinterpret_cast<double*>(base + L.probe); }
   double* Pz(int j) const { return zpad() + (size_t)(1 + j) * L.n_pad; }

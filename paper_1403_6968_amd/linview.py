@@ -21,9 +21,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblinview.so")
 
 LV_OK, LV_EINVAL, LV_ENOMEM, LV_EDEVICE, LV_ESTATE = 0, 1, 2, 3, 4
-LV_FP64, LV_FP32 = 0, 1
+LV_FP64, LV_FP32, LV_FP32_BF16SHADOW = 0, 1, 2
 
-_MODE_DTYPE = {LV_FP64: torch.float64, LV_FP32: torch.float32}
+_MODE_DTYPE = {LV_FP64: torch.float64, LV_FP32: torch.float32, LV_FP32_BF16SHADOW: torch.float32}
 
 EXPORTED = (
     "lv_status_str", "lv_last_error", "lv_view_footprint", "lv_view_create",

@@ -30,18 +30,19 @@ SHAPES = [(256, 16, 1), (300, 8, 3), (700, 16, 2), (513, 1, 2), (1100, 4, 5), (3
           (640, 2, 8), (256, 16, 8), (900, 16, 1), (128, 8, 7)]
 
 
-@pytest.mark.parametrize("dtype_name", ["f32", "f64"])
+@pytest.mark.parametrize("dtype_name", ["f32", "f64", "bf16"])
 def test_batch_rounds_match_single_views_and_oracle(dtype_name):
     need_gpu()
     import torch
     from paper_1403_6968_amd import linview as lv
-    td, nd = (torch.float32, np.float32) if dtype_name == "f32" else (torch.float64, np.float64)
+    td, nd = (torch.float64, np.float64) if dtype_name == "f64" else (torch.float32, np.float32)
+    mode = {"f32": lv.LV_FP32, "f64": lv.LV_FP64, "bf16": lv.LV_FP32_BF16SHADOW}[dtype_name]
     rounds = 4
     views, twins, ref, staged = [], [], [], []
     for v, (n, k, r) in enumerate(SHAPES):
         A = synth.gaussian_matrix(n, seed=30, config=4, view=v).astype(nd).astype(np.float64)
-        views.append(lv.View(dev(A, td), k, r_max=r))
-        twins.append(lv.View(dev(A, td), k, r_max=r))
+        views.append(lv.View(dev(A, td), k, r_max=r, mode=mode))
+        twins.append(lv.View(dev(A, td), k, r_max=r, mode=mode))
         ref.append(O.reeval(A, k))
     batch = lv.Batch(views)
     for t in range(rounds):
@@ -62,7 +63,7 @@ def test_batch_rounds_match_single_views_and_oracle(dtype_name):
             twins[v].update(dev(Up, td), dev(Vp, td))
             ref[v] = O.incr_update(ref[v], U, V)
         batch.update()
-    tol = 1e-10 if dtype_name == "f64" else 1e-4
+    tol = {"f64": 1e-10, "f32": 1e-4, "bf16": 5e-3}[dtype_name]
     worst = 0.0
     for v in range(len(SHAPES)):
         got, twin = read_all(views[v]), read_all(twins[v])
