@@ -111,8 +111,10 @@ lv_status timed(lv_view* v, int kind, hipStream_t s, const char* what, F&& launc
 }
 
 // One update through every level, factors in slab `sl` (App. A exponential
-// model; trigger of Sec. 4.4): levels 0..m-1 run the fused pass and the tail,
-// the top level the update-only pass.
+// model; trigger of Sec. 4.4): levels 0..m-1 run the fused pass and the tail
+// (or, for float storage at large level rank and with bfloat16 shadows, the
+// read-only skinny pass, the Gram and the update pass), the top level the
+// update-only pass.
 template <typename T>
 lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int64_t ldv, int sl,
                      hipStream_t s) {
@@ -125,25 +127,29 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
   for (int j = 0; j < L.m; ++j) {
     const int R = r_pad << j;
     if constexpr (sizeof(T) == 4) {
-      if (v->shadowed()) {
-        // skinny products from the shadow, FP64 Gram, then the rank update
-        // that also rewrites the shadow (after the skinny pass has read it)
-        st = timed(v, 0, s, "skinny (bf16)", [&] {
-          return launch_skinny_bf16(R, v->shadow(j), L.ldp, L.n_pad, L.tile_rows, sU, sV, L.W, v->partX<float>(j),
-                                    v->partY<float>(j), s);
+      if (v->shadowed() || skinny_on_mfma(R, 4)) {
+        // read-only skinny pass on the matrix cores (from the shadow, or from
+        // the float power), FP64 Gram, then the rank update (which rewrites
+        // the shadow after the skinny pass has read it)
+        st = timed(v, 0, s, "skinny", [&] {
+          return v->shadowed() ? launch_skinny_bf16(R, v->shadow(j), L.ldp, L.n_pad, L.tile_rows, sU, sV, L.W,
+                                                    v->partX<float>(j), v->partY<float>(j), s)
+                               : launch_skinny_f32(R, v->P<float>(j), L.ldp, L.n_pad, L.tile_rows, sU, sV, L.W,
+                                                   v->partX<float>(j), v->partY<float>(j), s);
         });
         if (st == LV_OK)
           st = timed(v, 0, s, "gram", [&] {
-            return launch_level_gram<float>(R, sU, sV, L.W, L.n_pad, L.tile_rows, v->partG(j), s);
+            return launch_level_gram<float>(R, sU, sV, L.W, L.n_pad, v->partG(j), s);
           });
         if (st == LV_OK)
-          st = timed(v, 0, s, "update + shadow", [&] {
-            return launch_level_update<float>(R, v->P<float>(j), L.ldp, L.n_pad, sU, sV, L.W, s, v->shadow(j));
+          st = timed(v, 0, s, "update", [&] {
+            return launch_level_update<float>(R, v->P<float>(j), L.ldp, L.n_pad, sU, sV, L.W, s,
+                                              v->shadowed() ? v->shadow(j) : nullptr);
           });
         if (st == LV_OK)
           st = timed(v, 1, s, "level tail", [&] {
             return launch_level_tail<float>(R, v->partX<float>(j), v->partY<float>(j), v->partG(j), L.nct, L.nrt,
-                                            L.n_pad, sU, sV, L.W, s);
+                                            1, L.n_pad, sU, sV, L.W, s);
           });
         if (st != LV_OK) return st;
         continue;
@@ -155,8 +161,8 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
     });
     if (st != LV_OK) return st;
     st = timed(v, 1, s, "level tail", [&] {
-      return launch_level_tail<T>(R, v->partX<T>(j), v->partY<T>(j), v->partG(j), L.nct, L.nrt, L.n_pad, sU,
-                                  sV, L.W, s);
+      return launch_level_tail<T>(R, v->partX<T>(j), v->partY<T>(j), v->partG(j), L.nct, L.nrt,
+                                  gram_in_pass(R, (int)sizeof(T)) ? L.nrt : 1, L.n_pad, sU, sV, L.W, s);
     });
     if (st != LV_OK) return st;
   }

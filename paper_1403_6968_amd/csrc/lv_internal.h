@@ -53,16 +53,22 @@ template <typename T> struct GramDesc {
 template <typename T> struct TailDesc {
   const T* partX; const T* partY; const double* partG; int nct; int nrt; int n_pad;
   T* slabU; T* slabV; int W; int block_begin;   // blocks: ceil(n_pad * R / 256)
+  int ng;                                       // Gram partials to add (1: already summed)
+};
+// Sum of ng Gram partials (count doubles each) into the first.
+struct GramSumDesc {
+  double* G; int ng; int count; int block_begin;   // blocks: ceil(count / 256)
 };
 template <typename T> struct UpdateDesc {
   T* P; int64_t ldp; int n_pad; int tile_rows; const T* Uj; const T* Vj; int W;
   int nct; int block_begin;             // blocks: nct x ceil(n_pad / tile_rows)
   uint16_t* S;                          // bfloat16 shadow of P rewritten by the pass, or null
 };
-// Skinny products of a level from the bfloat16 shadow S of P (ld ldp):
-// X = S U_j and Y = S^T V_j, R <= 128, same partial layouts as FusedDesc.
+// Read-only skinny products of a level on the matrix cores, from the
+// bfloat16 shadow of P or from P itself (float): X = P U_j and Y = P^T V_j
+// for R columns of the factors (partials with row stride pR, as FusedDesc).
 struct SkinnyDesc {
-  const uint16_t* S; int64_t ldp; int n_pad; int tile_rows;
+  const void* src; int64_t ldp; int n_pad; int tile_rows;
   const float* Uj; const float* Vj; int W; int R;
   float* partX; float* partY; int pR;
   int nct; int block_begin;             // blocks: nct x ceil(n_pad / tile_rows)
@@ -72,8 +78,26 @@ template <typename T> struct PrepDesc {
   T* slabU; T* slabV; int W; int64_t n_pad; int block_begin;   // blocks: ceil(n_pad * r_pad / 256)
 };
 
-// Rows per tile of the update-only pass.
+// Tiling of the update pass.  The vector kernel covers tiles of 256 rows x
+// (64 lanes x 16 bytes); float storage with rank R >= kMfmaUpdateRank uses
+// the matrix-core kernel on 128 x 128 tiles.
 constexpr int kUpdateTileRows = 256;
+constexpr int kMfmaUpdateRank = 32;
+constexpr int kMfmaUpdateTile = 128;
+inline bool update_on_mfma(int R, int elem) { return elem == 4 && R >= kMfmaUpdateRank; }
+inline int update_tile_rows(int R, int elem) { return update_on_mfma(R, elem) ? kMfmaUpdateTile : kUpdateTileRows; }
+inline int update_tile_cols(int R, int elem) { return update_on_mfma(R, elem) ? kMfmaUpdateTile : tile_cols_bytes(elem); }
+// Rows per partial of the stand-alone Gram kernel, and its partial count.
+constexpr int kGramRows = 64;
+inline int gram_tiles(int64_t n_pad) { return (int)(n_pad / kGramRows); }
+// Float storage with level rank R >= kMfmaSkinnyRank forms the skinny
+// products on the matrix cores in a read-only pass (then Gram, update);
+// smaller ranks use the fused vector pass.
+constexpr int kMfmaSkinnyRank = 16;
+inline bool skinny_on_mfma(int R, int elem) { return elem == 4 && R >= kMfmaSkinnyRank; }
+// Whether the fused pass of rank R forms the Gram partials itself (one per
+// row tile); otherwise the stand-alone Gram kernel and its sum provide G.
+inline bool gram_in_pass(int R, int elem) { return R <= kMaxFusedRank && !skinny_on_mfma(R, elem); }
 // Work-groups of a tail launch / Gram pairs per work-group for rank R.
 inline int tail_blocks(int64_t n_pad, int R) { return (int)((n_pad * R + 255) / 256); }
 inline int gram_pairs_per_block(int R) {
@@ -105,11 +129,11 @@ hipError_t launch_level_fused(int R, T* P, int64_t ldp, int64_t n_pad, int tile_
                               const T* slabU, const T* slabV, int W, T* partX, T* partY,
                               double* partG, hipStream_t s);
 
-// Tail of level j: reduce partials in a fixed order, G = sum of partial
-// Grams, U_{j+1} = [U_j, X + U_j G], V_{j+1} = [Y, V_j].
+// Tail of level j: reduce partials in a fixed order, G = sum of the ng
+// partial Grams, U_{j+1} = [U_j, X + U_j G], V_{j+1} = [Y, V_j].
 template <typename T>
 hipError_t launch_level_tail(int R, const T* partX, const T* partY, const double* partG,
-                             int nct, int nrt, int64_t n_pad, T* slabU, T* slabV, int W,
+                             int nct, int nrt, int ng, int64_t n_pad, T* slabU, T* slabV, int W,
                              hipStream_t s);
 
 // Update-only pass: P += U_j V_j^T for rank R (the top stored power).  With a
@@ -119,10 +143,12 @@ template <typename T>
 hipError_t launch_level_update(int R, T* P, int64_t ldp, int64_t n_pad, const T* slabU,
                                const T* slabV, int W, hipStream_t s, uint16_t* S = nullptr);
 
-// Partial Grams V_j^T U_j in double, one per row tile of tile_rows rows.
+// Gram V_j^T U_j in double: gram_tiles(n_pad) partials of kGramRows rows,
+// then their sum in fixed order into partG[0 .. R*R).
 template <typename T>
-hipError_t launch_level_gram(int R, const T* slabU, const T* slabV, int W, int64_t n_pad, int tile_rows,
-                             double* partG, hipStream_t s);
+hipError_t launch_level_gram(int R, const T* slabU, const T* slabV, int W, int64_t n_pad, double* partG,
+                             hipStream_t s);
+hipError_t launch_gram_sum_multi(const GramSumDesc* ds, int nd, int blocks, hipStream_t s);
 
 // Skinny products of level rank R (<= 128) from the bfloat16 shadow S on the
 // matrix cores (bf16 x bf16 -> fp32): partial X = S U_j, partial Y = S^T V_j
@@ -131,8 +157,18 @@ hipError_t launch_skinny_bf16(int R, const uint16_t* S, int64_t ldp, int64_t n_p
                               const float* slabU, const float* slabV, int W, float* partX, float* partY,
                               hipStream_t s);
 hipError_t launch_skinny_bf16_multi(int nb, const SkinnyDesc* ds, int nd, int blocks, hipStream_t s);
-// Factor blocks of 32 columns the skinny kernel needs for rank R.
+// Factor blocks of 32 columns the bfloat16 skinny kernel needs for rank R.
 inline int skinny_blocks_for(int R) { return R <= 32 ? 1 : R <= 64 ? 2 : 4; }
+
+// The same products from the float power P (v_mfma_f32_32x32x2f32, float
+// products and accumulation), R <= 128 (64 factor columns per launch).
+hipError_t launch_skinny_f32(int R, const float* P, int64_t ldp, int64_t n_pad, int tile_rows,
+                             const float* slabU, const float* slabV, int W, float* partX, float* partY,
+                             hipStream_t s);
+hipError_t launch_skinny_f32_multi(int nb, const SkinnyDesc* ds, int nd, int blocks, hipStream_t s);
+// Factor blocks of 32 columns per float skinny launch, and launches for R.
+inline int skinny_f32_blocks(int R) { return R <= 32 ? 1 : 2; }
+inline int skinny_f32_launches(int R) { return R <= 64 ? 1 : R / 64; }
 
 // S = bf16(P) for `count` consecutive floats (count a multiple of 4); with a
 // non-null gate only when *gate != 0.

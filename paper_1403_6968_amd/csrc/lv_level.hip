@@ -329,6 +329,31 @@ __global__ void __launch_bounds__(256) k_gram_multi(const GramDesc<T>* __restric
   gram_body<T, R>(d.Uj, d.Vj, d.W, d.n_pad, d.tile_rows, d.partG, local % d.nrt, local / d.nrt);
 }
 
+// G[idx] = sum over t < ng of G[t * count + idx], in index order, into the
+// first partial.
+__device__ __forceinline__ void gram_sum_body(double* __restrict__ G, const int ng, const int count, const int blk) {
+  const int idx = blk * 256 + (int)threadIdx.x;
+  if (idx >= count) return;
+  double g = 0.0;
+  int t = 0;
+  for (; t + 8 <= ng; t += 8) {
+    double v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = G[(int64_t)(t + e) * count + idx];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) g += v[e];
+  }
+  for (; t < ng; ++t) g += G[(int64_t)t * count + idx];
+  G[idx] = g;
+}
+
+__global__ void __launch_bounds__(256) k_gram_sum(const GramSumDesc d) { gram_sum_body(d.G, d.ng, d.count, blockIdx.x); }
+
+__global__ void __launch_bounds__(256) k_gram_sum_multi(const GramSumDesc* __restrict__ ds, int nd) {
+  const GramSumDesc d = ds[find_desc(ds, nd, (int)blockIdx.x)];
+  gram_sum_body(d.G, d.ng, d.count, (int)blockIdx.x - d.block_begin);
+}
+
 // ---------------------------------------------------------------- tail
 // One thread per (row, c): the partials of the row tiles / column tiles are
 // loaded in batches of 8 (independent loads in flight) and added in index
@@ -336,7 +361,8 @@ __global__ void __launch_bounds__(256) k_gram_multi(const GramDesc<T>* __restric
 template <typename T, int R>
 __device__ __forceinline__ void tail_body(const T* __restrict__ partX, const T* __restrict__ partY,
                                           const double* __restrict__ partG, const int nct, const int nrt,
-                                          const int n_pad, T* slabU, T* slabV, const int W, const int blk) {
+                                          const int ng, const int n_pad, T* slabU, T* slabV, const int W,
+                                          const int blk) {
   const T* Ucur = slabU;
   T* Unew = slabU + R;
   T* Vnew = slabV + (W - 2 * R);
@@ -344,7 +370,7 @@ __device__ __forceinline__ void tail_body(const T* __restrict__ partX, const T* 
   const int tid = threadIdx.x;
   for (int idx = tid; idx < R * R; idx += 256) {
     double g = 0.0;
-    for (int t = 0; t < nrt; ++t) g += partG[(int64_t)t * R * R + idx];
+    for (int t = 0; t < ng; ++t) g += partG[(int64_t)t * R * R + idx];
     G[idx] = g;
   }
   __syncthreads();
@@ -383,14 +409,14 @@ __device__ __forceinline__ void tail_body(const T* __restrict__ partX, const T* 
 
 template <typename T, int R>
 __global__ void __launch_bounds__(256) k_level_tail(const TailDesc<T> d) {
-  tail_body<T, R>(d.partX, d.partY, d.partG, d.nct, d.nrt, d.n_pad, d.slabU, d.slabV, d.W, blockIdx.x);
+  tail_body<T, R>(d.partX, d.partY, d.partG, d.nct, d.nrt, d.ng, d.n_pad, d.slabU, d.slabV, d.W, blockIdx.x);
 }
 
 template <typename T, int R>
 __global__ void __launch_bounds__(256) k_level_tail_multi(const TailDesc<T>* __restrict__ ds, int nd) {
   const int v = find_desc(ds, nd, (int)blockIdx.x);
   const TailDesc<T> d = ds[v];
-  tail_body<T, R>(d.partX, d.partY, d.partG, d.nct, d.nrt, d.n_pad, d.slabU, d.slabV, d.W,
+  tail_body<T, R>(d.partX, d.partY, d.partG, d.nct, d.nrt, d.ng, d.n_pad, d.slabU, d.slabV, d.W,
                   (int)blockIdx.x - d.block_begin);
 }
 
@@ -456,9 +482,104 @@ __device__ __forceinline__ void update_body(T* __restrict__ P, const int64_t ldp
   }
 }
 
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// P += U_j V_j^T on the matrix cores for float storage and R >= 32
+// (v_mfma_f32_32x32x2f32: float products, float accumulation).  Tile
+// 128 x 128; wave (wm, wn) owns the 64 x 64 quarter as 2 x 2 blocks of
+// 32 x 32.  The tile's factor rows pass through LDS 32 columns at a time.
+// In the four steps of a column group, lanes 0-31 supply column c0 + e and
+// lanes 32-63 column c0 + 4 + e (e = 0..3) for both U and V, so every
+// column of the sum is taken once.  The delta is accumulated from zero and
+// added to the old values (requested before the products) once.
+// Accumulator element v of lane l is row 8 (v / 4) + 4 (l / 32) + v % 4,
+// column l % 32 of its block.
+template <int R, bool SH>
+__device__ __forceinline__ void update_mfma_body(float* __restrict__ P, const int64_t ldp,
+                                                 const float* __restrict__ Uj, const float* __restrict__ Vj,
+                                                 const int W, uint16_t* __restrict__ S, const int ct, const int rt) {
+  constexpr int TT = kMfmaUpdateTile, KC = 32, KP = KC + 4;
+  static_assert(R % KC == 0, "rank must be a multiple of 32");
+  __shared__ __align__(16) float sU[TT][KP];
+  __shared__ __align__(16) float sV[TT][KP];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = wave_id();
+  const int wm = wave >> 1, wn = wave & 1;
+  const int l32 = lane & 31, lh = lane >> 5;
+  const int row0 = rt * TT, col0 = ct * TT;
+
+  float p[2][2][16];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v)
+        p[a][b][v] = P[(int64_t)(row0 + wm * 64 + a * 32 + 8 * (v / 4) + 4 * lh + (v % 4)) * ldp + col0 + wn * 64 +
+                       b * 32 + l32];
+  v16f acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
+
+  for (int kc = 0; kc < R; kc += KC) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < TT * KC / 4 / 256; ++i) {
+      const int q = tid + 256 * i;
+      const int r = q >> 3, c4 = (q & 7) * 4;
+      *reinterpret_cast<float4*>(&sU[r][c4]) = *reinterpret_cast<const float4*>(Uj + (int64_t)(row0 + r) * W + kc + c4);
+      *reinterpret_cast<float4*>(&sV[r][c4]) = *reinterpret_cast<const float4*>(Vj + (int64_t)(col0 + r) * W + kc + c4);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c0 = 0; c0 < KC; c0 += 8) {
+      float4 ua[2], vb[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) ua[a] = *reinterpret_cast<const float4*>(&sU[wm * 64 + a * 32 + l32][c0 + 4 * lh]);
+#pragma unroll
+      for (int b = 0; b < 2; ++b) vb[b] = *reinterpret_cast<const float4*>(&sV[wn * 64 + b * 32 + l32][c0 + 4 * lh]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ua[a].x, vb[b].x, acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ua[a].y, vb[b].y, acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ua[a].z, vb[b].z, acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ua[a].w, vb[b].w, acc[a][b], 0, 0, 0);
+        }
+    }
+  }
+
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t o = (int64_t)(row0 + wm * 64 + a * 32 + 8 * (v / 4) + 4 * lh + (v % 4)) * ldp + col0 +
+                          wn * 64 + b * 32 + l32;
+        const float x = p[a][b][v] + acc[a][b][v];
+        P[o] = x;
+        if constexpr (SH) S[o] = bf16_rne(x);
+      }
+}
+
+template <typename T, int R, bool SH>
+__device__ __forceinline__ void update_any(const UpdateDesc<T>& d, const int ct, const int rt) {
+  if constexpr (sizeof(T) == 4 && R >= kMfmaUpdateRank)
+    update_mfma_body<R, SH>(d.P, d.ldp, d.Uj, d.Vj, d.W, d.S, ct, rt);
+  else
+    update_body<T, R, SH>(d.P, d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.S, ct, rt);
+}
+
 template <typename T, int R, bool SH>
 __global__ void __launch_bounds__(256) k_level_update(const UpdateDesc<T> d) {
-  update_body<T, R, SH>(d.P, d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.S, blockIdx.x, blockIdx.y);
+  update_any<T, R, SH>(d, blockIdx.x, blockIdx.y);
 }
 
 template <typename T, int R, bool SH>
@@ -466,7 +587,7 @@ __global__ void __launch_bounds__(256) k_level_update_multi(const UpdateDesc<T>*
   const int v = find_desc(ds, nd, (int)blockIdx.x);
   const UpdateDesc<T> d = ds[v];
   const int local = (int)blockIdx.x - d.block_begin;
-  update_body<T, R, SH>(d.P, d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.S, local % d.nct, local / d.nct);
+  update_any<T, R, SH>(d, local % d.nct, local / d.nct);
 }
 
 // ---------------------------------------------------------------- small kernels
@@ -522,8 +643,8 @@ hipError_t fused_launch(T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T
 template <typename T, int R>
 hipError_t update_r(T* P, int64_t ldp, int64_t n_pad, const T* Uj, const T* Vj, int W,
                     hipStream_t s, uint16_t* S = nullptr) {
-  const int tile_rows = kUpdateTileRows;
-  const int nct = (int)(n_pad / tile_cols<T>());
+  const int tile_rows = update_tile_rows(R, (int)sizeof(T));
+  const int nct = (int)(n_pad / update_tile_cols(R, (int)sizeof(T)));
   const UpdateDesc<T> d{P, ldp, (int)n_pad, tile_rows, Uj, Vj, W, nct, 0, S};
   const dim3 grid((unsigned)nct, (unsigned)((n_pad + tile_rows - 1) / tile_rows));
   if constexpr (sizeof(T) == 4) {
@@ -537,12 +658,17 @@ hipError_t update_r(T* P, int64_t ldp, int64_t n_pad, const T* Uj, const T* Vj, 
   return hipGetLastError();
 }
 
+// Stand-alone Gram: gram_tiles(n_pad) partials, then their sum into the first.
 template <typename T, int R>
-hipError_t gram_r(const T* Uj, const T* Vj, int W, int64_t n_pad, int tile_rows, double* partG, hipStream_t s) {
-  const int nrt = (int)((n_pad + tile_rows - 1) / tile_rows);
-  const GramDesc<T> g{Uj, Vj, W, (int)n_pad, tile_rows, partG, nrt, 0};
-  const dim3 ggrid((unsigned)nrt, (unsigned)((R * R + gram_pairs_per_block(R) - 1) / gram_pairs_per_block(R)));
+hipError_t gram_r(const T* Uj, const T* Vj, int W, int64_t n_pad, double* partG, hipStream_t s) {
+  const int ng = gram_tiles(n_pad);
+  const GramDesc<T> g{Uj, Vj, W, (int)n_pad, kGramRows, partG, ng, 0};
+  const dim3 ggrid((unsigned)ng, (unsigned)((R * R + gram_pairs_per_block(R) - 1) / gram_pairs_per_block(R)));
   hipLaunchKernelGGL((k_gram<T, R>), ggrid, dim3(256), 0, s, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const GramSumDesc gs{partG, ng, R * R, 0};
+  hipLaunchKernelGGL(k_gram_sum, dim3((unsigned)((R * R + 255) / 256)), dim3(256), 0, s, gs);
   return hipGetLastError();
 }
 
@@ -564,16 +690,16 @@ hipError_t fused_r(T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* Uj,
                                                    partX + c0, partY + c0, nullptr, R, s);
       if (e != hipSuccess) return e;
     }
-    hipError_t e = gram_r<T, R>(Uj, Vj, W, n_pad, tile_rows, partG, s);
+    hipError_t e = gram_r<T, R>(Uj, Vj, W, n_pad, partG, s);
     if (e != hipSuccess) return e;
     return update_r<T, R>(P, ldp, n_pad, Uj, Vj, W, s);
   }
 }
 
 template <typename T, int R>
-hipError_t tail_r(const T* partX, const T* partY, const double* partG, int nct, int nrt,
+hipError_t tail_r(const T* partX, const T* partY, const double* partG, int nct, int nrt, int ng,
                   int64_t n_pad, T* slabU, T* slabV, int W, hipStream_t s) {
-  const TailDesc<T> d{partX, partY, partG, nct, nrt, (int)n_pad, slabU, slabV, W, 0};
+  const TailDesc<T> d{partX, partY, partG, nct, nrt, (int)n_pad, slabU, slabV, W, 0, ng};
   hipLaunchKernelGGL((k_level_tail<T, R>), dim3((unsigned)tail_blocks(n_pad, R)), dim3(256), 0, s, d);
   return hipGetLastError();
 }
@@ -620,8 +746,8 @@ hipError_t launch_level_fused(int R, T* P, int64_t ldp, int64_t n_pad, int tile_
 
 template <typename T>
 hipError_t launch_level_tail(int R, const T* partX, const T* partY, const double* partG, int nct,
-                             int nrt, int64_t n_pad, T* slabU, T* slabV, int W, hipStream_t s) {
-  LV_RANK_SWITCH(R, return (tail_r<T, RR>(partX, partY, partG, nct, nrt, n_pad, slabU, slabV, W, s)))
+                             int nrt, int ng, int64_t n_pad, T* slabU, T* slabV, int W, hipStream_t s) {
+  LV_RANK_SWITCH(R, return (tail_r<T, RR>(partX, partY, partG, nct, nrt, ng, n_pad, slabU, slabV, W, s)))
 }
 
 template <typename T>
@@ -634,11 +760,11 @@ hipError_t launch_level_update(int R, T* P, int64_t ldp, int64_t n_pad, const T*
 }
 
 template <typename T>
-hipError_t launch_level_gram(int R, const T* slabU, const T* slabV, int W, int64_t n_pad, int tile_rows,
-                             double* partG, hipStream_t s) {
+hipError_t launch_level_gram(int R, const T* slabU, const T* slabV, int W, int64_t n_pad, double* partG,
+                             hipStream_t s) {
   const T* Uj = slabU;
   const T* Vj = slabV + (W - R);
-  LV_RANK_SWITCH(R, return (gram_r<T, RR>(Uj, Vj, W, n_pad, tile_rows, partG, s)))
+  LV_RANK_SWITCH(R, return (gram_r<T, RR>(Uj, Vj, W, n_pad, partG, s)))
 }
 
 // ---- multi-view launchers
@@ -667,6 +793,12 @@ hipError_t launch_gram_multi(int R, const GramDesc<T>* ds, int nd, int blocks, h
   if (blocks <= 0) return hipSuccess;
   LV_RANK_SWITCH(R, hipLaunchKernelGGL((k_gram_multi<T, RR>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd);
                  return hipGetLastError())
+}
+
+hipError_t launch_gram_sum_multi(const GramSumDesc* ds, int nd, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gram_sum_multi, dim3((unsigned)blocks), dim3(256), 0, s, ds, nd);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -709,11 +841,11 @@ hipError_t launch_prep_multi(const PrepDesc<T>* ds, int nd, int blocks, hipStrea
                                      T*, T*, int, int64_t, hipStream_t);                          \
   template hipError_t launch_level_fused<T>(int, T*, int64_t, int64_t, int, const T*, const T*,   \
                                             int, T*, T*, double*, hipStream_t);                   \
-  template hipError_t launch_level_tail<T>(int, const T*, const T*, const double*, int, int,      \
+  template hipError_t launch_level_tail<T>(int, const T*, const T*, const double*, int, int, int, \
                                            int64_t, T*, T*, int, hipStream_t);                    \
   template hipError_t launch_level_update<T>(int, T*, int64_t, int64_t, const T*, const T*, int,  \
                                              hipStream_t, uint16_t*);                             \
-  template hipError_t launch_level_gram<T>(int, const T*, const T*, int, int64_t, int, double*,   \
+  template hipError_t launch_level_gram<T>(int, const T*, const T*, int, int64_t, double*,        \
                                            hipStream_t);                                          \
   template hipError_t launch_fused_multi<T>(int, bool, const FusedDesc<T>*, int, int, hipStream_t); \
   template hipError_t launch_gram_multi<T>(int, const GramDesc<T>*, int, int, hipStream_t);        \

@@ -9,7 +9,8 @@
 //     tails (reductions + next factors), one launch per R
 // Views with bfloat16 shadows run, below their top level, the shadow skinny
 // pass (one launch per factor-block count), the Gram and the update that
-// rewrites the shadow (one launch per R) in place of the fused pass.
+// rewrites the shadow (one launch per R) in place of the fused pass; float
+// views at level ranks from 16 up run the float skinny pass the same way.
 // Every view runs exactly the kernels of lv_view_update, so its result is
 // identical bit for bit to an update applied alone with the same factors.
 #pragma once
@@ -22,7 +23,7 @@
 
 namespace lv {
 
-enum Kind { kPrep, kFused, kChunk, kSkinny, kGram, kUpdate, kUpdateShadow, kTail };
+enum Kind { kPrep, kFused, kChunk, kSkinny, kSkinnyF32, kGram, kGramSum, kUpdate, kUpdateShadow, kTail };
 
 struct LaunchRec {
   Kind kind;
@@ -86,8 +87,9 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
   for (int j = 0; j <= max_m; ++j) {
     std::map<int, std::vector<FusedDesc<T>>> fused;
     std::vector<FusedDesc<T>> chunks;
-    std::map<int, std::vector<SkinnyDesc>> skinny;
+    std::map<int, std::vector<SkinnyDesc>> skinny, skinny32;
     std::map<int, std::vector<GramDesc<T>>> gram;
+    std::vector<GramSumDesc> gsum;
     std::map<int, std::vector<UpdateDesc<T>>> upd, updsh;
     std::map<int, std::vector<TailDesc<T>>> tail;
     for (lv_view* v : views) {
@@ -97,21 +99,30 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
       T* sU = v->slabU<T>(0);
       T* sV = v->slabV<T>(0);
       const T* Vj = sV + (L.W - R);
+      const int upd_rows = update_tile_rows(R, L.elem);
+      const int upd_nct = (int)(L.n_pad / update_tile_cols(R, L.elem));
       if (j == L.m) {
-        upd[R].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, kUpdateTileRows, sU, Vj, L.W,
-                          (int)(L.n_pad / tile_cols_bytes(L.elem)), 0});
+        upd[R].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, upd_rows, sU, Vj, L.W, upd_nct, 0});
         continue;
       }
-      const int upd_nct = (int)(L.n_pad / tile_cols_bytes(L.elem));
       if constexpr (sizeof(T) == 4) {
-        if (v->shadowed()) {
-          skinny[skinny_blocks_for(R)].push_back({v->shadow(j), L.ldp, (int)L.n_pad, L.tile_rows, sU, Vj, L.W, R,
-                                                  v->partX<T>(j), v->partY<T>(j), R, L.nct, 0});
-          gram[R].push_back({sU, Vj, L.W, (int)L.n_pad, L.tile_rows, v->partG(j), L.nrt, 0});
-          updsh[R].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, kUpdateTileRows, sU, Vj, L.W, upd_nct, 0,
-                              v->shadow(j)});
+        if (v->shadowed() || skinny_on_mfma(R, 4)) {
+          if (v->shadowed()) {
+            skinny[skinny_blocks_for(R)].push_back({v->shadow(j), L.ldp, (int)L.n_pad, L.tile_rows, sU, Vj, L.W, R,
+                                                    v->partX<T>(j), v->partY<T>(j), R, L.nct, 0});
+          } else {
+            const int per = R <= 64 ? R : 64;
+            for (int c0 = 0; c0 < R; c0 += per)
+              skinny32[skinny_f32_blocks(per)].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, L.tile_rows, sU + c0,
+                                                          Vj + c0, L.W, per, v->partX<T>(j) + c0,
+                                                          v->partY<T>(j) + c0, R, L.nct, 0});
+          }
+          gram[R].push_back({sU, Vj, L.W, (int)L.n_pad, kGramRows, v->partG(j), gram_tiles(L.n_pad), 0});
+          gsum.push_back({v->partG(j), gram_tiles(L.n_pad), R * R, 0});
+          (v->shadowed() ? updsh : upd)[R].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, upd_rows, sU, Vj, L.W,
+                                                      upd_nct, 0, v->shadowed() ? v->shadow(j) : nullptr});
           tail[R].push_back({v->partX<T>(j), v->partY<T>(j), v->partG(j), L.nct, L.nrt, (int)L.n_pad, sU, sV, L.W,
-                             0});
+                             0, 1});
           continue;
         }
       }
@@ -122,20 +133,23 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
         for (int c0 = 0; c0 < R; c0 += kMaxFusedRank)
           chunks.push_back({v->P<T>(j), L.ldp, (int)L.n_pad, L.tile_rows, sU + c0, Vj + c0, L.W,
                             v->partX<T>(j) + c0, v->partY<T>(j) + c0, nullptr, R, L.nct, 0});
-        gram[R].push_back({sU, Vj, L.W, (int)L.n_pad, L.tile_rows, v->partG(j), L.nrt, 0});
-        upd[R].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, kUpdateTileRows, sU, Vj, L.W,
-                          (int)(L.n_pad / tile_cols_bytes(L.elem)), 0});
+        gram[R].push_back({sU, Vj, L.W, (int)L.n_pad, kGramRows, v->partG(j), gram_tiles(L.n_pad), 0});
+        gsum.push_back({v->partG(j), gram_tiles(L.n_pad), R * R, 0});
+        upd[R].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, upd_rows, sU, Vj, L.W, upd_nct, 0});
       }
-      tail[R].push_back({v->partX<T>(j), v->partY<T>(j), v->partG(j), L.nct, L.nrt, (int)L.n_pad, sU, sV, L.W, 0});
+      tail[R].push_back({v->partX<T>(j), v->partY<T>(j), v->partG(j), L.nct, L.nrt, (int)L.n_pad, sU, sV, L.W, 0,
+                         gram_in_pass(R, L.elem) ? L.nrt : 1});
     }
     for (auto& kv : fused) pl.add(kFused, kv.first, kv.second, &fused_blocks<T>);
     pl.add(kChunk, kMaxFusedRank, chunks, &fused_blocks<T>);
     for (auto& kv : skinny) pl.add(kSkinny, kv.first, kv.second, &skinny_blocks);
+    for (auto& kv : skinny32) pl.add(kSkinnyF32, kv.first, kv.second, &skinny_blocks);
     for (auto& kv : gram) {
       const int R = kv.first;
       const int chunks_per_tile = (R * R + gram_pairs_per_block(R) - 1) / gram_pairs_per_block(R);
       pl.add(kGram, R, kv.second, [chunks_per_tile](const GramDesc<T>& d) { return d.nrt * chunks_per_tile; });
     }
+    pl.add(kGramSum, 0, gsum, [](const GramSumDesc& d) { return (d.count + 255) / 256; });
     for (auto& kv : upd) pl.add(kUpdate, kv.first, kv.second, &update_blocks<T>);
     for (auto& kv : updsh) pl.add(kUpdateShadow, kv.first, kv.second, &update_blocks<T>);
     for (auto& kv : tail) {
@@ -157,6 +171,8 @@ lv_status enqueue_round(const Plan& pl, const char* dbase, hipStream_t s) {
       case kFused: e = launch_fused_multi<T>(l.R, false, static_cast<const FusedDesc<T>*>(d), l.nd, l.blocks, s); break;
       case kChunk: e = launch_fused_multi<T>(l.R, true, static_cast<const FusedDesc<T>*>(d), l.nd, l.blocks, s); break;
       case kGram: e = launch_gram_multi<T>(l.R, static_cast<const GramDesc<T>*>(d), l.nd, l.blocks, s); break;
+      case kGramSum: e = launch_gram_sum_multi(static_cast<const GramSumDesc*>(d), l.nd, l.blocks, s); break;
+      case kSkinnyF32: e = launch_skinny_f32_multi(l.R, static_cast<const SkinnyDesc*>(d), l.nd, l.blocks, s); break;
       case kSkinny: e = launch_skinny_bf16_multi(l.R, static_cast<const SkinnyDesc*>(d), l.nd, l.blocks, s); break;
       case kUpdate: e = launch_update_multi<T>(l.R, false, static_cast<const UpdateDesc<T>*>(d), l.nd, l.blocks, s); break;
       case kUpdateShadow:

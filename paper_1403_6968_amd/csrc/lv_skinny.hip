@@ -1,0 +1,435 @@
+// Read-only skinny-product passes of a level on the matrix cores (App. A,
+// with the OLD power P_j):  X = P_j U_j,  Y^T = V_j^T P_j.
+//
+// BF16-shadow form (storage FP32): every stored power below the top keeps a
+// bfloat16 copy S_j, rewritten by the update pass that adds U_j V_j^T to
+// P_j.  k_skinny_bf16 reads the shadow (2 bytes per element) and multiplies
+// bfloat16 x bfloat16 with float accumulation (v_mfma_f32_32x32x16_bf16).
+// k_skinny_f32 reads the float power itself and multiplies in float
+// (v_mfma_f32_32x32x2f32): the FP32 method's products at level ranks where
+// the vector units, not HBM, would bound a fused pass.
+// Both write the partial X / Y layouts of the fused pass, so the common tail
+// assembles the next factors; the Gram V_j^T U_j is formed in FP64 apart.
+//
+// Lane layouts (64 lanes, l = lane, h = l / 32):
+//   bf16 32x32x16  A: lane l holds A[l % 32][8 h + e], e = 0..7
+//                  B: lane l holds B[8 h + e][l % 32]
+//   f32 32x32x2    A: lane l holds A[l % 32][h];  B: B[h][l % 32]
+//   both           C: element v of lane l is C[8 (v / 4) + 4 h + v % 4][l % 32]
+#include "lv_internal.h"
+
+#include <type_traits>
+
+namespace lv {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int TCB = 256;   // tile columns
+constexpr int CRB = 64;    // rows per LDS chunk
+constexpr int SPAD = 8;    // LDS row padding (bf16 elements, keeps 16-byte alignment)
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I = 0 .. N-1, so
+// that arrays indexed by I stay in registers.
+template <int I, int N, typename F> __device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+__device__ __forceinline__ bf16x8 lds8(const uint16_t* p) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(p));
+}
+
+// Tile: tile_rows x 256 columns of S, walked in chunks of 64 rows through
+// LDS; the next chunk of S and of V_j is held in registers while the
+// current one is used.
+// Factor columns are padded with zeros to 32 NB.
+//   X: per chunk, the 2 NB (row half, factor block) 32 x 32 outputs are
+//      shared round-robin by the 4 waves, K = the tile's 256 columns; one
+//      partial per (row, column tile).
+//   Y: wave w keeps the accumulators of tile columns [64 w, 64 w + 64) for
+//      every factor block over all chunks of the tile (K = rows); one
+//      partial per (column, row tile).
+// The B operand of Y needs 8 consecutive rows of one column: 8 LDS reads.
+template <int NB>
+__device__ __forceinline__ void skinny_body(const uint16_t* __restrict__ S, const int64_t ldp, const int n_pad,
+                                            const int tile_rows, const float* __restrict__ Uj,
+                                            const float* __restrict__ Vj, const int W, const int R,
+                                            float* __restrict__ partX, float* __restrict__ partY, const int pR,
+                                            const int ct, const int rt) {
+  constexpr int RP = 32 * NB;
+  __shared__ __align__(16) uint16_t sS[CRB][TCB + SPAD];
+  __shared__ __align__(16) uint16_t sUt[RP][TCB + SPAD];
+  __shared__ __align__(16) uint16_t sVt[RP][CRB + SPAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int col0 = ct * TCB;
+  const int row0 = rt * tile_rows;
+  const int rend = min(row0 + tile_rows, n_pad);
+  const int l32 = lane % 32, lh = lane / 32;
+  // chunk staging: thread -> rows tid / 32 + 8 i, 16-byte column group tid % 32
+  const int srow = tid / 32, sgrp = tid % 32;
+
+  constexpr int VPT = RP * CRB / 256;   // V_j values staged per thread and chunk
+  u16x8 pre[CRB / 8];
+  float pv[VPT];
+  auto fetch = [&](const int r0) {
+#pragma unroll
+    for (int i = 0; i < CRB / 8; ++i)
+      pre[i] = *reinterpret_cast<const u16x8*>(S + (int64_t)(r0 + srow + 8 * i) * ldp + col0 + sgrp * 8);
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int idx = tid + 256 * i;
+      const int rr = idx / RP, c = idx % RP;
+      pv[i] = c < R ? Vj[(int64_t)(r0 + rr) * W + c] : 0.f;
+    }
+  };
+  fetch(row0);
+
+  // U_j rows of the tile's columns, transposed: sUt[c][k] = U_j[col0 + k][c]
+  for (int idx = tid; idx < RP * TCB; idx += 256) {
+    const int k = idx / RP, c = idx % RP;
+    sUt[c][k] = c < R ? bf16_rne(Uj[(int64_t)(col0 + k) * W + c]) : (uint16_t)0;
+  }
+
+  v16f yacc[NB][2];
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) yacc[a][b][v] = 0.f;
+
+  for (int cr0 = row0; cr0 < rend; cr0 += CRB) {
+    __syncthreads();   // the previous chunk is no longer read
+#pragma unroll
+    for (int i = 0; i < CRB / 8; ++i) *reinterpret_cast<u16x8*>(&sS[srow + 8 * i][sgrp * 8]) = pre[i];
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int idx = tid + 256 * i;
+      sVt[idx % RP][idx / RP] = bf16_rne(pv[i]);
+    }
+    __syncthreads();
+    if (cr0 + CRB < rend) fetch(cr0 + CRB);
+
+    // X rows of the chunk
+    for (int t = wave; t < 2 * NB; t += 4) {
+      const int mb = t % 2, nb = t / 2;
+      v16f acc;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+#pragma unroll 4
+      for (int ks = 0; ks < TCB / 16; ++ks)
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lds8(&sS[mb * 32 + l32][ks * 16 + 8 * lh]),
+                                                       lds8(&sUt[nb * 32 + l32][ks * 16 + 8 * lh]), acc, 0, 0, 0);
+      const int c = nb * 32 + l32;
+      if (c < R) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int rr = mb * 32 + 8 * (v / 4) + 4 * lh + (v % 4);
+          partX[((int64_t)ct * n_pad + cr0 + rr) * pR + c] = acc[v];
+        }
+      }
+    }
+
+    // Y^T += V_chunk^T S_chunk
+#pragma unroll
+    for (int ks = 0; ks < CRB / 16; ++ks) {
+#pragma unroll
+      for (int cbi = 0; cbi < 2; ++cbi) {
+        const int colc = (2 * wave + cbi) * 32 + l32;
+        u16x8 bv;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bv[e] = sS[ks * 16 + 8 * lh + e][colc];
+        const bf16x8 b = __builtin_bit_cast(bf16x8, bv);
+#pragma unroll
+        for (int nbr = 0; nbr < NB; ++nbr)
+          yacc[nbr][cbi] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lds8(&sVt[nbr * 32 + l32][ks * 16 + 8 * lh]), b,
+                                                                   yacc[nbr][cbi], 0, 0, 0);
+      }
+    }
+  }
+
+#pragma unroll
+  for (int nbr = 0; nbr < NB; ++nbr)
+#pragma unroll
+    for (int cbi = 0; cbi < 2; ++cbi) {
+      const int col = col0 + (2 * wave + cbi) * 32 + l32;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int c = nbr * 32 + 8 * (v / 4) + 4 * lh + (v % 4);
+        if (c < R) partY[((int64_t)rt * n_pad + col) * pR + c] = yacc[nbr][cbi][v];
+      }
+    }
+}
+
+template <int NB>
+__global__ void __launch_bounds__(256) k_skinny_bf16(const SkinnyDesc d) {
+  skinny_body<NB>(static_cast<const uint16_t*>(d.src), d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.R, d.partX, d.partY, d.pR, blockIdx.x,
+                  blockIdx.y);
+}
+
+// Index of the descriptor whose block range holds block b (sorted by
+// block_begin, the first at 0).
+__device__ __forceinline__ int find_skinny(const SkinnyDesc* __restrict__ ds, int nd, int b) {
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ds[mid].block_begin <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int NB>
+__global__ void __launch_bounds__(256) k_skinny_bf16_multi(const SkinnyDesc* __restrict__ ds, int nd) {
+  const SkinnyDesc d = ds[find_skinny(ds, nd, (int)blockIdx.x)];
+  const int local = (int)blockIdx.x - d.block_begin;
+  skinny_body<NB>(static_cast<const uint16_t*>(d.src), d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.R, d.partX, d.partY, d.pR,
+                  local % d.nct, local / d.nct);
+}
+
+// Float skinny pass.  Tile: tile_rows x 256 columns of P, chunks of 32 rows
+// through LDS (the next chunk of P and V_j held in registers meanwhile);
+// factor columns padded with zeros to 32 NB (NB <= 2).
+//   X: the chunk's 32 x 32 NB outputs with K = 256 split over the waves
+//      (wave w: columns [64 w, 64 w + 64)); the four partial sums meet in
+//      LDS (over the chunk buffer, no longer read) and are added in wave
+//      order; one partial per (row, column tile).
+//   Y: as the bfloat16 kernel, wave w owns tile columns [64 w, 64 w + 64).
+// A group of four f32 steps covers 8 summation indices: lanes 0-31 supply
+// index g + e and lanes 32-63 index g + 4 + e in step e, for both operands.
+template <int NB>
+__device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, const int64_t ldp, const int n_pad,
+                                                const int tile_rows, const float* __restrict__ Uj,
+                                                const float* __restrict__ Vj, const int W, const int R,
+                                                float* __restrict__ partX, float* __restrict__ partY,
+                                                const int pR, const int ct, const int rt) {
+  constexpr int RP = 32 * NB;
+  constexpr int CR = 32;           // rows per chunk
+  constexpr int FP = 4;            // LDS row padding (floats)
+  static_assert(NB <= 2, "the X exchange buffer must fit in the chunk buffer");
+  __shared__ __align__(16) float sP[CR][TCB + FP];
+  __shared__ __align__(16) float sUt[RP][TCB + FP];
+  __shared__ __align__(16) float sVt[RP][CR + FP];
+  float* xbuf = &sP[0][0];         // [4 waves][NB][16 values][64 lanes]
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int col0 = ct * TCB;
+  const int row0 = rt * tile_rows;
+  const int rend = min(row0 + tile_rows, n_pad);
+  const int l32 = lane % 32, lh = lane / 32;
+  // chunk staging: thread -> rows tid / 64 + 4 i, f32x4 column group tid % 64
+  const int srow = tid / 64, sgrp = tid % 64;
+
+  constexpr int VPT = RP * CR / 256;
+  f32x4 pre[CR / 4];
+  float pv[VPT];
+  auto fetch = [&](const int r0) {
+    static_for<0, CR / 4>([&](auto i) {
+      pre[i] = *reinterpret_cast<const f32x4*>(P + (int64_t)(r0 + srow + 4 * i) * ldp + col0 + sgrp * 4);
+    });
+    static_for<0, VPT>([&](auto i) {
+      const int idx = tid + 256 * i;
+      const int rr = idx / RP, c = idx % RP;
+      pv[i] = c < R ? Vj[(int64_t)(r0 + rr) * W + c] : 0.f;
+    });
+  };
+  fetch(row0);
+
+  for (int idx = tid; idx < RP * TCB; idx += 256) {
+    const int k = idx / RP, c = idx % RP;
+    sUt[c][k] = c < R ? Uj[(int64_t)(col0 + k) * W + c] : 0.f;
+  }
+
+  v16f yacc[NB][2];
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) yacc[a][b][v] = 0.f;
+
+  for (int cr0 = row0; cr0 < rend; cr0 += CR) {
+    __syncthreads();   // the previous chunk's exchange buffer has been read
+    static_for<0, CR / 4>([&](auto i) { *reinterpret_cast<f32x4*>(&sP[srow + 4 * i][sgrp * 4]) = pre[i]; });
+    static_for<0, VPT>([&](auto i) {
+      const int idx = tid + 256 * i;
+      sVt[idx % RP][idx / RP] = pv[i];
+    });
+    __syncthreads();
+    if (cr0 + CR < rend) fetch(cr0 + CR);
+
+    // X partial over this wave's 64 columns
+    v16f xacc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) xacc[nb][v] = 0.f;
+#pragma unroll
+    for (int g = 0; g < 64; g += 8) {
+      const int k0 = wave * 64 + g + 4 * lh;
+      const f32x4 a = *reinterpret_cast<const f32x4*>(&sP[l32][k0]);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const f32x4 b = *reinterpret_cast<const f32x4*>(&sUt[nb * 32 + l32][k0]);
+        xacc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, xacc[nb], 0, 0, 0);
+        xacc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, xacc[nb], 0, 0, 0);
+        xacc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, xacc[nb], 0, 0, 0);
+        xacc[nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.w, xacc[nb], 0, 0, 0);
+      }
+    }
+
+    // Y^T += V_chunk^T P_chunk
+#pragma unroll
+    for (int g = 0; g < CR; g += 8) {
+      const int r0 = g + 4 * lh;
+#pragma unroll
+      for (int cbi = 0; cbi < 2; ++cbi) {
+        const int colc = (2 * wave + cbi) * 32 + l32;
+        const float b0 = sP[r0][colc], b1 = sP[r0 + 1][colc], b2 = sP[r0 + 2][colc], b3 = sP[r0 + 3][colc];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const f32x4 a = *reinterpret_cast<const f32x4*>(&sVt[nb * 32 + l32][r0]);
+          yacc[nb][cbi] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b0, yacc[nb][cbi], 0, 0, 0);
+          yacc[nb][cbi] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b1, yacc[nb][cbi], 0, 0, 0);
+          yacc[nb][cbi] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b2, yacc[nb][cbi], 0, 0, 0);
+          yacc[nb][cbi] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b3, yacc[nb][cbi], 0, 0, 0);
+        }
+      }
+    }
+
+    // exchange the X partials (sP is no longer read in this chunk)
+    __syncthreads();
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) xbuf[((wave * NB + nb) * 16 + v) * 64 + lane] = xacc[nb][v];
+    __syncthreads();
+    // thread -> (v, lane) slots of the 32 x 32 NB outputs
+#pragma unroll
+    for (int i = 0; i < NB * 4; ++i) {
+      const int slot = tid + 256 * i;          // [nb][v][lane]
+      const int ln = slot % 64, v = (slot / 64) % 16, nb = slot / 1024;
+      float x = 0.f;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) x += xbuf[((w * NB + nb) * 16 + v) * 64 + ln];
+      const int c = nb * 32 + ln % 32;
+      const int rr = 8 * (v / 4) + 4 * (ln / 32) + (v % 4);
+      if (c < R) partX[((int64_t)ct * n_pad + cr0 + rr) * pR + c] = x;
+    }
+  }
+
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int cbi = 0; cbi < 2; ++cbi) {
+      const int col = col0 + (2 * wave + cbi) * 32 + l32;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int c = nb * 32 + 8 * (v / 4) + 4 * lh + (v % 4);
+        if (c < R) partY[((int64_t)rt * n_pad + col) * pR + c] = yacc[nb][cbi][v];
+      }
+    }
+}
+
+template <int NB>
+__global__ void __launch_bounds__(256) k_skinny_f32(const SkinnyDesc d) {
+  skinny_f32_body<NB>(static_cast<const float*>(d.src), d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.R,
+                      d.partX, d.partY, d.pR, blockIdx.x, blockIdx.y);
+}
+
+template <int NB>
+__global__ void __launch_bounds__(256) k_skinny_f32_multi(const SkinnyDesc* __restrict__ ds, int nd) {
+  const SkinnyDesc d = ds[find_skinny(ds, nd, (int)blockIdx.x)];
+  const int local = (int)blockIdx.x - d.block_begin;
+  skinny_f32_body<NB>(static_cast<const float*>(d.src), d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.R,
+                      d.partX, d.partY, d.pR, local % d.nct, local / d.nct);
+}
+
+__global__ void __launch_bounds__(256)
+k_to_bf16(const float* __restrict__ P, uint16_t* __restrict__ S, int64_t count, const int* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
+  const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (i >= count) return;
+  const float4 p = *reinterpret_cast<const float4*>(P + i);
+  ushort4 sh;
+  sh.x = bf16_rne(p.x); sh.y = bf16_rne(p.y); sh.z = bf16_rne(p.z); sh.w = bf16_rne(p.w);
+  *reinterpret_cast<ushort4*>(S + i) = sh;
+}
+
+}  // namespace
+
+hipError_t launch_skinny_bf16(int R, const uint16_t* S, int64_t ldp, int64_t n_pad, int tile_rows,
+                              const float* slabU, const float* slabV, int W, float* partX, float* partY,
+                              hipStream_t s) {
+  if (R < 1 || R > 128 || n_pad % TCB != 0 || tile_rows % CRB != 0) return hipErrorInvalidValue;
+  const int nct = (int)(n_pad / TCB);
+  const SkinnyDesc d{S, ldp, (int)n_pad, tile_rows, slabU, slabV + (W - R), W, R, partX, partY, R, nct, 0};
+  const dim3 grid((unsigned)nct, (unsigned)((n_pad + tile_rows - 1) / tile_rows));
+  switch (skinny_blocks_for(R)) {
+    case 1: hipLaunchKernelGGL((k_skinny_bf16<1>), grid, dim3(256), 0, s, d); break;
+    case 2: hipLaunchKernelGGL((k_skinny_bf16<2>), grid, dim3(256), 0, s, d); break;
+    default: hipLaunchKernelGGL((k_skinny_bf16<4>), grid, dim3(256), 0, s, d); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_skinny_bf16_multi(int nb, const SkinnyDesc* ds, int nd, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  switch (nb) {
+    case 1: hipLaunchKernelGGL((k_skinny_bf16_multi<1>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
+    case 2: hipLaunchKernelGGL((k_skinny_bf16_multi<2>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
+    case 4: hipLaunchKernelGGL((k_skinny_bf16_multi<4>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_skinny_f32(int R, const float* P, int64_t ldp, int64_t n_pad, int tile_rows,
+                             const float* slabU, const float* slabV, int W, float* partX, float* partY,
+                             hipStream_t s) {
+  if (R < 1 || R > 128 || (R > 64 && R % 64 != 0) || n_pad % TCB != 0 || tile_rows % 32 != 0)
+    return hipErrorInvalidValue;
+  const int nct = (int)(n_pad / TCB);
+  const dim3 grid((unsigned)nct, (unsigned)((n_pad + tile_rows - 1) / tile_rows));
+  const float* Vj = slabV + (W - R);
+  const int per = R <= 64 ? R : 64;
+  for (int c0 = 0; c0 < R; c0 += per) {
+    const SkinnyDesc d{P, ldp, (int)n_pad, tile_rows, slabU + c0, Vj + c0, W, per, partX + c0, partY + c0, R, nct, 0};
+    if (skinny_f32_blocks(per) == 1)
+      hipLaunchKernelGGL((k_skinny_f32<1>), grid, dim3(256), 0, s, d);
+    else
+      hipLaunchKernelGGL((k_skinny_f32<2>), grid, dim3(256), 0, s, d);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_skinny_f32_multi(int nb, const SkinnyDesc* ds, int nd, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  switch (nb) {
+    case 1: hipLaunchKernelGGL((k_skinny_f32_multi<1>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
+    case 2: hipLaunchKernelGGL((k_skinny_f32_multi<2>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float* P, uint16_t* S, int64_t count, hipStream_t s, const int* gate) {
+  if (count % 4 != 0) return hipErrorInvalidValue;
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((count / 4 + 255) / 256)), dim3(256), 0, s, P, S, count, gate);
+  return hipGetLastError();
+}
+
+}  // namespace lv

@@ -77,7 +77,8 @@ inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode) {
     const size_t R = (size_t)L.r_pad << j;
     L.partX[j] = off; off = align_up(off + (size_t)L.nct * L.n_pad * R * L.elem);
     L.partY[j] = off; off = align_up(off + (size_t)L.nrt * L.n_pad * R * L.elem);
-    L.partG[j] = off; off = align_up(off + (size_t)L.nrt * R * R * sizeof(double));
+    const size_t ng = (size_t)(gram_tiles(L.n_pad) > L.nrt ? gram_tiles(L.n_pad) : L.nrt);
+    L.partG[j] = off; off = align_up(off + ng * R * R * sizeof(double));
   }
   if (mode == LV_FP32_BF16SHADOW)
     for (int j = 0; j < L.m; ++j) { L.shadow[j] = off; off = align_up(off + (size_t)L.n_pad * L.ldp * 2); }
