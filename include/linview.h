@@ -185,6 +185,15 @@ typedef struct {
 lv_status lv_view_set_timing(lv_view* v, int enable);
 lv_status lv_view_timing(lv_view* v, lv_timing* out);
 
+/* Rows per tile of the level pass of `level` (0 <= level < log2 k): the
+ * height of the P_j tiles whose partial sums of P_j^T V_j are reduced by the
+ * tail, so it fixes the summation order of the update.  Default 512;
+ * lv_batch_create sets it by autotuning.  Allowed values: multiples of 64
+ * in [256, 1024].  Two views with equal tiles, inputs and updates hold equal
+ * values bit for bit whichever entry point applies the updates. */
+lv_status lv_view_tile_rows(const lv_view* v, int level, int* rows);
+lv_status lv_view_set_tile_rows(lv_view* v, int level, int rows);
+
 /* Counters and shape of a view.  Reads the drift counters from the device
  * (a synchronous copy). */
 lv_status lv_view_stats(const lv_view* v, lv_stats* out);
@@ -206,7 +215,15 @@ void lv_view_destroy(lv_view* v);
  * runs as one multi-view launch per level rank (work-groups map to
  * (view, tile) through descriptor tables in the workspace), so small views
  * share the GPU instead of launching separately.  The per-view results equal
- * lv_view_update bit for bit.
+ * lv_view_update bit for bit (with the tile rows the batch chose, see
+ * lv_view_tile_rows).
+ *
+ * Tiles are autotuned at lv_batch_create: one round with zero inputs runs
+ * first (it leaves every stored power unchanged), then for each level and
+ * level rank the tile heights 256, 512 and 1024 rows are timed over that
+ * level's launches, and the fastest is kept in the views.  Choices are
+ * cached per process by device architecture, mode, rank and the orders of
+ * the views concerned, so an identical batch is not timed again.
  * --------------------------------------------------------------------- */
 typedef struct lv_batch lv_batch;
 
@@ -231,6 +248,10 @@ lv_status lv_batch_stage(lv_batch* b, int i, const void* U, const void* V, int64
 
 /* One round: every view applies its staged update (stream-ordered). */
 lv_status lv_batch_update(lv_batch* b, void* stream);
+
+/* Autotuning record of the batch: (level, rank) groups timed at creation,
+ * and groups whose choice came from the process cache. */
+lv_status lv_batch_tuning(const lv_batch* b, int* tuned_groups, int* cache_hits);
 
 /* Release the batch (after the stream has drained).  NULL is ignored. */
 void lv_batch_destroy(lv_batch* b);

@@ -132,9 +132,9 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
         // the float power), FP64 Gram, then the rank update (which rewrites
         // the shadow after the skinny pass has read it)
         st = timed(v, 0, s, "skinny", [&] {
-          return v->shadowed() ? launch_skinny_bf16(R, v->shadow(j), L.ldp, L.n_pad, L.tile_rows, sU, sV, L.W,
+          return v->shadowed() ? launch_skinny_bf16(R, v->shadow(j), L.ldp, L.n_pad, v->tile_rows[j], sU, sV, L.W,
                                                     v->partX<float>(j), v->partY<float>(j), s)
-                               : launch_skinny_f32(R, v->P<float>(j), L.ldp, L.n_pad, L.tile_rows, sU, sV, L.W,
+                               : launch_skinny_f32(R, v->P<float>(j), L.ldp, L.n_pad, v->tile_rows[j], sU, sV, L.W,
                                                    v->partX<float>(j), v->partY<float>(j), s);
         });
         if (st == LV_OK)
@@ -148,7 +148,7 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
           });
         if (st == LV_OK)
           st = timed(v, 1, s, "level tail", [&] {
-            return launch_level_tail<float>(R, v->partX<float>(j), v->partY<float>(j), v->partG(j), L.nct, L.nrt,
+            return launch_level_tail<float>(R, v->partX<float>(j), v->partY<float>(j), v->partG(j), L.nct, v->nrt(j),
                                             1, L.n_pad, sU, sV, L.W, s);
           });
         if (st != LV_OK) return st;
@@ -156,13 +156,13 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
       }
     }
     st = timed(v, 0, s, "level pass", [&] {
-      return launch_level_fused<T>(R, v->P<T>(j), L.ldp, L.n_pad, L.tile_rows, sU, sV, L.W, v->partX<T>(j),
+      return launch_level_fused<T>(R, v->P<T>(j), L.ldp, L.n_pad, v->tile_rows[j], sU, sV, L.W, v->partX<T>(j),
                                    v->partY<T>(j), v->partG(j), s);
     });
     if (st != LV_OK) return st;
     st = timed(v, 1, s, "level tail", [&] {
-      return launch_level_tail<T>(R, v->partX<T>(j), v->partY<T>(j), v->partG(j), L.nct, L.nrt,
-                                  gram_in_pass(R, (int)sizeof(T)) ? L.nrt : 1, L.n_pad, sU, sV, L.W, s);
+      return launch_level_tail<T>(R, v->partX<T>(j), v->partY<T>(j), v->partG(j), L.nct, v->nrt(j),
+                                  gram_in_pass(R, (int)sizeof(T)) ? v->nrt(j) : 1, L.n_pad, sU, sV, L.W, s);
     });
     if (st != LV_OK) return st;
   }
@@ -249,6 +249,7 @@ lv_status lv_view_create(const void* A, int64_t n, int64_t lda, int k, int r_max
   v->n = n; v->k = k; v->r_max = r_max; v->mode = mode; v->L = L;
   v->base = static_cast<char*>(workspace); v->ws_bytes = ws_bytes;
   v->updates = 0; v->reanchors = 0;
+  for (int j = 0; j < kMaxLevel; ++j) v->tile_rows[j] = L.tile_rows;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (mode == LV_FP64) {
     st = hip_check(launch_copy_pad<double, double>(static_cast<const double*>(A), lda, n, v->P<double>(0),
@@ -399,6 +400,22 @@ lv_status lv_view_stats(const lv_view* v, lv_stats* out) {
   double mx = 0.0;
   for (int j = 0; j < v->L.m; ++j) mx = res[j] > mx || res[j] != res[j] ? res[j] : mx;
   out->last_residual = mx;
+  return LV_OK;
+}
+
+lv_status lv_view_tile_rows(const lv_view* v, int level, int* rows) {
+  if (!v || !rows) return fail(LV_EINVAL, "view or rows is NULL");
+  if (level < 0 || level >= v->L.m) return fail(LV_EINVAL, "level %d has no level pass (levels 0..%d)", level, v->L.m - 1);
+  *rows = v->tile_rows[level];
+  return LV_OK;
+}
+
+lv_status lv_view_set_tile_rows(lv_view* v, int level, int rows) {
+  if (!v) return fail(LV_EINVAL, "view is NULL");
+  if (level < 0 || level >= v->L.m) return fail(LV_EINVAL, "level %d has no level pass (levels 0..%d)", level, v->L.m - 1);
+  if (rows < kMinTileRows || rows > kMaxTileRows || rows % 64 != 0)
+    return fail(LV_EINVAL, "tile rows %d not a multiple of 64 in [%d, %d]", rows, kMinTileRows, kMaxTileRows);
+  v->tile_rows[level] = rows;
   return LV_OK;
 }
 

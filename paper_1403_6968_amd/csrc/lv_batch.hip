@@ -3,9 +3,24 @@
 // (lv_round.h), and the whole round captured once into a HIP graph that each
 // round replays.  Workspace: per-view input staging (n_pad x r_max for U and
 // for V), then the round's descriptor tables.
+//
+// Tile autotuner: before capture, the rows per tile of every level pass are
+// chosen by timing.  One round with zero inputs runs first; it leaves every
+// stored power unchanged (P + 0) and every factor column zero, so that the
+// level launches can then be timed in isolation without changing any view.
+// For each (level, rank) group of views the candidates 256, 512 and 1024
+// rows are timed over the level's launches (pass, Gram, update, tail; the
+// partial count follows the tile height); the fastest is stored in the
+// views (lv_view_update then uses the same tiles) and in a process-wide
+// cache keyed by device architecture, mode, rank and the group's orders.
 #include "lv_round.h"
 
+#include <algorithm>
+#include <cstdio>
+#include <map>
+#include <mutex>
 #include <new>
+#include <string>
 
 using namespace lv;
 
@@ -48,6 +63,8 @@ BatchLayout batch_layout(const std::vector<lv_view*>& views, lv_mode mode, char*
 }  // namespace
 
 struct lv_batch {
+  int tuned_groups = 0;
+  int cache_hits = 0;
   std::vector<lv_view*> views;
   lv_mode mode;
   char* base;
@@ -56,6 +73,112 @@ struct lv_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
+
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune_cache;
+
+bool is_pass(Kind k) { return k == kFused || k == kChunk || k == kSkinny || k == kSkinnyF32; }
+
+lv_status upload_plan(lv_batch* b, hipStream_t s) {
+  lv_status st = hip_check(hipMemcpyAsync(b->base + b->bl.stage_bytes, b->bl.plan.bytes.data(), b->bl.plan.bytes.size(),
+                                          hipMemcpyHostToDevice, s), "upload descriptors");
+  if (st == LV_OK) st = hip_check(hipStreamSynchronize(s), "sync");
+  return st;
+}
+
+template <typename T>
+lv_status run_launches(const lv_batch* b, int level, hipStream_t s) {
+  const char* dbase = b->base + b->bl.stage_bytes;
+  Plan one;
+  for (const LaunchRec& l : b->bl.plan.launches)
+    if (level < 0 || l.level == level) one.launches.push_back(l);
+  return enqueue_round<T>(one, dbase, s);
+}
+
+template <typename T>
+lv_status autotune(lv_batch* b, hipStream_t s) {
+  std::vector<RoundInput> in;
+  for (size_t i = 0; i < b->views.size(); ++i) {
+    lv_view* v = b->views[i];
+    char* u = b->base + b->bl.stage_off[i];
+    in.push_back({u, v->r_max, u + stage_one(v), v->r_max, v->r_max});
+  }
+  // a zero round: unchanged powers, all factor columns zero
+  lv_status st = run_launches<T>(b, -1, s);
+  if (st != LV_OK) return st;
+  hipDeviceProp_t prop;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(LV_EDEVICE, "device query failed");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(LV_EDEVICE, "hipEventCreate failed");
+  int max_m = 0;
+  for (lv_view* v : b->views) max_m = std::max(max_m, v->L.m);
+  const int cands[] = {256, 512, 1024};
+  for (int j = 0; j < max_m && st == LV_OK; ++j) {
+    std::map<int, std::vector<lv_view*>> groups;   // level rank -> views with a pass at level j
+    for (lv_view* v : b->views)
+      if (j < v->L.m) groups[v->L.r_pad << j].push_back(v);
+    for (auto& g : groups) {
+      std::vector<int64_t> ns;
+      for (lv_view* v : g.second) ns.push_back(v->L.n_pad);
+      std::sort(ns.begin(), ns.end());
+      std::string key = std::string(prop.gcnArchName) + "|m" + std::to_string((int)b->mode) + "|R" +
+                        std::to_string(g.first) + "|n";
+      for (int64_t n : ns) key += ":" + std::to_string(n);
+      int best = -1;
+      {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) best = it->second;
+      }
+      if (best > 0) {
+        b->cache_hits += 1;
+      } else {
+        float best_ms = 0.f;
+        std::vector<int> seen_nrt;
+        for (int c : cands) {
+          // skip a candidate that gives every view the same row-tile count as one already timed
+          int sig = 0;
+          for (lv_view* v : g.second) sig = sig * 131 + (int)((v->L.n_pad + c - 1) / c);
+          if (std::find(seen_nrt.begin(), seen_nrt.end(), sig) != seen_nrt.end()) continue;
+          seen_nrt.push_back(sig);
+          for (lv_view* v : g.second) v->tile_rows[j] = c;
+          b->bl.plan = b->mode == LV_FP64 ? make_plan<double>(b->views, in) : make_plan<float>(b->views, in);
+          st = upload_plan(b, s);
+          if (st != LV_OK) break;
+          float t_min = 0.f;
+          for (int rep = 0; rep < 4 && st == LV_OK; ++rep) {
+            st = hip_check(hipEventRecord(e0, s), "event");
+            if (st == LV_OK) st = run_launches<T>(b, j, s);
+            if (st == LV_OK) st = hip_check(hipEventRecord(e1, s), "event");
+            if (st == LV_OK) st = hip_check(hipEventSynchronize(e1), "event sync");
+            float ms = 0.f;
+            if (st == LV_OK) st = hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
+            if (rep > 0 && (t_min == 0.f || ms < t_min)) t_min = ms;   // rep 0 warms up
+          }
+          if (st != LV_OK) break;
+          if (best < 0 || t_min < best_ms) { best = c; best_ms = t_min; }
+        }
+        if (st != LV_OK) break;
+        b->tuned_groups += 1;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = best;
+      }
+      for (lv_view* v : g.second) v->tile_rows[j] = best;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != LV_OK) return st;
+  b->bl.plan = b->mode == LV_FP64 ? make_plan<double>(b->views, in) : make_plan<float>(b->views, in);
+  return upload_plan(b, s);
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -96,12 +219,10 @@ lv_status lv_batch_create(lv_view* const* views, int count, void* workspace, siz
     return fail(LV_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, need);
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  // zero the staging buffers, upload the descriptors
+  // zero the staging buffers, upload the descriptors, tune the tiles
   st = hip_check(hipMemsetAsync(b->base, 0, b->bl.stage_bytes, s), "clear staging");
-  if (st == LV_OK)
-    st = hip_check(hipMemcpyAsync(b->base + b->bl.stage_bytes, b->bl.plan.bytes.data(), b->bl.plan.bytes.size(),
-                                  hipMemcpyHostToDevice, s), "upload descriptors");
-  if (st == LV_OK) st = hip_check(hipStreamSynchronize(s), "sync");
+  if (st == LV_OK) st = upload_plan(b, s);
+  if (st == LV_OK) st = mode == LV_FP64 ? autotune<double>(b, s) : autotune<float>(b, s);
   // capture one round on a private stream
   if (st == LV_OK) st = hip_check(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "create capture stream");
   if (st == LV_OK) st = hip_check(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed), "begin capture");
@@ -145,6 +266,13 @@ lv_status lv_batch_stage(lv_batch* b, int i, const void* U, const void* V, int64
   return hip_check(launch_prep<float>(static_cast<const float*>(U), ldu, static_cast<const float*>(V), ldv, v->n,
                                       (int)r, v->r_max, static_cast<float*>(su), static_cast<float*>(sv),
                                       v->r_max, v->L.n_pad, s), "stage");
+}
+
+lv_status lv_batch_tuning(const lv_batch* b, int* tuned_groups, int* cache_hits) {
+  if (!b) return fail(LV_EINVAL, "batch is NULL");
+  if (tuned_groups) *tuned_groups = b->tuned_groups;
+  if (cache_hits) *cache_hits = b->cache_hits;
+  return LV_OK;
 }
 
 lv_status lv_batch_update(lv_batch* b, void* stream) {

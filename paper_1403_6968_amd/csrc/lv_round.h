@@ -27,6 +27,7 @@ enum Kind { kPrep, kFused, kChunk, kSkinny, kSkinnyF32, kGram, kGramSum, kUpdate
 
 struct LaunchRec {
   Kind kind;
+  int level;    // level step of the round (-1: prep)
   int R;
   size_t off;   // byte offset of the descriptor array in the descriptor area
   int nd;
@@ -39,6 +40,8 @@ struct Plan {
   std::vector<char> bytes;
   std::vector<LaunchRec> launches;
 
+  int level = -1;   // level step the next add() belongs to
+
   template <typename D, typename F>
   void add(Kind kind, int R, std::vector<D>& ds, F blocks_of) {
     if (ds.empty()) return;
@@ -47,7 +50,7 @@ struct Plan {
     const size_t off = align_up(bytes.size());
     bytes.resize(off + ds.size() * sizeof(D));
     std::memcpy(bytes.data() + off, ds.data(), ds.size() * sizeof(D));
-    launches.push_back({kind, R, off, (int)ds.size(), b});
+    launches.push_back({kind, level, R, off, (int)ds.size(), b});
   }
 };
 
@@ -85,6 +88,7 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
   pl.add(kPrep, 0, prep, &prep_blocks<T>);
 
   for (int j = 0; j <= max_m; ++j) {
+    pl.level = j;
     std::map<int, std::vector<FusedDesc<T>>> fused;
     std::vector<FusedDesc<T>> chunks;
     std::map<int, std::vector<SkinnyDesc>> skinny, skinny32;
@@ -96,6 +100,8 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
       const Layout& L = v->L;
       if (j > L.m) continue;
       const int R = L.r_pad << j;
+      const int trows = j < L.m ? v->tile_rows[j] : 0;
+      const int nrt = j < L.m ? v->nrt(j) : 0;
       T* sU = v->slabU<T>(0);
       T* sV = v->slabV<T>(0);
       const T* Vj = sV + (L.W - R);
@@ -108,12 +114,12 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
       if constexpr (sizeof(T) == 4) {
         if (v->shadowed() || skinny_on_mfma(R, 4)) {
           if (v->shadowed()) {
-            skinny[skinny_blocks_for(R)].push_back({v->shadow(j), L.ldp, (int)L.n_pad, L.tile_rows, sU, Vj, L.W, R,
+            skinny[skinny_blocks_for(R)].push_back({v->shadow(j), L.ldp, (int)L.n_pad, trows, sU, Vj, L.W, R,
                                                     v->partX<T>(j), v->partY<T>(j), R, L.nct, 0});
           } else {
             const int per = R <= 64 ? R : 64;
             for (int c0 = 0; c0 < R; c0 += per)
-              skinny32[skinny_f32_blocks(per)].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, L.tile_rows, sU + c0,
+              skinny32[skinny_f32_blocks(per)].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, trows, sU + c0,
                                                           Vj + c0, L.W, per, v->partX<T>(j) + c0,
                                                           v->partY<T>(j) + c0, R, L.nct, 0});
           }
@@ -121,24 +127,24 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
           gsum.push_back({v->partG(j), gram_tiles(L.n_pad), R * R, 0});
           (v->shadowed() ? updsh : upd)[R].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, upd_rows, sU, Vj, L.W,
                                                       upd_nct, 0, v->shadowed() ? v->shadow(j) : nullptr});
-          tail[R].push_back({v->partX<T>(j), v->partY<T>(j), v->partG(j), L.nct, L.nrt, (int)L.n_pad, sU, sV, L.W,
+          tail[R].push_back({v->partX<T>(j), v->partY<T>(j), v->partG(j), L.nct, nrt, (int)L.n_pad, sU, sV, L.W,
                              0, 1});
           continue;
         }
       }
       if (R <= kMaxFusedRank) {
-        fused[R].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, L.tile_rows, sU, Vj, L.W, v->partX<T>(j),
+        fused[R].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, trows, sU, Vj, L.W, v->partX<T>(j),
                             v->partY<T>(j), v->partG(j), R, L.nct, 0});
       } else {
         for (int c0 = 0; c0 < R; c0 += kMaxFusedRank)
-          chunks.push_back({v->P<T>(j), L.ldp, (int)L.n_pad, L.tile_rows, sU + c0, Vj + c0, L.W,
+          chunks.push_back({v->P<T>(j), L.ldp, (int)L.n_pad, trows, sU + c0, Vj + c0, L.W,
                             v->partX<T>(j) + c0, v->partY<T>(j) + c0, nullptr, R, L.nct, 0});
         gram[R].push_back({sU, Vj, L.W, (int)L.n_pad, kGramRows, v->partG(j), gram_tiles(L.n_pad), 0});
         gsum.push_back({v->partG(j), gram_tiles(L.n_pad), R * R, 0});
         upd[R].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, upd_rows, sU, Vj, L.W, upd_nct, 0});
       }
-      tail[R].push_back({v->partX<T>(j), v->partY<T>(j), v->partG(j), L.nct, L.nrt, (int)L.n_pad, sU, sV, L.W, 0,
-                         gram_in_pass(R, L.elem) ? L.nrt : 1});
+      tail[R].push_back({v->partX<T>(j), v->partY<T>(j), v->partG(j), L.nct, nrt, (int)L.n_pad, sU, sV, L.W, 0,
+                         gram_in_pass(R, L.elem) ? nrt : 1});
     }
     for (auto& kv : fused) pl.add(kFused, kv.first, kv.second, &fused_blocks<T>);
     pl.add(kChunk, kMaxFusedRank, chunks, &fused_blocks<T>);

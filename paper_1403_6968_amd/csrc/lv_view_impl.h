@@ -23,13 +23,15 @@ constexpr size_t kAlign = 256;
 constexpr int64_t kMaxOrder = 65536;
 constexpr int kMaxK = 1024;
 constexpr int kMaxWidth = 256;   // k * r_pad: width of the top-level factors
-constexpr int kTileRows = 512;   // rows per tile of the fused level pass
+constexpr int kTileRows = 512;      // default rows per tile of a level pass
+constexpr int kMinTileRows = 256;   // tile rows a level pass may be set to:
+constexpr int kMaxTileRows = 1024;  //   multiples of 64 in [256, 1024]
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   int64_t n_pad = 0, ldp = 0;
-  int m = 0, r_pad = 0, W = 0, elem = 0, nct = 0, nrt = 0, tile_rows = 0;
+  int m = 0, r_pad = 0, W = 0, elem = 0, nct = 0, nrt_max = 0, tile_rows = 0;
   size_t P[kMaxLevel + 1] = {};
   size_t slabU[kMaxLevel + 1] = {};
   size_t slabV[kMaxLevel + 1] = {};
@@ -64,7 +66,7 @@ inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode) {
   L.W = k * L.r_pad;
   L.tile_rows = kTileRows;
   L.nct = (int)(L.n_pad / tile_cols_bytes(L.elem));
-  L.nrt = (int)((L.n_pad + L.tile_rows - 1) / L.tile_rows);
+  L.nrt_max = (int)((L.n_pad + kMinTileRows - 1) / kMinTileRows);   // partials sized for the smallest tiles
   size_t off = 0;
   const size_t mat = (size_t)L.n_pad * L.ldp * L.elem;
   for (int j = 0; j <= L.m; ++j) { L.P[j] = off; off = align_up(off + mat); }
@@ -76,8 +78,8 @@ inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode) {
   for (int j = 0; j < L.m; ++j) {
     const size_t R = (size_t)L.r_pad << j;
     L.partX[j] = off; off = align_up(off + (size_t)L.nct * L.n_pad * R * L.elem);
-    L.partY[j] = off; off = align_up(off + (size_t)L.nrt * L.n_pad * R * L.elem);
-    const size_t ng = (size_t)(gram_tiles(L.n_pad) > L.nrt ? gram_tiles(L.n_pad) : L.nrt);
+    L.partY[j] = off; off = align_up(off + (size_t)L.nrt_max * L.n_pad * R * L.elem);
+    const size_t ng = (size_t)(gram_tiles(L.n_pad) > L.nrt_max ? gram_tiles(L.n_pad) : L.nrt_max);
     L.partG[j] = off; off = align_up(off + ng * R * R * sizeof(double));
   }
   if (mode == LV_FP32_BF16SHADOW)
@@ -110,6 +112,11 @@ struct lv_view {
   size_t ws_bytes;
   int64_t updates;
   int64_t reanchors;
+  // Rows per tile of the level pass of each level below the top (set by the
+  // batch autotuner or lv_view_set_tile_rows; every path uses the same value,
+  // which fixes the reduction order of the partial sums).
+  int tile_rows[lv::kMaxLevel];
+  int nrt(int j) const { return (int)((L.n_pad + tile_rows[j] - 1) / tile_rows[j]); }
 
   // Kernel timing (diagnostics): event pairs per launch kind, resolved by
   // lv_view_timing.

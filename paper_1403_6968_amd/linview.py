@@ -33,6 +33,7 @@ EXPORTED = (
     "lv_batch_footprint", "lv_batch_create", "lv_batch_inputs", "lv_batch_stage", "lv_batch_update",
     "lv_batch_destroy", "lv_server_create", "lv_server_view_bytes", "lv_server_add_view",
     "lv_server_remove_view", "lv_server_view", "lv_server_now", "lv_server_submit", "lv_server_step",
+    "lv_view_tile_rows", "lv_view_set_tile_rows", "lv_batch_tuning",
     "lv_server_poll", "lv_server_drain", "lv_server_stats", "lv_server_destroy",
 )
 
@@ -120,6 +121,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "lv_server_stats": (I32, [P, c.POINTER(lv_server_counters)]),
         "lv_server_destroy": (None, [P]),
         "lv_view_timing": (I32, [P, c.POINTER(lv_timing)]),
+        "lv_view_tile_rows": (I32, [P, I32, c.POINTER(I32)]),
+        "lv_view_set_tile_rows": (I32, [P, I32, I32]),
+        "lv_batch_tuning": (I32, [P, c.POINTER(I32), c.POINTER(I32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -248,6 +252,22 @@ def lv_view_set_timing(view, enable: bool) -> None:
     _check(load().lv_view_set_timing(view, 1 if enable else 0))
 
 
+def lv_view_tile_rows(view, level: int) -> int:
+    rows = ctypes.c_int()
+    _check(load().lv_view_tile_rows(view, level, ctypes.byref(rows)))
+    return rows.value
+
+
+def lv_view_set_tile_rows(view, level: int, rows: int) -> None:
+    _check(load().lv_view_set_tile_rows(view, level, rows))
+
+
+def lv_batch_tuning(batch) -> dict:
+    t, h = ctypes.c_int(), ctypes.c_int()
+    _check(load().lv_batch_tuning(batch, ctypes.byref(t), ctypes.byref(h)))
+    return {"tuned_groups": t.value, "cache_hits": h.value}
+
+
 def lv_view_timing(view) -> dict:
     t = lv_timing()
     _check(load().lv_view_timing(view, ctypes.byref(t)))
@@ -336,6 +356,14 @@ class View:
     def timing(self) -> dict:
         return lv_view_timing(self.handle)
 
+    def tile_rows(self) -> list[int]:
+        """Rows per tile of the level pass of each level below the top."""
+        return [lv_view_tile_rows(self.handle, j) for j in range(len(self.powers()) - 1)]
+
+    def set_tile_rows(self, rows) -> None:
+        for j, r in enumerate(rows):
+            lv_view_set_tile_rows(self.handle, j, r)
+
     def powers(self) -> list[int]:
         out, p = [], 1
         while p <= self.k:
@@ -409,6 +437,9 @@ class Batch:
 
     def update(self, stream=None) -> None:
         lv_batch_update(self.handle, stream, self.device)
+
+    def tuning(self) -> dict:
+        return lv_batch_tuning(self.handle)
 
     def close(self) -> None:
         if getattr(self, "handle", None) is not None:

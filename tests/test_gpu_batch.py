@@ -2,6 +2,8 @@
 one graph-replayed round must equal the same views updated one by one with
 lv_view_update, bit for bit, and the FP64 oracle within tolerance.
 
+The batch autotunes the tile rows of every level pass at creation and
+stores them in the views; the one-by-one twins take the same tile rows.
 A batch stages every update at its view's full width r_max (unused columns
 zero).  Zero columns leave every value exact but a different width selects
 a different reduction order, so the one-by-one twins receive the same
@@ -45,6 +47,16 @@ def test_batch_rounds_match_single_views_and_oracle(dtype_name):
         twins.append(lv.View(dev(A, td), k, r_max=r, mode=mode))
         ref.append(O.reeval(A, k))
     batch = lv.Batch(views)
+    tun = batch.tuning()
+    note(f"autotuning {dtype_name}: {tun}; tiles {[v.tile_rows() for v in views]}")
+    assert tun["tuned_groups"] + tun["cache_hits"] > 0
+    for v, tw in zip(views, twins):
+        tw.set_tile_rows(v.tile_rows())      # the twins reduce in the same order
+    # the zero round of the autotuner left every view unchanged
+    for v in range(len(SHAPES)):
+        got, twin = read_all(views[v]), read_all(twins[v])
+        for i in got:
+            np.testing.assert_array_equal(got[i], twin[i])
     for t in range(rounds):
         for v, (n, k, r) in enumerate(SHAPES):
             if (v + t) % 4 == 3:                      # some views sit a round out

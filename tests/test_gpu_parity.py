@@ -54,13 +54,15 @@ def test_create_matches_reeval(n, k, dtype):
 
 # ---------------------------------------------------------------- updates
 
-def _run_updates(lv, n, k, r, T, dtype, seed, check_every, tol, dtol=None, batch=False):
+def _run_updates(lv, n, k, r, T, dtype, seed, check_every, tol, dtol=None, batch=False, tiles=None):
     import torch
     td, nd = (torch.float64, np.float64) if dtype == "f64" else (torch.float32, np.float32)
     A64 = synth.gaussian_matrix(n, seed=seed, config=2)
     Us64, Vs64 = synth.update_factors(n, r, T, seed=seed, config=2)
     A, Us, Vs = storage_inputs(A64, Us64, Vs64, nd)
     view = lv.View(dev(A, td), k, r_max=r)
+    if tiles is not None:
+        view.set_tile_rows([tiles] * (len(view.powers()) - 1))
     P0_ref = O.reeval(A, k)
     P0_got = read_all(view)
     P = dict(P0_ref)
@@ -114,6 +116,21 @@ def test_updates_shapes(n, k, r, dtype):
     tol = 1e-10 if dtype == "f64" else 1e-4
     dtol = 1e-7 if dtype == "f64" else 2e-2
     v = _run_updates(lv, n, k, r, 12, dtype, seed=n + k + r, check_every=6, tol=tol, dtol=dtol)
+    v.close()
+
+
+@pytest.mark.parametrize("tiles,dtype,r", [(256, "f32", 1), (1024, "f32", 4), (256, "f64", 2), (1024, "f64", 1)])
+def test_tile_rows_settings(tiles, dtype, r):
+    """Every allowed tile height gives a correct update (the partial counts of
+    the tail follow the tile height); n = 1300 leaves a ragged last tile."""
+    lv = _lv()
+    tol = 1e-10 if dtype == "f64" else 1e-4
+    v = _run_updates(lv, 1300, 16, r, 6, dtype, seed=77 + tiles, check_every=3, tol=tol, tiles=tiles)
+    assert v.tile_rows() == [tiles] * 4
+    with pytest.raises(lv.LinviewError):
+        lv.lv_view_set_tile_rows(v.handle, 0, 200)
+    with pytest.raises(lv.LinviewError):
+        lv.lv_view_set_tile_rows(v.handle, 4, 512)      # the top level has no level pass
     v.close()
 
 
