@@ -400,7 +400,9 @@ def main():
                          ("batched_64_views", lambda: bench_batched(torch, lv, synth, dev)),
                          ("serving_32_views", lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds)),
                          ("serving_32_views_fp32",
-                          lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds, shadow=False))):
+                          lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds, shadow=False)),
+                         ("serving_32_views_5k",
+                          lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds, rate=5000.0))):
             sec[name] = fn()
             torch.cuda.empty_cache()
             log(f"{name}: {sec[name]}")
