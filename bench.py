@@ -50,6 +50,8 @@ def parse():
     p.add_argument("--no-secondary", action="store_true",
                    help="skip the rank-4, batched and serving workloads")
     p.add_argument("--serve-seconds", type=float, default=2.0)
+    p.add_argument("--only", choices=["rank4", "batched", "serving"],
+                   help="run one secondary workload alone and print its result (for profilers)")
     return p.parse_args()
 
 
@@ -180,8 +182,8 @@ def counter_traffic(n, k, r):
     changed since the counters were taken."""
     import hashlib
     prof = os.path.join(ROOT, "profiles", "k_level_fused_n8192_k16_fp32_rank1_traffic.md")
-    src = os.path.join(ROOT, "paper_1403_6968_amd", "csrc", "lv_level.hip")
-    if (n, k, r) != (8192, 16, 1) or not os.path.exists(prof) or not os.path.exists(src):
+    srcs = [os.path.join(ROOT, "paper_1403_6968_amd", "csrc", f) for f in ("lv_fused.hip", "lv_device.h")]
+    if (n, k, r) != (8192, 16, 1) or not os.path.exists(prof) or not all(os.path.exists(f) for f in srcs):
         return None
     vals = {}
     for line in open(prof):
@@ -189,7 +191,10 @@ def counter_traffic(n, k, r):
             vals["bytes"] = float(line.split("=")[1].split()[0])
         elif line.startswith("source_sha256_prefix ="):
             vals["sha"] = line.split("=")[1].strip()
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in srcs:
+        h.update(open(f, "rb").read())
+    sha = h.hexdigest()[:16]
     if vals.get("sha") != sha or "bytes" not in vals:
         return None
     return vals["bytes"]
@@ -238,6 +243,12 @@ def main():
     lv.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.only:
+        fn = {"rank4": lambda: bench_rank4(torch, lv, synth, dev),
+              "batched": lambda: bench_batched(torch, lv, synth, dev),
+              "serving": lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds)}[args.only]
+        print(json.dumps({"only": args.only, "result": fn()}), flush=True)
+        return
     n, k, r = args.n, args.k, args.rank
     total = args.warmup + args.steps
 

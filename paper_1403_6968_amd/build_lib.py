@@ -20,8 +20,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblinview.so")
 
-SOURCES = ["lv_api.hip", "lv_level.hip", "lv_skinny.hip", "lv_gemm.hip", "lv_probe.hip", "lv_batch.hip",
-           "lv_server.hip"]
+SOURCES = ["lv_api.hip", "lv_level.hip", "lv_fused.hip", "lv_skinny.hip", "lv_gemm.hip", "lv_probe.hip",
+           "lv_batch.hip", "lv_server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

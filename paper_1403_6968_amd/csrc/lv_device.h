@@ -1,0 +1,50 @@
+// Device helpers shared by the level-kernel translation units.
+#pragma once
+
+#include "lv_internal.h"
+
+namespace lv {
+namespace {
+
+// 16-byte vector of T held as an array.
+template <typename T> struct alignas(16) V16 { T v[16 / sizeof(T)]; };
+
+template <typename T> __device__ __forceinline__ V16<T> ld16(const T* p) {
+  return *reinterpret_cast<const V16<T>*>(p);
+}
+template <typename T> __device__ __forceinline__ void st16(T* p, const V16<T>& x) {
+  *reinterpret_cast<V16<T>*>(p) = x;
+}
+
+__device__ __forceinline__ int wave_id() {
+  return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+// Index of the descriptor whose block range holds block `b` (descriptors are
+// sorted by block_begin, the first starts at 0): binary search, uniform.
+template <typename D>
+__device__ __forceinline__ int find_desc(const D* __restrict__ ds, int nd, int b) {
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ds[mid].block_begin <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace
+}  // namespace lv
+
+// switch over the level ranks 1..128 with RR a constant expression
+#define LV_RANK_SWITCH(R, CALL)            \
+  switch (R) {                              \
+    case 1: { constexpr int RR = 1; CALL; }   \
+    case 2: { constexpr int RR = 2; CALL; }   \
+    case 4: { constexpr int RR = 4; CALL; }   \
+    case 8: { constexpr int RR = 8; CALL; }   \
+    case 16: { constexpr int RR = 16; CALL; } \
+    case 32: { constexpr int RR = 32; CALL; } \
+    case 64: { constexpr int RR = 64; CALL; } \
+    case 128: { constexpr int RR = 128; CALL; } \
+    default: return hipErrorInvalidValue;   \
+  }

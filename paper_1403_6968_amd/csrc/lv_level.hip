@@ -1,18 +1,15 @@
-// Level kernels of the IncrExp update (LINVIEW, App. A exponential model).
+// Level kernels of the IncrExp update (LINVIEW, App. A exponential model)
+// other than the fused pass (lv_fused.hip) and the matrix-core skinny passes
+// (lv_skinny.hip): the Gram V_j^T U_j, the tail that reduces the partials and
+// assembles the next factors, the rank-R update pass, and small helpers.
 //
 // For one level j of the exponential model the update needs, with the OLD
 // stored power P = A^(2^j) and the level factors U_j, V_j (n x R, R = 2^j r):
 //     X = P U_j,   Y = P^T V_j,   G = V_j^T U_j,   P += U_j V_j^T
 // and then U_{j+1} = [U_j, X + U_j G], V_{j+1} = [Y, V_j]  (Sec. 4.3, App. A).
-//
-// k_level_fused does the first four in ONE read and ONE write of P: a tile of
-// P is streamed through registers once; Y and the rank-R update use the
-// coalesced row-segment layout directly, and the old values go through LDS
-// so that X can be formed with one row per lane (no cross-lane reductions).
-// Each tile writes partial X / Y (and the column-tile-0 tiles partial Grams);
-// k_level_tail reduces them in a fixed order (deterministic, no float
-// atomics) and assembles the next level's factors.  k_level_update is the
-// update-only pass of the top stored power.
+// The tail reduces the partials of every tile in a fixed order
+// (deterministic, no float atomics).  k_level_update is the update pass (the
+// top stored power, and every level whose products ran apart).
 //
 // Layouts (all row-major):
 //   P        n_pad x ldp, zero padding beyond n.
@@ -20,253 +17,11 @@
 //   slab V   n_pad x W; V_j = columns [W - R, W)  (callers pass the offset base).
 //   partX    [nct][n_pad][R]   (nct = n_pad / TC column tiles)
 //   partY    [nrt][n_pad][R]   (nrt row tiles)
-//   partG    [nrt][R][R] double
-#include "lv_internal.h"
+//   partG    [ng][R][R] double (ng partials, summed by the tail)
+#include "lv_device.h"
 
 namespace lv {
 namespace {
-
-// 16-byte vector of T held as an array.
-template <typename T> struct alignas(16) V16 { T v[16 / sizeof(T)]; };
-
-template <typename T> __device__ __forceinline__ V16<T> ld16(const T* p) {
-  return *reinterpret_cast<const V16<T>*>(p);
-}
-template <typename T> __device__ __forceinline__ void st16(T* p, const V16<T>& x) {
-  *reinterpret_cast<V16<T>*>(p) = x;
-}
-
-__device__ __forceinline__ int wave_id() {
-  return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-}
-
-// Index of the descriptor whose block range holds block `b` (descriptors are
-// sorted by block_begin, the first starts at 0): binary search, uniform.
-template <typename D>
-__device__ __forceinline__ int find_desc(const D* __restrict__ ds, int nd, int b) {
-  int lo = 0, hi = nd - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (ds[mid].block_begin <= b) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
-// ---------------------------------------------------------------- fused pass
-//
-// Block: 256 threads (4 waves).  Tile: tile_rows x TC, TC = 64 lanes x 16 B.
-// The tile's rows are cut into blocks of RB rows; wave w owns blocks
-// w, w + 4, w + 8, ... and processes each one end to end with no block-wide
-// synchronisation:
-//   Phase A  one 16-byte vector per lane per row: Y partial (yacc, the
-//            lane's own columns, V_j rows broadcast through the scalar unit),
-//            the old values to the wave's private LDS block, and
-//            P + U_j V_j^T back to HBM; the next block's rows are then
-//            requested at once so that they are in flight during Phase B.
-//   Phase B  lane (rho, q) = (lane % RB, lane / RB) sums row rho of the block
-//            over the q-th of NQ = 64 / RB column slices with the tile's
-//            U_j rows read from LDS (staged once per tile); the NQ slice
-//            sums are combined with xor-shuffles and one partial per
-//            (row, tile column) is written.
-// The four waves' Y accumulators are summed once at the end of the tile.
-//
-// UPD = false gives the read-only variant used for ranks above 16: the
-// skinny products of 16 factor columns at a time (partials written with row
-// stride pR at the chunk's column offset), the rank update and the Gram done
-// by k_level_update and k_gram.
-template <typename T, int R, int RB, bool UPD>
-__device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp, const int n_pad,
-                                           const int tile_rows, const T* __restrict__ Uj,
-                                           const T* __restrict__ Vj, const int W, T* __restrict__ partX,
-                                           T* __restrict__ partY, double* __restrict__ partG, const int pR,
-                                           const int ct, const int rt) {
-  constexpr int EPL = 16 / (int)sizeof(T);
-  constexpr int TC = 64 * EPL;
-  constexpr int NQ = 64 / RB;           // column slices in Phase B
-  constexpr int QW = TC / NQ;           // columns per slice
-  constexpr int LDSW = TC + EPL;        // padded LDS row (elements)
-  constexpr int UPAD = 4;               // LDS padding between U slices (elements)
-
-  __shared__ __align__(16) T tileP[4 * RB * LDSW];
-  __shared__ __align__(16) T utile[TC * R + NQ * UPAD];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = wave_id();
-  const int col0 = ct * TC;
-  const int row0 = rt * tile_rows;
-  const int nrows = min(tile_rows, n_pad - row0);
-  const int nblocks = nrows / RB;
-  const int lc = col0 + lane * EPL;
-  T* myP = tileP + wave * RB * LDSW;
-
-  // U_j rows of the tile's columns, slice-padded: (col, c) -> col*R + (col/QW)*UPAD + c.
-  for (int idx = tid; idx < TC * R; idx += 256) {
-    const int col = idx / R, c = idx % R;
-    utile[col * R + (col / QW) * UPAD + c] = Uj[(int64_t)(col0 + col) * W + c];
-  }
-
-  T vcol[EPL][UPD ? R : 1];
-  if constexpr (UPD) {
-#pragma unroll
-    for (int q = 0; q < EPL; ++q)
-#pragma unroll
-      for (int c = 0; c < R; ++c) vcol[q][c] = Vj[(int64_t)(lc + q) * W + c];
-  }
-
-  T yacc[EPL][R];
-#pragma unroll
-  for (int q = 0; q < EPL; ++q)
-#pragma unroll
-    for (int c = 0; c < R; ++c) yacc[q][c] = T(0);
-
-  __syncthreads();
-
-  const int rho = lane % RB;
-  const int qs = lane / RB;
-  const T* urow0 = utile + qs * (QW * R + UPAD);
-
-  V16<T> p[RB];
-  if (wave < nblocks) {
-    const int64_t r0 = row0 + wave * RB;
-#pragma unroll
-    for (int t = 0; t < RB; ++t) p[t] = ld16(P + (r0 + t) * ldp + lc);
-  }
-
-  for (int b = wave; b < nblocks; b += 4) {
-    const int64_t r0 = row0 + b * RB;
-
-#pragma unroll
-    for (int t = 0; t < RB; ++t) {
-      const int64_t i = r0 + t;
-      const T* vrow = Vj + i * W;
-      T vi[R];
-#pragma unroll
-      for (int c = 0; c < R; ++c) vi[c] = vrow[c];
-#pragma unroll
-      for (int q = 0; q < EPL; ++q)
-#pragma unroll
-        for (int c = 0; c < R; ++c) yacc[q][c] = fma(p[t].v[q], vi[c], yacc[q][c]);
-      st16(myP + t * LDSW + lane * EPL, p[t]);
-      if constexpr (UPD) {
-        const T* urow = Uj + i * W;
-        T ui[R];
-#pragma unroll
-        for (int c = 0; c < R; ++c) ui[c] = urow[c];
-#pragma unroll
-        for (int q = 0; q < EPL; ++q) {
-          T d = ui[0] * vcol[q][0];
-#pragma unroll
-          for (int c = 1; c < R; ++c) d = fma(ui[c], vcol[q][c], d);
-          p[t].v[q] += d;
-        }
-        st16(P + i * ldp + lc, p[t]);
-      }
-    }
-    if (b + 4 < nblocks) {
-      const int64_t rn = r0 + 4 * RB;
-#pragma unroll
-      for (int t = 0; t < RB; ++t) p[t] = ld16(P + (rn + t) * ldp + lc);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-    T x[R];
-#pragma unroll
-    for (int c = 0; c < R; ++c) x[c] = T(0);
-    const T* prow = myP + rho * LDSW + qs * QW;
-#pragma unroll 4
-    for (int l = 0; l < QW; l += EPL) {
-      const V16<T> pv = ld16(prow + l);
-#pragma unroll
-      for (int e = 0; e < EPL; ++e) {
-        const T* ur = urow0 + (l + e) * R;
-#pragma unroll
-        for (int c = 0; c < R; ++c) x[c] = fma(pv.v[e], ur[c], x[c]);
-      }
-    }
-#pragma unroll
-    for (int off = RB; off < 64; off <<= 1)
-#pragma unroll
-      for (int c = 0; c < R; ++c) x[c] += __shfl_xor(x[c], off);
-    if (qs == 0) {
-#pragma unroll
-      for (int c = 0; c < R; ++c) partX[((int64_t)ct * n_pad + r0 + rho) * pR + c] = x[c];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
-
-  // Y partial of this tile: sum the four waves' accumulators (in column
-  // chunks of YC factor columns when the tile buffer cannot hold all R).
-  constexpr int YCAP = (RB * LDSW) / TC;
-  constexpr int YC = R < YCAP ? R : YCAP;
-  static_assert(YC >= 1 && R % YC == 0, "Y reduction chunking");
-  T* ybuf = tileP;
-#pragma unroll
-  for (int c0 = 0; c0 < R; c0 += YC) {
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < EPL; ++q)
-#pragma unroll
-      for (int c = 0; c < YC; ++c) ybuf[(wave * TC + lane * EPL + q) * YC + c] = yacc[q][c0 + c];
-    __syncthreads();
-    for (int idx = tid; idx < TC * YC; idx += 256) {
-      const int cc = idx / YC, c = idx % YC;
-      const T s = ((ybuf[(0 * TC + cc) * YC + c] + ybuf[(1 * TC + cc) * YC + c]) +
-                   ybuf[(2 * TC + cc) * YC + c]) + ybuf[(3 * TC + cc) * YC + c];
-      partY[((int64_t)rt * n_pad + col0 + cc) * pR + c0 + c] = s;
-    }
-  }
-
-  // Partial Gram V_j^T U_j over this tile's rows (double accumulation):
-  // thread (pair, group) sums every G-th row of the tile for one (a, b), the
-  // groups are then added in a fixed order.
-  if (UPD && ct == 0) {
-    constexpr int NP = R * R;
-    constexpr int G = NP >= 256 ? 1 : 256 / NP;
-    double* gbuf = reinterpret_cast<double*>(tileP);
-    __syncthreads();
-    for (int base = 0; base < NP; base += 256) {
-      const int pair = base + (tid % (NP < 256 ? NP : 256));
-      const int grp = tid / (NP < 256 ? NP : 256);
-      double g = 0.0;
-      if (grp < G && pair < NP) {
-        const int a = pair / R, bb = pair % R;
-        const T* vp = Vj + a;
-        const T* up = Uj + bb;
-#pragma unroll 8
-        for (int i = row0 + grp; i < row0 + nrows; i += G)
-          g = fma((double)vp[(int64_t)i * W], (double)up[(int64_t)i * W], g);
-      }
-      gbuf[tid] = g;
-      __syncthreads();
-      if (tid < (NP - base < 256 ? NP - base : 256)) {
-        double s = 0.0;
-        for (int q = 0; q < G; ++q) s += gbuf[q * (NP < 256 ? NP : 256) + tid];
-        partG[(int64_t)rt * NP + base + tid] = s;
-      }
-      __syncthreads();
-    }
-  }
-}
-
-template <typename T, int R, int RB, bool UPD>
-__global__ void __launch_bounds__(256) k_level_fused(const FusedDesc<T> d) {
-  fused_body<T, R, RB, UPD>(d.P, d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.partX, d.partY, d.partG, d.pR,
-                            blockIdx.x, blockIdx.y);
-}
-
-template <typename T, int R, int RB, bool UPD>
-__global__ void __launch_bounds__(256) k_level_fused_multi(const FusedDesc<T>* __restrict__ ds, int nd) {
-  const int v = find_desc(ds, nd, (int)blockIdx.x);
-  const FusedDesc<T> d = ds[v];
-  const int local = (int)blockIdx.x - d.block_begin;
-  fused_body<T, R, RB, UPD>(d.P, d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.partX, d.partY, d.partG, d.pR,
-                            local % d.nct, local / d.nct);
-}
 
 // ---------------------------------------------------------------- Gram (ranks > 16)
 // Partial V_j^T U_j over one row tile (double accumulation, rows in index
@@ -630,16 +385,6 @@ __global__ void __launch_bounds__(256) k_prep_multi(const PrepDesc<T>* __restric
                (int)blockIdx.x - d.block_begin);
 }
 
-template <typename T, int R, int RB, bool UPD>
-hipError_t fused_launch(T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* Uj, const T* Vj,
-                        int W, T* partX, T* partY, double* partG, int pR, hipStream_t s) {
-  const int nct = (int)(n_pad / tile_cols<T>());
-  const FusedDesc<T> d{P, ldp, (int)n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, pR, nct, 0};
-  const dim3 grid((unsigned)nct, (unsigned)((n_pad + tile_rows - 1) / tile_rows));
-  hipLaunchKernelGGL((k_level_fused<T, R, RB, UPD>), grid, dim3(256), 0, s, d);
-  return hipGetLastError();
-}
-
 template <typename T, int R>
 hipError_t update_r(T* P, int64_t ldp, int64_t n_pad, const T* Uj, const T* Vj, int W,
                     hipStream_t s, uint16_t* S = nullptr) {
@@ -672,30 +417,6 @@ hipError_t gram_r(const T* Uj, const T* Vj, int W, int64_t n_pad, double* partG,
   return hipGetLastError();
 }
 
-// One level with rank R: for R <= 16 the fused pass; above, the skinny
-// products in 16-column chunks (read-only passes), the Gram, then the rank-R
-// update pass.
-template <typename T, int R>
-hipError_t fused_r(T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* Uj, const T* Vj,
-                   int W, T* partX, T* partY, double* partG, hipStream_t s) {
-  if constexpr (R <= kMaxFusedRank) {
-    // 16-row blocks keep more rows in flight per wave; at R >= 8 the factor
-    // registers make 8-row blocks (more resident waves) faster.
-    constexpr int RB = R >= 8 ? 8 : 16;
-    return fused_launch<T, R, RB, true>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, R, s);
-  } else {
-    constexpr int RC = kMaxFusedRank;
-    for (int c0 = 0; c0 < R; c0 += RC) {
-      hipError_t e = fused_launch<T, RC, 8, false>(P, ldp, n_pad, tile_rows, Uj + c0, Vj + c0, W,
-                                                   partX + c0, partY + c0, nullptr, R, s);
-      if (e != hipSuccess) return e;
-    }
-    hipError_t e = gram_r<T, R>(Uj, Vj, W, n_pad, partG, s);
-    if (e != hipSuccess) return e;
-    return update_r<T, R>(P, ldp, n_pad, Uj, Vj, W, s);
-  }
-}
-
 template <typename T, int R>
 hipError_t tail_r(const T* partX, const T* partY, const double* partG, int nct, int nrt, int ng,
                   int64_t n_pad, T* slabU, T* slabV, int W, hipStream_t s) {
@@ -703,19 +424,6 @@ hipError_t tail_r(const T* partX, const T* partY, const double* partG, int nct, 
   hipLaunchKernelGGL((k_level_tail<T, R>), dim3((unsigned)tail_blocks(n_pad, R)), dim3(256), 0, s, d);
   return hipGetLastError();
 }
-
-#define LV_RANK_SWITCH(R, CALL)            \
-  switch (R) {                              \
-    case 1: { constexpr int RR = 1; CALL; }   \
-    case 2: { constexpr int RR = 2; CALL; }   \
-    case 4: { constexpr int RR = 4; CALL; }   \
-    case 8: { constexpr int RR = 8; CALL; }   \
-    case 16: { constexpr int RR = 16; CALL; } \
-    case 32: { constexpr int RR = 32; CALL; } \
-    case 64: { constexpr int RR = 64; CALL; } \
-    case 128: { constexpr int RR = 128; CALL; } \
-    default: return hipErrorInvalidValue;   \
-  }
 
 }  // namespace
 
@@ -733,15 +441,6 @@ hipError_t launch_prep(const T* U, int64_t ldu, const T* V, int64_t ldv, int64_t
   const PrepDesc<T> d{U, ldu, V, ldv, n, r, r_pad, slabU, slabV, W, n_pad, 0};
   hipLaunchKernelGGL((k_prep<T>), dim3((unsigned)((n_pad * r_pad + 255) / 256)), dim3(256), 0, s, d);
   return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_level_fused(int R, T* P, int64_t ldp, int64_t n_pad, int tile_rows,
-                              const T* slabU, const T* slabV, int W, T* partX, T* partY,
-                              double* partG, hipStream_t s) {
-  const T* Uj = slabU;
-  const T* Vj = slabV + (W - R);
-  LV_RANK_SWITCH(R, return (fused_r<T, RR>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s)))
 }
 
 template <typename T>
@@ -765,27 +464,6 @@ hipError_t launch_level_gram(int R, const T* slabU, const T* slabV, int W, int64
   const T* Uj = slabU;
   const T* Vj = slabV + (W - R);
   LV_RANK_SWITCH(R, return (gram_r<T, RR>(Uj, Vj, W, n_pad, partG, s)))
-}
-
-// ---- multi-view launchers
-
-template <typename T>
-hipError_t launch_fused_multi(int R, bool chunk, const FusedDesc<T>* ds, int nd, int blocks, hipStream_t s) {
-  if (blocks <= 0) return hipSuccess;
-  if (chunk) {
-    hipLaunchKernelGGL((k_level_fused_multi<T, kMaxFusedRank, 8, false>), dim3((unsigned)blocks), dim3(256), 0, s,
-                       ds, nd);
-    return hipGetLastError();
-  }
-  switch (R) {
-    case 1: hipLaunchKernelGGL((k_level_fused_multi<T, 1, 16, true>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
-    case 2: hipLaunchKernelGGL((k_level_fused_multi<T, 2, 16, true>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
-    case 4: hipLaunchKernelGGL((k_level_fused_multi<T, 4, 16, true>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
-    case 8: hipLaunchKernelGGL((k_level_fused_multi<T, 8, 8, true>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
-    case 16: hipLaunchKernelGGL((k_level_fused_multi<T, 16, 8, true>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
 }
 
 template <typename T>
@@ -839,15 +517,12 @@ hipError_t launch_prep_multi(const PrepDesc<T>* ds, int nd, int blocks, hipStrea
 #define LV_INST(T)                                                                              \
   template hipError_t launch_prep<T>(const T*, int64_t, const T*, int64_t, int64_t, int, int,     \
                                      T*, T*, int, int64_t, hipStream_t);                          \
-  template hipError_t launch_level_fused<T>(int, T*, int64_t, int64_t, int, const T*, const T*,   \
-                                            int, T*, T*, double*, hipStream_t);                   \
   template hipError_t launch_level_tail<T>(int, const T*, const T*, const double*, int, int, int, \
                                            int64_t, T*, T*, int, hipStream_t);                    \
   template hipError_t launch_level_update<T>(int, T*, int64_t, int64_t, const T*, const T*, int,  \
                                              hipStream_t, uint16_t*);                             \
   template hipError_t launch_level_gram<T>(int, const T*, const T*, int, int64_t, double*,        \
                                            hipStream_t);                                          \
-  template hipError_t launch_fused_multi<T>(int, bool, const FusedDesc<T>*, int, int, hipStream_t); \
   template hipError_t launch_gram_multi<T>(int, const GramDesc<T>*, int, int, hipStream_t);        \
   template hipError_t launch_tail_multi<T>(int, const TailDesc<T>*, int, int, hipStream_t);        \
   template hipError_t launch_update_multi<T>(int, bool, const UpdateDesc<T>*, int, int, hipStream_t); \
