@@ -304,11 +304,16 @@ double lv_server_now(const lv_server* s);
 lv_status lv_server_submit(lv_server* s, int view_id, const void* u, const void* v, double arrival,
                            uint64_t* ticket);
 /* Launch one round over the views with pending requests (non-blocking;
- * *launched = requests in the round, 0 if none were pending). */
+ * *launched = requests in the round).  At most two rounds are in flight:
+ * one running and one queued behind it on the stream; while both are
+ * there, step launches nothing (*launched = 0) and new requests keep
+ * coalescing in the queues, so each round takes what arrived during the
+ * previous one and the device never waits for the host. */
 lv_status lv_server_step(lv_server* s, int* launched);
 /* Retire finished rounds without waiting; *completed = total applied. */
 lv_status lv_server_poll(lv_server* s, uint64_t* completed);
-/* Wait for every launched round. */
+/* Apply every queued request (launching rounds as room frees up), then wait
+ * for every launched round. */
 lv_status lv_server_drain(lv_server* s);
 lv_status lv_server_stats(const lv_server* s, lv_server_counters* out);
 /* Drain, destroy the views, release host resources (the caller frees the

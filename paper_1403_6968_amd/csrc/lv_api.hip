@@ -144,7 +144,7 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
         if (st == LV_OK)
           st = timed(v, 0, s, "update", [&] {
             return launch_level_update<float>(R, v->P<float>(j), L.ldp, L.n_pad, sU, sV, L.W, s,
-                                              v->shadowed() ? v->shadow(j) : nullptr);
+                                              v->shadowed() ? v->shadow(j) : nullptr, v->shadowed());
           });
         if (st == LV_OK)
           st = timed(v, 1, s, "level tail", [&] {
@@ -168,7 +168,7 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
   }
   const int Rm = r_pad << L.m;
   return timed(v, 2, s, "top update", [&] {
-    return launch_level_update<T>(Rm, v->P<T>(L.m), L.ldp, L.n_pad, sU, sV, L.W, s);
+    return launch_level_update<T>(Rm, v->P<T>(L.m), L.ldp, L.n_pad, sU, sV, L.W, s, nullptr, v->shadowed());
   });
 }
 

@@ -22,12 +22,8 @@ constexpr int kMaxLevel = 10;
 
 inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
-// float -> bfloat16 bits, rounding to nearest even (finite x).
-__device__ __forceinline__ uint16_t bf16_rne(float x) {
-  uint32_t u = __builtin_bit_cast(uint32_t, x);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
+// float -> bfloat16 bits, rounding to nearest even (v_cvt_pk_bf16_f32).
+__device__ __forceinline__ uint16_t bf16_rne(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 
 // Columns covered by one tile of the level pass: a wave reads a 1 KiB row
 // segment with one 16-byte vector per lane.
@@ -99,7 +95,11 @@ inline bool skinny_on_mfma(int R, int elem) { return elem == 4 && R >= kMfmaSkin
 // row tile); otherwise the stand-alone Gram kernel and its sum provide G.
 inline bool gram_in_pass(int R, int elem) { return R <= kMaxFusedRank && !skinny_on_mfma(R, elem); }
 // Work-groups of a tail launch / Gram pairs per work-group for rank R.
-inline int tail_blocks(int64_t n_pad, int R) { return (int)((n_pad * R + 255) / 256); }
+// Level ranks from which the tail works on 64-row x 32-column blocks.
+constexpr int kSlicedTailRank = 64;
+inline int tail_blocks(int64_t n_pad, int R) {
+  return R >= kSlicedTailRank ? (int)(n_pad / 64) * (R / 32) : (int)((n_pad * R + 255) / 256);
+}
 inline int gram_pairs_per_block(int R) {
   const int ppt = (R * R + 255) / 256 < 16 ? (R * R + 255) / 256 : 16;
   return 256 * ppt;
@@ -138,10 +138,12 @@ hipError_t launch_level_tail(int R, const T* partX, const T* partY, const double
 
 // Update-only pass: P += U_j V_j^T for rank R (the top stored power).  With a
 // non-null shadow S (float only) the pass also writes S = bf16(P) of the new
-// values.
+// values.  `split` (float, bfloat16-shadow mode) forms the matrix-core ranks
+// with split bfloat16 operands (three products) instead of float products.
 template <typename T>
 hipError_t launch_level_update(int R, T* P, int64_t ldp, int64_t n_pad, const T* slabU,
-                               const T* slabV, int W, hipStream_t s, uint16_t* S = nullptr);
+                               const T* slabV, int W, hipStream_t s, uint16_t* S = nullptr,
+                               bool split = false);
 
 // Gram V_j^T U_j in double: gram_tiles(n_pad) partials of kGramRows rows,
 // then their sum in fixed order into partG[0 .. R*R).
@@ -185,7 +187,8 @@ hipError_t launch_gram_multi(int R, const GramDesc<T>* ds, int nd, int blocks, h
 template <typename T>
 hipError_t launch_tail_multi(int R, const TailDesc<T>* ds, int nd, int blocks, hipStream_t s);
 template <typename T>
-hipError_t launch_update_multi(int R, bool shadow, const UpdateDesc<T>* ds, int nd, int blocks, hipStream_t s);
+hipError_t launch_update_multi(int R, bool shadow, bool split, const UpdateDesc<T>* ds, int nd, int blocks,
+                               hipStream_t s);
 template <typename T>
 hipError_t launch_prep_multi(const PrepDesc<T>* ds, int nd, int blocks, hipStream_t s);
 

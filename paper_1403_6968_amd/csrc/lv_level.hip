@@ -110,9 +110,29 @@ __global__ void __launch_bounds__(256) k_gram_sum_multi(const GramSumDesc* __res
 }
 
 // ---------------------------------------------------------------- tail
-// One thread per (row, c): the partials of the row tiles / column tiles are
-// loaded in batches of 8 (independent loads in flight) and added in index
-// order; the Gram partials are summed once per block into LDS.
+// Per output (row i, column c): x = sum of the column tiles' partial X and
+// y = sum of the row tiles' partial Y, each added in tile order in double
+// (loads in batches of 8), ug = sum_d U_j[i][d] G[d][c] in double.
+// R < 64: one thread per (row, c), the whole G in LDS.  R >= 64: a block
+// covers 64 rows x a 32-column slice and holds only G's slice (R x 32
+// doubles), each thread 8 rows of one column.  Same sums in the same order
+// either way.
+template <typename T>
+__device__ __forceinline__ double sum_partials(const T* __restrict__ part, const int64_t stride, const int64_t idx,
+                                               const int count) {
+  double x = 0.0;
+  int t = 0;
+  for (; t + 8 <= count; t += 8) {
+    T v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = part[(t + e) * stride + idx];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x += (double)v[e];
+  }
+  for (; t < count; ++t) x += (double)part[t * stride + idx];
+  return x;
+}
+
 template <typename T, int R>
 __device__ __forceinline__ void tail_body(const T* __restrict__ partX, const T* __restrict__ partY,
                                           const double* __restrict__ partG, const int nct, const int nrt,
@@ -121,45 +141,54 @@ __device__ __forceinline__ void tail_body(const T* __restrict__ partX, const T* 
   const T* Ucur = slabU;
   T* Unew = slabU + R;
   T* Vnew = slabV + (W - 2 * R);
-  __shared__ double G[R * R];
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < R * R; idx += 256) {
-    double g = 0.0;
-    for (int t = 0; t < ng; ++t) g += partG[(int64_t)t * R * R + idx];
-    G[idx] = g;
-  }
-  __syncthreads();
-  const int64_t pairs = (int64_t)n_pad * R;
-  const int64_t idx = (int64_t)blk * 256 + tid;
-  if (idx >= pairs) return;
-  const int64_t i = idx / R;
-  const int c = (int)(idx % R);
   const int64_t strideX = (int64_t)n_pad * R;
-  double x = 0.0;
-  int t = 0;
-  for (; t + 8 <= nct; t += 8) {
-    T v[8];
+  if constexpr (R < kSlicedTailRank) {
+    __shared__ double G[R * R];
+    for (int idx = tid; idx < R * R; idx += 256) {
+      double g = 0.0;
+      for (int t = 0; t < ng; ++t) g += partG[(int64_t)t * R * R + idx];
+      G[idx] = g;
+    }
+    __syncthreads();
+    const int64_t pairs = (int64_t)n_pad * R;
+    const int64_t idx = (int64_t)blk * 256 + tid;
+    if (idx >= pairs) return;
+    const int64_t i = idx / R;
+    const int c = (int)(idx % R);
+    const double x = sum_partials(partX, strideX, idx, nct);
+    const double y = sum_partials(partY, strideX, idx, nrt);
+    double ug = 0.0;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = partX[(t + e) * strideX + idx];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) x += (double)v[e];
+    for (int d = 0; d < R; ++d) ug = fma((double)Ucur[i * W + d], G[d * R + c], ug);
+    Unew[i * W + c] = (T)(x + ug);
+    Vnew[i * W + c] = (T)y;
+  } else {
+    constexpr int NS = R / 32;
+    __shared__ double G[R][32];
+    const int rb = blk / NS, cs = blk % NS;
+    const int cl = tid % 32;
+    const int c = cs * 32 + cl;
+    for (int e = tid; e < R * 32; e += 256) {
+      const int d = e / 32, cc = cs * 32 + e % 32;
+      double g = 0.0;
+      for (int t = 0; t < ng; ++t) g += partG[(int64_t)t * R * R + d * R + cc];
+      G[d][e % 32] = g;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int q = 0; q < 8; ++q) {
+      const int64_t i = (int64_t)rb * 64 + tid / 32 + 8 * q;
+      const int64_t idx = i * R + c;
+      const double x = sum_partials(partX, strideX, idx, nct);
+      const double y = sum_partials(partY, strideX, idx, nrt);
+      double ug = 0.0;
+#pragma unroll 8
+      for (int d = 0; d < R; ++d) ug = fma((double)Ucur[i * W + d], G[d][cl], ug);
+      Unew[i * W + c] = (T)(x + ug);
+      Vnew[i * W + c] = (T)y;
+    }
   }
-  for (; t < nct; ++t) x += (double)partX[t * strideX + idx];
-  double y = 0.0;
-  t = 0;
-  for (; t + 8 <= nrt; t += 8) {
-    T v[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = partY[(t + e) * strideX + idx];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) y += (double)v[e];
-  }
-  for (; t < nrt; ++t) y += (double)partY[t * strideX + idx];
-  double ug = 0.0;
-#pragma unroll
-  for (int d = 0; d < R; ++d) ug = fma((double)Ucur[i * W + d], G[d * R + c], ug);
-  Unew[i * W + c] = (T)(x + ug);
-  Vnew[i * W + c] = (T)y;
 }
 
 template <typename T, int R>
@@ -324,25 +353,130 @@ __device__ __forceinline__ void update_mfma_body(float* __restrict__ P, const in
       }
 }
 
-template <typename T, int R, bool SH>
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ float bf16_value(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
+
+// P += U_j V_j^T in the bfloat16-shadow mode for R >= 32, on the bfloat16
+// matrix cores with split operands: x = hi + lo with hi = bf16(x) and
+// lo = bf16(x - hi), and u v ~ hi_u hi_v + hi_u lo_v + lo_u hi_v (three
+// v_mfma_f32_32x32x16_bf16, float accumulation).  The dropped lo_u lo_v and
+// the rounding of lo leave a relative error of about 2^-16 per product.
+// Same tiles, waves and accumulator layout as update_mfma_body; a lane of a
+// 16-column step supplies factor columns 8 (l / 32) + e, e = 0..7, for both
+// operands.
+template <int R, bool SH>
+__device__ __forceinline__ void update_split_body(float* __restrict__ P, const int64_t ldp,
+                                                  const float* __restrict__ Uj, const float* __restrict__ Vj,
+                                                  const int W, uint16_t* __restrict__ S, const int ct, const int rt) {
+  constexpr int TT = kMfmaUpdateTile, KC = 32, KP = KC + 8;
+  static_assert(R % KC == 0, "rank must be a multiple of 32");
+  __shared__ __align__(16) uint16_t sUh[TT][KP], sUl[TT][KP], sVh[TT][KP], sVl[TT][KP];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = wave_id();
+  const int wm = wave >> 1, wn = wave & 1;
+  const int l32 = lane & 31, lh = lane >> 5;
+  const int row0 = rt * TT, col0 = ct * TT;
+
+  float p[2][2][16];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v)
+        p[a][b][v] = P[(int64_t)(row0 + wm * 64 + a * 32 + 8 * (v / 4) + 4 * lh + (v % 4)) * ldp + col0 + wn * 64 +
+                       b * 32 + l32];
+  v16f acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
+
+  for (int kc = 0; kc < R; kc += KC) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < TT * KC / 4 / 256; ++i) {
+      const int q = tid + 256 * i;
+      const int r = q >> 3, c4 = (q & 7) * 4;
+      const float4 u = *reinterpret_cast<const float4*>(Uj + (int64_t)(row0 + r) * W + kc + c4);
+      const float4 w = *reinterpret_cast<const float4*>(Vj + (int64_t)(col0 + r) * W + kc + c4);
+      const float uu[4] = {u.x, u.y, u.z, u.w}, ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint16_t uh = bf16_rne(uu[e]), wh = bf16_rne(ww[e]);
+        sUh[r][c4 + e] = uh;
+        sUl[r][c4 + e] = bf16_rne(uu[e] - bf16_value(uh));
+        sVh[r][c4 + e] = wh;
+        sVl[r][c4 + e] = bf16_rne(ww[e] - bf16_value(wh));
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < KC; ks += 16) {
+      bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        ah[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sUh[wm * 64 + a * 32 + l32][ks + 8 * lh]));
+        al[a] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sUl[wm * 64 + a * 32 + l32][ks + 8 * lh]));
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        bh[b] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sVh[wn * 64 + b * 32 + l32][ks + 8 * lh]));
+        bl[b] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(&sVl[wn * 64 + b * 32 + l32][ks + 8 * lh]));
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+        }
+    }
+  }
+
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t o = (int64_t)(row0 + wm * 64 + a * 32 + 8 * (v / 4) + 4 * lh + (v % 4)) * ldp + col0 +
+                          wn * 64 + b * 32 + l32;
+        const float x = p[a][b][v] + acc[a][b][v];
+        P[o] = x;
+        if constexpr (SH) S[o] = bf16_rne(x);
+      }
+}
+
+// SPLIT selects the split-bfloat16 products (bfloat16-shadow mode) for the
+// matrix-core ranks.
+template <typename T, int R, bool SH, bool SPLIT>
 __device__ __forceinline__ void update_any(const UpdateDesc<T>& d, const int ct, const int rt) {
-  if constexpr (sizeof(T) == 4 && R >= kMfmaUpdateRank)
+  if constexpr (sizeof(T) == 4 && R >= kMfmaUpdateRank && SPLIT)
+    update_split_body<R, SH>(d.P, d.ldp, d.Uj, d.Vj, d.W, d.S, ct, rt);
+  else if constexpr (sizeof(T) == 4 && R >= kMfmaUpdateRank)
     update_mfma_body<R, SH>(d.P, d.ldp, d.Uj, d.Vj, d.W, d.S, ct, rt);
   else
     update_body<T, R, SH>(d.P, d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.S, ct, rt);
 }
 
-template <typename T, int R, bool SH>
+template <typename T, int R, bool SH, bool SPLIT>
 __global__ void __launch_bounds__(256) k_level_update(const UpdateDesc<T> d) {
-  update_any<T, R, SH>(d, blockIdx.x, blockIdx.y);
+  update_any<T, R, SH, SPLIT>(d, blockIdx.x, blockIdx.y);
 }
 
-template <typename T, int R, bool SH>
+template <typename T, int R, bool SH, bool SPLIT>
 __global__ void __launch_bounds__(256) k_level_update_multi(const UpdateDesc<T>* __restrict__ ds, int nd) {
   const int v = find_desc(ds, nd, (int)blockIdx.x);
   const UpdateDesc<T> d = ds[v];
   const int local = (int)blockIdx.x - d.block_begin;
-  update_any<T, R, SH>(d, local % d.nct, local / d.nct);
+  update_any<T, R, SH, SPLIT>(d, local % d.nct, local / d.nct);
 }
 
 // ---------------------------------------------------------------- small kernels
@@ -387,19 +521,24 @@ __global__ void __launch_bounds__(256) k_prep_multi(const PrepDesc<T>* __restric
 
 template <typename T, int R>
 hipError_t update_r(T* P, int64_t ldp, int64_t n_pad, const T* Uj, const T* Vj, int W,
-                    hipStream_t s, uint16_t* S = nullptr) {
+                    hipStream_t s, uint16_t* S, bool split) {
   const int tile_rows = update_tile_rows(R, (int)sizeof(T));
   const int nct = (int)(n_pad / update_tile_cols(R, (int)sizeof(T)));
   const UpdateDesc<T> d{P, ldp, (int)n_pad, tile_rows, Uj, Vj, W, nct, 0, S};
   const dim3 grid((unsigned)nct, (unsigned)((n_pad + tile_rows - 1) / tile_rows));
   if constexpr (sizeof(T) == 4) {
-    if (S != nullptr) {
-      hipLaunchKernelGGL((k_level_update<T, R, true>), grid, dim3(256), 0, s, d);
-      return hipGetLastError();
-    }
+    if (S != nullptr && split)
+      hipLaunchKernelGGL((k_level_update<T, R, true, true>), grid, dim3(256), 0, s, d);
+    else if (S != nullptr)
+      hipLaunchKernelGGL((k_level_update<T, R, true, false>), grid, dim3(256), 0, s, d);
+    else if (split)
+      hipLaunchKernelGGL((k_level_update<T, R, false, true>), grid, dim3(256), 0, s, d);
+    else
+      hipLaunchKernelGGL((k_level_update<T, R, false, false>), grid, dim3(256), 0, s, d);
+    return hipGetLastError();
   }
-  if (S != nullptr) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_level_update<T, R, false>), grid, dim3(256), 0, s, d);
+  if (S != nullptr || split) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_level_update<T, R, false, false>), grid, dim3(256), 0, s, d);
   return hipGetLastError();
 }
 
@@ -451,11 +590,11 @@ hipError_t launch_level_tail(int R, const T* partX, const T* partY, const double
 
 template <typename T>
 hipError_t launch_level_update(int R, T* P, int64_t ldp, int64_t n_pad, const T* slabU,
-                               const T* slabV, int W, hipStream_t s, uint16_t* S) {
+                               const T* slabV, int W, hipStream_t s, uint16_t* S, bool split) {
   const T* Uj = slabU;
   const T* Vj = slabV + (W - R);
-  if (R == 256) return update_r<T, 256>(P, ldp, n_pad, Uj, Vj, W, s, S);
-  LV_RANK_SWITCH(R, return (update_r<T, RR>(P, ldp, n_pad, Uj, Vj, W, s, S)))
+  if (R == 256) return update_r<T, 256>(P, ldp, n_pad, Uj, Vj, W, s, S, split);
+  LV_RANK_SWITCH(R, return (update_r<T, RR>(P, ldp, n_pad, Uj, Vj, W, s, S, split)))
 }
 
 template <typename T>
@@ -486,25 +625,29 @@ hipError_t launch_tail_multi(int R, const TailDesc<T>* ds, int nd, int blocks, h
                  return hipGetLastError())
 }
 
-template <typename T, bool SH>
+template <typename T, bool SH, bool SPLIT>
 hipError_t update_multi_sh(int R, const UpdateDesc<T>* ds, int nd, int blocks, hipStream_t s) {
   if (R == 256) {
-    hipLaunchKernelGGL((k_level_update_multi<T, 256, SH>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd);
+    hipLaunchKernelGGL((k_level_update_multi<T, 256, SH, SPLIT>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd);
     return hipGetLastError();
   }
-  LV_RANK_SWITCH(R, hipLaunchKernelGGL((k_level_update_multi<T, RR, SH>), dim3((unsigned)blocks), dim3(256), 0, s,
-                                       ds, nd);
+  LV_RANK_SWITCH(R, hipLaunchKernelGGL((k_level_update_multi<T, RR, SH, SPLIT>), dim3((unsigned)blocks), dim3(256), 0,
+                                       s, ds, nd);
                  return hipGetLastError())
 }
 
 template <typename T>
-hipError_t launch_update_multi(int R, bool shadow, const UpdateDesc<T>* ds, int nd, int blocks, hipStream_t s) {
+hipError_t launch_update_multi(int R, bool shadow, bool split, const UpdateDesc<T>* ds, int nd, int blocks,
+                               hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   if constexpr (sizeof(T) == 4) {
-    if (shadow) return update_multi_sh<T, true>(R, ds, nd, blocks, s);
+    if (shadow && split) return update_multi_sh<T, true, true>(R, ds, nd, blocks, s);
+    if (shadow) return update_multi_sh<T, true, false>(R, ds, nd, blocks, s);
+    if (split) return update_multi_sh<T, false, true>(R, ds, nd, blocks, s);
+    return update_multi_sh<T, false, false>(R, ds, nd, blocks, s);
   }
-  if (shadow) return hipErrorInvalidValue;
-  return update_multi_sh<T, false>(R, ds, nd, blocks, s);
+  if (shadow || split) return hipErrorInvalidValue;
+  return update_multi_sh<T, false, false>(R, ds, nd, blocks, s);
 }
 
 template <typename T>
@@ -520,12 +663,12 @@ hipError_t launch_prep_multi(const PrepDesc<T>* ds, int nd, int blocks, hipStrea
   template hipError_t launch_level_tail<T>(int, const T*, const T*, const double*, int, int, int, \
                                            int64_t, T*, T*, int, hipStream_t);                    \
   template hipError_t launch_level_update<T>(int, T*, int64_t, int64_t, const T*, const T*, int,  \
-                                             hipStream_t, uint16_t*);                             \
+                                             hipStream_t, uint16_t*, bool);                       \
   template hipError_t launch_level_gram<T>(int, const T*, const T*, int, int64_t, double*,        \
                                            hipStream_t);                                          \
   template hipError_t launch_gram_multi<T>(int, const GramDesc<T>*, int, int, hipStream_t);        \
   template hipError_t launch_tail_multi<T>(int, const TailDesc<T>*, int, int, hipStream_t);        \
-  template hipError_t launch_update_multi<T>(int, bool, const UpdateDesc<T>*, int, int, hipStream_t); \
+  template hipError_t launch_update_multi<T>(int, bool, bool, const UpdateDesc<T>*, int, int, hipStream_t); \
   template hipError_t launch_prep_multi<T>(const PrepDesc<T>*, int, int, hipStream_t);
 LV_INST(float)
 LV_INST(double)

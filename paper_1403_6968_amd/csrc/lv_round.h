@@ -23,7 +23,7 @@
 
 namespace lv {
 
-enum Kind { kPrep, kFused, kChunk, kSkinny, kSkinnyF32, kGram, kGramSum, kUpdate, kUpdateShadow, kTail };
+enum Kind { kPrep, kFused, kChunk, kSkinny, kSkinnyF32, kGram, kGramSum, kUpdate, kUpdateShadow, kUpdateSplit, kTail };
 
 struct LaunchRec {
   Kind kind;
@@ -94,7 +94,7 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
     std::map<int, std::vector<SkinnyDesc>> skinny, skinny32;
     std::map<int, std::vector<GramDesc<T>>> gram;
     std::vector<GramSumDesc> gsum;
-    std::map<int, std::vector<UpdateDesc<T>>> upd, updsh;
+    std::map<int, std::vector<UpdateDesc<T>>> upd, updsh, updsplit;
     std::map<int, std::vector<TailDesc<T>>> tail;
     for (lv_view* v : views) {
       const Layout& L = v->L;
@@ -108,7 +108,8 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
       const int upd_rows = update_tile_rows(R, L.elem);
       const int upd_nct = (int)(L.n_pad / update_tile_cols(R, L.elem));
       if (j == L.m) {
-        upd[R].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, upd_rows, sU, Vj, L.W, upd_nct, 0});
+        (v->shadowed() ? updsplit : upd)[R].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, upd_rows, sU, Vj, L.W,
+                                                       upd_nct, 0});
         continue;
       }
       if constexpr (sizeof(T) == 4) {
@@ -158,6 +159,7 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
     pl.add(kGramSum, 0, gsum, [](const GramSumDesc& d) { return (d.count + 255) / 256; });
     for (auto& kv : upd) pl.add(kUpdate, kv.first, kv.second, &update_blocks<T>);
     for (auto& kv : updsh) pl.add(kUpdateShadow, kv.first, kv.second, &update_blocks<T>);
+    for (auto& kv : updsplit) pl.add(kUpdateSplit, kv.first, kv.second, &update_blocks<T>);
     for (auto& kv : tail) {
       const int R = kv.first;
       pl.add(kTail, R, kv.second, [R](const TailDesc<T>& d) { return tail_blocks(d.n_pad, R); });
@@ -180,9 +182,14 @@ lv_status enqueue_round(const Plan& pl, const char* dbase, hipStream_t s) {
       case kGramSum: e = launch_gram_sum_multi(static_cast<const GramSumDesc*>(d), l.nd, l.blocks, s); break;
       case kSkinnyF32: e = launch_skinny_f32_multi(l.R, static_cast<const SkinnyDesc*>(d), l.nd, l.blocks, s); break;
       case kSkinny: e = launch_skinny_bf16_multi(l.R, static_cast<const SkinnyDesc*>(d), l.nd, l.blocks, s); break;
-      case kUpdate: e = launch_update_multi<T>(l.R, false, static_cast<const UpdateDesc<T>*>(d), l.nd, l.blocks, s); break;
+      case kUpdate:
+        e = launch_update_multi<T>(l.R, false, false, static_cast<const UpdateDesc<T>*>(d), l.nd, l.blocks, s);
+        break;
       case kUpdateShadow:
-        e = launch_update_multi<T>(l.R, true, static_cast<const UpdateDesc<T>*>(d), l.nd, l.blocks, s);
+        e = launch_update_multi<T>(l.R, true, true, static_cast<const UpdateDesc<T>*>(d), l.nd, l.blocks, s);
+        break;
+      case kUpdateSplit:
+        e = launch_update_multi<T>(l.R, false, true, static_cast<const UpdateDesc<T>*>(d), l.nd, l.blocks, s);
         break;
       case kTail: e = launch_tail_multi<T>(l.R, static_cast<const TailDesc<T>*>(d), l.nd, l.blocks, s); break;
     }

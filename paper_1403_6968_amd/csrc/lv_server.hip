@@ -25,6 +25,8 @@ using namespace lv;
 namespace {
 
 constexpr int kRingSlots = 4;
+// Rounds in flight at once: one running, one queued behind it.
+constexpr int kMaxInFlight = 2;
 constexpr size_t kSlotBytes = 1 << 20;
 
 struct Pending {
@@ -140,7 +142,7 @@ int free_slot(lv_server* s) {
   return -1;
 }
 
-lv_status drain(lv_server* s) {
+lv_status wait_all(lv_server* s) {
   while (!s->inflight.empty()) {
     lv_status st = retire(s, true);
     if (st != LV_OK) return st;
@@ -149,10 +151,34 @@ lv_status drain(lv_server* s) {
 }
 
 template <typename T>
+lv_status step_impl(lv_server* s, int* launched);
+
+// Apply every queued request: launch rounds (waiting for room as needed)
+// until the queues are empty, then wait for every round.
+lv_status drain(lv_server* s) {
+  for (;;) {
+    bool pending = false;
+    for (auto& v : s->views) pending = pending || (v.alive && !v.q.empty());
+    if (!pending) break;
+    int launched = 0;
+    lv_status st = s->mode == LV_FP64 ? step_impl<double>(s, &launched) : step_impl<float>(s, &launched);
+    if (st != LV_OK) return st;
+    if (launched == 0) {
+      st = retire(s, true);
+      if (st != LV_OK) return st;
+    }
+  }
+  return wait_all(s);
+}
+
+template <typename T>
 lv_status step_impl(lv_server* s, int* launched) {
   *launched = 0;
   lv_status st = retire(s, false);
   if (st != LV_OK) return st;
+  // continuous batching: one round runs while the next waits behind it on
+  // the stream; further requests keep coalescing in the queues meanwhile
+  if ((int)s->inflight.size() >= kMaxInFlight) return LV_OK;
   std::vector<int> active;
   for (int i = 0; i < (int)s->views.size(); ++i)
     if (s->views[i].alive && !s->views[i].q.empty()) active.push_back(i);
