@@ -1,6 +1,7 @@
 // Batched rounds over many views: one update per view per round, every
 // level step of all views issued as one multi-view launch per level rank
-// (lv_round.h), and the whole round captured once into a HIP graph that each
+// (lv_round.h), the chains of views of different padded rank on parallel
+// stream lanes, and the whole round captured once into a HIP graph that each
 // round replays.  Workspace: per-view input staging (n_pad x r_max for U and
 // for V), then the round's descriptor tables.
 //
@@ -70,6 +71,7 @@ struct lv_batch {
   char* base;
   BatchLayout bl;
   hipStream_t cap = nullptr;
+  Lanes lanes;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -194,6 +196,7 @@ void lv_batch_destroy(lv_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap) (void)hipStreamDestroy(b->cap);
+  b->lanes.destroy();
   delete b;
 }
 
@@ -225,11 +228,12 @@ lv_status lv_batch_create(lv_view* const* views, int count, void* workspace, siz
   if (st == LV_OK) st = mode == LV_FP64 ? autotune<double>(b, s) : autotune<float>(b, s);
   // capture one round on a private stream
   if (st == LV_OK) st = hip_check(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "create capture stream");
+  if (st == LV_OK) st = b->lanes.init();
   if (st == LV_OK) st = hip_check(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed), "begin capture");
   if (st == LV_OK) {
     const char* dbase = b->base + b->bl.stage_bytes;
-    lv_status est = mode == LV_FP64 ? enqueue_round<double>(b->bl.plan, dbase, b->cap)
-                                    : enqueue_round<float>(b->bl.plan, dbase, b->cap);
+    lv_status est = mode == LV_FP64 ? enqueue_round<double>(b->bl.plan, dbase, b->cap, &b->lanes)
+                                    : enqueue_round<float>(b->bl.plan, dbase, b->cap, &b->lanes);
     lv_status cst = hip_check(hipStreamEndCapture(b->cap, &b->graph), "end capture");
     st = est != LV_OK ? est : cst;
   }

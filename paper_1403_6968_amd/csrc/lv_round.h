@@ -1,5 +1,6 @@
 // Round planner shared by batched rounds and the serving loop: for a set of
-// views with one update each, the per-level-step multi-view launches
+// views with one update each, per class of equal padded rank (an independent
+// chain, run on its own stream lane), the per-level-step multi-view launches
 //   prep (update -> factor slab 0, all views)
 //   for j = 0..max_m:
 //     fused passes (R <= 16), one launch per R
@@ -25,8 +26,13 @@ namespace lv {
 
 enum Kind { kPrep, kFused, kChunk, kSkinny, kSkinnyF32, kGram, kGramSum, kUpdate, kUpdateShadow, kUpdateSplit, kTail };
 
+// Views of equal padded rank form a class whose launches depend only on
+// each other; classes run as independent chains on up to kMaxLanes streams.
+constexpr int kMaxLanes = 4;
+
 struct LaunchRec {
   Kind kind;
+  int lane;     // stream lane (class chain) of the launch; the prep is lane 0
   int level;    // level step of the round (-1: prep)
   int R;
   size_t off;   // byte offset of the descriptor array in the descriptor area
@@ -41,6 +47,8 @@ struct Plan {
   std::vector<LaunchRec> launches;
 
   int level = -1;   // level step the next add() belongs to
+  int lane = 0;     // lane the next add() belongs to
+  int lanes = 1;    // lanes used
 
   template <typename D, typename F>
   void add(Kind kind, int R, std::vector<D>& ds, F blocks_of) {
@@ -50,7 +58,7 @@ struct Plan {
     const size_t off = align_up(bytes.size());
     bytes.resize(off + ds.size() * sizeof(D));
     std::memcpy(bytes.data() + off, ds.data(), ds.size() * sizeof(D));
-    launches.push_back({kind, level, R, off, (int)ds.size(), b});
+    launches.push_back({kind, lane, level, R, off, (int)ds.size(), b});
   }
 };
 
@@ -86,8 +94,18 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
     max_m = L.m > max_m ? L.m : max_m;
   }
   pl.add(kPrep, 0, prep, &prep_blocks<T>);
+  (void)max_m;
 
-  for (int j = 0; j <= max_m; ++j) {
+  // one chain of launches per class of equal padded rank, largest first
+  std::map<int, std::vector<lv_view*>, std::greater<int>> classes;
+  for (lv_view* v : views) classes[v->L.r_pad].push_back(v);
+  int ci = 0;
+  for (auto& cls : classes) {
+  pl.lane = ci++ % kMaxLanes;
+  pl.lanes = pl.lane + 1 > pl.lanes ? pl.lane + 1 : pl.lanes;
+  int cmax = 0;
+  for (lv_view* v : cls.second) cmax = v->L.m > cmax ? v->L.m : cmax;
+  for (int j = 0; j <= cmax; ++j) {
     pl.level = j;
     std::map<int, std::vector<FusedDesc<T>>> fused;
     std::vector<FusedDesc<T>> chunks;
@@ -96,7 +114,7 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
     std::vector<GramSumDesc> gsum;
     std::map<int, std::vector<UpdateDesc<T>>> upd, updsh, updsplit;
     std::map<int, std::vector<TailDesc<T>>> tail;
-    for (lv_view* v : views) {
+    for (lv_view* v : cls.second) {
       const Layout& L = v->L;
       if (j > L.m) continue;
       const int R = L.r_pad << j;
@@ -165,14 +183,57 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
       pl.add(kTail, R, kv.second, [R](const TailDesc<T>& d) { return tail_blocks(d.n_pad, R); });
     }
   }
+  }
   return pl;
 }
 
-// Launch a round whose descriptors are at `dbase` on the device.
+// Streams and events for running the lanes of a round concurrently (fork
+// after the prep, join at the end).  Streams at the default priority.
+struct Lanes {
+  hipStream_t s[kMaxLanes] = {};   // s[0] unused: lane 0 runs on the round's stream
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kMaxLanes] = {};
+
+  lv_status init() {
+    for (int i = 1; i < kMaxLanes; ++i)
+      if (hipStreamCreateWithFlags(&s[i], hipStreamNonBlocking) != hipSuccess)
+        return fail(LV_EDEVICE, "lane stream creation failed");
+    if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess)
+      return fail(LV_EDEVICE, "lane event creation failed");
+    for (int i = 0; i < kMaxLanes; ++i)
+      if (hipEventCreateWithFlags(&join[i], hipEventDisableTiming) != hipSuccess)
+        return fail(LV_EDEVICE, "lane event creation failed");
+    return LV_OK;
+  }
+  void destroy() {
+    for (int i = 1; i < kMaxLanes; ++i)
+      if (s[i]) (void)hipStreamDestroy(s[i]);
+    if (fork) (void)hipEventDestroy(fork);
+    for (int i = 0; i < kMaxLanes; ++i)
+      if (join[i]) (void)hipEventDestroy(join[i]);
+  }
+};
+
+// Launch a round whose descriptors are at `dbase` on the device.  With
+// `lanes`, lane i > 0 runs on lanes->s[i] after the prep (fork) and the
+// round's stream waits for every lane at the end (join); without, every
+// launch goes to `s` in plan order.
 template <typename T>
-lv_status enqueue_round(const Plan& pl, const char* dbase, hipStream_t s) {
+lv_status enqueue_round(const Plan& pl, const char* dbase, hipStream_t s0, const Lanes* lanes = nullptr) {
+  const bool par = lanes != nullptr && pl.lanes > 1;
+  bool forked = false;
   for (const LaunchRec& l : pl.launches) {
     const void* d = dbase + l.off;
+    hipStream_t s = s0;
+    if (par && l.kind != kPrep) {
+      if (!forked) {
+        if (hipEventRecord(lanes->fork, s0) != hipSuccess) return fail(LV_EDEVICE, "fork record");
+        for (int i = 1; i < pl.lanes; ++i)
+          if (hipStreamWaitEvent(lanes->s[i], lanes->fork, 0) != hipSuccess) return fail(LV_EDEVICE, "fork wait");
+        forked = true;
+      }
+      if (l.lane > 0) s = lanes->s[l.lane];
+    }
     hipError_t e = hipSuccess;
     switch (l.kind) {
       case kPrep: e = launch_prep_multi<T>(static_cast<const PrepDesc<T>*>(d), l.nd, l.blocks, s); break;
@@ -195,6 +256,12 @@ lv_status enqueue_round(const Plan& pl, const char* dbase, hipStream_t s) {
     }
     lv_status st = hip_check(e, "batch launch");
     if (st != LV_OK) return st;
+  }
+  if (forked) {
+    for (int i = 1; i < pl.lanes; ++i) {
+      if (hipEventRecord(lanes->join[i], lanes->s[i]) != hipSuccess) return fail(LV_EDEVICE, "join record");
+      if (hipStreamWaitEvent(s0, lanes->join[i], 0) != hipSuccess) return fail(LV_EDEVICE, "join wait");
+    }
   }
   return LV_OK;
 }

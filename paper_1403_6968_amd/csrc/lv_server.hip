@@ -62,6 +62,7 @@ struct lv_server {
   size_t arena_bytes;
   int rc;
   hipStream_t stream;
+  Lanes lanes;
   std::vector<std::pair<size_t, size_t>> free_blocks;  // (offset, size), sorted by offset
   std::vector<SView> views;
   std::deque<InFlight> inflight;
@@ -249,7 +250,7 @@ lv_status step_impl(lv_server* s, int* launched) {
   st = hip_check(hipMemcpyAsync(dslot, s->pinned[slot] + desc_pin, pl.bytes.size(), hipMemcpyHostToDevice, s->stream),
                  "upload descriptors");
   if (st != LV_OK) return st;
-  st = enqueue_round<T>(pl, dslot, s->stream);
+  st = enqueue_round<T>(pl, dslot, s->stream, &s->lanes);
   if (st != LV_OK) return st;
   if (hipEventCreateWithFlags(&f.ev, hipEventDisableTiming) != hipSuccess) return fail(LV_EDEVICE, "event create");
   st = hip_check(hipEventRecord(f.ev, s->stream), "event record");
@@ -284,6 +285,12 @@ lv_status lv_server_create(void* arena, size_t arena_bytes, lv_mode mode, int r_
   s->arena_bytes = arena_bytes;
   s->rc = r_coalesce;
   s->stream = static_cast<hipStream_t>(stream);
+  const lv_status lst = s->lanes.init();
+  if (lst != LV_OK) {
+    s->lanes.destroy();
+    delete s;
+    return lst;
+  }
   s->free_blocks.push_back({kRingSlots * kSlotBytes, arena_bytes - kRingSlots * kSlotBytes});
   s->t0 = std::chrono::steady_clock::now();
   *out = s;
@@ -404,6 +411,7 @@ void lv_server_destroy(lv_server* s) {
     if (v.alive) lv_view_destroy(v.view);
   for (int i = 0; i < kRingSlots; ++i)
     if (s->pinned[i]) (void)hipHostFree(s->pinned[i]);
+  s->lanes.destroy();
   delete s;
 }
 
