@@ -18,6 +18,7 @@
 
 #include "lv_view_impl.h"
 
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <vector>
@@ -96,11 +97,29 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
   pl.add(kPrep, 0, prep, &prep_blocks<T>);
   (void)max_m;
 
-  // one chain of launches per class of equal padded rank, largest first
-  std::map<int, std::vector<lv_view*>, std::greater<int>> classes;
-  for (lv_view* v : views) classes[v->L.r_pad].push_back(v);
+  // one chain of launches per class of equal padded rank, largest first;
+  // with fewer classes than lanes, a class is split into parts of about
+  // equal work (sum of n_pad^2 (m + 1)) so that every lane has a chain
+  std::map<int, std::vector<lv_view*>, std::greater<int>> by_rank;
+  for (lv_view* v : views) by_rank[v->L.r_pad].push_back(v);
+  const int nparts = by_rank.size() >= (size_t)kMaxLanes ? 1 : kMaxLanes / (int)by_rank.size();
+  std::vector<std::vector<lv_view*>> groups;
+  for (auto& kv : by_rank) {
+    std::vector<lv_view*> vs = kv.second;
+    std::stable_sort(vs.begin(), vs.end(), [](const lv_view* a, const lv_view* b) { return a->L.n_pad > b->L.n_pad; });
+    const int p = std::min<int>(nparts, (int)vs.size());
+    std::vector<std::vector<lv_view*>> parts(p);
+    std::vector<double> load(p, 0.0);
+    for (lv_view* v : vs) {
+      const int t = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      parts[t].push_back(v);
+      load[t] += (double)v->L.n_pad * v->L.n_pad * (v->L.m + 1);
+    }
+    for (auto& g : parts) groups.push_back(std::move(g));
+  }
   int ci = 0;
-  for (auto& cls : classes) {
+  for (auto& grp : groups) {
+  std::pair<const int, std::vector<lv_view*>> cls{0, grp};
   pl.lane = ci++ % kMaxLanes;
   pl.lanes = pl.lane + 1 > pl.lanes ? pl.lane + 1 : pl.lanes;
   int cmax = 0;
