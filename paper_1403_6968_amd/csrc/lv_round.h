@@ -118,12 +118,11 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
     for (auto& g : parts) groups.push_back(std::move(g));
   }
   int ci = 0;
-  for (auto& grp : groups) {
-  std::pair<const int, std::vector<lv_view*>> cls{0, grp};
+  for (const std::vector<lv_view*>& grp : groups) {
   pl.lane = ci++ % kMaxLanes;
   pl.lanes = pl.lane + 1 > pl.lanes ? pl.lane + 1 : pl.lanes;
   int cmax = 0;
-  for (lv_view* v : cls.second) cmax = v->L.m > cmax ? v->L.m : cmax;
+  for (lv_view* v : grp) cmax = v->L.m > cmax ? v->L.m : cmax;
   for (int j = 0; j <= cmax; ++j) {
     pl.level = j;
     std::map<int, std::vector<FusedDesc<T>>> fused;
@@ -133,7 +132,7 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
     std::vector<GramSumDesc> gsum;
     std::map<int, std::vector<UpdateDesc<T>>> upd, updsh, updsplit;
     std::map<int, std::vector<TailDesc<T>>> tail;
-    for (lv_view* v : cls.second) {
+    for (lv_view* v : grp) {
       const Layout& L = v->L;
       if (j > L.m) continue;
       const int R = L.r_pad << j;
