@@ -28,3 +28,8 @@ from .linview_oracle import (  # noqa: F401
     deltarel,
     OpCounter,
 )
+from .sums_oracle import (  # noqa: F401
+    reeval_sums,
+    incr_sums_factors,
+    incr_update_sums,
+)
