@@ -116,6 +116,26 @@ lv_status lv_view_create(const void* A, int64_t n, int64_t lda, int k, int r_max
                          lv_mode mode, void* workspace, size_t ws_bytes,
                          void* stream, lv_view** out);
 
+/* Creation flags.
+ *  LV_WITH_SUMS  also maintain the sums of powers S_i = I + A + ... + A^(i-1)
+ *                for i in {1, 2, 4, ..., k} (Sec. 5.3, Table 1, exponential
+ *                model: S_1 = I, S_{2i} = P_i S_i + S_i).  Every update then
+ *                also applies the factored deltas Delta S_i = Q_i W_i^T,
+ *                obtained from the old powers and sums by the delta rule of
+ *                Sec. 4.1:  Q_{2i} = [U_i, P_i Q_i + Q_i],
+ *                W_{2i} = [S_i^T V_i + W_i (Q_i^T V_i), W_i],  Q_1 = W_1 = 0
+ *                (U_i, V_i the factors of Delta P_i).  Creation and
+ *                re-anchoring evaluate the sums by the recurrence in double
+ *                precision and round once.  Such views are single-view only
+ *                (lv_batch_create and servers reject them). */
+#define LV_WITH_SUMS 1
+
+/* lv_view_footprint / lv_view_create with creation flags (0 = as those). */
+size_t lv_view_footprint_ex(int64_t n, int k, int r_max, lv_mode mode, int flags);
+lv_status lv_view_create_ex(const void* A, int64_t n, int64_t lda, int k, int r_max,
+                            lv_mode mode, int flags, void* workspace, size_t ws_bytes,
+                            void* stream, lv_view** out);
+
 /* Apply one update Delta A = U V^T (IncrExp, App. A exponential model; the
  * trigger of Sec. 4.4).
  *  U, V      n x r (device), leading dimensions ldu, ldv >= r.
@@ -136,6 +156,11 @@ lv_status lv_view_update_batch(lv_view* v, const void* U, const void* V, int64_t
  * leading dimension ldo >= n, device). */
 lv_status lv_view_read(const lv_view* v, int power, void* out, int64_t ldo, void* stream);
 
+/* Copy the stored sum S_index (index in {1, 2, 4, ..., k}; S_1 = I) of a
+ * view created with LV_WITH_SUMS to out (n x n, ld ldo >= n, device).
+ * LV_ESTATE for a view without sums. */
+lv_status lv_view_read_sum(const lv_view* v, int index, void* out, int64_t ldo, void* stream);
+
 /* Borrowed device pointer to stored power A^power and its leading
  * dimension (written to *ld if ld is non-null); NULL if power is not
  * stored.  Valid until the next update, re-anchor or destroy. */
@@ -150,7 +175,8 @@ lv_status lv_view_reanchor(lv_view* v, void* stream);
  * A^power: restores a checkpoint written with lv_view_read, or lets a test
  * perturb a stored power (its bfloat16 shadow, if any, is rewritten).  The
  * caller is responsible for consistency of the chain afterwards (see
- * lv_view_drift_check). */
+ * lv_view_drift_check); stored sums are not changed (lv_view_reanchor
+ * re-evaluates powers and sums from the stored A). */
 lv_status lv_view_write(lv_view* v, int power, const void* src, int64_t lds, void* stream);
 
 /* Drift check of the stored chain (the exponential model defines

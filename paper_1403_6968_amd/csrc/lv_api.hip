@@ -34,20 +34,48 @@ namespace {
 template <typename T>
 lv_status build_chain(lv_view* v, hipStream_t s, const int* gate = nullptr) {
   const Layout& L = v->L;
+  const int64_t cnt = L.n_pad * L.ldp;
+  if (L.sums) {
+    // S_1 = I (Sec. 5.3, Table 1)
+    lv_status st = hip_check(launch_set_identity<T>(v->S<T>(0), L.ldp, v->n, L.n_pad, s, gate), "S_1 = I");
+    if (st != LV_OK) return st;
+  }
   if (L.m == 0) return LV_OK;
   if constexpr (sizeof(T) == 8) {
     for (int j = 1; j <= L.m; ++j) {
       lv_status st = hip_check(launch_gemm<double>(v->P<double>(j - 1), L.ldp, v->P<double>(j - 1), L.ldp,
                                                    v->P<double>(j), L.ldp, L.n_pad, s, gate), "gemm f64");
       if (st != LV_OK) return st;
+      if (L.sums) {
+        // S_{2i} = P_i S_i + S_i
+        st = hip_check(launch_gemm<double>(v->P<double>(j - 1), L.ldp, v->S<double>(j - 1), L.ldp, v->S<double>(j),
+                                           L.ldp, L.n_pad, s, gate), "gemm f64 (sums)");
+        if (st == LV_OK) st = hip_check(launch_add<double>(v->S<double>(j), v->S<double>(j - 1), cnt, s, gate), "S add");
+        if (st != LV_OK) return st;
+      }
     }
   } else {
     lv_status st = hip_check(launch_copy_pad<float, double>(v->P<float>(0), L.ldp, L.n_pad, v->scratch(0),
                                                             L.n_pad, L.n_pad, s, gate), "widen P_1");
+    if (st == LV_OK && L.sums)
+      st = hip_check(launch_set_identity<double>(v->sscratch(0), L.n_pad, v->n, L.n_pad, s, gate), "S_1 = I (f64)");
     if (st != LV_OK) return st;
     for (int j = 1; j <= L.m; ++j) {
       double* src = v->scratch((j - 1) & 1);
       double* dst = v->scratch(j & 1);
+      if (L.sums) {
+        // S_{2i} = P_i S_i + S_i in double from the double P_i, rounded once
+        double* scur = v->sscratch((j - 1) & 1);
+        double* snew = v->sscratch(j & 1);
+        st = hip_check(launch_gemm<double>(src, L.n_pad, scur, L.n_pad, snew, L.n_pad, L.n_pad, s, gate),
+                       "gemm f64 (sums)");
+        if (st == LV_OK) st = hip_check(launch_add<double>(snew, scur, (int64_t)L.n_pad * L.n_pad, s, gate), "S add");
+        if (st == LV_OK)
+          st = hip_check(launch_copy_pad<double, float>(snew, L.n_pad, L.n_pad, v->S<float>(j), L.ldp, L.n_pad, s,
+                                                        gate),
+                         "round S");
+        if (st != LV_OK) return st;
+      }
       st = hip_check(launch_gemm<double>(src, L.n_pad, src, L.n_pad, dst, L.n_pad, L.n_pad, s, gate),
                      "gemm f64");
       if (st != LV_OK) return st;
@@ -110,6 +138,40 @@ lv_status timed(lv_view* v, int kind, hipStream_t s, const char* what, F&& launc
   return LV_OK;
 }
 
+// Sums of powers, level j after the powers' level step (the powers' partials
+// of level j are consumed, so the double path may write its unused X there):
+// Y_s = S_j^T V_j with the OLD S_j, G_s = Q_j^T V_j, S_j += Q_j W_j^T, and the
+// sums tail (Q_{j+1}, W_{j+1}).  Level 0 has Q_0 = 0 and S_0 = I: only the
+// tail runs.
+template <typename T>
+lv_status sums_level(lv_view* v, int j, int R, const T* sU, const T* sV, hipStream_t s) {
+  const Layout& L = v->L;
+  lv_status st = LV_OK;
+  if (j > 0) {
+    st = timed(v, 0, s, "sums: S^T V", [&] {
+      if constexpr (sizeof(T) == 4)
+        return launch_skinny_f32(R, v->S<float>(j), L.ldp, L.n_pad, v->tile_rows[j], v->slabQ<float>(), sV, L.W,
+                                 v->partXs<float>(j), v->partYs<float>(j), s, kWantY);
+      else
+        return launch_level_readonly<T>(R, v->S<T>(j), L.ldp, L.n_pad, v->tile_rows[j], v->slabQ<T>(),
+                                        sV + (L.W - R), L.W, v->partX<T>(j), v->partYs<T>(j), s);
+    });
+    if (st == LV_OK)
+      st = timed(v, 0, s, "sums: gram", [&] {
+        return launch_gram_cols<T>(R, sV + (L.W - R), v->slabQ<T>(), L.W, L.n_pad, v->partGs(j), s);
+      });
+    if (st == LV_OK)
+      st = timed(v, 0, s, "sums: update", [&] {
+        return launch_level_update<T>(R, v->S<T>(j), L.ldp, L.n_pad, v->slabQ<T>(), v->slabW<T>(), L.W, s);
+      });
+    if (st != LV_OK) return st;
+  }
+  return timed(v, 1, s, "sums: tail", [&] {
+    return launch_sums_tail<T>(R, v->partXs<T>(j), v->partYs<T>(j), v->partGs(j), L.nct, v->nrt(j), L.n_pad,
+                               v->slabQ<T>(), v->slabW<T>(), sU, sV, L.W, j == 0, s);
+  });
+}
+
 // One update through every level, factors in slab `sl` (App. A exponential
 // model; trigger of Sec. 4.4): levels 0..m-1 run the fused pass and the tail
 // (or, for float storage at large level rank and with bfloat16 shadows, the
@@ -126,6 +188,18 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
   if (st != LV_OK) return st;
   for (int j = 0; j < L.m; ++j) {
     const int R = r_pad << j;
+    if (L.sums && j > 0) {
+      // sums: X_s = P_j Q_j with the OLD P_j, before this level's update
+      st = timed(v, 0, s, "sums: P Q", [&] {
+        if constexpr (sizeof(T) == 4)
+          return launch_skinny_f32(R, v->P<float>(j), L.ldp, L.n_pad, v->tile_rows[j], v->slabQ<float>(), sV, L.W,
+                                   v->partXs<float>(j), v->partYs<float>(j), s, kWantX);
+        else
+          return launch_level_readonly<T>(R, v->P<T>(j), L.ldp, L.n_pad, v->tile_rows[j], v->slabQ<T>(),
+                                          sV + (L.W - R), L.W, v->partXs<T>(j), v->partYs<T>(j), s);
+      });
+      if (st != LV_OK) return st;
+    }
     if constexpr (sizeof(T) == 4) {
       if (v->shadowed() || skinny_on_mfma(R, 4)) {
         // read-only skinny pass on the matrix cores (from the shadow, or from
@@ -151,6 +225,7 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
             return launch_level_tail<float>(R, v->partX<float>(j), v->partY<float>(j), v->partG(j), L.nct, v->nrt(j),
                                             1, L.n_pad, sU, sV, L.W, s);
           });
+        if (st == LV_OK && L.sums) st = sums_level<T>(v, j, R, sU, sV, s);
         if (st != LV_OK) return st;
         continue;
       }
@@ -164,12 +239,18 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
       return launch_level_tail<T>(R, v->partX<T>(j), v->partY<T>(j), v->partG(j), L.nct, v->nrt(j),
                                   gram_in_pass(R, (int)sizeof(T)) ? v->nrt(j) : 1, L.n_pad, sU, sV, L.W, s);
     });
+    if (st == LV_OK && L.sums) st = sums_level<T>(v, j, R, sU, sV, s);
     if (st != LV_OK) return st;
   }
   const int Rm = r_pad << L.m;
-  return timed(v, 2, s, "top update", [&] {
+  st = timed(v, 2, s, "top update", [&] {
     return launch_level_update<T>(Rm, v->P<T>(L.m), L.ldp, L.n_pad, sU, sV, L.W, s, nullptr, v->shadowed());
   });
+  if (st == LV_OK && L.sums && L.m > 0)
+    st = timed(v, 2, s, "sums: top update", [&] {
+      return launch_level_update<T>(Rm, v->S<T>(L.m), L.ldp, L.n_pad, v->slabQ<T>(), v->slabW<T>(), L.W, s);
+    });
+  return st;
 }
 
 // ---------------------------------------------------------------- re-evaluation
@@ -225,23 +306,33 @@ const char* lv_status_str(lv_status s) {
 
 const char* lv_last_error(void) { return g_err; }
 
+size_t lv_view_footprint_ex(int64_t n, int k, int r_max, lv_mode mode, int flags) {
+  if (check_shape(n, k, r_max, mode) != LV_OK || (flags & ~LV_WITH_SUMS) != 0) return 0;
+  return make_layout(n, k, r_max, mode, flags).total;
+}
+
 size_t lv_view_footprint(int64_t n, int k, int r_max, lv_mode mode) {
-  if (check_shape(n, k, r_max, mode) != LV_OK) return 0;
-  return make_layout(n, k, r_max, mode).total;
+  return lv_view_footprint_ex(n, k, r_max, mode, 0);
 }
 
 lv_status lv_view_create(const void* A, int64_t n, int64_t lda, int k, int r_max, lv_mode mode,
                          void* workspace, size_t ws_bytes, void* stream, lv_view** out) {
+  return lv_view_create_ex(A, n, lda, k, r_max, mode, 0, workspace, ws_bytes, stream, out);
+}
+
+lv_status lv_view_create_ex(const void* A, int64_t n, int64_t lda, int k, int r_max, lv_mode mode, int flags,
+                            void* workspace, size_t ws_bytes, void* stream, lv_view** out) {
   g_err[0] = 0;
   if (!out) return fail(LV_EINVAL, "out is NULL");
   *out = nullptr;
   lv_status st = check_shape(n, k, r_max, mode);
   if (st != LV_OK) return st;
+  if ((flags & ~LV_WITH_SUMS) != 0) return fail(LV_EINVAL, "unknown creation flags 0x%x", flags);
   if (!A || !workspace) return fail(LV_EINVAL, "A or workspace is NULL");
   if (lda < n) return fail(LV_EINVAL, "lda = %lld < n = %lld", (long long)lda, (long long)n);
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
     return fail(LV_ENOMEM, "workspace is not %zu-byte aligned", kAlign);
-  const Layout L = make_layout(n, k, r_max, mode);
+  const Layout L = make_layout(n, k, r_max, mode, flags);
   if (ws_bytes < L.total)
     return fail(LV_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
   lv_view* v = new (std::nothrow) lv_view();
@@ -251,6 +342,14 @@ lv_status lv_view_create(const void* A, int64_t n, int64_t lda, int k, int r_max
   v->updates = 0; v->reanchors = 0;
   for (int j = 0; j < kMaxLevel; ++j) v->tile_rows[j] = L.tile_rows;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (L.sums) {
+    // the sum factor slabs start at zero: the W columns of level 0 are read as
+    // W_0 = 0 and are never written afterwards
+    st = hip_check(hipMemsetAsync(v->base + L.slabQ, 0, L.slabW - L.slabQ, s), "clear Q slab");
+    if (st == LV_OK)
+      st = hip_check(hipMemsetAsync(v->base + L.slabW, 0, (size_t)L.n_pad * L.W * L.elem, s), "clear W slab");
+    if (st != LV_OK) { delete v; return st; }
+  }
   if (mode == LV_FP64) {
     st = hip_check(launch_copy_pad<double, double>(static_cast<const double*>(A), lda, n, v->P<double>(0),
                                                    L.ldp, L.n_pad, s), "copy A");
@@ -329,6 +428,19 @@ lv_status lv_view_read(const lv_view* v, int power, void* out, int64_t ldo, void
   return hip_check(hipMemcpy2DAsync(out, ldo * es, src, v->L.ldp * es, v->n * es, v->n,
                                     hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)),
                    "read");
+}
+
+lv_status lv_view_read_sum(const lv_view* v, int index, void* out, int64_t ldo, void* stream) {
+  g_err[0] = 0;
+  const int j = power_level(v, index);
+  if (j < 0) return fail(LV_EINVAL, "sum index %d is not stored", index);
+  if (!v->L.sums) return fail(LV_ESTATE, "the view was created without LV_WITH_SUMS");
+  if (!out) return fail(LV_EINVAL, "out is NULL");
+  if (ldo < v->n) return fail(LV_EINVAL, "ldo < n");
+  const size_t es = v->L.elem;
+  return hip_check(hipMemcpy2DAsync(out, ldo * es, v->base + v->L.S[j], v->L.ldp * es, v->n * es, v->n,
+                                    hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)),
+                   "read sum");
 }
 
 const void* lv_view_data(const lv_view* v, int power, int64_t* ld) {

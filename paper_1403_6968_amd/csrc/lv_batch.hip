@@ -29,8 +29,10 @@ namespace {
 
 lv_status check_views(lv_view* const* views, int count, lv_mode* mode) {
   if (!views || count < 1) return fail(LV_EINVAL, "need at least one view");
-  for (int i = 0; i < count; ++i)
+  for (int i = 0; i < count; ++i) {
     if (!views[i]) return fail(LV_EINVAL, "view %d is NULL", i);
+    if (views[i]->L.sums) return fail(LV_EINVAL, "view %d maintains sums of powers: not supported in batches", i);
+  }
   *mode = views[0]->mode;
   for (int i = 1; i < count; ++i)
     if (views[i]->mode != *mode) return fail(LV_EINVAL, "views of different modes in one batch");

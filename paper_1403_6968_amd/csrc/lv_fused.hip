@@ -307,6 +307,34 @@ hipError_t launch_fused_multi(int R, bool chunk, const FusedDesc<T>* ds, int nd,
   return hipGetLastError();
 }
 
+// Read-only pass: partial X = P Uop and Y = P^T Vop for R columns (row
+// stride R), P unchanged: the fused kernel without its update and Gram, in
+// 16-column chunks above 16.
+template <typename T>
+hipError_t launch_level_readonly(int R, const T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* Uop,
+                                 const T* Vop, int W, T* partX, T* partY, hipStream_t s) {
+  T* Pm = const_cast<T*>(P);   // not written: UPD = false
+  switch (R) {
+    case 1: return fused_launch<T, 1, 16, false>(Pm, ldp, n_pad, tile_rows, Uop, Vop, W, partX, partY, nullptr, R, s);
+    case 2: return fused_launch<T, 2, 16, false>(Pm, ldp, n_pad, tile_rows, Uop, Vop, W, partX, partY, nullptr, R, s);
+    case 4: return fused_launch<T, 4, 16, false>(Pm, ldp, n_pad, tile_rows, Uop, Vop, W, partX, partY, nullptr, R, s);
+    case 8: return fused_launch<T, 8, 8, false>(Pm, ldp, n_pad, tile_rows, Uop, Vop, W, partX, partY, nullptr, R, s);
+    default: break;
+  }
+  if (R % kMaxFusedRank != 0 || R > 128) return hipErrorInvalidValue;
+  for (int c0 = 0; c0 < R; c0 += kMaxFusedRank) {
+    const hipError_t e = fused_launch<T, kMaxFusedRank, 8, false>(Pm, ldp, n_pad, tile_rows, Uop + c0, Vop + c0, W,
+                                                                  partX + c0, partY + c0, nullptr, R, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template hipError_t launch_level_readonly<float>(int, const float*, int64_t, int64_t, int, const float*, const float*,
+                                                 int, float*, float*, hipStream_t);
+template hipError_t launch_level_readonly<double>(int, const double*, int64_t, int64_t, int, const double*,
+                                                  const double*, int, double*, double*, hipStream_t);
+
 template hipError_t launch_level_fused<float>(int, float*, int64_t, int64_t, int, const float*, const float*, int,
                                               float*, float*, double*, hipStream_t);
 template hipError_t launch_level_fused<double>(int, double*, int64_t, int64_t, int, const double*, const double*,

@@ -60,6 +60,8 @@ template <typename T> struct UpdateDesc {
   int nct; int block_begin;             // blocks: nct x ceil(n_pad / tile_rows)
   uint16_t* S;                          // bfloat16 shadow of P rewritten by the pass, or null
 };
+// Products a read-only skinny pass forms.
+constexpr int kWantX = 1, kWantY = 2;
 // Read-only skinny products of a level on the matrix cores, from the
 // bfloat16 shadow of P or from P itself (float): X = P U_j and Y = P^T V_j
 // for R columns of the factors (partials with row stride pR, as FusedDesc).
@@ -68,6 +70,7 @@ struct SkinnyDesc {
   const float* Uj; const float* Vj; int W; int R;
   float* partX; float* partY; int pR;
   int nct; int block_begin;             // blocks: nct x ceil(n_pad / tile_rows)
+  int want = kWantX | kWantY;           // products formed (float pass only)
 };
 template <typename T> struct PrepDesc {
   const T* U; int64_t ldu; const T* V; int64_t ldv; int64_t n; int r; int r_pad;
@@ -166,7 +169,7 @@ inline int skinny_blocks_for(int R) { return R <= 32 ? 1 : R <= 64 ? 2 : 4; }
 // products and accumulation), R <= 128 (64 factor columns per launch).
 hipError_t launch_skinny_f32(int R, const float* P, int64_t ldp, int64_t n_pad, int tile_rows,
                              const float* slabU, const float* slabV, int W, float* partX, float* partY,
-                             hipStream_t s);
+                             hipStream_t s, int want = kWantX | kWantY);
 hipError_t launch_skinny_f32_multi(int nb, const SkinnyDesc* ds, int nd, int blocks, hipStream_t s);
 // Factor blocks of 32 columns per float skinny launch, and launches for R.
 inline int skinny_f32_blocks(int R) { return R <= 32 ? 1 : 2; }
@@ -176,6 +179,29 @@ inline int skinny_f32_launches(int R) { return R <= 64 ? 1 : R / 64; }
 // non-null gate only when *gate != 0.
 hipError_t launch_to_bf16(const float* P, uint16_t* S, int64_t count, hipStream_t s,
                           const int* gate = nullptr);
+
+// ---- sums of powers (views with LV_WITH_SUMS)
+
+// Read-only pass: partial X = P Uop, Y = P^T Vop for R columns (row stride
+// R), P unchanged (fused kernel without its update).
+template <typename T>
+hipError_t launch_level_readonly(int R, const T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* Uop,
+                                 const T* Vop, int W, T* partX, T* partY, hipStream_t s);
+// G = Vop^T Uop (R x R, double) into partG[0 .. R*R), operands given by
+// their first columns (row stride W).
+template <typename T>
+hipError_t launch_gram_cols(int R, const T* Uop, const T* Vop, int W, int64_t n_pad, double* partG, hipStream_t s);
+// Factors of the next level's sums (see k_sums_tail): Q_{j+1} = [U_j, X + Q_j],
+// W_{j+1} = [Y + W_j G, W_j]; `first` for level 0 (Q_0 = 0, S_0 = I).
+template <typename T>
+hipError_t launch_sums_tail(int R, const T* partX, const T* partY, const double* G, int nct, int nrt, int64_t n_pad,
+                            T* slabQ, T* slabW, const T* slabU, const T* slabV, int W, bool first, hipStream_t s);
+// S = I (n x n identity, zero padding to n_pad); dst += src (count elements).
+// With a non-null gate only when *gate != 0.
+template <typename T>
+hipError_t launch_set_identity(T* S, int64_t ld, int64_t n, int64_t n_pad, hipStream_t s, const int* gate = nullptr);
+template <typename T>
+hipError_t launch_add(T* dst, const T* src, int64_t count, hipStream_t s, const int* gate = nullptr);
 
 // Multi-view launches over device descriptor arrays (nd descriptors,
 // `blocks` work-groups in total).  `chunk` selects the read-only skinny pass

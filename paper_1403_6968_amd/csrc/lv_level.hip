@@ -204,6 +204,73 @@ __global__ void __launch_bounds__(256) k_level_tail_multi(const TailDesc<T>* __r
                   (int)blockIdx.x - d.block_begin);
 }
 
+// ---------------------------------------------------------------- sums tail
+// Factors of the sums for the next level (sums of powers, exponential
+// model): Q_{j+1} = [U_j, X + Q_j], W_{j+1} = [Y + W_j G, W_j] with
+// X = P_j Q_j, Y = S_j^T V_j (partials) and G = Q_j^T V_j (summed).  Q_j
+// occupies columns [0, R) of the Q slab and is replaced by U_j in place
+// (each thread reads its own entry before writing it); W_j = columns
+// [W - R, W) of the W slab.  At level 0 (first): Q_0 = 0, S_0 = I, so
+// X = 0, Y = V_0 and W_0 G = 0.
+template <typename T, int R>
+__device__ __forceinline__ void sums_tail_body(const T* __restrict__ partX, const T* __restrict__ partY,
+                                               const double* __restrict__ G, const int nct, const int nrt,
+                                               const int n_pad, T* slabQ, T* slabW, const T* __restrict__ Uj,
+                                               const T* __restrict__ Vj, const int W, const int first,
+                                               const int blk) {
+  __shared__ double Gs[R * R];
+  const int tid = threadIdx.x;
+  if (!first) {
+    for (int idx = tid; idx < R * R; idx += 256) Gs[idx] = G[idx];
+    __syncthreads();
+  }
+  const int64_t idx = (int64_t)blk * 256 + tid;
+  if (idx >= (int64_t)n_pad * R) return;
+  const int64_t i = idx / R;
+  const int c = (int)(idx % R);
+  const int64_t strideX = (int64_t)n_pad * R;
+  double x = 0.0, y, wg = 0.0;
+  T q = T(0);
+  if (first) {
+    y = (double)Vj[i * W + c];
+  } else {
+    x = sum_partials(partX, strideX, idx, nct);
+    y = sum_partials(partY, strideX, idx, nrt);
+    const T* Wj = slabW + (W - R);
+#pragma unroll
+    for (int d = 0; d < R; ++d) wg = fma((double)Wj[i * W + d], Gs[d * R + c], wg);
+    q = slabQ[i * W + c];
+  }
+  slabQ[i * W + R + c] = (T)(x + (double)q);
+  slabQ[i * W + c] = Uj[i * W + c];
+  slabW[i * W + (W - 2 * R) + c] = (T)(y + wg);
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(256)
+k_sums_tail(const T* partX, const T* partY, const double* G, int nct, int nrt, int n_pad, T* slabQ, T* slabW,
+            const T* Uj, const T* Vj, int W, int first) {
+  sums_tail_body<T, R>(partX, partY, G, nct, nrt, n_pad, slabQ, slabW, Uj, Vj, W, first, blockIdx.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_set_identity(T* __restrict__ S, int64_t ld, int64_t n, int64_t n_pad, const int* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
+  const int64_t i = blockIdx.x;
+  const int64_t j = (int64_t)blockIdx.y * 256 + threadIdx.x;
+  if (j >= n_pad) return;
+  S[i * ld + j] = (i == j && i < n) ? T(1) : T(0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_add(T* __restrict__ dst, const T* __restrict__ src, int64_t count, const int* __restrict__ gate) {
+  if (gate != nullptr && *gate == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < count) dst[i] += src[i];
+}
+
 // ---------------------------------------------------------------- update only
 // P += U_j V_j^T.  Lane holds a 16-byte column group; the wave walks batches
 // of 8 rows with U_j rows broadcast through the scalar unit; ranks above 16
@@ -612,6 +679,36 @@ hipError_t launch_gram_multi(int R, const GramDesc<T>* ds, int nd, int blocks, h
                  return hipGetLastError())
 }
 
+template <typename T>
+hipError_t launch_gram_cols(int R, const T* Uop, const T* Vop, int W, int64_t n_pad, double* partG, hipStream_t s) {
+  LV_RANK_SWITCH(R, return (gram_r<T, RR>(Uop, Vop, W, n_pad, partG, s)))
+}
+
+template <typename T>
+hipError_t launch_sums_tail(int R, const T* partX, const T* partY, const double* G, int nct, int nrt, int64_t n_pad,
+                            T* slabQ, T* slabW, const T* slabU, const T* slabV, int W, bool first, hipStream_t s) {
+  const T* Uj = slabU;
+  const T* Vj = slabV + (W - R);
+  const dim3 grid((unsigned)((n_pad * R + 255) / 256));
+  LV_RANK_SWITCH(R, hipLaunchKernelGGL((k_sums_tail<T, RR>), grid, dim3(256), 0, s, partX, partY, G, nct, nrt,
+                                       (int)n_pad, slabQ, slabW, Uj, Vj, W, first ? 1 : 0);
+                 return hipGetLastError())
+}
+
+template <typename T>
+hipError_t launch_set_identity(T* S, int64_t ld, int64_t n, int64_t n_pad, hipStream_t s, const int* gate) {
+  hipLaunchKernelGGL((k_set_identity<T>), dim3((unsigned)n_pad, (unsigned)((n_pad + 255) / 256)), dim3(256), 0, s, S,
+                     ld, n, n_pad, gate);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_add(T* dst, const T* src, int64_t count, hipStream_t s, const int* gate) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_add<T>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, dst, src, count, gate);
+  return hipGetLastError();
+}
+
 hipError_t launch_gram_sum_multi(const GramSumDesc* ds, int nd, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_gram_sum_multi, dim3((unsigned)blocks), dim3(256), 0, s, ds, nd);
@@ -669,7 +766,12 @@ hipError_t launch_prep_multi(const PrepDesc<T>* ds, int nd, int blocks, hipStrea
   template hipError_t launch_gram_multi<T>(int, const GramDesc<T>*, int, int, hipStream_t);        \
   template hipError_t launch_tail_multi<T>(int, const TailDesc<T>*, int, int, hipStream_t);        \
   template hipError_t launch_update_multi<T>(int, bool, bool, const UpdateDesc<T>*, int, int, hipStream_t); \
-  template hipError_t launch_prep_multi<T>(const PrepDesc<T>*, int, int, hipStream_t);
+  template hipError_t launch_prep_multi<T>(const PrepDesc<T>*, int, int, hipStream_t);                    \
+  template hipError_t launch_gram_cols<T>(int, const T*, const T*, int, int64_t, double*, hipStream_t);    \
+  template hipError_t launch_sums_tail<T>(int, const T*, const T*, const double*, int, int, int64_t, T*, T*, \
+                                          const T*, const T*, int, bool, hipStream_t);                     \
+  template hipError_t launch_set_identity<T>(T*, int64_t, int64_t, int64_t, hipStream_t, const int*);      \
+  template hipError_t launch_add<T>(T*, const T*, int64_t, hipStream_t, const int*);
 LV_INST(float)
 LV_INST(double)
 #undef LV_INST

@@ -205,12 +205,14 @@ __global__ void __launch_bounds__(256) k_skinny_bf16_multi(const SkinnyDesc* __r
 //   Y: as the bfloat16 kernel, wave w owns tile columns [64 w, 64 w + 64).
 // A group of four f32 steps covers 8 summation indices: lanes 0-31 supply
 // index g + e and lanes 32-63 index g + 4 + e in step e, for both operands.
+// `want` selects the products formed (bit 0: X, bit 1: Y; uniform).
 template <int NB>
 __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, const int64_t ldp, const int n_pad,
                                                 const int tile_rows, const float* __restrict__ Uj,
                                                 const float* __restrict__ Vj, const int W, const int R,
                                                 float* __restrict__ partX, float* __restrict__ partY,
-                                                const int pR, const int ct, const int rt) {
+                                                const int pR, const int want, const int ct, const int rt) {
+  const bool wx = (want & kWantX) != 0, wy = (want & kWantY) != 0;
   constexpr int RP = 32 * NB;
   constexpr int CR = 32;           // rows per chunk
   constexpr int FP = 4;            // LDS row padding (floats)
@@ -245,10 +247,11 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
   };
   fetch(row0);
 
-  for (int idx = tid; idx < RP * TCB; idx += 256) {
-    const int k = idx / RP, c = idx % RP;
-    sUt[c][k] = c < R ? Uj[(int64_t)(col0 + k) * W + c] : 0.f;
-  }
+  if (wx)
+    for (int idx = tid; idx < RP * TCB; idx += 256) {
+      const int k = idx / RP, c = idx % RP;
+      sUt[c][k] = c < R ? Uj[(int64_t)(col0 + k) * W + c] : 0.f;
+    }
 
   v16f yacc[NB][2];
 #pragma unroll
@@ -275,7 +278,7 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
 #pragma unroll
       for (int v = 0; v < 16; ++v) xacc[nb][v] = 0.f;
 #pragma unroll
-    for (int g = 0; g < 64; g += 8) {
+    for (int g = 0; g < (wx ? 64 : 0); g += 8) {
       const int k0 = wave * 64 + g + 4 * lh;
       const f32x4 a = *reinterpret_cast<const f32x4*>(&sP[l32][k0]);
 #pragma unroll
@@ -290,7 +293,7 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
 
     // Y^T += V_chunk^T P_chunk
 #pragma unroll
-    for (int g = 0; g < CR; g += 8) {
+    for (int g = 0; g < (wy ? CR : 0); g += 8) {
       const int r0 = g + 4 * lh;
 #pragma unroll
       for (int cbi = 0; cbi < 2; ++cbi) {
@@ -307,6 +310,7 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
       }
     }
 
+    if (!wx) continue;
     // exchange the X partials (sP is no longer read in this chunk)
     __syncthreads();
 #pragma unroll
@@ -328,6 +332,7 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
     }
   }
 
+  if (!wy) return;
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
@@ -344,7 +349,7 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
 template <int NB>
 __global__ void __launch_bounds__(256) k_skinny_f32(const SkinnyDesc d) {
   skinny_f32_body<NB>(static_cast<const float*>(d.src), d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.R,
-                      d.partX, d.partY, d.pR, blockIdx.x, blockIdx.y);
+                      d.partX, d.partY, d.pR, d.want, blockIdx.x, blockIdx.y);
 }
 
 template <int NB>
@@ -352,7 +357,7 @@ __global__ void __launch_bounds__(256) k_skinny_f32_multi(const SkinnyDesc* __re
   const SkinnyDesc d = ds[find_skinny(ds, nd, (int)blockIdx.x)];
   const int local = (int)blockIdx.x - d.block_begin;
   skinny_f32_body<NB>(static_cast<const float*>(d.src), d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.R,
-                      d.partX, d.partY, d.pR, local % d.nct, local / d.nct);
+                      d.partX, d.partY, d.pR, d.want, local % d.nct, local / d.nct);
 }
 
 __global__ void __launch_bounds__(256)
@@ -396,7 +401,7 @@ hipError_t launch_skinny_bf16_multi(int nb, const SkinnyDesc* ds, int nd, int bl
 
 hipError_t launch_skinny_f32(int R, const float* P, int64_t ldp, int64_t n_pad, int tile_rows,
                              const float* slabU, const float* slabV, int W, float* partX, float* partY,
-                             hipStream_t s) {
+                             hipStream_t s, int want) {
   if (R < 1 || R > 128 || (R > 64 && R % 64 != 0) || n_pad % TCB != 0 || tile_rows % 32 != 0)
     return hipErrorInvalidValue;
   const int nct = (int)(n_pad / TCB);
@@ -404,7 +409,8 @@ hipError_t launch_skinny_f32(int R, const float* P, int64_t ldp, int64_t n_pad, 
   const float* Vj = slabV + (W - R);
   const int per = R <= 64 ? R : 64;
   for (int c0 = 0; c0 < R; c0 += per) {
-    const SkinnyDesc d{P, ldp, (int)n_pad, tile_rows, slabU + c0, Vj + c0, W, per, partX + c0, partY + c0, R, nct, 0};
+    const SkinnyDesc d{P, ldp, (int)n_pad, tile_rows, slabU + c0, Vj + c0, W, per, partX + c0, partY + c0, R, nct, 0,
+                       want};
     if (skinny_f32_blocks(per) == 1)
       hipLaunchKernelGGL((k_skinny_f32<1>), grid, dim3(256), 0, s, d);
     else

@@ -40,6 +40,16 @@ struct Layout {
   size_t partG[kMaxLevel] = {};
   size_t shadow[kMaxLevel] = {};   // bfloat16 copies of P_0..P_{m-1} (LV_FP32_BF16SHADOW)
   size_t scratch[2] = {};
+  // sums of powers (LV_WITH_SUMS): S_1 = I, S_2, ..., S_k, their factor
+  // slabs Q (prefix columns) and W (suffix columns), per-level partials of
+  // P_j Q_j, S_j^T V_j and the Gram Q_j^T V_j, FP64 squaring scratch
+  bool sums = false;
+  size_t S[kMaxLevel + 1] = {};
+  size_t slabQ = 0, slabW = 0;
+  size_t partXs[kMaxLevel] = {};
+  size_t partYs[kMaxLevel] = {};
+  size_t partGs[kMaxLevel] = {};
+  size_t sscratch[2] = {};
   size_t probe = 0;  // zpad | Pz (m+1 vectors) | PPz (m vectors) | residuals | gate | counter
   size_t total = 0;
 };
@@ -56,8 +66,9 @@ inline lv_status check_shape(int64_t n, int k, int r_max, lv_mode mode) {
   return LV_OK;
 }
 
-inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode) {
+inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode, int flags = 0) {
   lv::Layout L;
+  L.sums = (flags & LV_WITH_SUMS) != 0;
   L.elem = mode == LV_FP64 ? 8 : 4;
   L.n_pad = round_up(n, kPadOrder);
   L.ldp = L.n_pad;
@@ -88,6 +99,22 @@ inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode) {
     const size_t dmat = (size_t)L.n_pad * L.n_pad * sizeof(double);
     L.scratch[0] = off; off = align_up(off + dmat);
     L.scratch[1] = off; off = align_up(off + dmat);
+  }
+  if (L.sums) {
+    for (int j = 0; j <= L.m; ++j) { L.S[j] = off; off = align_up(off + mat); }
+    L.slabQ = off; off = align_up(off + slab);
+    L.slabW = off; off = align_up(off + slab);
+    for (int j = 0; j < L.m; ++j) {
+      const size_t R = (size_t)L.r_pad << j;
+      L.partXs[j] = off; off = align_up(off + (size_t)L.nct * L.n_pad * R * L.elem);
+      L.partYs[j] = off; off = align_up(off + (size_t)L.nrt_max * L.n_pad * R * L.elem);
+      L.partGs[j] = off; off = align_up(off + (size_t)gram_tiles(L.n_pad) * R * R * sizeof(double));
+    }
+    if (mode != LV_FP64 && L.m > 0) {
+      const size_t dmat = (size_t)L.n_pad * L.n_pad * sizeof(double);
+      L.sscratch[0] = off; off = align_up(off + dmat);
+      L.sscratch[1] = off; off = align_up(off + dmat);
+    }
   }
   L.probe = off;
   off = align_up(off + (size_t)(2 * L.m + 2) * L.n_pad * sizeof(double) + kMaxLevel * sizeof(double) + 256);
@@ -131,6 +158,13 @@ struct lv_view {
   template <typename T> T* partX(int j) const { return reinterpret_cast<T*>(base + L.partX[j]); }
   template <typename T> T* partY(int j) const { return reinterpret_cast<T*>(base + L.partY[j]); }
   double* partG(int j) const { return reinterpret_cast<double*>(base + L.partG[j]); }
+  template <typename T> T* S(int j) const { return reinterpret_cast<T*>(base + L.S[j]); }
+  template <typename T> T* slabQ() const { return reinterpret_cast<T*>(base + L.slabQ); }
+  template <typename T> T* slabW() const { return reinterpret_cast<T*>(base + L.slabW); }
+  template <typename T> T* partXs(int j) const { return reinterpret_cast<T*>(base + L.partXs[j]); }
+  template <typename T> T* partYs(int j) const { return reinterpret_cast<T*>(base + L.partYs[j]); }
+  double* partGs(int j) const { return reinterpret_cast<double*>(base + L.partGs[j]); }
+  double* sscratch(int i) const { return reinterpret_cast<double*>(base + L.sscratch[i]); }
   uint16_t* shadow(int j) const { return reinterpret_cast<uint16_t*>(base + L.shadow[j]); }
   bool shadowed() const { return mode == LV_FP32_BF16SHADOW; }
   double* scratch(int i) const { return reinterpret_cast<double*>(base + L.scratch[i]); }

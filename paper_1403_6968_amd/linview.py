@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "liblinview.so")
 
 LV_OK, LV_EINVAL, LV_ENOMEM, LV_EDEVICE, LV_ESTATE = 0, 1, 2, 3, 4
 LV_FP64, LV_FP32, LV_FP32_BF16SHADOW = 0, 1, 2
+LV_WITH_SUMS = 1
 
 _MODE_DTYPE = {LV_FP64: torch.float64, LV_FP32: torch.float32, LV_FP32_BF16SHADOW: torch.float32}
 
@@ -34,6 +35,7 @@ EXPORTED = (
     "lv_batch_destroy", "lv_server_create", "lv_server_view_bytes", "lv_server_add_view",
     "lv_server_remove_view", "lv_server_view", "lv_server_now", "lv_server_submit", "lv_server_step",
     "lv_view_tile_rows", "lv_view_set_tile_rows", "lv_batch_tuning",
+    "lv_view_footprint_ex", "lv_view_create_ex", "lv_view_read_sum",
     "lv_server_poll", "lv_server_drain", "lv_server_stats", "lv_server_destroy",
 )
 
@@ -124,6 +126,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "lv_view_tile_rows": (I32, [P, I32, c.POINTER(I32)]),
         "lv_view_set_tile_rows": (I32, [P, I32, I32]),
         "lv_batch_tuning": (I32, [P, c.POINTER(I32), c.POINTER(I32)]),
+        "lv_view_footprint_ex": (SZ, [I64, I32, I32, I32, I32]),
+        "lv_view_create_ex": (I32, [P, I64, I64, I32, I32, I32, I32, P, SZ, P, c.POINTER(P)]),
+        "lv_view_read_sum": (I32, [P, I32, P, I64, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -168,12 +173,12 @@ def lv_last_error() -> str:
     return load().lv_last_error().decode()
 
 
-def lv_view_footprint(n: int, k: int, r_max: int, mode: int) -> int:
-    return int(load().lv_view_footprint(n, k, r_max, mode))
+def lv_view_footprint(n: int, k: int, r_max: int, mode: int, flags: int = 0) -> int:
+    return int(load().lv_view_footprint_ex(n, k, r_max, mode, flags))
 
 
 def lv_view_create(A: torch.Tensor, k: int, r_max: int, mode: int, workspace: torch.Tensor,
-                   stream=None) -> ctypes.c_void_p:
+                   stream=None, flags: int = 0) -> ctypes.c_void_p:
     lib = load()
     a, lda = _mat(A, _MODE_DTYPE[mode], "A")
     if A.shape[0] != A.shape[1]:
@@ -181,9 +186,9 @@ def lv_view_create(A: torch.Tensor, k: int, r_max: int, mode: int, workspace: to
     if workspace.device.type != "cuda" or not workspace.is_contiguous():
         raise ValueError("workspace must be a contiguous device tensor")
     h = ctypes.c_void_p()
-    _check(lib.lv_view_create(a, A.shape[0], lda, k, r_max, mode, workspace.data_ptr(),
-                              workspace.numel() * workspace.element_size(),
-                              _stream(stream, A.device), ctypes.byref(h)))
+    _check(lib.lv_view_create_ex(a, A.shape[0], lda, k, r_max, mode, flags, workspace.data_ptr(),
+                                 workspace.numel() * workspace.element_size(),
+                                 _stream(stream, A.device), ctypes.byref(h)))
     return h
 
 
@@ -305,7 +310,7 @@ class View:
     """A view of A^k whose workspace is a torch device tensor."""
 
     def __init__(self, A: torch.Tensor, k: int, r_max: int = 1, mode: int | None = None,
-                 stream=None):
+                 stream=None, sums: bool = False):
         if mode is None:
             mode = LV_FP64 if A.dtype == torch.float64 else LV_FP32
         self.mode = mode
@@ -313,13 +318,14 @@ class View:
         self.n = A.shape[0]
         self.k = k
         self.device = A.device
-        nbytes = lv_view_footprint(self.n, k, r_max, mode)
+        self.flags = LV_WITH_SUMS if sums else 0
+        nbytes = lv_view_footprint(self.n, k, r_max, mode, self.flags)
         if nbytes == 0:
             # Reproduce the library's validation message.
-            _check(load().lv_view_create(None, self.n, self.n, k, r_max, mode, None, 0, None,
-                                         ctypes.byref(ctypes.c_void_p())))
+            _check(load().lv_view_create_ex(None, self.n, self.n, k, r_max, mode, self.flags, None, 0, None,
+                                            ctypes.byref(ctypes.c_void_p())))
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
-        self.handle = lv_view_create(A, k, r_max, mode, self.workspace, stream)
+        self.handle = lv_view_create(A, k, r_max, mode, self.workspace, stream, self.flags)
 
     def update(self, U: torch.Tensor, V: torch.Tensor, stream=None) -> None:
         lv_view_update(self.handle, U, V, self.dtype, stream)
@@ -331,6 +337,13 @@ class View:
         power = self.k if power is None else power
         out = torch.empty(self.n, self.n, dtype=self.dtype, device=self.device)
         lv_view_read(self.handle, power, out, self.dtype, stream)
+        return out
+
+    def read_sum(self, index: int | None = None, stream=None) -> torch.Tensor:
+        """Stored sum S_index = I + A + ... + A^(index - 1) (views with sums)."""
+        index = self.k if index is None else index
+        out = torch.empty(self.n, self.n, dtype=self.dtype, device=self.device)
+        _check(load().lv_view_read_sum(self.handle, index, out.data_ptr(), out.stride(0), _stream(stream, self.device)))
         return out
 
     def reanchor(self, stream=None) -> None:
