@@ -50,7 +50,7 @@ def parse():
     p.add_argument("--no-secondary", action="store_true",
                    help="skip the rank-4, batched and serving workloads")
     p.add_argument("--serve-seconds", type=float, default=2.0)
-    p.add_argument("--only", choices=["rank4", "batched", "serving"],
+    p.add_argument("--only", choices=["rank4", "batched", "serving", "sums"],
                    help="run one secondary workload alone and print its result (for profilers)")
     return p.parse_args()
 
@@ -84,6 +84,34 @@ def bench_rank4(torch, lv, synth, dev, steps=40):
                     "level_passes_ms": tm["fused_ms"], "tails_ms": tm["tail_ms"], "top_update_ms": tm["top_ms"]}
     del A
     return out
+
+
+def bench_sums(torch, lv, synth, dev, steps=200):
+    """A^16 view with its sums of powers S_1..S_16 (LV_WITH_SUMS), n = 8192,
+    FP32, rank-1 updates: updates/s and algorithmic HBM bytes per update
+    (powers: one read and write of each stored power; sums: P_j and S_j read
+    once more and S_j read and written for j = 1..3, S_16 read and written)."""
+    n, k = 8192, 16
+    A = torch.from_numpy(synth.gaussian_matrix(n, seed=0, config=2).astype(np.float32)).to(dev)
+    U, V = synth.update_factors(n, 1, steps + 5, seed=0, config=2)
+    Ud = torch.from_numpy(U.astype(np.float32)).to(dev)
+    Vd = torch.from_numpy(V.astype(np.float32)).to(dev)
+    view = lv.View(A, k, sums=True)
+    del A
+    view.update_batch(Ud[:5], Vd[:5])
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    view.update_batch(Ud[5:], Vd[5:])
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    n_pad = view.stats()["n_pad"]
+    view.close()
+    alg = (40 + 56) * n_pad * n_pad
+    return {"workload": "A^16 and sums of powers S_1..S_16, n=8192, FP32, rank-1 updates",
+            "ms_per_update": ms, "updates_per_s": 1000.0 / ms, "alg_bytes_per_update": alg,
+            "alg_GBps": alg / (ms * 1e-3) / 1e9}
 
 
 def bench_batched(torch, lv, synth, dev, rounds=30):
@@ -246,7 +274,8 @@ def main():
     if args.only:
         fn = {"rank4": lambda: bench_rank4(torch, lv, synth, dev),
               "batched": lambda: bench_batched(torch, lv, synth, dev),
-              "serving": lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds)}[args.only]
+              "serving": lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds),
+              "sums": lambda: bench_sums(torch, lv, synth, dev)}[args.only]
         print(json.dumps({"only": args.only, "result": fn()}), flush=True)
         return
     n, k, r = args.n, args.k, args.rank
@@ -408,6 +437,7 @@ def main():
     if not args.quick and not args.no_secondary:
         sec = {}
         for name, fn in (("rank4_n16384", lambda: bench_rank4(torch, lv, synth, dev)),
+                         ("sums_n8192", lambda: bench_sums(torch, lv, synth, dev)),
                          ("batched_64_views", lambda: bench_batched(torch, lv, synth, dev)),
                          ("serving_32_views", lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds)),
                          ("serving_32_views_fp32",

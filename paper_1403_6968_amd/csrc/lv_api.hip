@@ -139,7 +139,9 @@ lv_status timed(lv_view* v, int kind, hipStream_t s, const char* what, F&& launc
 }
 
 // Sums of powers, level j after the powers' level step (the powers' partials
-// of level j are consumed, so the double path may write its unused X there):
+// of level j are consumed, so a pass may write its unused X there).  The
+// read-only passes run on the float matrix cores from rank 16 up, else on
+// the fused vector kernel without its update:
 // Y_s = S_j^T V_j with the OLD S_j, G_s = Q_j^T V_j, S_j += Q_j W_j^T, and the
 // sums tail (Q_{j+1}, W_{j+1}).  Level 0 has Q_0 = 0 and S_0 = I: only the
 // tail runs.
@@ -149,12 +151,12 @@ lv_status sums_level(lv_view* v, int j, int R, const T* sU, const T* sV, hipStre
   lv_status st = LV_OK;
   if (j > 0) {
     st = timed(v, 0, s, "sums: S^T V", [&] {
-      if constexpr (sizeof(T) == 4)
-        return launch_skinny_f32(R, v->S<float>(j), L.ldp, L.n_pad, v->tile_rows[j], v->slabQ<float>(), sV, L.W,
-                                 v->partXs<float>(j), v->partYs<float>(j), s, kWantY);
-      else
-        return launch_level_readonly<T>(R, v->S<T>(j), L.ldp, L.n_pad, v->tile_rows[j], v->slabQ<T>(),
-                                        sV + (L.W - R), L.W, v->partX<T>(j), v->partYs<T>(j), s);
+      if (skinny_on_mfma(R, (int)sizeof(T)))
+        return launch_skinny_f32(R, reinterpret_cast<const float*>(v->S<T>(j)), L.ldp, L.n_pad, v->tile_rows[j],
+                                 v->slabQ<float>(), reinterpret_cast<const float*>(sV), L.W,
+                                 reinterpret_cast<float*>(v->partX<T>(j)), v->partYs<float>(j), s, kWantY);
+      return launch_level_readonly<T>(R, v->S<T>(j), L.ldp, L.n_pad, v->tile_rows[j], v->slabQ<T>(),
+                                      sV + (L.W - R), L.W, v->partX<T>(j), v->partYs<T>(j), s);
     });
     if (st == LV_OK)
       st = timed(v, 0, s, "sums: gram", [&] {
@@ -191,12 +193,12 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
     if (L.sums && j > 0) {
       // sums: X_s = P_j Q_j with the OLD P_j, before this level's update
       st = timed(v, 0, s, "sums: P Q", [&] {
-        if constexpr (sizeof(T) == 4)
-          return launch_skinny_f32(R, v->P<float>(j), L.ldp, L.n_pad, v->tile_rows[j], v->slabQ<float>(), sV, L.W,
-                                   v->partXs<float>(j), v->partYs<float>(j), s, kWantX);
-        else
-          return launch_level_readonly<T>(R, v->P<T>(j), L.ldp, L.n_pad, v->tile_rows[j], v->slabQ<T>(),
-                                          sV + (L.W - R), L.W, v->partXs<T>(j), v->partYs<T>(j), s);
+        if (skinny_on_mfma(R, (int)sizeof(T)))
+          return launch_skinny_f32(R, reinterpret_cast<const float*>(v->P<T>(j)), L.ldp, L.n_pad, v->tile_rows[j],
+                                   v->slabQ<float>(), reinterpret_cast<const float*>(sV), L.W, v->partXs<float>(j),
+                                   v->partYs<float>(j), s, kWantX);
+        return launch_level_readonly<T>(R, v->P<T>(j), L.ldp, L.n_pad, v->tile_rows[j], v->slabQ<T>(),
+                                        sV + (L.W - R), L.W, v->partXs<T>(j), v->partYs<T>(j), s);
       });
       if (st != LV_OK) return st;
     }
