@@ -33,3 +33,7 @@ from .sums_oracle import (  # noqa: F401
     incr_sums_factors,
     incr_update_sums,
 )
+from .general_oracle import (  # noqa: F401
+    reeval_general,
+    incr_update_general,
+)

@@ -46,8 +46,8 @@ __device__ __forceinline__ bf16x8 lds8(const uint16_t* p) {
 }
 
 // Tile: tile_rows x 256 columns of S, walked in chunks of 64 rows through
-// LDS; the next chunk of S and of V_j is held in registers while the
-// current one is used.
+// LDS; the next chunk or two of S and of V_j are held in registers while
+// the current one is used.
 // Factor columns are padded with zeros to 32 NB.
 //   X: per chunk, the 2 NB (row half, factor block) 32 x 32 outputs are
 //      shared round-robin by the 4 waves, K = the tile's 256 columns; one
@@ -78,9 +78,13 @@ __device__ __forceinline__ void skinny_body(const uint16_t* __restrict__ S, cons
   const int srow = tid / 32, sgrp = tid % 32;
 
   constexpr int VPT = RP * CRB / 256;   // V_j values staged per thread and chunk
-  u16x8 pre[CRB / 8];
-  float pv[VPT];
-  auto fetch = [&](const int r0) {
+  // NB = 1: two chunks in flight, buffers A and B alternating (a tile has an
+  // even number of chunks: tile_rows and n_pad are multiples of 2 CRB);
+  // larger NB: one chunk (the accumulators need the registers)
+  constexpr int DEPTH = NB == 1 ? 2 : 1;
+  u16x8 preA[CRB / 8], preB[CRB / 8];
+  float pvA[VPT], pvB[VPT];
+  auto fetch = [&](u16x8 (&pre)[CRB / 8], float (&pv)[VPT], const int r0) {
 #pragma unroll
     for (int i = 0; i < CRB / 8; ++i)
       pre[i] = *reinterpret_cast<const u16x8*>(S + (int64_t)(r0 + srow + 8 * i) * ldp + col0 + sgrp * 8);
@@ -91,7 +95,8 @@ __device__ __forceinline__ void skinny_body(const uint16_t* __restrict__ S, cons
       pv[i] = c < R ? Vj[(int64_t)(r0 + rr) * W + c] : 0.f;
     }
   };
-  fetch(row0);
+  fetch(preA, pvA, row0);
+  if constexpr (DEPTH == 2) fetch(preB, pvB, row0 + CRB);
 
   // U_j rows of the tile's columns, transposed: sUt[c][k] = U_j[col0 + k][c]
   for (int idx = tid; idx < RP * TCB; idx += 256) {
@@ -107,7 +112,7 @@ __device__ __forceinline__ void skinny_body(const uint16_t* __restrict__ S, cons
 #pragma unroll
       for (int v = 0; v < 16; ++v) yacc[a][b][v] = 0.f;
 
-  for (int cr0 = row0; cr0 < rend; cr0 += CRB) {
+  auto chunk = [&](u16x8 (&pre)[CRB / 8], float (&pv)[VPT], const int cr0) {
     __syncthreads();   // the previous chunk is no longer read
 #pragma unroll
     for (int i = 0; i < CRB / 8; ++i) *reinterpret_cast<u16x8*>(&sS[srow + 8 * i][sgrp * 8]) = pre[i];
@@ -117,7 +122,7 @@ __device__ __forceinline__ void skinny_body(const uint16_t* __restrict__ S, cons
       sVt[idx % RP][idx / RP] = bf16_rne(pv[i]);
     }
     __syncthreads();
-    if (cr0 + CRB < rend) fetch(cr0 + CRB);
+    if (cr0 + DEPTH * CRB < rend) fetch(pre, pv, cr0 + DEPTH * CRB);
 
     // X rows of the chunk
     for (int t = wave; t < 2 * NB; t += 4) {
@@ -155,6 +160,15 @@ __device__ __forceinline__ void skinny_body(const uint16_t* __restrict__ S, cons
                                                                    yacc[nbr][cbi], 0, 0, 0);
       }
     }
+  };
+
+  if constexpr (DEPTH == 2) {
+    for (int cr0 = row0; cr0 < rend; cr0 += 2 * CRB) {
+      chunk(preA, pvA, cr0);
+      chunk(preB, pvB, cr0 + CRB);
+    }
+  } else {
+    for (int cr0 = row0; cr0 < rend; cr0 += CRB) chunk(preA, pvA, cr0);
   }
 
 #pragma unroll

@@ -1,0 +1,119 @@
+"""Pins of the general-form oracle (T_{i+1} = A T_i + B, Sec. 5.4, Table 1)
+against facts other than itself: the plain iteration T_{i+1} = A T_i + B
+run step by step (exact rationals on integers, and in floating point), the
+B = 0 case T_k = A^k T_0, the unrolled identity T_k = A^k T_0 + S_k B, the
+hybrid deltas against re-evaluation, and planted mistakes."""
+
+from __future__ import annotations
+
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+
+def _frac(M):
+    M = np.asarray(M, dtype=np.float64)
+    assert np.all(M == np.round(M))
+    return np.array([[Fraction(int(x)) for x in row] for row in M], dtype=object)
+
+
+def _iterate(Af, T0f, Bf, k):
+    """T_1 .. T_k by the plain iteration, in exact rationals."""
+    out, T = {}, T0f
+    for i in range(1, k + 1):
+        T = Af.dot(T) + Bf
+        out[i] = T
+    return out
+
+
+def _case(n, p, seed):
+    A = synth.integer_matrix((n, n), -1, 1, seed=seed)
+    T0 = synth.integer_matrix((n, p), -2, 2, seed=seed, tag=3)
+    B = synth.integer_matrix((n, p), -2, 2, seed=seed, tag=4)
+    return A, T0, B
+
+
+@pytest.mark.parametrize("n,p,k", [(3, 1, 1), (4, 2, 4), (4, 3, 8), (5, 1, 16)])
+def test_reeval_general_exact_iteration(n, p, k):
+    A, T0, B = _case(n, p, 30 + n + k)
+    T = O.reeval_general(A, T0, B, k)
+    ref = _iterate(_frac(A), _frac(T0), _frac(B), k)
+    for i in T:
+        assert (_frac(T[i]) == ref[i]).all(), i
+
+
+def test_reeval_general_zero_b_is_power_times_t0():
+    A = synth.gaussian_matrix(30, seed=31)
+    T0 = synth.rng(31, 0, 5).standard_normal((30, 4))
+    T = O.reeval_general(A, T0, np.zeros((30, 4)), 16)
+    P = O.reeval(A, 16)
+    assert max(np.abs(T[i] - P[i] @ T0).max() for i in T) < 1e-13
+
+
+def test_reeval_general_unrolled_identity():
+    A = synth.gaussian_matrix(40, seed=32)
+    g = synth.rng(32, 0, 5)
+    T0, B = g.standard_normal((40, 3)), g.standard_normal((40, 3))
+    k = 16
+    T, P, S = O.reeval_general(A, T0, B, k), O.reeval(A, k), O.reeval_sums(A, k)
+    assert np.abs(T[k] - (P[k] @ T0 + S[k] @ B)).max() < 1e-12
+
+
+def _exact_incr(fn, n, p, k, r, seed):
+    A, T0, B = _case(n, p, seed)
+    U = synth.integer_matrix((n, r), -1, 1, seed=seed, tag=1)
+    V = synth.integer_matrix((n, r), -1, 1, seed=seed, tag=2)
+    P, S, T = O.reeval(A, k), O.reeval_sums(A, k), O.reeval_general(A, T0, B, k)
+    _, _, Tn = fn(P, S, T, T0, B, U, V)
+    ref = _iterate(_frac(A + U @ V.T), _frac(T0), _frac(B), k)
+    return all((_frac(Tn[i]) == ref[i]).all() for i in Tn)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_incr_general_exact(seed):
+    assert _exact_incr(O.incr_update_general, n=4, p=1 + seed % 3, k=8, r=1 + seed % 2, seed=seed)
+
+
+def test_incr_general_many_updates():
+    n, p, k, T_ = 25, 3, 16, 6
+    A = synth.gaussian_matrix(n, seed=33)
+    g = synth.rng(33, 0, 5)
+    T0, B = g.standard_normal((n, p)), g.standard_normal((n, p))
+    Us, Vs = synth.update_factors(n, 2, T_, seed=33)
+    P, S, T = O.reeval(A, k), O.reeval_sums(A, k), O.reeval_general(A, T0, B, k)
+    for t in range(T_):
+        P, S, T = O.incr_update_general(P, S, T, T0, B, Us[t], Vs[t])
+    R = O.reeval_general(A + np.einsum("tir,tjr->ij", Us, Vs), T0, B, k)
+    assert max(O.maxrel(T[i], R[i]) for i in R) < 1e-12
+
+
+def _mutant(kind):
+    def fn(P, S, T, T0, B, U, V):
+        dQ, dW, dU, dV = O.incr_sums_factors(P, S, U, V)
+        D = {1: U @ (V.T @ T0)}
+        for i in O.levels(max(P))[1:]:
+            h = i // 2
+            Th = T[h] if kind == "old_t" else T[h] + D[h]
+            term_p = P[h] @ D[h]
+            if kind == "new_power":
+                term_p = (P[h] + dU[h] @ dV[h].T) @ D[h]
+            term_s = dQ[h] @ (dW[h].T @ B)
+            if kind == "drop_sums":
+                term_s = 0
+            D[i] = term_p + dU[h] @ (dV[h].T @ Th) + term_s
+        return P, S, {i: T[i] + D[i] for i in T}
+    return fn
+
+
+@pytest.mark.parametrize("kind", ["old_t", "new_power", "drop_sums"])
+def test_general_pins_catch_planted_mistakes(kind):
+    caught = not all(_exact_incr(_mutant(kind), n=4, p=2, k=8, r=1 + s % 2, seed=s) for s in range(4))
+    assert caught, kind
+
+
+def test_general_unmutated_copy_passes():
+    assert all(_exact_incr(_mutant("none"), n=4, p=2, k=8, r=1 + s % 2, seed=s) for s in range(4))
