@@ -161,6 +161,35 @@ lv_status lv_view_read(const lv_view* v, int power, void* out, int64_t ldo, void
  * LV_ESTATE for a view without sums. */
 lv_status lv_view_read_sum(const lv_view* v, int index, void* out, int64_t ldo, void* stream);
 
+/* General iterative form T_{i+1} = A T_i + B (Sec. 5.4 and Table 1,
+ * exponential model: T_1 = A T_0 + B, T_{2i} = P_i T_i + S_i B), T_i and B
+ * n x p.  A view created here stores T_1, T_2, T_4, ..., T_k beside the
+ * powers and the sums (it implies LV_WITH_SUMS) and keeps them current
+ * under lv_view_update / lv_view_update_batch by hybrid evaluation
+ * (Sec. 5.4): the change of each T_i is one dense n x p matrix D_i, taken
+ * from the old values by the delta rule of Sec. 4.1 (the factored form of
+ * App. B, multiplied out):
+ *     D_1 = U (V^T T_0),
+ *     D_{2i} = P_i D_i + U_i (V_i^T (T_i + D_i)) + Q_i (W_i^T B)
+ * with Delta P_i = U_i V_i^T and Delta S_i = Q_i W_i^T.  T_0 and B are fixed.
+ * Creation and re-anchoring evaluate every T_i by the recurrence in double
+ * precision from the double powers and sums and round once.
+ *  p        1 <= p <= 64 (padded to a power of two in the workspace).
+ *  T0, B    n x p (device, element type of the mode), leading dimensions
+ *           ldt, ldb >= p; copied into the workspace, not retained.
+ * Other arguments, ownership and errors as lv_view_create; the footprint
+ * is 0 for invalid arguments.  Such views are single-view only. */
+size_t lv_view_footprint_general(int64_t n, int k, int r_max, lv_mode mode, int64_t p);
+lv_status lv_view_create_general(const void* A, int64_t n, int64_t lda, int k, int r_max,
+                                 lv_mode mode, const void* T0, int64_t ldt, const void* B,
+                                 int64_t ldb, int64_t p, void* workspace, size_t ws_bytes,
+                                 void* stream, lv_view** out);
+
+/* Copy stored T_index (index in {1, 2, 4, ..., k}) of a general-form view to
+ * out (n x p, leading dimension ldo >= p, device).  LV_ESTATE for a view
+ * created otherwise. */
+lv_status lv_view_read_general(const lv_view* v, int index, void* out, int64_t ldo, void* stream);
+
 /* Borrowed device pointer to stored power A^power and its leading
  * dimension (written to *ld if ld is non-null); NULL if power is not
  * stored.  Valid until the next update, re-anchor or destroy. */
@@ -168,15 +197,16 @@ const void* lv_view_data(const lv_view* v, int power, int64_t* ld);
 
 /* Recompute every stored power from the current A (= the stored P_1) by
  * repeated squaring in double precision, discarding accumulated rounding
- * (bfloat16 shadows are rewritten from the new values). */
+ * (bfloat16 shadows are rewritten from the new values; stored sums and T_i
+ * are re-evaluated the same way). */
 lv_status lv_view_reanchor(lv_view* v, void* stream);
 
 /* Copy out (n x n, leading dimension lds >= n, device) into stored power
  * A^power: restores a checkpoint written with lv_view_read, or lets a test
  * perturb a stored power (its bfloat16 shadow, if any, is rewritten).  The
  * caller is responsible for consistency of the chain afterwards (see
- * lv_view_drift_check); stored sums are not changed (lv_view_reanchor
- * re-evaluates powers and sums from the stored A). */
+ * lv_view_drift_check); stored sums and T_i are not changed (lv_view_reanchor
+ * re-evaluates powers, sums and T_i from the stored A). */
 lv_status lv_view_write(lv_view* v, int power, const void* src, int64_t lds, void* stream);
 
 /* Drift check of the stored chain (the exponential model defines

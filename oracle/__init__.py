@@ -34,6 +34,7 @@ from .sums_oracle import (  # noqa: F401
     incr_update_sums,
 )
 from .general_oracle import (  # noqa: F401
+    iterate_general,
     reeval_general,
     incr_update_general,
 )

@@ -28,6 +28,21 @@ from .linview_oracle import levels, reeval
 from .sums_oracle import incr_sums_factors, reeval_sums
 
 
+def iterate_general(A: np.ndarray, T0: np.ndarray, B: np.ndarray, k: int) -> dict[int, np.ndarray]:
+    """T_1, T_2, T_4, ..., T_k by the defining iteration T_{i+1} = A T_i + B
+    (Sec. 5.4), one step at a time: k products of A with an n x p matrix,
+    cheap enough for full-size checks where the powers are not formed."""
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    want = set(levels(k))
+    out, T = {}, np.asarray(T0, dtype=np.float64)
+    for i in range(1, k + 1):
+        T = A @ T + B
+        if i in want:
+            out[i] = T
+    return out
+
+
 def reeval_general(A: np.ndarray, T0: np.ndarray, B: np.ndarray, k: int) -> dict[int, np.ndarray]:
     """T_1, T_2, T_4, ..., T_k by the exponential model of Table 1."""
     A = np.asarray(A, dtype=np.float64)

@@ -31,6 +31,36 @@ namespace {
 // Stored powers P_1..P_m from P_0 by repeated squaring in double precision
 // (Table 1, exponential model), then one rounding to the storage type.
 // With a non-null gate every kernel of the chain runs only if *gate != 0.
+// General form, creation step of level j in double (Table 1, exponential
+// model): T_1 = A T_0 + B for j = 0, else T_{2^j} = P T_{2^(j-1)} + S B with
+// P, S the double P_{j-1}, S_{j-1}; the double T ping-pongs in gT, the
+// stored T_{2^j} is its rounding.
+template <typename T>
+lv_status general_step(lv_view* v, int j, const double* P, const double* S, int64_t ld, hipStream_t s,
+                       const int* gate) {
+  const Layout& L = v->L;
+  lv_status st = LV_OK;
+  if (j == 0) {
+    st = hip_check(launch_copy_rect<T, double>(v->T0<T>(), L.pp, L.n_pad, L.pp, v->gT(0), L.n_pad, L.pp, s, gate),
+                   "widen T_0");
+    if (st == LV_OK)
+      st = hip_check(launch_copy_rect<T, double>(v->Bg<T>(), L.pp, L.n_pad, L.pp, v->gB(), L.n_pad, L.pp, s, gate),
+                     "widen B");
+    if (st == LV_OK)
+      st = hip_check(launch_gemm_np(L.pp, P, ld, v->gT(0), v->gT(1), v->gB(), L.n_pad, s, gate), "T_1 = A T_0 + B");
+  } else {
+    st = hip_check(launch_gemm_np(L.pp, S, ld, v->gB(), v->gTmp(), nullptr, L.n_pad, s, gate), "S B");
+    if (st == LV_OK)
+      st = hip_check(launch_gemm_np(L.pp, P, ld, v->gT(j & 1), v->gT((j + 1) & 1), v->gTmp(), L.n_pad, s, gate),
+                     "T = P T + S B");
+  }
+  if (st == LV_OK)
+    st = hip_check(launch_copy_rect<double, T>(v->gT((j + 1) & 1), L.pp, L.n_pad, L.pp, v->Tg<T>(j), L.n_pad, L.pp,
+                                                s, gate),
+                   "round T");
+  return st;
+}
+
 template <typename T>
 lv_status build_chain(lv_view* v, hipStream_t s, const int* gate = nullptr) {
   const Layout& L = v->L;
@@ -40,9 +70,16 @@ lv_status build_chain(lv_view* v, hipStream_t s, const int* gate = nullptr) {
     lv_status st = hip_check(launch_set_identity<T>(v->S<T>(0), L.ldp, v->n, L.n_pad, s, gate), "S_1 = I");
     if (st != LV_OK) return st;
   }
-  if (L.m == 0) return LV_OK;
   if constexpr (sizeof(T) == 8) {
+    if (L.general) {
+      lv_status st = general_step<double>(v, 0, v->P<double>(0), nullptr, L.ldp, s, gate);
+      if (st != LV_OK) return st;
+    }
     for (int j = 1; j <= L.m; ++j) {
+      if (L.general) {
+        lv_status st = general_step<double>(v, j, v->P<double>(j - 1), v->S<double>(j - 1), L.ldp, s, gate);
+        if (st != LV_OK) return st;
+      }
       lv_status st = hip_check(launch_gemm<double>(v->P<double>(j - 1), L.ldp, v->P<double>(j - 1), L.ldp,
                                                    v->P<double>(j), L.ldp, L.n_pad, s, gate), "gemm f64");
       if (st != LV_OK) return st;
@@ -55,14 +92,20 @@ lv_status build_chain(lv_view* v, hipStream_t s, const int* gate = nullptr) {
       }
     }
   } else {
+    if (L.m == 0 && !L.general) return LV_OK;
     lv_status st = hip_check(launch_copy_pad<float, double>(v->P<float>(0), L.ldp, L.n_pad, v->scratch(0),
                                                             L.n_pad, L.n_pad, s, gate), "widen P_1");
     if (st == LV_OK && L.sums)
       st = hip_check(launch_set_identity<double>(v->sscratch(0), L.n_pad, v->n, L.n_pad, s, gate), "S_1 = I (f64)");
+    if (st == LV_OK && L.general) st = general_step<float>(v, 0, v->scratch(0), nullptr, L.n_pad, s, gate);
     if (st != LV_OK) return st;
     for (int j = 1; j <= L.m; ++j) {
       double* src = v->scratch((j - 1) & 1);
       double* dst = v->scratch(j & 1);
+      if (L.general) {
+        st = general_step<float>(v, j, src, v->sscratch((j - 1) & 1), L.n_pad, s, gate);
+        if (st != LV_OK) return st;
+      }
       if (L.sums) {
         // S_{2i} = P_i S_i + S_i in double from the double P_i, rounded once
         double* scur = v->sscratch((j - 1) & 1);
@@ -174,6 +217,48 @@ lv_status sums_level(lv_view* v, int j, int R, const T* sU, const T* sV, hipStre
   });
 }
 
+// General form, level j (hybrid deltas, D_{2^j} in D[j & 1]): the product
+// X = P_j D_j with the OLD P_j, run before the level's update.  Float from
+// rank 16 up on the matrix cores (X only), else the read-only vector pass
+// (its transposed product is discarded).
+template <typename T>
+lv_status general_pass(lv_view* v, int j, hipStream_t s) {
+  const Layout& L = v->L;
+  const T* Dj = v->D<T>(j & 1);
+  return timed(v, 0, s, "general: P D", [&] {
+    if (skinny_on_mfma(L.pp, (int)sizeof(T)))
+      return launch_skinny_f32(L.pp, reinterpret_cast<const float*>(v->P<T>(j)), L.ldp, L.n_pad, v->tile_rows[j],
+                               reinterpret_cast<const float*>(Dj), reinterpret_cast<const float*>(Dj), L.pp,
+                               v->partXT<float>(), v->partYT<float>(), s, kWantX);
+    return launch_level_readonly<T>(L.pp, v->P<T>(j), L.ldp, L.n_pad, v->tile_rows[j], Dj, Dj, L.pp,
+                                    v->partXT<T>(), v->partYT<T>(), s);
+  });
+}
+
+// General form, rest of level j, after the powers' tail (U_j, V_j intact)
+// and before the sums tail (which overwrites Q_j):
+// a = V_j^T T_{2^j} (T_{2^j} already holds T + D), b = W_j^T B (j > 0,
+// W_0 = 0), D_{2^(j+1)} = X + U_j a + Q_j b, T_{2^(j+1)} += D.  With
+// j < 0 the first step: D_1 = U (V^T T_0), T_1 += D_1.
+template <typename T>
+lv_status general_tail(lv_view* v, int j, int R, const T* sU, const T* sV, hipStream_t s) {
+  const Layout& L = v->L;
+  const bool first = j < 0;
+  const T* src = first ? v->T0<T>() : v->Tg<T>(j);
+  lv_status st = timed(v, 0, s, "general: V^T T", [&] {
+    return launch_atb<T>(R, L.pp, sV + (L.W - R), L.W, src, L.pp, L.n_pad, v->atbA(), s);
+  });
+  if (st == LV_OK && j > 0)
+    st = timed(v, 0, s, "general: W^T B", [&] {
+      return launch_atb<T>(R, L.pp, v->slabW<T>() + (L.W - R), L.W, v->Bg<T>(), L.pp, L.n_pad, v->atbB(), s);
+    });
+  if (st != LV_OK) return st;
+  return timed(v, 1, s, "general: tail", [&] {
+    return launch_general_tail<T>(v->partXT<T>(), first ? 0 : L.nct, sU, j > 0 ? v->slabQ<T>() : nullptr, L.W, R,
+                                  v->atbA(), v->atbB(), v->D<T>((j + 1) & 1), v->Tg<T>(j + 1), L.n_pad, L.pp, s);
+  });
+}
+
 // One update through every level, factors in slab `sl` (App. A exponential
 // model; trigger of Sec. 4.4): levels 0..m-1 run the fused pass and the tail
 // (or, for float storage at large level rank and with bfloat16 shadows, the
@@ -187,9 +272,14 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
   T* sU = v->slabU<T>(sl);
   T* sV = v->slabV<T>(sl);
   lv_status st = hip_check(launch_prep<T>(U, ldu, V, ldv, v->n, r, r_pad, sU, sV, L.W, L.n_pad, s), "prep");
+  if (st == LV_OK && L.general) st = general_tail<T>(v, -1, r_pad, sU, sV, s);
   if (st != LV_OK) return st;
   for (int j = 0; j < L.m; ++j) {
     const int R = r_pad << j;
+    if (L.general) {
+      st = general_pass<T>(v, j, s);
+      if (st != LV_OK) return st;
+    }
     if (L.sums && j > 0) {
       // sums: X_s = P_j Q_j with the OLD P_j, before this level's update
       st = timed(v, 0, s, "sums: P Q", [&] {
@@ -227,6 +317,7 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
             return launch_level_tail<float>(R, v->partX<float>(j), v->partY<float>(j), v->partG(j), L.nct, v->nrt(j),
                                             1, L.n_pad, sU, sV, L.W, s);
           });
+        if (st == LV_OK && L.general) st = general_tail<T>(v, j, R, sU, sV, s);
         if (st == LV_OK && L.sums) st = sums_level<T>(v, j, R, sU, sV, s);
         if (st != LV_OK) return st;
         continue;
@@ -241,6 +332,7 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
       return launch_level_tail<T>(R, v->partX<T>(j), v->partY<T>(j), v->partG(j), L.nct, v->nrt(j),
                                   gram_in_pass(R, (int)sizeof(T)) ? v->nrt(j) : 1, L.n_pad, sU, sV, L.W, s);
     });
+    if (st == LV_OK && L.general) st = general_tail<T>(v, j, R, sU, sV, s);
     if (st == LV_OK && L.sums) st = sums_level<T>(v, j, R, sU, sV, s);
     if (st != LV_OK) return st;
   }
@@ -322,8 +414,15 @@ lv_status lv_view_create(const void* A, int64_t n, int64_t lda, int k, int r_max
   return lv_view_create_ex(A, n, lda, k, r_max, mode, 0, workspace, ws_bytes, stream, out);
 }
 
-lv_status lv_view_create_ex(const void* A, int64_t n, int64_t lda, int k, int r_max, lv_mode mode, int flags,
-                            void* workspace, size_t ws_bytes, void* stream, lv_view** out) {
+}  // extern "C"
+
+namespace {
+
+// Creation of every kind of view; p > 0 makes a general-form view with T_0
+// and B (n x p, leading dimensions ldt, ldb).
+lv_status create_view(const void* A, int64_t n, int64_t lda, int k, int r_max, lv_mode mode, int flags, int p,
+                      const void* T0, int64_t ldt, const void* B, int64_t ldb, void* workspace, size_t ws_bytes,
+                      void* stream, lv_view** out) {
   g_err[0] = 0;
   if (!out) return fail(LV_EINVAL, "out is NULL");
   *out = nullptr;
@@ -334,7 +433,7 @@ lv_status lv_view_create_ex(const void* A, int64_t n, int64_t lda, int k, int r_
   if (lda < n) return fail(LV_EINVAL, "lda = %lld < n = %lld", (long long)lda, (long long)n);
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
     return fail(LV_ENOMEM, "workspace is not %zu-byte aligned", kAlign);
-  const Layout L = make_layout(n, k, r_max, mode, flags);
+  const Layout L = make_layout(n, k, r_max, mode, flags, p);
   if (ws_bytes < L.total)
     return fail(LV_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
   lv_view* v = new (std::nothrow) lv_view();
@@ -355,10 +454,22 @@ lv_status lv_view_create_ex(const void* A, int64_t n, int64_t lda, int k, int r_
   if (mode == LV_FP64) {
     st = hip_check(launch_copy_pad<double, double>(static_cast<const double*>(A), lda, n, v->P<double>(0),
                                                    L.ldp, L.n_pad, s), "copy A");
+    if (st == LV_OK && L.general)
+      st = hip_check(launch_copy_rect<double, double>(static_cast<const double*>(T0), ldt, n, p, v->T0<double>(),
+                                                      L.n_pad, L.pp, s), "copy T_0");
+    if (st == LV_OK && L.general)
+      st = hip_check(launch_copy_rect<double, double>(static_cast<const double*>(B), ldb, n, p, v->Bg<double>(),
+                                                      L.n_pad, L.pp, s), "copy B");
     if (st == LV_OK) st = build_chain<double>(v, s);
   } else {
     st = hip_check(launch_copy_pad<float, float>(static_cast<const float*>(A), lda, n, v->P<float>(0),
                                                  L.ldp, L.n_pad, s), "copy A");
+    if (st == LV_OK && L.general)
+      st = hip_check(launch_copy_rect<float, float>(static_cast<const float*>(T0), ldt, n, p, v->T0<float>(),
+                                                    L.n_pad, L.pp, s), "copy T_0");
+    if (st == LV_OK && L.general)
+      st = hip_check(launch_copy_rect<float, float>(static_cast<const float*>(B), ldb, n, p, v->Bg<float>(),
+                                                    L.n_pad, L.pp, s), "copy B");
     if (st == LV_OK) st = build_chain<float>(v, s);
   }
   if (st == LV_OK)
@@ -366,6 +477,32 @@ lv_status lv_view_create_ex(const void* A, int64_t n, int64_t lda, int k, int r_
   if (st != LV_OK) { delete v; return st; }
   *out = v;
   return LV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lv_status lv_view_create_ex(const void* A, int64_t n, int64_t lda, int k, int r_max, lv_mode mode, int flags,
+                            void* workspace, size_t ws_bytes, void* stream, lv_view** out) {
+  return create_view(A, n, lda, k, r_max, mode, flags, 0, nullptr, 0, nullptr, 0, workspace, ws_bytes, stream, out);
+}
+
+size_t lv_view_footprint_general(int64_t n, int k, int r_max, lv_mode mode, int64_t p) {
+  if (check_shape(n, k, r_max, mode) != LV_OK || p < 1 || p > kMaxGeneralCols) return 0;
+  return make_layout(n, k, r_max, mode, LV_WITH_SUMS, (int)p).total;
+}
+
+lv_status lv_view_create_general(const void* A, int64_t n, int64_t lda, int k, int r_max, lv_mode mode,
+                                 const void* T0, int64_t ldt, const void* B, int64_t ldb, int64_t p,
+                                 void* workspace, size_t ws_bytes, void* stream, lv_view** out) {
+  g_err[0] = 0;
+  if (out) *out = nullptr;
+  if (p < 1 || p > kMaxGeneralCols) return fail(LV_EINVAL, "p = %lld outside [1, %d]", (long long)p, kMaxGeneralCols);
+  if (!T0 || !B) return fail(LV_EINVAL, "T0 or B is NULL");
+  if (ldt < p || ldb < p) return fail(LV_EINVAL, "ldt/ldb smaller than p");
+  return create_view(A, n, lda, k, r_max, mode, LV_WITH_SUMS, (int)p, T0, ldt, B, ldb, workspace, ws_bytes, stream,
+                     out);
 }
 
 static lv_status check_update_args(const lv_view* v, const void* U, const void* V, int64_t r,
@@ -443,6 +580,19 @@ lv_status lv_view_read_sum(const lv_view* v, int index, void* out, int64_t ldo, 
   return hip_check(hipMemcpy2DAsync(out, ldo * es, v->base + v->L.S[j], v->L.ldp * es, v->n * es, v->n,
                                     hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)),
                    "read sum");
+}
+
+lv_status lv_view_read_general(const lv_view* v, int index, void* out, int64_t ldo, void* stream) {
+  g_err[0] = 0;
+  const int j = power_level(v, index);
+  if (j < 0) return fail(LV_EINVAL, "T index %d is not stored", index);
+  if (!v->L.general) return fail(LV_ESTATE, "the view is not a general-form view");
+  if (!out) return fail(LV_EINVAL, "out is NULL");
+  if (ldo < v->L.p) return fail(LV_EINVAL, "ldo < p");
+  const size_t es = v->L.elem;
+  return hip_check(hipMemcpy2DAsync(out, ldo * es, v->base + v->L.T[j], v->L.pp * es, v->L.p * es, v->n,
+                                    hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)),
+                   "read T");
 }
 
 const void* lv_view_data(const lv_view* v, int power, int64_t* ld) {

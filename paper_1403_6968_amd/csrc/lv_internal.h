@@ -203,6 +203,29 @@ hipError_t launch_set_identity(T* S, int64_t ld, int64_t n, int64_t n_pad, hipSt
 template <typename T>
 hipError_t launch_add(T* dst, const T* src, int64_t count, hipStream_t s, const int* gate = nullptr);
 
+// ---- general form T_{i+1} = A T_i + B (hybrid deltas)
+
+// part[0 .. R*p) = A^T B (double) for A n_pad x R (lda), B n_pad x p (ldb):
+// 64-row partials, then their fixed-order sum (part holds n_pad / 64 partials).
+template <typename T>
+hipError_t launch_atb(int R, int p, const T* A, int64_t lda, const T* B, int64_t ldb, int64_t n_pad, double* part,
+                      hipStream_t s);
+// D = sum of nct partials of X + U a (+ Q b if Q is non-null), T += D
+// (n_pad x pp; U, Q with row stride W and R columns; a, b R x pp double).
+template <typename T>
+hipError_t launch_general_tail(const T* partX, int nct, const T* U, const T* Q, int W, int R, const double* a,
+                               const double* b, T* D, T* Tm, int64_t n_pad, int pp, hipStream_t s);
+// C = A B (+ C0 if non-null), A n_pad x n_pad (lda), B, C, C0 n_pad x pp,
+// double; pp in {1, 2, 4, ..., 64}.  With a non-null gate only when *gate != 0.
+hipError_t launch_gemm_np(int pp, const double* A, int64_t lda, const double* B, double* C, const double* C0,
+                          int64_t n_pad, hipStream_t s, const int* gate = nullptr);
+// dst (n_pad x pp, contiguous) = src (n x p, ld lds) zero-padded.
+template <typename Tin, typename Tout>
+hipError_t launch_copy_rect(const Tin* src, int64_t lds, int64_t n, int p, Tout* dst, int64_t n_pad, int pp,
+                            hipStream_t s, const int* gate = nullptr);
+// G[0 .. count) = sum over t < ng of G[t count + ...] (fixed order).
+hipError_t launch_gram_sum(double* G, int ng, int count, hipStream_t s);
+
 // Multi-view launches over device descriptor arrays (nd descriptors,
 // `blocks` work-groups in total).  `chunk` selects the read-only skinny pass
 // over 16 factor columns used for level ranks above kMaxFusedRank.

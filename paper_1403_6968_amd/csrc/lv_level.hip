@@ -709,6 +709,12 @@ hipError_t launch_add(T* dst, const T* src, int64_t count, hipStream_t s, const 
   return hipGetLastError();
 }
 
+hipError_t launch_gram_sum(double* G, int ng, int count, hipStream_t s) {
+  const GramSumDesc d{G, ng, count, 0};
+  hipLaunchKernelGGL(k_gram_sum, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, d);
+  return hipGetLastError();
+}
+
 hipError_t launch_gram_sum_multi(const GramSumDesc* ds, int nd, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_gram_sum_multi, dim3((unsigned)blocks), dim3(256), 0, s, ds, nd);

@@ -50,6 +50,16 @@ struct Layout {
   size_t partYs[kMaxLevel] = {};
   size_t partGs[kMaxLevel] = {};
   size_t sscratch[2] = {};
+  // general form T_{i+1} = A T_i + B with hybrid deltas (implies sums): p
+  // columns padded to pp, T_1, T_2, ..., T_k and T_0, B (storage type, n_pad x
+  // pp), the deltas D (two, ping-pong), partials of P_j D_j (and of the
+  // unused P_j^T D_j), FP64 partials of V_j^T T_j and W_j^T B, FP64 creation
+  // scratch (two T, one product, B)
+  bool general = false;
+  int p = 0, pp = 0;
+  size_t T[kMaxLevel + 1] = {};
+  size_t T0 = 0, B = 0, D[2] = {}, partXT = 0, partYT = 0, atbA = 0, atbB = 0;
+  size_t gT[2] = {}, gTmp = 0, gB = 0;
   size_t probe = 0;  // zpad | Pz (m+1 vectors) | PPz (m vectors) | residuals | gate | counter
   size_t total = 0;
 };
@@ -66,9 +76,13 @@ inline lv_status check_shape(int64_t n, int k, int r_max, lv_mode mode) {
   return LV_OK;
 }
 
-inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode, int flags = 0) {
+constexpr int kMaxGeneralCols = 64;   // p of the general form (padded to a power of two)
+constexpr int kAtbRows = 64;          // rows per FP64 partial of V^T T and W^T B
+
+inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode, int flags = 0, int p = 0) {
   lv::Layout L;
-  L.sums = (flags & LV_WITH_SUMS) != 0;
+  L.general = p > 0;
+  L.sums = (flags & LV_WITH_SUMS) != 0 || L.general;
   L.elem = mode == LV_FP64 ? 8 : 4;
   L.n_pad = round_up(n, kPadOrder);
   L.ldp = L.n_pad;
@@ -95,7 +109,7 @@ inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode, int flags =
   }
   if (mode == LV_FP32_BF16SHADOW)
     for (int j = 0; j < L.m; ++j) { L.shadow[j] = off; off = align_up(off + (size_t)L.n_pad * L.ldp * 2); }
-  if (mode != LV_FP64 && L.m > 0) {
+  if (mode != LV_FP64 && (L.m > 0 || L.general)) {
     const size_t dmat = (size_t)L.n_pad * L.n_pad * sizeof(double);
     L.scratch[0] = off; off = align_up(off + dmat);
     L.scratch[1] = off; off = align_up(off + dmat);
@@ -110,11 +124,31 @@ inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode, int flags =
       L.partYs[j] = off; off = align_up(off + (size_t)L.nrt_max * L.n_pad * R * L.elem);
       L.partGs[j] = off; off = align_up(off + (size_t)gram_tiles(L.n_pad) * R * R * sizeof(double));
     }
-    if (mode != LV_FP64 && L.m > 0) {
+    if (mode != LV_FP64 && (L.m > 0 || L.general)) {
       const size_t dmat = (size_t)L.n_pad * L.n_pad * sizeof(double);
       L.sscratch[0] = off; off = align_up(off + dmat);
       L.sscratch[1] = off; off = align_up(off + dmat);
     }
+  }
+  if (L.general) {
+    L.p = p;
+    L.pp = (int)next_pow2(p);
+    const size_t gmat = (size_t)L.n_pad * L.pp * L.elem;
+    const size_t gdbl = (size_t)L.n_pad * L.pp * sizeof(double);
+    for (int j = 0; j <= L.m; ++j) { L.T[j] = off; off = align_up(off + gmat); }
+    L.T0 = off; off = align_up(off + gmat);
+    L.B = off; off = align_up(off + gmat);
+    L.D[0] = off; off = align_up(off + gmat);
+    L.D[1] = off; off = align_up(off + gmat);
+    L.partXT = off; off = align_up(off + (size_t)L.nct * gmat);
+    L.partYT = off; off = align_up(off + (size_t)L.nrt_max * gmat);
+    const size_t atb = (size_t)(L.n_pad / kAtbRows) * L.W * L.pp * sizeof(double);
+    L.atbA = off; off = align_up(off + atb);
+    L.atbB = off; off = align_up(off + atb);
+    L.gT[0] = off; off = align_up(off + gdbl);
+    L.gT[1] = off; off = align_up(off + gdbl);
+    L.gTmp = off; off = align_up(off + gdbl);
+    L.gB = off; off = align_up(off + gdbl);
   }
   L.probe = off;
   off = align_up(off + (size_t)(2 * L.m + 2) * L.n_pad * sizeof(double) + kMaxLevel * sizeof(double) + 256);
@@ -165,6 +199,17 @@ struct lv_view {
   template <typename T> T* partYs(int j) const { return reinterpret_cast<T*>(base + L.partYs[j]); }
   double* partGs(int j) const { return reinterpret_cast<double*>(base + L.partGs[j]); }
   double* sscratch(int i) const { return reinterpret_cast<double*>(base + L.sscratch[i]); }
+  template <typename T> T* Tg(int j) const { return reinterpret_cast<T*>(base + L.T[j]); }
+  template <typename T> T* T0() const { return reinterpret_cast<T*>(base + L.T0); }
+  template <typename T> T* Bg() const { return reinterpret_cast<T*>(base + L.B); }
+  template <typename T> T* D(int i) const { return reinterpret_cast<T*>(base + L.D[i]); }
+  template <typename T> T* partXT() const { return reinterpret_cast<T*>(base + L.partXT); }
+  template <typename T> T* partYT() const { return reinterpret_cast<T*>(base + L.partYT); }
+  double* atbA() const { return reinterpret_cast<double*>(base + L.atbA); }
+  double* atbB() const { return reinterpret_cast<double*>(base + L.atbB); }
+  double* gT(int i) const { return reinterpret_cast<double*>(base + L.gT[i]); }
+  double* gTmp() const { return reinterpret_cast<double*>(base + L.gTmp); }
+  double* gB() const { return reinterpret_cast<double*>(base + L.gB); }
   uint16_t* shadow(int j) const { return reinterpret_cast<uint16_t*>(base + L.shadow[j]); }
   bool shadowed() const { return mode == LV_FP32_BF16SHADOW; }
   double* scratch(int i) const { return reinterpret_cast<double*>(base + L.scratch[i]); }

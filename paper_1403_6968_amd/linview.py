@@ -36,6 +36,7 @@ EXPORTED = (
     "lv_server_remove_view", "lv_server_view", "lv_server_now", "lv_server_submit", "lv_server_step",
     "lv_view_tile_rows", "lv_view_set_tile_rows", "lv_batch_tuning",
     "lv_view_footprint_ex", "lv_view_create_ex", "lv_view_read_sum",
+    "lv_view_footprint_general", "lv_view_create_general", "lv_view_read_general",
     "lv_server_poll", "lv_server_drain", "lv_server_stats", "lv_server_destroy",
 )
 
@@ -129,6 +130,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "lv_view_footprint_ex": (SZ, [I64, I32, I32, I32, I32]),
         "lv_view_create_ex": (I32, [P, I64, I64, I32, I32, I32, I32, P, SZ, P, c.POINTER(P)]),
         "lv_view_read_sum": (I32, [P, I32, P, I64, P]),
+        "lv_view_footprint_general": (SZ, [I64, I32, I32, I32, I64]),
+        "lv_view_create_general": (I32, [P, I64, I64, I32, I32, I32, P, I64, P, I64, I64, P, SZ, P,
+                                         c.POINTER(P)]),
+        "lv_view_read_general": (I32, [P, I32, P, I64, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -190,6 +195,35 @@ def lv_view_create(A: torch.Tensor, k: int, r_max: int, mode: int, workspace: to
                                  workspace.numel() * workspace.element_size(),
                                  _stream(stream, A.device), ctypes.byref(h)))
     return h
+
+
+def lv_view_footprint_general(n: int, k: int, r_max: int, mode: int, p: int) -> int:
+    return int(load().lv_view_footprint_general(n, k, r_max, mode, p))
+
+
+def lv_view_create_general(A: torch.Tensor, k: int, r_max: int, mode: int, T0: torch.Tensor,
+                           B: torch.Tensor, workspace: torch.Tensor, stream=None) -> ctypes.c_void_p:
+    lib = load()
+    dtype = _MODE_DTYPE[mode]
+    a, lda = _mat(A, dtype, "A")
+    t, ldt = _mat(T0, dtype, "T0")
+    b, ldb = _mat(B, dtype, "B")
+    if A.shape[0] != A.shape[1]:
+        raise ValueError("A must be square")
+    if T0.shape != B.shape or T0.shape[0] != A.shape[0]:
+        raise ValueError("T0 and B must both be n x p")
+    if workspace.device.type != "cuda" or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous device tensor")
+    h = ctypes.c_void_p()
+    _check(lib.lv_view_create_general(a, A.shape[0], lda, k, r_max, mode, t, ldt, b, ldb, T0.shape[1],
+                                      workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+                                      _stream(stream, A.device), ctypes.byref(h)))
+    return h
+
+
+def lv_view_read_general(view, index: int, out: torch.Tensor, dtype, stream=None) -> None:
+    o, ldo = _mat(out, dtype, "out")
+    _check(load().lv_view_read_general(view, index, o, ldo, _stream(stream, out.device)))
 
 
 def lv_view_update(view, U: torch.Tensor, V: torch.Tensor, dtype, stream=None) -> None:
@@ -310,7 +344,9 @@ class View:
     """A view of A^k whose workspace is a torch device tensor."""
 
     def __init__(self, A: torch.Tensor, k: int, r_max: int = 1, mode: int | None = None,
-                 stream=None, sums: bool = False):
+                 stream=None, sums: bool = False, general=None):
+        """general = (T0, B), both n x p: a view of the general form
+        T_{i+1} = A T_i + B as well (implies sums)."""
         if mode is None:
             mode = LV_FP64 if A.dtype == torch.float64 else LV_FP32
         self.mode = mode
@@ -318,7 +354,18 @@ class View:
         self.n = A.shape[0]
         self.k = k
         self.device = A.device
-        self.flags = LV_WITH_SUMS if sums else 0
+        self.flags = LV_WITH_SUMS if sums or general is not None else 0
+        self.p = 0
+        if general is not None:
+            T0, B = general
+            self.p = T0.shape[1]
+            nbytes = lv_view_footprint_general(self.n, k, r_max, mode, self.p)
+            if nbytes == 0:
+                _check(load().lv_view_create_general(None, self.n, self.n, k, r_max, mode, None, self.p, None,
+                                                     self.p, self.p, None, 0, None, ctypes.byref(ctypes.c_void_p())))
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+            self.handle = lv_view_create_general(A, k, r_max, mode, T0, B, self.workspace, stream)
+            return
         nbytes = lv_view_footprint(self.n, k, r_max, mode, self.flags)
         if nbytes == 0:
             # Reproduce the library's validation message.
@@ -344,6 +391,13 @@ class View:
         index = self.k if index is None else index
         out = torch.empty(self.n, self.n, dtype=self.dtype, device=self.device)
         _check(load().lv_view_read_sum(self.handle, index, out.data_ptr(), out.stride(0), _stream(stream, self.device)))
+        return out
+
+    def read_general(self, index: int | None = None, stream=None) -> torch.Tensor:
+        """Stored T_index of the general form (general-form views)."""
+        index = self.k if index is None else index
+        out = torch.empty(self.n, max(self.p, 1), dtype=self.dtype, device=self.device)
+        lv_view_read_general(self.handle, index, out, self.dtype, stream)
         return out
 
     def reanchor(self, stream=None) -> None:

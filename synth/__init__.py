@@ -13,6 +13,9 @@ Workload recipe (the paper's experiments use dense random matrices that are
   sigma = 1e-2 / sqrt(n), so each rank-1 term u v^T has norm about 1e-4.
 * Row updates (u = e_i) with Zipf-distributed row frequencies, as in the
   batch-update experiment (Sec. 7, Table 6).
+* General form T_{i+1} = A T_i + B: T_0 ~ N(0, 1), B ~ N(0, 0.01) (n x p),
+  and the gradient-descent regression of Sec. 7 (A = I - eta X^T X,
+  B = eta X^T Y, new training rows as rank-1 changes of A).
 
 Every generator draws from numpy's PCG64 seeded through a SeedSequence whose
 spawn key names the stream (config id, view id, purpose), so the same
@@ -29,6 +32,9 @@ from .gen import (  # noqa: F401
     random_dag,
     integer_matrix,
     round_to,
+    general_operands,
+    regression_problem,
+    regression_rows,
     KEY_A,
     KEY_UPDATES,
 )

@@ -11,6 +11,7 @@ KEY_ROWS = 3
 KEY_GRAPH = 4
 KEY_SPECTRAL = 5
 KEY_INT = 6
+KEY_GENERAL = 7
 
 
 def rng(seed: int, *key: int) -> np.random.Generator:
@@ -112,3 +113,43 @@ def round_to(x: np.ndarray, dtype) -> np.ndarray:
     """Round once to `dtype` (e.g. np.float32) and return the rounded values
     as an array of that dtype (C-contiguous)."""
     return np.ascontiguousarray(np.asarray(x, dtype=dtype))
+
+
+def general_operands(n: int, p: int, seed: int = 0, config: int = 0,
+                     view: int = 0) -> tuple[np.ndarray, np.ndarray]:
+    """T_0 and B of the general form T_{i+1} = A T_i + B, both n x p FP64:
+    T_0 with i.i.d. N(0, 1) entries, B with i.i.d. N(0, 0.01) entries (so
+    that with a spectral norm of A near 0.9 the fixed point B / (I - A) is
+    of the size of T_0)."""
+    g = rng(seed, config, KEY_GENERAL, view)
+    T0 = g.standard_normal((n, p))
+    B = g.standard_normal((n, p)) * 0.1
+    return T0, B
+
+
+def regression_problem(n: int, p: int, samples: int, seed: int = 0,
+                       config: int = 0) -> tuple[np.ndarray, np.ndarray, float]:
+    """Gradient-descent linear regression as a general form (the regression
+    experiment of Sec. 7): theta_{i+1} = theta_i - eta X^T (X theta_i - Y)
+    is T_{i+1} = A T_i + B with A = I - eta X^T X and B = eta X^T Y.
+    X (samples x n) and Y (samples x p) have i.i.d. N(0, 1) entries; eta is
+    1 / ||X||_2^2, which puts the spectrum of A in [0, 1).  Returns
+    (A, B, eta), FP64."""
+    g = rng(seed, config, KEY_GENERAL, 1)
+    X = g.standard_normal((samples, n))
+    Y = g.standard_normal((samples, p))
+    s = float(np.linalg.norm(X, 2)) if min(X.shape) <= 1024 else spectral_norm_estimate(X, seed=seed)
+    eta = 1.0 / (s * s)
+    A = np.eye(n) - eta * (X.T @ X)
+    B = eta * (X.T @ Y)
+    return A, B, eta
+
+
+def regression_rows(n: int, count: int, eta: float, seed: int = 0,
+                    config: int = 0) -> tuple[np.ndarray, np.ndarray]:
+    """New training rows x_t as rank-1 changes of A = I - eta X^T X:
+    Delta A = (-eta x_t) x_t^T.  x_t has i.i.d. N(0, 1) entries.  Returns
+    (U, V) of shape (count, n, 1)."""
+    g = rng(seed, config, KEY_GENERAL, 2)
+    x = g.standard_normal((count, n, 1))
+    return -eta * x, x.copy()

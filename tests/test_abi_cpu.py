@@ -143,3 +143,33 @@ def test_sums_footprint_and_flags(lib):
     st = lib.lv_view_create_ex(0x1000, 64, 64, 4, 1, L.LV_FP32, 8, 0x1000, 1 << 30, None, ctypes.byref(h))
     assert st == L.LV_EINVAL and "flags" in L.lv_last_error()
     assert lib.lv_view_read_sum(None, 1, 0x1000, 64, None) == L.LV_EINVAL
+
+
+def test_general_footprint_and_validation(lib):
+    from paper_1403_6968_amd import linview as L
+    for n, k, r, p in [(1000, 16, 1, 1), (300, 8, 4, 5), (513, 1, 2, 64)]:
+        sums = L.lv_view_footprint(n, k, r, L.LV_FP32, L.LV_WITH_SUMS)
+        gen = L.lv_view_footprint_general(n, k, r, L.LV_FP32, p)
+        n_pad = -(-n // 256) * 256
+        pp = 1 << (p - 1).bit_length()
+        m = k.bit_length() - 1
+        # T_1 .. T_k, T_0, B and the two deltas in storage type, four FP64 n x p buffers
+        assert gen >= sums + (m + 5) * n_pad * pp * 4 + 4 * n_pad * pp * 8
+    assert L.lv_view_footprint_general(1000, 16, 1, L.LV_FP32, 0) == 0
+    assert L.lv_view_footprint_general(1000, 16, 1, L.LV_FP32, 65) == 0
+    assert L.lv_view_footprint_general(1000, 6, 1, L.LV_FP32, 4) == 0
+    h = ctypes.c_void_p()
+    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1000, 4, 0x1000, 4, 65, 0x1000, 1 << 30,
+                                    None, ctypes.byref(h))
+    assert st == L.LV_EINVAL and "p = 65" in L.lv_last_error()
+    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, None, 4, 0x1000, 4, 4, 0x1000, 1 << 30,
+                                    None, ctypes.byref(h))
+    assert st == L.LV_EINVAL and "NULL" in L.lv_last_error()
+    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1000, 3, 0x1000, 4, 4, 0x1000, 1 << 30,
+                                    None, ctypes.byref(h))
+    assert st == L.LV_EINVAL and "ldt" in L.lv_last_error()
+    need = L.lv_view_footprint_general(64, 4, 1, L.LV_FP32, 4)
+    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1000, 4, 0x1000, 4, 4, 0x1000, need - 1,
+                                    None, ctypes.byref(h))
+    assert st == L.LV_ENOMEM and str(need) in L.lv_last_error()
+    assert lib.lv_view_read_general(None, 1, 0x1000, 4, None) == L.LV_EINVAL

@@ -117,3 +117,14 @@ def test_general_pins_catch_planted_mistakes(kind):
 
 def test_general_unmutated_copy_passes():
     assert all(_exact_incr(_mutant("none"), n=4, p=2, k=8, r=1 + s % 2, seed=s) for s in range(4))
+
+
+def test_iterate_general_matches_exact_iteration():
+    """The floating-point defining iteration (used for full-size checks)
+    agrees with the exact rational iteration on integer inputs."""
+    A, T0, B = _case(5, 2, 41)
+    it = O.iterate_general(A, T0, B, 8)
+    ref = _iterate(_frac(A), _frac(T0), _frac(B), 8)
+    assert sorted(it) == [1, 2, 4, 8]
+    for i in it:
+        assert (_frac(it[i]) == ref[i]).all(), i
