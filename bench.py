@@ -50,7 +50,7 @@ def parse():
     p.add_argument("--no-secondary", action="store_true",
                    help="skip the rank-4, batched and serving workloads")
     p.add_argument("--serve-seconds", type=float, default=2.0)
-    p.add_argument("--only", choices=["rank4", "batched", "serving", "sums"],
+    p.add_argument("--only", choices=["rank4", "batched", "serving", "sums", "general"],
                    help="run one secondary workload alone and print its result (for profilers)")
     return p.parse_args()
 
@@ -112,6 +112,56 @@ def bench_sums(torch, lv, synth, dev, steps=200):
     return {"workload": "A^16 and sums of powers S_1..S_16, n=8192, FP32, rank-1 updates",
             "ms_per_update": ms, "updates_per_s": 1000.0 / ms, "alg_bytes_per_update": alg,
             "alg_GBps": alg / (ms * 1e-3) / 1e9}
+
+
+def bench_general(torch, lv, synth, dev, steps=100, ps=(1, 16, 64)):
+    """General form T_{i+1} = A T_i + B (hybrid deltas on the exponential
+    model), n = 8192, k = 16, FP32, rank-1 updates, for several p: ms per
+    update of the general-form view (powers, sums and T_1..T_16 current),
+    against re-evaluation by the linear model on the GPU (A += U V^T, then
+    16 steps T = A T + B with torch.matmul; it yields T_16 only)."""
+    n, k = 8192, 16
+    A = torch.from_numpy(synth.gaussian_matrix(n, seed=0, config=2).astype(np.float32)).to(dev)
+    U, V = synth.update_factors(n, 1, steps + 5, seed=0, config=2)
+    Ud = torch.from_numpy(U.astype(np.float32)).to(dev)
+    Vd = torch.from_numpy(V.astype(np.float32)).to(dev)
+    out = {"workload": "general form T_{i+1} = A T_i + B, n=8192, k=16, FP32, rank-1 updates"}
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for p in ps:
+        T0, B = (torch.from_numpy(x.astype(np.float32)).to(dev) for x in synth.general_operands(n, p, seed=0))
+        view = lv.View(A, k, general=(T0, B))
+        view.update_batch(Ud[:5], Vd[:5])
+        torch.cuda.synchronize()
+        a.record()
+        view.update_batch(Ud[5:], Vd[5:])
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        view.close()
+        del view
+        torch.cuda.empty_cache()
+        Ar = A.clone()
+        reps = 20
+
+        def reeval_lin(t):
+            Ar.addmm_(Ud[t], Vd[t].t())
+            T = T0
+            for _ in range(k):
+                T = torch.addmm(B, Ar, T)
+            return T
+        reeval_lin(0)
+        torch.cuda.synchronize()
+        a.record()
+        for t in range(reps):
+            reeval_lin(1 + t)
+        b.record()
+        torch.cuda.synchronize()
+        lin_ms = a.elapsed_time(b) / reps
+        del Ar
+        out[f"p{p}"] = {"hybrid_exp_ms_per_update": ms, "updates_per_s": 1000.0 / ms,
+                        "reeval_lin_torch_ms": lin_ms, "reeval_lin_over_hybrid": lin_ms / ms}
+    del A
+    return out
 
 
 def bench_batched(torch, lv, synth, dev, rounds=30):
@@ -275,7 +325,8 @@ def main():
         fn = {"rank4": lambda: bench_rank4(torch, lv, synth, dev),
               "batched": lambda: bench_batched(torch, lv, synth, dev),
               "serving": lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds),
-              "sums": lambda: bench_sums(torch, lv, synth, dev)}[args.only]
+              "sums": lambda: bench_sums(torch, lv, synth, dev),
+              "general": lambda: bench_general(torch, lv, synth, dev)}[args.only]
         print(json.dumps({"only": args.only, "result": fn()}), flush=True)
         return
     n, k, r = args.n, args.k, args.rank
@@ -438,6 +489,7 @@ def main():
         sec = {}
         for name, fn in (("rank4_n16384", lambda: bench_rank4(torch, lv, synth, dev)),
                          ("sums_n8192", lambda: bench_sums(torch, lv, synth, dev)),
+                         ("general_n8192", lambda: bench_general(torch, lv, synth, dev)),
                          ("batched_64_views", lambda: bench_batched(torch, lv, synth, dev)),
                          ("serving_32_views", lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds)),
                          ("serving_32_views_fp32",
