@@ -38,3 +38,11 @@ from .general_oracle import (  # noqa: F401
     reeval_general,
     incr_update_general,
 )
+from .models_oracle import (  # noqa: F401
+    model_steps,
+    stored_powers,
+    reeval_model,
+    incr_model_factors,
+    incr_update_model,
+    paper_cost,
+)
