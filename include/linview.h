@@ -389,6 +389,48 @@ lv_status lv_reeval(const void* A, int64_t n, int64_t lda, int k,
                     lv_mode mode, void* out, int64_t ldo,
                     void* workspace, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- models
+ *
+ * Matrix-power views under the other iterative models of Sec. 3.2 and
+ * Table 1 (matrix-powers column), for comparing IncrLin / IncrSkip-s with
+ * IncrExp (Table 2; App. A):
+ *   LV_MODEL_LIN   stores P_1 .. P_k,  P_i = A P_{i-1}          (any k >= 1)
+ *   LV_MODEL_EXP   stores P_1, P_2, P_4, .., P_k, P_i = P_{i/2} P_{i/2}
+ *                  (k a power of two; the same model as lv_view, on this
+ *                  generic engine)
+ *   LV_MODEL_SKIP  the exponential model up to P_s, then
+ *                  P_i = P_s P_{i-s} for i = 2s, 3s, .., k
+ *                  (s a power of two dividing k)
+ * An update Delta A = U V^T forms, for every product P_c = P_a P_b in
+ * order and from the OLD matrices (App. A),
+ *     U_c = [U_a, P_a U_b + U_a (V_a^T U_b)],   V_c = [P_b^T V_a, V_b]
+ * (widths c * r), then applies P_c += U_c V_c^T to every stored matrix.
+ * Modes LV_FP64 and LV_FP32 (creation in double, rounded once).  k * r_max
+ * rounded up to a power of two must not exceed 128.  Workspace, streams,
+ * ownership and errors as for lv_view. */
+#define LV_MODEL_EXP 0
+#define LV_MODEL_LIN 1
+#define LV_MODEL_SKIP 2
+
+typedef struct lv_chain lv_chain;
+
+/* Workspace bytes; 0 for invalid arguments (s is ignored unless the model
+ * is LV_MODEL_SKIP). */
+size_t lv_chain_footprint(int64_t n, int k, int r_max, lv_mode mode, int model, int s);
+lv_status lv_chain_create(const void* A, int64_t n, int64_t lda, int k, int r_max, lv_mode mode,
+                          int model, int s, void* workspace, size_t ws_bytes, void* stream,
+                          lv_chain** out);
+/* One update Delta A = U V^T (U, V n x r device, ldu, ldv >= r, r <= r_max). */
+lv_status lv_chain_update(lv_chain* c, const void* U, const void* V, int64_t r, int64_t ldu,
+                          int64_t ldv, void* stream);
+/* Copy stored A^power (a power the model stores) to out (n x n, ldo >= n). */
+lv_status lv_chain_read(const lv_chain* c, int power, void* out, int64_t ldo, void* stream);
+/* Number of stored matrices (-1 for NULL); their powers, ascending, go to
+ * powers[0 .. min(count, cap)) when powers is non-null. */
+int lv_chain_powers(const lv_chain* c, int* powers, int cap);
+/* Release the handle (the caller frees the workspace).  NULL is ignored. */
+void lv_chain_destroy(lv_chain* c);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "liblinview.so")
 LV_OK, LV_EINVAL, LV_ENOMEM, LV_EDEVICE, LV_ESTATE = 0, 1, 2, 3, 4
 LV_FP64, LV_FP32, LV_FP32_BF16SHADOW = 0, 1, 2
 LV_WITH_SUMS = 1
+LV_MODEL_EXP, LV_MODEL_LIN, LV_MODEL_SKIP = 0, 1, 2
 
 _MODE_DTYPE = {LV_FP64: torch.float64, LV_FP32: torch.float32, LV_FP32_BF16SHADOW: torch.float32}
 
@@ -37,6 +38,8 @@ EXPORTED = (
     "lv_view_tile_rows", "lv_view_set_tile_rows", "lv_batch_tuning",
     "lv_view_footprint_ex", "lv_view_create_ex", "lv_view_read_sum",
     "lv_view_footprint_general", "lv_view_create_general", "lv_view_read_general",
+    "lv_chain_footprint", "lv_chain_create", "lv_chain_update", "lv_chain_read", "lv_chain_powers",
+    "lv_chain_destroy",
     "lv_server_poll", "lv_server_drain", "lv_server_stats", "lv_server_destroy",
 )
 
@@ -134,6 +137,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "lv_view_create_general": (I32, [P, I64, I64, I32, I32, I32, P, I64, P, I64, I64, P, SZ, P,
                                          c.POINTER(P)]),
         "lv_view_read_general": (I32, [P, I32, P, I64, P]),
+        "lv_chain_footprint": (SZ, [I64, I32, I32, I32, I32, I32]),
+        "lv_chain_create": (I32, [P, I64, I64, I32, I32, I32, I32, I32, P, SZ, P, c.POINTER(P)]),
+        "lv_chain_update": (I32, [P, P, P, I64, I64, I64, P]),
+        "lv_chain_read": (I32, [P, I32, P, I64, P]),
+        "lv_chain_powers": (I32, [P, c.POINTER(I32), I32]),
+        "lv_chain_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -620,3 +629,60 @@ def reeval(A: torch.Tensor, k: int, U=None, V=None, stream=None) -> torch.Tensor
     out = torch.empty(n, n, dtype=A.dtype, device=A.device)
     lv_reeval(A, k, U, V, mode, out, ws, stream)
     return out
+
+
+class Chain:
+    """A matrix-power view under the linear, skip-s or exponential model
+    (LV_MODEL_*), for comparing IncrLin / IncrSkip-s with IncrExp."""
+
+    def __init__(self, A: torch.Tensor, k: int, r_max: int = 1, model: int = LV_MODEL_LIN, s: int = 0,
+                 mode: int | None = None, stream=None):
+        if mode is None:
+            mode = LV_FP64 if A.dtype == torch.float64 else LV_FP32
+        self.mode, self.dtype = mode, _MODE_DTYPE[mode]
+        self.n, self.k, self.device = A.shape[0], k, A.device
+        lib = load()
+        nbytes = int(lib.lv_chain_footprint(self.n, k, r_max, mode, model, s))
+        if nbytes == 0:
+            _check(lib.lv_chain_create(None, self.n, self.n, k, r_max, mode, model, s, None, 0, None,
+                                       ctypes.byref(ctypes.c_void_p())))
+        a, lda = _mat(A, self.dtype, "A")
+        if A.shape[0] != A.shape[1]:
+            raise ValueError("A must be square")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+        h = ctypes.c_void_p()
+        _check(lib.lv_chain_create(a, self.n, lda, k, r_max, mode, model, s, self.workspace.data_ptr(), nbytes,
+                                   _stream(stream, A.device), ctypes.byref(h)))
+        self.handle = h
+
+    def powers(self) -> list[int]:
+        lib = load()
+        cnt = lib.lv_chain_powers(self.handle, None, 0)
+        buf = (ctypes.c_int * cnt)()
+        lib.lv_chain_powers(self.handle, buf, cnt)
+        return list(buf)
+
+    def update(self, U: torch.Tensor, V: torch.Tensor, stream=None) -> None:
+        u, ldu = _mat(U, self.dtype, "U")
+        v, ldv = _mat(V, self.dtype, "V")
+        if U.shape != V.shape:
+            raise ValueError("U and V must have the same shape")
+        _check(load().lv_chain_update(self.handle, u, v, U.shape[1], ldu, ldv, _stream(stream, self.device)))
+
+    def read(self, power: int | None = None, stream=None) -> torch.Tensor:
+        power = self.k if power is None else power
+        out = torch.empty(self.n, self.n, dtype=self.dtype, device=self.device)
+        _check(load().lv_chain_read(self.handle, power, out.data_ptr(), out.stride(0), _stream(stream, self.device)))
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None:
+            torch.cuda.synchronize(self.device)
+            load().lv_chain_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

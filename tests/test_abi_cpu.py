@@ -173,3 +173,36 @@ def test_general_footprint_and_validation(lib):
                                     None, ctypes.byref(h))
     assert st == L.LV_ENOMEM and str(need) in L.lv_last_error()
     assert lib.lv_view_read_general(None, 1, 0x1000, 4, None) == L.LV_EINVAL
+
+
+def test_chain_footprint_and_validation(lib):
+    from paper_1403_6968_amd import linview as L
+    n_pad = 1024
+    mat = n_pad * n_pad * 4
+    lin = L.load().lv_chain_footprint(1000, 16, 1, L.LV_FP32, L.LV_MODEL_LIN, 0)
+    exp = L.load().lv_chain_footprint(1000, 16, 1, L.LV_FP32, L.LV_MODEL_EXP, 0)
+    skip = L.load().lv_chain_footprint(1000, 16, 1, L.LV_FP32, L.LV_MODEL_SKIP, 4)
+    # Table 2 (space): k, log k + 1 and log s + k/s stored matrices
+    assert lin >= 16 * mat and exp >= 5 * mat and skip >= 6 * mat
+    assert lin > skip > exp
+    f = L.load().lv_chain_footprint
+    assert f(1000, 12, 1, L.LV_FP32, L.LV_MODEL_LIN, 0) > 0           # linear: any k
+    assert f(1000, 12, 1, L.LV_FP32, L.LV_MODEL_EXP, 0) == 0          # exponential: power of two
+    assert f(1000, 16, 1, L.LV_FP32, L.LV_MODEL_SKIP, 3) == 0         # s not a power of two
+    assert f(1000, 16, 1, L.LV_FP32, L.LV_MODEL_SKIP, 32) == 0        # s > k
+    assert f(1000, 12, 1, L.LV_FP32, L.LV_MODEL_SKIP, 8) == 0         # s does not divide k
+    assert f(1000, 128, 1, L.LV_FP32, L.LV_MODEL_LIN, 0) > 0
+    assert f(1000, 129, 1, L.LV_FP32, L.LV_MODEL_LIN, 0) == 0         # width k * r_pad > 128
+    assert f(1000, 16, 1, L.LV_FP32_BF16SHADOW, L.LV_MODEL_LIN, 0) == 0
+    assert f(1000, 16, 1, L.LV_FP32, 7, 0) == 0
+    h = ctypes.c_void_p()
+    st = lib.lv_chain_create(0x1000, 64, 64, 12, 1, L.LV_FP32, L.LV_MODEL_SKIP, 8, 0x1000, 1 << 30, None,
+                             ctypes.byref(h))
+    assert st == L.LV_EINVAL and "skip" in L.lv_last_error()
+    need = f(64, 8, 1, L.LV_FP32, L.LV_MODEL_LIN, 0)
+    st = lib.lv_chain_create(0x1000, 64, 64, 8, 1, L.LV_FP32, L.LV_MODEL_LIN, 0, 0x1000, need - 1, None,
+                             ctypes.byref(h))
+    assert st == L.LV_ENOMEM and str(need) in L.lv_last_error()
+    assert lib.lv_chain_update(None, 0x1000, 0x1000, 1, 1, 1, None) == L.LV_EINVAL
+    assert lib.lv_chain_read(None, 1, 0x1000, 64, None) == L.LV_EINVAL
+    assert lib.lv_chain_powers(None, None, 0) == -1
