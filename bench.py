@@ -50,7 +50,7 @@ def parse():
     p.add_argument("--no-secondary", action="store_true",
                    help="skip the rank-4, batched and serving workloads")
     p.add_argument("--serve-seconds", type=float, default=2.0)
-    p.add_argument("--only", choices=["rank4", "batched", "serving", "sums", "general"],
+    p.add_argument("--only", choices=["rank4", "batched", "serving", "sums", "general", "models"],
                    help="run one secondary workload alone and print its result (for profilers)")
     return p.parse_args()
 
@@ -161,6 +161,68 @@ def bench_general(torch, lv, synth, dev, steps=100, ps=(1, 16, 64)):
         out[f"p{p}"] = {"hybrid_exp_ms_per_update": ms, "updates_per_s": 1000.0 / ms,
                         "reeval_lin_torch_ms": lin_ms, "reeval_lin_over_hybrid": lin_ms / ms}
     del A
+    return out
+
+
+def _app_a_ops(model, n, k, s=None):
+    """Operations of one rank-1 refresh of every stored matrix, App. A's
+    closed forms (linear, exponential; skip-s: the exponential part up to s
+    plus the k/s - 1 skip products)."""
+    if model == "lin":
+        return n * n * (k * k + k - 1) + 1.5 * n * k * (k - 1)
+    if model == "exp":
+        return n * n * (4 * k - 3) + n * (k - 1) * (2 * k + 5) / 3
+    K = k // s
+    return (n * n * (4 * s - 3) + n * (s - 1) * (2 * s + 5) / 3 + n * n * (k * k / s + k - 2 * s)
+            + (2 * s + 1) * n * s * K * (K - 1) / 2)
+
+
+def bench_models(torch, lv, synth, dev, ks=(4, 8, 16, 32, 64), n=8192, skip_s=4):
+    """k sweep of the iterative models for A^k (the GPU analog of the k sweep
+    of Sec. 7, Fig. mp3, with the models of Table 2), n = 8192, FP32,
+    rank-1 updates: ms per update of IncrExp (the exponential view),
+    IncrLin and IncrSkip-s (model views), ReevalExp (own MFMA squaring
+    chain), with App. A's operation count of each incremental model."""
+    A = torch.from_numpy(synth.gaussian_matrix(n, seed=0, config=2).astype(np.float32)).to(dev)
+    U, V = synth.update_factors(n, 1, 40, seed=0, config=2)
+    Ud = torch.from_numpy(U.astype(np.float32)).to(dev)
+    Vd = torch.from_numpy(V.astype(np.float32)).to(dev)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps):
+        fn(0)
+        torch.cuda.synchronize()
+        a.record()
+        for t in range(reps):
+            fn(1 + t)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    out = {"workload": f"A^k, n={n}, FP32, rank-1 updates, k sweep", "skip_s": skip_s}
+    ws = torch.empty(lv.lv_reeval_footprint(n, 1, lv.LV_FP32), dtype=torch.uint8, device=dev)
+    res = torch.empty(n, n, dtype=torch.float32, device=dev)
+    for k in ks:
+        row = {}
+        view = lv.View(A, k)
+        row["incr_exp_ms"] = timed(lambda t: view.update(Ud[t], Vd[t]), 20)
+        view.close()
+        del view
+        for name, model, s, reps in (("incr_lin_ms", lv.LV_MODEL_LIN, 0, 3 if k >= 32 else 8),
+                                     ("incr_skip_ms", lv.LV_MODEL_SKIP, skip_s, 8)):
+            if model == lv.LV_MODEL_SKIP and k < skip_s:
+                continue
+            ch = lv.Chain(A, k, model=model, s=s)
+            row[name] = timed(lambda t: ch.update(Ud[t], Vd[t]), reps)
+            ch.close()
+            del ch
+            torch.cuda.empty_cache()
+        row["reeval_exp_ms"] = timed(lambda t: lv.lv_reeval(A, k, Ud[t], Vd[t], lv.LV_FP32, res, ws), 2)
+        row["ops_app_a"] = {"lin": _app_a_ops("lin", n, k), "exp": _app_a_ops("exp", n, k),
+                            "skip": _app_a_ops("skip", n, k, skip_s) if k >= skip_s else None}
+        out[f"k{k}"] = row
+        log(f"models k={k}: {row}")
+    del A, ws, res
     return out
 
 
@@ -326,7 +388,8 @@ def main():
               "batched": lambda: bench_batched(torch, lv, synth, dev),
               "serving": lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds),
               "sums": lambda: bench_sums(torch, lv, synth, dev),
-              "general": lambda: bench_general(torch, lv, synth, dev)}[args.only]
+              "general": lambda: bench_general(torch, lv, synth, dev),
+              "models": lambda: bench_models(torch, lv, synth, dev)}[args.only]
         print(json.dumps({"only": args.only, "result": fn()}), flush=True)
         return
     n, k, r = args.n, args.k, args.rank
