@@ -46,3 +46,9 @@ from .models_oracle import (  # noqa: F401
     incr_update_model,
     paper_cost,
 )
+from .ols_oracle import (  # noqa: F401
+    reeval_ols,
+    ols_delta_z,
+    sherman_morrison,
+    incr_update_ols,
+)
