@@ -50,7 +50,7 @@ def parse():
     p.add_argument("--no-secondary", action="store_true",
                    help="skip the rank-4, batched and serving workloads")
     p.add_argument("--serve-seconds", type=float, default=2.0)
-    p.add_argument("--only", choices=["rank4", "batched", "serving", "sums", "general", "models"],
+    p.add_argument("--only", choices=["rank4", "batched", "serving", "sums", "general", "models", "ols"],
                    help="run one secondary workload alone and print its result (for profilers)")
     return p.parse_args()
 
@@ -226,6 +226,54 @@ def bench_models(torch, lv, synth, dev, ks=(4, 8, 16, 32, 64), n=8192, skip_s=4)
     return out
 
 
+def bench_ols(torch, lv, synth, dev, m=16384, n=8192, p=16, steps=50):
+    """Least squares under data changes (Sec. 5.1, Sherman-Morrison), X
+    16384 x 8192, Y 16384 x 16, FP32: ms per row change and per dense
+    rank-1 change of X, against re-evaluation (the view's own creation:
+    X^T X, Newton-Schulz inverse, beta; and torch: X^T X, Cholesky solve)."""
+    g = synth.rng(0, 2, 94)
+    X = torch.from_numpy(g.standard_normal((m, n)).astype(np.float32)).to(dev)
+    Y = torch.from_numpy(g.standard_normal((m, p)).astype(np.float32)).to(dev)
+    rows = g.integers(0, m, size=steps + 5)
+    dx = torch.from_numpy((g.standard_normal((steps + 5, n)) * 0.3).astype(np.float32)).to(dev)
+    us = torch.from_numpy((g.standard_normal((steps + 5, m)) * 0.05).astype(np.float32)).to(dev)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ols = lv.Ols(X, Y)
+    torch.cuda.synchronize()
+    create_s = time.perf_counter() - t0
+    info = ols.info()
+
+    def timed(fn, reps):
+        fn(0)
+        torch.cuda.synchronize()
+        a.record()
+        for t in range(reps):
+            fn(1 + t)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+    row_ms = timed(lambda t: ols.update_row(int(rows[t]), dx[t]), steps)
+    dense_ms = timed(lambda t: ols.update(us[t], dx[t]), steps // 2)
+    ols.close()
+    del ols
+    torch.cuda.empty_cache()
+
+    def torch_reeval(t):
+        Z = X.t() @ X
+        L = torch.linalg.cholesky(Z)
+        return torch.cholesky_solve(X.t() @ Y, L)
+    torch_ms = timed(torch_reeval, 3)
+    del X, Y
+    alg = 3 * n * n * 4
+    return {"workload": f"OLS X {m}x{n}, Y {m}x{p}, FP32", "row_update_ms": row_ms, "dense_update_ms": dense_ms,
+            "row_updates_per_s": 1000.0 / row_ms, "row_update_alg_bytes": alg,
+            "row_update_alg_GBps": alg / (row_ms * 1e-3) / 1e9, "reeval_own_create_s": create_s,
+            "newton_schulz": info, "reeval_torch_cholesky_ms": torch_ms,
+            "speedup_row_vs_torch_reeval": torch_ms / row_ms}
+
+
 def bench_batched(torch, lv, synth, dev, rounds=30):
     """64 views, n in {512..4096}, k in {8, 16}, rank 1..8, FP32: one graph
     replay per round (every view applies one update)."""
@@ -389,7 +437,8 @@ def main():
               "serving": lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds),
               "sums": lambda: bench_sums(torch, lv, synth, dev),
               "general": lambda: bench_general(torch, lv, synth, dev),
-              "models": lambda: bench_models(torch, lv, synth, dev)}[args.only]
+              "models": lambda: bench_models(torch, lv, synth, dev),
+              "ols": lambda: bench_ols(torch, lv, synth, dev)}[args.only]
         print(json.dumps({"only": args.only, "result": fn()}), flush=True)
         return
     n, k, r = args.n, args.k, args.rank

@@ -431,6 +431,49 @@ int lv_chain_powers(const lv_chain* c, int* powers, int cap);
 /* Release the handle (the caller frees the workspace).  NULL is ignored. */
 void lv_chain_destroy(lv_chain* c);
 
+/* ---------------------------------------------------------------- OLS
+ *
+ * Ordinary least squares kept current under rank-1 changes of the data
+ * (Sec. 5.1, with the Sherman-Morrison formula of Sec. 4): X is m x n
+ * (predictors, m >= n), Y is m x p (responses), W = (X^T X)^{-1} and the
+ * estimate beta = W X^T Y (n x p).  For Delta X = u v^T,
+ *     Delta(X^T X) = p1 q1^T + p2 q2^T,  p1 = q2 = v,  q1 = X^T u,
+ *                    p2 = X^T u + v (u^T u),
+ * W takes the two outer products in turn by Sherman-Morrison (Delta W =
+ * R S^T, rank 2) and Delta beta = R S^T X^T Y + W v u^T Y + R S^T v u^T Y,
+ * all from the old X and W; X, X^T Y, W and beta are then updated.  Per
+ * update: one read of W, one read and write of W, O(m n) for X^T u and
+ * X += u v^T (O(n) with lv_ols_update_row), O(n p) for beta.  Both
+ * X^T X and its updated value must be nonsingular (the formula's
+ * condition; a singular update gives non-finite values).
+ * Creation (re-evaluation) forms X^T X and X^T Y in double, inverts by the
+ * Newton-Schulz iteration on the double matrix cores (synchronizes the
+ * stream once per iteration; LV_EINVAL if X^T X is singular or too
+ * ill-conditioned for the mode), and rounds W, X^T Y and beta once to the mode's type.
+ * Modes LV_FP64, LV_FP32; 1 <= n <= 32768, n <= m <= 2^22, 1 <= p <= 64.
+ * X, Y (device, leading dimensions ldx >= n, ldy >= p) are copied. */
+#define LV_OLS_BETA 0      /* n x p */
+#define LV_OLS_INVERSE 1   /* W, n x n */
+#define LV_OLS_X 2         /* the current data, m x n */
+
+typedef struct lv_ols lv_ols;
+
+size_t lv_ols_footprint(int64_t m, int64_t n, int64_t p, lv_mode mode);
+lv_status lv_ols_create(const void* X, int64_t m, int64_t n, int64_t ldx, const void* Y, int64_t p,
+                        int64_t ldy, lv_mode mode, void* workspace, size_t ws_bytes, void* stream,
+                        lv_ols** out);
+/* Delta X = u v^T; u (m elements) and v (n elements) on the device. */
+lv_status lv_ols_update(lv_ols* o, const void* u, const void* v, void* stream);
+/* Row change Delta X = e_row dx^T (dx: n elements on the device). */
+lv_status lv_ols_update_row(lv_ols* o, int64_t row, const void* dx, void* stream);
+/* Copy LV_OLS_BETA, LV_OLS_INVERSE or LV_OLS_X to out (device, ld ldo). */
+lv_status lv_ols_read(const lv_ols* o, int what, void* out, int64_t ldo, void* stream);
+/* Creation diagnostics: Newton-Schulz iterations, the final residual
+ * max|Z W - I| and the infinity-norm condition number ||Z|| ||W|| (creation
+ * fails when it exceeds 0.1 / unit roundoff of the mode). */
+lv_status lv_ols_info(const lv_ols* o, int* iterations, double* residual, double* cond);
+void lv_ols_destroy(lv_ols* o);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,6 +24,7 @@ LV_OK, LV_EINVAL, LV_ENOMEM, LV_EDEVICE, LV_ESTATE = 0, 1, 2, 3, 4
 LV_FP64, LV_FP32, LV_FP32_BF16SHADOW = 0, 1, 2
 LV_WITH_SUMS = 1
 LV_MODEL_EXP, LV_MODEL_LIN, LV_MODEL_SKIP = 0, 1, 2
+LV_OLS_BETA, LV_OLS_INVERSE, LV_OLS_X = 0, 1, 2
 
 _MODE_DTYPE = {LV_FP64: torch.float64, LV_FP32: torch.float32, LV_FP32_BF16SHADOW: torch.float32}
 
@@ -39,7 +40,8 @@ EXPORTED = (
     "lv_view_footprint_ex", "lv_view_create_ex", "lv_view_read_sum",
     "lv_view_footprint_general", "lv_view_create_general", "lv_view_read_general",
     "lv_chain_footprint", "lv_chain_create", "lv_chain_update", "lv_chain_read", "lv_chain_powers",
-    "lv_chain_destroy",
+    "lv_chain_destroy", "lv_ols_footprint", "lv_ols_create", "lv_ols_update", "lv_ols_update_row",
+    "lv_ols_read", "lv_ols_info", "lv_ols_destroy",
     "lv_server_poll", "lv_server_drain", "lv_server_stats", "lv_server_destroy",
 )
 
@@ -143,6 +145,13 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "lv_chain_read": (I32, [P, I32, P, I64, P]),
         "lv_chain_powers": (I32, [P, c.POINTER(I32), I32]),
         "lv_chain_destroy": (None, [P]),
+        "lv_ols_footprint": (SZ, [I64, I64, I64, I32]),
+        "lv_ols_create": (I32, [P, I64, I64, I64, P, I64, I64, I32, P, SZ, P, c.POINTER(P)]),
+        "lv_ols_update": (I32, [P, P, P, P]),
+        "lv_ols_update_row": (I32, [P, I64, P, P]),
+        "lv_ols_read": (I32, [P, I32, P, I64, P]),
+        "lv_ols_info": (I32, [P, c.POINTER(I32), c.POINTER(c.c_double), c.POINTER(c.c_double)]),
+        "lv_ols_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -679,6 +688,70 @@ class Chain:
         if getattr(self, "handle", None) is not None:
             torch.cuda.synchronize(self.device)
             load().lv_chain_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ols:
+    """Least squares beta = (X^T X)^{-1} X^T Y kept current under rank-1
+    changes of X (Sherman-Morrison); X (m x n) and Y (m x p) device tensors."""
+
+    def __init__(self, X: torch.Tensor, Y: torch.Tensor, mode: int | None = None, stream=None):
+        if mode is None:
+            mode = LV_FP64 if X.dtype == torch.float64 else LV_FP32
+        self.mode, self.dtype = mode, _MODE_DTYPE[mode]
+        self.m, self.n = X.shape
+        self.p = Y.shape[1]
+        self.device = X.device
+        lib = load()
+        nbytes = int(lib.lv_ols_footprint(self.m, self.n, self.p, mode))
+        if nbytes == 0:
+            _check(lib.lv_ols_create(None, self.m, self.n, self.n, None, self.p, self.p, mode, None, 0, None,
+                                     ctypes.byref(ctypes.c_void_p())))
+        x, ldx = _mat(X, self.dtype, "X")
+        y, ldy = _mat(Y, self.dtype, "Y")
+        if Y.shape[0] != self.m:
+            raise ValueError("X and Y must have the same number of rows")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
+        h = ctypes.c_void_p()
+        _check(lib.lv_ols_create(x, self.m, self.n, ldx, y, self.p, ldy, mode, self.workspace.data_ptr(), nbytes,
+                                 _stream(stream, X.device), ctypes.byref(h)))
+        self.handle = h
+
+    def _vec(self, x: torch.Tensor, length: int, name: str) -> int:
+        if x.device.type != "cuda" or x.dtype != self.dtype or not x.is_contiguous() or x.numel() != length:
+            raise ValueError(f"{name} must be a contiguous {self.dtype} device vector of {length} elements")
+        return x.data_ptr()
+
+    def update(self, u: torch.Tensor, v: torch.Tensor, stream=None) -> None:
+        """Delta X = u v^T."""
+        _check(load().lv_ols_update(self.handle, self._vec(u, self.m, "u"), self._vec(v, self.n, "v"),
+                                    _stream(stream, self.device)))
+
+    def update_row(self, row: int, dx: torch.Tensor, stream=None) -> None:
+        """Delta X = e_row dx^T."""
+        _check(load().lv_ols_update_row(self.handle, row, self._vec(dx, self.n, "dx"), _stream(stream, self.device)))
+
+    def read(self, what: int = LV_OLS_BETA, stream=None) -> torch.Tensor:
+        shape = {LV_OLS_BETA: (self.n, self.p), LV_OLS_INVERSE: (self.n, self.n), LV_OLS_X: (self.m, self.n)}[what]
+        out = torch.empty(*shape, dtype=self.dtype, device=self.device)
+        _check(load().lv_ols_read(self.handle, what, out.data_ptr(), shape[1], _stream(stream, self.device)))
+        return out
+
+    def info(self) -> dict:
+        it, res, cond = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+        _check(load().lv_ols_info(self.handle, ctypes.byref(it), ctypes.byref(res), ctypes.byref(cond)))
+        return {"iterations": it.value, "residual": res.value, "cond_inf": cond.value}
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None:
+            torch.cuda.synchronize(self.device)
+            load().lv_ols_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -206,3 +206,26 @@ def test_chain_footprint_and_validation(lib):
     assert lib.lv_chain_update(None, 0x1000, 0x1000, 1, 1, 1, None) == L.LV_EINVAL
     assert lib.lv_chain_read(None, 1, 0x1000, 64, None) == L.LV_EINVAL
     assert lib.lv_chain_powers(None, None, 0) == -1
+
+
+def test_ols_footprint_and_validation(lib):
+    from paper_1403_6968_amd import linview as L
+    f = L.load().lv_ols_footprint
+    a = f(2000, 1000, 4, L.LV_FP32)
+    # X (m x n), W (n x n) and the four double n x n creation buffers
+    assert a >= 2048 * 1024 * 4 + 1024 * 1024 * 4 + 4 * 1024 * 1024 * 8
+    assert f(2000, 1000, 4, L.LV_FP64) > a
+    assert f(999, 1000, 4, L.LV_FP32) == 0          # m < n
+    assert f(2000, 1000, 65, L.LV_FP32) == 0        # p > 64
+    assert f(2000, 1000, 0, L.LV_FP32) == 0
+    assert f(70000, 40000, 1, L.LV_FP32) == 0       # n > 32768
+    assert f(2000, 1000, 4, L.LV_FP32_BF16SHADOW) == 0
+    h = ctypes.c_void_p()
+    st = lib.lv_ols_create(0x1000, 10, 20, 20, 0x1000, 1, 1, L.LV_FP32, 0x1000, 1 << 30, None, ctypes.byref(h))
+    assert st == L.LV_EINVAL and "m = 10" in L.lv_last_error()
+    need = f(512, 256, 2, L.LV_FP32)
+    st = lib.lv_ols_create(0x1000, 512, 256, 256, 0x1000, 2, 2, L.LV_FP32, 0x1000, need - 1, None, ctypes.byref(h))
+    assert st == L.LV_ENOMEM and str(need) in L.lv_last_error()
+    assert lib.lv_ols_update(None, 0x1000, 0x1000, None) == L.LV_EINVAL
+    assert lib.lv_ols_update_row(None, 0, 0x1000, None) == L.LV_EINVAL
+    assert lib.lv_ols_read(None, 0, 0x1000, 1, None) == L.LV_EINVAL
