@@ -602,6 +602,8 @@ def main():
         for name, fn in (("rank4_n16384", lambda: bench_rank4(torch, lv, synth, dev)),
                          ("sums_n8192", lambda: bench_sums(torch, lv, synth, dev)),
                          ("general_n8192", lambda: bench_general(torch, lv, synth, dev)),
+                         ("models_k_sweep_n8192", lambda: bench_models(torch, lv, synth, dev)),
+                         ("ols_16384x8192", lambda: bench_ols(torch, lv, synth, dev)),
                          ("batched_64_views", lambda: bench_batched(torch, lv, synth, dev)),
                          ("serving_32_views", lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds)),
                          ("serving_32_views_fp32",
