@@ -16,6 +16,16 @@ template <typename T> __device__ __forceinline__ void st16(T* p, const V16<T>& x
   *reinterpret_cast<V16<T>*>(p) = x;
 }
 
+// Streaming variants for data touched once per pass (the stored powers):
+// non-temporal loads and stores.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <typename T> __device__ __forceinline__ V16<T> ld16_nt(const T* p) {
+  return __builtin_bit_cast(V16<T>, __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p)));
+}
+template <typename T> __device__ __forceinline__ void st16_nt(T* p, const V16<T>& x) {
+  __builtin_nontemporal_store(__builtin_bit_cast(u32x4, x), reinterpret_cast<u32x4*>(p));
+}
+
 __device__ __forceinline__ int wave_id() {
   return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }

@@ -104,7 +104,7 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
   if (wave < nblocks) {
     const int64_t r0 = row0 + wave * RB;
 #pragma unroll
-    for (int t = 0; t < RB; ++t) p[t] = ld16(P + (r0 + t) * ldp + lc);
+    for (int t = 0; t < RB; ++t) p[t] = ld16_nt(P + (r0 + t) * ldp + lc);
   }
 
   for (int b = wave; b < nblocks; b += 4) {
@@ -134,13 +134,13 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
           for (int c = 1; c < R; ++c) d = fma(ui[c], vcol[q][c], d);
           p[t].v[q] += d;
         }
-        st16(P + i * ldp + lc, p[t]);
+        st16_nt(P + i * ldp + lc, p[t]);
       }
     }
     if (b + 4 < nblocks) {
       const int64_t rn = r0 + 4 * RB;
 #pragma unroll
-      for (int t = 0; t < RB; ++t) p[t] = ld16(P + (rn + t) * ldp + lc);
+      for (int t = 0; t < RB; ++t) p[t] = ld16_nt(P + (rn + t) * ldp + lc);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();

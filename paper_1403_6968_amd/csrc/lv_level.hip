@@ -296,7 +296,7 @@ __device__ __forceinline__ void update_body(T* __restrict__ P, const int64_t ldp
   for (int rb = wave * RB; rb < nrows; rb += 4 * RB) {
     V16<T> p[RB];
 #pragma unroll
-    for (int t = 0; t < RB; ++t) p[t] = ld16(P + (int64_t)(row0 + rb + t) * ldp + lc);
+    for (int t = 0; t < RB; ++t) p[t] = ld16_nt(P + (int64_t)(row0 + rb + t) * ldp + lc);
     T d[RB][EPL];
 #pragma unroll
     for (int t = 0; t < RB; ++t)
@@ -321,7 +321,7 @@ __device__ __forceinline__ void update_body(T* __restrict__ P, const int64_t ldp
     for (int t = 0; t < RB; ++t) {
 #pragma unroll
       for (int q = 0; q < EPL; ++q) p[t].v[q] += d[t][q];
-      st16(P + (int64_t)(row0 + rb + t) * ldp + lc, p[t]);
+      st16_nt(P + (int64_t)(row0 + rb + t) * ldp + lc, p[t]);
       if constexpr (SH) {
         static_assert(EPL == 4, "shadows are kept for float storage only");
         ushort4 sh;
@@ -367,8 +367,8 @@ __device__ __forceinline__ void update_mfma_body(float* __restrict__ P, const in
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int v = 0; v < 16; ++v)
-        p[a][b][v] = P[(int64_t)(row0 + wm * 64 + a * 32 + 8 * (v / 4) + 4 * lh + (v % 4)) * ldp + col0 + wn * 64 +
-                       b * 32 + l32];
+        p[a][b][v] = __builtin_nontemporal_load(&P[(int64_t)(row0 + wm * 64 + a * 32 + 8 * (v / 4) + 4 * lh +
+                                                         (v % 4)) * ldp + col0 + wn * 64 + b * 32 + l32]);
   v16f acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -415,7 +415,7 @@ __device__ __forceinline__ void update_mfma_body(float* __restrict__ P, const in
         const int64_t o = (int64_t)(row0 + wm * 64 + a * 32 + 8 * (v / 4) + 4 * lh + (v % 4)) * ldp + col0 +
                           wn * 64 + b * 32 + l32;
         const float x = p[a][b][v] + acc[a][b][v];
-        P[o] = x;
+        __builtin_nontemporal_store(x, &P[o]);
         if constexpr (SH) S[o] = bf16_rne(x);
       }
 }
@@ -454,8 +454,8 @@ __device__ __forceinline__ void update_split_body(float* __restrict__ P, const i
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int v = 0; v < 16; ++v)
-        p[a][b][v] = P[(int64_t)(row0 + wm * 64 + a * 32 + 8 * (v / 4) + 4 * lh + (v % 4)) * ldp + col0 + wn * 64 +
-                       b * 32 + l32];
+        p[a][b][v] = __builtin_nontemporal_load(&P[(int64_t)(row0 + wm * 64 + a * 32 + 8 * (v / 4) + 4 * lh +
+                                                         (v % 4)) * ldp + col0 + wn * 64 + b * 32 + l32]);
   v16f acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -516,7 +516,7 @@ __device__ __forceinline__ void update_split_body(float* __restrict__ P, const i
         const int64_t o = (int64_t)(row0 + wm * 64 + a * 32 + 8 * (v / 4) + 4 * lh + (v % 4)) * ldp + col0 +
                           wn * 64 + b * 32 + l32;
         const float x = p[a][b][v] + acc[a][b][v];
-        P[o] = x;
+        __builtin_nontemporal_store(x, &P[o]);
         if constexpr (SH) S[o] = bf16_rne(x);
       }
 }

@@ -87,7 +87,8 @@ __device__ __forceinline__ void skinny_body(const uint16_t* __restrict__ S, cons
   auto fetch = [&](u16x8 (&pre)[CRB / 8], float (&pv)[VPT], const int r0) {
 #pragma unroll
     for (int i = 0; i < CRB / 8; ++i)
-      pre[i] = *reinterpret_cast<const u16x8*>(S + (int64_t)(r0 + srow + 8 * i) * ldp + col0 + sgrp * 8);
+      pre[i] = __builtin_nontemporal_load(reinterpret_cast<const u16x8*>(S + (int64_t)(r0 + srow + 8 * i) * ldp + col0 +
+                                                                     sgrp * 8));
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
       const int idx = tid + 256 * i;
@@ -251,7 +252,8 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
   float pv[VPT];
   auto fetch = [&](const int r0) {
     static_for<0, CR / 4>([&](auto i) {
-      pre[i] = *reinterpret_cast<const f32x4*>(P + (int64_t)(r0 + srow + 4 * i) * ldp + col0 + sgrp * 4);
+      pre[i] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(P + (int64_t)(r0 + srow + 4 * i) * ldp + col0 +
+                                                                     sgrp * 4));
     });
     static_for<0, VPT>([&](auto i) {
       const int idx = tid + 256 * i;
