@@ -13,6 +13,7 @@
 // inverts by the Newton-Schulz iteration X <- X (2I - Z X) on the double
 // matrix cores.
 #include "linview.h"
+#include "lv_device.h"
 #include "lv_internal.h"
 #include "lv_view_impl.h"
 
@@ -158,87 +159,176 @@ k_ols_operands(const double* __restrict__ xu, const double* __restrict__ uu, con
   Qk[j * 4 + 3] = T(0);
 }
 
+constexpr int kVecRows = 64;   // rows per block of k_ols_vectors (4 threads per row)
+
+// The 4-element partial record of row j in tile t (16 bytes for float, two
+// 16-byte loads for double).
+template <typename T>
+__device__ __forceinline__ void load4(const T* __restrict__ rec, double (&o)[4]) {
+  if constexpr (sizeof(T) == 4) {
+    const V16<float> a = ld16(reinterpret_cast<const float*>(rec));
+    o[0] = a.v[0]; o[1] = a.v[1]; o[2] = a.v[2]; o[3] = a.v[3];
+  } else {
+    const V16<double> a = ld16(reinterpret_cast<const double*>(rec));
+    const V16<double> b = ld16(reinterpret_cast<const double*>(rec) + 2);
+    o[0] = a.v[0]; o[1] = a.v[1]; o[2] = b.v[0]; o[3] = b.v[1];
+  }
+}
+
 // vec[j] = (a1, a2, wv, b1, b2): W p1, W p2, W v, W^T q1, W^T q2 from the
-// pass's partials (tile order, double).
+// pass's partials, and this block's partial sums of the four dot products
+// q1^T a1, b1^T p2, a1^T q2, q2^T a2 (dpart[blk][4]).  Four threads per row
+// each sum every fourth tile; the four sums are added in order (double).
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_ols_vectors(const T* __restrict__ partX, int nct, const T* __restrict__ partY, int nrt, int64_t n_pad,
-              double* __restrict__ vec) {
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= n_pad) return;
+              const T* __restrict__ Pk, const T* __restrict__ Qk, double* __restrict__ vec, double* __restrict__ dpart) {
+  __shared__ double sx[5][256];
+  __shared__ double red[4][kVecRows];
+  const int lr = (int)threadIdx.x >> 2, q = (int)threadIdx.x & 3;
+  const int64_t j = (int64_t)blockIdx.x * kVecRows + lr;      // n_pad is a multiple of 256
   double x0 = 0.0, x1 = 0.0, x2 = 0.0, y0 = 0.0, y1 = 0.0;
-  for (int t = 0; t < nct; ++t) {
-    const T* px = partX + ((int64_t)t * n_pad + j) * 4;
-    x0 += (double)px[0]; x1 += (double)px[1]; x2 += (double)px[2];
+  for (int t = q; t < nct; t += 4) {
+    double r[4];
+    load4(partX + ((int64_t)t * n_pad + j) * 4, r);
+    x0 += r[0]; x1 += r[1]; x2 += r[2];
   }
-  for (int t = 0; t < nrt; ++t) {
-    const T* py = partY + ((int64_t)t * n_pad + j) * 4;
-    y0 += (double)py[0]; y1 += (double)py[1];
+  for (int t = q; t < nrt; t += 4) {
+    double r[4];
+    load4(partY + ((int64_t)t * n_pad + j) * 4, r);
+    y0 += r[0]; y1 += r[1];
   }
-  double* o = vec + j * 5;
-  o[0] = x0; o[1] = x1; o[2] = x2; o[3] = y0; o[4] = y1;
+  sx[0][threadIdx.x] = x0; sx[1][threadIdx.x] = x1; sx[2][threadIdx.x] = x2;
+  sx[3][threadIdx.x] = y0; sx[4][threadIdx.x] = y1;
+  __syncthreads();
+  if (threadIdx.x < kVecRows) {
+    const int b = (int)threadIdx.x * 4;
+    const int64_t jj = (int64_t)blockIdx.x * kVecRows + threadIdx.x;
+    double o5[5];
+#pragma unroll
+    for (int e = 0; e < 5; ++e) o5[e] = ((sx[e][b] + sx[e][b + 1]) + sx[e][b + 2]) + sx[e][b + 3];
+    double* o = vec + jj * 5;
+#pragma unroll
+    for (int e = 0; e < 5; ++e) o[e] = o5[e];
+    const double q1 = (double)Qk[jj * 4 + 0], q2 = (double)Qk[jj * 4 + 1], p2 = (double)Pk[jj * 4 + 1];
+    red[0][threadIdx.x] = q1 * o5[0];
+    red[1][threadIdx.x] = o5[3] * p2;
+    red[2][threadIdx.x] = o5[0] * q2;
+    red[3][threadIdx.x] = q2 * o5[1];
+  }
+  __syncthreads();
+  for (int w = kVecRows / 2; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) red[e][threadIdx.x] += red[e][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) dpart[blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// dots[0..4) = q1^T a1, b1^T p2, a1^T q2, q2^T a2 (one block each, fixed order).
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_ols_dots(const double* __restrict__ vec, const T* __restrict__ Pk, const T* __restrict__ Qk, int64_t n_pad,
-           double* __restrict__ dots) {
-  const int which = blockIdx.x;
+// out[b] = sum over i < nblk of part[i * stride + b] for b = blockIdx.x:
+// 256 threads sum strided subsets, then a fixed-order tree.
+__global__ void __launch_bounds__(256) k_sum_partials(const double* __restrict__ part, int nblk, int stride,
+                                                      double* __restrict__ out) {
+  __shared__ double red[256];
   double acc = 0.0;
-  for (int64_t j = threadIdx.x; j < n_pad; j += 256) {
-    const double* o = vec + j * 5;
-    const double x = which == 0 ? (double)Qk[j * 4 + 0] * o[0]
-                   : which == 1 ? o[3] * (double)Pk[j * 4 + 1]
-                   : which == 2 ? o[0] * (double)Qk[j * 4 + 1]
-                                : (double)Qk[j * 4 + 1] * o[1];
-    acc += x;
+  for (int i = threadIdx.x; i < nblk; i += 256) acc += part[(int64_t)i * stride + blockIdx.x];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
   }
-  acc = block_sum(acc);
-  if (threadIdx.x == 0) dots[which] = acc;
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
-// Update factors R = [r1, r2], S = [s1, s2] of Delta W (dots d0..d3 as
-// k_ols_dots names them):
-//   l1 = -1 / (1 + q1^T W p1),  r1 = l1 W p1,  s1 = W^T q1,
+// Update factors R = [r1, r2], S = [s1, s2] of Delta W, with the dots
+// d0 = q1^T W p1, d1 = s1^T p2, d2 = r1^T q2 / l1, d3 = q2^T W p2:
+//   l1 = -1 / (1 + d0),  r1 = l1 W p1,  s1 = W^T q1,
 //   W1 p2 = W p2 + r1 (s1^T p2) = W p2 + l1 W p1 d1,
 //   W1^T q2 = W^T q2 + s1 (r1^T q2) = W^T q2 + l1 W^T q1 d2,
 //   l2 = -1 / (1 + q2^T W1 p2) = -1 / (1 + d3 + l1 d2 d1),
-//   r2 = l2 W1 p2,  s2 = W1^T q2.
+//   r2 = l2 W1 p2,  s2 = W1^T q2;
+// then this block's partials of S^T C (2 x pp) and S^T v (2) with the stored
+// (rounded) S: spart[blk][e * pp + c], spart[blk][2 pp + e].
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_ols_rs(const double* __restrict__ vec, const double* __restrict__ dots, T* __restrict__ Rs, T* __restrict__ Ss,
-         int64_t n_pad) {
+k_ols_rs(const double* __restrict__ vec, const double* __restrict__ dots, T* __restrict__ Rs,
+         T* __restrict__ Ss, const T* __restrict__ C, const T* __restrict__ v, int pp, double* __restrict__ spart) {
+  __shared__ double ls[2][256];
+  __shared__ double red[2][256];
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= n_pad) return;
   const double l1 = -1.0 / (1.0 + dots[0]);
   const double l2 = -1.0 / (1.0 + dots[3] + l1 * dots[2] * dots[1]);
   const double* o = vec + j * 5;
   const double w1p2 = o[1] + l1 * o[0] * dots[1];
   const double w1q2 = o[4] + l1 * o[3] * dots[2];
+  const T s1 = (T)o[3], s2 = (T)w1q2;
   Rs[j * 2 + 0] = (T)(l1 * o[0]);
   Rs[j * 2 + 1] = (T)(l2 * w1p2);
-  Ss[j * 2 + 0] = (T)o[3];
-  Ss[j * 2 + 1] = (T)w1q2;
+  Ss[j * 2 + 0] = s1;
+  Ss[j * 2 + 1] = s2;
+  ls[0][threadIdx.x] = (double)s1;
+  ls[1][threadIdx.x] = (double)s2;
+  __syncthreads();
+  // S^T C: thread (g, c) = (tid / pp, tid % pp) sums rows g, g + G, ... of
+  // the block (G = 256 / pp groups), then the groups are added in order
+  const int64_t r0 = (int64_t)blockIdx.x * 256;
+  const int G = 256 / pp;
+  const int c = (int)threadIdx.x % pp, g = (int)threadIdx.x / pp;
+  double a0 = 0.0, a1 = 0.0;
+  for (int r = g; r < 256; r += G) {
+    const double cv = (double)C[(r0 + r) * pp + c];
+    a0 = fma(ls[0][r], cv, a0);
+    a1 = fma(ls[1][r], cv, a1);
+  }
+  red[0][threadIdx.x] = a0;
+  red[1][threadIdx.x] = a1;
+  const double vj = (double)v[j];
+  double* out = spart + (int64_t)blockIdx.x * (2 * pp + 2);
+  __syncthreads();
+  if ((int)threadIdx.x < 2 * pp) {
+    const int e = (int)threadIdx.x / pp, cc = (int)threadIdx.x % pp;
+    double acc = 0.0;
+    for (int q = 0; q < G; ++q) acc += red[e][q * pp + cc];
+    out[threadIdx.x] = acc;
+  }
+  __syncthreads();
+  // S^T v
+  red[0][threadIdx.x] = ls[0][threadIdx.x] * vj;
+  red[1][threadIdx.x] = ls[1][threadIdx.x] * vj;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 2) out[2 * pp + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// beta += R (S^T C + (S^T v) uY) + (W v) uY;  C += v uY  (C = X^T Y, old
-// values in S^T C), one thread per (row, column).
+// beta += R (S^T C + (S^T v) uY) + (W v) uY;  C += v uY  (C = X^T Y; S^T C
+// from the old C; st = [S^T C (2 x pp), S^T v (2)]), one thread per (row,
+// column).  With X non-null (a row change
+// u = e_row) the thread of column 0 also applies X[row][j] += v[j].
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_ols_beta(const T* __restrict__ Rs, const double* __restrict__ vec, const double* __restrict__ stc,
-           const double* __restrict__ stv, const double* __restrict__ uy, const T* __restrict__ v, T* __restrict__ beta,
-           T* __restrict__ C, int64_t n_pad, int pp) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= n_pad * pp) return;
-  const int64_t j = e / pp;
-  const int c = (int)(e % pp);
-  const double y = uy[c];
-  double d = vec[j * 5 + 2] * y;
-  d = fma((double)Rs[j * 2 + 0], stc[c] + stv[0] * y, d);
-  d = fma((double)Rs[j * 2 + 1], stc[pp + c] + stv[1] * y, d);
-  beta[e] = (T)((double)beta[e] + d);
-  C[e] = (T)((double)C[e] + (double)v[j] * y);
+k_ols_beta(const T* __restrict__ Rs, const double* __restrict__ vec, const double* __restrict__ st,
+           const double* __restrict__ uy, const T* __restrict__ v, T* __restrict__ beta, T* __restrict__ C,
+           int64_t n_pad, int pp, T* __restrict__ X, int64_t row) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n_pad * pp; e += (int64_t)gridDim.x * 256) {
+    const int64_t j = e / pp;
+    const int c = (int)(e % pp);
+    const double y = uy[c];
+    double d = vec[j * 5 + 2] * y;
+    d = fma((double)Rs[j * 2 + 0], st[c] + st[2 * pp] * y, d);
+    d = fma((double)Rs[j * 2 + 1], st[pp + c] + st[2 * pp + 1] * y, d);
+    const double vj = (double)v[j];
+    beta[e] = (T)((double)beta[e] + d);
+    C[e] = (T)((double)C[e] + vj * y);
+    if (X != nullptr && c == 0) X[row * n_pad + j] = (T)((double)X[row * n_pad + j] + vj);
+  }
 }
 
 // X += u v^T over the m_pad x n_pad matrix.
@@ -251,21 +341,27 @@ k_rank1(T* __restrict__ X, int64_t m_pad, int64_t n_pad, const T* __restrict__ u
   }
 }
 
-// Row change (u = e_row): X^T u = X[row], u^T u = 1, u^T Y = Y[row].
+// Row change (u = e_row, v = dx): stages v (zero beyond n), the operand
+// slabs with X^T u = X[row] and u^T u = 1, and u^T Y = Y[row].
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_ols_row_stage(const T* __restrict__ X, const T* __restrict__ Y, int64_t row, int64_t n_pad, int pp,
-                double* __restrict__ xu, double* __restrict__ uu, double* __restrict__ uy) {
+k_ols_stage_row(const T* __restrict__ dx, int64_t n, const T* __restrict__ X, const T* __restrict__ Y, int64_t row,
+                int64_t n_pad, int pp, T* __restrict__ vbuf, T* __restrict__ Pk, T* __restrict__ Qk,
+                double* __restrict__ uy) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j < n_pad) xu[j] = (double)X[row * n_pad + j];
   if (j < pp) uy[j] = (double)Y[row * pp + j];
-  if (j == 0) uu[0] = 1.0;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_row_add(T* __restrict__ X, int64_t row, int64_t n_pad, const T* __restrict__ dx) {
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j < n_pad) X[row * n_pad + j] = (T)((double)X[row * n_pad + j] + (double)dx[j]);
+  if (j >= n_pad) return;
+  const T vt = j < n ? dx[j] : T(0);
+  const double vj = (double)vt, x = (double)X[row * n_pad + j];
+  vbuf[j] = vt;
+  Pk[j * 4 + 0] = vt;
+  Pk[j * 4 + 1] = (T)(x + vj);
+  Pk[j * 4 + 2] = vt;
+  Pk[j * 4 + 3] = T(0);
+  Qk[j * 4 + 0] = (T)x;
+  Qk[j * 4 + 1] = vt;
+  Qk[j * 4 + 2] = T(0);
+  Qk[j * 4 + 3] = T(0);
 }
 
 }  // namespace
@@ -275,8 +371,8 @@ struct lv_ols {
   int64_t m, n, p, m_pad, n_pad;
   int pp, elem, nct, nrt;
   lv_mode mode;
-  size_t X, Y, W, C, beta, ubuf, vbuf, Pk, Qk, Rs, Ss, partX, partY, vec, dots;
-  size_t pXu, pUu, pUy, pStc, pStv, red;
+  size_t X, Y, W, C, beta, ubuf, vbuf, Pk, Qk, Rs, Ss, partX, partY, vec;
+  size_t pXu, pUu, pUy, dpart, spart, sums, red;
   size_t Z, Xk, Xn, Tk, C64, B64;
   size_t total;
   char* base;
@@ -321,12 +417,12 @@ void layout_ols(lv_ols& o, int64_t m, int64_t n, int64_t p, lv_mode mode) {
   o.partX = take((size_t)o.nct * np * 4 * e);
   o.partY = take((size_t)o.nrt * np * 4 * e);
   o.vec = take(np * 5 * sizeof(double));
-  o.dots = take(8 * sizeof(double));
   o.pXu = take((mp / kAtbRows) * np * sizeof(double));
   o.pUu = take((mp / kAtbRows) * sizeof(double));
   o.pUy = take((mp / kAtbRows) * pp * sizeof(double));
-  o.pStc = take((np / kAtbRows) * 2 * pp * sizeof(double));
-  o.pStv = take((np / kAtbRows) * 2 * sizeof(double));
+  o.dpart = take((np / kVecRows) * 4 * sizeof(double));
+  o.sums = take((8 + 2 * kOlsMaxCols + 2) * sizeof(double));
+  o.spart = take((np / 256) * (2 * pp + 2) * sizeof(double));
   o.red = take((kRedBlocks + 8) * sizeof(double));
   o.Z = take(np * np * sizeof(double));
   o.Xk = take(np * np * sizeof(double));
@@ -410,54 +506,55 @@ lv_status ols_build(lv_ols* o, hipStream_t s) {
   return st;
 }
 
-// One update; row >= 0 selects the row change Delta X = e_row dx^T (dx
-// staged in vbuf), else Delta X = u v^T (staged in ubuf, vbuf).
+// One update.  row >= 0: the row change Delta X = e_row dx^T (dx: n values
+// on the device, staged here); else Delta X = u v^T with u, v staged in
+// ubuf, vbuf.  Launches: staging (row) or X^T u, u^T u, u^T Y and the
+// operand slabs (dense); the read-only pass over W; vectors and dot
+// partials; factors R, S and the S^T C, S^T v partials; W += R S^T; beta
+// and C (and the row of X); X += u v^T (dense).
 template <typename T>
-lv_status ols_update(lv_ols* o, int64_t row, hipStream_t s) {
+lv_status ols_update(lv_ols* o, int64_t row, const T* dx, hipStream_t s) {
   const int64_t np = o->n_pad, mp = o->m_pad;
   const int pp = o->pp;
-  const unsigned gv = (unsigned)((np + 255) / 256);
+  const unsigned gv = (unsigned)(np / 256);
   lv_status st = LV_OK;
   if (row >= 0) {
-    hipLaunchKernelGGL((k_ols_row_stage<T>), dim3(gv), dim3(256), 0, s, o->at<T>(o->X), o->at<T>(o->Y), row, np, pp,
-                       o->d(o->pXu), o->d(o->pUu), o->d(o->pUy));
+    hipLaunchKernelGGL((k_ols_stage_row<T>), dim3(gv), dim3(256), 0, s, dx, o->n, o->at<T>(o->X), o->at<T>(o->Y), row,
+                       np, pp, o->at<T>(o->vbuf), o->at<T>(o->Pk), o->at<T>(o->Qk), o->d(o->pUy));
     st = hip_check(hipGetLastError(), "row stage");
   } else {
     st = hip_check(launch_atb<T>(1, (int)np, o->at<T>(o->ubuf), 1, o->at<T>(o->X), np, mp, o->d(o->pXu), s), "X^T u");
     if (st == LV_OK) st = hip_check(launch_atb<T>(1, 1, o->at<T>(o->ubuf), 1, o->at<T>(o->ubuf), 1, mp, o->d(o->pUu), s), "u^T u");
     if (st == LV_OK)
       st = hip_check(launch_atb<T>(1, pp, o->at<T>(o->ubuf), 1, o->at<T>(o->Y), pp, mp, o->d(o->pUy), s), "u^T Y");
+    if (st == LV_OK) {
+      hipLaunchKernelGGL((k_ols_operands<T>), dim3(gv), dim3(256), 0, s, o->d(o->pXu), o->d(o->pUu),
+                         o->at<T>(o->vbuf), o->at<T>(o->Pk), o->at<T>(o->Qk), np);
+      st = hip_check(hipGetLastError(), "operands");
+    }
   }
-  if (st != LV_OK) return st;
-  hipLaunchKernelGGL((k_ols_operands<T>), dim3(gv), dim3(256), 0, s, o->d(o->pXu), o->d(o->pUu), o->at<T>(o->vbuf),
-                     o->at<T>(o->Pk), o->at<T>(o->Qk), np);
-  st = hip_check(hipGetLastError(), "operands");
   if (st == LV_OK)
     st = hip_check(launch_level_readonly<T>(4, o->at<T>(o->W), np, np, kTileRows, o->at<T>(o->Pk), o->at<T>(o->Qk), 4,
                                             o->at<T>(o->partX), o->at<T>(o->partY), s),
                    "W [p1 p2 v], W^T [q1 q2]");
   if (st != LV_OK) return st;
-  hipLaunchKernelGGL((k_ols_vectors<T>), dim3(gv), dim3(256), 0, s, o->at<T>(o->partX), o->nct, o->at<T>(o->partY),
-                     o->nrt, np, o->d(o->vec));
-  hipLaunchKernelGGL((k_ols_dots<T>), dim3(4), dim3(256), 0, s, o->d(o->vec), o->at<T>(o->Pk), o->at<T>(o->Qk), np,
-                     o->d(o->dots));
-  hipLaunchKernelGGL((k_ols_rs<T>), dim3(gv), dim3(256), 0, s, o->d(o->vec), o->d(o->dots), o->at<T>(o->Rs),
-                     o->at<T>(o->Ss), np);
+  const int nvb = (int)(np / kVecRows);
+  hipLaunchKernelGGL((k_ols_vectors<T>), dim3((unsigned)nvb), dim3(256), 0, s, o->at<T>(o->partX), o->nct,
+                     o->at<T>(o->partY), o->nrt, np, o->at<T>(o->Pk), o->at<T>(o->Qk), o->d(o->vec), o->d(o->dpart));
+  hipLaunchKernelGGL(k_sum_partials, dim3(4), dim3(256), 0, s, o->d(o->dpart), nvb, 4, o->d(o->sums));
+  hipLaunchKernelGGL((k_ols_rs<T>), dim3(gv), dim3(256), 0, s, o->d(o->vec), o->d(o->sums),
+                     o->at<T>(o->Rs), o->at<T>(o->Ss), o->at<T>(o->C), o->at<T>(o->vbuf), pp, o->d(o->spart));
   st = hip_check(hipGetLastError(), "Sherman-Morrison factors");
   if (st == LV_OK)
     st = hip_check(launch_level_update<T>(2, o->at<T>(o->W), np, np, o->at<T>(o->Rs), o->at<T>(o->Ss), 2, s),
                    "W += R S^T");
-  if (st == LV_OK)
-    st = hip_check(launch_atb<T>(2, pp, o->at<T>(o->Ss), 2, o->at<T>(o->C), pp, np, o->d(o->pStc), s), "S^T C");
-  if (st == LV_OK)
-    st = hip_check(launch_atb<T>(2, 1, o->at<T>(o->Ss), 2, o->at<T>(o->vbuf), 1, np, o->d(o->pStv), s), "S^T v");
   if (st != LV_OK) return st;
+  hipLaunchKernelGGL(k_sum_partials, dim3((unsigned)(2 * pp + 2)), dim3(256), 0, s, o->d(o->spart), (int)gv,
+                     2 * pp + 2, o->d(o->sums) + 8);
   hipLaunchKernelGGL((k_ols_beta<T>), dim3((unsigned)((np * pp + 255) / 256)), dim3(256), 0, s, o->at<T>(o->Rs),
-                     o->d(o->vec), o->d(o->pStc), o->d(o->pStv), o->d(o->pUy), o->at<T>(o->vbuf), o->at<T>(o->beta),
-                     o->at<T>(o->C), np, pp);
-  if (row >= 0)
-    hipLaunchKernelGGL((k_row_add<T>), dim3(gv), dim3(256), 0, s, o->at<T>(o->X), row, np, o->at<T>(o->vbuf));
-  else
+                     o->d(o->vec), o->d(o->sums) + 8, o->d(o->pUy), o->at<T>(o->vbuf), o->at<T>(o->beta),
+                     o->at<T>(o->C), np, pp, row >= 0 ? o->at<T>(o->X) : nullptr, row);
+  if (row < 0)
     hipLaunchKernelGGL((k_rank1<T>), dim3(2048), dim3(256), 0, s, o->at<T>(o->X), mp, np, o->at<T>(o->ubuf),
                        o->at<T>(o->vbuf));
   return hip_check(hipGetLastError(), "beta, X");
@@ -525,14 +622,14 @@ lv_status lv_ols_update(lv_ols* o, const void* u, const void* v, void* stream) {
     if (st == LV_OK)
       st = hip_check(launch_copy_rect<double, double>(static_cast<const double*>(v), 1, o->n, 1,
                                                       o->at<double>(o->vbuf), o->n_pad, 1, s), "stage v");
-    return st == LV_OK ? ols_update<double>(o, -1, s) : st;
+    return st == LV_OK ? ols_update<double>(o, -1, nullptr, s) : st;
   }
   st = hip_check(launch_copy_rect<float, float>(static_cast<const float*>(u), 1, o->m, 1, o->at<float>(o->ubuf),
                                                 o->m_pad, 1, s), "stage u");
   if (st == LV_OK)
     st = hip_check(launch_copy_rect<float, float>(static_cast<const float*>(v), 1, o->n, 1, o->at<float>(o->vbuf),
                                                   o->n_pad, 1, s), "stage v");
-  return st == LV_OK ? ols_update<float>(o, -1, s) : st;
+  return st == LV_OK ? ols_update<float>(o, -1, nullptr, s) : st;
 }
 
 lv_status lv_ols_update_row(lv_ols* o, int64_t row, const void* dx, void* stream) {
@@ -540,15 +637,8 @@ lv_status lv_ols_update_row(lv_ols* o, int64_t row, const void* dx, void* stream
   if (!o || !dx) return fail(LV_EINVAL, "handle or dx is NULL");
   if (row < 0 || row >= o->m) return fail(LV_EINVAL, "row %lld outside [0, %lld)", (long long)row, (long long)o->m);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  lv_status st;
-  if (o->mode == LV_FP64) {
-    st = hip_check(launch_copy_rect<double, double>(static_cast<const double*>(dx), 1, o->n, 1,
-                                                    o->at<double>(o->vbuf), o->n_pad, 1, s), "stage dx");
-    return st == LV_OK ? ols_update<double>(o, row, s) : st;
-  }
-  st = hip_check(launch_copy_rect<float, float>(static_cast<const float*>(dx), 1, o->n, 1, o->at<float>(o->vbuf),
-                                                o->n_pad, 1, s), "stage dx");
-  return st == LV_OK ? ols_update<float>(o, row, s) : st;
+  return o->mode == LV_FP64 ? ols_update<double>(o, row, static_cast<const double*>(dx), s)
+                            : ols_update<float>(o, row, static_cast<const float*>(dx), s);
 }
 
 lv_status lv_ols_read(const lv_ols* o, int what, void* out, int64_t ldo, void* stream) {
