@@ -37,6 +37,8 @@ from .general_oracle import (  # noqa: F401
     iterate_general,
     reeval_general,
     incr_update_general,
+    incr_general_factors,
+    incr_update_general_factored,
 )
 from .models_oracle import (  # noqa: F401
     model_steps,

@@ -18,6 +18,19 @@ Delta S_i = Q_i W_i^T:
     D_i = P_h D_h + U_h (V_h^T (T_h + D_h)) + Q_h (W_h^T B),   h = i/2,
 
 where P_h and T_h are the old values.
+
+Incremental evaluation keeps the change of T_i factored instead,
+Delta T_i = Y_i Z_i^T (App. B, exponential model, in our names):
+
+    Y_1 = U,  Z_1 = T_0^T V,
+    Y_i = [U_h, P_h Y_h + U_h (V_h^T Y_h), Q_h],
+    Z_i = [T_h^T V_h, Z_h, B^T W_h],                     h = i/2,
+
+all from the old values, with Q_1 = W_1 = 0 taken as blocks of width r (as
+the paper counts them) and Q_h of its own width r (h - 1) above: widths
+c_1 = r, c_2 = 3r, c_{2h} = h r + c_h + (h - 1) r; every T_i then takes
+T_i += Y_i Z_i^T.  (The paper's count (2i - 1) r also takes Q_h as h r wide;
+zero columns change no product.)
 """
 
 from __future__ import annotations
@@ -66,4 +79,34 @@ def incr_update_general(P, S, T, T0, B, U, V):
     Pn = {i: P[i] + dU[i] @ dV[i].T for i in P}
     Sn = {i: S[i] + dQ[i] @ dW[i].T for i in S}
     Tn = {i: T[i] + D[i] for i in T}
+    return Pn, Sn, Tn
+
+
+def incr_general_factors(P, S, T, T0, B, U, V):
+    """Factored deltas Delta T_i = Y_i Z_i^T of the general form (module
+    docstring, App. B), from the old powers, sums and T.  Q_1 and W_1 are
+    zero blocks of width r, as the paper counts them.  Returns (Y, Z)."""
+    dQ, dW, dU, dV = incr_sums_factors(P, S, U, V)
+    n, r = np.asarray(U).shape
+    dQ = dict(dQ)
+    dW = dict(dW)
+    dQ[1], dW[1] = np.zeros((n, r)), np.zeros((n, r))
+    Y = {1: np.asarray(U, dtype=np.float64)}
+    Z = {1: np.asarray(T0, dtype=np.float64).T @ np.asarray(V, dtype=np.float64)}
+    for i in levels(max(P))[1:]:
+        h = i // 2
+        Y[i] = np.hstack([dU[h], P[h] @ Y[h] + dU[h] @ (dV[h].T @ Y[h]), dQ[h]])
+        Z[i] = np.hstack([T[h].T @ dV[h], Z[h], np.asarray(B).T @ dW[h]])
+    return Y, Z
+
+
+def incr_update_general_factored(P, S, T, T0, B, U, V):
+    """Incremental (factored) step for the powers, the sums and T: all
+    factors from the old values, then every stored matrix takes its delta.
+    Returns (P', S', T')."""
+    dQ, dW, dU, dV = incr_sums_factors(P, S, U, V)
+    Y, Z = incr_general_factors(P, S, T, T0, B, U, V)
+    Pn = {i: P[i] + dU[i] @ dV[i].T for i in P}
+    Sn = {i: S[i] + dQ[i] @ dW[i].T for i in S}
+    Tn = {i: T[i] + Y[i] @ Z[i].T for i in T}
     return Pn, Sn, Tn

@@ -128,3 +128,80 @@ def test_iterate_general_matches_exact_iteration():
     assert sorted(it) == [1, 2, 4, 8]
     for i in it:
         assert (_frac(it[i]) == ref[i]).all(), i
+
+
+# ---- factored (incremental) deltas of App. B
+
+
+@pytest.mark.parametrize("n,p,k,r,seed", [(4, 2, 8, 1, 50), (5, 1, 16, 2, 51), (4, 3, 4, 1, 52), (3, 2, 2, 2, 53)])
+def test_factored_general_exact_iteration(n, p, k, r, seed):
+    A, T0, B = _case(n, p, seed)
+    U = synth.integer_matrix((n, r), -1, 1, seed=seed, tag=5)
+    V = synth.integer_matrix((n, r), -1, 1, seed=seed, tag=6)
+    _, _, Tn = O.incr_update_general_factored(O.reeval(A, k), O.reeval_sums(A, k), O.reeval_general(A, T0, B, k),
+                                              T0, B, U, V)
+    ref = _iterate(_frac(A + U @ V.T), _frac(T0), _frac(B), k)
+    for i in Tn:
+        assert (_frac(Tn[i]) == ref[i]).all(), i
+
+
+def test_factored_widths_and_agreement_with_hybrid():
+    n, p, k, r = 20, 3, 16, 2
+    A = synth.gaussian_matrix(n, seed=54)
+    T0, B = synth.general_operands(n, p, seed=54)
+    U, V = synth.update_factors(n, r, 1, seed=54)
+    P, S, T = O.reeval(A, k), O.reeval_sums(A, k), O.reeval_general(A, T0, B, k)
+    Y, Z = O.incr_general_factors(P, S, T, T0, B, U[0], V[0])
+    c = {1: r}
+    for i in O.levels(k)[1:]:
+        h = i // 2
+        c[i] = h * r + c[h] + max(h - 1, 1) * r
+    for i in Y:
+        assert Y[i].shape == (n, c[i]) and Z[i].shape == (p, c[i])
+    _, _, Th = O.incr_update_general(P, S, T, T0, B, U[0], V[0])
+    _, _, Tf = O.incr_update_general_factored(P, S, T, T0, B, U[0], V[0])
+    for i in Th:
+        assert O.maxrel(Tf[i], Th[i]) < 1e-13
+
+
+def _factored_mutant(kind):
+    def fn(P, S, T, T0, B, U, V):
+        dQ, dW, dU, dV = O.incr_sums_factors(P, S, U, V)
+        n, r = U.shape
+        dQ, dW = dict(dQ), dict(dW)
+        dQ[1], dW[1] = np.zeros((n, r)), np.zeros((n, r))
+        Y, Z = {1: U}, {1: T0.T @ V}
+        for i in O.levels(max(P))[1:]:
+            h = i // 2
+            Th = T[h] + Y[h] @ Z[h].T if kind == "new_t" else T[h]
+            cross = 0 if kind == "drop_cross" else dU[h] @ (dV[h].T @ Y[h])
+            Y[i] = np.hstack([dU[h], P[h] @ Y[h] + cross, dQ[h]])
+            Bt = T0.T if kind == "t0_for_b" else B.T
+            Z[i] = np.hstack([Th.T @ dV[h], Z[h], Bt @ dW[h]])
+        return {i: T[i] + Y[i] @ Z[i].T for i in T}
+    return fn
+
+
+@pytest.mark.parametrize("kind", ["new_t", "drop_cross", "t0_for_b"])
+def test_factored_pins_catch_planted_mistakes(kind):
+    caught = False
+    for seed in range(3):
+        A, T0, B = _case(4, 2, 60 + seed)
+        U = synth.integer_matrix((4, 1), -1, 1, seed=60 + seed, tag=5)
+        V = synth.integer_matrix((4, 1), -1, 1, seed=60 + seed, tag=6)
+        k = 8
+        Tn = _factored_mutant(kind)(O.reeval(A, k), O.reeval_sums(A, k), O.reeval_general(A, T0, B, k), T0, B, U, V)
+        ref = _iterate(_frac(A + U @ V.T), _frac(T0), _frac(B), k)
+        if not all((_frac(Tn[i]) == ref[i]).all() for i in Tn):
+            caught = True
+    assert caught, kind
+
+
+def test_factored_unmutated_copy_passes():
+    for seed in range(3):
+        A, T0, B = _case(4, 2, 60 + seed)
+        U = synth.integer_matrix((4, 1), -1, 1, seed=60 + seed, tag=5)
+        V = synth.integer_matrix((4, 1), -1, 1, seed=60 + seed, tag=6)
+        Tn = _factored_mutant("none")(O.reeval(A, 8), O.reeval_sums(A, 8), O.reeval_general(A, T0, B, 8), T0, B, U, V)
+        ref = _iterate(_frac(A + U @ V.T), _frac(T0), _frac(B), 8)
+        assert all((_frac(Tn[i]) == ref[i]).all() for i in Tn)
