@@ -172,18 +172,30 @@ lv_status lv_view_read_sum(const lv_view* v, int index, void* out, int64_t ldo, 
  *     D_1 = U (V^T T_0),
  *     D_{2i} = P_i D_i + U_i (V_i^T (T_i + D_i)) + Q_i (W_i^T B)
  * with Delta P_i = U_i V_i^T and Delta S_i = Q_i W_i^T.  T_0 and B are fixed.
+ * With strategy LV_GENERAL_FACTORED the change of each T_i is kept
+ * factored instead, Delta T_i = Y_i Z_i^T (incremental evaluation, App. B):
+ *     Y_1 = U, Z_1 = T_0^T V,
+ *     Y_{2i} = [U_i, P_i Y_i + U_i (V_i^T Y_i), Q_i],
+ *     Z_{2i} = [T_i^T V_i, Z_i, B^T W_i]         (widths (2i - 1) r),
+ * all from the old values, then T_i += Y_i Z_i^T; its cost grows with n p
+ * rather than n^2 p, for large p.
  * Creation and re-anchoring evaluate every T_i by the recurrence in double
  * precision from the double powers and sums and round once.
- *  p        1 <= p <= 64 (padded to a power of two in the workspace).
- *  T0, B    n x p (device, element type of the mode), leading dimensions
- *           ldt, ldb >= p; copied into the workspace, not retained.
+ *  p         hybrid: 1 <= p <= 64 (padded to a power of two in the
+ *            workspace); factored: 1 <= p <= 4096 (padded to a multiple of
+ *            128), and k * r_max rounded up to a power of two <= 128.
+ *  T0, B     n x p (device, element type of the mode), leading dimensions
+ *            ldt, ldb >= p; copied into the workspace, not retained.
+ *  strategy  LV_GENERAL_HYBRID or LV_GENERAL_FACTORED.
  * Other arguments, ownership and errors as lv_view_create; the footprint
  * is 0 for invalid arguments.  Such views are single-view only. */
-size_t lv_view_footprint_general(int64_t n, int k, int r_max, lv_mode mode, int64_t p);
+#define LV_GENERAL_HYBRID 0
+#define LV_GENERAL_FACTORED 1
+size_t lv_view_footprint_general(int64_t n, int k, int r_max, lv_mode mode, int64_t p, int strategy);
 lv_status lv_view_create_general(const void* A, int64_t n, int64_t lda, int k, int r_max,
                                  lv_mode mode, const void* T0, int64_t ldt, const void* B,
-                                 int64_t ldb, int64_t p, void* workspace, size_t ws_bytes,
-                                 void* stream, lv_view** out);
+                                 int64_t ldb, int64_t p, int strategy, void* workspace,
+                                 size_t ws_bytes, void* stream, lv_view** out);
 
 /* Copy stored T_index (index in {1, 2, 4, ..., k}) of a general-form view to
  * out (n x p, leading dimension ldo >= p, device).  LV_ESTATE for a view

@@ -46,8 +46,21 @@ lv_status general_step(lv_view* v, int j, const double* P, const double* S, int6
     if (st == LV_OK)
       st = hip_check(launch_copy_rect<T, double>(v->Bg<T>(), L.pp, L.n_pad, L.pp, v->gB(), L.n_pad, L.pp, s, gate),
                      "widen B");
-    if (st == LV_OK)
+    if (st == LV_OK && L.gfac) {
+      st = hip_check(launch_gemm_rect<double>(P, ld, v->gT(0), L.pp, v->gT(1), L.pp, L.n_pad, L.pp, L.n_pad, s, gate),
+                     "A T_0");
+      if (st == LV_OK) st = hip_check(launch_add<double>(v->gT(1), v->gB(), L.n_pad * L.pp, s, gate), "+ B");
+    } else if (st == LV_OK) {
       st = hip_check(launch_gemm_np(L.pp, P, ld, v->gT(0), v->gT(1), v->gB(), L.n_pad, s, gate), "T_1 = A T_0 + B");
+    }
+  } else if (L.gfac) {
+    st = hip_check(launch_gemm_rect<double>(S, ld, v->gB(), L.pp, v->gTmp(), L.pp, L.n_pad, L.pp, L.n_pad, s, gate),
+                   "S B");
+    if (st == LV_OK)
+      st = hip_check(launch_gemm_rect<double>(P, ld, v->gT(j & 1), L.pp, v->gT((j + 1) & 1), L.pp, L.n_pad, L.pp,
+                                              L.n_pad, s, gate),
+                     "P T");
+    if (st == LV_OK) st = hip_check(launch_add<double>(v->gT((j + 1) & 1), v->gTmp(), L.n_pad * L.pp, s, gate), "+ S B");
   } else {
     st = hip_check(launch_gemm_np(L.pp, S, ld, v->gB(), v->gTmp(), nullptr, L.n_pad, s, gate), "S B");
     if (st == LV_OK)
@@ -259,6 +272,85 @@ lv_status general_tail(lv_view* v, int j, int R, const T* sU, const T* sV, hipSt
   });
 }
 
+// General form with factored deltas Delta T_j = Y_j Z_j^T (App. B,
+// exponential model): Y_0 is the prefix [0, r_pad) of the powers' U slab,
+// Z_0 = T_0^T V.  Every T_j keeps its old value until the whole update has
+// formed its factors (gfac_finish applies T_j += Y_j Z_j^T).
+template <typename T>
+lv_status gfac_first(lv_view* v, const T* sV, hipStream_t s) {
+  const Layout& L = v->L;
+  lv_status st = timed(v, 0, s, "general: T_0^T V", [&] {
+    return launch_atb<T>(L.r_pad, L.pp, sV + (L.W - L.r_pad), L.W, v->T0<T>(), L.pp, L.n_pad, v->atbA(), s);
+  });
+  if (st != LV_OK) return st;
+  return timed(v, 1, s, "general: Z_0", [&] {
+    return launch_gfac_z<T>(v->atbA(), nullptr, 0, nullptr, L.r_pad, v->Ztf<T>(0), L.WY[0], L.pp, s);
+  });
+}
+
+// Level j, before the powers' update: X = P_j Y_j with the OLD P_j (the
+// float matrix cores from width 16, X only; else the read-only vector pass).
+template <typename T>
+lv_status gfac_pass(lv_view* v, int j, const T* sU, hipStream_t s) {
+  const Layout& L = v->L;
+  const T* Yj = j == 0 ? sU : v->Yf<T>(j);
+  const int sy = j == 0 ? L.W : L.WY[j];
+  const int R = L.WY[j];
+  return timed(v, 0, s, "general: P Y", [&] {
+    if (skinny_on_mfma(R, (int)sizeof(T)))
+      return launch_skinny_f32(R, reinterpret_cast<const float*>(v->P<T>(j)), L.ldp, L.n_pad, v->tile_rows[j],
+                               reinterpret_cast<const float*>(Yj), reinterpret_cast<const float*>(Yj), sy,
+                               v->partXT<float>(), v->partYT<float>(), s, kWantX);
+    return launch_level_readonly<T>(R, v->P<T>(j), L.ldp, L.n_pad, v->tile_rows[j], Yj, Yj, sy, v->partXT<T>(),
+                                    v->partYT<T>(), s);
+  });
+}
+
+// Level j, after the powers' tail (U_j, V_j intact) and before the sums'
+// tail (Q_j intact): G = V_j^T Y_j, a = V_j^T T_j (old T_j), b = W_j^T B
+// (j > 0), then Y_{j+1} = [U_j, X + U_j G, Q_j] and Z_{j+1}^T = [a; Z_j^T; b].
+template <typename T>
+lv_status gfac_tail(lv_view* v, int j, int R, const T* sU, const T* sV, hipStream_t s) {
+  const Layout& L = v->L;
+  const T* Yj = j == 0 ? sU : v->Yf<T>(j);
+  const int sy = j == 0 ? L.W : L.WY[j];
+  const T* Vj = sV + (L.W - R);
+  lv_status st = timed(v, 0, s, "general: V^T Y", [&] {
+    return launch_atb<T>(R, L.WY[j], Vj, L.W, Yj, sy, L.n_pad, v->atbG(), s);
+  });
+  if (st == LV_OK)
+    st = timed(v, 0, s, "general: V^T T", [&] {
+      return launch_atb<T>(R, L.pp, Vj, L.W, v->Tg<T>(j), L.pp, L.n_pad, v->atbA(), s);
+    });
+  if (st == LV_OK && j > 0)
+    st = timed(v, 0, s, "general: W^T B", [&] {
+      return launch_atb<T>(R, L.pp, v->slabW<T>() + (L.W - R), L.W, v->Bg<T>(), L.pp, L.n_pad, v->atbB(), s);
+    });
+  if (st == LV_OK)
+    st = timed(v, 1, s, "general: Y", [&] {
+      return launch_gfac_y<T>(v->partXT<T>(), L.nct, L.WY[j], sU, j > 0 ? v->slabQ<T>() : nullptr, L.W, R, v->atbG(),
+                              L.WY[j], L.wy[j], v->Yf<T>(j + 1), L.WY[j + 1], L.n_pad, s);
+    });
+  if (st == LV_OK)
+    st = timed(v, 1, s, "general: Z", [&] {
+      return launch_gfac_z<T>(v->atbA(), v->Ztf<T>(j), L.wy[j], j > 0 ? v->atbB() : nullptr, R, v->Ztf<T>(j + 1),
+                              L.WY[j + 1], L.pp, s);
+    });
+  return st;
+}
+
+template <typename T>
+lv_status gfac_finish(lv_view* v, const T* sU, hipStream_t s) {
+  const Layout& L = v->L;
+  lv_status st = LV_OK;
+  for (int j = 0; j <= L.m && st == LV_OK; ++j)
+    st = timed(v, 2, s, "general: T += Y Z^T", [&] {
+      return launch_rank_rect<T>(v->Tg<T>(j), j == 0 ? sU : v->Yf<T>(j), j == 0 ? L.W : L.WY[j], v->Ztf<T>(j),
+                                 L.wy[j], L.n_pad, L.pp, s);
+    });
+  return st;
+}
+
 // One update through every level, factors in slab `sl` (App. A exponential
 // model; trigger of Sec. 4.4): levels 0..m-1 run the fused pass and the tail
 // (or, for float storage at large level rank and with bfloat16 shadows, the
@@ -272,12 +364,13 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
   T* sU = v->slabU<T>(sl);
   T* sV = v->slabV<T>(sl);
   lv_status st = hip_check(launch_prep<T>(U, ldu, V, ldv, v->n, r, r_pad, sU, sV, L.W, L.n_pad, s), "prep");
-  if (st == LV_OK && L.general) st = general_tail<T>(v, -1, r_pad, sU, sV, s);
+  if (st == LV_OK && L.general)
+    st = L.gfac ? gfac_first<T>(v, sV, s) : general_tail<T>(v, -1, r_pad, sU, sV, s);
   if (st != LV_OK) return st;
   for (int j = 0; j < L.m; ++j) {
     const int R = r_pad << j;
     if (L.general) {
-      st = general_pass<T>(v, j, s);
+      st = L.gfac ? gfac_pass<T>(v, j, sU, s) : general_pass<T>(v, j, s);
       if (st != LV_OK) return st;
     }
     if (L.sums && j > 0) {
@@ -317,7 +410,8 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
             return launch_level_tail<float>(R, v->partX<float>(j), v->partY<float>(j), v->partG(j), L.nct, v->nrt(j),
                                             1, L.n_pad, sU, sV, L.W, s);
           });
-        if (st == LV_OK && L.general) st = general_tail<T>(v, j, R, sU, sV, s);
+        if (st == LV_OK && L.general)
+          st = L.gfac ? gfac_tail<T>(v, j, R, sU, sV, s) : general_tail<T>(v, j, R, sU, sV, s);
         if (st == LV_OK && L.sums) st = sums_level<T>(v, j, R, sU, sV, s);
         if (st != LV_OK) return st;
         continue;
@@ -332,7 +426,8 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
       return launch_level_tail<T>(R, v->partX<T>(j), v->partY<T>(j), v->partG(j), L.nct, v->nrt(j),
                                   gram_in_pass(R, (int)sizeof(T)) ? v->nrt(j) : 1, L.n_pad, sU, sV, L.W, s);
     });
-    if (st == LV_OK && L.general) st = general_tail<T>(v, j, R, sU, sV, s);
+    if (st == LV_OK && L.general)
+      st = L.gfac ? gfac_tail<T>(v, j, R, sU, sV, s) : general_tail<T>(v, j, R, sU, sV, s);
     if (st == LV_OK && L.sums) st = sums_level<T>(v, j, R, sU, sV, s);
     if (st != LV_OK) return st;
   }
@@ -344,6 +439,7 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
     st = timed(v, 2, s, "sums: top update", [&] {
       return launch_level_update<T>(Rm, v->S<T>(L.m), L.ldp, L.n_pad, v->slabQ<T>(), v->slabW<T>(), L.W, s);
     });
+  if (st == LV_OK && L.gfac) st = gfac_finish<T>(v, sU, s);
   return st;
 }
 
@@ -421,8 +517,8 @@ namespace {
 // Creation of every kind of view; p > 0 makes a general-form view with T_0
 // and B (n x p, leading dimensions ldt, ldb).
 lv_status create_view(const void* A, int64_t n, int64_t lda, int k, int r_max, lv_mode mode, int flags, int p,
-                      const void* T0, int64_t ldt, const void* B, int64_t ldb, void* workspace, size_t ws_bytes,
-                      void* stream, lv_view** out) {
+                      bool factored, const void* T0, int64_t ldt, const void* B, int64_t ldb, void* workspace,
+                      size_t ws_bytes, void* stream, lv_view** out) {
   g_err[0] = 0;
   if (!out) return fail(LV_EINVAL, "out is NULL");
   *out = nullptr;
@@ -433,7 +529,7 @@ lv_status create_view(const void* A, int64_t n, int64_t lda, int k, int r_max, l
   if (lda < n) return fail(LV_EINVAL, "lda = %lld < n = %lld", (long long)lda, (long long)n);
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
     return fail(LV_ENOMEM, "workspace is not %zu-byte aligned", kAlign);
-  const Layout L = make_layout(n, k, r_max, mode, flags, p);
+  const Layout L = make_layout(n, k, r_max, mode, flags, p, factored);
   if (ws_bytes < L.total)
     return fail(LV_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
   lv_view* v = new (std::nothrow) lv_view();
@@ -485,24 +581,51 @@ extern "C" {
 
 lv_status lv_view_create_ex(const void* A, int64_t n, int64_t lda, int k, int r_max, lv_mode mode, int flags,
                             void* workspace, size_t ws_bytes, void* stream, lv_view** out) {
-  return create_view(A, n, lda, k, r_max, mode, flags, 0, nullptr, 0, nullptr, 0, workspace, ws_bytes, stream, out);
+  return create_view(A, n, lda, k, r_max, mode, flags, 0, false, nullptr, 0, nullptr, 0, workspace, ws_bytes, stream,
+                     out);
 }
 
-size_t lv_view_footprint_general(int64_t n, int k, int r_max, lv_mode mode, int64_t p) {
-  if (check_shape(n, k, r_max, mode) != LV_OK || p < 1 || p > kMaxGeneralCols) return 0;
-  return make_layout(n, k, r_max, mode, LV_WITH_SUMS, (int)p).total;
+}  // extern "C"
+
+namespace {
+
+lv_status check_general(int64_t n, int k, int r_max, lv_mode mode, int64_t p, int strategy) {
+  lv_status st = check_shape(n, k, r_max, mode);
+  if (st != LV_OK) return st;
+  if (strategy == LV_GENERAL_HYBRID) {
+    if (p < 1 || p > kMaxGeneralCols)
+      return fail(LV_EINVAL, "p = %lld outside [1, %d] (hybrid deltas)", (long long)p, kMaxGeneralCols);
+  } else if (strategy == LV_GENERAL_FACTORED) {
+    if (p < 1 || p > kMaxGeneralColsF)
+      return fail(LV_EINVAL, "p = %lld outside [1, %d] (factored deltas)", (long long)p, kMaxGeneralColsF);
+    if ((int64_t)k * next_pow2(r_max) > kMaxGeneralWidthF)
+      return fail(LV_EINVAL, "factored deltas need k * r_max (rounded up to a power of two) <= %d", kMaxGeneralWidthF);
+  } else {
+    return fail(LV_EINVAL, "unknown strategy %d", strategy);
+  }
+  return LV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lv_view_footprint_general(int64_t n, int k, int r_max, lv_mode mode, int64_t p, int strategy) {
+  if (check_general(n, k, r_max, mode, p, strategy) != LV_OK) return 0;
+  return make_layout(n, k, r_max, mode, LV_WITH_SUMS, (int)p, strategy == LV_GENERAL_FACTORED).total;
 }
 
 lv_status lv_view_create_general(const void* A, int64_t n, int64_t lda, int k, int r_max, lv_mode mode,
-                                 const void* T0, int64_t ldt, const void* B, int64_t ldb, int64_t p,
+                                 const void* T0, int64_t ldt, const void* B, int64_t ldb, int64_t p, int strategy,
                                  void* workspace, size_t ws_bytes, void* stream, lv_view** out) {
   g_err[0] = 0;
   if (out) *out = nullptr;
-  if (p < 1 || p > kMaxGeneralCols) return fail(LV_EINVAL, "p = %lld outside [1, %d]", (long long)p, kMaxGeneralCols);
+  lv_status st = check_general(n, k, r_max, mode, p, strategy);
+  if (st != LV_OK) return st;
   if (!T0 || !B) return fail(LV_EINVAL, "T0 or B is NULL");
   if (ldt < p || ldb < p) return fail(LV_EINVAL, "ldt/ldb smaller than p");
-  return create_view(A, n, lda, k, r_max, mode, LV_WITH_SUMS, (int)p, T0, ldt, B, ldb, workspace, ws_bytes, stream,
-                     out);
+  return create_view(A, n, lda, k, r_max, mode, LV_WITH_SUMS, (int)p, strategy == LV_GENERAL_FACTORED, T0, ldt, B,
+                     ldb, workspace, ws_bytes, stream, out);
 }
 
 static lv_status check_update_args(const lv_view* v, const void* U, const void* V, int64_t r,

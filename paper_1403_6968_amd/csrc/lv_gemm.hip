@@ -1,7 +1,8 @@
 // Dense MFMA products for view creation / re-anchoring (double) and for the
 // re-evaluation baseline (double or float): C = A * B, n_pad x n_pad,
 // row-major, n_pad a multiple of 256 (the repeated squarings of Table 1's
-// exponential model, P_i = P_{i/2} P_{i/2}).
+// exponential model, P_i = P_{i/2} P_{i/2}); launch_gemm_rect runs the same
+// kernel on an M x K by K x N product (M, N multiples of 128, K of 16).
 //
 // Block tile 128 x 128 x 16, 256 threads as a 2 x 2 grid of waves, each wave
 // owning a 64 x 64 sub-tile of C built from MFMA blocks:
@@ -136,6 +137,17 @@ hipError_t launch_gemm(const T* A, int64_t lda, const T* B, int64_t ldb, T* C, i
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_gemm_rect(const T* A, int64_t lda, const T* B, int64_t ldb, T* C, int64_t ldc, int64_t M,
+                            int64_t N, int64_t K, hipStream_t s, const int* gate) {
+  if (M % BM != 0 || N % BN != 0 || K % BK != 0) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(N / BN), (unsigned)(M / BM));
+  hipLaunchKernelGGL((k_gemm<T>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, (int)K, gate);
+  return hipGetLastError();
+}
+
+template hipError_t launch_gemm_rect<double>(const double*, int64_t, const double*, int64_t, double*, int64_t,
+                                             int64_t, int64_t, int64_t, hipStream_t, const int*);
 template hipError_t launch_gemm<double>(const double*, int64_t, const double*, int64_t, double*,
                                         int64_t, int64_t, hipStream_t, const int*);
 template hipError_t launch_gemm<float>(const float*, int64_t, const float*, int64_t, float*,

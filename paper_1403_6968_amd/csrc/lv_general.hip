@@ -8,7 +8,11 @@
 // with Delta P_i = U_i V_i^T, Delta S_i = Q_i W_i^T.  The products P_i D_i
 // run as read-only skinny passes (lv_fused.hip / lv_skinny.hip); this file
 // holds the small reductions A^T B, the tail that assembles D_{2i} and adds
-// it to T_{2i}, and the (n x n)(n x p) product used at creation.
+// it to T_{2i}, and the (n x n)(n x p) product used at creation; and, for
+// incremental evaluation with factored deltas Delta T_i = Y_i Z_i^T (App. B),
+//     Y_{2i} = [U_i, P_i Y_i + U_i (V_i^T Y_i), Q_i],  Z_{2i} = [T_i^T V_i, Z_i, B^T W_i],
+// the kernels that assemble the new factor slabs (Z kept transposed, factor-
+// major) and apply T_i += Y_i Z_i^T.
 #include "lv_device.h"
 #include "lv_view_impl.h"
 
@@ -99,7 +103,82 @@ k_copy_rect(const Tin* __restrict__ src, int64_t lds, int64_t n, int p, Tout* __
   dst[idx] = (row < n && col < p) ? (Tout)src[row * lds + col] : Tout(0);
 }
 
+// Factored deltas: one thread per (row, column) of the new Y slab.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_gfac_y(const T* __restrict__ partX, int nct, int pR, const T* __restrict__ U, const T* __restrict__ Q, int W, int R,
+         const double* __restrict__ G, int ldg, int wy, T* __restrict__ Ynew, int WYn, int64_t n_pad) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= n_pad * WYn) return;
+  const int64_t row = idx / WYn;
+  const int col = (int)(idx % WYn);
+  double y = 0.0;
+  if (col < R) {
+    y = (double)U[row * W + col];
+  } else if (col < R + wy) {
+    const int c = col - R;
+    for (int t = 0; t < nct; ++t) y += (double)partX[((int64_t)t * n_pad + row) * pR + c];
+    for (int d = 0; d < R; ++d) y = fma((double)U[row * W + d], G[d * ldg + c], y);
+  } else if (col < 2 * R + wy && Q != nullptr) {
+    y = (double)Q[row * W + (col - R - wy)];
+  }
+  Ynew[idx] = (T)y;
+}
+
+// One thread per (factor row, column of T) of the new Zt slab.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_gfac_z(const double* __restrict__ a, const T* __restrict__ Zt, int wy, const double* __restrict__ b, int R,
+         T* __restrict__ Ztnew, int WYn, int pp) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)WYn * pp) return;
+  const int crow = (int)(idx / pp);
+  const int col = (int)(idx % pp);
+  T z = T(0);
+  if (crow < R) z = (T)a[(int64_t)crow * pp + col];
+  else if (crow < R + wy) z = Zt[(int64_t)(crow - R) * pp + col];
+  else if (crow < 2 * R + wy && b != nullptr) z = (T)b[(int64_t)(crow - R - wy) * pp + col];
+  Ztnew[idx] = z;
+}
+
+// Tm[row][col] += sum_c Y[row][c] Zt[c][col] (double), one thread per element.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_rank_rect(T* __restrict__ Tm, const T* __restrict__ Y, int sy, const T* __restrict__ Zt, int w, int64_t n_pad,
+            int pp) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= n_pad * pp) return;
+  const int64_t row = idx / pp;
+  const int col = (int)(idx % pp);
+  double d = 0.0;
+  for (int c = 0; c < w; ++c) d = fma((double)Y[row * sy + c], (double)Zt[(int64_t)c * pp + col], d);
+  Tm[idx] = (T)((double)Tm[idx] + d);
+}
+
 }  // namespace
+
+template <typename T>
+hipError_t launch_gfac_y(const T* partX, int nct, int pR, const T* U, const T* Q, int W, int R, const double* G,
+                         int ldg, int wy, T* Ynew, int WYn, int64_t n_pad, hipStream_t s) {
+  hipLaunchKernelGGL((k_gfac_y<T>), dim3((unsigned)((n_pad * WYn + 255) / 256)), dim3(256), 0, s, partX, nct, pR, U, Q,
+                     W, R, G, ldg, wy, Ynew, WYn, n_pad);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gfac_z(const double* a, const T* Zt, int wy, const double* b, int R, T* Ztnew, int WYn, int pp,
+                         hipStream_t s) {
+  hipLaunchKernelGGL((k_gfac_z<T>), dim3((unsigned)(((int64_t)WYn * pp + 255) / 256)), dim3(256), 0, s, a, Zt, wy, b,
+                     R, Ztnew, WYn, pp);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rank_rect(T* Tm, const T* Y, int sy, const T* Zt, int w, int64_t n_pad, int pp, hipStream_t s) {
+  hipLaunchKernelGGL((k_rank_rect<T>), dim3((unsigned)((n_pad * pp + 255) / 256)), dim3(256), 0, s, Tm, Y, sy, Zt, w,
+                     n_pad, pp);
+  return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_atb(int R, int p, const T* A, int64_t lda, const T* B, int64_t ldb, int64_t n_pad, double* part,
@@ -145,6 +224,15 @@ hipError_t launch_copy_rect(const Tin* src, int64_t lds, int64_t n, int p, Tout*
                                     hipStream_t);                                                             \
   template hipError_t launch_general_tail<T>(const T*, int, const T*, const T*, int, int, const double*,       \
                                              const double*, T*, T*, int64_t, int, hipStream_t);
+LV_INST(float)
+LV_INST(double)
+#undef LV_INST
+#define LV_INST(T)                                                                                             \
+  template hipError_t launch_gfac_y<T>(const T*, int, int, const T*, const T*, int, int, const double*, int, int, \
+                                       T*, int, int64_t, hipStream_t);                                         \
+  template hipError_t launch_gfac_z<T>(const double*, const T*, int, const double*, int, T*, int, int,         \
+                                       hipStream_t);                                                           \
+  template hipError_t launch_rank_rect<T>(T*, const T*, int, const T*, int, int64_t, int, hipStream_t);
 LV_INST(float)
 LV_INST(double)
 #undef LV_INST

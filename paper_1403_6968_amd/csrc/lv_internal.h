@@ -223,6 +223,21 @@ hipError_t launch_gemm_np(int pp, const double* A, int64_t lda, const double* B,
 template <typename Tin, typename Tout>
 hipError_t launch_copy_rect(const Tin* src, int64_t lds, int64_t n, int p, Tout* dst, int64_t n_pad, int pp,
                             hipStream_t s, const int* gate = nullptr);
+// Factored general-form deltas (Delta T_j = Y_j Z_j^T):
+// Ynew (n_pad x WYn) = [U_j (R cols, row stride W), sum of nct partials of
+// P_j Y_j (width wy, partial row stride pR) + U_j G (G R x ldg double),
+// Q_j (R cols, stride W; zero if Q is null), 0 ...].
+template <typename T>
+hipError_t launch_gfac_y(const T* partX, int nct, int pR, const T* U, const T* Q, int W, int R, const double* G,
+                         int ldg, int wy, T* Ynew, int WYn, int64_t n_pad, hipStream_t s);
+// Ztnew (WYn x pp, factor-major) = [a (R x pp, double), Zt_j (wy rows),
+// b (R x pp, double; zero if null), 0 ...].
+template <typename T>
+hipError_t launch_gfac_z(const double* a, const T* Zt, int wy, const double* b, int R, T* Ztnew, int WYn, int pp,
+                         hipStream_t s);
+// Tm (n_pad x pp) += Y (w columns, row stride sy) Zt (w x pp), double sums.
+template <typename T>
+hipError_t launch_rank_rect(T* Tm, const T* Y, int sy, const T* Zt, int w, int64_t n_pad, int pp, hipStream_t s);
 // G[0 .. count) = sum over t < ng of G[t count + ...] (fixed order).
 hipError_t launch_gram_sum(double* G, int ng, int count, hipStream_t s);
 
@@ -246,6 +261,10 @@ hipError_t launch_prep_multi(const PrepDesc<T>* ds, int nd, int blocks, hipStrea
 template <typename T>
 hipError_t launch_gemm(const T* A, int64_t lda, const T* B, int64_t ldb, T* C, int64_t ldc,
                        int64_t n_pad, hipStream_t s, const int* gate = nullptr);
+// C = A * B for A M x K, B K x N (M, N multiples of 128, K of 16), same kernel.
+template <typename T>
+hipError_t launch_gemm_rect(const T* A, int64_t lda, const T* B, int64_t ldb, T* C, int64_t ldc, int64_t M,
+                            int64_t N, int64_t K, hipStream_t s, const int* gate = nullptr);
 
 // ---- drift check (FP64 test of the stored chain P_{j+1} = P_j P_j)
 

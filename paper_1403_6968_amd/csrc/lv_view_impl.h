@@ -57,6 +57,16 @@ struct Layout {
   // scratch (two T, one product, B)
   bool general = false;
   int p = 0, pp = 0;
+  // factored deltas Delta T_j = Y_j Z_j^T instead (LV_GENERAL_FACTORED):
+  // p padded to a multiple of 128; Y_j slabs (n_pad x WY[j], true width
+  // wy[j]; Y_0 is the prefix of the powers' U slab), Z_j kept transposed
+  // (WY[j] x pp), FP64 partials of V_j^T Y_j
+  bool gfac = false;
+  int wy[kMaxLevel + 1] = {};
+  int WY[kMaxLevel + 1] = {};
+  size_t Y[kMaxLevel + 1] = {};
+  size_t Zt[kMaxLevel + 1] = {};
+  size_t atbG = 0;
   size_t T[kMaxLevel + 1] = {};
   size_t T0 = 0, B = 0, D[2] = {}, partXT = 0, partYT = 0, atbA = 0, atbB = 0;
   size_t gT[2] = {}, gTmp = 0, gB = 0;
@@ -76,12 +86,16 @@ inline lv_status check_shape(int64_t n, int k, int r_max, lv_mode mode) {
   return LV_OK;
 }
 
-constexpr int kMaxGeneralCols = 64;   // p of the general form (padded to a power of two)
+constexpr int kMaxGeneralCols = 64;      // p with hybrid deltas (padded to a power of two)
+constexpr int kMaxGeneralColsF = 4096;  // p with factored deltas (padded to a multiple of 128)
+constexpr int kMaxGeneralWidthF = 128;  // k * r_pad with factored deltas
 constexpr int kAtbRows = 64;          // rows per FP64 partial of V^T T and W^T B
 
-inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode, int flags = 0, int p = 0) {
+inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode, int flags = 0, int p = 0,
+                          bool factored = false) {
   lv::Layout L;
   L.general = p > 0;
+  L.gfac = L.general && factored;
   L.sums = (flags & LV_WITH_SUMS) != 0 || L.general;
   L.elem = mode == LV_FP64 ? 8 : 4;
   L.n_pad = round_up(n, kPadOrder);
@@ -132,17 +146,34 @@ inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode, int flags =
   }
   if (L.general) {
     L.p = p;
-    L.pp = (int)next_pow2(p);
+    L.pp = L.gfac ? (int)round_up(p, 128) : (int)next_pow2(p);
     const size_t gmat = (size_t)L.n_pad * L.pp * L.elem;
     const size_t gdbl = (size_t)L.n_pad * L.pp * sizeof(double);
     for (int j = 0; j <= L.m; ++j) { L.T[j] = off; off = align_up(off + gmat); }
     L.T0 = off; off = align_up(off + gmat);
     L.B = off; off = align_up(off + gmat);
-    L.D[0] = off; off = align_up(off + gmat);
-    L.D[1] = off; off = align_up(off + gmat);
-    L.partXT = off; off = align_up(off + (size_t)L.nct * gmat);
-    L.partYT = off; off = align_up(off + (size_t)L.nrt_max * gmat);
-    const size_t atb = (size_t)(L.n_pad / kAtbRows) * L.W * L.pp * sizeof(double);
+    const size_t rmax = (size_t)(L.m > 0 ? L.r_pad << (L.m - 1) : L.r_pad);
+    if (L.gfac) {
+      L.wy[0] = L.WY[0] = L.r_pad;
+      int wmax = L.r_pad;
+      for (int j = 1; j <= L.m; ++j) {
+        L.wy[j] = 2 * (L.r_pad << (j - 1)) + L.wy[j - 1];
+        L.WY[j] = (int)next_pow2(L.wy[j]);
+        if (j < L.m && L.WY[j] > wmax) wmax = L.WY[j];
+      }
+      for (int j = 1; j <= L.m; ++j) { L.Y[j] = off; off = align_up(off + (size_t)L.n_pad * L.WY[j] * L.elem); }
+      for (int j = 0; j <= L.m; ++j) { L.Zt[j] = off; off = align_up(off + (size_t)L.WY[j] * L.pp * L.elem); }
+      const size_t xmat = (size_t)L.n_pad * wmax * L.elem;
+      L.partXT = off; off = align_up(off + (size_t)L.nct * xmat);
+      L.partYT = off; off = align_up(off + (size_t)L.nrt_max * xmat);
+      L.atbG = off; off = align_up(off + (size_t)(L.n_pad / kAtbRows) * rmax * wmax * sizeof(double));
+    } else {
+      L.D[0] = off; off = align_up(off + gmat);
+      L.D[1] = off; off = align_up(off + gmat);
+      L.partXT = off; off = align_up(off + (size_t)L.nct * gmat);
+      L.partYT = off; off = align_up(off + (size_t)L.nrt_max * gmat);
+    }
+    const size_t atb = (size_t)(L.n_pad / kAtbRows) * rmax * L.pp * sizeof(double);
     L.atbA = off; off = align_up(off + atb);
     L.atbB = off; off = align_up(off + atb);
     L.gT[0] = off; off = align_up(off + gdbl);
@@ -206,6 +237,9 @@ struct lv_view {
   template <typename T> T* partXT() const { return reinterpret_cast<T*>(base + L.partXT); }
   template <typename T> T* partYT() const { return reinterpret_cast<T*>(base + L.partYT); }
   double* atbA() const { return reinterpret_cast<double*>(base + L.atbA); }
+  double* atbG() const { return reinterpret_cast<double*>(base + L.atbG); }
+  template <typename T> T* Yf(int j) const { return reinterpret_cast<T*>(base + L.Y[j]); }
+  template <typename T> T* Ztf(int j) const { return reinterpret_cast<T*>(base + L.Zt[j]); }
   double* atbB() const { return reinterpret_cast<double*>(base + L.atbB); }
   double* gT(int i) const { return reinterpret_cast<double*>(base + L.gT[i]); }
   double* gTmp() const { return reinterpret_cast<double*>(base + L.gTmp); }

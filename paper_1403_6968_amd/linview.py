@@ -25,6 +25,7 @@ LV_FP64, LV_FP32, LV_FP32_BF16SHADOW = 0, 1, 2
 LV_WITH_SUMS = 1
 LV_MODEL_EXP, LV_MODEL_LIN, LV_MODEL_SKIP = 0, 1, 2
 LV_OLS_BETA, LV_OLS_INVERSE, LV_OLS_X = 0, 1, 2
+LV_GENERAL_HYBRID, LV_GENERAL_FACTORED = 0, 1
 
 _MODE_DTYPE = {LV_FP64: torch.float64, LV_FP32: torch.float32, LV_FP32_BF16SHADOW: torch.float32}
 
@@ -135,8 +136,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "lv_view_footprint_ex": (SZ, [I64, I32, I32, I32, I32]),
         "lv_view_create_ex": (I32, [P, I64, I64, I32, I32, I32, I32, P, SZ, P, c.POINTER(P)]),
         "lv_view_read_sum": (I32, [P, I32, P, I64, P]),
-        "lv_view_footprint_general": (SZ, [I64, I32, I32, I32, I64]),
-        "lv_view_create_general": (I32, [P, I64, I64, I32, I32, I32, P, I64, P, I64, I64, P, SZ, P,
+        "lv_view_footprint_general": (SZ, [I64, I32, I32, I32, I64, I32]),
+        "lv_view_create_general": (I32, [P, I64, I64, I32, I32, I32, P, I64, P, I64, I64, I32, P, SZ, P,
                                          c.POINTER(P)]),
         "lv_view_read_general": (I32, [P, I32, P, I64, P]),
         "lv_chain_footprint": (SZ, [I64, I32, I32, I32, I32, I32]),
@@ -215,12 +216,14 @@ def lv_view_create(A: torch.Tensor, k: int, r_max: int, mode: int, workspace: to
     return h
 
 
-def lv_view_footprint_general(n: int, k: int, r_max: int, mode: int, p: int) -> int:
-    return int(load().lv_view_footprint_general(n, k, r_max, mode, p))
+def lv_view_footprint_general(n: int, k: int, r_max: int, mode: int, p: int,
+                              strategy: int = LV_GENERAL_HYBRID) -> int:
+    return int(load().lv_view_footprint_general(n, k, r_max, mode, p, strategy))
 
 
 def lv_view_create_general(A: torch.Tensor, k: int, r_max: int, mode: int, T0: torch.Tensor,
-                           B: torch.Tensor, workspace: torch.Tensor, stream=None) -> ctypes.c_void_p:
+                           B: torch.Tensor, workspace: torch.Tensor, stream=None,
+                           strategy: int = LV_GENERAL_HYBRID) -> ctypes.c_void_p:
     lib = load()
     dtype = _MODE_DTYPE[mode]
     a, lda = _mat(A, dtype, "A")
@@ -233,7 +236,7 @@ def lv_view_create_general(A: torch.Tensor, k: int, r_max: int, mode: int, T0: t
     if workspace.device.type != "cuda" or not workspace.is_contiguous():
         raise ValueError("workspace must be a contiguous device tensor")
     h = ctypes.c_void_p()
-    _check(lib.lv_view_create_general(a, A.shape[0], lda, k, r_max, mode, t, ldt, b, ldb, T0.shape[1],
+    _check(lib.lv_view_create_general(a, A.shape[0], lda, k, r_max, mode, t, ldt, b, ldb, T0.shape[1], strategy,
                                       workspace.data_ptr(), workspace.numel() * workspace.element_size(),
                                       _stream(stream, A.device), ctypes.byref(h)))
     return h
@@ -362,9 +365,10 @@ class View:
     """A view of A^k whose workspace is a torch device tensor."""
 
     def __init__(self, A: torch.Tensor, k: int, r_max: int = 1, mode: int | None = None,
-                 stream=None, sums: bool = False, general=None):
+                 stream=None, sums: bool = False, general=None, strategy: int = LV_GENERAL_HYBRID):
         """general = (T0, B), both n x p: a view of the general form
-        T_{i+1} = A T_i + B as well (implies sums)."""
+        T_{i+1} = A T_i + B as well (implies sums), with hybrid or factored
+        deltas (strategy)."""
         if mode is None:
             mode = LV_FP64 if A.dtype == torch.float64 else LV_FP32
         self.mode = mode
@@ -377,12 +381,13 @@ class View:
         if general is not None:
             T0, B = general
             self.p = T0.shape[1]
-            nbytes = lv_view_footprint_general(self.n, k, r_max, mode, self.p)
+            nbytes = lv_view_footprint_general(self.n, k, r_max, mode, self.p, strategy)
             if nbytes == 0:
                 _check(load().lv_view_create_general(None, self.n, self.n, k, r_max, mode, None, self.p, None,
-                                                     self.p, self.p, None, 0, None, ctypes.byref(ctypes.c_void_p())))
+                                                     self.p, self.p, strategy, None, 0, None,
+                                                     ctypes.byref(ctypes.c_void_p())))
             self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
-            self.handle = lv_view_create_general(A, k, r_max, mode, T0, B, self.workspace, stream)
+            self.handle = lv_view_create_general(A, k, r_max, mode, T0, B, self.workspace, stream, strategy)
             return
         nbytes = lv_view_footprint(self.n, k, r_max, mode, self.flags)
         if nbytes == 0:

@@ -158,18 +158,29 @@ def test_general_footprint_and_validation(lib):
     assert L.lv_view_footprint_general(1000, 16, 1, L.LV_FP32, 0) == 0
     assert L.lv_view_footprint_general(1000, 16, 1, L.LV_FP32, 65) == 0
     assert L.lv_view_footprint_general(1000, 6, 1, L.LV_FP32, 4) == 0
+    assert L.lv_view_footprint_general(1000, 16, 1, L.LV_FP32, 4, 7) == 0            # unknown strategy
+    F = L.LV_GENERAL_FACTORED
+    fac = L.lv_view_footprint_general(1000, 16, 1, L.LV_FP32, 1000, F)
+    # T_1 .. T_16, T_0, B in storage type (p padded to 1024) and four FP64 n x p creation buffers
+    assert fac >= L.lv_view_footprint(1000, 16, 1, L.LV_FP32, L.LV_WITH_SUMS) + 7 * 1024 * 1024 * 4 + 4 * 1024 * 1024 * 8
+    assert L.lv_view_footprint_general(1000, 16, 1, L.LV_FP32, 4096, F) > 0
+    assert L.lv_view_footprint_general(1000, 16, 1, L.LV_FP32, 4097, F) == 0
+    assert L.lv_view_footprint_general(1000, 16, 16, L.LV_FP32, 4, F) == 0            # k * r_pad > 128
     h = ctypes.c_void_p()
-    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1000, 4, 0x1000, 4, 65, 0x1000, 1 << 30,
+    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1000, 4, 0x1000, 4, 65, 0, 0x1000, 1 << 30,
                                     None, ctypes.byref(h))
     assert st == L.LV_EINVAL and "p = 65" in L.lv_last_error()
-    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, None, 4, 0x1000, 4, 4, 0x1000, 1 << 30,
+    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, None, 4, 0x1000, 4, 4, 0, 0x1000, 1 << 30,
                                     None, ctypes.byref(h))
     assert st == L.LV_EINVAL and "NULL" in L.lv_last_error()
-    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1000, 3, 0x1000, 4, 4, 0x1000, 1 << 30,
+    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1000, 3, 0x1000, 4, 4, 0, 0x1000, 1 << 30,
                                     None, ctypes.byref(h))
     assert st == L.LV_EINVAL and "ldt" in L.lv_last_error()
+    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1000, 4, 0x1000, 4, 4, 3, 0x1000, 1 << 30,
+                                    None, ctypes.byref(h))
+    assert st == L.LV_EINVAL and "strategy" in L.lv_last_error()
     need = L.lv_view_footprint_general(64, 4, 1, L.LV_FP32, 4)
-    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1000, 4, 0x1000, 4, 4, 0x1000, need - 1,
+    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1000, 4, 0x1000, 4, 4, 0, 0x1000, need - 1,
                                     None, ctypes.byref(h))
     assert st == L.LV_ENOMEM and str(need) in L.lv_last_error()
     assert lib.lv_view_read_general(None, 1, 0x1000, 4, None) == L.LV_EINVAL

@@ -212,3 +212,106 @@ def test_general_reanchor_and_errors():
                                                     dev(np.zeros((n, 65)), torch.float32)))
     for x in (view, twin, single, plain):
         x.close()
+
+
+# ---- factored (incremental) deltas, App. B
+
+
+@pytest.mark.parametrize("n,k,r,p,dtype,mode", [
+    (300, 16, 2, 3, "f64", "f64"), (1000, 16, 1, 1, "f32", "f32"), (600, 8, 4, 200, "f32", "f32"),
+    (257, 32, 3, 5, "f32", "f32"), (520, 8, 8, 130, "f64", "f64"), (700, 16, 2, 8, "f32", "bf16"),
+    (130, 1, 2, 2, "f32", "f32"), (384, 16, 1, 1000, "f32", "f32")])
+def test_general_factored_tracks_oracle(n, k, r, p, dtype, mode):
+    lv = _lv()
+    import torch
+    td, nd = (torch.float64, np.float64) if dtype == "f64" else (torch.float32, np.float32)
+    lvmode = {"f64": lv.LV_FP64, "f32": lv.LV_FP32, "bf16": lv.LV_FP32_BF16SHADOW}[mode]
+    tol = {"f64": 1e-10, "f32": 1e-4, "bf16": 5e-3}[mode]
+    dbase = {"f64": 1e-7, "f32": 1e-2, "bf16": 5e-2}[mode]
+    u = 2.0 ** -53 if dtype == "f64" else 2.0 ** -24
+    T = 8
+    A = _rounded(synth.gaussian_matrix(n, seed=70 + n, config=3), nd)
+    T0, B = (_rounded(x, nd) for x in synth.general_operands(n, p, seed=70 + n, config=3))
+    Us, Vs = (_rounded(x, nd) for x in synth.update_factors(n, r, T, seed=70 + n, config=3))
+    view = lv.View(dev(A, td), k, r_max=r, mode=lvmode, general=(dev(T0, td), dev(B, td)),
+                   strategy=lv.LV_GENERAL_FACTORED)
+    plain = lv.View(dev(A, td), k, r_max=r, mode=lvmode, sums=True)
+    P, S, Tr = O.reeval(A, k), O.reeval_sums(A, k), O.reeval_general(A, T0, B, k)
+    T_ref0, T_got0 = Tr, _ts(view)
+    create_err = max(O.maxrel(T_got0[i], Tr[i]) for i in Tr)
+    assert create_err < (1e-13 if dtype == "f64" else 1e-6), create_err
+    for t in range(T):
+        view.update(dev(Us[t], td), dev(Vs[t], td))
+        plain.update(dev(Us[t], td), dev(Vs[t], td))
+        P, S, Tr = O.incr_update_general_factored(P, S, Tr, T0, B, Us[t], Vs[t])
+    got = _ts(view)
+    worst = max(O.maxrel(got[i], Tr[i]) for i in Tr)
+    msg = []
+    for i in Tr:
+        dr = O.deltarel(got[i], T_got0[i], Tr[i], T_ref0[i])
+        dtol = dbase + 4 * np.sqrt(T) * u * np.abs(Tr[i]).max() / np.abs(Tr[i] - T_ref0[i]).max()
+        msg.append(f"T{i}: {dr:.1e}(<{dtol:.1e})")
+        assert dr < dtol, f"T_{i} deltarel {dr:.3e} >= {dtol:.3e}"
+    note(f"general factored n={n} k={k} r={r} p={p} {mode}: create {create_err:.1e}, after {T} updates maxrel "
+         f"{worst:.2e}; " + " ".join(msg))
+    assert worst < tol
+    pw, pp = read_all(view), read_all(plain)
+    for i in pw:
+        np.testing.assert_array_equal(pw[i], pp[i])
+    view.close()
+    plain.close()
+
+
+def test_general_factored_equals_hybrid_fp64():
+    lv = _lv()
+    import torch
+    n, k, r, p = 400, 16, 2, 6
+    A = synth.gaussian_matrix(n, seed=71)
+    T0, B = synth.general_operands(n, p, seed=71)
+    Us, Vs = synth.update_factors(n, r, 5, seed=71)
+    vh = lv.View(dev(A, torch.float64), k, r_max=r, general=(dev(T0, torch.float64), dev(B, torch.float64)))
+    vf = lv.View(dev(A, torch.float64), k, r_max=r, general=(dev(T0, torch.float64), dev(B, torch.float64)),
+                 strategy=lv.LV_GENERAL_FACTORED)
+    for t in range(5):
+        vh.update(dev(Us[t], torch.float64), dev(Vs[t], torch.float64))
+        vf.update(dev(Us[t], torch.float64), dev(Vs[t], torch.float64))
+    gh, gf = _ts(vh), _ts(vf)
+    for i in gh:
+        assert O.maxrel(gf[i], gh[i]) < 1e-12
+    vh.close()
+    vf.close()
+
+
+def test_general_factored_regression_p1000_full_size():
+    """The regression workload at the paper's p = 1000 with n = 8192, FP32,
+    factored deltas, rank-1 row additions; sampled columns of every T_i
+    against the defining iteration on the final A (columns of T evolve
+    independently)."""
+    lv = _lv()
+    import torch
+    n, p, k, T = 8192, 1000, 16, 6
+    A, B, eta = synth.regression_problem(n, p, n + n // 2, seed=9)
+    A, B = _rounded(A, np.float32), _rounded(B, np.float32)
+    T0 = np.zeros((n, p))
+    Us, Vs = (_rounded(x, np.float32) for x in synth.regression_rows(n, T, eta, seed=9))
+    view = lv.View(dev(A, torch.float32), k, general=(dev(T0, torch.float32), dev(B, torch.float32)),
+                   strategy=lv.LV_GENERAL_FACTORED)
+    cols = synth.rng(9, 0, 95).choice(p, size=8, replace=False)
+    base_got = {i: host(view.read_general(i))[:, cols] for i in view.powers()}
+    base_ref = O.iterate_general(A, T0[:, cols], B[:, cols], k)
+    for t in range(T):
+        view.update(dev(Us[t], torch.float32), dev(Vs[t], torch.float32))
+    Afin = A + np.einsum("tir,tjr->ij", Us, Vs)
+    ref = O.iterate_general(Afin, T0[:, cols], B[:, cols], k)
+    got = {i: host(view.read_general(i))[:, cols] for i in view.powers()}
+    u = 2.0 ** -24
+    msg = []
+    for i in ref:
+        mr = O.maxrel(got[i], ref[i])
+        dr = O.deltarel(got[i], base_got[i], ref[i], base_ref[i])
+        dtol = 1e-2 + 4 * np.sqrt(T) * u * np.abs(ref[i]).max() / np.abs(ref[i] - base_ref[i]).max()
+        msg.append(f"T{i}: {mr:.1e}/{dr:.1e}(<{dtol:.1e})")
+        assert mr < 1e-4, f"T_{i} maxrel {mr:.3e}"
+        assert dr < dtol, f"T_{i} deltarel {dr:.3e} >= {dtol:.3e}"
+    note(f"regression factored n={n} p={p}: " + " ".join(msg))
+    view.close()
