@@ -160,6 +160,39 @@ def bench_general(torch, lv, synth, dev, steps=100, ps=(1, 16, 64)):
         del Ar
         out[f"p{p}"] = {"hybrid_exp_ms_per_update": ms, "updates_per_s": 1000.0 / ms,
                         "reeval_lin_torch_ms": lin_ms, "reeval_lin_over_hybrid": lin_ms / ms}
+    # factored deltas (App. B) at p = 16 and at the regression experiment's p = 1000
+    for p in (16, 1000):
+        T0, B = (torch.from_numpy(x.astype(np.float32)).to(dev) for x in synth.general_operands(n, p, seed=0))
+        view = lv.View(A, k, general=(T0, B), strategy=lv.LV_GENERAL_FACTORED)
+        view.update_batch(Ud[:5], Vd[:5])
+        torch.cuda.synchronize()
+        a.record()
+        view.update_batch(Ud[5:5 + steps // 2], Vd[5:5 + steps // 2])
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / (steps // 2)
+        view.close()
+        del view
+        torch.cuda.empty_cache()
+        Ar = A.clone()
+
+        def reeval_lin(t):
+            Ar.addmm_(Ud[t], Vd[t].t())
+            T = T0
+            for _ in range(k):
+                T = torch.addmm(B, Ar, T)
+            return T
+        reeval_lin(0)
+        torch.cuda.synchronize()
+        a.record()
+        for t in range(5):
+            reeval_lin(1 + t)
+        b.record()
+        torch.cuda.synchronize()
+        lin_ms = a.elapsed_time(b) / 5
+        del Ar
+        out[f"p{p}_factored"] = {"factored_exp_ms_per_update": ms, "updates_per_s": 1000.0 / ms,
+                                 "reeval_lin_torch_ms": lin_ms, "reeval_lin_over_factored": lin_ms / ms}
     del A
     return out
 
