@@ -351,18 +351,18 @@ lv_status gfac_finish(lv_view* v, const T* sU, hipStream_t s) {
   return st;
 }
 
-// One update through every level, factors in slab `sl` (App. A exponential
+// One update through every level, factors in the view's slabs (App. A exponential
 // model; trigger of Sec. 4.4): levels 0..m-1 run the fused pass and the tail
 // (or, for float storage at large level rank and with bfloat16 shadows, the
 // read-only skinny pass, the Gram and the update pass), the top level the
 // update-only pass.
 template <typename T>
-lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int64_t ldv, int sl,
+lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int64_t ldv,
                      hipStream_t s) {
   const Layout& L = v->L;
   const int r_pad = (int)next_pow2(r);
-  T* sU = v->slabU<T>(sl);
-  T* sV = v->slabV<T>(sl);
+  T* sU = v->slabU<T>();
+  T* sV = v->slabV<T>();
   lv_status st = hip_check(launch_prep<T>(U, ldu, V, ldv, v->n, r, r_pad, sU, sV, L.W, L.n_pad, s), "prep");
   if (st == LV_OK && L.general)
     st = L.gfac ? gfac_first<T>(v, sV, s) : general_tail<T>(v, -1, r_pad, sU, sV, s);
@@ -644,8 +644,8 @@ lv_status lv_view_update(lv_view* v, const void* U, const void* V, int64_t r, in
   if (st != LV_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   st = v->mode == LV_FP64
-           ? update_one<double>(v, static_cast<const double*>(U), static_cast<const double*>(V), (int)r, ldu, ldv, 0, s)
-           : update_one<float>(v, static_cast<const float*>(U), static_cast<const float*>(V), (int)r, ldu, ldv, 0, s);
+           ? update_one<double>(v, static_cast<const double*>(U), static_cast<const double*>(V), (int)r, ldu, ldv, s)
+           : update_one<float>(v, static_cast<const float*>(U), static_cast<const float*>(V), (int)r, ldu, ldv, s);
   if (st == LV_OK) v->updates += 1;
   return st;
 }
@@ -666,8 +666,8 @@ lv_status lv_view_update_batch(lv_view* v, const void* U, const void* V, int64_t
     const char* Ut = static_cast<const char*>(U) + (size_t)(t * strideU) * es;
     const char* Vt = static_cast<const char*>(V) + (size_t)(t * strideV) * es;
     st = v->mode == LV_FP64
-             ? update_one<double>(v, reinterpret_cast<const double*>(Ut), reinterpret_cast<const double*>(Vt), (int)r, ldu, ldv, 0, s)
-             : update_one<float>(v, reinterpret_cast<const float*>(Ut), reinterpret_cast<const float*>(Vt), (int)r, ldu, ldv, 0, s);
+             ? update_one<double>(v, reinterpret_cast<const double*>(Ut), reinterpret_cast<const double*>(Vt), (int)r, ldu, ldv, s)
+             : update_one<float>(v, reinterpret_cast<const float*>(Ut), reinterpret_cast<const float*>(Vt), (int)r, ldu, ldv, s);
     if (st != LV_OK) return st;
     v->updates += 1;
   }

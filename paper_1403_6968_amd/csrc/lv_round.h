@@ -91,7 +91,7 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
     lv_view* v = views[i];
     const Layout& L = v->L;
     prep.push_back({static_cast<const T*>(in[i].U), in[i].ldu, static_cast<const T*>(in[i].V), in[i].ldv, v->n,
-                    in[i].r, L.r_pad, v->slabU<T>(0), v->slabV<T>(0), L.W, L.n_pad, 0});
+                    in[i].r, L.r_pad, v->slabU<T>(), v->slabV<T>(), L.W, L.n_pad, 0});
     max_m = L.m > max_m ? L.m : max_m;
   }
   pl.add(kPrep, 0, prep, &prep_blocks<T>);
@@ -138,8 +138,8 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
       const int R = L.r_pad << j;
       const int trows = j < L.m ? v->tile_rows[j] : 0;
       const int nrt = j < L.m ? v->nrt(j) : 0;
-      T* sU = v->slabU<T>(0);
-      T* sV = v->slabV<T>(0);
+      T* sU = v->slabU<T>();
+      T* sV = v->slabV<T>();
       const T* Vj = sV + (L.W - R);
       const int upd_rows = update_tile_rows(R, L.elem);
       const int upd_nct = (int)(L.n_pad / update_tile_cols(R, L.elem));

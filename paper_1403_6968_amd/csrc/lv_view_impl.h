@@ -33,8 +33,7 @@ struct Layout {
   int64_t n_pad = 0, ldp = 0;
   int m = 0, r_pad = 0, W = 0, elem = 0, nct = 0, nrt_max = 0, tile_rows = 0;
   size_t P[kMaxLevel + 1] = {};
-  size_t slabU[kMaxLevel + 1] = {};
-  size_t slabV[kMaxLevel + 1] = {};
+  size_t slabU = 0, slabV = 0;   // the update's factor slabs (every level's U_j, V_j)
   size_t partX[kMaxLevel] = {};
   size_t partY[kMaxLevel] = {};
   size_t partG[kMaxLevel] = {};
@@ -110,10 +109,8 @@ inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode, int flags =
   const size_t mat = (size_t)L.n_pad * L.ldp * L.elem;
   for (int j = 0; j <= L.m; ++j) { L.P[j] = off; off = align_up(off + mat); }
   const size_t slab = (size_t)L.n_pad * L.W * L.elem;
-  for (int j = 0; j <= L.m; ++j) {
-    L.slabU[j] = off; off = align_up(off + slab);
-    L.slabV[j] = off; off = align_up(off + slab);
-  }
+  L.slabU = off; off = align_up(off + slab);
+  L.slabV = off; off = align_up(off + slab);
   for (int j = 0; j < L.m; ++j) {
     const size_t R = (size_t)L.r_pad << j;
     L.partX[j] = off; off = align_up(off + (size_t)L.nct * L.n_pad * R * L.elem);
@@ -218,8 +215,8 @@ struct lv_view {
   std::vector<hipEvent_t> pool;
 
   template <typename T> T* P(int j) const { return reinterpret_cast<T*>(base + L.P[j]); }
-  template <typename T> T* slabU(int s) const { return reinterpret_cast<T*>(base + L.slabU[s]); }
-  template <typename T> T* slabV(int s) const { return reinterpret_cast<T*>(base + L.slabV[s]); }
+  template <typename T> T* slabU() const { return reinterpret_cast<T*>(base + L.slabU); }
+  template <typename T> T* slabV() const { return reinterpret_cast<T*>(base + L.slabV); }
   template <typename T> T* partX(int j) const { return reinterpret_cast<T*>(base + L.partX[j]); }
   template <typename T> T* partY(int j) const { return reinterpret_cast<T*>(base + L.partY[j]); }
   double* partG(int j) const { return reinterpret_cast<double*>(base + L.partG[j]); }

@@ -321,3 +321,23 @@ def test_general_factored_regression_p1000_full_size():
         assert dr < dtol, f"T_{i} deltarel {dr:.3e} >= {dtol:.3e}"
     note(f"regression factored n={n} p={p}: " + " ".join(msg))
     view.close()
+
+
+@pytest.mark.parametrize("strategy", [0, 1])
+def test_general_tiny_order(strategy):
+    """n = 5 (all padding), k = 8, FP64, both strategies."""
+    lv = _lv()
+    import torch
+    n, k, p = 5, 8, 3
+    A = synth.gaussian_matrix(n, seed=72)
+    T0, B = synth.general_operands(n, p, seed=72)
+    Us, Vs = synth.update_factors(n, 1, 3, seed=72)
+    view = lv.View(dev(A, torch.float64), k, general=(dev(T0, torch.float64), dev(B, torch.float64)),
+                   strategy=strategy)
+    P, S, Tr = O.reeval(A, k), O.reeval_sums(A, k), O.reeval_general(A, T0, B, k)
+    for t in range(3):
+        view.update(dev(Us[t], torch.float64), dev(Vs[t], torch.float64))
+        P, S, Tr = O.incr_update_general(P, S, Tr, T0, B, Us[t], Vs[t])
+    got = _ts(view)
+    assert max(O.maxrel(got[i], Tr[i]) for i in Tr) < 1e-12
+    view.close()

@@ -138,3 +138,21 @@ def test_models_errors():
     with pytest.raises(lv.LinviewError):
         ch.update(dev(np.zeros((64, 2)), torch.float32), dev(np.zeros((64, 2)), torch.float32))  # r > r_max
     ch.close()
+
+
+@pytest.mark.parametrize("model,k,s,n", [("lin", 5, 0, 3), ("skip", 8, 2, 1), ("exp", 4, 0, 7)])
+def test_models_tiny_orders(model, k, s, n):
+    """Orders far below one tile (all padding) under every model, FP64."""
+    lv = _lv()
+    import torch
+    sm = s if model == "skip" else None
+    A = synth.gaussian_matrix(n, seed=83 + n)
+    Us, Vs = synth.update_factors(n, 1, 3, seed=83 + n)
+    ch = lv.Chain(dev(A, torch.float64), k, model=MODEL[model], s=s)
+    P = O.reeval_model(A, model, k, sm)
+    for t in range(3):
+        ch.update(dev(Us[t], torch.float64), dev(Vs[t], torch.float64))
+        P = O.incr_update_model(P, Us[t], Vs[t], model, k, sm)
+    for i in P:
+        assert O.maxrel(host(ch.read(i)), P[i]) < 1e-12
+    ch.close()

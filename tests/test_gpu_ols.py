@@ -126,3 +126,27 @@ def test_ols_errors():
     with pytest.raises(ValueError):
         ols.update(dev(np.zeros(m - 1), torch.float64), dev(np.zeros(n), torch.float64))
     ols.close()
+
+
+@pytest.mark.parametrize("m,n,p", [(9, 3, 2), (5, 1, 1)])
+def test_ols_tiny(m, n, p):
+    """Orders far below one tile (all padding), FP64, dense and row changes."""
+    lv = _lv()
+    import torch
+    X, Y, g = _data(m, n, p, 20 + m, np.float64)
+    ols = lv.Ols(dev(X, torch.float64), dev(Y, torch.float64))
+    W, beta = O.reeval_ols(X, Y)
+    for t in range(4):
+        if t % 2:
+            row = int(g.integers(0, m))
+            dx = g.standard_normal((n, 1)) * 0.3
+            u = np.zeros((m, 1)); u[row] = 1.0
+            ols.update_row(row, dev(dx[:, 0], torch.float64))
+            X, W, beta = O.incr_update_ols(X, Y, W, beta, u, dx)
+        else:
+            u, v = g.standard_normal((m, 1)) * 0.1, g.standard_normal((n, 1)) * 0.3
+            ols.update(dev(u[:, 0], torch.float64), dev(v[:, 0], torch.float64))
+            X, W, beta = O.incr_update_ols(X, Y, W, beta, u, v)
+    assert O.maxrel(host(ols.read(lv.LV_OLS_BETA)), beta) < 1e-10
+    assert O.maxrel(host(ols.read(lv.LV_OLS_INVERSE)), W) < 1e-10
+    ols.close()
