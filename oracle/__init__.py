@@ -39,6 +39,9 @@ from .general_oracle import (  # noqa: F401
     incr_update_general,
     incr_general_factors,
     incr_update_general_factored,
+    reeval_general_lin,
+    incr_update_general_hybrid_lin,
+    incr_update_general_factored_lin,
 )
 from .models_oracle import (  # noqa: F401
     model_steps,

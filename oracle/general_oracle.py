@@ -37,7 +37,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .linview_oracle import levels, reeval
+from .linview_oracle import OpCounter, levels, reeval
 from .sums_oracle import incr_sums_factors, reeval_sums
 
 
@@ -110,3 +110,62 @@ def incr_update_general_factored(P, S, T, T0, B, U, V):
     Sn = {i: S[i] + dQ[i] @ dW[i].T for i in S}
     Tn = {i: T[i] + Y[i] @ Z[i].T for i in T}
     return Pn, Sn, Tn
+
+
+# ---- the linear model (Sec. 3.2, Table 1): T_{i+1} = A T_i + B stored for
+# every i = 1 .. k (App. B, linear model)
+
+
+def reeval_general_lin(A: np.ndarray, T0: np.ndarray, B: np.ndarray, k: int,
+                       counter: OpCounter | None = None) -> dict[int, np.ndarray]:
+    """ReevalLin: T_1 .. T_k by the iteration itself (k products with A)."""
+    c = counter if counter is not None else OpCounter()
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    out, T = {}, np.asarray(T0, dtype=np.float64)
+    for i in range(1, k + 1):
+        T = c.add(c.mm(A, T), B)
+        out[i] = T
+    return out
+
+
+def incr_update_general_hybrid_lin(A, T, T0, U, V, counter: OpCounter | None = None):
+    """HybridLin step (App. B, hybrid evaluation of the linear model): with
+    Delta A = U V^T and the old A and T,
+        Delta T_1 = U (V^T T_0),
+        Delta T_i = U (V^T T_{i-1}) + A Delta T_{i-1} + U (V^T Delta T_{i-1}),
+    each Delta T_i one n x p matrix; then T_i += Delta T_i and A += U V^T.
+    Returns (A', T')."""
+    c = counter if counter is not None else OpCounter()
+    A = np.asarray(A, dtype=np.float64)
+    U = np.asarray(U, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    D = {1: c.mm(U, c.mm(V.T, np.asarray(T0, dtype=np.float64)))}
+    for i in range(2, max(T) + 1):
+        t1 = c.mm(U, c.mm(V.T, T[i - 1]))
+        t2 = c.mm(A, D[i - 1])
+        t3 = c.mm(U, c.mm(V.T, D[i - 1]))
+        D[i] = c.add(c.add(t1, t2), t3)
+    return A + U @ V.T, {i: T[i] + D[i] for i in T}
+
+
+def incr_update_general_factored_lin(A, T, T0, U, V, counter: OpCounter | None = None):
+    """IncrLin step for the general form (App. B, linear model): factored
+    Delta T_i = Y_i Z_i^T with
+        Y_1 = U,  Z_1 = T_0^T V,
+        Y_i = [U, A Y_{i-1} + U (V^T Y_{i-1})],  Z_i = [T_{i-1}^T V, Z_{i-1}],
+    old A and T; widths i r.  Then T_i += Y_i Z_i^T and A += U V^T.
+    Returns (A', T')."""
+    c = counter if counter is not None else OpCounter()
+    A = np.asarray(A, dtype=np.float64)
+    U = np.asarray(U, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    Y = {1: U}
+    Z = {1: c.mm(np.asarray(T0, dtype=np.float64).T, V)}
+    for i in range(2, max(T) + 1):
+        Y[i] = np.hstack([U, c.add(c.mm(A, Y[i - 1]), c.mm(U, c.mm(V.T, Y[i - 1])))])
+        Z[i] = np.hstack([c.mm(T[i - 1].T, V), Z[i - 1]])
+    Tn = {}
+    for i in T:
+        Tn[i] = T[i] + c.mm(Y[i], Z[i].T)
+    return A + U @ V.T, Tn

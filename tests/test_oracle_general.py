@@ -205,3 +205,71 @@ def test_factored_unmutated_copy_passes():
         Tn = _factored_mutant("none")(O.reeval(A, 8), O.reeval_sums(A, 8), O.reeval_general(A, T0, B, 8), T0, B, U, V)
         ref = _iterate(_frac(A + U @ V.T), _frac(T0), _frac(B), 8)
         assert all((_frac(Tn[i]) == ref[i]).all() for i in Tn)
+
+
+# ---- linear model (App. B): ReevalLin, HybridLin, IncrLin
+
+
+def _lin_exact(fn, n, p, k, r, seed):
+    A, T0, B = _case(n, p, seed)
+    U = synth.integer_matrix((n, r), -1, 1, seed=seed, tag=7)
+    V = synth.integer_matrix((n, r), -1, 1, seed=seed, tag=8)
+    T = O.reeval_general_lin(A, T0, B, k)
+    An, Tn = fn(A, T, T0, U, V)
+    ref = _iterate(_frac(A + U @ V.T), _frac(T0), _frac(B), k)
+    return (_frac(An) == _frac(A + U @ V.T)).all() and all((_frac(Tn[i]) == ref[i]).all() for i in Tn)
+
+
+def test_reeval_general_lin_is_the_iteration():
+    A, T0, B = _case(4, 2, 80)
+    T = O.reeval_general_lin(A, T0, B, 7)
+    ref = _iterate(_frac(A), _frac(T0), _frac(B), 7)
+    assert sorted(T) == list(range(1, 8))
+    for i in T:
+        assert (_frac(T[i]) == ref[i]).all()
+
+
+@pytest.mark.parametrize("k,r,seed", [(6, 1, 81), (8, 2, 82), (3, 1, 83)])
+def test_general_lin_steps_exact(k, r, seed):
+    assert _lin_exact(O.incr_update_general_hybrid_lin, 4, 2, k, r, seed)
+    assert _lin_exact(O.incr_update_general_factored_lin, 4, 2, k, r, seed)
+
+
+@pytest.mark.parametrize("n,p,k", [(5, 1, 8), (7, 3, 16), (4, 6, 4)])
+def test_general_lin_operation_counts_match_appendix_b(n, p, k):
+    """App. B, linear model, rank-1 updates: incremental evaluation costs
+    2np + sum_{i=2..k} (n^2 (i-1) + 3n (i-1) + np (i+1)); hybrid evaluation
+    costs 2np + (k - 1)(p n^2 + 6np); re-evaluation k (p n^2 + np)."""
+    A = synth.gaussian_matrix(n, seed=84)
+    T0, B = synth.general_operands(n, p, seed=84)
+    U, V = synth.update_factors(n, 1, 1, seed=84)
+    T = O.reeval_general_lin(A, T0, B, k)
+    ci, ch, cr = O.OpCounter(), O.OpCounter(), O.OpCounter()
+    O.incr_update_general_factored_lin(A, T, T0, U[0], V[0], ci)
+    O.incr_update_general_hybrid_lin(A, T, T0, U[0], V[0], ch)
+    O.reeval_general_lin(A, T0, B, k, cr)
+    assert ci.ops == 2 * n * p + sum(n * n * (i - 1) + 3 * n * (i - 1) + n * p * (i + 1) for i in range(2, k + 1))
+    assert ch.ops == 2 * n * p + (k - 1) * (p * n * n + 6 * n * p)
+    assert cr.ops == k * (p * n * n + n * p)
+
+
+def _lin_mutant(kind):
+    def fn(A, T, T0, U, V):
+        An = A + U @ V.T
+        D = {1: U @ (V.T @ T0)}
+        for i in range(2, max(T) + 1):
+            Am = An if kind == "new_a" else A
+            t3 = 0 if kind == "drop_cross" else U @ (V.T @ D[i - 1])
+            Tp = T[i - 1] + D[i - 1] if kind == "new_t" else T[i - 1]
+            D[i] = U @ (V.T @ Tp) + Am @ D[i - 1] + t3
+        return An, {i: T[i] + D[i] for i in T}
+    return fn
+
+
+@pytest.mark.parametrize("kind", ["new_a", "drop_cross", "new_t"])
+def test_general_lin_pins_catch_planted_mistakes(kind):
+    assert not all(_lin_exact(_lin_mutant(kind), 4, 2, 6, 1, s) for s in range(85, 88)), kind
+
+
+def test_general_lin_unmutated_copy_passes():
+    assert all(_lin_exact(_lin_mutant("none"), 4, 2, 6, 1, s) for s in range(85, 88))
