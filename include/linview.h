@@ -486,6 +486,41 @@ lv_status lv_ols_read(const lv_ols* o, int what, void* out, int64_t ldo, void* s
 lv_status lv_ols_info(const lv_ols* o, int* iterations, double* residual, double* cond);
 void lv_ols_destroy(lv_ols* o);
 
+/* ---------------------------------------------------------------- linear model
+ *
+ * The general form T_{i+1} = A T_i + B under the linear model (Sec. 3.2,
+ * Table 1; App. B, linear model), T_0, B n x p: every T_1 .. T_k is stored
+ * and kept current under Delta A = U V^T by one of Table 2's strategies:
+ *   LV_GLIN_REEVAL  A += U V^T, then T_i = A T_{i-1} + B, i = 1 .. k;
+ *   LV_GLIN_HYBRID  Delta T_1 = U (V^T T_0),
+ *                   Delta T_i = A Delta T_{i-1} + U (V^T (T_{i-1} + Delta T_{i-1})),
+ *                   dense n x p deltas from the old A and T;
+ *   LV_GLIN_INCR    factored Delta T_i = Y_i Z_i^T, Y_1 = U, Z_1 = T_0^T V,
+ *                   Y_i = [U, A Y_{i-1} + U (V^T Y_{i-1})],
+ *                   Z_i = [T_{i-1}^T V, Z_{i-1}] (old A and T; widths i r);
+ * (hybrid and incremental then apply A += U V^T).  Creation evaluates the
+ * iteration in double and rounds once.  Modes LV_FP64, LV_FP32;
+ * 1 <= k <= 256; 1 <= p <= 4096 (p <= 64 padded to a power of two, wider p
+ * to a multiple of 128, whose products with A run on the MFMA GEMM);
+ * LV_GLIN_INCR needs k * r_max rounded up to a power of two <= 128.
+ * Workspace, streams, ownership and errors as for lv_view. */
+#define LV_GLIN_REEVAL 0
+#define LV_GLIN_HYBRID 1
+#define LV_GLIN_INCR 2
+
+typedef struct lv_glin lv_glin;
+
+size_t lv_glin_footprint(int64_t n, int k, int r_max, lv_mode mode, int64_t p, int strategy);
+lv_status lv_glin_create(const void* A, int64_t n, int64_t lda, int k, int r_max, lv_mode mode,
+                         const void* T0, int64_t ldt, const void* B, int64_t ldb, int64_t p,
+                         int strategy, void* workspace, size_t ws_bytes, void* stream, lv_glin** out);
+/* One update Delta A = U V^T (U, V n x r device, ldu, ldv >= r, r <= r_max). */
+lv_status lv_glin_update(lv_glin* g, const void* U, const void* V, int64_t r, int64_t ldu,
+                         int64_t ldv, void* stream);
+/* Copy T_i (0 <= i <= k; T_0 is the fixed start) to out (n x p, ldo >= p). */
+lv_status lv_glin_read(const lv_glin* g, int i, void* out, int64_t ldo, void* stream);
+void lv_glin_destroy(lv_glin* g);
+
 #ifdef __cplusplus
 }
 #endif

@@ -148,6 +148,8 @@ hipError_t launch_gemm_rect(const T* A, int64_t lda, const T* B, int64_t ldb, T*
 
 template hipError_t launch_gemm_rect<double>(const double*, int64_t, const double*, int64_t, double*, int64_t,
                                              int64_t, int64_t, int64_t, hipStream_t, const int*);
+template hipError_t launch_gemm_rect<float>(const float*, int64_t, const float*, int64_t, float*, int64_t,
+                                            int64_t, int64_t, int64_t, hipStream_t, const int*);
 template hipError_t launch_gemm<double>(const double*, int64_t, const double*, int64_t, double*,
                                         int64_t, int64_t, hipStream_t, const int*);
 template hipError_t launch_gemm<float>(const float*, int64_t, const float*, int64_t, float*,

@@ -26,6 +26,7 @@ LV_WITH_SUMS = 1
 LV_MODEL_EXP, LV_MODEL_LIN, LV_MODEL_SKIP = 0, 1, 2
 LV_OLS_BETA, LV_OLS_INVERSE, LV_OLS_X = 0, 1, 2
 LV_GENERAL_HYBRID, LV_GENERAL_FACTORED = 0, 1
+LV_GLIN_REEVAL, LV_GLIN_HYBRID, LV_GLIN_INCR = 0, 1, 2
 
 _MODE_DTYPE = {LV_FP64: torch.float64, LV_FP32: torch.float32, LV_FP32_BF16SHADOW: torch.float32}
 
@@ -43,6 +44,7 @@ EXPORTED = (
     "lv_chain_footprint", "lv_chain_create", "lv_chain_update", "lv_chain_read", "lv_chain_powers",
     "lv_chain_destroy", "lv_ols_footprint", "lv_ols_create", "lv_ols_update", "lv_ols_update_row",
     "lv_ols_read", "lv_ols_info", "lv_ols_destroy",
+    "lv_glin_footprint", "lv_glin_create", "lv_glin_update", "lv_glin_read", "lv_glin_destroy",
     "lv_server_poll", "lv_server_drain", "lv_server_stats", "lv_server_destroy",
 )
 
@@ -153,6 +155,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "lv_ols_read": (I32, [P, I32, P, I64, P]),
         "lv_ols_info": (I32, [P, c.POINTER(I32), c.POINTER(c.c_double), c.POINTER(c.c_double)]),
         "lv_ols_destroy": (None, [P]),
+        "lv_glin_footprint": (SZ, [I64, I32, I32, I32, I64, I32]),
+        "lv_glin_create": (I32, [P, I64, I64, I32, I32, I32, P, I64, P, I64, I64, I32, P, SZ, P, c.POINTER(P)]),
+        "lv_glin_update": (I32, [P, P, P, I64, I64, I64, P]),
+        "lv_glin_read": (I32, [P, I32, P, I64, P]),
+        "lv_glin_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -757,6 +764,59 @@ class Ols:
         if getattr(self, "handle", None) is not None:
             torch.cuda.synchronize(self.device)
             load().lv_ols_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class GLin:
+    """The general form T_{i+1} = A T_i + B under the linear model, every
+    T_1 .. T_k stored, kept current by re-evaluation, hybrid or incremental
+    evaluation (LV_GLIN_*)."""
+
+    def __init__(self, A: torch.Tensor, k: int, T0: torch.Tensor, B: torch.Tensor, r_max: int = 1,
+                 strategy: int = LV_GLIN_HYBRID, mode: int | None = None, stream=None):
+        if mode is None:
+            mode = LV_FP64 if A.dtype == torch.float64 else LV_FP32
+        self.mode, self.dtype = mode, _MODE_DTYPE[mode]
+        self.n, self.k, self.p, self.device = A.shape[0], k, T0.shape[1], A.device
+        lib = load()
+        nbytes = int(lib.lv_glin_footprint(self.n, k, r_max, mode, self.p, strategy))
+        if nbytes == 0:
+            _check(lib.lv_glin_create(None, self.n, self.n, k, r_max, mode, None, self.p, None, self.p, self.p,
+                                      strategy, None, 0, None, ctypes.byref(ctypes.c_void_p())))
+        a, lda = _mat(A, self.dtype, "A")
+        t, ldt = _mat(T0, self.dtype, "T0")
+        b, ldb = _mat(B, self.dtype, "B")
+        if A.shape[0] != A.shape[1] or T0.shape != B.shape or T0.shape[0] != self.n:
+            raise ValueError("A must be n x n and T0, B both n x p")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+        h = ctypes.c_void_p()
+        _check(lib.lv_glin_create(a, self.n, lda, k, r_max, mode, t, ldt, b, ldb, self.p, strategy,
+                                  self.workspace.data_ptr(), nbytes, _stream(stream, A.device), ctypes.byref(h)))
+        self.handle = h
+
+    def update(self, U: torch.Tensor, V: torch.Tensor, stream=None) -> None:
+        u, ldu = _mat(U, self.dtype, "U")
+        v, ldv = _mat(V, self.dtype, "V")
+        if U.shape != V.shape:
+            raise ValueError("U and V must have the same shape")
+        _check(load().lv_glin_update(self.handle, u, v, U.shape[1], ldu, ldv, _stream(stream, self.device)))
+
+    def read(self, i: int | None = None, stream=None) -> torch.Tensor:
+        i = self.k if i is None else i
+        out = torch.empty(self.n, self.p, dtype=self.dtype, device=self.device)
+        _check(load().lv_glin_read(self.handle, i, out.data_ptr(), self.p, _stream(stream, self.device)))
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None:
+            torch.cuda.synchronize(self.device)
+            load().lv_glin_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -240,3 +240,31 @@ def test_ols_footprint_and_validation(lib):
     assert lib.lv_ols_update(None, 0x1000, 0x1000, None) == L.LV_EINVAL
     assert lib.lv_ols_update_row(None, 0, 0x1000, None) == L.LV_EINVAL
     assert lib.lv_ols_read(None, 0, 0x1000, 1, None) == L.LV_EINVAL
+
+
+def test_glin_footprint_and_validation(lib):
+    from paper_1403_6968_amd import linview as L
+    f = L.load().lv_glin_footprint
+    n_pad = 1024
+    re = f(1000, 16, 1, L.LV_FP32, 4, L.LV_GLIN_REEVAL)
+    hy = f(1000, 16, 1, L.LV_FP32, 4, L.LV_GLIN_HYBRID)
+    inc = f(1000, 16, 1, L.LV_FP32, 4, L.LV_GLIN_INCR)
+    # A (FP32) and its FP64 copy, T_0 .. T_16 and B
+    assert re >= n_pad * n_pad * 12 + 18 * n_pad * 4 * 4
+    assert hy > re and inc > re
+    assert f(1000, 12, 1, L.LV_FP32, 4, L.LV_GLIN_HYBRID) > 0            # any k
+    assert f(1000, 257, 1, L.LV_FP32, 4, L.LV_GLIN_HYBRID) == 0
+    assert f(1000, 16, 1, L.LV_FP32, 4097, L.LV_GLIN_REEVAL) == 0
+    assert f(1000, 16, 16, L.LV_FP32, 4, L.LV_GLIN_INCR) == 0             # k * r_pad > 128
+    assert f(1000, 16, 1, L.LV_FP32, 4, 3) == 0
+    assert f(1000, 16, 1, L.LV_FP32_BF16SHADOW, 4, L.LV_GLIN_HYBRID) == 0
+    h = ctypes.c_void_p()
+    st = lib.lv_glin_create(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1000, 4, 0x1000, 4, 4, 5, 0x1000, 1 << 30, None,
+                            ctypes.byref(h))
+    assert st == L.LV_EINVAL and "strategy" in L.lv_last_error()
+    need = f(64, 4, 1, L.LV_FP32, 4, L.LV_GLIN_INCR)
+    st = lib.lv_glin_create(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1000, 4, 0x1000, 4, 4, L.LV_GLIN_INCR, 0x1000,
+                            need - 1, None, ctypes.byref(h))
+    assert st == L.LV_ENOMEM and str(need) in L.lv_last_error()
+    assert lib.lv_glin_update(None, 0x1000, 0x1000, 1, 1, 1, None) == L.LV_EINVAL
+    assert lib.lv_glin_read(None, 1, 0x1000, 4, None) == L.LV_EINVAL
