@@ -50,7 +50,7 @@ def parse():
     p.add_argument("--no-secondary", action="store_true",
                    help="skip the rank-4, batched and serving workloads")
     p.add_argument("--serve-seconds", type=float, default=2.0)
-    p.add_argument("--only", choices=["rank4", "batched", "serving", "sums", "general", "models", "ols"],
+    p.add_argument("--only", choices=["rank4", "batched", "serving", "sums", "general", "models", "ols", "glin"],
                    help="run one secondary workload alone and print its result (for profilers)")
     return p.parse_args()
 
@@ -307,6 +307,43 @@ def bench_ols(torch, lv, synth, dev, m=16384, n=8192, p=16, steps=50):
             "speedup_row_vs_torch_reeval": torch_ms / row_ms}
 
 
+def bench_glin(torch, lv, synth, dev, ps=(1, 16, 64, 1000)):
+    """The general form under the linear model with B = 0 (the p sweep of the
+    paper's general-form experiment), n = 8192, k = 16, FP32, rank-1 updates:
+    ms per update of re-evaluation, hybrid and incremental evaluation
+    (every T_1 .. T_16 kept current by each)."""
+    n, k = 8192, 16
+    A = torch.from_numpy(synth.gaussian_matrix(n, seed=0, config=2).astype(np.float32)).to(dev)
+    U, V = synth.update_factors(n, 1, 40, seed=0, config=2)
+    Ud = torch.from_numpy(U.astype(np.float32)).to(dev)
+    Vd = torch.from_numpy(V.astype(np.float32)).to(dev)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {"workload": "general form T_{i+1} = A T_i (B = 0), linear model, n=8192, k=16, FP32, rank-1 updates"}
+    for p in ps:
+        T0 = torch.from_numpy(synth.general_operands(n, p, seed=0)[0].astype(np.float32)).to(dev)
+        B = torch.zeros_like(T0)
+        row = {}
+        for name, strat in (("reeval_lin_ms", lv.LV_GLIN_REEVAL), ("hybrid_lin_ms", lv.LV_GLIN_HYBRID),
+                            ("incr_lin_ms", lv.LV_GLIN_INCR)):
+            g = lv.GLin(A, k, T0, B, strategy=strat)
+            g.update(Ud[0], Vd[0])
+            torch.cuda.synchronize()
+            reps = 10
+            a.record()
+            for t in range(reps):
+                g.update(Ud[1 + t], Vd[1 + t])
+            b.record()
+            torch.cuda.synchronize()
+            row[name] = a.elapsed_time(b) / reps
+            g.close()
+            del g
+            torch.cuda.empty_cache()
+        out[f"p{p}"] = row
+        log(f"glin p={p}: {row}")
+    del A
+    return out
+
+
 def bench_batched(torch, lv, synth, dev, rounds=30):
     """64 views, n in {512..4096}, k in {8, 16}, rank 1..8, FP32: one graph
     replay per round (every view applies one update)."""
@@ -471,7 +508,8 @@ def main():
               "sums": lambda: bench_sums(torch, lv, synth, dev),
               "general": lambda: bench_general(torch, lv, synth, dev),
               "models": lambda: bench_models(torch, lv, synth, dev),
-              "ols": lambda: bench_ols(torch, lv, synth, dev)}[args.only]
+              "ols": lambda: bench_ols(torch, lv, synth, dev),
+              "glin": lambda: bench_glin(torch, lv, synth, dev)}[args.only]
         print(json.dumps({"only": args.only, "result": fn()}), flush=True)
         return
     n, k, r = args.n, args.k, args.rank
@@ -637,6 +675,7 @@ def main():
                          ("general_n8192", lambda: bench_general(torch, lv, synth, dev)),
                          ("models_k_sweep_n8192", lambda: bench_models(torch, lv, synth, dev)),
                          ("ols_16384x8192", lambda: bench_ols(torch, lv, synth, dev)),
+                         ("general_linear_model_n8192", lambda: bench_glin(torch, lv, synth, dev)),
                          ("batched_64_views", lambda: bench_batched(torch, lv, synth, dev)),
                          ("serving_32_views", lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds)),
                          ("serving_32_views_fp32",
