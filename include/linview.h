@@ -187,19 +187,29 @@ lv_status lv_view_read_sum(const lv_view* v, int index, void* out, int64_t ldo, 
  *  T0, B     n x p (device, element type of the mode), leading dimensions
  *            ldt, ldb >= p; copied into the workspace, not retained.
  *  strategy  LV_GENERAL_HYBRID or LV_GENERAL_FACTORED.
+ *  s         0 (or k): the exponential model above.  Else the skip-s model
+ *            (Table 1; App. B skip model; factored deltas only): the powers
+ *            and sums stop at P_s, S_s (s a power of two dividing k), and
+ *            beyond T_s the view stores T_2s, T_3s, ..., T_k with
+ *            T_js = P_s T_(j-1)s + S_s B, whose factored deltas are
+ *            [U_s, P_s Y + U_s (V_s^T Y), Q_s] [T^T V_s, Z, B^T W_s]^T from the
+ *            previous T's factors (Y, Z) and the top-level ones;
+ *            (2k - 1 - 2s) * r_max rounded up must not exceed 128.
  * Other arguments, ownership and errors as lv_view_create; the footprint
  * is 0 for invalid arguments.  Such views are single-view only. */
 #define LV_GENERAL_HYBRID 0
 #define LV_GENERAL_FACTORED 1
-size_t lv_view_footprint_general(int64_t n, int k, int r_max, lv_mode mode, int64_t p, int strategy);
+size_t lv_view_footprint_general(int64_t n, int k, int r_max, lv_mode mode, int64_t p, int strategy,
+                                 int s);
 lv_status lv_view_create_general(const void* A, int64_t n, int64_t lda, int k, int r_max,
                                  lv_mode mode, const void* T0, int64_t ldt, const void* B,
-                                 int64_t ldb, int64_t p, int strategy, void* workspace,
+                                 int64_t ldb, int64_t p, int strategy, int s, void* workspace,
                                  size_t ws_bytes, void* stream, lv_view** out);
 
-/* Copy stored T_index (index in {1, 2, 4, ..., k}) of a general-form view to
- * out (n x p, leading dimension ldo >= p, device).  LV_ESTATE for a view
- * created otherwise. */
+/* Copy stored T_index (index in {1, 2, 4, ..., k}, or {1, 2, 4, ..., s, 2s,
+ * 3s, ..., k} under the skip model) of a general-form view to out (n x p,
+ * leading dimension ldo >= p, device).  LV_ESTATE for a view created
+ * otherwise. */
 lv_status lv_view_read_general(const lv_view* v, int index, void* out, int64_t ldo, void* stream);
 
 /* Borrowed device pointer to stored power A^power and its leading

@@ -39,6 +39,10 @@ from .general_oracle import (  # noqa: F401
     incr_update_general,
     incr_general_factors,
     incr_update_general_factored,
+    skip_indices,
+    reeval_general_skip,
+    incr_general_factors_skip,
+    incr_update_general_factored_skip,
     reeval_general_lin,
     incr_update_general_hybrid_lin,
     incr_update_general_factored_lin,

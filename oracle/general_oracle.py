@@ -31,6 +31,15 @@ the paper counts them) and Q_h of its own width r (h - 1) above: widths
 c_1 = r, c_2 = 3r, c_{2h} = h r + c_h + (h - 1) r; every T_i then takes
 T_i += Y_i Z_i^T.  (The paper's count (2i - 1) r also takes Q_h as h r wide;
 zero columns change no product.)
+
+Skip-s model (Table 1, general form column; App. B): the exponential model
+up to T_s, then T_{js} = P_s T_{(j-1)s} + S_s B for j = 2 .. k/s, so that
+the same expansion with h = (j - 1)s and the top-level factors gives
+
+    Y_{js} = [U_s, P_s Y_h + U_s (V_s^T Y_h), Q_s],
+    Z_{js} = [T_h^T V_s, Z_h, B^T W_s],
+
+widths c_{js} = c_h + s r + (s - 1) r (Q_1 again a zero block of width r).
 """
 
 from __future__ import annotations
@@ -106,6 +115,60 @@ def incr_update_general_factored(P, S, T, T0, B, U, V):
     Returns (P', S', T')."""
     dQ, dW, dU, dV = incr_sums_factors(P, S, U, V)
     Y, Z = incr_general_factors(P, S, T, T0, B, U, V)
+    Pn = {i: P[i] + dU[i] @ dV[i].T for i in P}
+    Sn = {i: S[i] + dQ[i] @ dW[i].T for i in S}
+    Tn = {i: T[i] + Y[i] @ Z[i].T for i in T}
+    return Pn, Sn, Tn
+
+
+def _check_skip(k: int, s: int) -> None:
+    if s < 1 or s & (s - 1) or k % s:
+        raise ValueError(f"skip model needs s a power of two dividing k, got s={s}, k={k}")
+
+
+def skip_indices(k: int, s: int) -> list[int]:
+    """Indices of the stored T under the skip-s model: 1, 2, 4, .., s, 2s, .., k."""
+    _check_skip(k, s)
+    return levels(s) + list(range(2 * s, k + 1, s))
+
+
+def reeval_general_skip(A: np.ndarray, T0: np.ndarray, B: np.ndarray, k: int, s: int) -> dict[int, np.ndarray]:
+    """T_1, T_2, .., T_s by the exponential model, then T_2s, .., T_k by
+    T_{js} = P_s T_{(j-1)s} + S_s B (skip-s model of Table 1)."""
+    _check_skip(k, s)
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    T = reeval_general(A, T0, B, s)
+    Ps, Ss = reeval(A, s)[s], reeval_sums(A, s)[s]
+    for i in range(2 * s, k + 1, s):
+        T[i] = Ps @ T[i - s] + Ss @ B
+    return T
+
+
+def incr_general_factors_skip(P, S, T, T0, B, U, V, s: int):
+    """Factored deltas of every stored T under the skip-s model (module
+    docstring), from the old powers and sums up to s and the old T.
+    Returns (Y, Z)."""
+    U = np.asarray(U, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    Y, Z = incr_general_factors(P, S, {i: T[i] for i in levels(s)}, T0, B, U, V)
+    dQ, dW, dU, dV = incr_sums_factors(P, S, U, V)
+    n, r = U.shape
+    Qs, Ws = (dQ[s], dW[s]) if s > 1 else (np.zeros((n, r)), np.zeros((n, r)))
+    for i in range(2 * s, max(T) + 1, s):
+        h = i - s
+        Y[i] = np.hstack([dU[s], P[s] @ Y[h] + dU[s] @ (dV[s].T @ Y[h]), Qs])
+        Z[i] = np.hstack([T[h].T @ dV[s], Z[h], B.T @ Ws])
+    return Y, Z
+
+
+def incr_update_general_factored_skip(P, S, T, T0, B, U, V, s: int):
+    """IncrSkip-s step for the powers and sums up to s and every stored T:
+    all factors from the old values, then every stored matrix takes its
+    delta.  Returns (P', S', T')."""
+    dQ, dW, dU, dV = incr_sums_factors(P, S, U, V)
+    Y, Z = incr_general_factors_skip(P, S, T, T0, B, U, V, s)
     Pn = {i: P[i] + dU[i] @ dV[i].T for i in P}
     Sn = {i: S[i] + dQ[i] @ dW[i].T for i in S}
     Tn = {i: T[i] + Y[i] @ Z[i].T for i in T}

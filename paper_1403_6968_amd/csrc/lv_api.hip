@@ -74,6 +74,27 @@ lv_status general_step(lv_view* v, int j, const double* P, const double* S, int6
   return st;
 }
 
+// Skip model, creation: T_{(q+1)s} = P_s T_{qs} + S_s B for q = 1 .. nsk in
+// double from the double P_s, S_s (the last level's T_s sits in gT((m+1) & 1)).
+template <typename T>
+lv_status skip_steps(lv_view* v, const double* P, const double* S, int64_t ld, hipStream_t s, const int* gate) {
+  const Layout& L = v->L;
+  lv_status st = LV_OK;
+  for (int q = 1; q <= L.nsk && st == LV_OK; ++q) {
+    double* prev = v->gT((L.m + q) & 1);
+    double* next = v->gT((L.m + q + 1) & 1);
+    st = hip_check(launch_gemm_rect<double>(S, ld, v->gB(), L.pp, v->gTmp(), L.pp, L.n_pad, L.pp, L.n_pad, s, gate),
+                   "S_s B");
+    if (st == LV_OK)
+      st = hip_check(launch_gemm_rect<double>(P, ld, prev, L.pp, next, L.pp, L.n_pad, L.pp, L.n_pad, s, gate), "P_s T");
+    if (st == LV_OK) st = hip_check(launch_add<double>(next, v->gTmp(), L.n_pad * L.pp, s, gate), "+ S_s B");
+    if (st == LV_OK)
+      st = hip_check(launch_copy_rect<double, T>(next, L.pp, L.n_pad, L.pp, v->Tskp<T>(q), L.n_pad, L.pp, s, gate),
+                     "round T");
+  }
+  return st;
+}
+
 template <typename T>
 lv_status build_chain(lv_view* v, hipStream_t s, const int* gate = nullptr) {
   const Layout& L = v->L;
@@ -103,6 +124,10 @@ lv_status build_chain(lv_view* v, hipStream_t s, const int* gate = nullptr) {
         if (st == LV_OK) st = hip_check(launch_add<double>(v->S<double>(j), v->S<double>(j - 1), cnt, s, gate), "S add");
         if (st != LV_OK) return st;
       }
+    }
+    if (L.nsk > 0) {
+      lv_status st = skip_steps<double>(v, v->P<double>(L.m), v->S<double>(L.m), L.ldp, s, gate);
+      if (st != LV_OK) return st;
     }
   } else {
     if (L.m == 0 && !L.general) return LV_OK;
@@ -138,6 +163,10 @@ lv_status build_chain(lv_view* v, hipStream_t s, const int* gate = nullptr) {
       st = hip_check(launch_copy_pad<double, float>(dst, L.n_pad, L.n_pad, v->P<float>(j), L.ldp, L.n_pad, s,
                                                     gate),
                      "round P");
+      if (st != LV_OK) return st;
+    }
+    if (L.nsk > 0) {
+      st = skip_steps<float>(v, v->scratch(L.m & 1), v->sscratch(L.m & 1), L.n_pad, s, gate);
       if (st != LV_OK) return st;
     }
     if (v->shadowed())
@@ -272,30 +301,38 @@ lv_status general_tail(lv_view* v, int j, int R, const T* sU, const T* sV, hipSt
   });
 }
 
+// Widths of the factored deltas for an update of padded rank ru (the slabs
+// are laid out for r_max; their columns beyond these widths are zero):
+// Y_j, Z_j have (2^(j+1) - 1) ru columns, the skip factors wy(m) + 2 q ru 2^m.
+inline int gw(int ru, int j) { return ((2 << j) - 1) * ru; }
+inline int gW(int ru, int j) { return (int)next_pow2(gw(ru, j)); }
+inline int gwsk(const Layout& L, int ru, int q) { return gw(ru, L.m) + q * 2 * (ru << L.m); }
+inline int gWsk(const Layout& L, int ru, int q) { return (int)next_pow2(gwsk(L, ru, q)); }
+
 // General form with factored deltas Delta T_j = Y_j Z_j^T (App. B,
 // exponential model): Y_0 is the prefix [0, r_pad) of the powers' U slab,
 // Z_0 = T_0^T V.  Every T_j keeps its old value until the whole update has
 // formed its factors (gfac_finish applies T_j += Y_j Z_j^T).
 template <typename T>
-lv_status gfac_first(lv_view* v, const T* sV, hipStream_t s) {
+lv_status gfac_first(lv_view* v, int ru, const T* sV, hipStream_t s) {
   const Layout& L = v->L;
   lv_status st = timed(v, 0, s, "general: T_0^T V", [&] {
-    return launch_atb<T>(L.r_pad, L.pp, sV + (L.W - L.r_pad), L.W, v->T0<T>(), L.pp, L.n_pad, v->atbA(), s);
+    return launch_atb<T>(ru, L.pp, sV + (L.W - ru), L.W, v->T0<T>(), L.pp, L.n_pad, v->atbA(), s);
   });
   if (st != LV_OK) return st;
   return timed(v, 1, s, "general: Z_0", [&] {
-    return launch_gfac_z<T>(v->atbA(), nullptr, 0, nullptr, L.r_pad, v->Ztf<T>(0), L.WY[0], L.pp, s);
+    return launch_gfac_z<T>(v->atbA(), nullptr, 0, nullptr, ru, v->Ztf<T>(0), L.WY[0], L.pp, s);
   });
 }
 
 // Level j, before the powers' update: X = P_j Y_j with the OLD P_j (the
 // float matrix cores from width 16, X only; else the read-only vector pass).
 template <typename T>
-lv_status gfac_pass(lv_view* v, int j, const T* sU, hipStream_t s) {
+lv_status gfac_pass(lv_view* v, int j, int ru, const T* sU, hipStream_t s) {
   const Layout& L = v->L;
   const T* Yj = j == 0 ? sU : v->Yf<T>(j);
   const int sy = j == 0 ? L.W : L.WY[j];
-  const int R = L.WY[j];
+  const int R = gW(ru, j);
   return timed(v, 0, s, "general: P Y", [&] {
     if (skinny_on_mfma(R, (int)sizeof(T)))
       return launch_skinny_f32(R, reinterpret_cast<const float*>(v->P<T>(j)), L.ldp, L.n_pad, v->tile_rows[j],
@@ -310,13 +347,14 @@ lv_status gfac_pass(lv_view* v, int j, const T* sU, hipStream_t s) {
 // tail (Q_j intact): G = V_j^T Y_j, a = V_j^T T_j (old T_j), b = W_j^T B
 // (j > 0), then Y_{j+1} = [U_j, X + U_j G, Q_j] and Z_{j+1}^T = [a; Z_j^T; b].
 template <typename T>
-lv_status gfac_tail(lv_view* v, int j, int R, const T* sU, const T* sV, hipStream_t s) {
+lv_status gfac_tail(lv_view* v, int j, int R, int ru, const T* sU, const T* sV, hipStream_t s) {
   const Layout& L = v->L;
   const T* Yj = j == 0 ? sU : v->Yf<T>(j);
   const int sy = j == 0 ? L.W : L.WY[j];
+  const int wj = gW(ru, j);
   const T* Vj = sV + (L.W - R);
   lv_status st = timed(v, 0, s, "general: V^T Y", [&] {
-    return launch_atb<T>(R, L.WY[j], Vj, L.W, Yj, sy, L.n_pad, v->atbG(), s);
+    return launch_atb<T>(R, wj, Vj, L.W, Yj, sy, L.n_pad, v->atbG(), s);
   });
   if (st == LV_OK)
     st = timed(v, 0, s, "general: V^T T", [&] {
@@ -328,25 +366,81 @@ lv_status gfac_tail(lv_view* v, int j, int R, const T* sU, const T* sV, hipStrea
     });
   if (st == LV_OK)
     st = timed(v, 1, s, "general: Y", [&] {
-      return launch_gfac_y<T>(v->partXT<T>(), L.nct, L.WY[j], sU, j > 0 ? v->slabQ<T>() : nullptr, L.W, R, v->atbG(),
-                              L.WY[j], L.wy[j], v->Yf<T>(j + 1), L.WY[j + 1], L.n_pad, s);
+      return launch_gfac_y<T>(v->partXT<T>(), L.nct, wj, sU, j > 0 ? v->slabQ<T>() : nullptr, L.W, R, v->atbG(), wj,
+                              gw(ru, j), v->Yf<T>(j + 1), L.WY[j + 1], L.n_pad, s);
     });
   if (st == LV_OK)
     st = timed(v, 1, s, "general: Z", [&] {
-      return launch_gfac_z<T>(v->atbA(), v->Ztf<T>(j), L.wy[j], j > 0 ? v->atbB() : nullptr, R, v->Ztf<T>(j + 1),
+      return launch_gfac_z<T>(v->atbA(), v->Ztf<T>(j), gw(ru, j), j > 0 ? v->atbB() : nullptr, R, v->Ztf<T>(j + 1),
                               L.WY[j + 1], L.pp, s);
     });
   return st;
 }
 
+// Skip model (Table 1; App. B skip model, factored): for q = 1 .. nsk,
+// T_{(q+1)s} = P_s T_{qs} + S_s B gives, with the OLD P_s, T_{qs} and the
+// top-level factors U_s, V_s, Q_s, W_s (all formed by the level loop),
+//   Y = [U_s, P_s Y_prev + U_s (V_s^T Y_prev), Q_s],  Z = [T_prev^T V_s, Z_prev, B^T W_s].
+// Runs before the top update of P_s.
 template <typename T>
-lv_status gfac_finish(lv_view* v, const T* sU, hipStream_t s) {
+lv_status gfac_skip(lv_view* v, int ru, const T* sU, const T* sV, hipStream_t s) {
+  const Layout& L = v->L;
+  const int Rm = ru << L.m;
+  const T* Vm = sV + (L.W - Rm);
+  lv_status st = LV_OK;
+  if (L.m > 0)
+    st = timed(v, 0, s, "general: W_s^T B", [&] {
+      return launch_atb<T>(Rm, L.pp, v->slabW<T>() + (L.W - Rm), L.W, v->Bg<T>(), L.pp, L.n_pad, v->atbB(), s);
+    });
+  for (int q = 1; q <= L.nsk && st == LV_OK; ++q) {
+    const T* Yp = q > 1 ? v->Yskp<T>(q - 1) : (L.m == 0 ? sU : v->Yf<T>(L.m));
+    const int sp = q > 1 ? L.WYsk(q - 1) : (L.m == 0 ? L.W : L.WY[L.m]);
+    const int wp = q > 1 ? gWsk(L, ru, q - 1) : gW(ru, L.m);
+    const T* Zp = q > 1 ? v->Ztskp<T>(q - 1) : v->Ztf<T>(L.m);
+    const T* Tp = q > 1 ? v->Tskp<T>(q - 1) : v->Tg<T>(L.m);
+    st = timed(v, 0, s, "general: P_s Y", [&] {
+      if (skinny_on_mfma(wp, (int)sizeof(T)))
+        return launch_skinny_f32(wp, reinterpret_cast<const float*>(v->P<T>(L.m)), L.ldp, L.n_pad, kTileRows,
+                                 reinterpret_cast<const float*>(Yp), reinterpret_cast<const float*>(Yp), sp,
+                                 v->partXT<float>(), v->partYT<float>(), s, kWantX);
+      return launch_level_readonly<T>(wp, v->P<T>(L.m), L.ldp, L.n_pad, kTileRows, Yp, Yp, sp, v->partXT<T>(),
+                                      v->partYT<T>(), s);
+    });
+    if (st == LV_OK)
+      st = timed(v, 0, s, "general: V_s^T Y", [&] {
+        return launch_atb<T>(Rm, wp, Vm, L.W, Yp, sp, L.n_pad, v->atbG(), s);
+      });
+    if (st == LV_OK)
+      st = timed(v, 0, s, "general: V_s^T T", [&] {
+        return launch_atb<T>(Rm, L.pp, Vm, L.W, Tp, L.pp, L.n_pad, v->atbA(), s);
+      });
+    if (st == LV_OK)
+      st = timed(v, 1, s, "general: Y (skip)", [&] {
+        return launch_gfac_y<T>(v->partXT<T>(), L.nct, wp, sU, L.m > 0 ? v->slabQ<T>() : nullptr, L.W, Rm,
+                                v->atbG(), wp, gwsk(L, ru, q - 1), v->Yskp<T>(q), L.WYsk(q), L.n_pad, s);
+      });
+    if (st == LV_OK)
+      st = timed(v, 1, s, "general: Z (skip)", [&] {
+        return launch_gfac_z<T>(v->atbA(), Zp, gwsk(L, ru, q - 1), L.m > 0 ? v->atbB() : nullptr, Rm, v->Ztskp<T>(q),
+                                L.WYsk(q), L.pp, s);
+      });
+  }
+  return st;
+}
+
+template <typename T>
+lv_status gfac_finish(lv_view* v, int ru, const T* sU, hipStream_t s) {
   const Layout& L = v->L;
   lv_status st = LV_OK;
   for (int j = 0; j <= L.m && st == LV_OK; ++j)
     st = timed(v, 2, s, "general: T += Y Z^T", [&] {
       return launch_rank_rect<T>(v->Tg<T>(j), j == 0 ? sU : v->Yf<T>(j), j == 0 ? L.W : L.WY[j], v->Ztf<T>(j),
-                                 L.wy[j], L.n_pad, L.pp, s);
+                                 gw(ru, j), L.n_pad, L.pp, s);
+    });
+  for (int q = 1; q <= L.nsk && st == LV_OK; ++q)
+    st = timed(v, 2, s, "general: T += Y Z^T (skip)", [&] {
+      return launch_rank_rect<T>(v->Tskp<T>(q), v->Yskp<T>(q), L.WYsk(q), v->Ztskp<T>(q), gwsk(L, ru, q), L.n_pad,
+                                 L.pp, s);
     });
   return st;
 }
@@ -365,12 +459,12 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
   T* sV = v->slabV<T>();
   lv_status st = hip_check(launch_prep<T>(U, ldu, V, ldv, v->n, r, r_pad, sU, sV, L.W, L.n_pad, s), "prep");
   if (st == LV_OK && L.general)
-    st = L.gfac ? gfac_first<T>(v, sV, s) : general_tail<T>(v, -1, r_pad, sU, sV, s);
+    st = L.gfac ? gfac_first<T>(v, r_pad, sV, s) : general_tail<T>(v, -1, r_pad, sU, sV, s);
   if (st != LV_OK) return st;
   for (int j = 0; j < L.m; ++j) {
     const int R = r_pad << j;
     if (L.general) {
-      st = L.gfac ? gfac_pass<T>(v, j, sU, s) : general_pass<T>(v, j, s);
+      st = L.gfac ? gfac_pass<T>(v, j, r_pad, sU, s) : general_pass<T>(v, j, s);
       if (st != LV_OK) return st;
     }
     if (L.sums && j > 0) {
@@ -411,7 +505,7 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
                                             1, L.n_pad, sU, sV, L.W, s);
           });
         if (st == LV_OK && L.general)
-          st = L.gfac ? gfac_tail<T>(v, j, R, sU, sV, s) : general_tail<T>(v, j, R, sU, sV, s);
+          st = L.gfac ? gfac_tail<T>(v, j, R, r_pad, sU, sV, s) : general_tail<T>(v, j, R, sU, sV, s);
         if (st == LV_OK && L.sums) st = sums_level<T>(v, j, R, sU, sV, s);
         if (st != LV_OK) return st;
         continue;
@@ -427,8 +521,12 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
                                   gram_in_pass(R, (int)sizeof(T)) ? v->nrt(j) : 1, L.n_pad, sU, sV, L.W, s);
     });
     if (st == LV_OK && L.general)
-      st = L.gfac ? gfac_tail<T>(v, j, R, sU, sV, s) : general_tail<T>(v, j, R, sU, sV, s);
+      st = L.gfac ? gfac_tail<T>(v, j, R, r_pad, sU, sV, s) : general_tail<T>(v, j, R, sU, sV, s);
     if (st == LV_OK && L.sums) st = sums_level<T>(v, j, R, sU, sV, s);
+    if (st != LV_OK) return st;
+  }
+  if (L.nsk > 0) {
+    st = gfac_skip<T>(v, r_pad, sU, sV, s);
     if (st != LV_OK) return st;
   }
   const int Rm = r_pad << L.m;
@@ -439,7 +537,7 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
     st = timed(v, 2, s, "sums: top update", [&] {
       return launch_level_update<T>(Rm, v->S<T>(L.m), L.ldp, L.n_pad, v->slabQ<T>(), v->slabW<T>(), L.W, s);
     });
-  if (st == LV_OK && L.gfac) st = gfac_finish<T>(v, sU, s);
+  if (st == LV_OK && L.gfac) st = gfac_finish<T>(v, r_pad, sU, s);
   return st;
 }
 
@@ -517,7 +615,7 @@ namespace {
 // Creation of every kind of view; p > 0 makes a general-form view with T_0
 // and B (n x p, leading dimensions ldt, ldb).
 lv_status create_view(const void* A, int64_t n, int64_t lda, int k, int r_max, lv_mode mode, int flags, int p,
-                      bool factored, const void* T0, int64_t ldt, const void* B, int64_t ldb, void* workspace,
+                      bool factored, int kT, const void* T0, int64_t ldt, const void* B, int64_t ldb, void* workspace,
                       size_t ws_bytes, void* stream, lv_view** out) {
   g_err[0] = 0;
   if (!out) return fail(LV_EINVAL, "out is NULL");
@@ -529,7 +627,7 @@ lv_status create_view(const void* A, int64_t n, int64_t lda, int k, int r_max, l
   if (lda < n) return fail(LV_EINVAL, "lda = %lld < n = %lld", (long long)lda, (long long)n);
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
     return fail(LV_ENOMEM, "workspace is not %zu-byte aligned", kAlign);
-  const Layout L = make_layout(n, k, r_max, mode, flags, p, factored);
+  const Layout L = make_layout(n, k, r_max, mode, flags, p, factored, kT);
   if (ws_bytes < L.total)
     return fail(LV_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
   lv_view* v = new (std::nothrow) lv_view();
@@ -581,16 +679,29 @@ extern "C" {
 
 lv_status lv_view_create_ex(const void* A, int64_t n, int64_t lda, int k, int r_max, lv_mode mode, int flags,
                             void* workspace, size_t ws_bytes, void* stream, lv_view** out) {
-  return create_view(A, n, lda, k, r_max, mode, flags, 0, false, nullptr, 0, nullptr, 0, workspace, ws_bytes, stream,
-                     out);
+  return create_view(A, n, lda, k, r_max, mode, flags, 0, false, 0, nullptr, 0, nullptr, 0, workspace, ws_bytes,
+                     stream, out);
 }
 
 }  // extern "C"
 
 namespace {
 
-lv_status check_general(int64_t n, int k, int r_max, lv_mode mode, int64_t p, int strategy) {
-  lv_status st = check_shape(n, k, r_max, mode);
+// k iterations of T; the powers and sums run to s (s = 0 or s = k: the
+// exponential model; else the skip-s model, factored deltas only).
+lv_status check_general(int64_t n, int k, int r_max, lv_mode mode, int64_t p, int strategy, int s) {
+  if (s != 0 && s != k) {
+    if (strategy != LV_GENERAL_FACTORED) return fail(LV_EINVAL, "the skip model needs factored deltas");
+    if (!is_pow2(s) || s > k || k % s != 0 || k > kMaxK)
+      return fail(LV_EINVAL, "the skip model needs s a power of two dividing k, got s = %d, k = %d", s, k);
+    const int64_t r_pad = next_pow2(r_max);
+    // the widest operand of a P_s pass: (2k - 1 - 2s) r_pad columns
+    if ((int64_t)(2 * k - 1 - 2 * s) * r_pad > 128 || (int64_t)(2 * k - 1) * r_pad > 256)
+      return fail(LV_EINVAL, "skip model: (2k - 1 - 2s) * r_max (rounded up) must not exceed 128");
+  } else {
+    s = k;
+  }
+  lv_status st = check_shape(n, s, r_max, mode);
   if (st != LV_OK) return st;
   if (strategy == LV_GENERAL_HYBRID) {
     if (p < 1 || p > kMaxGeneralCols)
@@ -598,7 +709,7 @@ lv_status check_general(int64_t n, int k, int r_max, lv_mode mode, int64_t p, in
   } else if (strategy == LV_GENERAL_FACTORED) {
     if (p < 1 || p > kMaxGeneralColsF)
       return fail(LV_EINVAL, "p = %lld outside [1, %d] (factored deltas)", (long long)p, kMaxGeneralColsF);
-    if ((int64_t)k * next_pow2(r_max) > kMaxGeneralWidthF)
+    if ((int64_t)s * next_pow2(r_max) > kMaxGeneralWidthF)
       return fail(LV_EINVAL, "factored deltas need k * r_max (rounded up to a power of two) <= %d", kMaxGeneralWidthF);
   } else {
     return fail(LV_EINVAL, "unknown strategy %d", strategy);
@@ -610,22 +721,23 @@ lv_status check_general(int64_t n, int k, int r_max, lv_mode mode, int64_t p, in
 
 extern "C" {
 
-size_t lv_view_footprint_general(int64_t n, int k, int r_max, lv_mode mode, int64_t p, int strategy) {
-  if (check_general(n, k, r_max, mode, p, strategy) != LV_OK) return 0;
-  return make_layout(n, k, r_max, mode, LV_WITH_SUMS, (int)p, strategy == LV_GENERAL_FACTORED).total;
+size_t lv_view_footprint_general(int64_t n, int k, int r_max, lv_mode mode, int64_t p, int strategy, int s) {
+  if (check_general(n, k, r_max, mode, p, strategy, s) != LV_OK) return 0;
+  const int sp = s == 0 ? k : s;
+  return make_layout(n, sp, r_max, mode, LV_WITH_SUMS, (int)p, strategy == LV_GENERAL_FACTORED, k).total;
 }
 
 lv_status lv_view_create_general(const void* A, int64_t n, int64_t lda, int k, int r_max, lv_mode mode,
                                  const void* T0, int64_t ldt, const void* B, int64_t ldb, int64_t p, int strategy,
-                                 void* workspace, size_t ws_bytes, void* stream, lv_view** out) {
+                                 int s, void* workspace, size_t ws_bytes, void* stream, lv_view** out) {
   g_err[0] = 0;
   if (out) *out = nullptr;
-  lv_status st = check_general(n, k, r_max, mode, p, strategy);
+  lv_status st = check_general(n, k, r_max, mode, p, strategy, s);
   if (st != LV_OK) return st;
   if (!T0 || !B) return fail(LV_EINVAL, "T0 or B is NULL");
   if (ldt < p || ldb < p) return fail(LV_EINVAL, "ldt/ldb smaller than p");
-  return create_view(A, n, lda, k, r_max, mode, LV_WITH_SUMS, (int)p, strategy == LV_GENERAL_FACTORED, T0, ldt, B,
-                     ldb, workspace, ws_bytes, stream, out);
+  return create_view(A, n, lda, s == 0 ? k : s, r_max, mode, LV_WITH_SUMS, (int)p, strategy == LV_GENERAL_FACTORED,
+                     k, T0, ldt, B, ldb, workspace, ws_bytes, stream, out);
 }
 
 static lv_status check_update_args(const lv_view* v, const void* U, const void* V, int64_t r,
@@ -707,13 +819,22 @@ lv_status lv_view_read_sum(const lv_view* v, int index, void* out, int64_t ldo, 
 
 lv_status lv_view_read_general(const lv_view* v, int index, void* out, int64_t ldo, void* stream) {
   g_err[0] = 0;
-  const int j = power_level(v, index);
-  if (j < 0) return fail(LV_EINVAL, "T index %d is not stored", index);
+  if (!v) return fail(LV_EINVAL, "view is NULL");
   if (!v->L.general) return fail(LV_ESTATE, "the view is not a general-form view");
+  // T_1, T_2, T_4, ..., T_s, then (skip model) T_2s, T_3s, ..., T_k
+  const int j = power_level(v, index);
+  size_t off = 0;
+  if (j >= 0) {
+    off = v->L.T[j];
+  } else if (v->L.nsk > 0 && index > v->k && index <= v->L.kT && index % v->k == 0) {
+    off = v->L.Tsk + (size_t)(index / v->k - 2) * v->L.tstride;
+  } else {
+    return fail(LV_EINVAL, "T index %d is not stored", index);
+  }
   if (!out) return fail(LV_EINVAL, "out is NULL");
   if (ldo < v->L.p) return fail(LV_EINVAL, "ldo < p");
   const size_t es = v->L.elem;
-  return hip_check(hipMemcpy2DAsync(out, ldo * es, v->base + v->L.T[j], v->L.pp * es, v->L.p * es, v->n,
+  return hip_check(hipMemcpy2DAsync(out, ldo * es, v->base + off, v->L.pp * es, v->L.p * es, v->n,
                                     hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)),
                    "read T");
 }

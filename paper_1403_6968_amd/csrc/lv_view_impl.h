@@ -66,6 +66,13 @@ struct Layout {
   size_t Y[kMaxLevel + 1] = {};
   size_t Zt[kMaxLevel + 1] = {};
   size_t atbG = 0;
+  // skip-s model (factored deltas only): the powers and sums stop at
+  // P_s = P_{2^m}; T_{2s}, T_{3s}, ..., T_{kT} follow T_{js} = P_s T_{(j-1)s} + S_s B
+  // (nsk of them, uniform strides), with factor slabs of widths wsk(q)
+  int kT = 0, nsk = 0;
+  size_t Tsk = 0, Ysk = 0, Ztsk = 0, tstride = 0, ystride = 0, zstride = 0;
+  int wsk(int q) const { return wy[m] + q * 2 * (r_pad << m); }
+  int WYsk(int q) const { return (int)next_pow2(wsk(q)); }
   size_t T[kMaxLevel + 1] = {};
   size_t T0 = 0, B = 0, D[2] = {}, partXT = 0, partYT = 0, atbA = 0, atbB = 0;
   size_t gT[2] = {}, gTmp = 0, gB = 0;
@@ -91,10 +98,12 @@ constexpr int kMaxGeneralWidthF = 128;  // k * r_pad with factored deltas
 constexpr int kAtbRows = 64;          // rows per FP64 partial of V^T T and W^T B
 
 inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode, int flags = 0, int p = 0,
-                          bool factored = false) {
+                          bool factored = false, int kT = 0) {
   lv::Layout L;
   L.general = p > 0;
   L.gfac = L.general && factored;
+  L.kT = kT > 0 ? kT : k;
+  L.nsk = L.gfac ? L.kT / k - 1 : 0;
   L.sums = (flags & LV_WITH_SUMS) != 0 || L.general;
   L.elem = mode == LV_FP64 ? 8 : 4;
   L.n_pad = round_up(n, kPadOrder);
@@ -149,7 +158,7 @@ inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode, int flags =
     for (int j = 0; j <= L.m; ++j) { L.T[j] = off; off = align_up(off + gmat); }
     L.T0 = off; off = align_up(off + gmat);
     L.B = off; off = align_up(off + gmat);
-    const size_t rmax = (size_t)(L.m > 0 ? L.r_pad << (L.m - 1) : L.r_pad);
+    size_t rmax = (size_t)(L.m > 0 ? L.r_pad << (L.m - 1) : L.r_pad);
     if (L.gfac) {
       L.wy[0] = L.WY[0] = L.r_pad;
       int wmax = L.r_pad;
@@ -160,6 +169,17 @@ inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode, int flags =
       }
       for (int j = 1; j <= L.m; ++j) { L.Y[j] = off; off = align_up(off + (size_t)L.n_pad * L.WY[j] * L.elem); }
       for (int j = 0; j <= L.m; ++j) { L.Zt[j] = off; off = align_up(off + (size_t)L.WY[j] * L.pp * L.elem); }
+      if (L.nsk > 0) {
+        rmax = (size_t)(L.r_pad << L.m);
+        for (int q = 0; q < L.nsk; ++q) wmax = L.WYsk(q) > wmax ? L.WYsk(q) : wmax;   // widths of the P_s passes
+        const int wtop = L.WYsk(L.nsk);
+        L.tstride = align_up(gmat);
+        L.ystride = align_up((size_t)L.n_pad * wtop * L.elem);
+        L.zstride = align_up((size_t)wtop * L.pp * L.elem);
+        L.Tsk = off; off += L.nsk * L.tstride;
+        L.Ysk = off; off += L.nsk * L.ystride;
+        L.Ztsk = off; off += L.nsk * L.zstride;
+      }
       const size_t xmat = (size_t)L.n_pad * wmax * L.elem;
       L.partXT = off; off = align_up(off + (size_t)L.nct * xmat);
       L.partYT = off; off = align_up(off + (size_t)L.nrt_max * xmat);
@@ -237,6 +257,10 @@ struct lv_view {
   double* atbG() const { return reinterpret_cast<double*>(base + L.atbG); }
   template <typename T> T* Yf(int j) const { return reinterpret_cast<T*>(base + L.Y[j]); }
   template <typename T> T* Ztf(int j) const { return reinterpret_cast<T*>(base + L.Zt[j]); }
+  // skip-model T_{(q+1)s}, its Y and Z^T slabs (q = 1 .. nsk)
+  template <typename T> T* Tskp(int q) const { return reinterpret_cast<T*>(base + L.Tsk + (size_t)(q - 1) * L.tstride); }
+  template <typename T> T* Yskp(int q) const { return reinterpret_cast<T*>(base + L.Ysk + (size_t)(q - 1) * L.ystride); }
+  template <typename T> T* Ztskp(int q) const { return reinterpret_cast<T*>(base + L.Ztsk + (size_t)(q - 1) * L.zstride); }
   double* atbB() const { return reinterpret_cast<double*>(base + L.atbB); }
   double* gT(int i) const { return reinterpret_cast<double*>(base + L.gT[i]); }
   double* gTmp() const { return reinterpret_cast<double*>(base + L.gTmp); }

@@ -138,8 +138,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "lv_view_footprint_ex": (SZ, [I64, I32, I32, I32, I32]),
         "lv_view_create_ex": (I32, [P, I64, I64, I32, I32, I32, I32, P, SZ, P, c.POINTER(P)]),
         "lv_view_read_sum": (I32, [P, I32, P, I64, P]),
-        "lv_view_footprint_general": (SZ, [I64, I32, I32, I32, I64, I32]),
-        "lv_view_create_general": (I32, [P, I64, I64, I32, I32, I32, P, I64, P, I64, I64, I32, P, SZ, P,
+        "lv_view_footprint_general": (SZ, [I64, I32, I32, I32, I64, I32, I32]),
+        "lv_view_create_general": (I32, [P, I64, I64, I32, I32, I32, P, I64, P, I64, I64, I32, I32, P, SZ, P,
                                          c.POINTER(P)]),
         "lv_view_read_general": (I32, [P, I32, P, I64, P]),
         "lv_chain_footprint": (SZ, [I64, I32, I32, I32, I32, I32]),
@@ -224,13 +224,13 @@ def lv_view_create(A: torch.Tensor, k: int, r_max: int, mode: int, workspace: to
 
 
 def lv_view_footprint_general(n: int, k: int, r_max: int, mode: int, p: int,
-                              strategy: int = LV_GENERAL_HYBRID) -> int:
-    return int(load().lv_view_footprint_general(n, k, r_max, mode, p, strategy))
+                              strategy: int = LV_GENERAL_HYBRID, s: int = 0) -> int:
+    return int(load().lv_view_footprint_general(n, k, r_max, mode, p, strategy, s))
 
 
 def lv_view_create_general(A: torch.Tensor, k: int, r_max: int, mode: int, T0: torch.Tensor,
                            B: torch.Tensor, workspace: torch.Tensor, stream=None,
-                           strategy: int = LV_GENERAL_HYBRID) -> ctypes.c_void_p:
+                           strategy: int = LV_GENERAL_HYBRID, s: int = 0) -> ctypes.c_void_p:
     lib = load()
     dtype = _MODE_DTYPE[mode]
     a, lda = _mat(A, dtype, "A")
@@ -244,7 +244,7 @@ def lv_view_create_general(A: torch.Tensor, k: int, r_max: int, mode: int, T0: t
         raise ValueError("workspace must be a contiguous device tensor")
     h = ctypes.c_void_p()
     _check(lib.lv_view_create_general(a, A.shape[0], lda, k, r_max, mode, t, ldt, b, ldb, T0.shape[1], strategy,
-                                      workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+                                      s, workspace.data_ptr(), workspace.numel() * workspace.element_size(),
                                       _stream(stream, A.device), ctypes.byref(h)))
     return h
 
@@ -372,29 +372,32 @@ class View:
     """A view of A^k whose workspace is a torch device tensor."""
 
     def __init__(self, A: torch.Tensor, k: int, r_max: int = 1, mode: int | None = None,
-                 stream=None, sums: bool = False, general=None, strategy: int = LV_GENERAL_HYBRID):
+                 stream=None, sums: bool = False, general=None, strategy: int = LV_GENERAL_HYBRID,
+                 skip: int = 0):
         """general = (T0, B), both n x p: a view of the general form
         T_{i+1} = A T_i + B as well (implies sums), with hybrid or factored
-        deltas (strategy)."""
+        deltas (strategy).  skip = s > 0 (factored only): the powers and sums
+        stop at s and T_2s, T_3s, ..., T_k follow the skip-s model."""
         if mode is None:
             mode = LV_FP64 if A.dtype == torch.float64 else LV_FP32
         self.mode = mode
         self.dtype = _MODE_DTYPE[mode]
         self.n = A.shape[0]
         self.k = k
+        self.kp = skip if skip else k  # highest stored power
         self.device = A.device
         self.flags = LV_WITH_SUMS if sums or general is not None else 0
         self.p = 0
         if general is not None:
             T0, B = general
             self.p = T0.shape[1]
-            nbytes = lv_view_footprint_general(self.n, k, r_max, mode, self.p, strategy)
+            nbytes = lv_view_footprint_general(self.n, k, r_max, mode, self.p, strategy, skip)
             if nbytes == 0:
                 _check(load().lv_view_create_general(None, self.n, self.n, k, r_max, mode, None, self.p, None,
-                                                     self.p, self.p, strategy, None, 0, None,
+                                                     self.p, self.p, strategy, skip, None, 0, None,
                                                      ctypes.byref(ctypes.c_void_p())))
             self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
-            self.handle = lv_view_create_general(A, k, r_max, mode, T0, B, self.workspace, stream, strategy)
+            self.handle = lv_view_create_general(A, k, r_max, mode, T0, B, self.workspace, stream, strategy, skip)
             return
         nbytes = lv_view_footprint(self.n, k, r_max, mode, self.flags)
         if nbytes == 0:
@@ -411,14 +414,14 @@ class View:
         lv_view_update_batch(self.handle, U, V, self.dtype, stream)
 
     def read(self, power: int | None = None, stream=None) -> torch.Tensor:
-        power = self.k if power is None else power
+        power = self.kp if power is None else power
         out = torch.empty(self.n, self.n, dtype=self.dtype, device=self.device)
         lv_view_read(self.handle, power, out, self.dtype, stream)
         return out
 
     def read_sum(self, index: int | None = None, stream=None) -> torch.Tensor:
         """Stored sum S_index = I + A + ... + A^(index - 1) (views with sums)."""
-        index = self.k if index is None else index
+        index = self.kp if index is None else index
         out = torch.empty(self.n, self.n, dtype=self.dtype, device=self.device)
         _check(load().lv_view_read_sum(self.handle, index, out.data_ptr(), out.stride(0), _stream(stream, self.device)))
         return out
@@ -463,10 +466,15 @@ class View:
 
     def powers(self) -> list[int]:
         out, p = [], 1
-        while p <= self.k:
+        while p <= self.kp:
             out.append(p)
             p *= 2
         return out
+
+    def general_indices(self) -> list[int]:
+        """Indices i of the stored T_i (general-form views): 1, 2, 4, .., s,
+        then 2s, 3s, .., k under the skip-s model."""
+        return self.powers() + list(range(2 * self.kp, self.k + 1, self.kp))
 
     def close(self) -> None:
         if getattr(self, "handle", None) is not None:

@@ -167,23 +167,47 @@ def test_general_footprint_and_validation(lib):
     assert L.lv_view_footprint_general(1000, 16, 1, L.LV_FP32, 4097, F) == 0
     assert L.lv_view_footprint_general(1000, 16, 16, L.LV_FP32, 4, F) == 0            # k * r_pad > 128
     h = ctypes.c_void_p()
-    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1000, 4, 0x1000, 4, 65, 0, 0x1000, 1 << 30,
+    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1000, 4, 0x1000, 4, 65, 0, 0, 0x1000, 1 << 30,
                                     None, ctypes.byref(h))
     assert st == L.LV_EINVAL and "p = 65" in L.lv_last_error()
-    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, None, 4, 0x1000, 4, 4, 0, 0x1000, 1 << 30,
+    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, None, 4, 0x1000, 4, 4, 0, 0, 0x1000, 1 << 30,
                                     None, ctypes.byref(h))
     assert st == L.LV_EINVAL and "NULL" in L.lv_last_error()
-    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1000, 3, 0x1000, 4, 4, 0, 0x1000, 1 << 30,
+    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1000, 3, 0x1000, 4, 4, 0, 0, 0x1000, 1 << 30,
                                     None, ctypes.byref(h))
     assert st == L.LV_EINVAL and "ldt" in L.lv_last_error()
-    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1000, 4, 0x1000, 4, 4, 3, 0x1000, 1 << 30,
+    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1000, 4, 0x1000, 4, 4, 3, 0, 0x1000, 1 << 30,
                                     None, ctypes.byref(h))
     assert st == L.LV_EINVAL and "strategy" in L.lv_last_error()
     need = L.lv_view_footprint_general(64, 4, 1, L.LV_FP32, 4)
-    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1000, 4, 0x1000, 4, 4, 0, 0x1000, need - 1,
+    st = lib.lv_view_create_general(0x1000, 64, 64, 4, 1, L.LV_FP32, 0x1000, 4, 0x1000, 4, 4, 0, 0, 0x1000, need - 1,
                                     None, ctypes.byref(h))
     assert st == L.LV_ENOMEM and str(need) in L.lv_last_error()
     assert lib.lv_view_read_general(None, 1, 0x1000, 4, None) == L.LV_EINVAL
+
+
+def test_general_skip_footprint_and_validation(lib):
+    from paper_1403_6968_amd import linview as L
+    F = L.LV_GENERAL_FACTORED
+    exp16 = L.lv_view_footprint_general(1000, 16, 1, L.LV_FP32, 8, F)
+    assert L.lv_view_footprint_general(1000, 16, 1, L.LV_FP32, 8, F, 16) == exp16        # s = k: exponential
+    sk = L.lv_view_footprint_general(1000, 16, 1, L.LV_FP32, 8, F, 4)
+    exp4 = L.lv_view_footprint_general(1000, 4, 1, L.LV_FP32, 8, F)
+    # three more T (T_8, T_12, T_16) with their factor slabs, no powers beyond P_4
+    assert exp4 + 3 * 1024 * 128 * 4 < sk < exp16
+    assert L.lv_view_footprint_general(1000, 16, 1, L.LV_FP32, 8, F, 3) == 0             # s not a power of two
+    assert L.lv_view_footprint_general(1000, 12, 1, L.LV_FP32, 8, F, 8) == 0             # s does not divide k
+    assert L.lv_view_footprint_general(1000, 12, 1, L.LV_FP32, 8, F, 4) > 0
+    assert L.lv_view_footprint_general(1000, 16, 1, L.LV_FP32, 8, L.LV_GENERAL_HYBRID, 4) == 0
+    assert L.lv_view_footprint_general(1000, 64, 2, L.LV_FP32, 8, F, 2) == 0             # (2k - 1 - 2s) r > 128
+    assert L.lv_view_footprint_general(1000, 32, 2, L.LV_FP32, 8, F, 8) > 0              # 47 * 2 <= 128
+    h = ctypes.c_void_p()
+    st = lib.lv_view_create_general(0x1000, 64, 64, 16, 1, L.LV_FP32, 0x1000, 4, 0x1000, 4, 4, 0, 4, 0x1000,
+                                    1 << 30, None, ctypes.byref(h))
+    assert st == L.LV_EINVAL and "factored" in L.lv_last_error()
+    st = lib.lv_view_create_general(0x1000, 64, 64, 16, 1, L.LV_FP32, 0x1000, 4, 0x1000, 4, 4, F, 6, 0x1000,
+                                    1 << 30, None, ctypes.byref(h))
+    assert st == L.LV_EINVAL and "s = 6" in L.lv_last_error()
 
 
 def test_chain_footprint_and_validation(lib):

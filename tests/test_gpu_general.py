@@ -341,3 +341,61 @@ def test_general_tiny_order(strategy):
     got = _ts(view)
     assert max(O.maxrel(got[i], Tr[i]) for i in Tr) < 1e-12
     view.close()
+
+
+# ---- skip-s model with factored deltas (Table 1, App. B); updates of rank
+# below r_max exercise the factor widths of the update's own rank
+
+
+@pytest.mark.parametrize("n,k,s,r_max,r_upd,p,dtype", [
+    (300, 16, 4, 2, 2, 3, "f64"), (1000, 16, 4, 1, 1, 1, "f32"), (600, 8, 2, 4, 2, 40, "f32"),
+    (257, 8, 1, 2, 1, 5, "f32"), (520, 16, 8, 2, 1, 130, "f64"), (130, 4, 2, 1, 1, 2, "f32"),
+    (400, 8, 8, 4, 1, 6, "f32"), (333, 16, 16, 8, 3, 9, "f64")])
+def test_general_skip_tracks_oracle(n, k, s, r_max, r_upd, p, dtype):
+    lv = _lv()
+    import torch
+    td, nd = (torch.float64, np.float64) if dtype == "f64" else (torch.float32, np.float32)
+    mode = lv.LV_FP64 if dtype == "f64" else lv.LV_FP32
+    tol, dbase = (1e-10, 1e-7) if dtype == "f64" else (1e-4, 1e-2)
+    u = 2.0 ** -53 if dtype == "f64" else 2.0 ** -24
+    T = 6
+    A = _rounded(synth.gaussian_matrix(n, seed=75 + n, config=3), nd)
+    T0, B = (_rounded(x, nd) for x in synth.general_operands(n, p, seed=75 + n, config=3))
+    Us, Vs = (_rounded(x, nd) for x in synth.update_factors(n, r_upd, T, seed=75 + n, config=3))
+    view = lv.View(dev(A, td), k, r_max=r_max, mode=mode, general=(dev(T0, td), dev(B, td)),
+                   strategy=lv.LV_GENERAL_FACTORED, skip=s)
+    plain = lv.View(dev(A, td), s, r_max=r_max, mode=mode, sums=True)
+    idx = O.skip_indices(k, s)
+    assert view.general_indices() == idx
+    P, S, Tr = O.reeval(A, s), O.reeval_sums(A, s), O.reeval_general_skip(A, T0, B, k, s)
+    T_ref0 = Tr
+    T_got0 = {i: host(view.read_general(i)) for i in idx}
+    create_err = max(O.maxrel(T_got0[i], Tr[i]) for i in idx)
+    assert create_err < (1e-13 if dtype == "f64" else 1e-6), create_err
+    for t in range(T):
+        view.update(dev(Us[t], td), dev(Vs[t], td))
+        plain.update(dev(Us[t], td), dev(Vs[t], td))
+        P, S, Tr = O.incr_update_general_factored_skip(P, S, Tr, T0, B, Us[t], Vs[t], s)
+    got = {i: host(view.read_general(i)) for i in idx}
+    worst = max(O.maxrel(got[i], Tr[i]) for i in idx)
+    msg = []
+    for i in idx:
+        dr = O.deltarel(got[i], T_got0[i], Tr[i], T_ref0[i])
+        dtol = dbase + 4 * np.sqrt(T) * u * np.abs(Tr[i]).max() / np.abs(Tr[i] - T_ref0[i]).max()
+        msg.append(f"T{i}: {dr:.1e}(<{dtol:.1e})")
+        assert dr < dtol, f"T_{i} deltarel {dr:.3e} >= {dtol:.3e}"
+    note(f"general skip n={n} k={k} s={s} r={r_upd}/{r_max} p={p} {dtype}: create {create_err:.1e}, after {T} "
+         f"updates maxrel {worst:.2e}; " + " ".join(msg))
+    assert worst < tol
+    # the stored powers and sums (up to P_s) are those of a plain view with sums
+    pw, pp = read_all(view), read_all(plain)
+    assert sorted(pw) == sorted(pp)
+    for i in pw:
+        np.testing.assert_array_equal(pw[i], pp[i])
+    for i in view.powers():
+        np.testing.assert_array_equal(host(view.read_sum(i)), host(plain.read_sum(i)))
+    # the skip model's indices are the only T stored
+    with pytest.raises(lv.LinviewError):
+        view.read_general(3 if s != 1 else k + 1)
+    view.close()
+    plain.close()

@@ -273,3 +273,98 @@ def test_general_lin_pins_catch_planted_mistakes(kind):
 
 def test_general_lin_unmutated_copy_passes():
     assert all(_lin_exact(_lin_mutant("none"), 4, 2, 6, 1, s) for s in range(85, 88))
+
+
+# ---- skip-s model (Table 1, App. B): exponential up to T_s, then steps of s
+
+
+def _skip_state(A, T0, B, k, s):
+    return O.reeval(A, s), O.reeval_sums(A, s), O.reeval_general_skip(A, T0, B, k, s)
+
+
+@pytest.mark.parametrize("k,s", [(8, 2), (8, 1), (16, 4), (4, 4), (12, 4)])
+def test_reeval_general_skip_is_the_iteration(k, s):
+    A, T0, B = _case(4, 2, 70 + k + s)
+    T = O.reeval_general_skip(A, T0, B, k, s)
+    assert sorted(T) == O.skip_indices(k, s)
+    ref = _iterate(_frac(A), _frac(T0), _frac(B), k)
+    for i in T:
+        assert (_frac(T[i]) == ref[i]).all(), i
+
+
+def test_skip_indices_and_validation():
+    assert O.skip_indices(16, 4) == [1, 2, 4, 8, 12, 16]
+    assert O.skip_indices(8, 1) == [1, 2, 3, 4, 5, 6, 7, 8]
+    assert O.skip_indices(8, 8) == [1, 2, 4, 8]
+    for k, s in [(8, 3), (8, 16), (6, 4)]:
+        with pytest.raises(ValueError):
+            O.skip_indices(k, s)
+
+
+def _skip_exact(fn, n, p, k, s, r, seed):
+    A, T0, B = _case(n, p, seed)
+    U = synth.integer_matrix((n, r), -1, 1, seed=seed, tag=8)
+    V = synth.integer_matrix((n, r), -1, 1, seed=seed, tag=9)
+    P, S, T = _skip_state(A, T0, B, k, s)
+    Tn = fn(P, S, T, T0, B, U, V, s)
+    ref = _iterate(_frac(A + U @ V.T), _frac(T0), _frac(B), k)
+    return all((_frac(Tn[i]) == ref[i]).all() for i in Tn)
+
+
+def _skip_update(P, S, T, T0, B, U, V, s):
+    return O.incr_update_general_factored_skip(P, S, T, T0, B, U, V, s)[2]
+
+
+@pytest.mark.parametrize("k,s,r,seed", [(8, 2, 1, 0), (8, 1, 2, 1), (16, 4, 1, 2), (12, 4, 2, 3), (8, 4, 1, 4)])
+def test_skip_factored_exact(k, s, r, seed):
+    assert _skip_exact(_skip_update, 4, 2, k, s, r, 80 + seed)
+
+
+def test_skip_factored_widths_and_many_updates():
+    n, p, k, s, r = 30, 3, 16, 4, 2
+    A = synth.gaussian_matrix(n, seed=34)
+    g = synth.rng(34, 0, 5)
+    T0, B = g.standard_normal((n, p)), g.standard_normal((n, p))
+    Us, Vs = synth.update_factors(n, r, 5, seed=34)
+    P, S, T = _skip_state(A, T0, B, k, s)
+    Y, Z = O.incr_general_factors_skip(P, S, T, T0, B, Us[0], Vs[0], s)
+    c = {1: r}
+    for i in O.levels(s)[1:]:
+        c[i] = (i // 2) * r + c[i // 2] + max(i // 2 - 1, 1) * r      # Q_1: a zero block of width r
+    for i in range(2 * s, k + 1, s):
+        c[i] = c[i - s] + s * r + max(s - 1, 1) * r
+    for i in T:
+        assert Y[i].shape == (n, c[i]) and Z[i].shape == (p, c[i]), i
+    for t in range(5):
+        P, S, T = O.incr_update_general_factored_skip(P, S, T, T0, B, Us[t], Vs[t], s)
+    R = O.reeval_general_skip(A + np.einsum("tir,tjr->ij", Us, Vs), T0, B, k, s)
+    assert max(O.maxrel(T[i], R[i]) for i in R) < 1e-12
+
+
+def _skip_mutant(kind):
+    def fn(P, S, T, T0, B, U, V, s):
+        Y, Z = O.incr_general_factors(P, S, {i: T[i] for i in O.levels(s)}, T0, B, U, V)
+        dQ, dW, dU, dV = O.incr_sums_factors(P, S, U, V)
+        n, r = U.shape
+        Qs, Ws = (dQ[s], dW[s]) if s > 1 else (np.zeros((n, r)), np.zeros((n, r)))
+        for i in range(2 * s, max(T) + 1, s):
+            h = i - s
+            Ps = P[s] + dU[s] @ dV[s].T if kind == "new_power" else P[s]
+            cross = 0 if kind == "drop_cross" else dU[s] @ (dV[s].T @ Y[h])
+            Th = T[h] + Y[h] @ Z[h].T if kind == "new_t" else T[h]
+            Y[i] = np.hstack([dU[s], Ps @ Y[h] + cross, Qs])
+            Wb = np.zeros_like(Ws) if kind == "drop_sums" else Ws
+            Z[i] = np.hstack([Th.T @ dV[s], Z[h], B.T @ Wb])
+        return {i: T[i] + Y[i] @ Z[i].T for i in T}
+    return fn
+
+
+@pytest.mark.parametrize("kind", ["new_power", "drop_cross", "new_t", "drop_sums"])
+def test_skip_pins_catch_planted_mistakes(kind):
+    cases = [(8, 2, 1, 90), (16, 4, 1, 91), (8, 2, 2, 92)]
+    assert not all(_skip_exact(_skip_mutant(kind), 4, 2, k, s, r, seed) for k, s, r, seed in cases), kind
+
+
+def test_skip_unmutated_copy_passes():
+    cases = [(8, 2, 1, 90), (16, 4, 1, 91), (8, 2, 2, 92)]
+    assert all(_skip_exact(_skip_mutant("none"), 4, 2, k, s, r, seed) for k, s, r, seed in cases)
