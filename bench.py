@@ -89,8 +89,8 @@ def bench_rank4(torch, lv, synth, dev, steps=40):
 def bench_sums(torch, lv, synth, dev, steps=200):
     """A^16 view with its sums of powers S_1..S_16 (LV_WITH_SUMS), n = 8192,
     FP32, rank-1 updates: updates/s and algorithmic HBM bytes per update
-    (powers: one read and write of each stored power; sums: P_j and S_j read
-    once more and S_j read and written for j = 1..3, S_16 read and written)."""
+    (one read and one write of each stored power and of S_2 .. S_16: P_j Q_j
+    rides on the powers' pass, S_j^T V_j on the update pass of S_j)."""
     n, k = 8192, 16
     A = torch.from_numpy(synth.gaussian_matrix(n, seed=0, config=2).astype(np.float32)).to(dev)
     U, V = synth.update_factors(n, 1, steps + 5, seed=0, config=2)
@@ -108,7 +108,7 @@ def bench_sums(torch, lv, synth, dev, steps=200):
     ms = a.elapsed_time(b) / steps
     n_pad = view.stats()["n_pad"]
     view.close()
-    alg = (40 + 56) * n_pad * n_pad
+    alg = (40 + 32) * n_pad * n_pad
     return {"workload": "A^16 and sums of powers S_1..S_16, n=8192, FP32, rank-1 updates",
             "ms_per_update": ms, "updates_per_s": 1000.0 / ms, "alg_bytes_per_update": alg,
             "alg_GBps": alg / (ms * 1e-3) / 1e9}
@@ -193,6 +193,22 @@ def bench_general(torch, lv, synth, dev, steps=100, ps=(1, 16, 64)):
         del Ar
         out[f"p{p}_factored"] = {"factored_exp_ms_per_update": ms, "updates_per_s": 1000.0 / ms,
                                  "reeval_lin_torch_ms": lin_ms, "reeval_lin_over_factored": lin_ms / ms}
+    # skip-4 model with factored deltas (Table 1, App. B): powers and sums up
+    # to P_4, S_4; T_1, T_2, T_4, then T_8, T_12, T_16 by steps of 4
+    for p in (16, 1000):
+        T0, B = (torch.from_numpy(x.astype(np.float32)).to(dev) for x in synth.general_operands(n, p, seed=0))
+        view = lv.View(A, k, general=(T0, B), strategy=lv.LV_GENERAL_FACTORED, skip=4)
+        view.update_batch(Ud[:5], Vd[:5])
+        torch.cuda.synchronize()
+        a.record()
+        view.update_batch(Ud[5:5 + steps // 2], Vd[5:5 + steps // 2])
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / (steps // 2)
+        view.close()
+        del view
+        torch.cuda.empty_cache()
+        out[f"p{p}_factored_skip4"] = {"factored_skip4_ms_per_update": ms, "updates_per_s": 1000.0 / ms}
     del A
     return out
 

@@ -224,17 +224,29 @@ lv_status timed(lv_view* v, int kind, hipStream_t s, const char* what, F&& launc
 }
 
 // Sums of powers, level j after the powers' level step (the powers' partials
-// of level j are consumed, so a pass may write its unused X there).  The
-// read-only passes run on the float matrix cores from rank 16 up, else on
-// the fused vector kernel without its update:
+// of level j are consumed, so a pass may write its unused X there):
 // Y_s = S_j^T V_j with the OLD S_j, G_s = Q_j^T V_j, S_j += Q_j W_j^T, and the
-// sums tail (Q_{j+1}, W_{j+1}).  Level 0 has Q_0 = 0 and S_0 = I: only the
-// tail runs.
+// sums tail (Q_{j+1}, W_{j+1}).  Below the matrix-core ranks Y_s and the
+// update share one pass over S_j (launch_sums_fused); from float rank 16 up
+// Y_s is a read-only pass on the matrix cores, then the update pass.  Level
+// 0 has Q_0 = 0 and S_0 = I: only the tail runs.  (X_s = P_j Q_j came from
+// the powers' pass or from its own read-only pass before it.)
 template <typename T>
 lv_status sums_level(lv_view* v, int j, int R, const T* sU, const T* sV, hipStream_t s) {
   const Layout& L = v->L;
   lv_status st = LV_OK;
-  if (j > 0) {
+  if (j > 0 && sums_fused(R, (int)sizeof(T))) {
+    // one pass over S_j: Y = S_j^T V_j (old S_j), S_j += Q_j W_j^T
+    st = timed(v, 0, s, "sums: pass", [&] {
+      return launch_sums_fused<T>(R, v->S<T>(j), L.ldp, L.n_pad, v->tile_rows[j], v->slabQ<T>(), v->slabW<T>(), sV,
+                                  L.W, v->partYs<T>(j), s);
+    });
+    if (st == LV_OK)
+      st = timed(v, 0, s, "sums: gram", [&] {
+        return launch_gram_cols<T>(R, sV + (L.W - R), v->slabQ<T>(), L.W, L.n_pad, v->partGs(j), s);
+      });
+    if (st != LV_OK) return st;
+  } else if (j > 0) {
     st = timed(v, 0, s, "sums: S^T V", [&] {
       if (skinny_on_mfma(R, (int)sizeof(T)))
         return launch_skinny_f32(R, reinterpret_cast<const float*>(v->S<T>(j)), L.ldp, L.n_pad, v->tile_rows[j],
@@ -467,7 +479,8 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
       st = L.gfac ? gfac_pass<T>(v, j, r_pad, sU, s) : general_pass<T>(v, j, s);
       if (st != LV_OK) return st;
     }
-    if (L.sums && j > 0) {
+    const bool q_in_pass = L.sums && j > 0 && powers_pass_with_q(R, (int)sizeof(T), v->shadowed());
+    if (L.sums && j > 0 && !q_in_pass) {
       // sums: X_s = P_j Q_j with the OLD P_j, before this level's update
       st = timed(v, 0, s, "sums: P Q", [&] {
         if (skinny_on_mfma(R, (int)sizeof(T)))
@@ -512,6 +525,9 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
       }
     }
     st = timed(v, 0, s, "level pass", [&] {
+      if (q_in_pass)
+        return launch_level_fused_q<T>(R, v->P<T>(j), L.ldp, L.n_pad, v->tile_rows[j], sU, sV, v->slabQ<T>(), L.W,
+                                       v->partX<T>(j), v->partY<T>(j), v->partG(j), v->partXs<T>(j), s);
       return launch_level_fused<T>(R, v->P<T>(j), L.ldp, L.n_pad, v->tile_rows[j], sU, sV, L.W, v->partX<T>(j),
                                    v->partY<T>(j), v->partG(j), s);
     });

@@ -48,21 +48,32 @@ namespace {
 // skinny products of 16 factor columns at a time (partials written with row
 // stride pR at the chunk's column offset), the rank update and the Gram done
 // by k_level_update and k_gram.
-template <typename T, int R, int RB, bool UPD>
+//
+// Two variants serve views that keep the sums of powers as well (one pass
+// over a stored matrix instead of two):
+//   XE = R   X is formed for XE more columns, taken from Ux (same stride W):
+//            X = P [U_j, Q_j], the second block's partials to partX2 (row
+//            stride XE); the powers' pass thus also yields P_j Q_j.
+//   SP       the sums pass: no X; Y = S^T Vy with the old S and the rank
+//            update S += Uj Vj^T (Uj = Q_j, Vj = W_j), no Gram.
+template <typename T, int R, int RB, bool UPD, int XE = 0, bool SP = false>
 __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp, const int n_pad,
                                            const int tile_rows, const T* __restrict__ Uj,
                                            const T* __restrict__ Vj, const int W, T* __restrict__ partX,
                                            T* __restrict__ partY, double* __restrict__ partG, const int pR,
-                                           const int ct, const int rt) {
+                                           const int ct, const int rt, const T* __restrict__ Ux = nullptr,
+                                           T* __restrict__ partX2 = nullptr, const T* __restrict__ Vy = nullptr) {
   constexpr int EPL = 16 / (int)sizeof(T);
   constexpr int TC = 64 * EPL;
   constexpr int NQ = 64 / RB;           // column slices in Phase B
   constexpr int QW = TC / NQ;           // columns per slice
   constexpr int LDSW = TC + EPL;        // padded LDS row (elements)
   constexpr int UPAD = 4;               // LDS padding between U slices (elements)
+  constexpr int XR = R + XE;            // columns of X
+  static_assert(!SP || (UPD && XE == 0), "the sums pass updates and forms no X");
 
   __shared__ __align__(16) T tileP[4 * RB * LDSW];
-  __shared__ __align__(16) T utile[TC * R + NQ * UPAD];
+  __shared__ __align__(16) T utile[SP ? 1 : TC * XR + NQ * UPAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -74,11 +85,15 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
   const int lc = col0 + lane * EPL;
   T* myP = tileP + wave * RB * LDSW;
 
-  // U_j rows of the tile's columns, slice-padded: (col, c) -> col*R + (col/QW)*UPAD + c.
-  for (int idx = tid; idx < TC * R; idx += 256) {
-    const int col = idx / R, c = idx % R;
-    utile[col * R + (col / QW) * UPAD + c] = Uj[(int64_t)(col0 + col) * W + c];
+  // X operand rows of the tile's columns, slice-padded: (col, c) -> col*XR + (col/QW)*UPAD + c.
+  if constexpr (!SP) {
+    for (int idx = tid; idx < TC * XR; idx += 256) {
+      const int col = idx / XR, c = idx % XR;
+      const int64_t g = (int64_t)(col0 + col) * W;
+      utile[col * XR + (col / QW) * UPAD + c] = (XE == 0 || c < R) ? Uj[g + c] : Ux[g + c - R];
+    }
   }
+  const T* __restrict__ Yop = SP ? Vy : Vj;
 
   T vcol[EPL][UPD ? R : 1];
   if constexpr (UPD) {
@@ -98,7 +113,7 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
 
   const int rho = lane % RB;
   const int qs = lane / RB;
-  const T* urow0 = utile + qs * (QW * R + UPAD);
+  const T* urow0 = utile + qs * (QW * XR + UPAD);
 
   V16<T> p[RB];
   if (wave < nblocks) {
@@ -113,7 +128,7 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
 #pragma unroll
     for (int t = 0; t < RB; ++t) {
       const int64_t i = r0 + t;
-      const T* vrow = Vj + i * W;
+      const T* vrow = Yop + i * W;
       T vi[R];
 #pragma unroll
       for (int c = 0; c < R; ++c) vi[c] = vrow[c];
@@ -121,7 +136,7 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
       for (int q = 0; q < EPL; ++q)
 #pragma unroll
         for (int c = 0; c < R; ++c) yacc[q][c] = fma(p[t].v[q], vi[c], yacc[q][c]);
-      st16(myP + t * LDSW + lane * EPL, p[t]);
+      if constexpr (!SP) st16(myP + t * LDSW + lane * EPL, p[t]);
       if constexpr (UPD) {
         const T* urow = Uj + i * W;
         T ui[R];
@@ -142,31 +157,36 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
 #pragma unroll
       for (int t = 0; t < RB; ++t) p[t] = ld16_nt(P + (rn + t) * ldp + lc);
     }
+    if constexpr (SP) continue;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-    T x[R];
+    T x[XR];
 #pragma unroll
-    for (int c = 0; c < R; ++c) x[c] = T(0);
+    for (int c = 0; c < XR; ++c) x[c] = T(0);
     const T* prow = myP + rho * LDSW + qs * QW;
 #pragma unroll 4
     for (int l = 0; l < QW; l += EPL) {
       const V16<T> pv = ld16(prow + l);
 #pragma unroll
       for (int e = 0; e < EPL; ++e) {
-        const T* ur = urow0 + (l + e) * R;
+        const T* ur = urow0 + (l + e) * XR;
 #pragma unroll
-        for (int c = 0; c < R; ++c) x[c] = fma(pv.v[e], ur[c], x[c]);
+        for (int c = 0; c < XR; ++c) x[c] = fma(pv.v[e], ur[c], x[c]);
       }
     }
 #pragma unroll
     for (int off = RB; off < 64; off <<= 1)
 #pragma unroll
-      for (int c = 0; c < R; ++c) x[c] += __shfl_xor(x[c], off);
+      for (int c = 0; c < XR; ++c) x[c] += __shfl_xor(x[c], off);
     if (qs == 0) {
 #pragma unroll
       for (int c = 0; c < R; ++c) partX[((int64_t)ct * n_pad + r0 + rho) * pR + c] = x[c];
+      if constexpr (XE > 0) {
+#pragma unroll
+        for (int c = 0; c < XE; ++c) partX2[((int64_t)ct * n_pad + r0 + rho) * XE + c] = x[R + c];
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -198,7 +218,7 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
   // Partial Gram V_j^T U_j over this tile's rows (double accumulation):
   // thread (pair, group) sums every G-th row of the tile for one (a, b), the
   // groups are then added in a fixed order.
-  if (UPD && ct == 0) {
+  if (UPD && !SP && ct == 0) {
     constexpr int NP = R * R;
     constexpr int G = NP >= 256 ? 1 : 256 / NP;
     double* gbuf = reinterpret_cast<double*>(tileP);
@@ -231,6 +251,20 @@ template <typename T, int R, int RB, bool UPD>
 __global__ void __launch_bounds__(256) k_level_fused(const FusedDesc<T> d) {
   fused_body<T, R, RB, UPD>(d.P, d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.partX, d.partY, d.partG, d.pR,
                             blockIdx.x, blockIdx.y);
+}
+
+// The powers' pass of a view with sums: X also for Q_j (XE = R columns).
+template <typename T, int R, int RB>
+__global__ void __launch_bounds__(256) k_level_fused_q(const FusedDesc<T> d) {
+  fused_body<T, R, RB, true, R, false>(d.P, d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.partX, d.partY, d.partG,
+                                       d.pR, blockIdx.x, blockIdx.y, d.Ux, d.partX2, nullptr);
+}
+
+// The sums pass: Y = S^T Vy (old S), S += Q_j W_j^T.
+template <typename T, int R, int RB>
+__global__ void __launch_bounds__(256) k_sums_fused(const FusedDesc<T> d) {
+  fused_body<T, R, RB, true, 0, true>(d.P, d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, nullptr, d.partY, nullptr,
+                                      d.pR, blockIdx.x, blockIdx.y, nullptr, nullptr, d.Vy);
 }
 
 template <typename T, int R, int RB, bool UPD>
@@ -289,6 +323,45 @@ hipError_t launch_level_fused(int R, T* P, int64_t ldp, int64_t n_pad, int tile_
 }
 
 template <typename T>
+hipError_t launch_level_fused_q(int R, T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* slabU,
+                                const T* slabV, const T* slabQ, int W, T* partX, T* partY, double* partG, T* partXq,
+                                hipStream_t s) {
+  // the row blocks (RB) of the plain pass for the same R: the same summation
+  // order, so X for U_j, Y, the Gram and the update are bit-identical to it
+  const int nct = (int)(n_pad / tile_cols<T>());
+  FusedDesc<T> d{P, ldp, (int)n_pad, tile_rows, slabU, slabV + (W - R), W, partX, partY, partG, R, nct, 0};
+  d.Ux = slabQ;
+  d.partX2 = partXq;
+  const dim3 grid((unsigned)nct, (unsigned)((n_pad + tile_rows - 1) / tile_rows));
+  switch (R) {
+    case 1: hipLaunchKernelGGL((k_level_fused_q<T, 1, 16>), grid, dim3(256), 0, s, d); break;
+    case 2: hipLaunchKernelGGL((k_level_fused_q<T, 2, 16>), grid, dim3(256), 0, s, d); break;
+    case 4: hipLaunchKernelGGL((k_level_fused_q<T, 4, 16>), grid, dim3(256), 0, s, d); break;
+    case 8: hipLaunchKernelGGL((k_level_fused_q<T, 8, 8>), grid, dim3(256), 0, s, d); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sums_fused(int R, T* S, int64_t ldp, int64_t n_pad, int tile_rows, const T* slabQ,
+                             const T* slabW, const T* slabV, int W, T* partY, hipStream_t s) {
+  const int nct = (int)(n_pad / tile_cols<T>());
+  FusedDesc<T> d{S, ldp, (int)n_pad, tile_rows, slabQ, slabW + (W - R), W, nullptr, partY, nullptr, R, nct, 0};
+  d.Vy = slabV + (W - R);
+  const dim3 grid((unsigned)nct, (unsigned)((n_pad + tile_rows - 1) / tile_rows));
+  switch (R) {
+    case 1: hipLaunchKernelGGL((k_sums_fused<T, 1, 8>), grid, dim3(256), 0, s, d); break;
+    case 2: hipLaunchKernelGGL((k_sums_fused<T, 2, 8>), grid, dim3(256), 0, s, d); break;
+    case 4: hipLaunchKernelGGL((k_sums_fused<T, 4, 8>), grid, dim3(256), 0, s, d); break;
+    case 8: hipLaunchKernelGGL((k_sums_fused<T, 8, 8>), grid, dim3(256), 0, s, d); break;
+    case 16: hipLaunchKernelGGL((k_sums_fused<T, 16, 8>), grid, dim3(256), 0, s, d); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_fused_multi(int R, bool chunk, const FusedDesc<T>* ds, int nd, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   if (chunk) {
@@ -339,6 +412,14 @@ template hipError_t launch_level_fused<float>(int, float*, int64_t, int64_t, int
                                               float*, float*, double*, hipStream_t);
 template hipError_t launch_level_fused<double>(int, double*, int64_t, int64_t, int, const double*, const double*,
                                                int, double*, double*, double*, hipStream_t);
+template hipError_t launch_level_fused_q<float>(int, float*, int64_t, int64_t, int, const float*, const float*,
+                                                const float*, int, float*, float*, double*, float*, hipStream_t);
+template hipError_t launch_level_fused_q<double>(int, double*, int64_t, int64_t, int, const double*, const double*,
+                                                 const double*, int, double*, double*, double*, double*, hipStream_t);
+template hipError_t launch_sums_fused<float>(int, float*, int64_t, int64_t, int, const float*, const float*,
+                                             const float*, int, float*, hipStream_t);
+template hipError_t launch_sums_fused<double>(int, double*, int64_t, int64_t, int, const double*, const double*,
+                                              const double*, int, double*, hipStream_t);
 template hipError_t launch_fused_multi<float>(int, bool, const FusedDesc<float>*, int, int, hipStream_t);
 template hipError_t launch_fused_multi<double>(int, bool, const FusedDesc<double>*, int, int, hipStream_t);
 

@@ -41,6 +41,9 @@ template <typename T> struct FusedDesc {
   const T* Uj; const T* Vj; int W;      // U_j = Uj[i*W + c], V_j = Vj[i*W + c]
   T* partX; T* partY; double* partG; int pR;
   int nct; int block_begin;             // blocks: nct x ceil(n_pad / tile_rows)
+  const T* Ux = nullptr;                // extra X operand (powers' pass of a view with sums)
+  T* partX2 = nullptr;                  //   and its partials
+  const T* Vy = nullptr;                // Y operand of the sums pass
 };
 template <typename T> struct GramDesc {
   const T* Uj; const T* Vj; int W; int n_pad; int tile_rows; double* partG;
@@ -97,6 +100,14 @@ inline bool skinny_on_mfma(int R, int elem) { return elem == 4 && R >= kMfmaSkin
 // Whether the fused pass of rank R forms the Gram partials itself (one per
 // row tile); otherwise the stand-alone Gram kernel and its sum provide G.
 inline bool gram_in_pass(int R, int elem) { return R <= kMaxFusedRank && !skinny_on_mfma(R, elem); }
+// Views with sums: the powers' fused pass also forms P_j Q_j (its X for 2R
+// columns) where the level runs the fused vector pass and 2R <= 16.
+inline bool powers_pass_with_q(int R, int elem, bool shadowed) {
+  return !shadowed && 2 * R <= kMaxFusedRank && !skinny_on_mfma(R, elem);
+}
+// The sums pass (Y = S^T V_j and the rank update of S in one pass) on the
+// vector kernel, below the ranks that run on the matrix cores.
+inline bool sums_fused(int R, int elem) { return R <= kMaxFusedRank && !skinny_on_mfma(R, elem); }
 // Work-groups of a tail launch / Gram pairs per work-group for rank R.
 // Level ranks from which the tail works on 64-row x 32-column blocks.
 constexpr int kSlicedTailRank = 64;
@@ -187,6 +198,19 @@ hipError_t launch_to_bf16(const float* P, uint16_t* S, int64_t count, hipStream_
 template <typename T>
 hipError_t launch_level_readonly(int R, const T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* Uop,
                                  const T* Vop, int W, T* partX, T* partY, hipStream_t s);
+// The powers' fused pass of a view with sums (R <= 8): as launch_level_fused
+// for level rank R, and X = P Q_j (Q_j = columns [0, R) of slabQ) in the same
+// read of P, its partials to partXq ([nct][n_pad][R]).
+template <typename T>
+hipError_t launch_level_fused_q(int R, T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* slabU,
+                                const T* slabV, const T* slabQ, int W, T* partX, T* partY, double* partG, T* partXq,
+                                hipStream_t s);
+// The sums pass (R <= 16): partial Y = S^T V_j with the old S (V_j = columns
+// [W - R, W) of slabV; partials [nrt][n_pad][R]) and S += Q_j W_j^T, one read
+// and one write of S.
+template <typename T>
+hipError_t launch_sums_fused(int R, T* S, int64_t ldp, int64_t n_pad, int tile_rows, const T* slabQ,
+                             const T* slabW, const T* slabV, int W, T* partY, hipStream_t s);
 // G = Vop^T Uop (R x R, double) into partG[0 .. R*R), operands given by
 // their first columns (row stride W).
 template <typename T>
