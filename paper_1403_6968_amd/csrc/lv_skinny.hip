@@ -379,21 +379,22 @@ __global__ void __launch_bounds__(256) k_skinny_f32_multi(const SkinnyDesc* __re
 // X-only float pass on the matrix cores: partial X = P U for R <= 16 NB
 // factor columns (zero-padded), P streamed from HBM straight into the MFMA
 // operand registers: no LDS staging of P, no exchange between waves.
-// Block: 4 waves over kXRows rows x 256 columns of P; wave w takes the
-// 16-row strips w, w + 4, ..., each read in two halves of 128 columns, the
-// next half requested before the current one is multiplied.
+// Block: kXWaves waves over kXRows rows x 256 columns of P; wave w takes
+// the 16-row strips w, w + kXWaves, ..., each read in two halves of 128
+// columns, the next half requested before the current one is multiplied.
 // v_mfma_f32_16x16x4f32: A (16 x 4): lane l holds A[l % 16][l / 16];
 // B (4 x 16): lane l holds B[l / 16][l % 16]; C: element v of lane l is
-// C[4 (l / 16) + v][l % 16].  Lane l reads 8 consecutive floats of strip
-// row l % 16 at column 8 (l / 16) of a 32-column group (a 128-byte segment
-// per row); step e of the group's 8 products takes its e-th float, i.e.
-// the summation index 8 (l / 16) + e of the group, and the B operand the
-// matching U row.
-constexpr int kXRows = 256;
-constexpr int XUS = 2;   // LDS row padding of the U tile (floats)
+// C[4 (l / 16) + v][l % 16].  In a 32-column group, lane l reads 4 floats
+// of strip row l % 16 at column 4 (l / 16) and 4 at column 16 + 4 (l / 16)
+// (each load a contiguous 64-byte segment per row); step e of the group's
+// 8 products takes the e-th of these floats as its summation index, and the
+// B operand the matching U row.
+constexpr int kXWaves = 8;
+constexpr int kXRows = 512;
+constexpr int XUS = 4;   // LDS row padding of the U tile (floats): rows 4 apart in distinct banks
 
 template <int NB>
-__global__ void __launch_bounds__(256) k_xprod_f32(const SkinnyDesc d) {
+__global__ void __launch_bounds__(64 * kXWaves) k_xprod_f32(const SkinnyDesc d) {
   constexpr int RP = 16 * NB;
   __shared__ float sU[TCB][RP + XUS];
   const int tid = threadIdx.x;
@@ -406,27 +407,27 @@ __global__ void __launch_bounds__(256) k_xprod_f32(const SkinnyDesc d) {
   const int nstrips = (min(row0 + kXRows, d.n_pad) - row0) / 16;
   const float* __restrict__ P = static_cast<const float*>(d.src);
 
-  for (int idx = tid; idx < TCB * RP; idx += 256) {
+  f32x4 bufA[4][2], bufB[4][2];
+  auto load_half = [&](f32x4 (&b)[4][2], const int r, const int h) {
+    const float* src = P + (int64_t)(r + l16) * d.ldp + col0 + 128 * h + 4 * lq;
+    static_for<0, 4>([&](auto g) {
+      b[g][0] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(src + 32 * g));
+      b[g][1] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(src + 32 * g + 16));
+    });
+  };
+  for (int idx = tid; idx < TCB * RP; idx += 64 * kXWaves) {
     const int k = idx / RP, c = idx % RP;
     sU[k][c] = c < d.R ? d.Uj[(int64_t)(col0 + k) * d.W + c] : 0.f;
   }
   __syncthreads();
 
-  f32x4 bufA[4][2], bufB[4][2];
-  auto load_half = [&](f32x4 (&b)[4][2], const int r, const int h) {
-    const float* src = P + (int64_t)(r + l16) * d.ldp + col0 + 128 * h + 8 * lq;
-    static_for<0, 4>([&](auto g) {
-      b[g][0] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(src + 32 * g));
-      b[g][1] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(src + 32 * g + 4));
-    });
-  };
   typedef float v4f __attribute__((ext_vector_type(4)));
   v4f acc[NB];
   auto multiply = [&](f32x4 (&b)[4][2], const int h) {
     static_for<0, 4>([&](auto g) {
       static_for<0, 8>([&](auto e) {
         const float a = e < 4 ? b[g][0][e % 4] : b[g][1][e % 4];
-        const int k = 128 * h + 32 * g + 8 * lq + e;
+        const int k = 128 * h + 32 * g + 4 * lq + (e < 4 ? e : 12 + e);
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
           acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, sU[k][nb * 16 + l16], acc[nb], 0, 0, 0);
@@ -435,7 +436,7 @@ __global__ void __launch_bounds__(256) k_xprod_f32(const SkinnyDesc d) {
   };
 
   if (wave < nstrips) load_half(bufA, row0 + 16 * wave, 0);
-  for (int st = wave; st < nstrips; st += 4) {
+  for (int st = wave; st < nstrips; st += kXWaves) {
     const int r = row0 + 16 * st;
     // U operands are re-read from LDS in every strip: held in registers across
     // strips (as the compiler would otherwise do) they cost the occupancy
@@ -444,7 +445,7 @@ __global__ void __launch_bounds__(256) k_xprod_f32(const SkinnyDesc d) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[nb] = v4f{0.f, 0.f, 0.f, 0.f};
     multiply(bufA, 0);
-    if (st + 4 < nstrips) load_half(bufA, r + 64, 0);
+    if (st + kXWaves < nstrips) load_half(bufA, r + 16 * kXWaves, 0);
     multiply(bufB, 1);
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
@@ -511,11 +512,11 @@ hipError_t launch_skinny_f32(int R, const float* P, int64_t ldp, int64_t n_pad, 
       const SkinnyDesc d{P, ldp, (int)n_pad, kXRows, slabU + c0, nullptr, W, per, partX + c0, nullptr, R, nct, 0,
                          kWantX};
       if (per <= 16)
-        hipLaunchKernelGGL((k_xprod_f32<1>), grid, dim3(256), 0, s, d);
+        hipLaunchKernelGGL((k_xprod_f32<1>), grid, dim3(64 * kXWaves), 0, s, d);
       else if (per <= 32)
-        hipLaunchKernelGGL((k_xprod_f32<2>), grid, dim3(256), 0, s, d);
+        hipLaunchKernelGGL((k_xprod_f32<2>), grid, dim3(64 * kXWaves), 0, s, d);
       else
-        hipLaunchKernelGGL((k_xprod_f32<4>), grid, dim3(256), 0, s, d);
+        hipLaunchKernelGGL((k_xprod_f32<4>), grid, dim3(64 * kXWaves), 0, s, d);
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
