@@ -155,6 +155,46 @@ k_rank_rect(T* __restrict__ Tm, const T* __restrict__ Y, int sy, const T* __rest
   Tm[idx] = (T)((double)Tm[idx] + d);
 }
 
+// The same for a 4 x 4 block per thread (four rows, four consecutive
+// columns; n_pad and pp multiples of 4): each Zt row segment is loaded once
+// for the four rows, each Y value once for the four columns.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_rank_rect4(T* __restrict__ Tm, const T* __restrict__ Y, int sy, const T* __restrict__ Zt, int w, int64_t n_pad,
+             int pp) {
+  typedef T v4 __attribute__((ext_vector_type(4)));
+  const int q4 = pp / 4;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (n_pad / 4) * q4) return;
+  const int64_t row0 = (idx / q4) * 4;
+  const int col = (int)(idx % q4) * 4;
+  double d[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) d[a][b] = 0.0;
+  for (int c = 0; c < w; ++c) {
+    const v4 z = *reinterpret_cast<const v4*>(Zt + (int64_t)c * pp + col);
+    const double zz[4] = {(double)z.x, (double)z.y, (double)z.z, (double)z.w};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const double y = (double)Y[(row0 + a) * sy + c];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) d[a][b] = fma(y, zz[b], d[a][b]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    v4* tp = reinterpret_cast<v4*>(Tm + (row0 + a) * pp + col);
+    v4 t = *tp;
+    t.x = (T)((double)t.x + d[a][0]);
+    t.y = (T)((double)t.y + d[a][1]);
+    t.z = (T)((double)t.z + d[a][2]);
+    t.w = (T)((double)t.w + d[a][3]);
+    *tp = t;
+  }
+}
+
 }  // namespace
 
 template <typename T>
@@ -175,6 +215,11 @@ hipError_t launch_gfac_z(const double* a, const T* Zt, int wy, const double* b, 
 
 template <typename T>
 hipError_t launch_rank_rect(T* Tm, const T* Y, int sy, const T* Zt, int w, int64_t n_pad, int pp, hipStream_t s) {
+  if (pp % 4 == 0 && n_pad % 4 == 0) {
+    hipLaunchKernelGGL((k_rank_rect4<T>), dim3((unsigned)((n_pad / 4 * (pp / 4) + 255) / 256)), dim3(256), 0, s, Tm,
+                       Y, sy, Zt, w, n_pad, pp);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((k_rank_rect<T>), dim3((unsigned)((n_pad * pp + 255) / 256)), dim3(256), 0, s, Tm, Y, sy, Zt, w,
                      n_pad, pp);
   return hipGetLastError();
