@@ -182,8 +182,9 @@ hipError_t launch_skinny_f32(int R, const float* P, int64_t ldp, int64_t n_pad, 
                              const float* slabU, const float* slabV, int W, float* partX, float* partY,
                              hipStream_t s, int want = kWantX | kWantY);
 hipError_t launch_skinny_f32_multi(int nb, const SkinnyDesc* ds, int nd, int blocks, hipStream_t s);
-// Factor blocks of 32 columns per float skinny launch, and launches for R.
-inline int skinny_f32_blocks(int R) { return R <= 32 ? 1 : 2; }
+// Width class of a float skinny launch (0: the 16-wide pass for R <= 16;
+// 1, 2: one or two 32-column factor blocks), and the launches for R.
+inline int skinny_f32_blocks(int R) { return R <= 16 ? 0 : R <= 32 ? 1 : 2; }
 inline int skinny_f32_launches(int R) { return R <= 64 ? 1 : R / 64; }
 
 // S = bf16(P) for `count` consecutive floats (count a multiple of 4); with a

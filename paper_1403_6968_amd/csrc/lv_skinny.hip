@@ -362,6 +362,151 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
     }
 }
 
+// Float skinny pass for at most 16 factor columns on v_mfma_f32_16x16x4f32:
+// half the matrix-core work of the 32-wide pass at these ranks.  Tiling,
+// chunk staging, the X exchange and the partial layouts as skinny_f32_body.
+// 16x16x4 layouts: A (16 x 4): lane l holds A[l % 16][l / 16]; B (4 x 16):
+// lane l holds B[l / 16][l % 16]; C: element v of lane l is
+// C[4 (l / 16) + v][l % 16].  A group of four steps covers 16 summation
+// indices: lane l supplies index g + 4 (l / 16) + e in step e, for both
+// operands.
+__device__ __forceinline__ void skinny16_f32_body(const float* __restrict__ P, const int64_t ldp, const int n_pad,
+                                                  const int tile_rows, const float* __restrict__ Uj,
+                                                  const float* __restrict__ Vj, const int W, const int R,
+                                                  float* __restrict__ partX, float* __restrict__ partY,
+                                                  const int pR, const int want, const int ct, const int rt) {
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  const bool wx = (want & kWantX) != 0, wy = (want & kWantY) != 0;
+  constexpr int RP = 16;
+  constexpr int CR = 32;           // rows per chunk
+  constexpr int FP = 4;            // LDS row padding (floats)
+  __shared__ __align__(16) float sP[CR][TCB + FP];
+  __shared__ __align__(16) float sUt[RP][TCB + FP];
+  __shared__ __align__(16) float sVt[RP][CR + FP];
+  float* xbuf = &sP[0][0];         // [4 waves][2 row blocks][4 values][64 lanes]
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int col0 = ct * TCB;
+  const int row0 = rt * tile_rows;
+  const int rend = min(row0 + tile_rows, n_pad);
+  const int l16 = lane % 16, lq = lane / 16;
+  const int srow = tid / 64, sgrp = tid % 64;
+
+  constexpr int VPT = RP * CR / 256;
+  f32x4 pre[CR / 4];
+  float pv[VPT];
+  auto fetch = [&](const int r0) {
+    static_for<0, CR / 4>([&](auto i) {
+      pre[i] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(P + (int64_t)(r0 + srow + 4 * i) * ldp + col0 +
+                                                                     sgrp * 4));
+    });
+    static_for<0, VPT>([&](auto i) {
+      const int idx = tid + 256 * i;
+      const int rr = idx / RP, c = idx % RP;
+      pv[i] = c < R ? Vj[(int64_t)(r0 + rr) * W + c] : 0.f;
+    });
+  };
+  fetch(row0);
+
+  if (wx)
+    for (int idx = tid; idx < RP * TCB; idx += 256) {
+      const int k = idx / RP, c = idx % RP;
+      sUt[c][k] = c < R ? Uj[(int64_t)(col0 + k) * W + c] : 0.f;
+    }
+
+  v4f yacc[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) yacc[cb] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  for (int cr0 = row0; cr0 < rend; cr0 += CR) {
+    __syncthreads();   // the previous chunk's exchange buffer has been read
+    static_for<0, CR / 4>([&](auto i) { *reinterpret_cast<f32x4*>(&sP[srow + 4 * i][sgrp * 4]) = pre[i]; });
+    static_for<0, VPT>([&](auto i) {
+      const int idx = tid + 256 * i;
+      sVt[idx % RP][idx / RP] = pv[i];
+    });
+    __syncthreads();
+    if (cr0 + CR < rend) fetch(cr0 + CR);
+
+    // X partial over this wave's 64 columns, two 16-row blocks
+    v4f xacc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+    for (int g = 0; g < (wx ? 64 : 0); g += 16) {
+      const int k0 = wave * 64 + g + 4 * lq;
+      const f32x4 b = *reinterpret_cast<const f32x4*>(&sUt[l16][k0]);
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) {
+        const f32x4 a = *reinterpret_cast<const f32x4*>(&sP[mb * 16 + l16][k0]);
+        xacc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, xacc[mb], 0, 0, 0);
+        xacc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, xacc[mb], 0, 0, 0);
+        xacc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, xacc[mb], 0, 0, 0);
+        xacc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, xacc[mb], 0, 0, 0);
+      }
+    }
+
+    // Y^T += V_chunk^T P_chunk for this wave's four 16-column blocks
+#pragma unroll
+    for (int g = 0; g < (wy ? CR : 0); g += 16) {
+      const int r0 = g + 4 * lq;
+      const f32x4 a = *reinterpret_cast<const f32x4*>(&sVt[l16][r0]);
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        const int colc = wave * 64 + cb * 16 + l16;
+        yacc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, sP[r0][colc], yacc[cb], 0, 0, 0);
+        yacc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, sP[r0 + 1][colc], yacc[cb], 0, 0, 0);
+        yacc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, sP[r0 + 2][colc], yacc[cb], 0, 0, 0);
+        yacc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, sP[r0 + 3][colc], yacc[cb], 0, 0, 0);
+      }
+    }
+
+    if (!wx) continue;
+    // exchange the X partials (sP is no longer read in this chunk)
+    __syncthreads();
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) xbuf[((wave * 2 + mb) * 4 + v) * 64 + lane] = xacc[mb][v];
+    __syncthreads();
+    // thread -> (row block, value, lane) slots of the 32 x 16 outputs
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int slot = tid + 256 * i;          // [mb][v][lane]
+      const int ln = slot % 64, v = (slot / 64) % 4, mb = slot / 256;
+      float x = 0.f;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) x += xbuf[((w * 2 + mb) * 4 + v) * 64 + ln];
+      const int c = ln % 16;
+      const int rr = mb * 16 + 4 * (ln / 16) + v;
+      if (c < R) partX[((int64_t)ct * n_pad + cr0 + rr) * pR + c] = x;
+    }
+  }
+
+  if (!wy) return;
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    const int col = col0 + wave * 64 + cb * 16 + l16;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int c = 4 * lq + v;
+      if (c < R) partY[((int64_t)rt * n_pad + col) * pR + c] = yacc[cb][v];
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_skinny16_f32(const SkinnyDesc d) {
+  skinny16_f32_body(static_cast<const float*>(d.src), d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.R, d.partX,
+                    d.partY, d.pR, d.want, blockIdx.x, blockIdx.y);
+}
+
+__global__ void __launch_bounds__(256) k_skinny16_f32_multi(const SkinnyDesc* __restrict__ ds, int nd) {
+  const SkinnyDesc d = ds[find_skinny(ds, nd, (int)blockIdx.x)];
+  const int local = (int)blockIdx.x - d.block_begin;
+  skinny16_f32_body(static_cast<const float*>(d.src), d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.R, d.partX,
+                    d.partY, d.pR, d.want, local % d.nct, local / d.nct);
+}
+
 template <int NB>
 __global__ void __launch_bounds__(256) k_skinny_f32(const SkinnyDesc d) {
   skinny_f32_body<NB>(static_cast<const float*>(d.src), d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.R,
@@ -529,7 +674,9 @@ hipError_t launch_skinny_f32(int R, const float* P, int64_t ldp, int64_t n_pad, 
   for (int c0 = 0; c0 < R; c0 += per) {
     const SkinnyDesc d{P, ldp, (int)n_pad, tile_rows, slabU + c0, Vj + c0, W, per, partX + c0, partY + c0, R, nct, 0,
                        want};
-    if (skinny_f32_blocks(per) == 1)
+    if (skinny_f32_blocks(per) == 0)
+      hipLaunchKernelGGL(k_skinny16_f32, grid, dim3(256), 0, s, d);
+    else if (skinny_f32_blocks(per) == 1)
       hipLaunchKernelGGL((k_skinny_f32<1>), grid, dim3(256), 0, s, d);
     else
       hipLaunchKernelGGL((k_skinny_f32<2>), grid, dim3(256), 0, s, d);
@@ -542,6 +689,7 @@ hipError_t launch_skinny_f32(int R, const float* P, int64_t ldp, int64_t n_pad, 
 hipError_t launch_skinny_f32_multi(int nb, const SkinnyDesc* ds, int nd, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   switch (nb) {
+    case 0: hipLaunchKernelGGL(k_skinny16_f32_multi, dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
     case 1: hipLaunchKernelGGL((k_skinny_f32_multi<1>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
     case 2: hipLaunchKernelGGL((k_skinny_f32_multi<2>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
     default: return hipErrorInvalidValue;
