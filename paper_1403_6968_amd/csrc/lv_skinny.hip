@@ -7,8 +7,10 @@
 // bfloat16 x bfloat16 with float accumulation (v_mfma_f32_32x32x16_bf16).
 // k_skinny_f32 reads the float power itself and multiplies in float
 // (v_mfma_f32_32x32x2f32): the FP32 method's products at level ranks where
-// the vector units, not HBM, would bound a fused pass.
-// Both write the partial X / Y layouts of the fused pass, so the common tail
+// the vector units, not HBM, would bound a fused pass; k_skinny16_f32 is
+// its 16-column form (v_mfma_f32_16x16x4f32), and k_xprod_f32 forms X alone
+// with P loaded straight into the operand registers (no LDS staging).
+// All write the partial X / Y layouts of the fused pass, so the common tail
 // assembles the next factors; the Gram V_j^T U_j is formed in FP64 apart.
 //
 // Lane layouts (64 lanes, l = lane, h = l / 32):
