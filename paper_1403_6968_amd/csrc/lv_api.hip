@@ -378,8 +378,9 @@ lv_status gfac_tail(lv_view* v, int j, int R, int ru, const T* sU, const T* sV, 
     });
   if (st == LV_OK)
     st = timed(v, 1, s, "general: Y", [&] {
-      return launch_gfac_y<T>(v->partXT<T>(), L.nct, wj, sU, j > 0 ? v->slabQ<T>() : nullptr, L.W, R, v->atbG(), wj,
-                              gw(ru, j), v->Yf<T>(j + 1), L.WY[j + 1], L.n_pad, s);
+      // X = P_j Y_j: at level 0 (Y_0 = U_0) the partials of the powers' pass
+      return launch_gfac_y<T>(j == 0 ? v->partX<T>(0) : v->partXT<T>(), L.nct, wj, sU, j > 0 ? v->slabQ<T>() : nullptr,
+                              L.W, R, v->atbG(), wj, gw(ru, j), v->Yf<T>(j + 1), L.WY[j + 1], L.n_pad, s);
     });
   if (st == LV_OK)
     st = timed(v, 1, s, "general: Z", [&] {
@@ -475,7 +476,8 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
   if (st != LV_OK) return st;
   for (int j = 0; j < L.m; ++j) {
     const int R = r_pad << j;
-    if (L.general) {
+    if (L.general && !(L.gfac && j == 0)) {
+      // (factored deltas at level 0: P_0 Y_0 = P_0 U_0 is the powers' own X)
       st = L.gfac ? gfac_pass<T>(v, j, r_pad, sU, s) : general_pass<T>(v, j, s);
       if (st != LV_OK) return st;
     }
