@@ -476,12 +476,19 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
   if (st != LV_OK) return st;
   for (int j = 0; j < L.m; ++j) {
     const int R = r_pad << j;
-    if (L.general && !(L.gfac && j == 0)) {
-      // (factored deltas at level 0: P_0 Y_0 = P_0 U_0 is the powers' own X)
+    // The general form's product with the OLD P_j: P_j D_j (hybrid) or P_j Y_j
+    // (factored; at level 0 Y_0 = U_0, so the powers' own X serves).  It
+    // rides on the powers' fused pass when the X width allows, like P_j Q_j
+    // of the sums; else it is a read-only pass of its own.
+    const bool gen_op = L.general && !(L.gfac && j == 0);
+    const bool vec_level = fused_vector_level(R, (int)sizeof(T), v->shadowed());
+    const bool q_in_pass = L.sums && j > 0 && vec_level && fused_extra_fits(R, true, 0);
+    const int xd = !gen_op ? 0 : L.gfac ? gW(r_pad, j) : L.pp;
+    const bool d_in_pass = gen_op && vec_level && fused_extra_fits(R, q_in_pass, xd);
+    if (gen_op && !d_in_pass) {
       st = L.gfac ? gfac_pass<T>(v, j, r_pad, sU, s) : general_pass<T>(v, j, s);
       if (st != LV_OK) return st;
     }
-    const bool q_in_pass = L.sums && j > 0 && powers_pass_with_q(R, (int)sizeof(T), v->shadowed());
     if (L.sums && j > 0 && !q_in_pass) {
       // sums: X_s = P_j Q_j with the OLD P_j, before this level's update
       st = timed(v, 0, s, "sums: P Q", [&] {
@@ -527,9 +534,13 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
       }
     }
     st = timed(v, 0, s, "level pass", [&] {
-      if (q_in_pass)
-        return launch_level_fused_q<T>(R, v->P<T>(j), L.ldp, L.n_pad, v->tile_rows[j], sU, sV, v->slabQ<T>(), L.W,
-                                       v->partX<T>(j), v->partY<T>(j), v->partG(j), v->partXs<T>(j), s);
+      if (q_in_pass || d_in_pass) {
+        const T* Dop = !d_in_pass ? nullptr : L.gfac ? v->Yf<T>(j) : v->D<T>(j & 1);
+        const int ldd = L.gfac ? L.WY[j] : L.pp;
+        return launch_level_fused_x<T>(R, v->P<T>(j), L.ldp, L.n_pad, v->tile_rows[j], sU, sV, L.W, v->partX<T>(j),
+                                       v->partY<T>(j), v->partG(j), q_in_pass ? v->slabQ<T>() : nullptr,
+                                       v->partXs<T>(j), Dop, ldd, d_in_pass ? xd : 0, v->partXT<T>(), s);
+      }
       return launch_level_fused<T>(R, v->P<T>(j), L.ldp, L.n_pad, v->tile_rows[j], sU, sV, L.W, v->partX<T>(j),
                                    v->partY<T>(j), v->partG(j), s);
     });

@@ -49,28 +49,32 @@ namespace {
 // stride pR at the chunk's column offset), the rank update and the Gram done
 // by k_level_update and k_gram.
 //
-// Two variants serve views that keep the sums of powers as well (one pass
-// over a stored matrix instead of two):
-//   XE = R   X is formed for XE more columns, taken from Ux (same stride W):
-//            X = P [U_j, Q_j], the second block's partials to partX2 (row
-//            stride XE); the powers' pass thus also yields P_j Q_j.
+// Variants for views that keep the sums of powers or a general form as well
+// (one pass over a stored matrix instead of two or three):
+//   XE, XD   X is formed for XE + XD more columns: XE taken from Ux (same
+//            stride W), XD from Ud (stride Wd), X = P [U_j, Q_j, D_j]; the
+//            extra blocks' partials go to partX2 (row stride XE) and partX3
+//            (row stride XD).  The powers' pass thus also yields P_j Q_j
+//            (sums) and P_j D_j (the general form's delta or factor slab).
 //   SP       the sums pass: no X; Y = S^T Vy with the old S and the rank
 //            update S += Uj Vj^T (Uj = Q_j, Vj = W_j), no Gram.
-template <typename T, int R, int RB, bool UPD, int XE = 0, bool SP = false>
+template <typename T, int R, int RB, bool UPD, int XE = 0, bool SP = false, int XD = 0>
 __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp, const int n_pad,
                                            const int tile_rows, const T* __restrict__ Uj,
                                            const T* __restrict__ Vj, const int W, T* __restrict__ partX,
                                            T* __restrict__ partY, double* __restrict__ partG, const int pR,
                                            const int ct, const int rt, const T* __restrict__ Ux = nullptr,
-                                           T* __restrict__ partX2 = nullptr, const T* __restrict__ Vy = nullptr) {
+                                           T* __restrict__ partX2 = nullptr, const T* __restrict__ Vy = nullptr,
+                                           const T* __restrict__ Ud = nullptr, const int Wd = 0,
+                                           T* __restrict__ partX3 = nullptr) {
   constexpr int EPL = 16 / (int)sizeof(T);
   constexpr int TC = 64 * EPL;
   constexpr int NQ = 64 / RB;           // column slices in Phase B
   constexpr int QW = TC / NQ;           // columns per slice
   constexpr int LDSW = TC + EPL;        // padded LDS row (elements)
   constexpr int UPAD = 4;               // LDS padding between U slices (elements)
-  constexpr int XR = R + XE;            // columns of X
-  static_assert(!SP || (UPD && XE == 0), "the sums pass updates and forms no X");
+  constexpr int XR = R + XE + XD;       // columns of X
+  static_assert(!SP || (UPD && XE == 0 && XD == 0), "the sums pass updates and forms no X");
 
   __shared__ __align__(16) T tileP[4 * RB * LDSW];
   __shared__ __align__(16) T utile[SP ? 1 : TC * XR + NQ * UPAD];
@@ -90,7 +94,8 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
     for (int idx = tid; idx < TC * XR; idx += 256) {
       const int col = idx / XR, c = idx % XR;
       const int64_t g = (int64_t)(col0 + col) * W;
-      utile[col * XR + (col / QW) * UPAD + c] = (XE == 0 || c < R) ? Uj[g + c] : Ux[g + c - R];
+      utile[col * XR + (col / QW) * UPAD + c] =
+          c < R ? Uj[g + c] : c < R + XE ? Ux[g + c - R] : Ud[(int64_t)(col0 + col) * Wd + c - R - XE];
     }
   }
   const T* __restrict__ Yop = SP ? Vy : Vj;
@@ -187,6 +192,10 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
 #pragma unroll
         for (int c = 0; c < XE; ++c) partX2[((int64_t)ct * n_pad + r0 + rho) * XE + c] = x[R + c];
       }
+      if constexpr (XD > 0) {
+#pragma unroll
+        for (int c = 0; c < XD; ++c) partX3[((int64_t)ct * n_pad + r0 + rho) * XD + c] = x[R + XE + c];
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -253,11 +262,13 @@ __global__ void __launch_bounds__(256) k_level_fused(const FusedDesc<T> d) {
                             blockIdx.x, blockIdx.y);
 }
 
-// The powers' pass of a view with sums: X also for Q_j (XE = R columns).
-template <typename T, int R, int RB>
-__global__ void __launch_bounds__(256) k_level_fused_q(const FusedDesc<T> d) {
-  fused_body<T, R, RB, true, R, false>(d.P, d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.partX, d.partY, d.partG,
-                                       d.pR, blockIdx.x, blockIdx.y, d.Ux, d.partX2, nullptr);
+// The powers' pass of a view with sums or a general form: X also for Q_j
+// (XE = R columns or none) and for D_j (XD columns or none).
+template <typename T, int R, int RB, int XE, int XD>
+__global__ void __launch_bounds__(256) k_level_fused_x(const FusedDesc<T> d) {
+  fused_body<T, R, RB, true, XE, false, XD>(d.P, d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.partX, d.partY,
+                                            d.partG, d.pR, blockIdx.x, blockIdx.y, d.Ux, d.partX2, nullptr, d.Ud,
+                                            d.Wd, d.partX3);
 }
 
 // The sums pass: Y = S^T Vy (old S), S += Q_j W_j^T.
@@ -322,25 +333,52 @@ hipError_t launch_level_fused(int R, T* P, int64_t ldp, int64_t n_pad, int tile_
   LV_RANK_SWITCH(R, return (fused_r<T, RR>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s)))
 }
 
+// Launch k_level_fused_x for level rank R with XE (0 or R) and xd (0, 1, 2,
+// 4 or 8) extra columns, R + XE + xd <= fused_x_cap(R); the row blocks (RB) of the plain
+// pass for the same R: the same summation order, so X for U_j, Y, the Gram
+// and the update are bit-identical to it.
+template <typename T, int R, int XE>
+hipError_t fused_x_launch(int xd, const FusedDesc<T>& d, dim3 grid, hipStream_t s) {
+  constexpr int RB = R >= 8 ? 8 : 16;
+  switch (xd) {
+#define LV_FUSED_X_CASE(XD)                                                                   \
+    case XD:                                                                                  \
+      if constexpr (R + XE + XD <= fused_x_cap(R)) {                                          \
+        hipLaunchKernelGGL((k_level_fused_x<T, R, RB, XE, XD>), grid, dim3(256), 0, s, d);    \
+        return hipGetLastError();                                                             \
+      }                                                                                       \
+      return hipErrorInvalidValue;
+    LV_FUSED_X_CASE(0)
+    LV_FUSED_X_CASE(1)
+    LV_FUSED_X_CASE(2)
+    LV_FUSED_X_CASE(4)
+    LV_FUSED_X_CASE(8)
+#undef LV_FUSED_X_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename T>
-hipError_t launch_level_fused_q(int R, T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* slabU,
-                                const T* slabV, const T* slabQ, int W, T* partX, T* partY, double* partG, T* partXq,
-                                hipStream_t s) {
-  // the row blocks (RB) of the plain pass for the same R: the same summation
-  // order, so X for U_j, Y, the Gram and the update are bit-identical to it
+hipError_t launch_level_fused_x(int R, T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* slabU,
+                                const T* slabV, int W, T* partX, T* partY, double* partG, const T* slabQ, T* partXq,
+                                const T* Dop, int ldd, int xd, T* partXd, hipStream_t s) {
+  if (!fused_extra_fits(R, slabQ != nullptr, xd)) return hipErrorInvalidValue;
   const int nct = (int)(n_pad / tile_cols<T>());
   FusedDesc<T> d{P, ldp, (int)n_pad, tile_rows, slabU, slabV + (W - R), W, partX, partY, partG, R, nct, 0};
   d.Ux = slabQ;
   d.partX2 = partXq;
+  d.Ud = Dop;
+  d.Wd = ldd;
+  d.partX3 = partXd;
   const dim3 grid((unsigned)nct, (unsigned)((n_pad + tile_rows - 1) / tile_rows));
+  const bool q = slabQ != nullptr;
   switch (R) {
-    case 1: hipLaunchKernelGGL((k_level_fused_q<T, 1, 16>), grid, dim3(256), 0, s, d); break;
-    case 2: hipLaunchKernelGGL((k_level_fused_q<T, 2, 16>), grid, dim3(256), 0, s, d); break;
-    case 4: hipLaunchKernelGGL((k_level_fused_q<T, 4, 16>), grid, dim3(256), 0, s, d); break;
-    case 8: hipLaunchKernelGGL((k_level_fused_q<T, 8, 8>), grid, dim3(256), 0, s, d); break;
+    case 1: return q ? fused_x_launch<T, 1, 1>(xd, d, grid, s) : fused_x_launch<T, 1, 0>(xd, d, grid, s);
+    case 2: return q ? fused_x_launch<T, 2, 2>(xd, d, grid, s) : fused_x_launch<T, 2, 0>(xd, d, grid, s);
+    case 4: return q ? fused_x_launch<T, 4, 4>(xd, d, grid, s) : fused_x_launch<T, 4, 0>(xd, d, grid, s);
+    case 8: return q ? fused_x_launch<T, 8, 8>(xd, d, grid, s) : fused_x_launch<T, 8, 0>(xd, d, grid, s);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 template <typename T>
@@ -412,10 +450,12 @@ template hipError_t launch_level_fused<float>(int, float*, int64_t, int64_t, int
                                               float*, float*, double*, hipStream_t);
 template hipError_t launch_level_fused<double>(int, double*, int64_t, int64_t, int, const double*, const double*,
                                                int, double*, double*, double*, hipStream_t);
-template hipError_t launch_level_fused_q<float>(int, float*, int64_t, int64_t, int, const float*, const float*,
-                                                const float*, int, float*, float*, double*, float*, hipStream_t);
-template hipError_t launch_level_fused_q<double>(int, double*, int64_t, int64_t, int, const double*, const double*,
-                                                 const double*, int, double*, double*, double*, double*, hipStream_t);
+template hipError_t launch_level_fused_x<float>(int, float*, int64_t, int64_t, int, const float*, const float*, int,
+                                                float*, float*, double*, const float*, float*, const float*, int, int,
+                                                float*, hipStream_t);
+template hipError_t launch_level_fused_x<double>(int, double*, int64_t, int64_t, int, const double*, const double*,
+                                                 int, double*, double*, double*, const double*, double*,
+                                                 const double*, int, int, double*, hipStream_t);
 template hipError_t launch_sums_fused<float>(int, float*, int64_t, int64_t, int, const float*, const float*,
                                              const float*, int, float*, hipStream_t);
 template hipError_t launch_sums_fused<double>(int, double*, int64_t, int64_t, int, const double*, const double*,

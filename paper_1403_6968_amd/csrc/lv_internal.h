@@ -44,6 +44,8 @@ template <typename T> struct FusedDesc {
   const T* Ux = nullptr;                // extra X operand (powers' pass of a view with sums)
   T* partX2 = nullptr;                  //   and its partials
   const T* Vy = nullptr;                // Y operand of the sums pass
+  const T* Ud = nullptr; int Wd = 0;    // general form: extra X operand (row stride Wd)
+  T* partX3 = nullptr;                  //   and its partials
 };
 template <typename T> struct GramDesc {
   const T* Uj; const T* Vj; int W; int n_pad; int tile_rows; double* partG;
@@ -100,11 +102,16 @@ inline bool skinny_on_mfma(int R, int elem) { return elem == 4 && R >= kMfmaSkin
 // Whether the fused pass of rank R forms the Gram partials itself (one per
 // row tile); otherwise the stand-alone Gram kernel and its sum provide G.
 inline bool gram_in_pass(int R, int elem) { return R <= kMaxFusedRank && !skinny_on_mfma(R, elem); }
-// Views with sums: the powers' fused pass also forms P_j Q_j (its X for 2R
-// columns) where the level runs the fused vector pass and 2R <= 16.
-inline bool powers_pass_with_q(int R, int elem, bool shadowed) {
-  return !shadowed && 2 * R <= kMaxFusedRank && !skinny_on_mfma(R, elem);
+// The powers' fused pass of a level with rank R can also form X for Q_j (R
+// more columns, views with sums) and for xd columns of a general-form operand
+// (xd a power of two up to 8) when the level runs the fused vector pass and
+// the X width stays within fused_x_cap(R): 16 columns with the 8-row blocks
+// of R = 8, 12 with the 16-row blocks below (the LDS of two blocks per CU).
+constexpr int fused_x_cap(int R) { return R >= 8 ? 16 : 12; }
+inline bool fused_extra_fits(int R, bool q, int xd) {
+  return R <= 8 && (xd == 0 || xd == 1 || xd == 2 || xd == 4 || xd == 8) && R + (q ? R : 0) + xd <= fused_x_cap(R);
 }
+inline bool fused_vector_level(int R, int elem, bool shadowed) { return !shadowed && !skinny_on_mfma(R, elem); }
 // The sums pass (Y = S^T V_j and the rank update of S in one pass) on the
 // vector kernel, below the ranks that run on the matrix cores.
 inline bool sums_fused(int R, int elem) { return R <= kMaxFusedRank && !skinny_on_mfma(R, elem); }
@@ -199,13 +206,15 @@ hipError_t launch_to_bf16(const float* P, uint16_t* S, int64_t count, hipStream_
 template <typename T>
 hipError_t launch_level_readonly(int R, const T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* Uop,
                                  const T* Vop, int W, T* partX, T* partY, hipStream_t s);
-// The powers' fused pass of a view with sums (R <= 8): as launch_level_fused
-// for level rank R, and X = P Q_j (Q_j = columns [0, R) of slabQ) in the same
-// read of P, its partials to partXq ([nct][n_pad][R]).
+// The powers' fused pass with extra X columns (fused_extra_fits): as
+// launch_level_fused for level rank R, and in the same read of P
+// X = P Q_j (slabQ non-null; Q_j = columns [0, R) of slabQ, partials to
+// partXq, [nct][n_pad][R]) and X = P D (Dop non-null; xd columns with row
+// stride ldd, partials to partXd, [nct][n_pad][xd]).
 template <typename T>
-hipError_t launch_level_fused_q(int R, T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* slabU,
-                                const T* slabV, const T* slabQ, int W, T* partX, T* partY, double* partG, T* partXq,
-                                hipStream_t s);
+hipError_t launch_level_fused_x(int R, T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* slabU,
+                                const T* slabV, int W, T* partX, T* partY, double* partG, const T* slabQ, T* partXq,
+                                const T* Dop, int ldd, int xd, T* partXd, hipStream_t s);
 // The sums pass (R <= 16): partial Y = S^T V_j with the old S (V_j = columns
 // [W - R, W) of slabV; partials [nrt][n_pad][R]) and S += Q_j W_j^T, one read
 // and one write of S.
