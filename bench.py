@@ -397,10 +397,13 @@ def bench_batched(torch, lv, synth, dev, rounds=30):
             "alg_bytes_per_round": bytes_round, "alg_GBps": bytes_round / (ms * 1e-3) / 1e9}
 
 
-def bench_serving(torch, lv, synth, dev, seconds=2.0, rate=20000.0, r_coalesce=16, shadow=True):
+def bench_serving(torch, lv, synth, dev, seconds=2.0, rate=20000.0, r_coalesce=16, shadow=True,
+                  hold=(16, 0.03)):
     """32 views, n log-uniform in [2048, 16384], k = 16, FP32 (with bfloat16
     shadows by default); Poisson arrivals at `rate` requests/s over views with
-    Zipf(1.1) popularity; per-view coalescing, continuous batching."""
+    Zipf(1.1) popularity; per-view coalescing, continuous batching; rounds
+    hold a view until it has hold[0] requests queued or its oldest has waited
+    hold[1] s."""
     mode = lv.LV_FP32_BF16SHADOW if shadow else lv.LV_FP32
     g = synth.rng(0, 5, 0)
     ns = np.exp(g.uniform(np.log(2048), np.log(16384), size=32)).astype(int)
@@ -411,6 +414,7 @@ def bench_serving(torch, lv, synth, dev, seconds=2.0, rate=20000.0, r_coalesce=1
     need = sum(probe.view_bytes(int(n), 16) for n in ns)
     probe.close()
     srv = lv.Server((16 << 20) + need, mode=mode, r_coalesce=r_coalesce)
+    srv.set_hold(*hold)
     ids = []
     for v in range(32):
         A = torch.from_numpy(synth.gaussian_matrix(int(ns[v]), seed=0, config=5, view=v).astype(np.float32)).to(dev)
@@ -441,8 +445,9 @@ def bench_serving(torch, lv, synth, dev, seconds=2.0, rate=20000.0, r_coalesce=1
     t_end = srv.now()
     st = srv.stats()
     srv.close()
-    return {"workload": "32 views, n log-uniform [2048,16384], k=16, %s, Poisson %.0f req/s, Zipf(1.1)"
-                        % ("FP32 + BF16 shadows" if shadow else "FP32", rate),
+    return {"workload": "32 views, n log-uniform [2048,16384], k=16, %s, Poisson %.0f req/s, Zipf(1.1), "
+                        "hold %d requests / %.0f ms" % ("FP32 + BF16 shadows" if shadow else "FP32", rate, hold[0],
+                                                        hold[1] * 1e3),
             "offered_per_s": rate, "completed": int(st["completed"]),
             "throughput_per_s": st["completed"] / (t_end - t0), "rounds": int(st["rounds"]),
             "mean_coalesced_rank": st["completed"] / max(st["coalesced_updates"], 1),

@@ -367,6 +367,15 @@ lv_status lv_server_create(void* arena, size_t arena_bytes, lv_mode mode, int r_
                            void* stream, lv_server** out);
 /* Arena bytes one view of order n and power k takes (0 if invalid). */
 size_t lv_server_view_bytes(const lv_server* s, int64_t n, int k);
+/* Hold policy of the rounds (coalescing of Sec. 4.2 traded against latency):
+ * a view with pending requests joins a round only once it has
+ * min(min_fill, r_coalesce) requests queued or its oldest request has
+ * waited max_wait_s seconds (arrival clock), so rounds carry fuller updates
+ * and the busiest views get more rounds; with no round in flight every
+ * view with pending requests goes, so queued work never waits on an idle
+ * device.  min_fill = 1 (the default) puts every pending view in every
+ * round.  LV_EINVAL for min_fill < 1 or a negative (or NaN) max_wait_s. */
+lv_status lv_server_set_hold(lv_server* s, int min_fill, double max_wait_s);
 /* Admit a view of A^k (A: n x n device, lda >= n); LV_ENOMEM when no free
  * block is large enough (the caller may retry after removals). */
 lv_status lv_server_add_view(lv_server* s, const void* A, int64_t n, int64_t lda, int k,

@@ -61,6 +61,8 @@ struct lv_server {
   char* arena;
   size_t arena_bytes;
   int rc;
+  int hold_fill = 1;        // hold policy: a view joins a round once it has
+  double hold_wait = 0.0;   //   hold_fill requests queued or waited hold_wait s
   hipStream_t stream;
   Lanes lanes;
   std::vector<std::pair<size_t, size_t>> free_blocks;  // (offset, size), sorted by offset
@@ -181,8 +183,17 @@ lv_status step_impl(lv_server* s, int* launched) {
   // the stream; further requests keep coalescing in the queues meanwhile
   if ((int)s->inflight.size() >= kMaxInFlight) return LV_OK;
   std::vector<int> active;
-  for (int i = 0; i < (int)s->views.size(); ++i)
-    if (s->views[i].alive && !s->views[i].q.empty()) active.push_back(i);
+  const double t = now_s(s->t0);
+  const int fill = std::min(s->hold_fill, s->rc);
+  for (int i = 0; i < (int)s->views.size(); ++i) {
+    const SView& sv = s->views[i];
+    if (sv.alive && !sv.q.empty() && ((int)sv.q.size() >= fill || t - sv.q.front().arrival >= s->hold_wait))
+      active.push_back(i);
+  }
+  // work-conserving: with no round in flight every pending view goes
+  if (active.empty() && s->inflight.empty())
+    for (int i = 0; i < (int)s->views.size(); ++i)
+      if (s->views[i].alive && !s->views[i].q.empty()) active.push_back(i);
   if (active.empty()) return LV_OK;
   int slot = free_slot(s);
   while (slot < 0) {
@@ -298,6 +309,15 @@ lv_status lv_server_create(void* arena, size_t arena_bytes, lv_mode mode, int r_
 }
 
 size_t lv_server_view_bytes(const lv_server* s, int64_t n, int k) { return s ? view_block_bytes(s, n, k) : 0; }
+
+lv_status lv_server_set_hold(lv_server* s, int min_fill, double max_wait_s) {
+  g_err[0] = 0;
+  if (!s) return fail(LV_EINVAL, "server is NULL");
+  if (min_fill < 1 || !(max_wait_s >= 0.0)) return fail(LV_EINVAL, "min_fill < 1 or max_wait_s < 0");
+  s->hold_fill = min_fill;
+  s->hold_wait = max_wait_s;
+  return LV_OK;
+}
 
 lv_status lv_server_add_view(lv_server* s, const void* A, int64_t n, int64_t lda, int k, int* view_id) {
   g_err[0] = 0;

@@ -36,7 +36,7 @@ EXPORTED = (
     "lv_view_reanchor", "lv_view_stats", "lv_view_destroy", "lv_reeval_footprint",
     "lv_reeval", "lv_view_set_timing", "lv_view_timing", "lv_view_write", "lv_view_drift_check",
     "lv_batch_footprint", "lv_batch_create", "lv_batch_inputs", "lv_batch_stage", "lv_batch_update",
-    "lv_batch_destroy", "lv_server_create", "lv_server_view_bytes", "lv_server_add_view",
+    "lv_batch_destroy", "lv_server_create", "lv_server_view_bytes", "lv_server_set_hold", "lv_server_add_view",
     "lv_server_remove_view", "lv_server_view", "lv_server_now", "lv_server_submit", "lv_server_step",
     "lv_view_tile_rows", "lv_view_set_tile_rows", "lv_batch_tuning",
     "lv_view_footprint_ex", "lv_view_create_ex", "lv_view_read_sum",
@@ -121,6 +121,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "lv_batch_destroy": (None, [P]),
         "lv_server_create": (I32, [P, SZ, I32, I32, P, c.POINTER(P)]),
         "lv_server_view_bytes": (SZ, [P, I64, I32]),
+        "lv_server_set_hold": (I32, [P, I32, c.c_double]),
         "lv_server_add_view": (I32, [P, P, I64, I64, I32, c.POINTER(I32)]),
         "lv_server_remove_view": (I32, [P, I32]),
         "lv_server_view": (P, [P, I32]),
@@ -582,6 +583,11 @@ class Server:
 
     def view_bytes(self, n: int, k: int) -> int:
         return int(load().lv_server_view_bytes(self.handle, n, k))
+
+    def set_hold(self, min_fill: int, max_wait_s: float) -> None:
+        """Rounds take a view once it has min_fill requests queued or its
+        oldest has waited max_wait_s (min_fill = 1: every pending view)."""
+        _check(load().lv_server_set_hold(self.handle, min_fill, max_wait_s))
 
     def add_view(self, A: torch.Tensor, k: int) -> int:
         a, lda = _mat(A, self.dtype, "A")

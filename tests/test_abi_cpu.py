@@ -184,6 +184,7 @@ def test_general_footprint_and_validation(lib):
                                     None, ctypes.byref(h))
     assert st == L.LV_ENOMEM and str(need) in L.lv_last_error()
     assert lib.lv_view_read_general(None, 1, 0x1000, 4, None) == L.LV_EINVAL
+    assert lib.lv_server_set_hold(None, 1, 0.0) == L.LV_EINVAL
 
 
 def test_general_skip_footprint_and_validation(lib):

@@ -65,13 +65,15 @@ def _requests():
     return [reqs[i] for i in order]
 
 
-def _serve(lv, views_subset, reqs, step_every, mode=None):
+def _serve(lv, views_subset, reqs, step_every, mode=None, hold=None):
     import torch
     mode = lv.LV_FP32 if mode is None else mode
     probe = lv.Server(8 * MiB, mode=mode)
     total = sum(probe.view_bytes(SHAPES[v][0], SHAPES[v][1]) for v in views_subset)
     probe.close()
     srv = lv.Server(8 * MiB + total, mode=mode, r_coalesce=4)
+    if hold is not None:
+        srv.set_hold(*hold)
     ids = {}
     for v in views_subset:
         n, k = SHAPES[v]
@@ -119,3 +121,32 @@ def test_mix_equals_alone_and_oracle(shadow):
             assert mr < tol, (v, p, mr)
             assert ma < tol, (v, p, ma)
         note(f"view {v} n={n} k={k}: maxrel vs oracle {max(O.maxrel(mix[v][p], ref[p]) for p in ref):.2e}")
+
+
+def test_hold_policy_applies_every_request():
+    """With a hold policy (a view waits for a full rank-4 update, or for the
+    device to run idle) every request is still applied, the updates are
+    fuller, and the views equal the ones served without holding and the
+    oracle."""
+    lv = _lv()
+    reqs = _requests()
+    base, st0 = _serve(lv, range(len(SHAPES)), reqs, step_every=5)
+    held, st1 = _serve(lv, range(len(SHAPES)), reqs, step_every=5, hold=(4, 10.0))
+    note(f"no hold {st0}; hold {st1}")
+    assert st1["submitted"] == st1["completed"] == len(reqs)
+    assert st1["coalesced_updates"] <= st0["coalesced_updates"]
+    for v, (n, k) in enumerate(SHAPES):
+        A = synth.gaussian_matrix(n, seed=42, config=5, view=v).astype(np.float32).astype(np.float64)
+        for vv, u, w in reqs:
+            if vv == v:
+                A += np.outer(u.astype(np.float64), w.astype(np.float64))
+        ref = O.reeval(A, k)
+        for p in ref:
+            assert O.maxrel(held[v][p], ref[p]) < 1e-4, (v, p)
+            assert O.maxrel(held[v][p], base[v][p]) < 1e-4, (v, p)
+    srv = lv.Server(8 * MiB, r_coalesce=4)
+    with pytest.raises(lv.LinviewError):
+        srv.set_hold(0, 0.0)
+    with pytest.raises(lv.LinviewError):
+        srv.set_hold(1, -1.0)
+    srv.close()
