@@ -181,7 +181,7 @@ hipError_t launch_skinny_bf16(int R, const uint16_t* S, int64_t ldp, int64_t n_p
                               hipStream_t s);
 hipError_t launch_skinny_bf16_multi(int nb, const SkinnyDesc* ds, int nd, int blocks, hipStream_t s);
 // Factor blocks of 32 columns the bfloat16 skinny kernel needs for rank R.
-inline int skinny_blocks_for(int R) { return R <= 32 ? 1 : R <= 64 ? 2 : 4; }
+inline int skinny_blocks_for(int R) { return R <= 32 ? 1 : 2; }   // R <= 64 per launch
 
 // The same products from the float power P (v_mfma_f32_32x32x2f32, float
 // products and accumulation), R <= 128 (64 factor columns per launch).

@@ -151,8 +151,11 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
       if constexpr (sizeof(T) == 4) {
         if (v->shadowed() || skinny_on_mfma(R, 4)) {
           if (v->shadowed()) {
-            skinny[skinny_blocks_for(R)].push_back({v->shadow(j), L.ldp, (int)L.n_pad, trows, sU, Vj, L.W, R,
-                                                    v->partX<T>(j), v->partY<T>(j), R, L.nct, 0});
+            const int per = R <= 64 ? R : 64;
+            for (int c0 = 0; c0 < R; c0 += per)
+              skinny[skinny_blocks_for(per)].push_back({v->shadow(j), L.ldp, (int)L.n_pad, trows, sU + c0, Vj + c0,
+                                                        L.W, per, v->partX<T>(j) + c0, v->partY<T>(j) + c0, R,
+                                                        L.nct, 0});
           } else {
             const int per = R <= 64 ? R : 64;
             for (int c0 = 0; c0 < R; c0 += per)

@@ -621,16 +621,25 @@ k_to_bf16(const float* __restrict__ P, uint16_t* __restrict__ S, int64_t count, 
 hipError_t launch_skinny_bf16(int R, const uint16_t* S, int64_t ldp, int64_t n_pad, int tile_rows,
                               const float* slabU, const float* slabV, int W, float* partX, float* partY,
                               hipStream_t s) {
-  if (R < 1 || R > 128 || n_pad % TCB != 0 || tile_rows % CRB != 0) return hipErrorInvalidValue;
+  if (R < 1 || R > 128 || (R > 64 && R % 64 != 0) || n_pad % TCB != 0 || tile_rows % CRB != 0)
+    return hipErrorInvalidValue;
   const int nct = (int)(n_pad / TCB);
-  const SkinnyDesc d{S, ldp, (int)n_pad, tile_rows, slabU, slabV + (W - R), W, R, partX, partY, R, nct, 0};
   const dim3 grid((unsigned)nct, (unsigned)((n_pad + tile_rows - 1) / tile_rows));
-  switch (skinny_blocks_for(R)) {
-    case 1: hipLaunchKernelGGL((k_skinny_bf16<1>), grid, dim3(256), 0, s, d); break;
-    case 2: hipLaunchKernelGGL((k_skinny_bf16<2>), grid, dim3(256), 0, s, d); break;
-    default: hipLaunchKernelGGL((k_skinny_bf16<4>), grid, dim3(256), 0, s, d); break;
+  const float* Vj = slabV + (W - R);
+  // at most 64 factor columns per launch: two launches of the two-block
+  // kernel for R = 128 read the shadow twice but run at twice the occupancy
+  // of one four-block launch (whose LDS allows one block per CU)
+  const int per = R <= 64 ? R : 64;
+  for (int c0 = 0; c0 < R; c0 += per) {
+    const SkinnyDesc d{S, ldp, (int)n_pad, tile_rows, slabU + c0, Vj + c0, W, per, partX + c0, partY + c0, R, nct, 0};
+    if (skinny_blocks_for(per) == 1)
+      hipLaunchKernelGGL((k_skinny_bf16<1>), grid, dim3(256), 0, s, d);
+    else
+      hipLaunchKernelGGL((k_skinny_bf16<2>), grid, dim3(256), 0, s, d);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 hipError_t launch_skinny_bf16_multi(int nb, const SkinnyDesc* ds, int nd, int blocks, hipStream_t s) {
@@ -638,7 +647,6 @@ hipError_t launch_skinny_bf16_multi(int nb, const SkinnyDesc* ds, int nd, int bl
   switch (nb) {
     case 1: hipLaunchKernelGGL((k_skinny_bf16_multi<1>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
     case 2: hipLaunchKernelGGL((k_skinny_bf16_multi<2>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
-    case 4: hipLaunchKernelGGL((k_skinny_bf16_multi<4>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
