@@ -399,3 +399,44 @@ def test_general_skip_tracks_oracle(n, k, s, r_max, r_upd, p, dtype):
         view.read_general(3 if s != 1 else k + 1)
     view.close()
     plain.close()
+
+
+def test_general_skip_full_size_against_iteration():
+    """Skip-4 model with factored deltas at n = 8192, k = 16, p = 16, FP32,
+    rank 1, 8 updates: every stored T_i (1, 2, 4, 8, 12, 16) against the
+    defining iteration T_{i+1} = A T_i + B on the final A."""
+    lv = _lv()
+    import torch
+    n, k, s, p, T = 8192, 16, 4, 16, 8
+    A = _rounded(synth.gaussian_matrix(n, seed=63, config=3), np.float32)
+    T0, B = (_rounded(x, np.float32) for x in synth.general_operands(n, p, seed=63, config=3))
+    Us, Vs = (_rounded(x, np.float32) for x in synth.update_factors(n, 1, T, seed=63, config=3))
+    view = lv.View(dev(A, torch.float32), k, general=(dev(T0, torch.float32), dev(B, torch.float32)),
+                   strategy=lv.LV_GENERAL_FACTORED, skip=s)
+    idx = O.skip_indices(k, s)
+
+    def iterate(Am):
+        out, Tm = {}, T0
+        for i in range(1, k + 1):
+            Tm = Am @ Tm + B
+            if i in idx:
+                out[i] = Tm
+        return out
+
+    base_got = {i: host(view.read_general(i)) for i in idx}
+    base_ref = iterate(A)
+    for t in range(T):
+        view.update(dev(Us[t], torch.float32), dev(Vs[t], torch.float32))
+    ref = iterate(A + np.einsum("tir,tjr->ij", Us, Vs))
+    got = {i: host(view.read_general(i)) for i in idx}
+    u = 2.0 ** -24
+    msg = []
+    for i in idx:
+        mr = O.maxrel(got[i], ref[i])
+        dr = O.deltarel(got[i], base_got[i], ref[i], base_ref[i])
+        dtol = 1e-2 + 4 * np.sqrt(T) * u * np.abs(ref[i]).max() / np.abs(ref[i] - base_ref[i]).max()
+        msg.append(f"T{i}: {mr:.1e}/{dr:.1e}(<{dtol:.1e})")
+        assert mr < 1e-4, f"T_{i} maxrel {mr:.3e}"
+        assert dr < dtol, f"T_{i} deltarel {dr:.3e} >= {dtol:.3e}"
+    note("general skip-4 full size: " + " ".join(msg))
+    view.close()
