@@ -75,9 +75,13 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
   constexpr int UPAD = 4;               // LDS padding between U slices (elements)
   constexpr int XR = R + XE + XD;       // columns of X
   static_assert(!SP || (UPD && XE == 0 && XD == 0), "the sums pass updates and forms no X");
+  // Phase B on the matrix cores (float, 8-row blocks, X at most 16 columns):
+  // there the vector units would carry the three products of the pass.
+  constexpr bool MFX = sizeof(T) == 4 && RB == 8 && XR <= 16 && !SP;
+  constexpr int UTW = TC + 4;           // row of the transposed U tile (MFX)
 
   __shared__ __align__(16) T tileP[4 * RB * LDSW];
-  __shared__ __align__(16) T utile[SP ? 1 : TC * XR + NQ * UPAD];
+  __shared__ __align__(16) T utile[SP ? 1 : MFX ? 16 * UTW : TC * XR + NQ * UPAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -89,8 +93,17 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
   const int lc = col0 + lane * EPL;
   T* myP = tileP + wave * RB * LDSW;
 
-  // X operand rows of the tile's columns, slice-padded: (col, c) -> col*XR + (col/QW)*UPAD + c.
-  if constexpr (!SP) {
+  // X operand rows of the tile's columns, slice-padded: (col, c) -> col*XR + (col/QW)*UPAD + c;
+  // for MFX transposed, (col, c) -> c*UTW + col, columns XR..15 zero.
+  if constexpr (MFX) {
+    for (int idx = tid; idx < TC * 16; idx += 256) {
+      const int col = idx / 16, c = idx % 16;
+      const int64_t g = (int64_t)(col0 + col) * W;
+      utile[c * UTW + col] = c < R ? Uj[g + c]
+                           : c < R + XE ? Ux[g + c - R]
+                           : c < XR ? Ud[(int64_t)(col0 + col) * Wd + c - R - XE] : T(0);
+    }
+  } else if constexpr (!SP) {
     for (int idx = tid; idx < TC * XR; idx += 256) {
       const int col = idx / XR, c = idx % XR;
       const int64_t g = (int64_t)(col0 + col) * W;
@@ -166,6 +179,49 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    if constexpr (MFX) {
+      // X_block (16 x 16, rows RB..15 zero) = P_block U_tile on
+      // v_mfma_f32_16x16x4f32: lane l supplies row l % 16 of the block and
+      // U column l % 16, summation index 16 j + 4 (l / 16) + e in step e of
+      // group j (two accumulators, even and odd groups, added at the end);
+      // element v of lane l is X[4 (l / 16) + v][l % 16].
+      typedef float v4f __attribute__((ext_vector_type(4)));
+      const int l16 = lane % 16, lq = lane / 16;
+      v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+      // lanes of rows RB..15 read row 0 (in bounds) and supply zeros
+      const bool live = l16 < RB;
+      const float* arow = reinterpret_cast<const float*>(myP) + (live ? l16 : 0) * LDSW + 4 * lq;
+      const float* brow = reinterpret_cast<const float*>(utile) + l16 * UTW + 4 * lq;
+#pragma unroll
+      for (int j = 0; j < TC / 16; j += 2) {
+        const V16<float> a0 = ld16(arow + 16 * j);
+        const V16<float> b0 = ld16(brow + 16 * j);
+        const V16<float> a1 = ld16(arow + 16 * j + 16);
+        const V16<float> b1 = ld16(brow + 16 * j + 16);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(live ? a0.v[e] : 0.f, b0.v[e], acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(live ? a1.v[e] : 0.f, b1.v[e], acc1, 0, 0, 0);
+        }
+      }
+      if (lq < RB / 4) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = r0 + 4 * lq + v;
+          const float xv = acc0[v] + acc1[v];
+          if (l16 < R) partX[((int64_t)ct * n_pad + row) * pR + l16] = xv;
+          if constexpr (XE > 0)
+            if (l16 >= R && l16 < R + XE) partX2[((int64_t)ct * n_pad + row) * XE + l16 - R] = xv;
+          if constexpr (XD > 0)
+            if (l16 >= R + XE && l16 < XR) partX3[((int64_t)ct * n_pad + row) * XD + l16 - R - XE] = xv;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      continue;
+    }
 
     T x[XR];
 #pragma unroll
