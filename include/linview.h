@@ -183,7 +183,8 @@ lv_status lv_view_read_sum(const lv_view* v, int index, void* out, int64_t ldo, 
  * precision from the double powers and sums and round once.
  *  p         hybrid: 1 <= p <= 64 (padded to a power of two in the
  *            workspace); factored: 1 <= p <= 4096 (padded to a multiple of
- *            128), and k * r_max rounded up to a power of two <= 128.
+ *            128), and k * r_max (s * r_max under the skip model below)
+ *            rounded up to a power of two <= 128.
  *  T0, B     n x p (device, element type of the mode), leading dimensions
  *            ldt, ldb >= p; copied into the workspace, not retained.
  *  strategy  LV_GENERAL_HYBRID or LV_GENERAL_FACTORED.
