@@ -10,8 +10,10 @@ Koch, "LINVIEW: Incremental View Maintenance for Complex Analytical
 Queries", arXiv 1403.6968) that it follows.  All arithmetic is float64.
 
 Pins (what fixes each function other than itself) are in
-`tests/test_oracle_pins.py`; every function here is pinned, none is
-"parity unpinned".
+`tests/test_oracle_pins.py` (powers), `test_oracle_sums.py`,
+`test_oracle_general.py` (general form: exponential, skip-s and linear
+models), `test_oracle_models.py` and `test_oracle_ols.py`; every function
+here is pinned, none is "parity unpinned".
 """
 
 from .linview_oracle import (  # noqa: F401
