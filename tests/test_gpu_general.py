@@ -440,3 +440,34 @@ def test_general_skip_full_size_against_iteration():
         assert dr < dtol, f"T_{i} deltarel {dr:.3e} >= {dtol:.3e}"
     note("general skip-4 full size: " + " ".join(msg))
     view.close()
+
+
+def test_general_skip_reanchor_and_batch():
+    """Skip-4 view (k = 16): re-anchoring rebuilds every stored T from the
+    current A (T_8, T_12, T_16 included); batched updates give the same T bit
+    for bit as single updates."""
+    lv = _lv()
+    import torch
+    n, k, s, p = 400, 16, 4, 6
+    A = _rounded(synth.gaussian_matrix(n, seed=64), np.float32)
+    T0, B = (_rounded(x, np.float32) for x in synth.general_operands(n, p, seed=64))
+    Us, Vs = (_rounded(x, np.float32) for x in synth.update_factors(n, 1, 3, seed=64))
+
+    def make():
+        return lv.View(dev(A, torch.float32), k, general=(dev(T0, torch.float32), dev(B, torch.float32)),
+                       strategy=lv.LV_GENERAL_FACTORED, skip=s)
+
+    view, twin = make(), make()
+    for t in range(3):
+        view.update(dev(Us[t], torch.float32), dev(Vs[t], torch.float32))
+    twin.update_batch(dev(Us, torch.float32), dev(Vs, torch.float32))
+    idx = view.general_indices()
+    for i in idx:
+        np.testing.assert_array_equal(host(view.read_general(i)), host(twin.read_general(i)))
+    view.reanchor()
+    ref = O.reeval_general_skip(host(view.read(1)), T0, B, k, s)
+    assert max(O.maxrel(host(view.read_general(i)), ref[i]) for i in idx) < 1e-6
+    with pytest.raises(lv.LinviewError):
+        view.read(8)                                       # the powers stop at P_4
+    view.close()
+    twin.close()
