@@ -512,7 +512,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(views shard by whole views or by row blocks; see the design notes)", file=sys.stderr)
+              "(views would shard by whole views, or by row blocks of the stored powers)", file=sys.stderr)
         sys.exit(2)
 
     import torch
