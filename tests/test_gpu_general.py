@@ -142,7 +142,7 @@ def test_general_regression_workload():
     view.close()
 
 
-@pytest.mark.parametrize("n,p,mode", [(8192, 16, "f32"), (8192, 1, "bf16")])
+@pytest.mark.parametrize("n,p,mode", [(8192, 16, "f32"), (8192, 1, "bf16"), (8192, 1, "f32")])
 def test_general_full_size_against_iteration(n, p, mode):
     """n = 8192, k = 16, rank 1, 12 updates; every stored T_i against the
     defining iteration on the final A (no powers formed on the host)."""
