@@ -289,14 +289,47 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
     __syncthreads();
     if (cr0 + CR < rend) fetch(cr0 + CR);
 
-    // X partial over this wave's 64 columns
+    if constexpr (NB == 1) {
+      // one 32-column factor block: wave w forms the 16 x 16 X tile of rows
+      // 16 (w % 2) .. +15 and factor columns 16 (w / 2) .. +15 over the whole
+      // tile width on v_mfma_f32_16x16x4f32 (lane l: row / column l % 16,
+      // summation index g + 4 (l / 16) + e), so no partial sums cross waves
+      if (wx) {
+        typedef float v4f __attribute__((ext_vector_type(4)));
+        const int l16 = lane % 16, lq = lane / 16;
+        const int mb = wave % 2, nbx = wave / 2;
+        v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+        for (int g = 0; g < TCB; g += 32) {
+          const f32x4 a0 = *reinterpret_cast<const f32x4*>(&sP[mb * 16 + l16][g + 4 * lq]);
+          const f32x4 b0 = *reinterpret_cast<const f32x4*>(&sUt[nbx * 16 + l16][g + 4 * lq]);
+          const f32x4 a1 = *reinterpret_cast<const f32x4*>(&sP[mb * 16 + l16][g + 16 + 4 * lq]);
+          const f32x4 b1 = *reinterpret_cast<const f32x4*>(&sUt[nbx * 16 + l16][g + 16 + 4 * lq]);
+          acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.x, b0.x, acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.x, b1.x, acc1, 0, 0, 0);
+          acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.y, b0.y, acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.y, b1.y, acc1, 0, 0, 0);
+          acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.z, b0.z, acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.z, b1.z, acc1, 0, 0, 0);
+          acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.w, b0.w, acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.w, b1.w, acc1, 0, 0, 0);
+        }
+        const int c = nbx * 16 + l16;
+        if (c < R) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            partX[((int64_t)ct * n_pad + cr0 + mb * 16 + 4 * lq + v) * pR + c] = acc0[v] + acc1[v];
+        }
+      }
+    }
+    // X partial over this wave's 64 columns (two factor blocks)
     v16f xacc[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
       for (int v = 0; v < 16; ++v) xacc[nb][v] = 0.f;
 #pragma unroll
-    for (int g = 0; g < (wx ? 64 : 0); g += 8) {
+    for (int g = 0; g < (wx && NB > 1 ? 64 : 0); g += 8) {
       const int k0 = wave * 64 + g + 4 * lh;
       const f32x4 a = *reinterpret_cast<const f32x4*>(&sP[l32][k0]);
 #pragma unroll
@@ -328,7 +361,7 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
       }
     }
 
-    if (!wx) continue;
+    if (!wx || NB == 1) continue;
     // exchange the X partials (sP is no longer read in this chunk)
     __syncthreads();
 #pragma unroll
