@@ -184,15 +184,14 @@ hipError_t launch_skinny_bf16_multi(int nb, const SkinnyDesc* ds, int nd, int bl
 inline int skinny_blocks_for(int R) { return R <= 32 ? 1 : 2; }   // R <= 64 per launch
 
 // The same products from the float power P (v_mfma_f32_32x32x2f32, float
-// products and accumulation), R <= 128 (64 factor columns per launch).
+// products and accumulation), R <= 128 (32 factor columns per launch; X alone: 64).
 hipError_t launch_skinny_f32(int R, const float* P, int64_t ldp, int64_t n_pad, int tile_rows,
                              const float* slabU, const float* slabV, int W, float* partX, float* partY,
                              hipStream_t s, int want = kWantX | kWantY);
 hipError_t launch_skinny_f32_multi(int nb, const SkinnyDesc* ds, int nd, int blocks, hipStream_t s);
-// Width class of a float skinny launch (0: the 16-wide pass for R <= 16;
-// 1, 2: one or two 32-column factor blocks), and the launches for R.
-inline int skinny_f32_blocks(int R) { return R <= 16 ? 0 : R <= 32 ? 1 : 2; }
-inline int skinny_f32_launches(int R) { return R <= 64 ? 1 : R / 64; }
+// Width class of a float skinny launch of at most 32 factor columns (0: the
+// 16-wide pass for R <= 16; 1: one 32-column factor block).
+inline int skinny_f32_blocks(int R) { return R <= 16 ? 0 : 1; }
 
 // S = bf16(P) for `count` consecutive floats (count a multiple of 4); with a
 // non-null gate only when *gate != 0.

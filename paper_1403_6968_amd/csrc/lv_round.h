@@ -157,7 +157,7 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
                                                         L.W, per, v->partX<T>(j) + c0, v->partY<T>(j) + c0, R,
                                                         L.nct, 0});
           } else {
-            const int per = R <= 64 ? R : 64;
+            const int per = R <= 32 ? R : 32;
             for (int c0 = 0; c0 < R; c0 += per)
               skinny32[skinny_f32_blocks(per)].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, trows, sU + c0,
                                                           Vj + c0, L.W, per, v->partX<T>(j) + c0,

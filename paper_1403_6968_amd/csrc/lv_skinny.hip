@@ -713,16 +713,16 @@ hipError_t launch_skinny_f32(int R, const float* P, int64_t ldp, int64_t n_pad, 
   const int nct = (int)(n_pad / TCB);
   const dim3 grid((unsigned)nct, (unsigned)((n_pad + tile_rows - 1) / tile_rows));
   const float* Vj = slabV + (W - R);
-  const int per = R <= 64 ? R : 64;
+  // at most 32 factor columns per launch: the one-block kernel (two blocks
+  // per CU, no X exchange) twice beats the two-block kernel (one per CU)
+  const int per = R <= 32 ? R : 32;
   for (int c0 = 0; c0 < R; c0 += per) {
     const SkinnyDesc d{P, ldp, (int)n_pad, tile_rows, slabU + c0, Vj + c0, W, per, partX + c0, partY + c0, R, nct, 0,
                        want};
     if (skinny_f32_blocks(per) == 0)
       hipLaunchKernelGGL(k_skinny16_f32, grid, dim3(256), 0, s, d);
-    else if (skinny_f32_blocks(per) == 1)
-      hipLaunchKernelGGL((k_skinny_f32<1>), grid, dim3(256), 0, s, d);
     else
-      hipLaunchKernelGGL((k_skinny_f32<2>), grid, dim3(256), 0, s, d);
+      hipLaunchKernelGGL((k_skinny_f32<1>), grid, dim3(256), 0, s, d);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -734,7 +734,6 @@ hipError_t launch_skinny_f32_multi(int nb, const SkinnyDesc* ds, int nd, int blo
   switch (nb) {
     case 0: hipLaunchKernelGGL(k_skinny16_f32_multi, dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
     case 1: hipLaunchKernelGGL((k_skinny_f32_multi<1>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
-    case 2: hipLaunchKernelGGL((k_skinny_f32_multi<2>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
