@@ -533,13 +533,21 @@ __device__ __forceinline__ void update_any(const UpdateDesc<T>& d, const int ct,
     update_body<T, R, SH>(d.P, d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.S, ct, rt);
 }
 
+// Float matrix-core ranks: at least two waves per SIMD (the 128 x 128
+// tile's old values stay in registers while its delta is formed).  Not for
+// the split-bfloat16 products, which would spill at large ranks.
+template <typename T, int R, bool SPLIT> constexpr int update_min_waves() {
+  return sizeof(T) == 4 && R >= kMfmaUpdateRank && !SPLIT ? 2 : 1;
+}
+
 template <typename T, int R, bool SH, bool SPLIT>
-__global__ void __launch_bounds__(256) k_level_update(const UpdateDesc<T> d) {
+__global__ void __launch_bounds__(256, (update_min_waves<T, R, SPLIT>())) k_level_update(const UpdateDesc<T> d) {
   update_any<T, R, SH, SPLIT>(d, blockIdx.x, blockIdx.y);
 }
 
 template <typename T, int R, bool SH, bool SPLIT>
-__global__ void __launch_bounds__(256) k_level_update_multi(const UpdateDesc<T>* __restrict__ ds, int nd) {
+__global__ void __launch_bounds__(256, (update_min_waves<T, R, SPLIT>()))
+k_level_update_multi(const UpdateDesc<T>* __restrict__ ds, int nd) {
   const int v = find_desc(ds, nd, (int)blockIdx.x);
   const UpdateDesc<T> d = ds[v];
   const int local = (int)blockIdx.x - d.block_begin;
