@@ -421,6 +421,34 @@ lv_status lv_reeval(const void* A, int64_t n, int64_t lda, int k,
                     lv_mode mode, void* out, int64_t ldo,
                     void* workspace, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- streaming ceiling
+ *
+ * Measured HBM ceiling for the level passes (diagnostics; none of the
+ * method's arithmetic).  One launch streams `bytes` with the access pattern
+ * of the level passes: 16-byte non-temporal loads and stores, whole 1 KiB
+ * row segments per wave, work-groups of 256 threads striding over chunks of
+ * depth x 4 KiB.  Kinds:
+ *   LV_STREAM_RMW    dst[i] = 1 * dst[i] in place (one read and one write at
+ *                    the same address, as a level pass does to P_j)
+ *   LV_STREAM_COPY   dst[i] = 1 * src[i]
+ *   LV_STREAM_READ   reads src; one float per thread (blocks * 1 KiB) goes
+ *                    to dst so that the loads stay live
+ *   LV_STREAM_WRITE  dst[i] = 0
+ *  bytes      a positive multiple of depth * 4096.
+ *  blocks     work-groups in the grid, 1 .. 2^20 (blocks per CU x CUs).
+ *  depth      16-byte vectors per thread per iteration: 1, 2, 4, 8, 16, 32.
+ *  pipelined  nonzero: the next iteration's loads are issued before the
+ *             current stores (2 x depth vectors in flight per thread).
+ * Buffers are device memory, 16-byte aligned, owned by the caller.  The
+ * caller times the launch with events on `stream`.  LV_EINVAL for bad
+ * arguments (nothing is launched). */
+#define LV_STREAM_RMW 0
+#define LV_STREAM_COPY 1
+#define LV_STREAM_READ 2
+#define LV_STREAM_WRITE 3
+lv_status lv_stream_probe(int kind, void* dst, const void* src, size_t bytes, int blocks, int depth,
+                          int pipelined, void* stream);
+
 /* ---------------------------------------------------------------- models
  *
  * Matrix-power views under the other iterative models of Sec. 3.2 and

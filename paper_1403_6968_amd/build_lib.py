@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "liblinview.so")
 
 SOURCES = ["lv_api.hip", "lv_level.hip", "lv_fused.hip", "lv_skinny.hip", "lv_gemm.hip", "lv_probe.hip",
            "lv_batch.hip", "lv_server.hip", "lv_general.hip",
-           "lv_chain.hip", "lv_ols.hip", "lv_glin.hip"]
+           "lv_chain.hip", "lv_ols.hip", "lv_glin.hip", "lv_stream.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

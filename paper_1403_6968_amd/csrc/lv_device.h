@@ -26,6 +26,17 @@ template <typename T> __device__ __forceinline__ void st16_nt(T* p, const V16<T>
   __builtin_nontemporal_store(__builtin_bit_cast(u32x4, x), reinterpret_cast<u32x4*>(p));
 }
 
+// Value of x in lane l (l uniform), broadcast to the whole wave.
+template <typename T> __device__ __forceinline__ T lane_bcast(T x, int l) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
+  } else {
+    static_assert(sizeof(T) == 8, "32- or 64-bit values");
+    const int2 h = __builtin_bit_cast(int2, x);
+    return __builtin_bit_cast(T, make_int2(__builtin_amdgcn_readlane(h.x, l), __builtin_amdgcn_readlane(h.y, l)));
+  }
+}
+
 __device__ __forceinline__ int wave_id() {
   return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }

@@ -28,10 +28,14 @@ namespace {
 
 // ---------------------------------------------------------------- fused pass
 //
-// Block: 256 threads (4 waves).  Tile: tile_rows x TC, TC = 64 lanes x 16 B.
-// The tile's rows are cut into blocks of RB rows; wave w owns blocks
-// w, w + 4, w + 8, ... and processes each one end to end with no block-wide
-// synchronisation:
+// Block: 256 threads (4 waves).  Columns: TC = 64 lanes x 16 B.  Rows: the
+// matrix is cut into blocks of RB rows, and the ns = ceil(n_pad / tile_rows)
+// row slices of a column tile interleave: slice s owns the row blocks
+// b = s, s + ns, s + 2 ns, ... (about tile_rows rows in all), and its wave w
+// the i-th of them for i = w, w + 4, w + 8, ...  At any moment the grid thus
+// streams one contiguous band of rows rather than ns bands a tile apart,
+// which the HBM serves at a markedly higher rate.  Each wave processes its
+// blocks end to end with no block-wide synchronisation:
 //   Phase A  one 16-byte vector per lane per row: Y partial (yacc, the
 //            lane's own columns, V_j rows broadcast through the scalar unit),
 //            the old values to the wave's private LDS block, and
@@ -87,11 +91,44 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
   const int lane = tid & 63;
   const int wave = wave_id();
   const int col0 = ct * TC;
-  const int row0 = rt * tile_rows;
-  const int nrows = min(tile_rows, n_pad - row0);
-  const int nblocks = nrows / RB;
+  const int ns = (n_pad + tile_rows - 1) / tile_rows;   // row slices
+  const int nb_all = n_pad / RB;
+  const int nblocks = (nb_all - rt + ns - 1) / ns;      // row blocks of slice rt
+  // first row of the slice's i-th row block
+  auto blk_row = [&](int i) -> int64_t { return (int64_t)(rt + ns * i) * RB; };
   const int lc = col0 + lane * EPL;
   T* myP = tileP + wave * RB * LDSW;
+  const T* __restrict__ Yop = SP ? Vy : Vj;
+
+  // The block's factor rows (Y operand and, with the update, U_j): entry
+  // e = t R + c of the RB x R block sits in lane e % 64 of fy[e / 64] (fu),
+  // fetched with one gathered vector load per 64 entries together with the
+  // block's rows of P, and broadcast row by row with readlane (no scalar
+  // load, and so no scalar-cache round trip, on the row loop).  PD blocks
+  // beyond the current one are in flight while it is processed (slots
+  // 1..PD); the first ones are requested before the tile's operands are
+  // staged.
+  constexpr int FN = (RB * R + 63) / 64;
+  constexpr int PD = fused_prefetch(R);
+  V16<T> pb[PD + 1][RB];
+  T fyb[PD + 1][FN], fub[PD + 1][UPD ? FN : 1];
+  auto load_block = [&](int slot, int64_t r0) {
+#pragma unroll
+    for (int t = 0; t < RB; ++t) pb[slot][t] = ld16_nt(P + (r0 + t) * ldp + lc);
+#pragma unroll
+    for (int f = 0; f < FN; ++f) {
+      const int e = lane + 64 * f;
+      const int64_t o = (r0 + (e < RB * R ? e / R : 0)) * W + (e < RB * R ? e % R : 0);
+      fyb[slot][f] = Yop[o];
+      if constexpr (UPD) fub[slot][f] = Uj[o];
+    }
+  };
+#pragma unroll
+  for (int d = 0; d < (PD > 0 ? PD : 1); ++d)
+    if (wave + 4 * d < nblocks) load_block(d, blk_row(wave + 4 * d));
+  V16<T>* p = pb[0];
+  T* fy = fyb[0];
+  T* fu = fub[0];
 
   // X operand rows of the tile's columns, slice-padded: (col, c) -> col*XR + (col/QW)*UPAD + c;
   // for MFX transposed, (col, c) -> c*UTW + col, columns XR..15 zero.
@@ -111,8 +148,6 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
           c < R ? Uj[g + c] : c < R + XE ? Ux[g + c - R] : Ud[(int64_t)(col0 + col) * Wd + c - R - XE];
     }
   }
-  const T* __restrict__ Yop = SP ? Vy : Vj;
-
   T vcol[EPL][UPD ? R : 1];
   if constexpr (UPD) {
 #pragma unroll
@@ -133,33 +168,27 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
   const int qs = lane / RB;
   const T* urow0 = utile + qs * (QW * XR + UPAD);
 
-  V16<T> p[RB];
-  if (wave < nblocks) {
-    const int64_t r0 = row0 + wave * RB;
-#pragma unroll
-    for (int t = 0; t < RB; ++t) p[t] = ld16_nt(P + (r0 + t) * ldp + lc);
-  }
-
   for (int b = wave; b < nblocks; b += 4) {
-    const int64_t r0 = row0 + b * RB;
+    const int64_t r0 = blk_row(b);
+    if constexpr (PD > 0) {
+      if (b + 4 * PD < nblocks) load_block(PD, blk_row(b + 4 * PD));
+    }
 
 #pragma unroll
     for (int t = 0; t < RB; ++t) {
       const int64_t i = r0 + t;
-      const T* vrow = Yop + i * W;
       T vi[R];
 #pragma unroll
-      for (int c = 0; c < R; ++c) vi[c] = vrow[c];
+      for (int c = 0; c < R; ++c) vi[c] = lane_bcast(fy[(t * R + c) / 64], (t * R + c) % 64);
 #pragma unroll
       for (int q = 0; q < EPL; ++q)
 #pragma unroll
         for (int c = 0; c < R; ++c) yacc[q][c] = fma(p[t].v[q], vi[c], yacc[q][c]);
       if constexpr (!SP) st16(myP + t * LDSW + lane * EPL, p[t]);
       if constexpr (UPD) {
-        const T* urow = Uj + i * W;
         T ui[R];
 #pragma unroll
-        for (int c = 0; c < R; ++c) ui[c] = urow[c];
+        for (int c = 0; c < R; ++c) ui[c] = lane_bcast(fu[(t * R + c) / 64], (t * R + c) % 64);
 #pragma unroll
         for (int q = 0; q < EPL; ++q) {
           T d = ui[0] * vcol[q][0];
@@ -170,10 +199,21 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
         st16_nt(P + i * ldp + lc, p[t]);
       }
     }
-    if (b + 4 < nblocks) {
-      const int64_t rn = r0 + 4 * RB;
+    // the next block moves into slot 0 (register moves; with PD = 0 it is
+    // requested only now, while X of this block is formed)
+    if constexpr (PD == 0) {
+      if (b + 4 < nblocks) load_block(0, blk_row(b + 4));
+    } else {
 #pragma unroll
-      for (int t = 0; t < RB; ++t) p[t] = ld16_nt(P + (rn + t) * ldp + lc);
+      for (int d = 0; d < PD; ++d) {
+#pragma unroll
+        for (int t = 0; t < RB; ++t) pb[d][t] = pb[d + 1][t];
+#pragma unroll
+        for (int f = 0; f < FN; ++f) {
+          fyb[d][f] = fyb[d + 1][f];
+          if constexpr (UPD) fub[d][f] = fub[d + 1][f];
+        }
+      }
     }
     if constexpr (SP) continue;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -280,34 +320,42 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
     }
   }
 
-  // Partial Gram V_j^T U_j over this tile's rows (double accumulation):
-  // thread (pair, group) sums every G-th row of the tile for one (a, b), the
-  // groups are then added in a fixed order.
-  if (UPD && !SP && ct == 0) {
+  // Partial Gram V_j^T U_j over this slice's rows (double accumulation).
+  // The R^2 pairs are spread over the column tiles (pair p on column tile
+  // p mod nct), so no block carries much more work than the others; for
+  // the pairs of its tile, thread (pair, group) sums every G-th row of the
+  // slice (counted in slice order) and the groups are then added in a fixed
+  // order.
+  if constexpr (UPD && !SP) {
     constexpr int NP = R * R;
-    constexpr int G = NP >= 256 ? 1 : 256 / NP;
+    const int nct = n_pad / TC;
+    const int npb = ct < NP ? (NP - ct + nct - 1) / nct : 0;   // pairs of this tile
     double* gbuf = reinterpret_cast<double*>(tileP);
-    __syncthreads();
-    for (int base = 0; base < NP; base += 256) {
-      const int pair = base + (tid % (NP < 256 ? NP : 256));
-      const int grp = tid / (NP < 256 ? NP : 256);
+    const int nsr = nblocks * RB;   // rows of the slice
+    for (int base = 0; base < npb; base += 256) {
+      const int cnt = npb - base < 256 ? npb - base : 256;
+      const int G = 256 / cnt;
+      const int pi = tid % cnt, grp = tid / cnt;
+      const int pair = ct + nct * (base + pi);
+      __syncthreads();
       double g = 0.0;
-      if (grp < G && pair < NP) {
+      if (grp < G) {
         const int a = pair / R, bb = pair % R;
         const T* vp = Vj + a;
         const T* up = Uj + bb;
 #pragma unroll 8
-        for (int i = row0 + grp; i < row0 + nrows; i += G)
-          g = fma((double)vp[(int64_t)i * W], (double)up[(int64_t)i * W], g);
+        for (int q = grp; q < nsr; q += G) {
+          const int64_t i = blk_row(q / RB) + q % RB;
+          g = fma((double)vp[i * W], (double)up[i * W], g);
+        }
       }
       gbuf[tid] = g;
       __syncthreads();
-      if (tid < (NP - base < 256 ? NP - base : 256)) {
-        double s = 0.0;
-        for (int q = 0; q < G; ++q) s += gbuf[q * (NP < 256 ? NP : 256) + tid];
-        partG[(int64_t)rt * NP + base + tid] = s;
+      if (tid < cnt) {
+        double sum = 0.0;
+        for (int q = 0; q < G; ++q) sum += gbuf[q * cnt + tid];
+        partG[(int64_t)rt * NP + pair] = sum;
       }
-      __syncthreads();
     }
   }
 }
@@ -360,9 +408,7 @@ template <typename T, int R>
 hipError_t fused_r(T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* Uj, const T* Vj,
                    int W, T* partX, T* partY, double* partG, hipStream_t s) {
   if constexpr (R <= kMaxFusedRank) {
-    // 16-row blocks keep more rows in flight per wave; at R >= 8 the factor
-    // registers make 8-row blocks (more resident waves) faster.
-    constexpr int RB = R >= 8 ? 8 : 16;
+    constexpr int RB = fused_row_block(R);
     return fused_launch<T, R, RB, true>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, R, s);
   } else {
     constexpr int RC = kMaxFusedRank;
@@ -395,7 +441,7 @@ hipError_t launch_level_fused(int R, T* P, int64_t ldp, int64_t n_pad, int tile_
 // and the update are bit-identical to it.
 template <typename T, int R, int XE>
 hipError_t fused_x_launch(int xd, const FusedDesc<T>& d, dim3 grid, hipStream_t s) {
-  constexpr int RB = R >= 8 ? 8 : 16;
+  constexpr int RB = fused_row_block(R);
   switch (xd) {
 #define LV_FUSED_X_CASE(XD)                                                                   \
     case XD:                                                                                  \
@@ -464,11 +510,11 @@ hipError_t launch_fused_multi(int R, bool chunk, const FusedDesc<T>* ds, int nd,
     return hipGetLastError();
   }
   switch (R) {
-    case 1: hipLaunchKernelGGL((k_level_fused_multi<T, 1, 16, true>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
-    case 2: hipLaunchKernelGGL((k_level_fused_multi<T, 2, 16, true>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
-    case 4: hipLaunchKernelGGL((k_level_fused_multi<T, 4, 16, true>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
-    case 8: hipLaunchKernelGGL((k_level_fused_multi<T, 8, 8, true>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
-    case 16: hipLaunchKernelGGL((k_level_fused_multi<T, 16, 8, true>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
+    case 1: hipLaunchKernelGGL((k_level_fused_multi<T, 1, fused_row_block(1), true>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
+    case 2: hipLaunchKernelGGL((k_level_fused_multi<T, 2, fused_row_block(2), true>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
+    case 4: hipLaunchKernelGGL((k_level_fused_multi<T, 4, fused_row_block(4), true>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
+    case 8: hipLaunchKernelGGL((k_level_fused_multi<T, 8, fused_row_block(8), true>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
+    case 16: hipLaunchKernelGGL((k_level_fused_multi<T, 16, fused_row_block(16), true>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -482,10 +528,10 @@ hipError_t launch_level_readonly(int R, const T* P, int64_t ldp, int64_t n_pad, 
                                  const T* Vop, int W, T* partX, T* partY, hipStream_t s) {
   T* Pm = const_cast<T*>(P);   // not written: UPD = false
   switch (R) {
-    case 1: return fused_launch<T, 1, 16, false>(Pm, ldp, n_pad, tile_rows, Uop, Vop, W, partX, partY, nullptr, R, s);
-    case 2: return fused_launch<T, 2, 16, false>(Pm, ldp, n_pad, tile_rows, Uop, Vop, W, partX, partY, nullptr, R, s);
-    case 4: return fused_launch<T, 4, 16, false>(Pm, ldp, n_pad, tile_rows, Uop, Vop, W, partX, partY, nullptr, R, s);
-    case 8: return fused_launch<T, 8, 8, false>(Pm, ldp, n_pad, tile_rows, Uop, Vop, W, partX, partY, nullptr, R, s);
+    case 1: return fused_launch<T, 1, fused_row_block(1), false>(Pm, ldp, n_pad, tile_rows, Uop, Vop, W, partX, partY, nullptr, R, s);
+    case 2: return fused_launch<T, 2, fused_row_block(2), false>(Pm, ldp, n_pad, tile_rows, Uop, Vop, W, partX, partY, nullptr, R, s);
+    case 4: return fused_launch<T, 4, fused_row_block(4), false>(Pm, ldp, n_pad, tile_rows, Uop, Vop, W, partX, partY, nullptr, R, s);
+    case 8: return fused_launch<T, 8, fused_row_block(8), false>(Pm, ldp, n_pad, tile_rows, Uop, Vop, W, partX, partY, nullptr, R, s);
     default: break;
   }
   if (R % kMaxFusedRank != 0 || R > 128) return hipErrorInvalidValue;

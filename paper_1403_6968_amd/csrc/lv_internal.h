@@ -17,6 +17,11 @@ constexpr int kPadOrder = 256;
 // Largest level rank handled by the register-resident fused pass; larger
 // ranks run the skinny products in chunks of this many factor columns.
 constexpr int kMaxFusedRank = 16;
+// Rows per block of the fused level pass for level rank R: a wave streams
+// RB rows of its 16-byte column group per step.
+constexpr int fused_row_block(int R) { return R >= 8 ? 8 : 4; }
+// Row blocks of the fused pass in flight beyond the one being processed.
+constexpr int fused_prefetch(int R) { return R >= 8 ? 0 : 1; }
 // Largest level of the exponential model (k <= 2^kMaxLevel).
 constexpr int kMaxLevel = 10;
 
@@ -90,6 +95,19 @@ constexpr int kMfmaUpdateRank = 32;
 constexpr int kMfmaUpdateTile = 128;
 inline bool update_on_mfma(int R, int elem) { return elem == 4 && R >= kMfmaUpdateRank; }
 inline int update_tile_rows(int R, int elem) { return update_on_mfma(R, elem) ? kMfmaUpdateTile : kUpdateTileRows; }
+// Work-groups a single-view streaming pass aims for, and the rows per
+// (interleaved) slice of the vector update pass that give about that many
+// for one view of padded order n_pad (several views in one launch keep
+// update_tile_rows).
+constexpr int kStreamBlocks = 512;
+inline int update_slice_rows(int R, int elem, int64_t n_pad) {
+  if (update_on_mfma(R, elem)) return kMfmaUpdateTile;
+  const int64_t nct = n_pad / tile_cols_bytes(elem);
+  int64_t ns = kStreamBlocks / (nct > 0 ? nct : 1);
+  const int64_t ns_max = n_pad / (4 * 8);   // at least one 8-row block per wave
+  ns = ns < 1 ? 1 : ns > ns_max ? ns_max : ns;
+  return (int)((n_pad + ns - 1) / ns);
+}
 inline int update_tile_cols(int R, int elem) { return update_on_mfma(R, elem) ? kMfmaUpdateTile : tile_cols_bytes(elem); }
 // Rows per partial of the stand-alone Gram kernel, and its partial count.
 constexpr int kGramRows = 64;

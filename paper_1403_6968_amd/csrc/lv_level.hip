@@ -272,10 +272,14 @@ k_add(T* __restrict__ dst, const T* __restrict__ src, int64_t count, const int* 
 }
 
 // ---------------------------------------------------------------- update only
-// P += U_j V_j^T.  Lane holds a 16-byte column group; the wave walks batches
-// of 8 rows with U_j rows broadcast through the scalar unit; ranks above 16
-// are processed in groups of 16 columns of the factors.  SH (float only):
-// the new values are also written to the bfloat16 shadow S (same ld).
+// P += U_j V_j^T.  Lane holds a 16-byte column group (its V_j rows stay in
+// registers); the wave walks blocks of 8 rows in the interleaved row slices
+// of the fused pass, with the next block's rows of P and U_j requested
+// before the current block is updated.  The block's U_j entries come with
+// one gathered vector load per 64 entries and are broadcast by readlane.
+// Ranks above 16 are processed in groups of 16 columns of the factors.
+// SH (float only): the new values are also written to the bfloat16 shadow S
+// (same ld).
 template <typename T, int R, bool SH>
 __device__ __forceinline__ void update_body(T* __restrict__ P, const int64_t ldp, const int n_pad,
                                             const int tile_rows, const T* __restrict__ Uj,
@@ -286,50 +290,95 @@ __device__ __forceinline__ void update_body(T* __restrict__ P, const int64_t ldp
   constexpr int RG = R < 16 ? R : 16;
   constexpr int NG = R / RG;
   constexpr int RB = 8;
+  // U_j entries per lane per block (one factor group; several groups, double
+  // storage at ranks above 16, read U_j rows through the scalar unit)
+  constexpr int FN = NG == 1 ? (RB * R + 63) / 64 : 1;
   const int lane = threadIdx.x & 63;
   const int wave = wave_id();
   const int col0 = ct * TC;
-  const int row0 = rt * tile_rows;
-  const int nrows = min(tile_rows, n_pad - row0);
   const int lc = col0 + lane * EPL;
+  // interleaved row slices (as the fused pass): slice rt of ns owns the row
+  // blocks rt, rt + ns, rt + 2 ns, ...; wave w every fourth of them from w
+  const int ns = (n_pad + tile_rows - 1) / tile_rows;
+  const int nb_all = n_pad / RB;
 
-  for (int rb = wave * RB; rb < nrows; rb += 4 * RB) {
-    V16<T> p[RB];
+  V16<T> p[RB], pn[RB];
+  T fu[FN], fun[FN];
+  auto load = [&](int b, V16<T>* pp, T* ff) {
+    const int64_t r0 = (int64_t)b * RB;
 #pragma unroll
-    for (int t = 0; t < RB; ++t) p[t] = ld16_nt(P + (int64_t)(row0 + rb + t) * ldp + lc);
+    for (int t = 0; t < RB; ++t) pp[t] = ld16_nt(P + (r0 + t) * ldp + lc);
+    if constexpr (NG == 1) {
+#pragma unroll
+      for (int f = 0; f < FN; ++f) {
+        const int e = lane + 64 * f;
+        ff[f] = e < RB * R ? Uj[(r0 + e / R) * W + e % R] : T(0);
+      }
+    }
+  };
+  T vcol[EPL][NG == 1 ? RG : 1];
+  if constexpr (NG == 1) {
+#pragma unroll
+    for (int q = 0; q < EPL; ++q)
+#pragma unroll
+      for (int c = 0; c < RG; ++c) vcol[q][c] = Vj[(int64_t)(lc + q) * W + c];
+  }
+
+  int b = rt + ns * wave;
+  if (b < nb_all) load(b, p, fu);
+  for (; b < nb_all; b += 4 * ns) {
+    const int64_t r0 = (int64_t)b * RB;
+    if (b + 4 * ns < nb_all) load(b + 4 * ns, pn, fun);
     T d[RB][EPL];
 #pragma unroll
     for (int t = 0; t < RB; ++t)
 #pragma unroll
       for (int q = 0; q < EPL; ++q) d[t][q] = T(0);
-    for (int g = 0; g < NG; ++g) {
-      T vcol[EPL][RG];
-#pragma unroll
-      for (int q = 0; q < EPL; ++q)
-#pragma unroll
-        for (int c = 0; c < RG; ++c) vcol[q][c] = Vj[(int64_t)(lc + q) * W + g * RG + c];
+    if constexpr (NG == 1) {
 #pragma unroll
       for (int t = 0; t < RB; ++t) {
-        const T* urow = Uj + (int64_t)(row0 + rb + t) * W + g * RG;
+        T u[RG];
+#pragma unroll
+        for (int c = 0; c < RG; ++c) u[c] = lane_bcast(fu[(t * R + c) / 64], (t * R + c) % 64);
 #pragma unroll
         for (int q = 0; q < EPL; ++q)
 #pragma unroll
-          for (int c = 0; c < RG; ++c) d[t][q] = fma(urow[c], vcol[q][c], d[t][q]);
+          for (int c = 0; c < RG; ++c) d[t][q] = fma(u[c], vcol[q][c], d[t][q]);
+      }
+    } else {
+      for (int g = 0; g < NG; ++g) {
+        T vg[EPL][RG];
+#pragma unroll
+        for (int q = 0; q < EPL; ++q)
+#pragma unroll
+          for (int c = 0; c < RG; ++c) vg[q][c] = Vj[(int64_t)(lc + q) * W + g * RG + c];
+#pragma unroll
+        for (int t = 0; t < RB; ++t) {
+          const T* urow = Uj + (r0 + t) * W + g * RG;
+#pragma unroll
+          for (int q = 0; q < EPL; ++q)
+#pragma unroll
+            for (int c = 0; c < RG; ++c) d[t][q] = fma(urow[c], vg[q][c], d[t][q]);
+        }
       }
     }
 #pragma unroll
     for (int t = 0; t < RB; ++t) {
 #pragma unroll
       for (int q = 0; q < EPL; ++q) p[t].v[q] += d[t][q];
-      st16_nt(P + (int64_t)(row0 + rb + t) * ldp + lc, p[t]);
+      st16_nt(P + (r0 + t) * ldp + lc, p[t]);
       if constexpr (SH) {
         static_assert(EPL == 4, "shadows are kept for float storage only");
         ushort4 sh;
         sh.x = bf16_rne(p[t].v[0]); sh.y = bf16_rne(p[t].v[1]);
         sh.z = bf16_rne(p[t].v[2]); sh.w = bf16_rne(p[t].v[3]);
-        *reinterpret_cast<ushort4*>(S + (int64_t)(row0 + rb + t) * ldp + lc) = sh;
+        *reinterpret_cast<ushort4*>(S + (r0 + t) * ldp + lc) = sh;
       }
     }
+#pragma unroll
+    for (int t = 0; t < RB; ++t) p[t] = pn[t];
+#pragma unroll
+    for (int f = 0; f < FN; ++f) fu[f] = fun[f];
   }
 }
 
@@ -597,7 +646,7 @@ __global__ void __launch_bounds__(256) k_prep_multi(const PrepDesc<T>* __restric
 template <typename T, int R>
 hipError_t update_r(T* P, int64_t ldp, int64_t n_pad, const T* Uj, const T* Vj, int W,
                     hipStream_t s, uint16_t* S, bool split) {
-  const int tile_rows = update_tile_rows(R, (int)sizeof(T));
+  const int tile_rows = update_slice_rows(R, (int)sizeof(T), n_pad);
   const int nct = (int)(n_pad / update_tile_cols(R, (int)sizeof(T)));
   const UpdateDesc<T> d{P, ldp, (int)n_pad, tile_rows, Uj, Vj, W, nct, 0, S};
   const dim3 grid((unsigned)nct, (unsigned)((n_pad + tile_rows - 1) / tile_rows));

@@ -27,6 +27,7 @@ LV_MODEL_EXP, LV_MODEL_LIN, LV_MODEL_SKIP = 0, 1, 2
 LV_OLS_BETA, LV_OLS_INVERSE, LV_OLS_X = 0, 1, 2
 LV_GENERAL_HYBRID, LV_GENERAL_FACTORED = 0, 1
 LV_GLIN_REEVAL, LV_GLIN_HYBRID, LV_GLIN_INCR = 0, 1, 2
+LV_STREAM_RMW, LV_STREAM_COPY, LV_STREAM_READ, LV_STREAM_WRITE = 0, 1, 2, 3
 
 _MODE_DTYPE = {LV_FP64: torch.float64, LV_FP32: torch.float32, LV_FP32_BF16SHADOW: torch.float32}
 
@@ -46,6 +47,7 @@ EXPORTED = (
     "lv_ols_read", "lv_ols_info", "lv_ols_destroy",
     "lv_glin_footprint", "lv_glin_create", "lv_glin_update", "lv_glin_read", "lv_glin_destroy",
     "lv_server_poll", "lv_server_drain", "lv_server_stats", "lv_server_destroy",
+    "lv_stream_probe",
 )
 
 
@@ -161,6 +163,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "lv_glin_update": (I32, [P, P, P, I64, I64, I64, P]),
         "lv_glin_read": (I32, [P, I32, P, I64, P]),
         "lv_glin_destroy": (None, [P]),
+        "lv_stream_probe": (I32, [I32, P, P, SZ, I32, I32, I32, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -344,6 +347,22 @@ def lv_view_timing(view) -> dict:
 
 def lv_view_destroy(view) -> None:
     load().lv_view_destroy(view)
+
+
+def lv_stream_probe(kind: int, dst: torch.Tensor, src, nbytes: int, blocks: int, depth: int,
+                    pipelined: bool = False, stream=None) -> None:
+    """One launch of the streaming-ceiling kernel over nbytes of dst (and
+    src); the caller times it with events on the stream."""
+    if dst.device.type != "cuda" or (src is not None and src.device.type != "cuda"):
+        raise TypeError("dst and src must be device tensors")
+    if nbytes > dst.numel() * dst.element_size() and kind != LV_STREAM_READ:
+        raise ValueError("dst is smaller than nbytes")
+    if src is not None and nbytes > src.numel() * src.element_size():
+        raise ValueError("src is smaller than nbytes")
+    if kind == LV_STREAM_READ and dst.numel() * dst.element_size() < blocks * 1024:
+        raise ValueError("READ needs blocks * 1024 bytes of dst")
+    _check(load().lv_stream_probe(kind, dst.data_ptr(), None if src is None else src.data_ptr(), nbytes, blocks,
+                                  depth, int(bool(pipelined)), _stream(stream, dst.device)))
 
 
 def lv_reeval_footprint(n: int, r_max: int, mode: int) -> int:
