@@ -80,9 +80,10 @@ __device__ __forceinline__ void skinny_body(const uint16_t* __restrict__ S, cons
   const int srow = tid / 32, sgrp = tid % 32;
 
   constexpr int VPT = RP * CRB / 256;   // V_j values staged per thread and chunk
-  // NB = 1: two chunks in flight, buffers A and B alternating (a tile has an
-  // even number of chunks: tile_rows and n_pad are multiples of 2 CRB);
-  // larger NB: one chunk (the accumulators need the registers)
+  // NB = 1: two chunks in flight, buffers A and B alternating (a tile may
+  // have an odd number of chunks: tile_rows is any multiple of 64 and the
+  // last tile may be ragged, so the second chunk of a pair and its fetch are
+  // guarded); larger NB: one chunk (the accumulators need the registers)
   constexpr int DEPTH = NB == 1 ? 2 : 1;
   u16x8 preA[CRB / 8], preB[CRB / 8];
   float pvA[VPT], pvB[VPT];
@@ -99,7 +100,9 @@ __device__ __forceinline__ void skinny_body(const uint16_t* __restrict__ S, cons
     }
   };
   fetch(preA, pvA, row0);
-  if constexpr (DEPTH == 2) fetch(preB, pvB, row0 + CRB);
+  if constexpr (DEPTH == 2) {
+    if (row0 + CRB < rend) fetch(preB, pvB, row0 + CRB);
+  }
 
   // U_j rows of the tile's columns, transposed: sUt[c][k] = U_j[col0 + k][c]
   for (int idx = tid; idx < RP * TCB; idx += 256) {
@@ -168,7 +171,7 @@ __device__ __forceinline__ void skinny_body(const uint16_t* __restrict__ S, cons
   if constexpr (DEPTH == 2) {
     for (int cr0 = row0; cr0 < rend; cr0 += 2 * CRB) {
       chunk(preA, pvA, cr0);
-      chunk(preB, pvB, cr0 + CRB);
+      if (cr0 + CRB < rend) chunk(preB, pvB, cr0 + CRB);
     }
   } else {
     for (int cr0 = row0; cr0 < rend; cr0 += CRB) chunk(preA, pvA, cr0);

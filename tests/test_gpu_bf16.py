@@ -55,7 +55,7 @@ def _edges(n, r, count, cur, g):
     return out
 
 
-def _exact_case(A, k, r, updates):
+def _exact_case(A, k, r, updates, tiles=None):
     lv = _lv()
     import torch
     n = A.shape[0]
@@ -69,11 +69,13 @@ def _exact_case(A, k, r, updates):
     assert big < 256, "precondition: shadowed powers and factors exact in bfloat16"
     assert np.abs(P[k]).max() < 2 ** 24
     view = lv.View(dev(A, torch.float32), k, r_max=r, mode=lv.LV_FP32_BF16SHADOW)
+    if tiles is not None:
+        view.set_tile_rows([tiles] * (len(view.powers()) - 1))
     for U, V in updates:
         view.update(dev(U, torch.float32), dev(V, torch.float32))
     got = read_all(view)
     for i in P:
-        np.testing.assert_array_equal(got[i], P[i], err_msg=f"P_{i}")
+        np.testing.assert_array_equal(got[i], P[i], err_msg=f"P_{i} (tile rows {tiles})")
     note(f"exact: n={n} k={k} r={r}: max entry {max(np.abs(P[i]).max() for i in P):.0f}, "
          f"nonzeros of P_k {int((P[k] != 0).sum())}")
     view.close()
@@ -103,6 +105,46 @@ def test_integer_permutation_high_rank_exact(n, k, r):
     A[np.arange(n), g.permutation(n)] = 1.0
     cur = A.copy()
     _exact_case(A, k, r, _edges(n, r, 2, cur, g))
+
+
+# Tile heights whose tiles hold an odd number of 64-row chunks (320, 448,
+# 576) or end in a ragged tile with an odd count (n = 1300 pads to 1536:
+# 1536 = 3 x 448 + 192).  The skinny pass from the shadow pairs chunks at
+# level ranks up to 32; an unguarded second chunk would re-add stale rows
+# into Y and write X rows beyond the tile, which the exact integer counts
+# expose.
+@pytest.mark.parametrize("tiles", [320, 448, 576, 960])
+def test_odd_chunk_tiles_exact(tiles):
+    n, k, r = 1300, 16, 2
+    g = synth.rng(8, 0, 80, tiles)
+    A = np.zeros((n, n))
+    A[np.arange(n), g.permutation(n)] = 1.0
+    cur = A.copy()
+    _exact_case(A, k, r, _edges(n, r, 3, cur, g), tiles=tiles)
+
+
+@pytest.mark.parametrize("tiles", [320, 448])
+def test_odd_chunk_tiles_random(tiles):
+    lv = _lv()
+    import torch
+    n, k, r, T = 1300, 16, 4, 6
+    A64 = synth.gaussian_matrix(n, seed=44, config=3)
+    Us, Vs = synth.update_factors(n, r, T, seed=44, config=3)
+    A, Us, Vs = storage_inputs(A64, Us, Vs, np.float32)
+    view = lv.View(dev(A, torch.float32), k, r_max=r, mode=lv.LV_FP32_BF16SHADOW)
+    view.set_tile_rows([tiles] * 4)
+    base = read_all(view)
+    P0 = O.reeval(A, k)
+    P = P0
+    for t in range(T):
+        P = O.incr_update(P, Us[t], Vs[t])
+        view.update(dev(Us[t], torch.float32), dev(Vs[t], torch.float32))
+    got = read_all(view)
+    view.close()
+    for i in P:
+        mr, dr = O.maxrel(got[i], P[i]), O.deltarel(got[i], base[i], P[i], P0[i])
+        note(f"tiles {tiles} P{i}: maxrel {mr:.2e} deltarel {dr:.2e}")
+        assert mr < 5e-3 and dr < 5e-2, f"P_{i}"
 
 
 # (n, k, r): ragged orders; level ranks from 1 to 128 on shadowed levels
