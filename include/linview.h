@@ -421,6 +421,39 @@ lv_status lv_reeval(const void* A, int64_t n, int64_t lda, int k,
                     lv_mode mode, void* out, int64_t ldo,
                     void* workspace, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- allocation-free update
+ *
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one
+ * update Delta A = U V^T of stored powers the caller holds, exactly as
+ * lv_view_update applies it to a view of the same order, power, mode and
+ * rank with the default tile rows (the same kernels, so equal results bit
+ * for bit).  The factor slabs and reduction partials live in a static
+ * device array of the library (64 MiB per GPU, held until the process
+ * ends); the call allocates nothing.  A shape needs 2 n W e bytes of
+ * factor slabs (W = k r_pad, r_pad = r rounded up to a power of two, e the
+ * element size) and, for each level j < m with rank R = 2^j r_pad, partials
+ * of n R e (nct + n / 256) bytes (nct = n / 256 column tiles in FP32,
+ * n / 128 in FP64) and 8 R^2 max(n / 256, n / 64) bytes of Gram partials,
+ * each region rounded up to 256 bytes: n = 8192, k = 16, r = 1 in FP32
+ * takes 31 MiB.  Calls on one GPU share that array, so calls that overlap
+ * on one GPU (different streams or host threads) race and must be
+ * serialised by the caller.
+ *  powers   host array of m + 1 device pointers (k = 2^m): powers[j] holds
+ *           A^(2^j), n x n with leading dimension ld, updated in place.
+ *  n        a multiple of 256 (the kernels' padding granule), <= 65536.
+ *  ld       >= n, ld * element size a multiple of 16 bytes; pointers 16-byte
+ *           aligned.
+ *  mode     LV_FP32 or LV_FP64 (element type float or double).
+ *  U, V     n x r (device), ldu, ldv >= r; k * r rounded up to a power of
+ *           two <= 256.
+ * LV_EINVAL for bad arguments; LV_ENOMEM when the scratch the shape needs
+ * exceeds the array.  Nothing is enqueued on failure unless the status is
+ * LV_EDEVICE. */
+lv_status lv_powers_update_noalloc(void* const* powers, int64_t n, int64_t ld, int k, lv_mode mode,
+                                   const void* U, const void* V, int64_t r, int64_t ldu, int64_t ldv,
+                                   void* stream);
+
 /* ---------------------------------------------------------------- streaming ceiling
  *
  * Measured HBM ceiling for the level passes (diagnostics; none of the

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1018,6 +1019,86 @@ lv_status lv_reeval(const void* A, int64_t n, int64_t lda, int k, const void* U,
   return reeval_impl<float>(static_cast<const float*>(A), n, lda, k, static_cast<const float*>(U),
                             static_cast<const float*>(V), (int)r, ldu, ldv, static_cast<float*>(out), ldo, ws,
                             s);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- allocation-free update
+//
+// The factor slabs and per-level partials of lv_powers_update_noalloc live in
+// one file-scope device array, `scratch`.  Each GPU holds its own copy until
+// the process ends; host code never passes the array's name to a kernel but
+// the device address hipGetSymbolAddress returns for the current device,
+// looked up once per device on the first call there.  Every byte of it that
+// a call reads is written earlier in the same call (slab columns by the
+// staging kernel and the tails, partials by the level passes), so nothing
+// needs clearing between calls; calls that overlap on one GPU race.
+namespace {
+
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+__device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+lv_status scratch_of_current_device(char** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_check(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(LV_EDEVICE, "device %d beyond the %d supported", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_check(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return LV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lv_status lv_powers_update_noalloc(void* const* powers, int64_t n, int64_t ld, int k, lv_mode mode, const void* U,
+                                   const void* V, int64_t r, int64_t ldu, int64_t ldv, void* stream) {
+  g_err[0] = 0;
+  if (mode != LV_FP64 && mode != LV_FP32) return fail(LV_EINVAL, "mode must be LV_FP64 or LV_FP32");
+  if (n < kPadOrder || n % kPadOrder != 0 || n > kMaxOrder)
+    return fail(LV_EINVAL, "n = %lld is not a positive multiple of %d up to %lld", (long long)n, kPadOrder,
+                (long long)kMaxOrder);
+  if (r < 1 || r > kMaxWidth) return fail(LV_EINVAL, "rank r = %lld outside [1, %d]", (long long)r, kMaxWidth);
+  lv_status st = check_shape(n, k, (int)r, mode);
+  if (st != LV_OK) return st;
+  const int elem = mode == LV_FP64 ? 8 : 4;
+  if (!powers) return fail(LV_EINVAL, "powers is NULL");
+  if (ld < n || (ld * elem) % 16 != 0) return fail(LV_EINVAL, "ld = %lld is below n or not a multiple of 16 bytes",
+                                                   (long long)ld);
+  const int m = ilog2(k);
+  for (int j = 0; j <= m; ++j)
+    if (!powers[j] || reinterpret_cast<uintptr_t>(powers[j]) % 16 != 0)
+      return fail(LV_EINVAL, "powers[%d] is NULL or not 16-byte aligned", j);
+  if (!U || !V) return fail(LV_EINVAL, "U or V is NULL");
+  if (ldu < r || ldv < r) return fail(LV_EINVAL, "ldu/ldv smaller than r");
+  const Layout L = make_layout(n, k, (int)r, mode, 0, 0, false, 0, true);
+  if (L.total > kNoAllocScratchBytes)
+    return fail(LV_ENOMEM, "n = %lld, k = %d, r = %lld needs %zu bytes of scratch; the static array holds %zu",
+                (long long)n, k, (long long)r, L.total, kNoAllocScratchBytes);
+  char* base = nullptr;
+  st = scratch_of_current_device(&base);
+  if (st != LV_OK) return st;
+  // a transient view over the caller's powers and the scratch (host only)
+  lv_view v;
+  v.n = n; v.k = k; v.r_max = (int)r; v.mode = mode; v.L = L; v.L.ldp = ld;
+  v.base = base; v.ws_bytes = kNoAllocScratchBytes; v.updates = 0; v.reanchors = 0;
+  for (int j = 0; j < kMaxLevel; ++j) v.tile_rows[j] = L.tile_rows;
+  for (int j = 0; j <= m; ++j) v.pext[j] = static_cast<char*>(powers[j]);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return mode == LV_FP64
+             ? update_one<double>(&v, static_cast<const double*>(U), static_cast<const double*>(V), (int)r, ldu, ldv, s)
+             : update_one<float>(&v, static_cast<const float*>(U), static_cast<const float*>(V), (int)r, ldu, ldv, s);
 }
 
 }  // extern "C"

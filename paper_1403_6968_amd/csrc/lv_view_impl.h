@@ -97,8 +97,12 @@ constexpr int kMaxGeneralColsF = 4096;  // p with factored deltas (padded to a m
 constexpr int kMaxGeneralWidthF = 128;  // k * r_pad with factored deltas
 constexpr int kAtbRows = 64;          // rows per FP64 partial of V^T T and W^T B
 
+// ext_powers: the stored powers live outside the workspace (the caller's
+// buffers); the layout then holds only the factor slabs and the per-level
+// partials of an update (the regions a plain update of a FP32 or FP64 view
+// touches) and starts with them at offset 0.
 inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode, int flags = 0, int p = 0,
-                          bool factored = false, int kT = 0) {
+                          bool factored = false, int kT = 0, bool ext_powers = false) {
   lv::Layout L;
   L.general = p > 0;
   L.gfac = L.general && factored;
@@ -116,7 +120,8 @@ inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode, int flags =
   L.nrt_max = (int)((L.n_pad + kMinTileRows - 1) / kMinTileRows);   // partials sized for the smallest tiles
   size_t off = 0;
   const size_t mat = (size_t)L.n_pad * L.ldp * L.elem;
-  for (int j = 0; j <= L.m; ++j) { L.P[j] = off; off = align_up(off + mat); }
+  if (!ext_powers)
+    for (int j = 0; j <= L.m; ++j) { L.P[j] = off; off = align_up(off + mat); }
   const size_t slab = (size_t)L.n_pad * L.W * L.elem;
   L.slabU = off; off = align_up(off + slab);
   L.slabV = off; off = align_up(off + slab);
@@ -126,6 +131,10 @@ inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode, int flags =
     L.partY[j] = off; off = align_up(off + (size_t)L.nrt_max * L.n_pad * R * L.elem);
     const size_t ng = (size_t)(gram_tiles(L.n_pad) > L.nrt_max ? gram_tiles(L.n_pad) : L.nrt_max);
     L.partG[j] = off; off = align_up(off + ng * R * R * sizeof(double));
+  }
+  if (ext_powers) {
+    L.total = off;
+    return L;
   }
   if (mode == LV_FP32_BF16SHADOW)
     for (int j = 0; j < L.m; ++j) { L.shadow[j] = off; off = align_up(off + (size_t)L.n_pad * L.ldp * 2); }
@@ -234,7 +243,10 @@ struct lv_view {
   std::vector<Pair> pending;
   std::vector<hipEvent_t> pool;
 
-  template <typename T> T* P(int j) const { return reinterpret_cast<T*>(base + L.P[j]); }
+  // stored powers held outside the workspace (set by the allocation-free
+  // update entry point; null for views created on a workspace)
+  char* pext[lv::kMaxLevel + 1] = {};
+  template <typename T> T* P(int j) const { return reinterpret_cast<T*>(pext[j] ? pext[j] : base + L.P[j]); }
   template <typename T> T* slabU() const { return reinterpret_cast<T*>(base + L.slabU); }
   template <typename T> T* slabV() const { return reinterpret_cast<T*>(base + L.slabV); }
   template <typename T> T* partX(int j) const { return reinterpret_cast<T*>(base + L.partX[j]); }

@@ -47,7 +47,7 @@ EXPORTED = (
     "lv_ols_read", "lv_ols_info", "lv_ols_destroy",
     "lv_glin_footprint", "lv_glin_create", "lv_glin_update", "lv_glin_read", "lv_glin_destroy",
     "lv_server_poll", "lv_server_drain", "lv_server_stats", "lv_server_destroy",
-    "lv_stream_probe",
+    "lv_stream_probe", "lv_powers_update_noalloc",
 )
 
 
@@ -164,6 +164,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "lv_glin_read": (I32, [P, I32, P, I64, P]),
         "lv_glin_destroy": (None, [P]),
         "lv_stream_probe": (I32, [I32, P, P, SZ, I32, I32, I32, P]),
+        "lv_powers_update_noalloc": (I32, [c.POINTER(P), I64, I64, I32, I32, P, P, I64, I64, I64, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -363,6 +364,26 @@ def lv_stream_probe(kind: int, dst: torch.Tensor, src, nbytes: int, blocks: int,
         raise ValueError("READ needs blocks * 1024 bytes of dst")
     _check(load().lv_stream_probe(kind, dst.data_ptr(), None if src is None else src.data_ptr(), nbytes, blocks,
                                   depth, int(bool(pipelined)), _stream(stream, dst.device)))
+
+
+def lv_powers_update_noalloc(powers, U: torch.Tensor, V: torch.Tensor, mode: int, stream=None) -> None:
+    """One update of caller-held stored powers (A, A^2, ..., A^k, each n x n
+    with one leading dimension) through the allocation-free entry point."""
+    dtype = _MODE_DTYPE[mode]
+    ptrs, lds = [], set()
+    for i, P in enumerate(powers):
+        p, ld = _mat(P, dtype, f"powers[{i}]")
+        if P.shape[0] != P.shape[1] or P.shape[0] != powers[0].shape[0]:
+            raise ValueError("every stored power must be n x n")
+        ptrs.append(p)
+        lds.add(ld)
+    if len(lds) != 1:
+        raise ValueError("the stored powers must share one leading dimension")
+    u, ldu = _mat(U, dtype, "U")
+    v, ldv = _mat(V, dtype, "V")
+    arr = (ctypes.c_void_p * len(ptrs))(*ptrs)
+    _check(load().lv_powers_update_noalloc(arr, powers[0].shape[0], lds.pop(), 1 << (len(ptrs) - 1), mode, u, v,
+                                           U.shape[1], ldu, ldv, _stream(stream, U.device)))
 
 
 def lv_reeval_footprint(n: int, r_max: int, mode: int) -> int:
