@@ -86,6 +86,12 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
 
   __shared__ __align__(16) T tileP[4 * RB * LDSW];
   __shared__ __align__(16) T utile[SP ? 1 : MFX ? 16 * UTW : TC * XR + NQ * UPAD];
+  // per wave: the current row block's factor entries (Y operand, then U_j),
+  // row-major RB x R each, read back as wave-uniform broadcasts
+  constexpr int FB = RB * R;
+  __shared__ __align__(16) T facs[4][UPD ? 2 : 1][FB];
+  // MFX: a zero row that supplies the A operand of the rows RB..15
+  __shared__ __align__(16) float zrow[MFX ? TC : 1];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -103,8 +109,9 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
   // The block's factor rows (Y operand and, with the update, U_j): entry
   // e = t R + c of the RB x R block sits in lane e % 64 of fy[e / 64] (fu),
   // fetched with one gathered vector load per 64 entries together with the
-  // block's rows of P, and broadcast row by row with readlane (no scalar
-  // load, and so no scalar-cache round trip, on the row loop).  PD blocks
+  // block's rows of P; the wave writes them to its LDS block and reads them
+  // back row by row as broadcasts (no scalar load, and so no scalar-cache
+  // round trip, on the row loop, and no VALU work to broadcast).  PD blocks
   // beyond the current one are in flight while it is processed (slots
   // 1..PD); the first ones are requested before the tile's operands are
   // staged.
@@ -133,6 +140,7 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
   // X operand rows of the tile's columns, slice-padded: (col, c) -> col*XR + (col/QW)*UPAD + c;
   // for MFX transposed, (col, c) -> c*UTW + col, columns XR..15 zero.
   if constexpr (MFX) {
+    for (int idx = tid; idx < TC; idx += 256) zrow[idx] = 0.f;
     for (int idx = tid; idx < TC * 16; idx += 256) {
       const int col = idx / 16, c = idx % 16;
       const int64_t g = (int64_t)(col0 + col) * W;
@@ -168,18 +176,30 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
   const int qs = lane / RB;
   const T* urow0 = utile + qs * (QW * XR + UPAD);
 
+  T* fac_y = facs[wave][0];
+  T* fac_u = facs[wave][UPD ? 1 : 0];
   for (int b = wave; b < nblocks; b += 4) {
     const int64_t r0 = blk_row(b);
+#pragma unroll
+    for (int f = 0; f < FN; ++f) {
+      if (lane + 64 * f < FB) {
+        fac_y[lane + 64 * f] = fy[f];
+        if constexpr (UPD) fac_u[lane + 64 * f] = fu[f];
+      }
+    }
     if constexpr (PD > 0) {
       if (b + 4 * PD < nblocks) load_block(PD, blk_row(b + 4 * PD));
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
 #pragma unroll
     for (int t = 0; t < RB; ++t) {
       const int64_t i = r0 + t;
       T vi[R];
 #pragma unroll
-      for (int c = 0; c < R; ++c) vi[c] = lane_bcast(fy[(t * R + c) / 64], (t * R + c) % 64);
+      for (int c = 0; c < R; ++c) vi[c] = fac_y[t * R + c];
 #pragma unroll
       for (int q = 0; q < EPL; ++q)
 #pragma unroll
@@ -188,7 +208,7 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
       if constexpr (UPD) {
         T ui[R];
 #pragma unroll
-        for (int c = 0; c < R; ++c) ui[c] = lane_bcast(fu[(t * R + c) / 64], (t * R + c) % 64);
+        for (int c = 0; c < R; ++c) ui[c] = fac_u[t * R + c];
 #pragma unroll
         for (int q = 0; q < EPL; ++q) {
           T d = ui[0] * vcol[q][0];
@@ -229,9 +249,8 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
       typedef float v4f __attribute__((ext_vector_type(4)));
       const int l16 = lane % 16, lq = lane / 16;
       v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-      // lanes of rows RB..15 read row 0 (in bounds) and supply zeros
-      const bool live = l16 < RB;
-      const float* arow = reinterpret_cast<const float*>(myP) + (live ? l16 : 0) * LDSW + 4 * lq;
+      // lanes of rows RB..15 read the zero row
+      const float* arow = (l16 < RB ? reinterpret_cast<const float*>(myP) + l16 * LDSW : zrow) + 4 * lq;
       const float* brow = reinterpret_cast<const float*>(utile) + l16 * UTW + 4 * lq;
 #pragma unroll
       for (int j = 0; j < TC / 16; j += 2) {
@@ -241,8 +260,8 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
         const V16<float> b1 = ld16(brow + 16 * j + 16);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(live ? a0.v[e] : 0.f, b0.v[e], acc0, 0, 0, 0);
-          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(live ? a1.v[e] : 0.f, b1.v[e], acc1, 0, 0, 0);
+          acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.v[e], b0.v[e], acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.v[e], b1.v[e], acc1, 0, 0, 0);
         }
       }
       if (lq < RB / 4) {

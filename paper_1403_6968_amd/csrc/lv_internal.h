@@ -136,8 +136,11 @@ inline bool sums_fused(int R, int elem) { return R <= kMaxFusedRank && !skinny_o
 // Work-groups of a tail launch / Gram pairs per work-group for rank R.
 // Level ranks from which the tail works on 64-row x 32-column blocks.
 constexpr int kSlicedTailRank = 64;
+// Lanes per output entry of the tail below kSlicedTailRank.
+constexpr int kTailLanes = 8;
 inline int tail_blocks(int64_t n_pad, int R) {
-  return R >= kSlicedTailRank ? (int)(n_pad / 64) * (R / 32) : (int)((n_pad * R + 255) / 256);
+  return R >= kSlicedTailRank ? (int)(n_pad / 64) * (R / 32)
+                              : (int)((n_pad * R * kTailLanes + 255) / 256);
 }
 inline int gram_pairs_per_block(int R) {
   const int ppt = (R * R + 255) / 256 < 16 ? (R * R + 255) / 256 : 16;

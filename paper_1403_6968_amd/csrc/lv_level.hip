@@ -144,25 +144,47 @@ __device__ __forceinline__ void tail_body(const T* __restrict__ partX, const T* 
   const int tid = threadIdx.x;
   const int64_t strideX = (int64_t)n_pad * R;
   if constexpr (R < kSlicedTailRank) {
+    // kTailLanes lanes per output entry (i, c): lane s sums the partials
+    // s, s + kTailLanes, ... (and the terms d of U_j G with d = s mod
+    // kTailLanes), then a butterfly over the lanes adds the lane sums (every
+    // lane ends with the same value: each step adds the same two numbers).
+    constexpr int TL = kTailLanes;
     __shared__ double G[R * R];
     for (int idx = tid; idx < R * R; idx += 256) {
       double g = 0.0;
-      for (int t = 0; t < ng; ++t) g += partG[(int64_t)t * R * R + idx];
+      int t = 0;
+      for (; t + 4 <= ng; t += 4) {
+        double v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = partG[(int64_t)(t + e) * R * R + idx];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) g += v[e];
+      }
+      for (; t < ng; ++t) g += partG[(int64_t)t * R * R + idx];
       G[idx] = g;
     }
     __syncthreads();
     const int64_t pairs = (int64_t)n_pad * R;
-    const int64_t idx = (int64_t)blk * 256 + tid;
-    if (idx >= pairs) return;
+    const int64_t idx = (int64_t)blk * (256 / TL) + tid / TL;
+    const int sl = tid % TL;
+    if (idx >= pairs) return;   // whole lane groups leave together
     const int64_t i = idx / R;
     const int c = (int)(idx % R);
-    const double x = sum_partials(partX, strideX, idx, nct);
-    const double y = sum_partials(partY, strideX, idx, nrt);
-    double ug = 0.0;
+    double x = 0.0, y = 0.0, ug = 0.0;
+    for (int t = sl; t < nct; t += TL) x += (double)partX[(int64_t)t * strideX + idx];
+    for (int t = sl; t < nrt; t += TL) y += (double)partY[(int64_t)t * strideX + idx];
 #pragma unroll
-    for (int d = 0; d < R; ++d) ug = fma((double)Ucur[i * W + d], G[d * R + c], ug);
-    Unew[i * W + c] = (T)(x + ug);
-    Vnew[i * W + c] = (T)y;
+    for (int d = sl; d < R; d += TL) ug = fma((double)Ucur[i * W + d], G[d * R + c], ug);
+#pragma unroll
+    for (int off = TL / 2; off > 0; off >>= 1) {
+      x += __shfl_xor(x, off, TL);
+      y += __shfl_xor(y, off, TL);
+      ug += __shfl_xor(ug, off, TL);
+    }
+    if (sl == 0) {
+      Unew[i * W + c] = (T)(x + ug);
+      Vnew[i * W + c] = (T)y;
+    }
   } else {
     constexpr int NS = R / 32;
     __shared__ double G[R][32];
@@ -276,7 +298,8 @@ k_add(T* __restrict__ dst, const T* __restrict__ src, int64_t count, const int* 
 // registers); the wave walks blocks of 8 rows in the interleaved row slices
 // of the fused pass, with the next block's rows of P and U_j requested
 // before the current block is updated.  The block's U_j entries come with
-// one gathered vector load per 64 entries and are broadcast by readlane.
+// one gathered vector load per 64 entries; the wave stores them to its LDS
+// block and reads them back row by row as broadcasts.
 // Ranks above 16 are processed in groups of 16 columns of the factors.
 // SH (float only): the new values are also written to the bfloat16 shadow S
 // (same ld).
@@ -324,10 +347,21 @@ __device__ __forceinline__ void update_body(T* __restrict__ P, const int64_t ldp
       for (int c = 0; c < RG; ++c) vcol[q][c] = Vj[(int64_t)(lc + q) * W + c];
   }
 
+  __shared__ __align__(16) T facs[4][NG == 1 ? RB * R : 1];
+  T* fac = facs[wave];
+
   int b = rt + ns * wave;
   if (b < nb_all) load(b, p, fu);
   for (; b < nb_all; b += 4 * ns) {
     const int64_t r0 = (int64_t)b * RB;
+    if constexpr (NG == 1) {
+#pragma unroll
+      for (int f = 0; f < FN; ++f)
+        if (lane + 64 * f < RB * R) fac[lane + 64 * f] = fu[f];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     if (b + 4 * ns < nb_all) load(b + 4 * ns, pn, fun);
     T d[RB][EPL];
 #pragma unroll
@@ -339,7 +373,7 @@ __device__ __forceinline__ void update_body(T* __restrict__ P, const int64_t ldp
       for (int t = 0; t < RB; ++t) {
         T u[RG];
 #pragma unroll
-        for (int c = 0; c < RG; ++c) u[c] = lane_bcast(fu[(t * R + c) / 64], (t * R + c) % 64);
+        for (int c = 0; c < RG; ++c) u[c] = fac[t * R + c];
 #pragma unroll
         for (int q = 0; q < EPL; ++q)
 #pragma unroll
@@ -379,6 +413,11 @@ __device__ __forceinline__ void update_body(T* __restrict__ P, const int64_t ldp
     for (int t = 0; t < RB; ++t) p[t] = pn[t];
 #pragma unroll
     for (int f = 0; f < FN; ++f) fu[f] = fun[f];
+    // the next block's entries overwrite the LDS block only after every
+    // lane has read this block's
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
