@@ -118,7 +118,7 @@ lv_status lv_view_create(const void* A, int64_t n, int64_t lda, int k, int r_max
 
 /* Creation flags.
  *  LV_WITH_SUMS  also maintain the sums of powers S_i = I + A + ... + A^(i-1)
- *                for i in {1, 2, 4, ..., k} (Sec. 5.3, Table 1, exponential
+ *                for i in {1, 2, 4, ..., k} (Sec. 5.2.3, Table 1, exponential
  *                model: S_1 = I, S_{2i} = P_i S_i + S_i).  Every update then
  *                also applies the factored deltas Delta S_i = Q_i W_i^T,
  *                obtained from the old powers and sums by the delta rule of
@@ -161,12 +161,12 @@ lv_status lv_view_read(const lv_view* v, int power, void* out, int64_t ldo, void
  * LV_ESTATE for a view without sums. */
 lv_status lv_view_read_sum(const lv_view* v, int index, void* out, int64_t ldo, void* stream);
 
-/* General iterative form T_{i+1} = A T_i + B (Sec. 5.4 and Table 1,
+/* General iterative form T_{i+1} = A T_i + B (Sec. 5.3 and Table 1,
  * exponential model: T_1 = A T_0 + B, T_{2i} = P_i T_i + S_i B), T_i and B
  * n x p.  A view created here stores T_1, T_2, T_4, ..., T_k beside the
  * powers and the sums (it implies LV_WITH_SUMS) and keeps them current
  * under lv_view_update / lv_view_update_batch by hybrid evaluation
- * (Sec. 5.4): the change of each T_i is one dense n x p matrix D_i, taken
+ * (Sec. 5.3.2): the change of each T_i is one dense n x p matrix D_i, taken
  * from the old values by the delta rule of Sec. 4.1 (the factored form of
  * App. B, multiplied out):
  *     D_1 = U (V^T T_0),

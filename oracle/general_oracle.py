@@ -2,13 +2,13 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Sec. 5.4 and Table 1 (general form column, exponential model):
+Sec. 5.3 and Table 1 (general form column, exponential model):
 
     T_1 = A T_0 + B,    T_i = P_{i/2} T_{i/2} + S_{i/2} B   for i = 2, 4, ..., k,
 
 with the powers P_i and the sums S_i of the exponential model; T is n x p.
 
-Hybrid evaluation (Sec. 5.4, "Hybrid evaluation") keeps the change of every
+Hybrid evaluation (Sec. 5.3.2, "Hybrid evaluation") keeps the change of every
 T_i as one n x p matrix D_i instead of factors.  By the delta rule of
 Sec. 4.1 with old operands (the same expansion as the factored form of
 App. B, multiplied out), for Delta A = U V^T, Delta P_i = U_i V_i^T and
@@ -52,7 +52,7 @@ from .sums_oracle import incr_sums_factors, reeval_sums
 
 def iterate_general(A: np.ndarray, T0: np.ndarray, B: np.ndarray, k: int) -> dict[int, np.ndarray]:
     """T_1, T_2, T_4, ..., T_k by the defining iteration T_{i+1} = A T_i + B
-    (Sec. 5.4), one step at a time: k products of A with an n x p matrix,
+    (Sec. 5.3), one step at a time: k products of A with an n x p matrix,
     cheap enough for full-size checks where the powers are not formed."""
     A = np.asarray(A, dtype=np.float64)
     B = np.asarray(B, dtype=np.float64)

@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Sec. 5.3 ("Sums of Matrix Powers") and Table 1 give the exponential model
+Sec. 5.2.3 ("Sums of Matrix Powers") and Table 1 give the exponential model
 
     S_1 = I,     S_i = P_{i/2} S_{i/2} + S_{i/2}   for i = 2, 4, ..., k,
 

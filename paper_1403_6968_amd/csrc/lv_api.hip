@@ -101,7 +101,7 @@ lv_status build_chain(lv_view* v, hipStream_t s, const int* gate = nullptr) {
   const Layout& L = v->L;
   const int64_t cnt = L.n_pad * L.ldp;
   if (L.sums) {
-    // S_1 = I (Sec. 5.3, Table 1)
+    // S_1 = I (Sec. 5.2.3, Table 1)
     lv_status st = hip_check(launch_set_identity<T>(v->S<T>(0), L.ldp, v->n, L.n_pad, s, gate), "S_1 = I");
     if (st != LV_OK) return st;
   }

@@ -1,7 +1,7 @@
-// General iterative form T_{i+1} = A T_i + B (LINVIEW Sec. 5.4, Table 1,
+// General iterative form T_{i+1} = A T_i + B (LINVIEW Sec. 5.3, Table 1,
 // exponential model: T_1 = A T_0 + B, T_{2i} = P_i T_i + S_i B), maintained
 // by hybrid evaluation: the change of every stored T_i is one dense n x p
-// matrix D_i (Sec. 5.4, "Hybrid evaluation"), obtained from the old values
+// matrix D_i (Sec. 5.3.2, "Hybrid evaluation"), obtained from the old values
 // by the delta rule of Sec. 4.1:
 //     D_1 = U (V^T T_0),
 //     D_{2i} = P_i D_i + U_i (V_i^T (T_i + D_i)) + Q_i (W_i^T B)

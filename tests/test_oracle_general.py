@@ -1,4 +1,4 @@
-"""Pins of the general-form oracle (T_{i+1} = A T_i + B, Sec. 5.4, Table 1)
+"""Pins of the general-form oracle (T_{i+1} = A T_i + B, Sec. 5.3, Table 1)
 against facts other than itself: the plain iteration T_{i+1} = A T_i + B
 run step by step (exact rationals on integers, and in floating point), the
 B = 0 case T_k = A^k T_0, the unrolled identity T_k = A^k T_0 + S_k B, the

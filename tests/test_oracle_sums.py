@@ -1,4 +1,4 @@
-"""Pins of the sums-of-powers oracle (S_k = I + A + ... + A^(k-1), Sec. 5.3,
+"""Pins of the sums-of-powers oracle (S_k = I + A + ... + A^(k-1), Sec. 5.2.3,
 Table 1) against facts other than itself: exact rational brute-force sums,
 closed forms (geometric series of a diagonal matrix, the band of a shift
 matrix), the telescoping identity (I - A) S_k = I - A^k, the factor widths
