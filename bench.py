@@ -55,10 +55,12 @@ def parse():
     return p.parse_args()
 
 
-def bench_rank4(torch, lv, synth, dev, steps=40):
+def bench_rank4(torch, lv, synth, dev, steps=200, drift_every=100):
     """A^16 view, n = 16384, rank-4 updates: plain FP32 and FP32 with
     bfloat16 shadows (skinny products on the matrix cores), updates/s and the
-    per-kind kernel time of one update."""
+    per-kind kernel time of one update.  Both views run the periodic drift
+    check every `drift_every` updates with the mode's default bound (the
+    timed updates include those checks); one check is also timed alone."""
     n, k, r = 16384, 16, 4
     A = torch.from_numpy(synth.gaussian_matrix(n, seed=0, config=3).astype(np.float32)).to(dev)
     U, V = synth.update_factors(n, r, steps + 5, seed=0, config=3)
@@ -68,6 +70,7 @@ def bench_rank4(torch, lv, synth, dev, steps=40):
     for tag, mode in (("fp32", lv.LV_FP32), ("bf16shadow", lv.LV_FP32_BF16SHADOW)):
         view = lv.View(A, k, r_max=r, mode=mode)
         view.update_batch(Ud[:5], Vd[:5])
+        view.set_drift_check(drift_every)          # counts from here: 5 updates applied
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
@@ -75,13 +78,26 @@ def bench_rank4(torch, lv, synth, dev, steps=40):
         b.record()
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / steps
+        st = view.stats()
+        z = torch.from_numpy(synth.rng(0, 3, 77).choice([-1.0, 1.0], size=n)).to(dev)
+        view.drift_check(z, tau=st["drift_tau"])
+        torch.cuda.synchronize()
+        a.record()
+        view.drift_check(z, tau=st["drift_tau"])
+        b.record()
+        torch.cuda.synchronize()
+        drift = {"every": drift_every, "tau": st["drift_tau"], "checks_in_timed_updates": int(st["drift_checks"]),
+                 "reanchors": int(st["drift_reanchors"]), "last_residual": st["last_residual"],
+                 "check_ms": a.elapsed_time(b),
+                 "check_cost_per_update_ms": a.elapsed_time(b) / drift_every}
         view.set_timing(True)
         view.update(Ud[0], Vd[0])
         tm = view.timing()
         view.set_timing(False)
         view.close()
         out[tag] = {"ms_per_update": ms, "updates_per_s": 1000.0 / ms, "rank1_equiv_per_s": 4000.0 / ms,
-                    "level_passes_ms": tm["fused_ms"], "tails_ms": tm["tail_ms"], "top_update_ms": tm["top_ms"]}
+                    "level_passes_ms": tm["fused_ms"], "tails_ms": tm["tail_ms"], "top_update_ms": tm["top_ms"],
+                    "drift_check": drift}
     del A
     return out
 
@@ -398,12 +414,13 @@ def bench_batched(torch, lv, synth, dev, rounds=30):
 
 
 def bench_serving(torch, lv, synth, dev, seconds=2.0, rate=20000.0, r_coalesce=16, shadow=True,
-                  hold=(16, 0.03)):
+                  hold=(16, 0.03), drift_every=100):
     """32 views, n log-uniform in [2048, 16384], k = 16, FP32 (with bfloat16
     shadows by default); Poisson arrivals at `rate` requests/s over views with
     Zipf(1.1) popularity; per-view coalescing, continuous batching; rounds
     hold a view until it has hold[0] requests queued or its oldest has waited
-    hold[1] s."""
+    hold[1] s.  Every view runs the periodic drift check every
+    `drift_every` of its coalesced updates (inside the served rounds)."""
     mode = lv.LV_FP32_BF16SHADOW if shadow else lv.LV_FP32
     g = synth.rng(0, 5, 0)
     ns = np.exp(g.uniform(np.log(2048), np.log(16384), size=32)).astype(int)
@@ -419,6 +436,7 @@ def bench_serving(torch, lv, synth, dev, seconds=2.0, rate=20000.0, r_coalesce=1
     for v in range(32):
         A = torch.from_numpy(synth.gaussian_matrix(int(ns[v]), seed=0, config=5, view=v).astype(np.float32)).to(dev)
         ids.append(srv.add_view(A, 16))
+        srv.set_drift_check(ids[-1], drift_every)
         del A
     torch.cuda.synchronize()
     pool = []
@@ -444,6 +462,7 @@ def bench_serving(torch, lv, synth, dev, seconds=2.0, rate=20000.0, r_coalesce=1
     srv.drain()
     t_end = srv.now()
     st = srv.stats()
+    vst = [srv.view_stats(i) for i in ids]
     srv.close()
     return {"workload": "32 views, n log-uniform [2048,16384], k=16, %s, Poisson %.0f req/s, Zipf(1.1), "
                         "hold %d requests / %.0f ms" % ("FP32 + BF16 shadows" if shadow else "FP32", rate, hold[0],
@@ -452,7 +471,10 @@ def bench_serving(torch, lv, synth, dev, seconds=2.0, rate=20000.0, r_coalesce=1
             "throughput_per_s": st["completed"] / (t_end - t0), "rounds": int(st["rounds"]),
             "mean_coalesced_rank": st["completed"] / max(st["coalesced_updates"], 1),
             "latency_p50_ms": st["latency_p50_s"] * 1e3, "latency_p99_ms": st["latency_p99_s"] * 1e3,
-            "arena_GB": need / 1e9}
+            "arena_GB": need / 1e9,
+            "drift_check": {"every": drift_every, "checks": int(sum(x["drift_checks"] for x in vst)),
+                            "reanchors": int(sum(x["drift_reanchors"] for x in vst)),
+                            "max_last_residual": float(max(x["last_residual"] for x in vst))}}
 
 
 def counter_traffic(n, k, r):

@@ -84,8 +84,11 @@ typedef struct {
   int64_t updates;    /* updates applied since creation                    */
   int64_t reanchors;  /* re-evaluations requested by lv_view_reanchor       */
   size_t footprint;   /* workspace bytes in use                            */
-  int64_t drift_reanchors; /* re-evaluations triggered by lv_view_drift_check */
+  int64_t drift_reanchors; /* re-evaluations triggered by drift checks     */
   double last_residual;    /* max_j rho_j of the last drift check          */
+  int64_t drift_checks;    /* periodic drift checks run (enqueued)         */
+  int64_t drift_every;     /* interval of the periodic check (0: off)      */
+  double drift_tau;        /* its bound                                    */
 } lv_stats;
 
 /* Human-readable name of a status code (static string). */
@@ -246,6 +249,28 @@ lv_status lv_view_write(lv_view* v, int power, const void* src, int64_t lds, voi
  * the last max_j rho_j (it waits for the device to read them). */
 lv_status lv_view_drift_check(lv_view* v, const void* z, double tau, double* residuals,
                               void* stream);
+
+/* Periodic drift check: after every `every`-th update of the view (counted
+ * as lv_stats.updates, whichever entry point applies it: lv_view_update,
+ * lv_view_update_batch, batch rounds or server rounds), the check of
+ * lv_view_drift_check runs on the update's stream with this view's probe
+ * vector and bound, and re-anchors the chain on the device when some
+ * rho_j > tau.  every = 0 turns it off (the default).
+ *  tau   the bound; tau < 0 takes the mode's default: LV_DRIFT_TAU_FP64,
+ *        LV_DRIFT_TAU_FP32 or LV_DRIFT_TAU_BF16SHADOW, a tenth of the
+ *        maximum relative error the mode is held to against the exact
+ *        powers (1e-10, 1e-4 and 5e-3): rho_j compares two ways of forming
+ *        P_{j+1} z from the stored values, so it stays of the order of the
+ *        storage rounding (about 20 units of 2^-24 after 1000 float updates
+ *        of an n = 8192 view) until the chain drifts.
+ *  z     n doubles on the device, copied into the view; NULL takes the
+ *        library's probe vector (entries +1 / -1 from splitmix64, fixed seed).
+ * Each check reads every stored power twice (2 m + 1 matrix-vector
+ * products).  LV_EINVAL for a negative interval or a NaN bound. */
+#define LV_DRIFT_TAU_FP64 1e-11
+#define LV_DRIFT_TAU_FP32 1e-5
+#define LV_DRIFT_TAU_BF16SHADOW 5e-4
+lv_status lv_view_set_drift_check(lv_view* v, int64_t every, double tau, const void* z, void* stream);
 
 /* Per-kernel timing of a view's updates (diagnostics).  While enabled, the
  * library brackets every level-pass launch with HIP events recorded on the

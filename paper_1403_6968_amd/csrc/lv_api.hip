@@ -181,12 +181,15 @@ lv_status build_chain(lv_view* v, hipStream_t s, const int* gate = nullptr) {
 
 // Drift check: P_j z for every level, P_j (P_j z) below the top, the
 // residual kernel (gate + counter), then the gated squaring chain.
+// `padded`: z already holds n_pad entries with zeros beyond n (the view's own
+// probe vector of the periodic check); else it is the caller's n entries.
 template <typename T>
-lv_status drift_check(lv_view* v, const double* z, double tau, hipStream_t s) {
+lv_status drift_check(lv_view* v, const double* z, double tau, hipStream_t s, bool padded = false) {
   const Layout& L = v->L;
-  lv_status st = hip_check(launch_vec_pad(z, v->n, v->zpad(), L.n_pad, s), "pad z");
+  lv_status st = padded ? LV_OK : hip_check(launch_vec_pad(z, v->n, v->zpad(), L.n_pad, s), "pad z");
+  const double* zp = padded ? z : v->zpad();
   for (int j = 0; j <= L.m && st == LV_OK; ++j)
-    st = hip_check(launch_matvec<T>(v->P<T>(j), L.ldp, L.n_pad, v->zpad(), v->Pz(j), s), "P z");
+    st = hip_check(launch_matvec<T>(v->P<T>(j), L.ldp, L.n_pad, zp, v->Pz(j), s), "P z");
   for (int j = 0; j < L.m && st == LV_OK; ++j)
     st = hip_check(launch_matvec<T>(v->P<T>(j), L.ldp, L.n_pad, v->Pz(j), v->PPz(j), s), "P P z");
   if (st != LV_OK) return st;
@@ -196,6 +199,19 @@ lv_status drift_check(lv_view* v, const double* z, double tau, hipStream_t s) {
   if (st != LV_OK) return st;
   return build_chain<T>(v, s, v->gate());
 }
+
+}  // namespace
+
+namespace lv {
+lv_status periodic_drift(lv_view* v, hipStream_t s) {
+  if (v->drift_every <= 0 || v->L.m == 0 || v->updates % v->drift_every != 0) return LV_OK;
+  v->drift_checks += 1;
+  return v->mode == LV_FP64 ? drift_check<double>(v, v->drift_z(), v->drift_tau, s, true)
+                            : drift_check<float>(v, v->drift_z(), v->drift_tau, s, true);
+}
+}  // namespace lv
+
+namespace {
 
 hipEvent_t take_event(lv_view* v) {
   if (!v->pool.empty()) { hipEvent_t e = v->pool.back(); v->pool.pop_back(); return e; }
@@ -788,8 +804,9 @@ lv_status lv_view_update(lv_view* v, const void* U, const void* V, int64_t r, in
   st = v->mode == LV_FP64
            ? update_one<double>(v, static_cast<const double*>(U), static_cast<const double*>(V), (int)r, ldu, ldv, s)
            : update_one<float>(v, static_cast<const float*>(U), static_cast<const float*>(V), (int)r, ldu, ldv, s);
-  if (st == LV_OK) v->updates += 1;
-  return st;
+  if (st != LV_OK) return st;
+  v->updates += 1;
+  return periodic_drift(v, s);
 }
 
 lv_status lv_view_update_batch(lv_view* v, const void* U, const void* V, int64_t r, int64_t count,
@@ -812,6 +829,8 @@ lv_status lv_view_update_batch(lv_view* v, const void* U, const void* V, int64_t
              : update_one<float>(v, reinterpret_cast<const float*>(Ut), reinterpret_cast<const float*>(Vt), (int)r, ldu, ldv, s);
     if (st != LV_OK) return st;
     v->updates += 1;
+    st = periodic_drift(v, s);
+    if (st != LV_OK) return st;
   }
   return LV_OK;
 }
@@ -900,6 +919,23 @@ lv_status lv_view_drift_check(lv_view* v, const void* z, double tau, double* res
   return st;
 }
 
+lv_status lv_view_set_drift_check(lv_view* v, int64_t every, double tau, const void* z, void* stream) {
+  g_err[0] = 0;
+  if (!v) return fail(LV_EINVAL, "view is NULL");
+  if (every < 0) return fail(LV_EINVAL, "every = %lld < 0", (long long)every);
+  if (tau != tau) return fail(LV_EINVAL, "tau is NaN");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const lv_status st =
+      z ? hip_check(launch_vec_pad(static_cast<const double*>(z), v->n, v->drift_z(), v->L.n_pad, s), "copy z")
+        : hip_check(launch_sign_vector(v->drift_z(), v->n, v->L.n_pad, 0x4C494E56494557ull, s), "probe vector");
+  if (st != LV_OK) return st;
+  v->drift_every = every;
+  v->drift_tau = tau >= 0.0 ? tau
+                 : v->mode == LV_FP64 ? LV_DRIFT_TAU_FP64
+                 : v->mode == LV_FP32 ? LV_DRIFT_TAU_FP32 : LV_DRIFT_TAU_BF16SHADOW;
+  return LV_OK;
+}
+
 lv_status lv_view_write(lv_view* v, int power, const void* src, int64_t lds, void* stream) {
   g_err[0] = 0;
   const int j = power_level(v, power);
@@ -938,6 +974,9 @@ lv_status lv_view_stats(const lv_view* v, lv_stats* out) {
   double mx = 0.0;
   for (int j = 0; j < v->L.m; ++j) mx = res[j] > mx || res[j] != res[j] ? res[j] : mx;
   out->last_residual = mx;
+  out->drift_checks = v->drift_checks;
+  out->drift_every = v->drift_every;
+  out->drift_tau = v->drift_tau;
   return LV_OK;
 }
 

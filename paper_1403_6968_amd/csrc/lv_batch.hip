@@ -284,10 +284,15 @@ lv_status lv_batch_tuning(const lv_batch* b, int* tuned_groups, int* cache_hits)
 lv_status lv_batch_update(lv_batch* b, void* stream) {
   g_err[0] = 0;
   if (!b) return fail(LV_EINVAL, "batch is NULL");
-  lv_status st = hip_check(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)), "graph launch");
-  if (st == LV_OK)
-    for (lv_view* v : b->views) v->updates += 1;
-  return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  lv_status st = hip_check(hipGraphLaunch(b->exec, s), "graph launch");
+  if (st != LV_OK) return st;
+  for (lv_view* v : b->views) {
+    v->updates += 1;
+    st = periodic_drift(v, s);
+    if (st != LV_OK) return st;
+  }
+  return LV_OK;
 }
 
 }  // extern "C"

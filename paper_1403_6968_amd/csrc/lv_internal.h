@@ -324,6 +324,7 @@ hipError_t launch_gemm_rect(const T* A, int64_t lda, const T* B, int64_t ldb, T*
 
 // x = z zero-padded to n_pad (double).
 hipError_t launch_vec_pad(const double* z, int64_t n, double* x, int64_t n_pad, hipStream_t s);
+hipError_t launch_sign_vector(double* z, int64_t n, int64_t n_pad, unsigned long long seed, hipStream_t s);
 
 // y = P x with double accumulation, P n_pad x n_pad (ld ldp) of type T.
 template <typename T>

@@ -96,7 +96,26 @@ k_drift_residual(const double* __restrict__ Pz, const double* __restrict__ PPz, 
   }
 }
 
+// Probe vector of the periodic check when the caller gives none: entries
+// +1 or -1 from the top bit of splitmix64 (Steele, Lea and Flood, 2014) of
+// seed + i, zero beyond n.
+__global__ void __launch_bounds__(256)
+k_sign_vector(double* __restrict__ z, int64_t n, int64_t n_pad, unsigned long long seed) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_pad) return;
+  unsigned long long x = seed + 0x9E3779B97F4A7C15ull * (unsigned long long)(i + 1);
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  x ^= x >> 31;
+  z[i] = i < n ? ((x >> 63) ? 1.0 : -1.0) : 0.0;
+}
+
 }  // namespace
+
+hipError_t launch_sign_vector(double* z, int64_t n, int64_t n_pad, unsigned long long seed, hipStream_t s) {
+  hipLaunchKernelGGL(k_sign_vector, dim3((unsigned)((n_pad + 255) / 256)), dim3(256), 0, s, z, n, n_pad, seed);
+  return hipGetLastError();
+}
 
 hipError_t launch_vec_pad(const double* z, int64_t n, double* x, int64_t n_pad, hipStream_t s) {
   hipLaunchKernelGGL(k_vec_pad, dim3((unsigned)((n_pad + 255) / 256)), dim3(256), 0, s, z, n, x, n_pad);

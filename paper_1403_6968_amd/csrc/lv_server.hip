@@ -266,7 +266,12 @@ lv_status step_impl(lv_server* s, int* launched) {
   if (hipEventCreateWithFlags(&f.ev, hipEventDisableTiming) != hipSuccess) return fail(LV_EDEVICE, "event create");
   st = hip_check(hipEventRecord(f.ev, s->stream), "event record");
   if (st != LV_OK) return st;
-  for (size_t a = 0; a < active.size(); ++a) s->views[active[a]].view->updates += 1;
+  for (size_t a = 0; a < active.size(); ++a) {
+    lv_view* v = s->views[active[a]].view;
+    v->updates += 1;
+    st = periodic_drift(v, s->stream);   // after the round's completion event
+    if (st != LV_OK) return st;
+  }
   s->slot_busy[slot] = true;
   *launched = (int)f.tickets.size();
   s->rounds += 1;

@@ -77,6 +77,7 @@ struct Layout {
   size_t T0 = 0, B = 0, D[2] = {}, partXT = 0, partYT = 0, atbA = 0, atbB = 0;
   size_t gT[2] = {}, gTmp = 0, gB = 0;
   size_t probe = 0;  // zpad | Pz (m+1 vectors) | PPz (m vectors) | residuals | gate | counter
+  size_t drift_z = 0;  // probe vector of the periodic drift check (n_pad doubles)
   size_t total = 0;
 };
 
@@ -209,9 +210,15 @@ inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode, int flags =
   }
   L.probe = off;
   off = align_up(off + (size_t)(2 * L.m + 2) * L.n_pad * sizeof(double) + kMaxLevel * sizeof(double) + 256);
+  L.drift_z = off;
+  off = align_up(off + (size_t)L.n_pad * sizeof(double));
   L.total = off;
   return L;
 }
+
+// The periodic drift check of a view after an update (no-op unless the
+// view's update count is a multiple of its interval); stream-ordered on s.
+lv_status periodic_drift(::lv_view* v, hipStream_t s);
 
 inline lv_status hip_check(hipError_t e, const char* what) {
   if (e == hipSuccess) return LV_OK;
@@ -230,6 +237,11 @@ struct lv_view {
   size_t ws_bytes;
   int64_t updates;
   int64_t reanchors;
+  // periodic drift check: after every drift_every-th update (0: never) with
+  // bound drift_tau and the probe vector at L.drift_z; checks enqueued so far
+  int64_t drift_every = 0;
+  double drift_tau = 0.0;
+  int64_t drift_checks = 0;
   // Rows per tile of the level pass of each level below the top (set by the
   // batch autotuner or lv_view_set_tile_rows; every path uses the same value,
   // which fixes the reduction order of the partial sums).
@@ -281,6 +293,7 @@ struct lv_view {
   bool shadowed() const { return mode == LV_FP32_BF16SHADOW; }
   double* scratch(int i) const { return reinterpret_cast<double*>(base + L.scratch[i]); }
   double* zpad() const { return reinterpret_cast<double*>(base + L.probe); }
+  double* drift_z() const { return reinterpret_cast<double*>(base + L.drift_z); }
   double* Pz(int j) const { return zpad() + (size_t)(1 + j) * L.n_pad; }
   double* PPz(int j) const { return zpad() + (size_t)(L.m + 2 + j) * L.n_pad; }
   double* residuals() const { return zpad() + (size_t)(2 * L.m + 2) * L.n_pad; }

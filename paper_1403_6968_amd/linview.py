@@ -47,7 +47,7 @@ EXPORTED = (
     "lv_ols_read", "lv_ols_info", "lv_ols_destroy",
     "lv_glin_footprint", "lv_glin_create", "lv_glin_update", "lv_glin_read", "lv_glin_destroy",
     "lv_server_poll", "lv_server_drain", "lv_server_stats", "lv_server_destroy",
-    "lv_stream_probe", "lv_powers_update_noalloc",
+    "lv_stream_probe", "lv_powers_update_noalloc", "lv_view_set_drift_check",
 )
 
 
@@ -63,7 +63,8 @@ class lv_stats(ctypes.Structure):
         ("k", ctypes.c_int32), ("levels", ctypes.c_int32), ("r_max", ctypes.c_int32),
         ("mode", ctypes.c_int32), ("updates", ctypes.c_int64), ("reanchors", ctypes.c_int64),
         ("footprint", ctypes.c_size_t), ("drift_reanchors", ctypes.c_int64),
-        ("last_residual", ctypes.c_double),
+        ("last_residual", ctypes.c_double), ("drift_checks", ctypes.c_int64),
+        ("drift_every", ctypes.c_int64), ("drift_tau", ctypes.c_double),
     ]
 
 
@@ -165,6 +166,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "lv_glin_destroy": (None, [P]),
         "lv_stream_probe": (I32, [I32, P, P, SZ, I32, I32, I32, P]),
         "lv_powers_update_noalloc": (I32, [c.POINTER(P), I64, I64, I32, I32, P, P, I64, I64, I64, P]),
+        "lv_view_set_drift_check": (I32, [P, I64, c.c_double, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -302,6 +304,14 @@ def lv_view_drift_check(view, z: torch.Tensor, tau: float, residuals=None, strea
     _check(load().lv_view_drift_check(view, z.data_ptr(), float(tau),
                                       None if residuals is None else residuals.data_ptr(),
                                       _stream(stream, z.device)))
+
+
+def lv_view_set_drift_check(view, every: int, tau: float = -1.0, z=None, stream=None, device=None) -> None:
+    if z is not None and (z.dtype != torch.float64 or z.device.type != "cuda" or not z.is_contiguous()):
+        raise TypeError("z must be a contiguous float64 device vector")
+    dev = z.device if z is not None else (device or torch.device("cuda"))
+    _check(load().lv_view_set_drift_check(view, int(every), float(tau), None if z is None else z.data_ptr(),
+                                          _stream(stream, dev)))
 
 
 def lv_view_data(view, power: int):
@@ -488,6 +498,11 @@ class View:
         lv_view_drift_check(self.handle, z, tau, res if m > 0 else None, stream)
         return res[:m]
 
+    def set_drift_check(self, every: int, tau: float = -1.0, z=None, stream=None) -> None:
+        """Run the drift check after every `every`-th update (0: off);
+        tau < 0 takes the mode's default bound."""
+        lv_view_set_drift_check(self.handle, every, tau, z, stream, self.device)
+
     def stats(self) -> dict:
         return lv_view_stats(self.handle)
 
@@ -672,6 +687,20 @@ class Server:
         st = lv_server_counters()
         _check(load().lv_server_stats(self.handle, ctypes.byref(st)))
         return {f: getattr(st, f) for f, _ in lv_server_counters._fields_}
+
+    def _view(self, vid: int) -> ctypes.c_void_p:
+        h = load().lv_server_view(self.handle, vid)
+        if not h:
+            raise LinviewError(LV_EINVAL, f"no view {vid}")
+        return ctypes.c_void_p(h)
+
+    def set_drift_check(self, vid: int, every: int, tau: float = -1.0, z=None) -> None:
+        """Periodic drift check of view vid every `every` of its (coalesced)
+        updates; tau < 0 takes the mode's default bound."""
+        lv_view_set_drift_check(self._view(vid), every, tau, z, self._stream, self.device)
+
+    def view_stats(self, vid: int) -> dict:
+        return lv_view_stats(self._view(vid))
 
     def read(self, vid: int, power: int) -> torch.Tensor:
         h = load().lv_server_view(self.handle, vid)

@@ -99,3 +99,108 @@ def test_reanchor_after_perturbation_fp64():
     for i, M in read_all(view).items():
         assert O.maxrel(M, P[i]) < 1e-10
     view.close()
+
+
+def _perturb(lv, torch, view, power, rel, seed):
+    """Add a relative perturbation of size rel to stored power `power`."""
+    M = host(view.read(power))
+    g = synth.rng(seed, 0, 11)
+    M = M + rel * np.abs(M).max() * g.standard_normal(M.shape)
+    view.write(power, dev(M, view.dtype))
+
+
+@pytest.mark.parametrize("modename", ["fp32", "bf16shadow", "fp64"])
+def test_periodic_check_reanchors_within_interval(modename):
+    """Every D-th update runs the check with the mode's default bound: a
+    clean chain passes, a perturbed A^k written between two checks is caught
+    by the next one and the chain is re-evaluated from the stored A, after
+    which the view follows the oracle again."""
+    lv = _lv()
+    import torch
+    mode = {"fp32": lv.LV_FP32, "bf16shadow": lv.LV_FP32_BF16SHADOW, "fp64": lv.LV_FP64}[modename]
+    dtype = torch.float64 if mode == lv.LV_FP64 else torch.float32
+    np_t = np.float64 if mode == lv.LV_FP64 else np.float32
+    n, k, r, D, T = 700, 16, 2, 5, 13
+    A = np.asarray(synth.gaussian_matrix(n, seed=23), dtype=np_t).astype(np.float64)
+    Us, Vs = synth.update_factors(n, r, T, seed=23)
+    Us = np.asarray(Us, dtype=np_t).astype(np.float64)
+    Vs = np.asarray(Vs, dtype=np_t).astype(np.float64)
+    view = lv.View(dev(A, dtype), k, r_max=r, mode=mode)
+    view.set_drift_check(D)
+    st = view.stats()
+    assert st["drift_every"] == D
+    assert st["drift_tau"] == {lv.LV_FP32: 1e-5, lv.LV_FP32_BF16SHADOW: 5e-4, lv.LV_FP64: 1e-11}[mode]
+    # updates 1..7 (a check after update 5 finds the chain clean)
+    view.update_batch(dev(Us[:7], dtype), dev(Vs[:7], dtype))
+    st = view.stats()
+    note(f"{modename}: after 7 updates checks={st['drift_checks']} residual={st['last_residual']:.2e}")
+    assert st["drift_checks"] == 1 and st["drift_reanchors"] == 0
+    assert st["last_residual"] < st["drift_tau"]
+    # corrupt A^k: the check after update 10 must catch it and re-anchor
+    _perturb(lv, torch, view, k, 1e-2, 24)
+    for t in range(7, T):
+        view.update(dev(Us[t], dtype), dev(Vs[t], dtype))
+    st = view.stats()
+    note(f"{modename}: after {T} updates checks={st['drift_checks']} reanchors={st['drift_reanchors']}")
+    assert st["drift_checks"] == 2 and st["drift_reanchors"] == 1
+    P = O.apply_updates(O.reeval(A, k), Us, Vs)
+    tol = {lv.LV_FP32: 1e-4, lv.LV_FP32_BF16SHADOW: 5e-3, lv.LV_FP64: 1e-10}[mode]
+    got = read_all(view)
+    for i in P:
+        err = O.maxrel(got[i], P[i])
+        assert err < tol, f"A^{i}: maxrel {err:.2e}"
+    view.close()
+
+
+def test_periodic_check_in_batch_rounds():
+    """Batched rounds count as updates of every view and run each view's
+    periodic check after the round."""
+    lv = _lv()
+    import torch
+    ns, k, r, D = (512, 768), 8, 1, 3
+    views, refs = [], []
+    for q, n in enumerate(ns):
+        A = np.asarray(synth.gaussian_matrix(n, seed=30 + q), dtype=np.float32).astype(np.float64)
+        v = lv.View(dev(A, torch.float32), k, r_max=r)
+        v.set_drift_check(D)
+        views.append(v)
+        refs.append(O.reeval(A, k))
+    batch = lv.Batch(views)
+    for t in range(7):
+        for q, n in enumerate(ns):
+            U, V = synth.update_factors(n, r, 1, seed=40 + 10 * t + q)
+            U = np.asarray(U[0], dtype=np.float32).astype(np.float64)
+            V = np.asarray(V[0], dtype=np.float32).astype(np.float64)
+            batch.stage(q, dev(U, torch.float32), dev(V, torch.float32))
+            refs[q] = O.incr_update(refs[q], U, V)
+        if t == 4:
+            _perturb(lv, torch, views[1], k, 1e-2, 25)     # between the checks after rounds 3 and 6
+        batch.update()
+    torch.cuda.synchronize()
+    for q, v in enumerate(views):
+        st = v.stats()
+        note(f"view {q}: checks={st['drift_checks']} reanchors={st['drift_reanchors']}")
+        assert st["drift_checks"] == 2
+        assert st["drift_reanchors"] == (1 if q == 1 else 0)
+        got = read_all(v)
+        for i in refs[q]:
+            assert O.maxrel(got[i], refs[q][i]) < 1e-4
+    batch.close()
+    for v in views:
+        v.close()
+
+
+def test_set_drift_check_arguments():
+    lv = _lv()
+    import torch
+    view = lv.View(torch.zeros(256, 256, device="cuda"), 4)
+    with pytest.raises(lv.LinviewError):
+        view.set_drift_check(-1)
+    with pytest.raises(lv.LinviewError):
+        view.set_drift_check(4, float("nan"))
+    view.set_drift_check(4, 0.25, dev(np.ones(256), torch.float64))
+    st = view.stats()
+    assert st["drift_every"] == 4 and st["drift_tau"] == 0.25
+    view.set_drift_check(0)
+    assert view.stats()["drift_every"] == 0
+    view.close()
