@@ -50,7 +50,8 @@ def parse():
     p.add_argument("--no-secondary", action="store_true",
                    help="skip the rank-4, batched and serving workloads")
     p.add_argument("--serve-seconds", type=float, default=2.0)
-    p.add_argument("--only", choices=["rank4", "batched", "serving", "sums", "general", "models", "ols", "glin"],
+    p.add_argument("--only", choices=["rank4", "batched", "serving", "sums", "general", "models", "ols", "glin",
+                                      "fp64", "small", "serving32"],
                    help="run one secondary workload alone and print its result (for profilers)")
     return p.parse_args()
 
@@ -100,6 +101,96 @@ def bench_rank4(torch, lv, synth, dev, steps=200, drift_every=100):
                     "drift_check": drift}
     del A
     return out
+
+
+def _time_ms(torch, fn, reps=3):
+    """Best of `reps` event-timed runs of fn() on the current stream."""
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    return best
+
+
+def bench_fp64(torch, lv, synth, dev, steps=100):
+    """The headline view in the paper's precision (Sec. 7: double-precision
+    matrices): A^16, n = 8192, FP64, rank-1 updates; updates/s, algorithmic
+    HBM rate (one read and one write of each stored power, 80 n^2 bytes per
+    update) and FP64 re-evaluation (the library's f64 matrix-core GEMM and
+    torch.matmul)."""
+    n, k = 8192, 16
+    A = torch.from_numpy(synth.gaussian_matrix(n, seed=0, config=2)).to(dev)
+    U, V = synth.update_factors(n, 1, steps + 5, seed=0, config=2)
+    Ud, Vd = torch.from_numpy(U).to(dev), torch.from_numpy(V).to(dev)
+    view = lv.View(A, k)
+    view.update_batch(Ud[:5], Vd[:5])
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    view.update_batch(Ud[5:], Vd[5:])
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    n_pad = view.stats()["n_pad"]
+    view.close()
+    own = _time_ms(torch, lambda: lv.reeval(A, k, Ud[0], Vd[0]), reps=2)
+
+    def vendor():
+        X = torch.addmm(A, Ud[0], Vd[0].t())
+        for _ in range(4):
+            X = torch.matmul(X, X)
+        return X
+    tm = _time_ms(torch, vendor, reps=2)
+    alg = 2 * 8 * 5 * n_pad * n_pad
+    del A
+    return {"workload": "A^16 matrix-power view, n=8192, FP64, rank-1 updates (IncrExp)",
+            "ms_per_update": ms, "updates_per_s": 1000.0 / ms, "alg_bytes_per_update": alg,
+            "alg_GBps": alg / (ms * 1e-3) / 1e9,
+            "reeval_own_f64_mfma_ms": own, "reeval_torch_matmul_ms": tm,
+            "reeval_own_tflops": 2.0 * n ** 3 * 4 / (own * 1e-3) / 1e12,
+            "speedup_incremental_vs_best_reeval": min(own, tm) / ms}
+
+
+def bench_small_fp64(torch, lv, synth, dev, updates=100):
+    """The small configuration: A^16, n = 256, FP64, 100 rank-1 updates;
+    incremental updates on the GPU, GPU re-evaluation after each update, and
+    the FP64 oracle's incremental update and re-evaluation on the host."""
+    import oracle as O
+    n, k = 256, 16
+    A64 = synth.gaussian_matrix(n, seed=0, config=1)
+    Us, Vs = synth.update_factors(n, 1, updates, seed=0, config=1)
+    A = torch.from_numpy(A64).to(dev)
+    Ud, Vd = torch.from_numpy(Us).to(dev), torch.from_numpy(Vs).to(dev)
+    view = lv.View(A, k)
+    view.update_batch(Ud[:5], Vd[:5])
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    view.update_batch(Ud, Vd)
+    b.record()
+    torch.cuda.synchronize()
+    gpu_incr = a.elapsed_time(b) / updates
+    view.close()
+    gpu_reeval = _time_ms(torch, lambda: lv.reeval(A, k, Ud[0], Vd[0]))
+    P = O.reeval(A64, k)
+    t0 = time.perf_counter()
+    for t in range(updates):
+        P = O.incr_update(P, Us[t], Vs[t])
+    cpu_incr = (time.perf_counter() - t0) / updates * 1e3
+    t0 = time.perf_counter()
+    for _ in range(10):
+        O.reeval(A64, k)
+    cpu_reeval = (time.perf_counter() - t0) / 10 * 1e3
+    return {"workload": "A^16, n=256, FP64, 100 rank-1 updates",
+            "gpu_incremental_ms": gpu_incr, "gpu_reeval_ms": gpu_reeval,
+            "oracle_incremental_ms": cpu_incr, "oracle_reeval_ms": cpu_reeval,
+            "note": "fits in cache and is bound by launch latency; no roofline claim"}
 
 
 def bench_sums(torch, lv, synth, dev, steps=200):
@@ -414,13 +505,17 @@ def bench_batched(torch, lv, synth, dev, rounds=30):
 
 
 def bench_serving(torch, lv, synth, dev, seconds=2.0, rate=20000.0, r_coalesce=16, shadow=True,
-                  hold=(16, 0.03), drift_every=100):
+                  hold=(16, 0.03), drift_every=100, budget_bytes=None, evict=4):
     """32 views, n log-uniform in [2048, 16384], k = 16, FP32 (with bfloat16
     shadows by default); Poisson arrivals at `rate` requests/s over views with
     Zipf(1.1) popularity; per-view coalescing, continuous batching; rounds
     hold a view until it has hold[0] requests queued or its oldest has waited
     hold[1] s.  Every view runs the periodic drift check every
-    `drift_every` of its coalesced updates (inside the served rounds)."""
+    `drift_every` of its coalesced updates (inside the served rounds).
+    With budget_bytes the arena is that large and the admission queue is on:
+    views are added hottest first, those that do not fit wait (their
+    requests queue), and half-way through the run the `evict` coldest
+    admitted views are removed, which admits waiting views."""
     mode = lv.LV_FP32_BF16SHADOW if shadow else lv.LV_FP32
     g = synth.rng(0, 5, 0)
     ns = np.exp(g.uniform(np.log(2048), np.log(16384), size=32)).astype(int)
@@ -430,15 +525,24 @@ def bench_serving(torch, lv, synth, dev, seconds=2.0, rate=20000.0, r_coalesce=1
     probe = lv.Server(16 << 20, mode=mode, r_coalesce=r_coalesce)
     need = sum(probe.view_bytes(int(n), 16) for n in ns)
     probe.close()
-    srv = lv.Server((16 << 20) + need, mode=mode, r_coalesce=r_coalesce)
+    arena = (16 << 20) + need if budget_bytes is None else int(budget_bytes)
+    srv = lv.Server(arena, mode=mode, r_coalesce=r_coalesce)
     srv.set_hold(*hold)
-    ids = []
-    for v in range(32):
+    if budget_bytes is not None:
+        srv.set_admission_queue(True)
+    # views by popularity rank: hottest first (the add order decides admission under a budget)
+    rank_of = np.empty(32, dtype=int)
+    rank_of[perm] = np.arange(32)          # view perm[j] has popularity rank j
+    ids = [None] * 32
+    for v in sorted(range(32), key=lambda x: rank_of[x]):
         A = torch.from_numpy(synth.gaussian_matrix(int(ns[v]), seed=0, config=5, view=v).astype(np.float32)).to(dev)
-        ids.append(srv.add_view(A, 16))
-        srv.set_drift_check(ids[-1], drift_every)
+        ids[v] = srv.add_view(A, 16)
+        if srv.view_handle(ids[v]):      # admitted (not waiting)
+            srv.set_drift_check(ids[v], drift_every)
         del A
     torch.cuda.synchronize()
+    st_start = srv.stats()
+    removed = set()
     pool = []
     for v in range(32):
         U, V = synth.update_factors(int(ns[v]), 1, 8, seed=0, config=5, view=v)
@@ -449,20 +553,28 @@ def bench_serving(torch, lv, synth, dev, seconds=2.0, rate=20000.0, r_coalesce=1
     t0 = srv.now() + 0.05
     arrivals = t0 + np.cumsum(gaps)
     i = 0
+    half = count // 2
     while i < count:
         now = srv.now()
         while i < count and arrivals[i] <= now:
             v = int(targets[i])
-            u, w = pool[v]
-            srv.submit(ids[v], u[i % 8], w[i % 8], float(arrivals[i]))
+            if v not in removed:
+                u, w = pool[v]
+                srv.submit(ids[v], u[i % 8], w[i % 8], float(arrivals[i]))
             i += 1
+            if budget_bytes is not None and i == half:
+                # the coldest admitted views leave; their room admits waiting views
+                admitted = [v for v in range(32) if srv.view_handle(ids[v])]
+                for v in sorted(admitted, key=lambda x: -rank_of[x])[:evict]:
+                    srv.remove_view(ids[v])
+                    removed.add(v)
         srv.step()
     while srv.step() > 0:
         pass
     srv.drain()
     t_end = srv.now()
     st = srv.stats()
-    vst = [srv.view_stats(i) for i in ids]
+    vst = [srv.view_stats(ids[v]) for v in range(32) if v not in removed and srv.view_handle(ids[v])]
     srv.close()
     return {"workload": "32 views, n log-uniform [2048,16384], k=16, %s, Poisson %.0f req/s, Zipf(1.1), "
                         "hold %d requests / %.0f ms" % ("FP32 + BF16 shadows" if shadow else "FP32", rate, hold[0],
@@ -471,10 +583,16 @@ def bench_serving(torch, lv, synth, dev, seconds=2.0, rate=20000.0, r_coalesce=1
             "throughput_per_s": st["completed"] / (t_end - t0), "rounds": int(st["rounds"]),
             "mean_coalesced_rank": st["completed"] / max(st["coalesced_updates"], 1),
             "latency_p50_ms": st["latency_p50_s"] * 1e3, "latency_p99_ms": st["latency_p99_s"] * 1e3,
-            "arena_GB": need / 1e9,
+            "arena_GB": arena / 1e9, "views_need_GB": need / 1e9,
             "drift_check": {"every": drift_every, "checks": int(sum(x["drift_checks"] for x in vst)),
                             "reanchors": int(sum(x["drift_reanchors"] for x in vst)),
-                            "max_last_residual": float(max(x["last_residual"] for x in vst))}}
+                            "max_last_residual": float(max(x["last_residual"] for x in vst))},
+            **({} if budget_bytes is None else {
+                "budget_GB": arena / 1e9, "views_admitted_at_start": int(st_start["views"]),
+                "views_waiting_at_start": int(st_start["views_waiting"]), "views_removed_midway": len(removed),
+                "views_admitted_later": int(st["admitted_late"]), "views_still_waiting": int(st["views_waiting"]),
+                "requests_submitted": int(st["submitted"]),
+                "requests_waiting_for_admission": int(st["submitted"] - st["completed"])})}
 
 
 def counter_traffic(n, k, r):
@@ -501,32 +619,56 @@ def counter_traffic(n, k, r):
     return vals["bytes"]
 
 
-def cpu_baseline(A32, Us, Vs, k, budget_s):
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(A32, Us, Vs, k, budget_s, one_thread_s=8.0):
     """The FP64 oracle (unchanged) timed on the host on a bounded sample of
-    the same workload: as many of the first updates as fit in the budget."""
+    the same workload: as many of the first updates as fit in the budget
+    with the BLAS pool at its default size, then with one thread."""
     import oracle as O
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
+        threadpool_limits = None
         threads = os.cpu_count() or 1
     A = A32.astype(np.float64)
     t0 = time.perf_counter()
     P = O.reeval(A, k)
     t_setup = time.perf_counter() - t0
     log(f"cpu oracle: reeval (setup) {t_setup:.1f} s")
-    done, t0 = 0, time.perf_counter()
-    while done < len(Us):
-        P = O.incr_update(P, Us[done].astype(np.float64), Vs[done].astype(np.float64))
-        done += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    el = time.perf_counter() - t0
+
+    def run(P, first, budget):
+        done, t0 = 0, time.perf_counter()
+        while first + done < len(Us):
+            P = O.incr_update(P, Us[first + done].astype(np.float64), Vs[first + done].astype(np.float64))
+            done += 1
+            if time.perf_counter() - t0 >= budget:
+                break
+        return P, done, time.perf_counter() - t0
+
+    P, done, el = run(P, 0, budget_s)
+    one = None
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            _, d1, e1 = run(P, done, one_thread_s)
+        one = {"value": d1 / e1, "updates": d1, "seconds": e1}
+        log(f"cpu oracle: 1 thread {d1 / e1:.3f} updates/s")
     return {
         "value": done / el, "unit": "updates/s", "cores": int(threads), "kind": "oracle",
         "sample": f"{done} rank-1 updates of the same n={A.shape[0]} k={k} view in FP64 "
-                  f"({el:.1f} s); oracle re-evaluation of all powers took {t_setup:.1f} s",
-        "reeval_s": t_setup,
+                  f"({el:.1f} s); oracle re-evaluation of all powers took {t_setup:.1f} s; then "
+                  f"{one['updates'] if one else 0} more updates with one BLAS thread",
+        "reeval_s": t_setup, "nproc": os.cpu_count(), "cpu_model": _cpu_model(),
+        "one_thread": one,
     }
 
 
@@ -548,11 +690,14 @@ def main():
         fn = {"rank4": lambda: bench_rank4(torch, lv, synth, dev),
               "batched": lambda: bench_batched(torch, lv, synth, dev),
               "serving": lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds),
+              "serving32": lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds, budget_bytes=32e9),
               "sums": lambda: bench_sums(torch, lv, synth, dev),
               "general": lambda: bench_general(torch, lv, synth, dev),
               "models": lambda: bench_models(torch, lv, synth, dev),
               "ols": lambda: bench_ols(torch, lv, synth, dev),
-              "glin": lambda: bench_glin(torch, lv, synth, dev)}[args.only]
+              "glin": lambda: bench_glin(torch, lv, synth, dev),
+              "fp64": lambda: bench_fp64(torch, lv, synth, dev),
+              "small": lambda: bench_small_fp64(torch, lv, synth, dev)}[args.only]
         print(json.dumps({"only": args.only, "result": fn()}), flush=True)
         return
     n, k, r = args.n, args.k, args.rank
@@ -713,7 +858,9 @@ def main():
     torch.cuda.empty_cache()
     if not args.quick and not args.no_secondary:
         sec = {}
-        for name, fn in (("rank4_n16384", lambda: bench_rank4(torch, lv, synth, dev)),
+        for name, fn in (("fp64_n8192", lambda: bench_fp64(torch, lv, synth, dev)),
+                         ("small_n256_fp64", lambda: bench_small_fp64(torch, lv, synth, dev)),
+                         ("rank4_n16384", lambda: bench_rank4(torch, lv, synth, dev)),
                          ("sums_n8192", lambda: bench_sums(torch, lv, synth, dev)),
                          ("general_n8192", lambda: bench_general(torch, lv, synth, dev)),
                          ("models_k_sweep_n8192", lambda: bench_models(torch, lv, synth, dev)),
@@ -724,7 +871,9 @@ def main():
                          ("serving_32_views_fp32",
                           lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds, shadow=False)),
                          ("serving_32_views_5k",
-                          lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds, rate=5000.0))):
+                          lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds, rate=5000.0)),
+                         ("serving_32_views_32GB",
+                          lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds, budget_bytes=32e9))):
             sec[name] = fn()
             torch.cuda.empty_cache()
             log(f"{name}: {sec[name]}")

@@ -385,6 +385,8 @@ typedef struct {
   double latency_p50_s;       /* arrival -> completion, over completed requests */
   double latency_p99_s;
   double latency_max_s;
+  int32_t views_waiting;      /* views in the admission queue                   */
+  uint64_t admitted_late;     /* views admitted from the queue so far           */
 } lv_server_counters;
 
 /* arena: device, 256-byte aligned, >= 4 MiB (descriptor ring) plus the
@@ -402,13 +404,24 @@ size_t lv_server_view_bytes(const lv_server* s, int64_t n, int k);
  * device.  min_fill = 1 (the default) puts every pending view in every
  * round.  LV_EINVAL for min_fill < 1 or a negative (or NaN) max_wait_s. */
 lv_status lv_server_set_hold(lv_server* s, int min_fill, double max_wait_s);
-/* Admit a view of A^k (A: n x n device, lda >= n); LV_ENOMEM when no free
- * block is large enough (the caller may retry after removals). */
+/* Admit a view of A^k (A: n x n device, lda >= n).  When no free block is
+ * large enough: LV_ENOMEM, unless the admission queue is on (below), in
+ * which case the view waits: A is copied to pinned host memory (the call
+ * returns once the copy is done), the view gets its id, requests to it are
+ * accepted and queued, and it is admitted (created from the host copy) as
+ * soon as a removal frees room for it.  Waiting views are admitted in the
+ * order they were added, each one that fits.  LV_ENOMEM still when the view
+ * is larger than the whole arena. */
 lv_status lv_server_add_view(lv_server* s, const void* A, int64_t n, int64_t lda, int k,
                              int* view_id);
-/* Wait for in-flight rounds, then free the view and its block. */
+/* Admission queue on (enable != 0) or off (the default). */
+lv_status lv_server_set_admission_queue(lv_server* s, int enable);
+/* Wait for in-flight rounds, then free the view and its block, and admit
+ * waiting views that now fit.  A waiting view is dropped with its queued
+ * requests (they no longer count as submitted). */
 lv_status lv_server_remove_view(lv_server* s, int view_id);
-/* The view handle (for lv_view_read / lv_view_data); NULL if none. */
+/* The view handle (for lv_view_read / lv_view_data); NULL if none or
+ * while the view waits for admission. */
 lv_view* lv_server_view(lv_server* s, int view_id);
 /* Seconds on the server's clock (arrival times are on this clock). */
 double lv_server_now(const lv_server* s);
@@ -425,8 +438,9 @@ lv_status lv_server_submit(lv_server* s, int view_id, const void* u, const void*
 lv_status lv_server_step(lv_server* s, int* launched);
 /* Retire finished rounds without waiting; *completed = total applied. */
 lv_status lv_server_poll(lv_server* s, uint64_t* completed);
-/* Apply every queued request (launching rounds as room frees up), then wait
- * for every launched round. */
+/* Apply every queued request of the admitted views (launching rounds as
+ * room frees up), then wait for every launched round.  Requests of views
+ * still waiting for admission stay queued. */
 lv_status lv_server_drain(lv_server* s);
 lv_status lv_server_stats(const lv_server* s, lv_server_counters* out);
 /* Drain, destroy the views, release host resources (the caller frees the

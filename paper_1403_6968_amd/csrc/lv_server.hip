@@ -41,6 +41,14 @@ struct SView {
   std::deque<Pending> q;
   char* stage = nullptr;
   bool alive = false;
+  // waiting in the admission queue: A (n x n, pinned host memory, read by
+  // the creation kernels when the view is admitted), its order and power,
+  // and its place in the queue
+  bool waiting = false;
+  void* hostA = nullptr;
+  int64_t n = 0;
+  int k = 0;
+  uint64_t wait_seq = 0;
 };
 
 struct InFlight {
@@ -73,6 +81,8 @@ struct lv_server {
   bool slot_busy[kRingSlots] = {};
   uint64_t next_ticket = 1;
   uint64_t submitted = 0, completed = 0, rounds = 0, coalesced_updates = 0;
+  bool queue_views = false;      // admission queue on (views wait for arena space)
+  uint64_t next_wait_seq = 1, admitted_late = 0;
   std::vector<double> lat;
   std::chrono::steady_clock::time_point t0;
 };
@@ -119,6 +129,48 @@ size_t largest_free(const lv_server* s) {
   size_t m = 0;
   for (auto& b : s->free_blocks) m = b.second > m ? b.second : m;
   return m;
+}
+
+// Create a view in a fresh arena block of `bytes` at `off` from A (device
+// or pinned host memory).
+lv_status create_in_block(lv_server* s, SView& sv, const void* A, int64_t n, int64_t lda, int k, size_t off,
+                          size_t bytes) {
+  lv_view* v = nullptr;
+  const size_t fp = align_up(lv_view_footprint(n, k, s->rc, s->mode));
+  const lv_status st = lv_view_create(A, n, lda, k, s->rc, s->mode, s->arena + off, fp, s->stream, &v);
+  if (st != LV_OK) return st;
+  sv.view = v;
+  sv.off = off;
+  sv.bytes = bytes;
+  sv.stage = s->arena + off + fp;
+  sv.alive = true;
+  return LV_OK;
+}
+
+// Admit waiting views, in the order they arrived, each one that fits now.
+lv_status admit_waiting(lv_server* s) {
+  std::vector<int> order;
+  for (int i = 0; i < (int)s->views.size(); ++i)
+    if (s->views[i].waiting) order.push_back(i);
+  std::sort(order.begin(), order.end(),
+            [&](int a, int b) { return s->views[a].wait_seq < s->views[b].wait_seq; });
+  for (int i : order) {
+    SView& sv = s->views[i];
+    const size_t bytes = view_block_bytes(s, sv.n, sv.k);
+    size_t off = 0;
+    if (!arena_alloc(s, bytes, &off)) continue;
+    lv_status st = create_in_block(s, sv, sv.hostA, sv.n, sv.n, sv.k, off, bytes);
+    if (st == LV_OK) st = hip_check(hipStreamSynchronize(s->stream), "admission");   // host copy of A read
+    if (st != LV_OK) {
+      arena_free(s, off, bytes);
+      return st;
+    }
+    (void)hipHostFree(sv.hostA);
+    sv.hostA = nullptr;
+    sv.waiting = false;
+    s->admitted_late += 1;
+  }
+  return LV_OK;
 }
 
 // Retire finished rounds (block = wait for the oldest one first).
@@ -324,27 +376,45 @@ lv_status lv_server_set_hold(lv_server* s, int min_fill, double max_wait_s) {
   return LV_OK;
 }
 
+lv_status lv_server_set_admission_queue(lv_server* s, int enable) {
+  g_err[0] = 0;
+  if (!s) return fail(LV_EINVAL, "server is NULL");
+  s->queue_views = enable != 0;
+  return LV_OK;
+}
+
 lv_status lv_server_add_view(lv_server* s, const void* A, int64_t n, int64_t lda, int k, int* view_id) {
   g_err[0] = 0;
-  if (!s || !view_id) return fail(LV_EINVAL, "server or view_id is NULL");
+  if (!s || !view_id || !A) return fail(LV_EINVAL, "server, A or view_id is NULL");
+  if (lda < n) return fail(LV_EINVAL, "lda < n");
   const size_t bytes = view_block_bytes(s, n, k);
   if (bytes == 0) return fail(LV_EINVAL, "invalid view shape n=%lld k=%d r=%d", (long long)n, k, s->rc);
-  size_t off = 0;
-  if (!arena_alloc(s, bytes, &off))
-    return fail(LV_ENOMEM, "admission: view needs %zu bytes, largest free block is %zu", bytes, largest_free(s));
-  lv_view* v = nullptr;
-  const size_t fp = align_up(lv_view_footprint(n, k, s->rc, s->mode));
-  lv_status st = lv_view_create(A, n, lda, k, s->rc, s->mode, s->arena + off, fp, s->stream, &v);
-  if (st != LV_OK) { arena_free(s, off, bytes); return st; }
   SView sv;
-  sv.view = v;
-  sv.off = off;
-  sv.bytes = bytes;
-  sv.stage = s->arena + off + fp;
-  sv.alive = true;
+  size_t off = 0;
+  if (arena_alloc(s, bytes, &off)) {
+    const lv_status st = create_in_block(s, sv, A, n, lda, k, off, bytes);
+    if (st != LV_OK) { arena_free(s, off, bytes); return st; }
+  } else if (!s->queue_views || bytes > s->arena_bytes - kRingSlots * kSlotBytes) {
+    return fail(LV_ENOMEM, "admission: view needs %zu bytes, largest free block is %zu", bytes, largest_free(s));
+  } else {
+    // wait for arena space: keep A in pinned host memory until admission
+    const size_t abytes = (size_t)n * n * s->elem;
+    void* h = nullptr;
+    if (hipHostMalloc(&h, abytes, hipHostMallocDefault) != hipSuccess)
+      return fail(LV_ENOMEM, "pinned host copy of A (%zu bytes) for the admission queue failed", abytes);
+    lv_status st = hip_check(hipMemcpy2DAsync(h, (size_t)n * s->elem, A, (size_t)lda * s->elem, (size_t)n * s->elem,
+                                              (size_t)n, hipMemcpyDeviceToHost, s->stream), "copy A to the host");
+    if (st == LV_OK) st = hip_check(hipStreamSynchronize(s->stream), "copy A to the host");
+    if (st != LV_OK) { (void)hipHostFree(h); return st; }
+    sv.waiting = true;
+    sv.hostA = h;
+    sv.n = n;
+    sv.k = k;
+    sv.wait_seq = s->next_wait_seq++;
+  }
   int id = -1;
   for (int i = 0; i < (int)s->views.size(); ++i)
-    if (!s->views[i].alive && s->views[i].view == nullptr) { id = i; break; }
+    if (!s->views[i].alive && !s->views[i].waiting && s->views[i].view == nullptr) { id = i; break; }
   if (id < 0) { id = (int)s->views.size(); s->views.push_back(std::move(sv)); }
   else s->views[id] = std::move(sv);
   *view_id = id;
@@ -353,14 +423,22 @@ lv_status lv_server_add_view(lv_server* s, const void* A, int64_t n, int64_t lda
 
 lv_status lv_server_remove_view(lv_server* s, int id) {
   g_err[0] = 0;
-  if (!s || id < 0 || id >= (int)s->views.size() || !s->views[id].alive) return fail(LV_EINVAL, "no such view");
+  if (!s || id < 0 || id >= (int)s->views.size() || !(s->views[id].alive || s->views[id].waiting))
+    return fail(LV_EINVAL, "no such view");
+  if (s->views[id].waiting) {   // never admitted: drop it and its queued requests
+    SView& sv = s->views[id];
+    s->submitted -= sv.q.size();
+    (void)hipHostFree(sv.hostA);
+    sv = SView();
+    return LV_OK;
+  }
   lv_status st = drain(s);
   if (st != LV_OK) return st;
   SView& sv = s->views[id];
   lv_view_destroy(sv.view);
   arena_free(s, sv.off, sv.bytes);
   sv = SView();
-  return LV_OK;
+  return admit_waiting(s);
 }
 
 lv_view* lv_server_view(lv_server* s, int id) {
@@ -371,10 +449,11 @@ lv_view* lv_server_view(lv_server* s, int id) {
 double lv_server_now(const lv_server* s) { return s ? now_s(s->t0) : 0.0; }
 
 lv_status lv_server_submit(lv_server* s, int id, const void* u, const void* v, double arrival, uint64_t* ticket) {
-  if (!s || id < 0 || id >= (int)s->views.size() || !s->views[id].alive) return fail(LV_EINVAL, "no such view");
+  if (!s || id < 0 || id >= (int)s->views.size() || !(s->views[id].alive || s->views[id].waiting))
+    return fail(LV_EINVAL, "no such view");
   if (!u || !v) return fail(LV_EINVAL, "u or v is NULL");
   SView& sv = s->views[id];
-  const size_t bytes = (size_t)sv.view->n * s->elem;
+  const size_t bytes = (size_t)(sv.alive ? sv.view->n : sv.n) * s->elem;
   Pending p;
   p.ticket = s->next_ticket++;
   p.arrival = arrival >= 0.0 ? arrival : now_s(s->t0);
@@ -413,9 +492,14 @@ lv_status lv_server_stats(const lv_server* s, lv_server_counters* out) {
   out->completed = s->completed;
   out->rounds = s->rounds;
   out->coalesced_updates = s->coalesced_updates;
-  int nv = 0;
-  for (auto& v : s->views) nv += v.alive ? 1 : 0;
+  int nv = 0, nw = 0;
+  for (auto& v : s->views) {
+    nv += v.alive ? 1 : 0;
+    nw += v.waiting ? 1 : 0;
+  }
   out->views = nv;
+  out->views_waiting = nw;
+  out->admitted_late = s->admitted_late;
   out->arena_free = 0;
   for (auto& b : s->free_blocks) out->arena_free += b.second;
   if (!s->lat.empty()) {
@@ -432,8 +516,10 @@ lv_status lv_server_stats(const lv_server* s, lv_server_counters* out) {
 void lv_server_destroy(lv_server* s) {
   if (!s) return;
   (void)drain(s);
-  for (auto& v : s->views)
+  for (auto& v : s->views) {
     if (v.alive) lv_view_destroy(v.view);
+    if (v.hostA) (void)hipHostFree(v.hostA);
+  }
   for (int i = 0; i < kRingSlots; ++i)
     if (s->pinned[i]) (void)hipHostFree(s->pinned[i]);
   s->lanes.destroy();

@@ -47,7 +47,7 @@ EXPORTED = (
     "lv_ols_read", "lv_ols_info", "lv_ols_destroy",
     "lv_glin_footprint", "lv_glin_create", "lv_glin_update", "lv_glin_read", "lv_glin_destroy",
     "lv_server_poll", "lv_server_drain", "lv_server_stats", "lv_server_destroy",
-    "lv_stream_probe", "lv_powers_update_noalloc", "lv_view_set_drift_check",
+    "lv_stream_probe", "lv_powers_update_noalloc", "lv_view_set_drift_check", "lv_server_set_admission_queue",
 )
 
 
@@ -82,6 +82,7 @@ class lv_server_counters(ctypes.Structure):
         ("coalesced_updates", ctypes.c_uint64), ("views", ctypes.c_int32),
         ("arena_free", ctypes.c_size_t), ("latency_p50_s", ctypes.c_double),
         ("latency_p99_s", ctypes.c_double), ("latency_max_s", ctypes.c_double),
+        ("views_waiting", ctypes.c_int32), ("admitted_late", ctypes.c_uint64),
     ]
 
 
@@ -167,6 +168,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "lv_stream_probe": (I32, [I32, P, P, SZ, I32, I32, I32, P]),
         "lv_powers_update_noalloc": (I32, [c.POINTER(P), I64, I64, I32, I32, P, P, I64, I64, I64, P]),
         "lv_view_set_drift_check": (I32, [P, I64, c.c_double, P, P]),
+        "lv_server_set_admission_queue": (I32, [P, I32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -644,6 +646,11 @@ class Server:
         oldest has waited max_wait_s (min_fill = 1: every pending view)."""
         _check(load().lv_server_set_hold(self.handle, min_fill, max_wait_s))
 
+    def set_admission_queue(self, enable: bool) -> None:
+        """Views that do not fit wait (A kept on the host) and are admitted
+        when removals free room."""
+        _check(load().lv_server_set_admission_queue(self.handle, int(bool(enable))))
+
     def add_view(self, A: torch.Tensor, k: int) -> int:
         a, lda = _mat(A, self.dtype, "A")
         vid = ctypes.c_int()
@@ -693,6 +700,11 @@ class Server:
         if not h:
             raise LinviewError(LV_EINVAL, f"no view {vid}")
         return ctypes.c_void_p(h)
+
+    def view_handle(self, vid: int):
+        """The admitted view's handle, or None (waiting or removed)."""
+        h = load().lv_server_view(self.handle, vid)
+        return ctypes.c_void_p(h) if h else None
 
     def set_drift_check(self, vid: int, every: int, tau: float = -1.0, z=None) -> None:
         """Periodic drift check of view vid every `every` of its (coalesced)

@@ -105,3 +105,48 @@ def test_batch_errors():
     with pytest.raises(lv.LinviewError):
         batch.stage(1)                                 # no such view
     batch.close(); a.close(); b.close()
+
+
+def test_batched_workload_full_size_against_oracle():
+    """The batched benchmark's workload at its real size: 64 views, n in
+    {512, 1024, 2048, 4096}, k in {8, 16}, ranks 1..8, FP32, drawn by the
+    same generator as bench.py; three rounds through one batch (autotuned
+    tiles, the round planner's lane split at 64 views), then every element of
+    every stored power of every view against the FP64 oracle."""
+    need_gpu()
+    import torch
+    from paper_1403_6968_amd import linview as lv
+    g = synth.rng(0, 4, 0)
+    ns = g.choice([512, 1024, 2048, 4096], size=64)
+    ks = g.choice([8, 16], size=64)
+    rs = g.integers(1, 9, size=64)
+    rounds = 3
+    views, ref = [], []
+    for v in range(64):
+        n, k, r = int(ns[v]), int(ks[v]), int(rs[v])
+        A = synth.gaussian_matrix(n, seed=0, config=4, view=v).astype(np.float32).astype(np.float64)
+        views.append(lv.View(dev(A, torch.float32), k, r_max=r))
+        ref.append(O.reeval(A, k))
+    note("64 views created")
+    batch = lv.Batch(views)
+    for t in range(rounds):
+        for v in range(64):
+            n, r = int(ns[v]), int(rs[v])
+            U, V = synth.update_factors(n, r, rounds, seed=0, config=4, view=v)
+            U = U[t].astype(np.float32).astype(np.float64)
+            V = V[t].astype(np.float32).astype(np.float64)
+            batch.stage(v, dev(U, torch.float32), dev(V, torch.float32))
+            ref[v] = O.incr_update(ref[v], U, V)
+        batch.update()
+    torch.cuda.synchronize()
+    worst = 0.0
+    for v in range(64):
+        got = read_all(views[v])
+        for i in ref[v]:
+            err = O.maxrel(got[i], ref[v][i])
+            worst = max(worst, err)
+            assert err < 1e-4, f"view {v} (n={ns[v]}, k={ks[v]}, r={rs[v]}) A^{i}: maxrel {err:.2e}"
+    note(f"64 views after {rounds} rounds: worst maxrel {worst:.2e}")
+    batch.close()
+    for x in views:
+        x.close()

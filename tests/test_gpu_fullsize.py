@@ -1,10 +1,10 @@
 """Full-size parity: the benchmark's workload (A^16, n = 8192, FP32, 1000
 rank-1 updates applied with lv_view_update_batch as bench.py does), checked
-every 100 updates on sampled rows and columns of every stored power.
-
-The oracle computes each sampled row / column of A_t^(2^j) by definition
-(repeated vector-matrix products with the FP64 accumulated A_t, see
-oracle.power_rows / power_cols), so no n x n power is formed on the host.
+every 100 updates element by element on every stored power against the
+oracle's re-evaluation of the accumulated A_t (oracle.reeval, FP64), and on
+sampled rows and columns against the definition: each sampled row / column
+of A_t^(2^j) by repeated vector-matrix products with the FP64 accumulated
+A_t (oracle.power_rows / power_cols), no n x n power formed.
 
 Tolerances over the samples: maxrel 1e-4 (FP32).  deltarel (error of the
 accumulated change) is bounded by FP32 storage itself: every update adds a
@@ -66,7 +66,13 @@ def test_bench_workload_sampled_every_100_updates():
             C = At @ C
         return out
 
+    def gpu_full():
+        return {i: view.read(i).double().cpu().numpy() for i in powers}
+
     A64 = A.astype(np.float64)
+    full0, rfull0 = gpu_full(), O.reeval(A64, k)
+    for i in powers:      # creation: one rounding of the FP64 chain
+        assert O.maxrel(full0[i], rfull0[i]) < 1e-6
     g0, r0 = gpu_samples(), ref_samples(A64)
     # ref_samples' recurrence agrees with the oracle's definition-based routine
     assert O.maxrel(r0[16][0], O.power_rows(A64, 16, rows)) < 1e-12
@@ -93,6 +99,18 @@ def test_bench_workload_sampled_every_100_updates():
             assert mr < 1e-4, f"P_{i} maxrel {mr:.3e} after {t}"
             assert dr < dtol, f"P_{i} deltarel {dr:.3e} >= {dtol:.3e} after {t}"
         note(f"after {t0 + every}: maxrel/deltarel " + " ".join(msg))
+        # every element of every stored power against the oracle's re-evaluation
+        full, rfull = gpu_full(), O.reeval(At, k)
+        msg = []
+        for i in powers:
+            mr = O.maxrel(full[i], rfull[i])
+            dr = O.deltarel(full[i], full0[i], rfull[i], rfull0[i])
+            dtol = 1e-2 + 4 * np.sqrt(t) * 2.0 ** -24 * np.abs(rfull[i]).max() / np.abs(rfull[i] - rfull0[i]).max()
+            msg.append(f"P{i}: {mr:.2e}/{dr:.2e}(<{dtol:.1e})")
+            assert mr < 1e-4, f"P_{i} full maxrel {mr:.3e} after {t}"
+            assert dr < dtol, f"P_{i} full deltarel {dr:.3e} >= {dtol:.3e} after {t}"
+        del full, rfull
+        note(f"after {t0 + every}, every element: " + " ".join(msg))
     # the stored chain after 1000 FP32 updates still satisfies P_{2i} = P_i P_i
     z = dev(synth.rng(0, 2, 9).standard_normal(n), torch.float64)
     res = view.drift_check(z, tau=1e-3).cpu().numpy()
