@@ -18,7 +18,9 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblinview.so")
+# LINVIEW_LIBRARY selects another build of the same library (the host
+# AddressSanitizer build of the CPU tests); there is no fallback either way.
+LIB_PATH = os.environ.get("LINVIEW_LIBRARY") or os.path.join(_HERE, "liblinview.so")
 
 LV_OK, LV_EINVAL, LV_ENOMEM, LV_EDEVICE, LV_ESTATE = 0, 1, 2, 3, 4
 LV_FP64, LV_FP32, LV_FP32_BF16SHADOW = 0, 1, 2
