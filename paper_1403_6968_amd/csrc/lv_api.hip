@@ -523,17 +523,21 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
         // read-only skinny pass on the matrix cores (from the shadow, or from
         // the float power), FP64 Gram, then the rank update (which rewrites
         // the shadow after the skinny pass has read it)
+        // with the float power at R = 16 or 32 the skinny pass applies the
+        // update itself (one read of P_j); else the update pass follows
+        const bool fused_upd = !v->shadowed() && skinny_fuses_update(R);
         st = timed(v, 0, s, "skinny", [&] {
           return v->shadowed() ? launch_skinny_bf16(R, v->shadow(j), L.ldp, L.n_pad, v->tile_rows[j], sU, sV, L.W,
                                                     v->partX<float>(j), v->partY<float>(j), s)
                                : launch_skinny_f32(R, v->P<float>(j), L.ldp, L.n_pad, v->tile_rows[j], sU, sV, L.W,
-                                                   v->partX<float>(j), v->partY<float>(j), s);
+                                                   v->partX<float>(j), v->partY<float>(j), s, kWantX | kWantY,
+                                                   fused_upd);
         });
         if (st == LV_OK)
           st = timed(v, 0, s, "gram", [&] {
             return launch_level_gram<float>(R, sU, sV, L.W, L.n_pad, v->partG(j), s);
           });
-        if (st == LV_OK)
+        if (st == LV_OK && !fused_upd)
           st = timed(v, 0, s, "update", [&] {
             return launch_level_update<float>(R, v->P<float>(j), L.ldp, L.n_pad, sU, sV, L.W, s,
                                               v->shadowed() ? v->shadow(j) : nullptr, v->shadowed());

@@ -206,13 +206,23 @@ inline int skinny_blocks_for(int R) { return R <= 32 ? 1 : 2; }   // R <= 64 per
 
 // The same products from the float power P (v_mfma_f32_32x32x2f32, float
 // products and accumulation), R <= 128 (32 factor columns per launch; X alone: 64).
+// update: also apply P += U_j V_j^T in the same pass (one read and one write
+// of P; R = 16 or 32, X and Y both, see skinny_fuses_update).
 hipError_t launch_skinny_f32(int R, const float* P, int64_t ldp, int64_t n_pad, int tile_rows,
                              const float* slabU, const float* slabV, int W, float* partX, float* partY,
-                             hipStream_t s, int want = kWantX | kWantY);
+                             hipStream_t s, int want = kWantX | kWantY, bool update = false);
+// nb: the width class below, plus 2 for the update-fused kernels.
 hipError_t launch_skinny_f32_multi(int nb, const SkinnyDesc* ds, int nd, int blocks, hipStream_t s);
 // Width class of a float skinny launch of at most 32 factor columns (0: the
 // 16-wide pass for R <= 16; 1: one 32-column factor block).
 inline int skinny_f32_blocks(int R) { return R <= 16 ? 0 : 1; }
+// Float level ranks whose skinny pass on the matrix cores also applies the
+// rank update (a second pass over P would otherwise follow).  The kernels
+// take R = 16 or 32; at 32 the fused block (one per CU by its LDS, one
+// 32-row chunk in flight) is slower than the skinny pass plus the update
+// pass (839 vs 771 us at n = 16384), so only R = 16 uses it.
+inline bool skinny_fuses_update(int R) { return R == 16; }
+inline bool skinny_update_kernel(int R) { return R == 16 || R == 32; }
 
 // S = bf16(P) for `count` consecutive floats (count a multiple of 4); with a
 // non-null gate only when *gate != 0.

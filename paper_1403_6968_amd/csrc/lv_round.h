@@ -156,6 +156,10 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
               skinny[skinny_blocks_for(per)].push_back({v->shadow(j), L.ldp, (int)L.n_pad, trows, sU + c0, Vj + c0,
                                                         L.W, per, v->partX<T>(j) + c0, v->partY<T>(j) + c0, R,
                                                         L.nct, 0});
+          } else if (skinny_fuses_update(R)) {
+            // the skinny pass applies the update too (class + 2: the fused kernels)
+            skinny32[2 + skinny_f32_blocks(R)].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, trows, sU, Vj, L.W, R,
+                                                          v->partX<T>(j), v->partY<T>(j), R, L.nct, 0});
           } else {
             const int per = R <= 32 ? R : 32;
             for (int c0 = 0; c0 < R; c0 += per)
@@ -165,8 +169,9 @@ Plan make_plan(const std::vector<lv_view*>& views, const std::vector<RoundInput>
           }
           gram[R].push_back({sU, Vj, L.W, (int)L.n_pad, kGramRows, v->partG(j), gram_tiles(L.n_pad), 0});
           gsum.push_back({v->partG(j), gram_tiles(L.n_pad), R * R, 0});
-          (v->shadowed() ? updsh : upd)[R].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, upd_rows, sU, Vj, L.W,
-                                                      upd_nct, 0, v->shadowed() ? v->shadow(j) : nullptr});
+          if (v->shadowed() || !skinny_fuses_update(R))
+            (v->shadowed() ? updsh : upd)[R].push_back({v->P<T>(j), L.ldp, (int)L.n_pad, upd_rows, sU, Vj, L.W,
+                                                        upd_nct, 0, v->shadowed() ? v->shadow(j) : nullptr});
           tail[R].push_back({v->partX<T>(j), v->partY<T>(j), v->partG(j), L.nct, nrt, (int)L.n_pad, sU, sV, L.W,
                              0, 1});
           continue;

@@ -215,6 +215,47 @@ __global__ void __launch_bounds__(256) k_skinny_bf16_multi(const SkinnyDesc* __r
                   local % d.nct, local / d.nct);
 }
 
+
+// Update fused into the float skinny pass (R = 16 or 32 factor columns, one
+// launch): blocks of 512 threads, waves 0-3 form X and Y on the matrix cores
+// as the read-only pass does and waves 4-7 apply P += U_j V_j^T to the same
+// chunk on the vector units: update wave wu takes rows wu + 4 i of the chunk
+// and lane g the columns 4 g .. 4 g + 3; the old values come from the chunk
+// in LDS, U_j rows of the chunk from sUr, V_j rows of the tile's columns
+// from sVc (sVc[c][k] = V_j[col0 + k][c]); the delta is summed over c in
+// order from zero and added once; the new rows go straight to HBM.  The
+// matrix-core and vector work of a chunk share the SIMDs.
+template <int CR, int SW, int UW>
+__device__ __forceinline__ void chunk_update(float* __restrict__ P, const int64_t ldp, const int col0, const int cr0,
+                                             const int R, const float (*sP)[SW], const float (*sUr)[UW],
+                                             const float (*sVc)[SW], const int wu, const int lane) {
+  float d[CR / 4][4];
+#pragma unroll
+  for (int i = 0; i < CR / 4; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) d[i][q] = 0.f;
+  for (int c0 = 0; c0 < R; c0 += 4) {
+    f32x4 v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = *reinterpret_cast<const f32x4*>(&sVc[c0 + e][4 * lane]);
+#pragma unroll
+    for (int i = 0; i < CR / 4; ++i) {
+      const f32x4 u = *reinterpret_cast<const f32x4*>(&sUr[wu + 4 * i][c0]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d[i][q] = fma(u[e], v[e][q], d[i][q]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < CR / 4; ++i) {
+    f32x4 p = *reinterpret_cast<const f32x4*>(&sP[wu + 4 * i][4 * lane]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) p[q] += d[i][q];
+    __builtin_nontemporal_store(p, reinterpret_cast<f32x4*>(P + (int64_t)(cr0 + wu + 4 * i) * ldp + col0 + 4 * lane));
+  }
+}
+
 // Float skinny pass.  Tile: tile_rows x 256 columns of P, chunks of 32 rows
 // through LDS (the next chunk of P and V_j held in registers meanwhile);
 // factor columns padded with zeros to 32 NB (NB <= 2).
@@ -226,7 +267,7 @@ __global__ void __launch_bounds__(256) k_skinny_bf16_multi(const SkinnyDesc* __r
 // A group of four f32 steps covers 8 summation indices: lanes 0-31 supply
 // index g + e and lanes 32-63 index g + 4 + e in step e, for both operands.
 // `want` selects the products formed (bit 0: X, bit 1: Y; uniform).
-template <int NB>
+template <int NB, bool UPD = false>
 __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, const int64_t ldp, const int n_pad,
                                                 const int tile_rows, const float* __restrict__ Uj,
                                                 const float* __restrict__ Vj, const int W, const int R,
@@ -236,13 +277,18 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
   constexpr int RP = 32 * NB;
   constexpr int CR = 32;           // rows per chunk
   constexpr int FP = 4;            // LDS row padding (floats)
+  constexpr int NT = UPD ? 512 : 256;
   static_assert(NB <= 2, "the X exchange buffer must fit in the chunk buffer");
+  static_assert(!UPD || NB == 1, "the fused update takes all factor columns in one launch");
   __shared__ __align__(16) float sP[CR][TCB + FP];
   __shared__ __align__(16) float sUt[RP][TCB + FP];
   __shared__ __align__(16) float sVt[RP][CR + FP];
+  __shared__ __align__(16) float sVc[UPD ? RP : 1][TCB + FP];
+  __shared__ __align__(16) float sUr[UPD ? CR : 1][RP + FP];
   float* xbuf = &sP[0][0];         // [4 waves][NB][16 values][64 lanes]
 
   const int tid = threadIdx.x;
+  const bool mwave = !UPD || tid < 256;   // matrix-core waves (all of them without the update)
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int col0 = ct * TCB;
@@ -266,12 +312,27 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
       pv[i] = c < R ? Vj[(int64_t)(r0 + rr) * W + c] : 0.f;
     });
   };
-  fetch(row0);
+  // update waves: the chunk's U_j rows (thread t = tid - 256 holds entries t + 256 i)
+  float pu[UPD ? VPT : 1];
+  auto fetch_u = [&](const int r0) {
+    static_for<0, VPT>([&](auto i) {
+      const int idx = tid - 256 + 256 * i;
+      const int rr = idx / RP, c = idx % RP;
+      pu[i] = c < R ? Uj[(int64_t)(r0 + rr) * W + c] : 0.f;
+    });
+  };
+  if (mwave) fetch(row0);
+  else if constexpr (UPD) fetch_u(row0);
 
   if (wx)
-    for (int idx = tid; idx < RP * TCB; idx += 256) {
+    for (int idx = tid; idx < RP * TCB; idx += NT) {
       const int k = idx / RP, c = idx % RP;
       sUt[c][k] = c < R ? Uj[(int64_t)(col0 + k) * W + c] : 0.f;
+    }
+  if constexpr (UPD)
+    for (int idx = tid; idx < RP * TCB; idx += NT) {
+      const int k = idx / RP, c = idx % RP;
+      sVc[c][k] = c < R ? Vj[(int64_t)(col0 + k) * W + c] : 0.f;
     }
 
   v16f yacc[NB][2];
@@ -284,12 +345,26 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
 
   for (int cr0 = row0; cr0 < rend; cr0 += CR) {
     __syncthreads();   // the previous chunk's exchange buffer has been read
-    static_for<0, CR / 4>([&](auto i) { *reinterpret_cast<f32x4*>(&sP[srow + 4 * i][sgrp * 4]) = pre[i]; });
-    static_for<0, VPT>([&](auto i) {
-      const int idx = tid + 256 * i;
-      sVt[idx % RP][idx / RP] = pv[i];
-    });
+    if (mwave) {
+      static_for<0, CR / 4>([&](auto i) { *reinterpret_cast<f32x4*>(&sP[srow + 4 * i][sgrp * 4]) = pre[i]; });
+      static_for<0, VPT>([&](auto i) {
+        const int idx = tid + 256 * i;
+        sVt[idx % RP][idx / RP] = pv[i];
+      });
+    } else if constexpr (UPD) {
+      static_for<0, VPT>([&](auto i) {
+        const int idx = tid - 256 + 256 * i;
+        sUr[idx / RP][idx % RP] = pu[i];
+      });
+    }
     __syncthreads();
+    if constexpr (UPD) {
+      if (!mwave) {
+        if (cr0 + CR < rend) fetch_u(cr0 + CR);
+        chunk_update<CR, TCB + FP, RP + FP>(const_cast<float*>(P), ldp, col0, cr0, R, sP, sUr, sVc, wave - 4, lane);
+        continue;
+      }
+    }
     if (cr0 + CR < rend) fetch(cr0 + CR);
 
     if constexpr (NB == 1) {
@@ -386,7 +461,7 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
     }
   }
 
-  if (!wy) return;
+  if (!wy || !mwave) return;
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
@@ -408,6 +483,7 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
 // C[4 (l / 16) + v][l % 16].  A group of four steps covers 16 summation
 // indices: lane l supplies index g + 4 (l / 16) + e in step e, for both
 // operands.
+template <bool UPD = false>
 __device__ __forceinline__ void skinny16_f32_body(const float* __restrict__ P, const int64_t ldp, const int n_pad,
                                                   const int tile_rows, const float* __restrict__ Uj,
                                                   const float* __restrict__ Vj, const int W, const int R,
@@ -418,12 +494,16 @@ __device__ __forceinline__ void skinny16_f32_body(const float* __restrict__ P, c
   constexpr int RP = 16;
   constexpr int CR = 32;           // rows per chunk
   constexpr int FP = 4;            // LDS row padding (floats)
+  constexpr int NT = UPD ? 512 : 256;
   __shared__ __align__(16) float sP[CR][TCB + FP];
   __shared__ __align__(16) float sUt[RP][TCB + FP];
   __shared__ __align__(16) float sVt[RP][CR + FP];
+  __shared__ __align__(16) float sVc[UPD ? RP : 1][TCB + FP];
+  __shared__ __align__(16) float sUr[UPD ? CR : 1][RP + FP];
   float* xbuf = &sP[0][0];         // [4 waves][2 row blocks][4 values][64 lanes]
 
   const int tid = threadIdx.x;
+  const bool mwave = !UPD || tid < 256;   // matrix-core waves (all of them without the update)
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int col0 = ct * TCB;
@@ -446,12 +526,27 @@ __device__ __forceinline__ void skinny16_f32_body(const float* __restrict__ P, c
       pv[i] = c < R ? Vj[(int64_t)(r0 + rr) * W + c] : 0.f;
     });
   };
-  fetch(row0);
+  // update waves: the chunk's U_j rows (thread t = tid - 256 holds entries t + 256 i)
+  float pu[UPD ? VPT : 1];
+  auto fetch_u = [&](const int r0) {
+    static_for<0, VPT>([&](auto i) {
+      const int idx = tid - 256 + 256 * i;
+      const int rr = idx / RP, c = idx % RP;
+      pu[i] = c < R ? Uj[(int64_t)(r0 + rr) * W + c] : 0.f;
+    });
+  };
+  if (mwave) fetch(row0);
+  else if constexpr (UPD) fetch_u(row0);
 
   if (wx)
-    for (int idx = tid; idx < RP * TCB; idx += 256) {
+    for (int idx = tid; idx < RP * TCB; idx += NT) {
       const int k = idx / RP, c = idx % RP;
       sUt[c][k] = c < R ? Uj[(int64_t)(col0 + k) * W + c] : 0.f;
+    }
+  if constexpr (UPD)
+    for (int idx = tid; idx < RP * TCB; idx += NT) {
+      const int k = idx / RP, c = idx % RP;
+      sVc[c][k] = c < R ? Vj[(int64_t)(col0 + k) * W + c] : 0.f;
     }
 
   v4f yacc[4];
@@ -460,12 +555,30 @@ __device__ __forceinline__ void skinny16_f32_body(const float* __restrict__ P, c
 
   for (int cr0 = row0; cr0 < rend; cr0 += CR) {
     __syncthreads();   // the previous chunk's exchange buffer has been read
-    static_for<0, CR / 4>([&](auto i) { *reinterpret_cast<f32x4*>(&sP[srow + 4 * i][sgrp * 4]) = pre[i]; });
-    static_for<0, VPT>([&](auto i) {
-      const int idx = tid + 256 * i;
-      sVt[idx % RP][idx / RP] = pv[i];
-    });
+    if (mwave) {
+      static_for<0, CR / 4>([&](auto i) { *reinterpret_cast<f32x4*>(&sP[srow + 4 * i][sgrp * 4]) = pre[i]; });
+      static_for<0, VPT>([&](auto i) {
+        const int idx = tid + 256 * i;
+        sVt[idx % RP][idx / RP] = pv[i];
+      });
+    } else if constexpr (UPD) {
+      static_for<0, VPT>([&](auto i) {
+        const int idx = tid - 256 + 256 * i;
+        sUr[idx / RP][idx % RP] = pu[i];
+      });
+    }
     __syncthreads();
+    if constexpr (UPD) {
+      if (!mwave) {
+        if (cr0 + CR < rend) fetch_u(cr0 + CR);
+        chunk_update<CR, TCB + FP, RP + FP>(const_cast<float*>(P), ldp, col0, cr0, R, sP, sUr, sVc, wave - 4, lane);
+        if (wx) {              // the X exchange below overwrites the chunk: take part in its barriers
+          __syncthreads();
+          __syncthreads();
+        }
+        continue;
+      }
+    }
     if (cr0 + CR < rend) fetch(cr0 + CR);
 
     // X partial over this wave's 64 columns, two 16-row blocks
@@ -521,7 +634,7 @@ __device__ __forceinline__ void skinny16_f32_body(const float* __restrict__ P, c
     }
   }
 
-  if (!wy) return;
+  if (!wy || !mwave) return;
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) {
     const int col = col0 + wave * 64 + cb * 16 + l16;
@@ -533,30 +646,32 @@ __device__ __forceinline__ void skinny16_f32_body(const float* __restrict__ P, c
   }
 }
 
-__global__ void __launch_bounds__(256) k_skinny16_f32(const SkinnyDesc d) {
-  skinny16_f32_body(static_cast<const float*>(d.src), d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.R, d.partX,
-                    d.partY, d.pR, d.want, blockIdx.x, blockIdx.y);
+template <bool UPD>
+__global__ void __launch_bounds__(UPD ? 512 : 256) k_skinny16_f32(const SkinnyDesc d) {
+  skinny16_f32_body<UPD>(static_cast<const float*>(d.src), d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.R,
+                         d.partX, d.partY, d.pR, d.want, blockIdx.x, blockIdx.y);
 }
 
-__global__ void __launch_bounds__(256) k_skinny16_f32_multi(const SkinnyDesc* __restrict__ ds, int nd) {
+template <bool UPD>
+__global__ void __launch_bounds__(UPD ? 512 : 256) k_skinny16_f32_multi(const SkinnyDesc* __restrict__ ds, int nd) {
   const SkinnyDesc d = ds[find_skinny(ds, nd, (int)blockIdx.x)];
   const int local = (int)blockIdx.x - d.block_begin;
-  skinny16_f32_body(static_cast<const float*>(d.src), d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.R, d.partX,
-                    d.partY, d.pR, d.want, local % d.nct, local / d.nct);
+  skinny16_f32_body<UPD>(static_cast<const float*>(d.src), d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.R,
+                         d.partX, d.partY, d.pR, d.want, local % d.nct, local / d.nct);
 }
 
-template <int NB>
-__global__ void __launch_bounds__(256) k_skinny_f32(const SkinnyDesc d) {
-  skinny_f32_body<NB>(static_cast<const float*>(d.src), d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.R,
-                      d.partX, d.partY, d.pR, d.want, blockIdx.x, blockIdx.y);
+template <int NB, bool UPD>
+__global__ void __launch_bounds__(UPD ? 512 : 256) k_skinny_f32(const SkinnyDesc d) {
+  skinny_f32_body<NB, UPD>(static_cast<const float*>(d.src), d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.R,
+                           d.partX, d.partY, d.pR, d.want, blockIdx.x, blockIdx.y);
 }
 
-template <int NB>
-__global__ void __launch_bounds__(256) k_skinny_f32_multi(const SkinnyDesc* __restrict__ ds, int nd) {
+template <int NB, bool UPD>
+__global__ void __launch_bounds__(UPD ? 512 : 256) k_skinny_f32_multi(const SkinnyDesc* __restrict__ ds, int nd) {
   const SkinnyDesc d = ds[find_skinny(ds, nd, (int)blockIdx.x)];
   const int local = (int)blockIdx.x - d.block_begin;
-  skinny_f32_body<NB>(static_cast<const float*>(d.src), d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.R,
-                      d.partX, d.partY, d.pR, d.want, local % d.nct, local / d.nct);
+  skinny_f32_body<NB, UPD>(static_cast<const float*>(d.src), d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.R,
+                           d.partX, d.partY, d.pR, d.want, local % d.nct, local / d.nct);
 }
 
 // X-only float pass on the matrix cores: partial X = P U for R <= 16 NB
@@ -690,9 +805,21 @@ hipError_t launch_skinny_bf16_multi(int nb, const SkinnyDesc* ds, int nd, int bl
 
 hipError_t launch_skinny_f32(int R, const float* P, int64_t ldp, int64_t n_pad, int tile_rows,
                              const float* slabU, const float* slabV, int W, float* partX, float* partY,
-                             hipStream_t s, int want) {
+                             hipStream_t s, int want, bool update) {
   if (R < 1 || R > 128 || (R > 64 && R % 64 != 0) || n_pad % TCB != 0 || tile_rows % 32 != 0)
     return hipErrorInvalidValue;
+  if (update) {
+    // one launch over all R columns with the update fused (X and Y both)
+    if (!skinny_update_kernel(R) || want != (kWantX | kWantY)) return hipErrorInvalidValue;
+    const int nct = (int)(n_pad / TCB);
+    const dim3 grid((unsigned)nct, (unsigned)((n_pad + tile_rows - 1) / tile_rows));
+    const SkinnyDesc d{P, ldp, (int)n_pad, tile_rows, slabU, slabV + (W - R), W, R, partX, partY, R, nct, 0, want};
+    if (R <= 16)
+      hipLaunchKernelGGL(k_skinny16_f32<true>, grid, dim3(512), 0, s, d);
+    else
+      hipLaunchKernelGGL((k_skinny_f32<1, true>), grid, dim3(512), 0, s, d);
+    return hipGetLastError();
+  }
   if (want == kWantX) {
     // X only: the direct-operand pass (row tiling of its own; the X partials
     // do not depend on it)
@@ -723,9 +850,9 @@ hipError_t launch_skinny_f32(int R, const float* P, int64_t ldp, int64_t n_pad, 
     const SkinnyDesc d{P, ldp, (int)n_pad, tile_rows, slabU + c0, Vj + c0, W, per, partX + c0, partY + c0, R, nct, 0,
                        want};
     if (skinny_f32_blocks(per) == 0)
-      hipLaunchKernelGGL(k_skinny16_f32, grid, dim3(256), 0, s, d);
+      hipLaunchKernelGGL(k_skinny16_f32<false>, grid, dim3(256), 0, s, d);
     else
-      hipLaunchKernelGGL((k_skinny_f32<1>), grid, dim3(256), 0, s, d);
+      hipLaunchKernelGGL((k_skinny_f32<1, false>), grid, dim3(256), 0, s, d);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -735,8 +862,10 @@ hipError_t launch_skinny_f32(int R, const float* P, int64_t ldp, int64_t n_pad, 
 hipError_t launch_skinny_f32_multi(int nb, const SkinnyDesc* ds, int nd, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
   switch (nb) {
-    case 0: hipLaunchKernelGGL(k_skinny16_f32_multi, dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
-    case 1: hipLaunchKernelGGL((k_skinny_f32_multi<1>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
+    case 0: hipLaunchKernelGGL(k_skinny16_f32_multi<false>, dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
+    case 1: hipLaunchKernelGGL((k_skinny_f32_multi<1, false>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd); break;
+    case 2: hipLaunchKernelGGL(k_skinny16_f32_multi<true>, dim3((unsigned)blocks), dim3(512), 0, s, ds, nd); break;
+    case 3: hipLaunchKernelGGL((k_skinny_f32_multi<1, true>), dim3((unsigned)blocks), dim3(512), 0, s, ds, nd); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
