@@ -481,7 +481,23 @@ def bench_batched(torch, lv, synth, dev, rounds=30):
         A = torch.from_numpy(synth.gaussian_matrix(n, seed=0, config=4, view=v).astype(np.float32)).to(dev)
         views.append(lv.View(A, k, r_max=r))
         bytes_round += 2 * 4 * (int(np.log2(k)) + 1) * views[-1].stats()["n_pad"] ** 2
+    import tempfile
+    t0 = time.perf_counter()
     batch = lv.Batch(views)
+    tune_s = time.perf_counter() - t0
+    tuning = dict(batch.tuning())
+    # the tuner's choices persist through its JSON cache: a fresh process
+    # cache loaded from the file serves a new batch of the same views
+    cache = os.path.join(tempfile.mkdtemp(), "linview_tune.json")
+    lv.lv_tune_cache_save(cache)
+    lv.lv_tune_cache_clear()
+    tuning["cache_entries"] = lv.lv_tune_cache_load(cache)
+    batch.close()
+    t0 = time.perf_counter()
+    batch = lv.Batch(views)
+    tuning["reload"] = dict(batch.tuning())
+    tuning["create_s"], tuning["create_from_cache_s"] = tune_s, time.perf_counter() - t0
+    tuning["tile_rows"] = sorted({t for x in views for t in x.tile_rows()})
     for v in range(64):
         n, r = int(ns[v]), int(rs[v])
         U, V = synth.update_factors(n, r, 1, seed=0, config=4, view=v)
@@ -501,7 +517,8 @@ def bench_batched(torch, lv, synth, dev, rounds=30):
         x.close()
     return {"workload": "64 views, n in {512,1024,2048,4096}, k in {8,16}, rank 1..8, FP32",
             "round_ms": ms, "view_updates_per_s": 64 * 1000.0 / ms,
-            "alg_bytes_per_round": bytes_round, "alg_GBps": bytes_round / (ms * 1e-3) / 1e9}
+            "alg_bytes_per_round": bytes_round, "alg_GBps": bytes_round / (ms * 1e-3) / 1e9,
+            "autotune": tuning}
 
 
 def bench_serving(torch, lv, synth, dev, seconds=2.0, rate=20000.0, r_coalesce=16, shadow=True,

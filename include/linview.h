@@ -324,10 +324,12 @@ void lv_view_destroy(lv_view* v);
  *
  * Tiles are autotuned at lv_batch_create: one round with zero inputs runs
  * first (it leaves every stored power unchanged), then for each level and
- * level rank the tile heights 256, 512 and 1024 rows are timed over that
- * level's launches, and the fastest is kept in the views.  Choices are
- * cached per process by device architecture, mode, rank and the orders of
- * the views concerned, so an identical batch is not timed again.
+ * level rank the tile heights 256, 384, ..., 1024 rows (every multiple of
+ * 128) are timed over that level's launches, and the fastest is kept in the
+ * views.  Choices are cached per process by device architecture, mode,
+ * rank and the orders of the views concerned (rounded up to powers of two),
+ * so a batch of the same shape is not timed again; lv_tune_cache_save /
+ * lv_tune_cache_load keep them across processes.
  * --------------------------------------------------------------------- */
 typedef struct lv_batch lv_batch;
 
@@ -356,6 +358,19 @@ lv_status lv_batch_update(lv_batch* b, void* stream);
 /* Autotuning record of the batch: (level, rank) groups timed at creation,
  * and groups whose choice came from the process cache. */
 lv_status lv_batch_tuning(const lv_batch* b, int* tuned_groups, int* cache_hits);
+
+/* The autotuner's choices persist across processes through a JSON file: a
+ * flat object mapping "arch|m<mode>|R<level rank>|n:<n bucket>:..." (the
+ * device architecture, the mode, the level rank and the orders of the
+ * group's views, each rounded up to a power of two) to tile rows.
+ * lv_tune_cache_save writes the process cache (atomically, by rename);
+ * lv_tune_cache_load merges a file into it (*entries = entries read; an
+ * entry whose tile rows lv_view_set_tile_rows would refuse makes the whole
+ * load fail with LV_EINVAL and changes nothing); lv_tune_cache_clear
+ * empties it.  Host only; thread-safe. */
+lv_status lv_tune_cache_save(const char* path);
+lv_status lv_tune_cache_load(const char* path, int* entries);
+void lv_tune_cache_clear(void);
 
 /* Release the batch (after the stream has drained).  NULL is ignored. */
 void lv_batch_destroy(lv_batch* b);

@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <new>
@@ -121,17 +122,21 @@ lv_status autotune(lv_batch* b, hipStream_t s) {
     return fail(LV_EDEVICE, "hipEventCreate failed");
   int max_m = 0;
   for (lv_view* v : b->views) max_m = std::max(max_m, v->L.m);
-  const int cands[] = {256, 512, 1024};
+  // tile rows: every multiple of 128 from 256 to 1024 (the allowed range)
+  const int cands[] = {256, 384, 512, 640, 768, 896, 1024};
   for (int j = 0; j < max_m && st == LV_OK; ++j) {
     std::map<int, std::vector<lv_view*>> groups;   // level rank -> views with a pass at level j
     for (lv_view* v : b->views)
       if (j < v->L.m) groups[v->L.r_pad << j].push_back(v);
     for (auto& g : groups) {
+      // key: architecture, mode, level rank and the group's orders, each
+      // rounded up to a power of two (its n bucket)
       std::vector<int64_t> ns;
-      for (lv_view* v : g.second) ns.push_back(v->L.n_pad);
+      for (lv_view* v : g.second) ns.push_back(next_pow2(v->L.n_pad));
       std::sort(ns.begin(), ns.end());
-      std::string key = std::string(prop.gcnArchName) + "|m" + std::to_string((int)b->mode) + "|R" +
-                        std::to_string(g.first) + "|n";
+      std::string arch(prop.gcnArchName);
+      arch = arch.substr(0, arch.find(':'));
+      std::string key = arch + "|m" + std::to_string((int)b->mode) + "|R" + std::to_string(g.first) + "|n";
       for (int64_t n : ns) key += ":" + std::to_string(n);
       int best = -1;
       {
@@ -185,6 +190,68 @@ lv_status autotune(lv_batch* b, hipStream_t s) {
 }  // namespace
 
 extern "C" {
+
+lv_status lv_tune_cache_save(const char* path) {
+  g_err[0] = 0;
+  if (!path) return fail(LV_EINVAL, "path is NULL");
+  std::map<std::string, int> copy;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    copy = g_tune_cache;
+  }
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return fail(LV_EINVAL, "cannot write %s", tmp.c_str());
+  std::fprintf(f, "{\n");
+  size_t i = 0;
+  for (auto& kv : copy)
+    std::fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < copy.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  const bool ok = std::fclose(f) == 0;
+  if (!ok || std::rename(tmp.c_str(), path) != 0) return fail(LV_EINVAL, "cannot write %s", path);
+  return LV_OK;
+}
+
+lv_status lv_tune_cache_load(const char* path, int* entries) {
+  g_err[0] = 0;
+  if (!path) return fail(LV_EINVAL, "path is NULL");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(LV_EINVAL, "cannot read %s", path);
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+  std::fclose(f);
+  // the file is a flat JSON object of "key": tile-rows pairs (as written by
+  // lv_tune_cache_save); keys hold no quotes or escapes
+  std::map<std::string, int> add;
+  size_t pos = text.find('{');
+  if (pos == std::string::npos) return fail(LV_EINVAL, "%s: not a JSON object", path);
+  for (;;) {
+    const size_t q0 = text.find('"', pos + 1);
+    if (q0 == std::string::npos) break;
+    const size_t q1 = text.find('"', q0 + 1);
+    const size_t colon = q1 == std::string::npos ? q1 : text.find(':', q1 + 1);
+    if (colon == std::string::npos) return fail(LV_EINVAL, "%s: malformed entry", path);
+    char* end = nullptr;
+    const long rows = std::strtol(text.c_str() + colon + 1, &end, 10);
+    if (end == text.c_str() + colon + 1 || rows < kMinTileRows || rows > kMaxTileRows || rows % 64 != 0)
+      return fail(LV_EINVAL, "%s: bad tile rows for %s", path, text.substr(q0 + 1, q1 - q0 - 1).c_str());
+    add[text.substr(q0 + 1, q1 - q0 - 1)] = (int)rows;
+    pos = (size_t)(end - text.c_str());
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto& kv : add) g_tune_cache[kv.first] = kv.second;
+  }
+  if (entries) *entries = (int)add.size();
+  return LV_OK;
+}
+
+void lv_tune_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache.clear();
+}
 
 size_t lv_batch_footprint(lv_view* const* views, int count) {
   lv_mode mode;

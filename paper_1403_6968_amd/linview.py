@@ -50,6 +50,7 @@ EXPORTED = (
     "lv_glin_footprint", "lv_glin_create", "lv_glin_update", "lv_glin_read", "lv_glin_destroy",
     "lv_server_poll", "lv_server_drain", "lv_server_stats", "lv_server_destroy",
     "lv_stream_probe", "lv_powers_update_noalloc", "lv_view_set_drift_check", "lv_server_set_admission_queue",
+    "lv_tune_cache_save", "lv_tune_cache_load", "lv_tune_cache_clear",
 )
 
 
@@ -171,6 +172,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "lv_powers_update_noalloc": (I32, [c.POINTER(P), I64, I64, I32, I32, P, P, I64, I64, I64, P]),
         "lv_view_set_drift_check": (I32, [P, I64, c.c_double, P, P]),
         "lv_server_set_admission_queue": (I32, [P, I32]),
+        "lv_tune_cache_save": (I32, [c.c_char_p]),
+        "lv_tune_cache_load": (I32, [c.c_char_p, c.POINTER(I32)]),
+        "lv_tune_cache_clear": (None, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -346,6 +350,20 @@ def lv_view_tile_rows(view, level: int) -> int:
 
 def lv_view_set_tile_rows(view, level: int, rows: int) -> None:
     _check(load().lv_view_set_tile_rows(view, level, rows))
+
+
+def lv_tune_cache_save(path: str) -> None:
+    _check(load().lv_tune_cache_save(os.fsencode(path)))
+
+
+def lv_tune_cache_load(path: str) -> int:
+    n = ctypes.c_int()
+    _check(load().lv_tune_cache_load(os.fsencode(path), ctypes.byref(n)))
+    return n.value
+
+
+def lv_tune_cache_clear() -> None:
+    load().lv_tune_cache_clear()
 
 
 def lv_batch_tuning(batch) -> dict:

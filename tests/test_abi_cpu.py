@@ -293,3 +293,28 @@ def test_glin_footprint_and_validation(lib):
     assert st == L.LV_ENOMEM and str(need) in L.lv_last_error()
     assert lib.lv_glin_update(None, 0x1000, 0x1000, 1, 1, 1, None) == L.LV_EINVAL
     assert lib.lv_glin_read(None, 1, 0x1000, 4, None) == L.LV_EINVAL
+
+
+def test_tune_cache_json_roundtrip(lib, tmp_path):
+    """The autotuner's cache persists as a flat JSON object; loading merges,
+    saving writes every entry back, bad tile rows are refused."""
+    import json
+    from paper_1403_6968_amd import linview as L
+    L.lv_tune_cache_clear()
+    src = tmp_path / "tune.json"
+    src.write_text(json.dumps({"gfx950|m1|R8|n:1024:4096": 512, "gfx950|m1|R1|n:8192": 256}))
+    assert L.lv_tune_cache_load(str(src)) == 2
+    out = tmp_path / "out.json"
+    L.lv_tune_cache_save(str(out))
+    assert json.loads(out.read_text()) == {"gfx950|m1|R8|n:1024:4096": 512, "gfx950|m1|R1|n:8192": 256}
+    bad = tmp_path / "bad.json"
+    bad.write_text(json.dumps({"gfx950|m1|R2|n:512": 300}))
+    with pytest.raises(L.LinviewError):
+        L.lv_tune_cache_load(str(bad))
+    with pytest.raises(L.LinviewError):
+        L.lv_tune_cache_load(str(tmp_path / "missing.json"))
+    L.lv_tune_cache_save(str(out))                     # the failed loads changed nothing
+    assert len(json.loads(out.read_text())) == 2
+    L.lv_tune_cache_clear()
+    L.lv_tune_cache_save(str(out))
+    assert json.loads(out.read_text()) == {}

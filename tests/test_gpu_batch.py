@@ -150,3 +150,34 @@ def test_batched_workload_full_size_against_oracle():
     batch.close()
     for x in views:
         x.close()
+
+
+def test_autotune_cache_persists_through_json(tmp_path):
+    """Tile rows chosen by the autotuner, saved as JSON, cleared from the
+    process and loaded again, serve a second batch of the same shapes
+    without timing anything."""
+    need_gpu()
+    import torch
+    from paper_1403_6968_amd import linview as lv
+    shapes = [(700, 16, 2), (1500, 8, 4), (3000, 16, 1)]
+    mk = lambda: [lv.View(dev(synth.gaussian_matrix(n, seed=50, config=4, view=v).astype(np.float32), torch.float32),
+                          k, r_max=r) for v, (n, k, r) in enumerate(shapes)]
+    lv.lv_tune_cache_clear()
+    a = mk()
+    ba = lv.Batch(a)
+    t1 = ba.tuning()
+    assert t1["tuned_groups"] > 0 and t1["cache_hits"] == 0
+    path = str(tmp_path / "tune.json")
+    lv.lv_tune_cache_save(path)
+    lv.lv_tune_cache_clear()
+    assert lv.lv_tune_cache_load(path) == t1["tuned_groups"]
+    b = mk()
+    bb = lv.Batch(b)
+    t2 = bb.tuning()
+    note(f"first {t1}, after reload {t2}; tiles {[v.tile_rows() for v in a]}")
+    assert t2["tuned_groups"] == 0 and t2["cache_hits"] == t1["tuned_groups"]
+    assert [v.tile_rows() for v in a] == [v.tile_rows() for v in b]
+    for x in (ba, bb):
+        x.close()
+    for v in a + b:
+        v.close()
