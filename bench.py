@@ -51,7 +51,7 @@ def parse():
                    help="skip the rank-4, batched and serving workloads")
     p.add_argument("--serve-seconds", type=float, default=2.0)
     p.add_argument("--only", choices=["rank4", "batched", "serving", "sums", "general", "models", "ols", "glin",
-                                      "fp64", "small", "serving32"],
+                                      "fp64", "small", "serving32", "capacity"],
                    help="run one secondary workload alone and print its result (for profilers)")
     return p.parse_args()
 
@@ -612,6 +612,56 @@ def bench_serving(torch, lv, synth, dev, seconds=2.0, rate=20000.0, r_coalesce=1
                 "requests_waiting_for_admission": int(st["submitted"] - st["completed"])})}
 
 
+def bench_serving_capacity(torch, lv, synth, dev, rate=20000.0, r_cap=16, shadow=True, reps=6):
+    """A bound for the serving workload from measured update times: every
+    one of its 32 views (same orders, k = 16, same mode) applies rank-r_cap
+    updates alone on the device; even if every request were coalesced into
+    a full rank-r_cap update (the widest a k = 16 view takes: k r_max <= 256),
+    serving `rate` requests/s needs sum_v (rate p_v / r_cap) T_v seconds of
+    device time per second.  Above 1 the offered rate cannot be sustained by
+    any coalescing within the cap; rate / need is the best the device can
+    sustain."""
+    mode = lv.LV_FP32_BF16SHADOW if shadow else lv.LV_FP32
+    g = synth.rng(0, 5, 0)
+    ns = np.exp(g.uniform(np.log(2048), np.log(16384), size=32)).astype(int)
+    pop = np.arange(1, 33, dtype=np.float64) ** -1.1
+    pop /= pop.sum()
+    perm = g.permutation(32)
+    share = np.empty(32)
+    share[perm] = pop
+    times = {}
+    need = 0.0
+    per_view = []
+    for v in range(32):
+        n = int(ns[v])
+        A = torch.from_numpy(synth.gaussian_matrix(n, seed=0, config=5, view=v).astype(np.float32)).to(dev)
+        U, V = synth.update_factors(n, r_cap, reps + 2, seed=0, config=5, view=v)
+        Ud, Vd = torch.from_numpy(U.astype(np.float32)).to(dev), torch.from_numpy(V.astype(np.float32)).to(dev)
+        view = lv.View(A, 16, r_max=r_cap, mode=mode)
+        del A
+        view.update_batch(Ud[:2], Vd[:2])
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        view.update_batch(Ud[2:], Vd[2:])
+        b.record()
+        torch.cuda.synchronize()
+        view.close()
+        t = a.elapsed_time(b) / reps * 1e-3
+        times[n] = t
+        need += rate * share[v] / r_cap * t
+        per_view.append((float(share[v]), n, t))
+    hottest = max(per_view)
+    return {"workload": "32 serving views (n log-uniform [2048,16384], k=16, %s), rank-%d updates timed alone"
+                        % ("FP32 + BF16 shadows" if shadow else "FP32", r_cap),
+            "offered_per_s": rate,
+            "device_s_per_s_at_full_coalescing": need,
+            "max_sustainable_per_s": rate / need,
+            "hottest_view": {"n": hottest[1], "share": hottest[0], "update_ms": hottest[2] * 1e3,
+                             "max_rate_per_s": r_cap / hottest[2], "offered_per_s": rate * hottest[0]},
+            "update_ms_by_n": {str(n): t * 1e3 for n, t in sorted(times.items())}}
+
+
 def counter_traffic(n, k, r):
     """HBM bytes per fused launch from the committed rocprofv3 counter
     summary, or None when the workload differs or the kernel source has
@@ -708,6 +758,7 @@ def main():
               "batched": lambda: bench_batched(torch, lv, synth, dev),
               "serving": lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds),
               "serving32": lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds, budget_bytes=32e9),
+              "capacity": lambda: bench_serving_capacity(torch, lv, synth, dev),
               "sums": lambda: bench_sums(torch, lv, synth, dev),
               "general": lambda: bench_general(torch, lv, synth, dev),
               "models": lambda: bench_models(torch, lv, synth, dev),
@@ -890,7 +941,8 @@ def main():
                          ("serving_32_views_5k",
                           lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds, rate=5000.0)),
                          ("serving_32_views_32GB",
-                          lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds, budget_bytes=32e9))):
+                          lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds, budget_bytes=32e9)),
+                         ("serving_capacity_bound", lambda: bench_serving_capacity(torch, lv, synth, dev))):
             sec[name] = fn()
             torch.cuda.empty_cache()
             log(f"{name}: {sec[name]}")
