@@ -313,7 +313,7 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
     });
   };
   // update waves: the chunk's U_j rows (thread t = tid - 256 holds entries t + 256 i)
-  float pu[UPD ? VPT : 1];
+  float pu[VPT];
   auto fetch_u = [&](const int r0) {
     static_for<0, VPT>([&](auto i) {
       const int idx = tid - 256 + 256 * i;
@@ -527,7 +527,7 @@ __device__ __forceinline__ void skinny16_f32_body(const float* __restrict__ P, c
     });
   };
   // update waves: the chunk's U_j rows (thread t = tid - 256 holds entries t + 256 i)
-  float pu[UPD ? VPT : 1];
+  float pu[VPT];
   auto fetch_u = [&](const int r0) {
     static_for<0, VPT>([&](auto i) {
       const int idx = tid - 256 + 256 * i;
