@@ -150,10 +150,27 @@ lv_status lv_view_update(lv_view* v, const void* U, const void* V, int64_t r,
 
 /* Apply `count` updates in order, (U_t, V_t) = (U + t*strideU, V + t*strideV)
  * for t = 0..count-1 (strides in elements).  The result equals `count`
- * calls of lv_view_update, bit for bit.  count >= 0. */
+ * calls of lv_view_update, bit for bit.  count >= 0.
+ * Pipelining: for a view without sums or general form and with k >= 4,
+ * level j of update t depends only on P_j after update t-1 and on the
+ * factors that level j-1 of update t assembles (App. A), so the levels run
+ * as up to four stages on streams of their own (stage 0 on `stream`; the
+ * others are created on the first such call, on the current device) and
+ * up to min(log2 k + 1, 5) successive updates are in flight, each with
+ * a factor-slab pair of the workspace.  Every kernel sees the inputs of the
+ * sequential order; the call returns with all stages joined into `stream`,
+ * so stream order is as for one call of lv_view_update per update.  Not
+ * used while kernel timing is on; a periodic drift check falling inside
+ * the batch joins the stages first.  Two batches on one view must not
+ * overlap (as for every call on a view). */
 lv_status lv_view_update_batch(lv_view* v, const void* U, const void* V, int64_t r,
                                int64_t count, int64_t ldu, int64_t ldv,
                                int64_t strideU, int64_t strideV, void* stream);
+
+/* Turn the pipelining of lv_view_update_batch on (default) or off
+ * (enable = 0: every batch runs its updates one after the other on
+ * `stream`; the results are the same bit for bit). */
+lv_status lv_view_set_pipeline(lv_view* v, int enable);
 
 /* Copy stored power A^power (power in {1, 2, 4, ..., k}) to out (n x n,
  * leading dimension ldo >= n, device). */

@@ -475,85 +475,75 @@ lv_status gfac_finish(lv_view* v, int ru, const T* sU, hipStream_t s) {
   return st;
 }
 
-// One update through every level, factors in the view's slabs (App. A exponential
-// model; trigger of Sec. 4.4): levels 0..m-1 run the fused pass and the tail
-// (or, for float storage at large level rank and with bfloat16 shadows, the
-// read-only skinny pass, the Gram and the update pass), the top level the
-// update-only pass.
+// Level j of one update (App. A exponential model; trigger of Sec. 4.4) with
+// the update's factors in the slabs sU, sV: the fused pass and the tail (or,
+// for float storage at large level rank and with bfloat16 shadows, the
+// read-only skinny pass, the Gram and the update pass), then the sums' and
+// the general form's level steps.  Stream-ordered on s.
 template <typename T>
-lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int64_t ldv,
-                     hipStream_t s) {
+lv_status level_step(lv_view* v, int j, int r_pad, T* sU, T* sV, hipStream_t s) {
   const Layout& L = v->L;
-  const int r_pad = (int)next_pow2(r);
-  T* sU = v->slabU<T>();
-  T* sV = v->slabV<T>();
-  lv_status st = hip_check(launch_prep<T>(U, ldu, V, ldv, v->n, r, r_pad, sU, sV, L.W, L.n_pad, s), "prep");
-  if (st == LV_OK && L.general)
-    st = L.gfac ? gfac_first<T>(v, r_pad, sV, s) : general_tail<T>(v, -1, r_pad, sU, sV, s);
-  if (st != LV_OK) return st;
-  for (int j = 0; j < L.m; ++j) {
-    const int R = r_pad << j;
-    // The general form's product with the OLD P_j: P_j D_j (hybrid) or P_j Y_j
-    // (factored; at level 0 Y_0 = U_0, so the powers' own X serves).  It
-    // rides on the powers' fused pass when the X width allows, like P_j Q_j
-    // of the sums; else it is a read-only pass of its own.
-    const bool gen_op = L.general && !(L.gfac && j == 0);
-    const bool vec_level = fused_vector_level(R, (int)sizeof(T), v->shadowed());
-    const bool q_in_pass = L.sums && j > 0 && vec_level && fused_extra_fits(R, true, 0);
-    const int xd = !gen_op ? 0 : L.gfac ? gW(r_pad, j) : L.pp;
-    const bool d_in_pass = gen_op && vec_level && fused_extra_fits(R, q_in_pass, xd);
-    if (gen_op && !d_in_pass) {
-      st = L.gfac ? gfac_pass<T>(v, j, r_pad, sU, s) : general_pass<T>(v, j, s);
-      if (st != LV_OK) return st;
-    }
-    if (L.sums && j > 0 && !q_in_pass) {
-      // sums: X_s = P_j Q_j with the OLD P_j, before this level's update
-      st = timed(v, 0, s, "sums: P Q", [&] {
-        if (skinny_on_mfma(R, (int)sizeof(T)))
-          return launch_skinny_f32(R, reinterpret_cast<const float*>(v->P<T>(j)), L.ldp, L.n_pad, v->tile_rows[j],
-                                   v->slabQ<float>(), reinterpret_cast<const float*>(sV), L.W, v->partXs<float>(j),
-                                   v->partYs<float>(j), s, kWantX);
-        return launch_level_readonly<T>(R, v->P<T>(j), L.ldp, L.n_pad, v->tile_rows[j], v->slabQ<T>(),
-                                        sV + (L.W - R), L.W, v->partXs<T>(j), v->partYs<T>(j), s);
+  lv_status st = LV_OK;
+  const int R = r_pad << j;
+  // The general form's product with the OLD P_j: P_j D_j (hybrid) or P_j Y_j
+  // (factored; at level 0 Y_0 = U_0, so the powers' own X serves).  It
+  // rides on the powers' fused pass when the X width allows, like P_j Q_j
+  // of the sums; else it is a read-only pass of its own.
+  const bool gen_op = L.general && !(L.gfac && j == 0);
+  const bool vec_level = fused_vector_level(R, (int)sizeof(T), v->shadowed());
+  const bool q_in_pass = L.sums && j > 0 && vec_level && fused_extra_fits(R, true, 0);
+  const int xd = !gen_op ? 0 : L.gfac ? gW(r_pad, j) : L.pp;
+  const bool d_in_pass = gen_op && vec_level && fused_extra_fits(R, q_in_pass, xd);
+  if (gen_op && !d_in_pass) {
+    st = L.gfac ? gfac_pass<T>(v, j, r_pad, sU, s) : general_pass<T>(v, j, s);
+    if (st != LV_OK) return st;
+  }
+  if (L.sums && j > 0 && !q_in_pass) {
+    // sums: X_s = P_j Q_j with the OLD P_j, before this level's update
+    st = timed(v, 0, s, "sums: P Q", [&] {
+      if (skinny_on_mfma(R, (int)sizeof(T)))
+        return launch_skinny_f32(R, reinterpret_cast<const float*>(v->P<T>(j)), L.ldp, L.n_pad, v->tile_rows[j],
+                                 v->slabQ<float>(), reinterpret_cast<const float*>(sV), L.W, v->partXs<float>(j),
+                                 v->partYs<float>(j), s, kWantX);
+      return launch_level_readonly<T>(R, v->P<T>(j), L.ldp, L.n_pad, v->tile_rows[j], v->slabQ<T>(),
+                                      sV + (L.W - R), L.W, v->partXs<T>(j), v->partYs<T>(j), s);
+    });
+    if (st != LV_OK) return st;
+  }
+  bool on_cores = false;
+  if constexpr (sizeof(T) == 4) {
+    if (v->shadowed() || skinny_on_mfma(R, 4)) {
+      on_cores = true;
+      // read-only skinny pass on the matrix cores (from the shadow, or from
+      // the float power), FP64 Gram, then the rank update (which rewrites
+      // the shadow after the skinny pass has read it); with the float power
+      // at R = 16 the skinny pass applies the update itself (one read of
+      // P_j), else the update pass follows
+      const bool fused_upd = !v->shadowed() && skinny_fuses_update(R);
+      st = timed(v, 0, s, "skinny", [&] {
+        return v->shadowed() ? launch_skinny_bf16(R, v->shadow(j), L.ldp, L.n_pad, v->tile_rows[j], sU, sV, L.W,
+                                                  v->partX<float>(j), v->partY<float>(j), s)
+                             : launch_skinny_f32(R, v->P<float>(j), L.ldp, L.n_pad, v->tile_rows[j], sU, sV, L.W,
+                                                 v->partX<float>(j), v->partY<float>(j), s, kWantX | kWantY,
+                                                 fused_upd);
       });
-      if (st != LV_OK) return st;
-    }
-    if constexpr (sizeof(T) == 4) {
-      if (v->shadowed() || skinny_on_mfma(R, 4)) {
-        // read-only skinny pass on the matrix cores (from the shadow, or from
-        // the float power), FP64 Gram, then the rank update (which rewrites
-        // the shadow after the skinny pass has read it)
-        // with the float power at R = 16 or 32 the skinny pass applies the
-        // update itself (one read of P_j); else the update pass follows
-        const bool fused_upd = !v->shadowed() && skinny_fuses_update(R);
-        st = timed(v, 0, s, "skinny", [&] {
-          return v->shadowed() ? launch_skinny_bf16(R, v->shadow(j), L.ldp, L.n_pad, v->tile_rows[j], sU, sV, L.W,
-                                                    v->partX<float>(j), v->partY<float>(j), s)
-                               : launch_skinny_f32(R, v->P<float>(j), L.ldp, L.n_pad, v->tile_rows[j], sU, sV, L.W,
-                                                   v->partX<float>(j), v->partY<float>(j), s, kWantX | kWantY,
-                                                   fused_upd);
+      if (st == LV_OK)
+        st = timed(v, 0, s, "gram", [&] {
+          return launch_level_gram<float>(R, sU, sV, L.W, L.n_pad, v->partG(j), s);
         });
-        if (st == LV_OK)
-          st = timed(v, 0, s, "gram", [&] {
-            return launch_level_gram<float>(R, sU, sV, L.W, L.n_pad, v->partG(j), s);
-          });
-        if (st == LV_OK && !fused_upd)
-          st = timed(v, 0, s, "update", [&] {
-            return launch_level_update<float>(R, v->P<float>(j), L.ldp, L.n_pad, sU, sV, L.W, s,
-                                              v->shadowed() ? v->shadow(j) : nullptr, v->shadowed());
-          });
-        if (st == LV_OK)
-          st = timed(v, 1, s, "level tail", [&] {
-            return launch_level_tail<float>(R, v->partX<float>(j), v->partY<float>(j), v->partG(j), L.nct, v->nrt(j),
-                                            1, L.n_pad, sU, sV, L.W, s);
-          });
-        if (st == LV_OK && L.general)
-          st = L.gfac ? gfac_tail<T>(v, j, R, r_pad, sU, sV, s) : general_tail<T>(v, j, R, sU, sV, s);
-        if (st == LV_OK && L.sums) st = sums_level<T>(v, j, R, sU, sV, s);
-        if (st != LV_OK) return st;
-        continue;
-      }
+      if (st == LV_OK && !fused_upd)
+        st = timed(v, 0, s, "update", [&] {
+          return launch_level_update<float>(R, v->P<float>(j), L.ldp, L.n_pad, sU, sV, L.W, s,
+                                            v->shadowed() ? v->shadow(j) : nullptr, v->shadowed());
+        });
+      if (st == LV_OK)
+        st = timed(v, 1, s, "level tail", [&] {
+          return launch_level_tail<float>(R, v->partX<float>(j), v->partY<float>(j), v->partG(j), L.nct, v->nrt(j),
+                                          1, L.n_pad, sU, sV, L.W, s);
+        });
     }
+  }
+  if (!on_cores) {
     st = timed(v, 0, s, "level pass", [&] {
       if (q_in_pass || d_in_pass) {
         const T* Dop = !d_in_pass ? nullptr : L.gfac ? v->Yf<T>(j) : v->D<T>(j & 1);
@@ -565,30 +555,143 @@ lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int
       return launch_level_fused<T>(R, v->P<T>(j), L.ldp, L.n_pad, v->tile_rows[j], sU, sV, L.W, v->partX<T>(j),
                                    v->partY<T>(j), v->partG(j), s);
     });
-    if (st != LV_OK) return st;
-    st = timed(v, 1, s, "level tail", [&] {
-      return launch_level_tail<T>(R, v->partX<T>(j), v->partY<T>(j), v->partG(j), L.nct, v->nrt(j),
-                                  gram_in_pass(R, (int)sizeof(T)) ? v->nrt(j) : 1, L.n_pad, sU, sV, L.W, s);
-    });
-    if (st == LV_OK && L.general)
-      st = L.gfac ? gfac_tail<T>(v, j, R, r_pad, sU, sV, s) : general_tail<T>(v, j, R, sU, sV, s);
-    if (st == LV_OK && L.sums) st = sums_level<T>(v, j, R, sU, sV, s);
-    if (st != LV_OK) return st;
+    if (st == LV_OK)
+      st = timed(v, 1, s, "level tail", [&] {
+        return launch_level_tail<T>(R, v->partX<T>(j), v->partY<T>(j), v->partG(j), L.nct, v->nrt(j),
+                                    gram_in_pass(R, (int)sizeof(T)) ? v->nrt(j) : 1, L.n_pad, sU, sV, L.W, s);
+      });
   }
-  if (L.nsk > 0) {
-    st = gfac_skip<T>(v, r_pad, sU, sV, s);
-    if (st != LV_OK) return st;
-  }
+  if (st == LV_OK && L.general)
+    st = L.gfac ? gfac_tail<T>(v, j, R, r_pad, sU, sV, s) : general_tail<T>(v, j, R, sU, sV, s);
+  if (st == LV_OK && L.sums) st = sums_level<T>(v, j, R, sU, sV, s);
+  return st;
+}
+
+// The update-only pass of the top stored power P_m with U_m, V_m.
+template <typename T>
+lv_status top_step(lv_view* v, int r_pad, T* sU, T* sV, hipStream_t s) {
+  const Layout& L = v->L;
   const int Rm = r_pad << L.m;
-  st = timed(v, 2, s, "top update", [&] {
+  return timed(v, 2, s, "top update", [&] {
     return launch_level_update<T>(Rm, v->P<T>(L.m), L.ldp, L.n_pad, sU, sV, L.W, s, nullptr, v->shadowed());
   });
+}
+
+// One update through every level, factors in the view's slabs (App. A
+// exponential model; trigger of Sec. 4.4): the level steps 0..m-1, then the
+// top level's update-only pass.
+template <typename T>
+lv_status update_one(lv_view* v, const T* U, const T* V, int r, int64_t ldu, int64_t ldv,
+                     hipStream_t s) {
+  const Layout& L = v->L;
+  const int r_pad = (int)next_pow2(r);
+  T* sU = v->slabU<T>();
+  T* sV = v->slabV<T>();
+  lv_status st = hip_check(launch_prep<T>(U, ldu, V, ldv, v->n, r, r_pad, sU, sV, L.W, L.n_pad, s), "prep");
+  if (st == LV_OK && L.general)
+    st = L.gfac ? gfac_first<T>(v, r_pad, sV, s) : general_tail<T>(v, -1, r_pad, sU, sV, s);
+  for (int j = 0; j < L.m && st == LV_OK; ++j) st = level_step<T>(v, j, r_pad, sU, sV, s);
+  if (st == LV_OK && L.nsk > 0) st = gfac_skip<T>(v, r_pad, sU, sV, s);
+  if (st == LV_OK) st = top_step<T>(v, r_pad, sU, sV, s);
   if (st == LV_OK && L.sums && L.m > 0)
     st = timed(v, 2, s, "sums: top update", [&] {
-      return launch_level_update<T>(Rm, v->S<T>(L.m), L.ldp, L.n_pad, v->slabQ<T>(), v->slabW<T>(), L.W, s);
+      return launch_level_update<T>(r_pad << L.m, v->S<T>(L.m), L.ldp, L.n_pad, v->slabQ<T>(), v->slabW<T>(), L.W,
+                                    s);
     });
   if (st == LV_OK && L.gfac) st = gfac_finish<T>(v, r_pad, sU, s);
   return st;
+}
+
+// Pipelined batch of updates (plain views: no sums, no general form).  Level
+// j of update t needs only P_j as update t-1 left it and the factors that
+// level j-1 of update t assembled, so the levels are cut into stages
+// (contiguous level ranges, at most kPipeStreams), each on a stream of its
+// own (stage 0 on the caller's stream), and successive updates flow through
+// them: while a stage works on update t the earlier stages already work on
+// t+1, t+2, ...  Each update in flight holds one of pipe_slots factor-slab
+// pairs; a slab is reused only after the top level of the update that held
+// it has finished.  Every kernel sees exactly the inputs of the sequential
+// order, so the results are bit-identical to it.
+inline int pipe_stage(const lv_view* v, int j) { return j * v->pipe_nstages / v->L.m; }
+
+lv_status pipe_setup(lv_view* v) {
+  if (v->pipe_nstages > 0) return LV_OK;
+  const int ns = v->L.m < kPipeStreams ? v->L.m : kPipeStreams;
+  for (int q = 1; q < ns; ++q)
+    if (hipStreamCreateWithFlags(&v->pstream[q], hipStreamNonBlocking) != hipSuccess)
+      return fail(LV_EDEVICE, "hipStreamCreateWithFlags failed");
+  auto mk = [](hipEvent_t* e) { return hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess; };
+  bool ok = mk(&v->pfork);
+  for (int q = 0; q < ns && ok; ++q) ok = mk(&v->pjoin[q]);
+  for (int sl = 0; sl < v->L.pipe_slots && ok; ++sl) {
+    ok = mk(&v->pfree[sl]);
+    for (int j = 0; j + 1 < v->L.m && ok; ++j) ok = mk(&v->pready[j][sl]);
+  }
+  if (!ok) return fail(LV_EDEVICE, "hipEventCreateWithFlags failed");
+  v->pipe_nstages = ns;
+  return LV_OK;
+}
+
+// The stage streams wait for the caller's stream (fork) or the caller's
+// stream for every stage (join).
+lv_status pipe_fork(lv_view* v, hipStream_t s) {
+  if (hipEventRecord(v->pfork, s) != hipSuccess) return fail(LV_EDEVICE, "hipEventRecord failed");
+  for (int q = 1; q < v->pipe_nstages; ++q)
+    if (hipStreamWaitEvent(v->pstream[q], v->pfork, 0) != hipSuccess) return fail(LV_EDEVICE, "hipStreamWaitEvent failed");
+  return LV_OK;
+}
+
+lv_status pipe_join(lv_view* v, hipStream_t s) {
+  for (int q = 1; q < v->pipe_nstages; ++q) {
+    if (hipEventRecord(v->pjoin[q], v->pstream[q]) != hipSuccess) return fail(LV_EDEVICE, "hipEventRecord failed");
+    if (hipStreamWaitEvent(s, v->pjoin[q], 0) != hipSuccess) return fail(LV_EDEVICE, "hipStreamWaitEvent failed");
+  }
+  return LV_OK;
+}
+
+template <typename T>
+lv_status update_batch_pipelined(lv_view* v, const char* U, const char* V, int r, int64_t count, int64_t ldu,
+                                 int64_t ldv, int64_t strideU, int64_t strideV, hipStream_t s) {
+  const Layout& L = v->L;
+  lv_status st = pipe_setup(v);
+  if (st != LV_OK) return st;
+  st = pipe_fork(v, s);
+  if (st != LV_OK) return st;
+  const int r_pad = (int)next_pow2(r);
+  const int D = L.pipe_slots;
+  auto stream_of = [&](int j) { const int q = pipe_stage(v, j); return q == 0 ? s : v->pstream[q]; };
+  auto ev = [&](hipError_t e, const char* what) { return e == hipSuccess ? LV_OK : fail(LV_EDEVICE, "%s failed", what); };
+  for (int64_t t = 0; t < count && st == LV_OK; ++t) {
+    const int sl = (int)(t % D);
+    T* sU = v->slabU<T>(sl);
+    T* sV = v->slabV<T>(sl);
+    const T* Ut = reinterpret_cast<const T*>(U + (size_t)(t * strideU) * sizeof(T));
+    const T* Vt = reinterpret_cast<const T*>(V + (size_t)(t * strideV) * sizeof(T));
+    // the slab is free once the top level of update t - D is done with it
+    if (t >= D) st = ev(hipStreamWaitEvent(s, v->pfree[sl], 0), "hipStreamWaitEvent");
+    if (st == LV_OK) st = hip_check(launch_prep<T>(Ut, ldu, Vt, ldv, v->n, r, r_pad, sU, sV, L.W, L.n_pad, s), "prep");
+    for (int j = 0; j < L.m && st == LV_OK; ++j) {
+      hipStream_t sj = stream_of(j);
+      if (j > 0 && pipe_stage(v, j - 1) != pipe_stage(v, j))
+        st = ev(hipStreamWaitEvent(sj, v->pready[j - 1][sl], 0), "hipStreamWaitEvent");
+      if (st == LV_OK) st = level_step<T>(v, j, r_pad, sU, sV, sj);
+      if (st == LV_OK && j + 1 < L.m && pipe_stage(v, j + 1) != pipe_stage(v, j))
+        st = ev(hipEventRecord(v->pready[j][sl], sj), "hipEventRecord");
+    }
+    hipStream_t st_top = stream_of(L.m - 1);
+    if (st == LV_OK) st = top_step<T>(v, r_pad, sU, sV, st_top);
+    if (st == LV_OK) st = ev(hipEventRecord(v->pfree[sl], st_top), "hipEventRecord");
+    if (st != LV_OK) break;
+    v->updates += 1;
+    if (v->drift_every > 0 && v->updates % v->drift_every == 0) {
+      // the drift check reads every power: all stages join, then fork again
+      st = pipe_join(v, s);
+      if (st == LV_OK) st = periodic_drift(v, s);
+      if (st == LV_OK) st = pipe_fork(v, s);
+    }
+  }
+  const lv_status sj = pipe_join(v, s);
+  return st != LV_OK ? st : sj;
 }
 
 // ---------------------------------------------------------------- re-evaluation
@@ -824,6 +927,12 @@ lv_status lv_view_update_batch(lv_view* v, const void* U, const void* V, int64_t
   if (count > 1 && (strideU < v->n * ldu || strideV < v->n * ldv))
     return fail(LV_EINVAL, "strides smaller than one n x r factor");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (count > 1 && v->pipeline && !v->timing && v->L.pipe_slots > 1)
+    return v->mode == LV_FP64
+               ? update_batch_pipelined<double>(v, static_cast<const char*>(U), static_cast<const char*>(V), (int)r,
+                                                count, ldu, ldv, strideU, strideV, s)
+               : update_batch_pipelined<float>(v, static_cast<const char*>(U), static_cast<const char*>(V), (int)r,
+                                               count, ldu, ldv, strideU, strideV, s);
   const size_t es = v->L.elem;
   for (int64_t t = 0; t < count; ++t) {
     const char* Ut = static_cast<const char*>(U) + (size_t)(t * strideU) * es;
@@ -1000,6 +1109,13 @@ lv_status lv_view_set_tile_rows(lv_view* v, int level, int rows) {
   return LV_OK;
 }
 
+lv_status lv_view_set_pipeline(lv_view* v, int enable) {
+  g_err[0] = 0;
+  if (!v) return fail(LV_EINVAL, "view is NULL");
+  v->pipeline = enable != 0;
+  return LV_OK;
+}
+
 lv_status lv_view_set_timing(lv_view* v, int enable) {
   if (!v) return fail(LV_EINVAL, "view is NULL");
   v->timing = enable != 0;
@@ -1028,6 +1144,12 @@ lv_status lv_view_timing(lv_view* v, lv_timing* out) {
 
 void lv_view_destroy(lv_view* v) {
   if (!v) return;
+  for (int q = 1; q < v->pipe_nstages; ++q) (void)hipStreamDestroy(v->pstream[q]);
+  for (hipEvent_t e : v->pjoin) if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : v->pfree) if (e) (void)hipEventDestroy(e);
+  for (auto& row : v->pready)
+    for (hipEvent_t e : row) if (e) (void)hipEventDestroy(e);
+  if (v->pfork) (void)hipEventDestroy(v->pfork);
   for (auto& p : v->pending) { v->pool.push_back(p.a); v->pool.push_back(p.b); }
   for (hipEvent_t e : v->pool) (void)hipEventDestroy(e);
   delete v;

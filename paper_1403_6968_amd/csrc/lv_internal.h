@@ -24,6 +24,10 @@ constexpr int fused_row_block(int R) { return R >= 8 ? 8 : 4; }
 constexpr int fused_prefetch(int R) { return R >= 8 ? 0 : 1; }
 // Largest level of the exponential model (k <= 2^kMaxLevel).
 constexpr int kMaxLevel = 10;
+// Pipelined batches: at most this many stage streams and factor-slab slots
+// (updates in flight).
+constexpr int kPipeStreams = 4;
+constexpr int kMaxPipeSlots = 5;
 
 inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 

@@ -34,6 +34,10 @@ struct Layout {
   int m = 0, r_pad = 0, W = 0, elem = 0, nct = 0, nrt_max = 0, tile_rows = 0;
   size_t P[kMaxLevel + 1] = {};
   size_t slabU = 0, slabV = 0;   // the update's factor slabs (every level's U_j, V_j)
+  // factor-slab pairs of the pipelined batch (plain views with m >= 2): slot
+  // 0 is slabU / slabV, slots 1 .. pipe_slots - 1 follow
+  int pipe_slots = 0;
+  size_t pslabU[kMaxPipeSlots] = {}, pslabV[kMaxPipeSlots] = {};
   size_t partX[kMaxLevel] = {};
   size_t partY[kMaxLevel] = {};
   size_t partG[kMaxLevel] = {};
@@ -126,6 +130,15 @@ inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode, int flags =
   const size_t slab = (size_t)L.n_pad * L.W * L.elem;
   L.slabU = off; off = align_up(off + slab);
   L.slabV = off; off = align_up(off + slab);
+  L.pslabU[0] = L.slabU;
+  L.pslabV[0] = L.slabV;
+  if (!ext_powers && !L.sums && L.m >= 2) {
+    L.pipe_slots = L.m + 1 < kMaxPipeSlots ? L.m + 1 : kMaxPipeSlots;
+    for (int q = 1; q < L.pipe_slots; ++q) {
+      L.pslabU[q] = off; off = align_up(off + slab);
+      L.pslabV[q] = off; off = align_up(off + slab);
+    }
+  }
   for (int j = 0; j < L.m; ++j) {
     const size_t R = (size_t)L.r_pad << j;
     L.partX[j] = off; off = align_up(off + (size_t)L.nct * L.n_pad * R * L.elem);
@@ -255,12 +268,27 @@ struct lv_view {
   std::vector<Pair> pending;
   std::vector<hipEvent_t> pool;
 
+  // Pipelined update_batch (plain views, L.pipe_slots > 1): stage streams
+  // (stage 0 runs on the caller's stream; created on first use), the events
+  // that order the stages (pready: level j's factors of the update in a slot
+  // are assembled; pfree: the slot's update is through its top level) and
+  // fork / join events.  pipeline = false keeps every batch sequential.
+  bool pipeline = true;
+  int pipe_nstages = 0;
+  hipStream_t pstream[lv::kPipeStreams] = {};
+  hipEvent_t pready[lv::kMaxLevel][lv::kMaxPipeSlots] = {};
+  hipEvent_t pfree[lv::kMaxPipeSlots] = {};
+  hipEvent_t pfork = nullptr;
+  hipEvent_t pjoin[lv::kPipeStreams] = {};
+
   // stored powers held outside the workspace (set by the allocation-free
   // update entry point; null for views created on a workspace)
   char* pext[lv::kMaxLevel + 1] = {};
   template <typename T> T* P(int j) const { return reinterpret_cast<T*>(pext[j] ? pext[j] : base + L.P[j]); }
   template <typename T> T* slabU() const { return reinterpret_cast<T*>(base + L.slabU); }
   template <typename T> T* slabV() const { return reinterpret_cast<T*>(base + L.slabV); }
+  template <typename T> T* slabU(int slot) const { return reinterpret_cast<T*>(base + L.pslabU[slot]); }
+  template <typename T> T* slabV(int slot) const { return reinterpret_cast<T*>(base + L.pslabV[slot]); }
   template <typename T> T* partX(int j) const { return reinterpret_cast<T*>(base + L.partX[j]); }
   template <typename T> T* partY(int j) const { return reinterpret_cast<T*>(base + L.partY[j]); }
   double* partG(int j) const { return reinterpret_cast<double*>(base + L.partG[j]); }
