@@ -70,6 +70,7 @@ def bench_rank4(torch, lv, synth, dev, steps=200, drift_every=100):
     out = {"workload": "A^16, n=16384, rank-4 updates"}
     for tag, mode in (("fp32", lv.LV_FP32), ("bf16shadow", lv.LV_FP32_BF16SHADOW)):
         view = lv.View(A, k, r_max=r, mode=mode)
+        tiles = view.autotune(pipelined=True, trial_updates=12)
         view.update_batch(Ud[:5], Vd[:5])
         view.set_drift_check(drift_every)          # counts from here: 5 updates applied
         torch.cuda.synchronize()
@@ -97,6 +98,7 @@ def bench_rank4(torch, lv, synth, dev, steps=200, drift_every=100):
         view.set_timing(False)
         view.close()
         out[tag] = {"ms_per_update": ms, "updates_per_s": 1000.0 / ms, "rank1_equiv_per_s": 4000.0 / ms,
+                    "tile_rows": tiles,
                     "level_passes_ms": tm["fused_ms"], "tails_ms": tm["tail_ms"], "top_update_ms": tm["top_ms"],
                     "drift_check": drift}
     del A
@@ -129,6 +131,7 @@ def bench_fp64(torch, lv, synth, dev, steps=100):
     U, V = synth.update_factors(n, 1, steps + 5, seed=0, config=2)
     Ud, Vd = torch.from_numpy(U).to(dev), torch.from_numpy(V).to(dev)
     view = lv.View(A, k)
+    tiles = view.autotune(pipelined=True, trial_updates=12)
     view.update_batch(Ud[:5], Vd[:5])
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -151,7 +154,7 @@ def bench_fp64(torch, lv, synth, dev, steps=100):
     del A
     return {"workload": "A^16 matrix-power view, n=8192, FP64, rank-1 updates (IncrExp)",
             "ms_per_update": ms, "updates_per_s": 1000.0 / ms, "alg_bytes_per_update": alg,
-            "alg_GBps": alg / (ms * 1e-3) / 1e9,
+            "alg_GBps": alg / (ms * 1e-3) / 1e9, "tile_rows": tiles,
             "reeval_own_f64_mfma_ms": own, "reeval_torch_matmul_ms": tm,
             "reeval_own_tflops": 2.0 * n ** 3 * 4 / (own * 1e-3) / 1e12,
             "speedup_incremental_vs_best_reeval": min(own, tm) / ms}
@@ -775,7 +778,7 @@ def main():
     A64 = synth.gaussian_matrix(n, seed=args.seed, config=2)
     A32 = A64.astype(np.float32)
     del A64
-    Us64, Vs64 = synth.update_factors(n, r, total + args.latency_samples + args.timing_updates,
+    Us64, Vs64 = synth.update_factors(n, r, total + 2 * args.latency_samples + args.timing_updates,
                                       seed=args.seed, config=2)
     Us, Vs = Us64.astype(np.float32), Vs64.astype(np.float32)
     del Us64, Vs64
@@ -792,6 +795,10 @@ def main():
     torch.cuda.synchronize()
     create_s = time.perf_counter() - t0
     log(f"view created in {create_s:.2f} s (FP64 MFMA squarings)")
+    # tile rows for pipelined batches, picked by timing zero updates (the
+    # view's values are unchanged); every later call uses them
+    tile_rows = view.autotune(pipelined=True, trial_updates=24)
+    log(f"autotuned tile rows: {tile_rows}")
 
     # warmup
     view.update_batch(Ud[:args.warmup], Vd[:args.warmup])
@@ -820,15 +827,16 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"A^{k} matrix-power view, n={n}, FP32, rank-{r} updates (IncrExp)",
-                   "n": n, "k": k, "rank": r, "updates_timed": args.steps},
+                   "n": n, "k": k, "rank": r, "updates_timed": args.steps,
+                   "batch": "one lv_view_update_batch call, levels pipelined over streams",
+                   "tile_rows": tile_rows},
         "rank1_equiv_updates_per_s": ups * r,
         "hbm_GBps_algorithmic": alg_bytes_update * ups / 1e9,
         "create_s": create_s,
     }
 
-    if not args.quick:
-        # per-update latency
-        base = total
+    def latency(base):
+        """p50 / p99 of single lv_view_update calls (event pairs on the stream)."""
         lat = []
         for t in range(args.latency_samples):
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -838,9 +846,13 @@ def main():
             lat.append((a, b))
         torch.cuda.synchronize()
         lat_ms = np.array([a.elapsed_time(b) for a, b in lat])
-        result["latency_ms"] = {"p50": float(np.percentile(lat_ms, 50)),
-                                "p99": float(np.percentile(lat_ms, 99)),
-                                "samples": int(len(lat_ms))}
+        return {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
+                "samples": int(len(lat_ms))}
+
+    if not args.quick:
+        # per-update latency (single updates are sequential: each one's levels form a chain)
+        base = total
+        result["latency_ms"] = latency(base)
         log(f"latency p50 {result['latency_ms']['p50']:.3f} ms p99 {result['latency_ms']['p99']:.3f} ms")
 
         # dominant kernel: the fused level pass, timed with events by the library
@@ -855,7 +867,12 @@ def main():
         result["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                               "frac": achieved / HBM_PEAK_GBPS, "traffic": counter_traffic(n, k, r),
                               "kernel": "k_level_fused (levels 0..m-1)",
-                              "avg_launch_ms": fused_ms, "bytes_per_launch": bytes_launch}
+                              "avg_launch_ms": fused_ms, "bytes_per_launch": bytes_launch,
+                              # every pass of the timed (pipelined) region: the algorithmic bytes of
+                              # all m + 1 stored powers per update over the region's event time
+                              "timed_region_all_passes": {
+                                  "GBps": result["hbm_GBps_algorithmic"],
+                                  "frac": result["hbm_GBps_algorithmic"] / HBM_PEAK_GBPS}}
         result["kernel_ms_per_update"] = {
             "fused": tm["fused_ms"] / args.timing_updates, "tail": tm["tail_ms"] / args.timing_updates,
             "top_update": tm["top_ms"] / args.timing_updates}
@@ -863,6 +880,14 @@ def main():
         result["top_update_GBps"] = bytes_launch / (top_ms * 1e-3) / 1e9
         log(f"fused pass avg {fused_ms * 1e3:.1f} us -> {achieved:.0f} GB/s; "
             f"top update avg {top_ms * 1e3:.1f} us; per update {result['kernel_ms_per_update']}")
+
+        # the same view with tiles tuned for single updates instead (the
+        # tiles that suit pipelined batches lengthen each pass run alone)
+        lat_tiles = view.autotune(pipelined=False, trial_updates=24)
+        base += args.timing_updates
+        result["latency_ms_single_update_tiles"] = dict(latency(base), tile_rows=lat_tiles)
+        log(f"with tile rows {lat_tiles}: latency p50 {result['latency_ms_single_update_tiles']['p50']:.3f} ms "
+            f"p99 {result['latency_ms_single_update_tiles']['p99']:.3f} ms")
 
     if True:
         # measured streaming ceiling: a plain device copy of one stored power's size

@@ -167,6 +167,18 @@ lv_status lv_view_update_batch(lv_view* v, const void* U, const void* V, int64_t
                                int64_t count, int64_t ldu, int64_t ldv,
                                int64_t strideU, int64_t strideV, void* stream);
 
+/* Pick the view's tile rows (the same at every level) by measurement:
+ * for each allowed height 256, 384, ..., 1024 times `trial_updates` zero
+ * updates (U = V = 0, which leave every stored value and the update count
+ * unchanged bit for bit) as lv_view_update_batch runs them, pipelined
+ * (pipelined != 0) or one after the other, and keeps the fastest; *chosen
+ * (may be NULL) receives it.  Blocks the host until the trials are done
+ * (stream-ordered on `stream`).  The choice depends on the device's timing,
+ * so two runs may choose differently; lv_view_set_tile_rows fixes a value.
+ * Views without sums or general form (else LV_ESTATE); trial_updates in
+ * [2, 1000]. */
+lv_status lv_view_autotune(lv_view* v, int pipelined, int64_t trial_updates, void* stream, int* chosen);
+
 /* Turn the pipelining of lv_view_update_batch on (default) or off
  * (enable = 0: every batch runs its updates one after the other on
  * `stream`; the results are the same bit for bit). */

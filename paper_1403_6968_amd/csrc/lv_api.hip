@@ -481,7 +481,7 @@ lv_status gfac_finish(lv_view* v, int ru, const T* sU, hipStream_t s) {
 // read-only skinny pass, the Gram and the update pass), then the sums' and
 // the general form's level steps.  Stream-ordered on s.
 template <typename T>
-lv_status level_step(lv_view* v, int j, int r_pad, T* sU, T* sV, hipStream_t s) {
+lv_status level_step(lv_view* v, int j, int r_pad, T* sU, T* sV, hipStream_t s, bool pipelined = false) {
   const Layout& L = v->L;
   lv_status st = LV_OK;
   const int R = r_pad << j;
@@ -553,7 +553,8 @@ lv_status level_step(lv_view* v, int j, int r_pad, T* sU, T* sV, hipStream_t s) 
                                        v->partXs<T>(j), Dop, ldd, d_in_pass ? xd : 0, v->partXT<T>(), s);
       }
       return launch_level_fused<T>(R, v->P<T>(j), L.ldp, L.n_pad, v->tile_rows[j], sU, sV, L.W, v->partX<T>(j),
-                                   v->partY<T>(j), v->partG(j), s);
+                                   v->partY<T>(j), v->partG(j), s,
+                                   pipelined ? pipe_slice_groups(L.nct, v->nrt(j)) : 0);
     });
     if (st == LV_OK)
       st = timed(v, 1, s, "level tail", [&] {
@@ -674,7 +675,7 @@ lv_status update_batch_pipelined(lv_view* v, const char* U, const char* V, int r
       hipStream_t sj = stream_of(j);
       if (j > 0 && pipe_stage(v, j - 1) != pipe_stage(v, j))
         st = ev(hipStreamWaitEvent(sj, v->pready[j - 1][sl], 0), "hipStreamWaitEvent");
-      if (st == LV_OK) st = level_step<T>(v, j, r_pad, sU, sV, sj);
+      if (st == LV_OK) st = level_step<T>(v, j, r_pad, sU, sV, sj, true);
       if (st == LV_OK && j + 1 < L.m && pipe_stage(v, j + 1) != pipe_stage(v, j))
         st = ev(hipEventRecord(v->pready[j][sl], sj), "hipEventRecord");
     }
@@ -821,6 +822,8 @@ lv_status create_view(const void* A, int64_t n, int64_t lda, int k, int r_max, l
   }
   if (st == LV_OK)
     st = hip_check(hipMemsetAsync(v->gate(), 0, 128, s), "clear drift counters");
+  if (st == LV_OK)
+    st = hip_check(hipMemsetAsync(v->base + L.zfac, 0, (size_t)L.n_pad * L.r_pad * L.elem, s), "clear zero factors");
   if (st != LV_OK) { delete v; return st; }
   *out = v;
   return LV_OK;
@@ -1106,6 +1109,73 @@ lv_status lv_view_set_tile_rows(lv_view* v, int level, int rows) {
   if (rows < kMinTileRows || rows > kMaxTileRows || rows % 64 != 0)
     return fail(LV_EINVAL, "tile rows %d not a multiple of 64 in [%d, %d]", rows, kMinTileRows, kMaxTileRows);
   v->tile_rows[level] = rows;
+  return LV_OK;
+}
+
+lv_status lv_view_autotune(lv_view* v, int pipelined, int64_t trial_updates, void* stream, int* chosen) {
+  g_err[0] = 0;
+  if (!v) return fail(LV_EINVAL, "view is NULL");
+  if (v->L.sums) return fail(LV_ESTATE, "autotune takes views without sums or general form");
+  if (trial_updates < 2 || trial_updates > 1000) return fail(LV_EINVAL, "trial_updates %lld not in [2, 1000]",
+                                                               (long long)trial_updates);
+  if (v->L.m == 0) { if (chosen) *chosen = v->tile_rows[0]; return LV_OK; }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
+    return fail(LV_EDEVICE, "hipEventCreate failed");
+  }
+  // zero updates: every stored value and the update count stay as they are;
+  // no drift check, no timing records
+  int saved[kMaxLevel];
+  for (int j = 0; j < kMaxLevel; ++j) saved[j] = v->tile_rows[j];
+  const int64_t updates = v->updates, every = v->drift_every;
+  const bool timing = v->timing, pipe = v->pipeline;
+  v->drift_every = 0;
+  v->timing = false;
+  v->pipeline = pipelined != 0;
+  const char* Z = v->base + v->L.zfac;
+  const int r = v->L.r_pad;
+  auto run = [&](int64_t count) -> lv_status {
+    if (v->pipeline && v->L.pipe_slots > 1)
+      return v->mode == LV_FP64 ? update_batch_pipelined<double>(v, Z, Z, r, count, r, r, 0, 0, s)
+                                : update_batch_pipelined<float>(v, Z, Z, r, count, r, r, 0, 0, s);
+    for (int64_t t = 0; t < count; ++t) {
+      const lv_status st = v->mode == LV_FP64
+                               ? update_one<double>(v, reinterpret_cast<const double*>(Z),
+                                                    reinterpret_cast<const double*>(Z), r, r, r, s)
+                               : update_one<float>(v, reinterpret_cast<const float*>(Z),
+                                                   reinterpret_cast<const float*>(Z), r, r, r, s);
+      if (st != LV_OK) return st;
+    }
+    return LV_OK;
+  };
+  lv_status st = LV_OK;
+  float best = 0.0f;
+  int best_rows = saved[0];
+  for (int rows = kMinTileRows; rows <= kMaxTileRows && st == LV_OK; rows += 128) {
+    for (int j = 0; j < v->L.m; ++j) v->tile_rows[j] = rows;
+    st = run(2);
+    if (st == LV_OK && hipEventRecord(a, s) != hipSuccess) st = fail(LV_EDEVICE, "hipEventRecord failed");
+    if (st == LV_OK) st = run(trial_updates);
+    if (st == LV_OK && (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess))
+      st = fail(LV_EDEVICE, "timing the trial failed");
+    float ms = 0.0f;
+    if (st == LV_OK && hipEventElapsedTime(&ms, a, b) != hipSuccess) st = fail(LV_EDEVICE, "hipEventElapsedTime failed");
+    if (st == LV_OK && (best == 0.0f || ms < best)) { best = ms; best_rows = rows; }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  v->updates = updates;
+  v->drift_every = every;
+  v->timing = timing;
+  v->pipeline = pipe;
+  if (st != LV_OK) {
+    for (int j = 0; j < kMaxLevel; ++j) v->tile_rows[j] = saved[j];
+    return st;
+  }
+  for (int j = 0; j < v->L.m; ++j) v->tile_rows[j] = best_rows;
+  if (chosen) *chosen = best_rows;
   return LV_OK;
 }
 

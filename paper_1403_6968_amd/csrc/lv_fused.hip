@@ -385,6 +385,20 @@ __global__ void __launch_bounds__(256) k_level_fused(const FusedDesc<T> d) {
                             blockIdx.x, blockIdx.y);
 }
 
+// The same pass with gridDim.y below the slice count: row slices rt =
+// blockIdx.y, blockIdx.y + gridDim.y, ... one after the other (fewer,
+// longer-lived work-groups; every slice is summed exactly as with one
+// work-group per slice, so the partials are the same bit for bit).
+template <typename T, int R, int RB, bool UPD>
+__global__ void __launch_bounds__(256) k_level_fused_grouped(const FusedDesc<T> d) {
+  const int ns = (d.n_pad + d.tile_rows - 1) / d.tile_rows;
+  for (int rt = blockIdx.y; rt < ns; rt += gridDim.y) {
+    fused_body<T, R, RB, UPD>(d.P, d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.partX, d.partY, d.partG, d.pR,
+                              blockIdx.x, rt);
+    __syncthreads();   // the next slice restages the LDS tiles
+  }
+}
+
 // The powers' pass of a view with sums or a general form: X also for Q_j
 // (XE = R columns or none) and for D_j (XD columns or none).
 template <typename T, int R, int RB, int XE, int XD>
@@ -412,11 +426,18 @@ __global__ void __launch_bounds__(256) k_level_fused_multi(const FusedDesc<T>* _
 
 template <typename T, int R, int RB, bool UPD>
 hipError_t fused_launch(T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* Uj, const T* Vj,
-                        int W, T* partX, T* partY, double* partG, int pR, hipStream_t s) {
+                        int W, T* partX, T* partY, double* partG, int pR, hipStream_t s, int slice_groups = 0) {
   const int nct = (int)(n_pad / tile_cols<T>());
   const FusedDesc<T> d{P, ldp, (int)n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, pR, nct, 0};
-  const dim3 grid((unsigned)nct, (unsigned)((n_pad + tile_rows - 1) / tile_rows));
-  hipLaunchKernelGGL((k_level_fused<T, R, RB, UPD>), grid, dim3(256), 0, s, d);
+  const int ns = (int)((n_pad + tile_rows - 1) / tile_rows);
+  if constexpr (UPD && R <= 8) {
+    if (slice_groups > 0 && slice_groups < ns) {
+      hipLaunchKernelGGL((k_level_fused_grouped<T, R, RB, UPD>), dim3((unsigned)nct, (unsigned)slice_groups),
+                         dim3(256), 0, s, d);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_level_fused<T, R, RB, UPD>), dim3((unsigned)nct, (unsigned)ns), dim3(256), 0, s, d);
   return hipGetLastError();
 }
 
@@ -425,10 +446,11 @@ hipError_t fused_launch(T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T
 // update pass.
 template <typename T, int R>
 hipError_t fused_r(T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* Uj, const T* Vj,
-                   int W, T* partX, T* partY, double* partG, hipStream_t s) {
+                   int W, T* partX, T* partY, double* partG, hipStream_t s, int slice_groups) {
   if constexpr (R <= kMaxFusedRank) {
     constexpr int RB = fused_row_block(R);
-    return fused_launch<T, R, RB, true>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, R, s);
+    return fused_launch<T, R, RB, true>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, R, s,
+                                        slice_groups);
   } else {
     constexpr int RC = kMaxFusedRank;
     for (int c0 = 0; c0 < R; c0 += RC) {
@@ -448,10 +470,11 @@ hipError_t fused_r(T* P, int64_t ldp, int64_t n_pad, int tile_rows, const T* Uj,
 template <typename T>
 hipError_t launch_level_fused(int R, T* P, int64_t ldp, int64_t n_pad, int tile_rows,
                               const T* slabU, const T* slabV, int W, T* partX, T* partY,
-                              double* partG, hipStream_t s) {
+                              double* partG, hipStream_t s, int slice_groups) {
   const T* Uj = slabU;
   const T* Vj = slabV + (W - R);
-  LV_RANK_SWITCH(R, return (fused_r<T, RR>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s)))
+  LV_RANK_SWITCH(R, return (fused_r<T, RR>(P, ldp, n_pad, tile_rows, Uj, Vj, W, partX, partY, partG, s,
+                                           slice_groups)))
 }
 
 // Launch k_level_fused_x for level rank R with XE (0 or R) and xd (0, 1, 2,
@@ -568,9 +591,9 @@ template hipError_t launch_level_readonly<double>(int, const double*, int64_t, i
                                                   const double*, int, double*, double*, hipStream_t);
 
 template hipError_t launch_level_fused<float>(int, float*, int64_t, int64_t, int, const float*, const float*, int,
-                                              float*, float*, double*, hipStream_t);
+                                              float*, float*, double*, hipStream_t, int);
 template hipError_t launch_level_fused<double>(int, double*, int64_t, int64_t, int, const double*, const double*,
-                                               int, double*, double*, double*, hipStream_t);
+                                               int, double*, double*, double*, hipStream_t, int);
 template hipError_t launch_level_fused_x<float>(int, float*, int64_t, int64_t, int, const float*, const float*, int,
                                                 float*, float*, double*, const float*, float*, const float*, int, int,
                                                 float*, hipStream_t);

@@ -28,6 +28,16 @@ constexpr int kMaxLevel = 10;
 // (updates in flight).
 constexpr int kPipeStreams = 4;
 constexpr int kMaxPipeSlots = 5;
+// Work-groups a fused level pass is cut into inside a pipelined batch: one
+// per compute unit (the device has 256), so that the passes of two stages
+// share every unit instead of one pass filling the device with two
+// work-groups per unit.  Returns the work-groups per column tile for nct
+// column tiles and ns row slices (each takes ceil(ns / groups) slices).
+constexpr int kPipePassBlocks = 256;
+inline int pipe_slice_groups(int nct, int ns) {
+  const int spb = (nct * ns + kPipePassBlocks - 1) / kPipePassBlocks;
+  return spb <= 1 ? ns : (ns + spb - 1) / spb;
+}
 
 inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
@@ -169,11 +179,13 @@ hipError_t launch_prep(const T* U, int64_t ldu, const T* V, int64_t ldv, int64_t
 
 // Fused level pass for level rank R: partial X = P U_j, partial Y = P^T V_j,
 // partial Gram V_j^T U_j (column tile 0 only), and P += U_j V_j^T, in one
-// read and one write of P.
+// read and one write of P.  slice_groups > 0: that many work-groups per
+// column tile, each taking several row slices in turn (same partials, bit
+// for bit; see pipe_slice_groups).
 template <typename T>
 hipError_t launch_level_fused(int R, T* P, int64_t ldp, int64_t n_pad, int tile_rows,
                               const T* slabU, const T* slabV, int W, T* partX, T* partY,
-                              double* partG, hipStream_t s);
+                              double* partG, hipStream_t s, int slice_groups = 0);
 
 // Tail of level j: reduce partials in a fixed order, G = sum of the ng
 // partial Grams, U_{j+1} = [U_j, X + U_j G], V_{j+1} = [Y, V_j].

@@ -38,6 +38,9 @@ struct Layout {
   // 0 is slabU / slabV, slots 1 .. pipe_slots - 1 follow
   int pipe_slots = 0;
   size_t pslabU[kMaxPipeSlots] = {}, pslabV[kMaxPipeSlots] = {};
+  // n_pad x r_pad zeros (set at creation): the factors of the zero updates
+  // that lv_view_autotune times (P + 0 0^T = P exactly)
+  size_t zfac = 0;
   size_t partX[kMaxLevel] = {};
   size_t partY[kMaxLevel] = {};
   size_t partG[kMaxLevel] = {};
@@ -138,6 +141,10 @@ inline Layout make_layout(int64_t n, int k, int r_max, lv_mode mode, int flags =
       L.pslabU[q] = off; off = align_up(off + slab);
       L.pslabV[q] = off; off = align_up(off + slab);
     }
+  }
+  if (!ext_powers) {
+    L.zfac = off;
+    off = align_up(off + (size_t)L.n_pad * L.r_pad * L.elem);
   }
   for (int j = 0; j < L.m; ++j) {
     const size_t R = (size_t)L.r_pad << j;

@@ -37,7 +37,7 @@ EXPORTED = (
     "lv_status_str", "lv_last_error", "lv_view_footprint", "lv_view_create",
     "lv_view_update", "lv_view_update_batch", "lv_view_read", "lv_view_data",
     "lv_view_reanchor", "lv_view_stats", "lv_view_destroy", "lv_reeval_footprint",
-    "lv_reeval", "lv_view_set_timing", "lv_view_set_pipeline", "lv_view_timing", "lv_view_write", "lv_view_drift_check",
+    "lv_reeval", "lv_view_set_timing", "lv_view_set_pipeline", "lv_view_autotune", "lv_view_timing", "lv_view_write", "lv_view_drift_check",
     "lv_batch_footprint", "lv_batch_create", "lv_batch_inputs", "lv_batch_stage", "lv_batch_update",
     "lv_batch_destroy", "lv_server_create", "lv_server_view_bytes", "lv_server_set_hold", "lv_server_add_view",
     "lv_server_remove_view", "lv_server_view", "lv_server_now", "lv_server_submit", "lv_server_step",
@@ -119,6 +119,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "lv_reeval": (I32, [P, I64, I64, I32, P, P, I64, I64, I64, I32, P, I64, P, SZ, P]),
         "lv_view_set_timing": (I32, [P, I32]),
         "lv_view_set_pipeline": (I32, [P, I32]),
+        "lv_view_autotune": (I32, [P, I32, I64, P, P]),
         "lv_view_write": (I32, [P, I32, P, I64, P]),
         "lv_view_drift_check": (I32, [P, P, c.c_double, P, P]),
         "lv_batch_footprint": (SZ, [c.POINTER(P), I32]),
@@ -347,6 +348,13 @@ def lv_view_set_pipeline(view, enable: bool) -> None:
     _check(load().lv_view_set_pipeline(view, 1 if enable else 0))
 
 
+def lv_view_autotune(view, pipelined: bool = True, trial_updates: int = 24, stream=None, device=None) -> int:
+    chosen = ctypes.c_int()
+    _check(load().lv_view_autotune(view, 1 if pipelined else 0, int(trial_updates), _stream(stream, device),
+                                   ctypes.byref(chosen)))
+    return chosen.value
+
+
 def lv_view_tile_rows(view, level: int) -> int:
     rows = ctypes.c_int()
     _check(load().lv_view_tile_rows(view, level, ctypes.byref(rows)))
@@ -539,6 +547,10 @@ class View:
     def set_pipeline(self, enable: bool) -> None:
         """Pipelined (default) or sequential update_batch; equal results."""
         lv_view_set_pipeline(self.handle, enable)
+
+    def autotune(self, pipelined: bool = True, trial_updates: int = 24, stream=None) -> int:
+        """Tile rows chosen by timing zero updates (the view is unchanged)."""
+        return lv_view_autotune(self.handle, pipelined, trial_updates, stream, self.device)
 
     def timing(self) -> dict:
         return lv_view_timing(self.handle)

@@ -127,6 +127,8 @@ def test_tile_and_tuning_calls_validate(lib):
     assert lib.lv_view_tile_rows(None, 0, ctypes.byref(rows)) == L.LV_EINVAL
     assert lib.lv_view_set_tile_rows(None, 0, 512) == L.LV_EINVAL
     assert lib.lv_batch_tuning(None, None, None) == L.LV_EINVAL
+    assert lib.lv_view_set_pipeline(None, 1) == L.LV_EINVAL
+    assert lib.lv_view_autotune(None, 1, 24, None, None) == L.LV_EINVAL
 
 
 def test_sums_footprint_and_flags(lib):

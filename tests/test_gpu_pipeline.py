@@ -130,3 +130,37 @@ def test_two_views_pipelined_concurrently():
             assert torch.equal(v.read(p), w.read(p)), p
         v.close()
         w.close()
+
+
+@pytest.mark.parametrize("pipelined", [True, False])
+def test_autotune_leaves_view_unchanged(pipelined):
+    """lv_view_autotune times zero updates only: every stored power and the
+    update count are unchanged bit for bit, the chosen height is an allowed
+    one and is set on every level; updates after it still equal the
+    sequential order with the same tiles and the oracle."""
+    torch, lv, mode, dt, A, Us, Vs = _setup("fp32", 1300, 16, 1, 12, seed=15)
+    Ad, Ud, Vd = dev(A, dt), dev(Us, dt), dev(Vs, dt)
+    a = lv.View(Ad, 16)
+    a.update_batch(Ud[:4], Vd[:4])
+    torch.cuda.synchronize()
+    before = {p: a.read(p) for p in a.powers()}
+    rows = a.autotune(pipelined=pipelined, trial_updates=4)
+    note(f"pipelined={pipelined}: chose {rows} tile rows")
+    assert rows in range(256, 1025, 128)
+    assert a.tile_rows() == [rows] * 4
+    assert a.stats()["updates"] == 4
+    for p in a.powers():
+        assert torch.equal(a.read(p), before[p]), p
+    b = lv.View(Ad, 16)                      # the same tile history as a: 512, then the chosen rows
+    b.set_pipeline(False)
+    b.update_batch(Ud[:4], Vd[:4])
+    b.set_tile_rows([rows] * 4)
+    a.update_batch(Ud[4:], Vd[4:])
+    b.update_batch(Ud[4:], Vd[4:])
+    ref = _oracle(A, Us, Vs, 16)
+    for p in a.powers():
+        pa = a.read(p)
+        assert torch.equal(pa, b.read(p)), p
+        assert O.maxrel(host(pa), ref[p]) < 1e-4
+    a.close()
+    b.close()
