@@ -50,7 +50,7 @@ def parse():
     p.add_argument("--no-secondary", action="store_true",
                    help="skip the rank-4, batched and serving workloads")
     p.add_argument("--serve-seconds", type=float, default=2.0)
-    p.add_argument("--only", choices=["rank4", "batched", "serving", "sums", "general", "models", "ols", "glin",
+    p.add_argument("--only", choices=["rank4", "batched", "serving", "sums", "general", "models", "ols", "glin", "ceiling",
                                       "fp64", "small", "serving32", "capacity"],
                    help="run one secondary workload alone and print its result (for profilers)")
     return p.parse_args()
@@ -102,6 +102,56 @@ def bench_rank4(torch, lv, synth, dev, steps=200, drift_every=100):
                     "level_passes_ms": tm["fused_ms"], "tails_ms": tm["tail_ms"], "top_update_ms": tm["top_ms"],
                     "drift_check": drift}
     del A
+    return out
+
+
+def stream_ceiling(torch, lv, dev, power_bytes, reps=5):
+    """Measured HBM ceiling for the level passes' access pattern: the
+    library's streaming kernels (lv_stream_probe: 16-byte non-temporal loads
+    and stores, whole 1 KiB row segments per wave) swept over work-groups
+    per CU (1..32), 4 KiB chunks in flight per iteration (1..32) and
+    pipelined / plain issue, on buffers of 2 GiB and of one stored power.
+    Per kind and size the best median rate; RMW (read and write of one
+    buffer in place) is the level passes' pattern."""
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    big = 2 << 30
+    a = torch.zeros(big // 4, dtype=torch.float32, device=dev)
+    b = torch.zeros(big // 4, dtype=torch.float32, device=dev)
+    sink = torch.zeros(32 * cus * 256, dtype=torch.float32, device=dev)
+    names = {lv.LV_STREAM_RMW: "rmw", lv.LV_STREAM_COPY: "copy", lv.LV_STREAM_READ: "read",
+             lv.LV_STREAM_WRITE: "write"}
+    out = {"kernel": "lv_stream_probe", "cus": cus}
+    for nbytes, tag in ((big, "2GiB"), (power_bytes, "one_power")):
+        nbytes -= nbytes % (4096 * 32)
+        for kind, name in names.items():
+            best = None
+            for depth in (1, 2, 4, 8, 16, 32):
+                for bpc in (1, 2, 4, 8, 16, 32):
+                    for pipe in ((0,) if kind == lv.LV_STREAM_WRITE else (0, 1)):
+                        if kind == lv.LV_STREAM_READ:
+                            f = lambda: lv.lv_stream_probe(kind, sink, a, nbytes, bpc * cus, depth, pipe)
+                        elif kind == lv.LV_STREAM_COPY:
+                            f = lambda: lv.lv_stream_probe(kind, b, a, nbytes, bpc * cus, depth, pipe)
+                        else:
+                            f = lambda: lv.lv_stream_probe(kind, a, None, nbytes, bpc * cus, depth, pipe)
+                        f()
+                        evs = []
+                        for _ in range(reps):
+                            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                            e0.record()
+                            f()
+                            e1.record()
+                            evs.append((e0, e1))
+                        torch.cuda.synchronize()
+                        ms = sorted(x.elapsed_time(y) for x, y in evs)[reps // 2]
+                        moved = nbytes * (2 if kind in (lv.LV_STREAM_RMW, lv.LV_STREAM_COPY) else 1)
+                        gbps = moved / (ms * 1e-3) / 1e9
+                        if best is None or gbps > best["GBps"]:
+                            best = {"GBps": gbps, "blocks_per_cu": bpc, "depth": depth, "pipelined": pipe,
+                                    "bytes": nbytes}
+            out[f"{name}_{tag}"] = best
+    del a, b, sink
+    torch.cuda.empty_cache()
     return out
 
 
@@ -768,6 +818,7 @@ def main():
               "ols": lambda: bench_ols(torch, lv, synth, dev),
               "glin": lambda: bench_glin(torch, lv, synth, dev),
               "fp64": lambda: bench_fp64(torch, lv, synth, dev),
+              "ceiling": lambda: stream_ceiling(torch, lv, dev, 4 * 8192 * 8192),
               "small": lambda: bench_small_fp64(torch, lv, synth, dev)}[args.only]
         print(json.dumps({"only": args.only, "result": fn()}), flush=True)
         return
@@ -905,10 +956,21 @@ def main():
         copy_ms = a.elapsed_time(b) / 10
         result["copy_ref"] = {"bytes": 2 * 4 * n_pad * n_pad, "ms": copy_ms,
                               "GBps": 2 * 4 * n_pad * n_pad / (copy_ms * 1e-3) / 1e9}
-        if "roofline" in result:
-            result["roofline"]["frac_of_copy"] = result["roofline"]["achieved"] / result["copy_ref"]["GBps"]
         log(f"copy reference: {result['copy_ref']['GBps']:.0f} GB/s")
         del src, dst
+    if not args.quick:
+        # measured ceiling of the passes' access pattern (in-place read and write)
+        ceil = stream_ceiling(torch, lv, dev, 4 * n_pad * n_pad)
+        result["stream_ceiling"] = ceil
+        rmw = max(ceil["rmw_one_power"]["GBps"], ceil["rmw_2GiB"]["GBps"])
+        log(f"streaming ceiling (in-place read+write): {ceil['rmw_one_power']['GBps']:.0f} GB/s on one power, "
+            f"{ceil['rmw_2GiB']['GBps']:.0f} GB/s on 2 GiB; copy {ceil['copy_2GiB']['GBps']:.0f}, "
+            f"read {ceil['read_2GiB']['GBps']:.0f}, write {ceil['write_2GiB']['GBps']:.0f}")
+        if "roofline" in result:
+            result["roofline"]["frac_of_copy"] = result["roofline"]["achieved"] / result["copy_ref"]["GBps"]
+            result["roofline"]["frac_of_stream_ceiling"] = result["roofline"]["achieved"] / rmw
+            agg = result["roofline"]["timed_region_all_passes"]
+            agg["frac_of_stream_ceiling"] = agg["GBps"] / rmw
 
     if not args.quick and not args.no_reeval:
         ws = torch.empty(lv.lv_reeval_footprint(n, r, lv.LV_FP32), dtype=torch.uint8, device=dev)

@@ -32,10 +32,11 @@ constexpr int kMaxPipeSlots = 5;
 // per compute unit (the device has 256), so that the passes of two stages
 // share every unit instead of one pass filling the device with two
 // work-groups per unit.  Returns the work-groups per column tile for nct
-// column tiles and ns row slices (each takes ceil(ns / groups) slices).
+// column tiles and ns row slices (each takes ceil(ns / groups) slices;
+// never fewer than kPipePassBlocks work-groups in all).
 constexpr int kPipePassBlocks = 256;
 inline int pipe_slice_groups(int nct, int ns) {
-  const int spb = (nct * ns + kPipePassBlocks - 1) / kPipePassBlocks;
+  const int spb = nct * ns / kPipePassBlocks;
   return spb <= 1 ? ns : (ns + spb - 1) / spb;
 }
 
