@@ -256,9 +256,11 @@ __device__ __forceinline__ void chunk_update(float* __restrict__ P, const int64_
   }
 }
 
-// Float skinny pass.  Tile: tile_rows x 256 columns of P, chunks of 32 rows
-// through LDS (the next chunk of P and V_j held in registers meanwhile);
-// factor columns padded with zeros to 32 NB (NB <= 2).
+// Float skinny pass.  Tile: about tile_rows x 256 columns of P, chunks of 32
+// rows through LDS (the next chunk of P and V_j held in registers meanwhile);
+// factor columns padded with zeros to 32 NB (NB <= 2).  The ns row slices of
+// a column tile interleave by chunks (slice rt takes chunks rt, rt + ns, ...),
+// so the grid streams one band of rows at a time.
 //   X: the chunk's 32 x 32 NB outputs with K = 256 split over the waves
 //      (wave w: columns [64 w, 64 w + 64)); the four partial sums meet in
 //      LDS (over the chunk buffer, no longer read) and are added in wave
@@ -292,8 +294,11 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int col0 = ct * TCB;
-  const int row0 = rt * tile_rows;
-  const int rend = min(row0 + tile_rows, n_pad);
+  // interleaved chunks: slice rt of ns takes chunks rt, rt + ns, ...
+  const int ns = (n_pad + tile_rows - 1) / tile_rows;
+  const int CS = ns * 32;
+  const int row0 = rt * 32;
+  const int rend = n_pad;
   const int l32 = lane % 32, lh = lane / 32;
   // chunk staging: thread -> rows tid / 64 + 4 i, f32x4 column group tid % 64
   const int srow = tid / 64, sgrp = tid % 64;
@@ -343,7 +348,7 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
 #pragma unroll
       for (int v = 0; v < 16; ++v) yacc[a][b][v] = 0.f;
 
-  for (int cr0 = row0; cr0 < rend; cr0 += CR) {
+  for (int cr0 = row0; cr0 < rend; cr0 += CS) {
     __syncthreads();   // the previous chunk's exchange buffer has been read
     if (mwave) {
       static_for<0, CR / 4>([&](auto i) { *reinterpret_cast<f32x4*>(&sP[srow + 4 * i][sgrp * 4]) = pre[i]; });
@@ -360,12 +365,12 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
     __syncthreads();
     if constexpr (UPD) {
       if (!mwave) {
-        if (cr0 + CR < rend) fetch_u(cr0 + CR);
+        if (cr0 + CS < rend) fetch_u(cr0 + CS);
         chunk_update<CR, TCB + FP, RP + FP>(const_cast<float*>(P), ldp, col0, cr0, R, sP, sUr, sVc, wave - 4, lane);
         continue;
       }
     }
-    if (cr0 + CR < rend) fetch(cr0 + CR);
+    if (cr0 + CS < rend) fetch(cr0 + CS);
 
     if constexpr (NB == 1) {
       // one 32-column factor block: wave w forms the 16 x 16 X tile of rows
@@ -507,8 +512,11 @@ __device__ __forceinline__ void skinny16_f32_body(const float* __restrict__ P, c
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int col0 = ct * TCB;
-  const int row0 = rt * tile_rows;
-  const int rend = min(row0 + tile_rows, n_pad);
+  // interleaved chunks: slice rt of ns takes chunks rt, rt + ns, ...
+  const int ns = (n_pad + tile_rows - 1) / tile_rows;
+  const int CS = ns * 32;
+  const int row0 = rt * 32;
+  const int rend = n_pad;
   const int l16 = lane % 16, lq = lane / 16;
   const int srow = tid / 64, sgrp = tid % 64;
 
@@ -553,7 +561,7 @@ __device__ __forceinline__ void skinny16_f32_body(const float* __restrict__ P, c
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) yacc[cb] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  for (int cr0 = row0; cr0 < rend; cr0 += CR) {
+  for (int cr0 = row0; cr0 < rend; cr0 += CS) {
     __syncthreads();   // the previous chunk's exchange buffer has been read
     if (mwave) {
       static_for<0, CR / 4>([&](auto i) { *reinterpret_cast<f32x4*>(&sP[srow + 4 * i][sgrp * 4]) = pre[i]; });
@@ -570,7 +578,7 @@ __device__ __forceinline__ void skinny16_f32_body(const float* __restrict__ P, c
     __syncthreads();
     if constexpr (UPD) {
       if (!mwave) {
-        if (cr0 + CR < rend) fetch_u(cr0 + CR);
+        if (cr0 + CS < rend) fetch_u(cr0 + CS);
         chunk_update<CR, TCB + FP, RP + FP>(const_cast<float*>(P), ldp, col0, cr0, R, sP, sUr, sVc, wave - 4, lane);
         if (wx) {              // the X exchange below overwrites the chunk: take part in its barriers
           __syncthreads();
@@ -579,7 +587,7 @@ __device__ __forceinline__ void skinny16_f32_body(const float* __restrict__ P, c
         continue;
       }
     }
-    if (cr0 + CR < rend) fetch(cr0 + CR);
+    if (cr0 + CS < rend) fetch(cr0 + CS);
 
     // X partial over this wave's 64 columns, two 16-row blocks
     v4f xacc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
