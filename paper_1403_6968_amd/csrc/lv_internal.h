@@ -149,12 +149,16 @@ inline bool fused_vector_level(int R, int elem, bool shadowed) { return !shadowe
 // vector kernel, below the ranks that run on the matrix cores.
 inline bool sums_fused(int R, int elem) { return R <= kMaxFusedRank && !skinny_on_mfma(R, elem); }
 // Work-groups of a tail launch / Gram pairs per work-group for rank R.
-// Level ranks from which the tail works on 64-row x 32-column blocks.
-constexpr int kSlicedTailRank = 64;
+// Level ranks from which the tail works on column slices of min(R, 32)
+// columns, one column per lane and kTailRowsPerThread rows per thread.
+constexpr int kSlicedTailRank = 16;
+constexpr int kTailRowsPerThread = 4;
+inline int tail_slice_cols(int R) { return R < 32 ? R : 32; }
+inline int tail_block_rows(int R) { return 256 / tail_slice_cols(R) * kTailRowsPerThread; }
 // Lanes per output entry of the tail below kSlicedTailRank.
 constexpr int kTailLanes = 8;
 inline int tail_blocks(int64_t n_pad, int R) {
-  return R >= kSlicedTailRank ? (int)(n_pad / 64) * (R / 32)
+  return R >= kSlicedTailRank ? (int)(n_pad / tail_block_rows(R)) * (R / tail_slice_cols(R))
                               : (int)((n_pad * R * kTailLanes + 255) / 256);
 }
 inline int gram_pairs_per_block(int R) {

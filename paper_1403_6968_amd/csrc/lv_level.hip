@@ -186,29 +186,60 @@ __device__ __forceinline__ void tail_body(const T* __restrict__ partX, const T* 
       Vnew[i * W + c] = (T)y;
     }
   } else {
-    constexpr int NS = R / 32;
-    __shared__ double G[R][32];
+    // Column slice cs of CW columns: lane column cl = tid % CW, row lane
+    // rl = tid / CW; the thread takes rows rl + TPR q (q < Q) of the
+    // block's RPB rows, so a wave reads whole 128-byte row segments of
+    // every partial and carries Q independent sums.  Each entry sums its
+    // partials t = 0, 1, ... and its terms d = 0, 1, ... of U_j G in index
+    // order.
+    constexpr int CW = R < 32 ? R : 32;
+    constexpr int NS = R / CW;
+    constexpr int TPR = 256 / CW;
+    constexpr int Q = kTailRowsPerThread;
+    constexpr int RPB = TPR * Q;
+    __shared__ double G[R][CW];
     const int rb = blk / NS, cs = blk % NS;
-    const int cl = tid % 32;
-    const int c = cs * 32 + cl;
-    for (int e = tid; e < R * 32; e += 256) {
-      const int d = e / 32, cc = cs * 32 + e % 32;
+    const int cl = tid % CW, rl = tid / CW;
+    const int c = cs * CW + cl;
+    for (int e = tid; e < R * CW; e += 256) {
+      const int d = e / CW, cc = cs * CW + e % CW;
       double g = 0.0;
       for (int t = 0; t < ng; ++t) g += partG[(int64_t)t * R * R + d * R + cc];
-      G[d][e % 32] = g;
+      G[d][e % CW] = g;
     }
     __syncthreads();
-#pragma unroll 1
-    for (int q = 0; q < 8; ++q) {
-      const int64_t i = (int64_t)rb * 64 + tid / 32 + 8 * q;
-      const int64_t idx = i * R + c;
-      const double x = sum_partials(partX, strideX, idx, nct);
-      const double y = sum_partials(partY, strideX, idx, nrt);
+    int64_t idx[Q];
+    double x[Q], y[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      idx[q] = ((int64_t)rb * RPB + rl + TPR * q) * R + c;
+      x[q] = 0.0;
+      y[q] = 0.0;
+    }
+#pragma unroll 2
+    for (int t = 0; t < nct; ++t) {
+      T v[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) v[q] = partX[(int64_t)t * strideX + idx[q]];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) x[q] += (double)v[q];
+    }
+#pragma unroll 2
+    for (int t = 0; t < nrt; ++t) {
+      T v[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) v[q] = partY[(int64_t)t * strideX + idx[q]];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) y[q] += (double)v[q];
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int64_t i = (int64_t)rb * RPB + rl + TPR * q;
       double ug = 0.0;
 #pragma unroll 8
       for (int d = 0; d < R; ++d) ug = fma((double)Ucur[i * W + d], G[d][cl], ug);
-      Unew[i * W + c] = (T)(x + ug);
-      Vnew[i * W + c] = (T)y;
+      Unew[i * W + c] = (T)(x[q] + ug);
+      Vnew[i * W + c] = (T)y[q];
     }
   }
 }

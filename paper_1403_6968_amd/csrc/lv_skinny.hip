@@ -190,8 +190,10 @@ __device__ __forceinline__ void skinny_body(const uint16_t* __restrict__ S, cons
     }
 }
 
+// Two waves per SIMD (two work-groups per CU, which the LDS allows): the
+// one-block form would otherwise take 258 registers and run one wave per SIMD.
 template <int NB>
-__global__ void __launch_bounds__(256) k_skinny_bf16(const SkinnyDesc d) {
+__global__ void __launch_bounds__(256, 2) k_skinny_bf16(const SkinnyDesc d) {
   skinny_body<NB>(static_cast<const uint16_t*>(d.src), d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.R, d.partX, d.partY, d.pR, blockIdx.x,
                   blockIdx.y);
 }
@@ -208,7 +210,7 @@ __device__ __forceinline__ int find_skinny(const SkinnyDesc* __restrict__ ds, in
 }
 
 template <int NB>
-__global__ void __launch_bounds__(256) k_skinny_bf16_multi(const SkinnyDesc* __restrict__ ds, int nd) {
+__global__ void __launch_bounds__(256, 2) k_skinny_bf16_multi(const SkinnyDesc* __restrict__ ds, int nd) {
   const SkinnyDesc d = ds[find_skinny(ds, nd, (int)blockIdx.x)];
   const int local = (int)blockIdx.x - d.block_begin;
   skinny_body<NB>(static_cast<const uint16_t*>(d.src), d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.R, d.partX, d.partY, d.pR,
