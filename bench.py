@@ -51,7 +51,7 @@ def parse():
                    help="skip the rank-4, batched and serving workloads")
     p.add_argument("--serve-seconds", type=float, default=2.0)
     p.add_argument("--only", choices=["rank4", "batched", "serving", "sums", "general", "models", "ols", "glin", "ceiling",
-                                      "fp64", "small", "serving32", "capacity"],
+                                      "fp64", "small", "serving32", "capacity", "serving_kernels"],
                    help="run one secondary workload alone and print its result (for profilers)")
     return p.parse_args()
 
@@ -715,6 +715,32 @@ def bench_serving_capacity(torch, lv, synth, dev, rate=20000.0, r_cap=16, shadow
             "update_ms_by_n": {str(n): t * 1e3 for n, t in sorted(times.items())}}
 
 
+def bench_serving_kernels(torch, lv, synth, dev, reps=2):
+    """The kernels of one rank-16 update of serving views, for a kernel
+    trace: the largest serving view (n = 15278) and a middle one (n = 7022)
+    with bfloat16 shadows, and the largest in plain FP32, each applying
+    rank-16 updates one at a time (as a serving round runs a view's levels)."""
+    out = {}
+    for n, mode, tag in ((15278, lv.LV_FP32_BF16SHADOW, "shadow"), (7022, lv.LV_FP32_BF16SHADOW, "shadow"),
+                         (15278, lv.LV_FP32, "fp32")):
+        A = torch.from_numpy(synth.gaussian_matrix(n, seed=0, config=5, view=1).astype(np.float32)).to(dev)
+        U, V = synth.update_factors(n, 16, reps + 2, seed=0, config=5, view=1)
+        Ud, Vd = torch.from_numpy(U.astype(np.float32)).to(dev), torch.from_numpy(V.astype(np.float32)).to(dev)
+        view = lv.View(A, 16, r_max=16, mode=mode)
+        del A
+        view.set_pipeline(False)
+        view.update_batch(Ud[:2], Vd[:2])
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        view.update_batch(Ud[2:], Vd[2:])
+        b.record()
+        torch.cuda.synchronize()
+        view.close()
+        out[f"n{n}_{tag}"] = {"ms_per_rank16_update": a.elapsed_time(b) / reps}
+    return out
+
+
 def counter_traffic(n, k, r):
     """HBM bytes per fused launch from the committed rocprofv3 counter
     summary, or None when the workload differs or the kernel source has
@@ -812,6 +838,7 @@ def main():
               "serving": lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds),
               "serving32": lambda: bench_serving(torch, lv, synth, dev, args.serve_seconds, budget_bytes=32e9),
               "capacity": lambda: bench_serving_capacity(torch, lv, synth, dev),
+              "serving_kernels": lambda: bench_serving_kernels(torch, lv, synth, dev),
               "sums": lambda: bench_sums(torch, lv, synth, dev),
               "general": lambda: bench_general(torch, lv, synth, dev),
               "models": lambda: bench_models(torch, lv, synth, dev),
