@@ -37,6 +37,31 @@ template <typename T> __device__ __forceinline__ T lane_bcast(T x, int l) {
   }
 }
 
+// Staging of a work-group's operand tile: thread tid moves entries
+// e = 0 .. COUNT-1 (entry e is the group-wide index tid + NT e; entries at
+// or beyond N are skipped).  The loads of a batch of up to 16 entries are all
+// issued before any of them is stored, so the staging costs a few memory
+// latencies rather than one per entry.  ld(idx) returns the value of entry
+// idx, st(idx, v) stores it.
+template <int COUNT, int NT, typename V, typename Ld, typename St>
+__device__ __forceinline__ void batched_stage(const int tid, const int N, Ld&& ld, St&& st) {
+  constexpr int B = COUNT < 16 ? COUNT : 16;
+#pragma unroll
+  for (int e0 = 0; e0 < COUNT; e0 += B) {
+    V v[B];
+#pragma unroll
+    for (int e = 0; e < B; ++e) {
+      const int idx = tid + NT * (e0 + e);
+      if (e0 + e < COUNT) v[e] = idx < N ? ld(idx) : V(0);
+    }
+#pragma unroll
+    for (int e = 0; e < B; ++e) {
+      const int idx = tid + NT * (e0 + e);
+      if (e0 + e < COUNT && idx < N) st(idx, v[e]);
+    }
+  }
+}
+
 __device__ __forceinline__ int wave_id() {
   return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }

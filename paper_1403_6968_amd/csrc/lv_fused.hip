@@ -139,22 +139,24 @@ __device__ __forceinline__ void fused_body(T* __restrict__ P, const int64_t ldp,
 
   // X operand rows of the tile's columns, slice-padded: (col, c) -> col*XR + (col/QW)*UPAD + c;
   // for MFX transposed, (col, c) -> c*UTW + col, columns XR..15 zero.
+  auto xop = [&](const int col, const int c) -> T {   // X operand (col, c), zero beyond XR
+    const int64_t g = (int64_t)(col0 + col) * W;
+    return c < R ? Uj[g + c]
+         : c < R + XE ? Ux[g + c - R]
+         : c < XR ? Ud[(int64_t)(col0 + col) * Wd + c - R - XE] : T(0);
+  };
   if constexpr (MFX) {
     for (int idx = tid; idx < TC; idx += 256) zrow[idx] = 0.f;
-    for (int idx = tid; idx < TC * 16; idx += 256) {
-      const int col = idx / 16, c = idx % 16;
-      const int64_t g = (int64_t)(col0 + col) * W;
-      utile[c * UTW + col] = c < R ? Uj[g + c]
-                           : c < R + XE ? Ux[g + c - R]
-                           : c < XR ? Ud[(int64_t)(col0 + col) * Wd + c - R - XE] : T(0);
-    }
+    batched_stage<(TC * 16 + 255) / 256, 256, T>(
+        tid, TC * 16, [&](int idx) { return xop(idx / 16, idx % 16); },
+        [&](int idx, T v) { utile[(idx % 16) * UTW + idx / 16] = v; });
   } else if constexpr (!SP) {
-    for (int idx = tid; idx < TC * XR; idx += 256) {
-      const int col = idx / XR, c = idx % XR;
-      const int64_t g = (int64_t)(col0 + col) * W;
-      utile[col * XR + (col / QW) * UPAD + c] =
-          c < R ? Uj[g + c] : c < R + XE ? Ux[g + c - R] : Ud[(int64_t)(col0 + col) * Wd + c - R - XE];
-    }
+    batched_stage<(TC * XR + 255) / 256, 256, T>(
+        tid, TC * XR, [&](int idx) { return xop(idx / XR, idx % XR); },
+        [&](int idx, T v) {
+          const int col = idx / XR;
+          utile[col * XR + (col / QW) * UPAD + idx % XR] = v;
+        });
   }
   T vcol[EPL][UPD ? R : 1];
   if constexpr (UPD) {

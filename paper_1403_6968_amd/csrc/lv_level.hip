@@ -48,11 +48,12 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ Uj, const T* __r
   for (int e = 0; e < PPT; ++e) g[e] = 0.0;
   for (int i0 = row0; i0 < row0 + nrows; i0 += RS) {
     __syncthreads();
-    for (int idx = tid; idx < RS * R; idx += 256) {
-      const int rr = idx / R, c = idx % R;
-      su[rr][c] = Uj[(int64_t)(i0 + rr) * W + c];
-      sv[rr][c] = Vj[(int64_t)(i0 + rr) * W + c];
-    }
+    batched_stage<(RS * R + 255) / 256, 256, T>(
+        tid, RS * R, [&](int idx) { return Uj[(int64_t)(i0 + idx / R) * W + idx % R]; },
+        [&](int idx, T v) { su[idx / R][idx % R] = v; });
+    batched_stage<(RS * R + 255) / 256, 256, T>(
+        tid, RS * R, [&](int idx) { return Vj[(int64_t)(i0 + idx / R) * W + idx % R]; },
+        [&](int idx, T v) { sv[idx / R][idx % R] = v; });
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < PPT; ++e) {
@@ -201,11 +202,28 @@ __device__ __forceinline__ void tail_body(const T* __restrict__ partX, const T* 
     const int rb = blk / NS, cs = blk % NS;
     const int cl = tid % CW, rl = tid / CW;
     const int c = cs * CW + cl;
-    for (int e = tid; e < R * CW; e += 256) {
-      const int d = e / CW, cc = cs * CW + e % CW;
-      double g = 0.0;
-      for (int t = 0; t < ng; ++t) g += partG[(int64_t)t * R * R + d * R + cc];
-      G[d][e % CW] = g;
+    {
+      // the G slice: each entry sums its ng partials in order; the loads of
+      // all of a thread's entries for one partial are issued together
+      constexpr int GE = (R * CW + 255) / 256;
+      double g[GE];
+#pragma unroll
+      for (int e = 0; e < GE; ++e) g[e] = 0.0;
+      for (int t = 0; t < ng; ++t) {
+        double v[GE];
+#pragma unroll
+        for (int e = 0; e < GE; ++e) {
+          const int idx = tid + 256 * e;
+          v[e] = idx < R * CW ? partG[(int64_t)t * R * R + (idx / CW) * R + cs * CW + idx % CW] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < GE; ++e) g[e] += v[e];
+      }
+#pragma unroll
+      for (int e = 0; e < GE; ++e) {
+        const int idx = tid + 256 * e;
+        if (idx < R * CW) G[idx / CW][idx % CW] = g[e];
+      }
     }
     __syncthreads();
     int64_t idx[Q];

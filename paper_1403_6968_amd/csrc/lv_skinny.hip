@@ -18,7 +18,7 @@
 //                  B: lane l holds B[8 h + e][l % 32]
 //   f32 32x32x2    A: lane l holds A[l % 32][h];  B: B[h][l % 32]
 //   both           C: element v of lane l is C[8 (v / 4) + 4 h + v % 4][l % 32]
-#include "lv_internal.h"
+#include "lv_device.h"
 
 #include <type_traits>
 
@@ -105,10 +105,9 @@ __device__ __forceinline__ void skinny_body(const uint16_t* __restrict__ S, cons
   }
 
   // U_j rows of the tile's columns, transposed: sUt[c][k] = U_j[col0 + k][c]
-  for (int idx = tid; idx < RP * TCB; idx += 256) {
-    const int k = idx / RP, c = idx % RP;
-    sUt[c][k] = c < R ? bf16_rne(Uj[(int64_t)(col0 + k) * W + c]) : (uint16_t)0;
-  }
+  batched_stage<RP * TCB / 256, 256, float>(
+      tid, RP * TCB, [&](int idx) { const int c = idx % RP; return c < R ? Uj[(int64_t)(col0 + idx / RP) * W + c] : 0.f; },
+      [&](int idx, float v) { sUt[idx % RP][idx / RP] = bf16_rne(v); });
 
   v16f yacc[NB][2];
 #pragma unroll
@@ -332,15 +331,13 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
   else if constexpr (UPD) fetch_u(row0);
 
   if (wx)
-    for (int idx = tid; idx < RP * TCB; idx += NT) {
-      const int k = idx / RP, c = idx % RP;
-      sUt[c][k] = c < R ? Uj[(int64_t)(col0 + k) * W + c] : 0.f;
-    }
+    batched_stage<RP * TCB / NT, NT, float>(
+        tid, RP * TCB, [&](int idx) { const int c = idx % RP; return c < R ? Uj[(int64_t)(col0 + idx / RP) * W + c] : 0.f; },
+        [&](int idx, float v) { sUt[idx % RP][idx / RP] = v; });
   if constexpr (UPD)
-    for (int idx = tid; idx < RP * TCB; idx += NT) {
-      const int k = idx / RP, c = idx % RP;
-      sVc[c][k] = c < R ? Vj[(int64_t)(col0 + k) * W + c] : 0.f;
-    }
+    batched_stage<RP * TCB / NT, NT, float>(
+        tid, RP * TCB, [&](int idx) { const int c = idx % RP; return c < R ? Vj[(int64_t)(col0 + idx / RP) * W + c] : 0.f; },
+        [&](int idx, float v) { sVc[idx % RP][idx / RP] = v; });
 
   v16f yacc[NB][2];
 #pragma unroll
@@ -549,15 +546,13 @@ __device__ __forceinline__ void skinny16_f32_body(const float* __restrict__ P, c
   else if constexpr (UPD) fetch_u(row0);
 
   if (wx)
-    for (int idx = tid; idx < RP * TCB; idx += NT) {
-      const int k = idx / RP, c = idx % RP;
-      sUt[c][k] = c < R ? Uj[(int64_t)(col0 + k) * W + c] : 0.f;
-    }
+    batched_stage<RP * TCB / NT, NT, float>(
+        tid, RP * TCB, [&](int idx) { const int c = idx % RP; return c < R ? Uj[(int64_t)(col0 + idx / RP) * W + c] : 0.f; },
+        [&](int idx, float v) { sUt[idx % RP][idx / RP] = v; });
   if constexpr (UPD)
-    for (int idx = tid; idx < RP * TCB; idx += NT) {
-      const int k = idx / RP, c = idx % RP;
-      sVc[c][k] = c < R ? Vj[(int64_t)(col0 + k) * W + c] : 0.f;
-    }
+    batched_stage<RP * TCB / NT, NT, float>(
+        tid, RP * TCB, [&](int idx) { const int c = idx % RP; return c < R ? Vj[(int64_t)(col0 + idx / RP) * W + c] : 0.f; },
+        [&](int idx, float v) { sVc[idx % RP][idx / RP] = v; });
 
   v4f yacc[4];
 #pragma unroll
@@ -723,10 +718,10 @@ __global__ void __launch_bounds__(64 * kXWaves) k_xprod_f32(const SkinnyDesc d) 
       b[g][1] = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(src + 32 * g + 16));
     });
   };
-  for (int idx = tid; idx < TCB * RP; idx += 64 * kXWaves) {
-    const int k = idx / RP, c = idx % RP;
-    sU[k][c] = c < d.R ? d.Uj[(int64_t)(col0 + k) * d.W + c] : 0.f;
-  }
+  batched_stage<TCB * RP / (64 * kXWaves), 64 * kXWaves, float>(
+      tid, TCB * RP,
+      [&](int idx) { const int c = idx % RP; return c < d.R ? d.Uj[(int64_t)(col0 + idx / RP) * d.W + c] : 0.f; },
+      [&](int idx, float v) { sU[idx / RP][idx % RP] = v; });
   __syncthreads();
 
   typedef float v4f __attribute__((ext_vector_type(4)));
