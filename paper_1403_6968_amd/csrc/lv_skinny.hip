@@ -47,9 +47,10 @@ __device__ __forceinline__ bf16x8 lds8(const uint16_t* p) {
   return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(p));
 }
 
-// Tile: tile_rows x 256 columns of S, walked in chunks of 64 rows through
-// LDS; the next chunk or two of S and of V_j are held in registers while
-// the current one is used.
+// Tile: about tile_rows x 256 columns of S (the slices of a column tile
+// interleave by 64-row chunks), walked in chunks through LDS; the next
+// chunk or two of S and of V_j are held in registers while the current one
+// is used.
 // Factor columns are padded with zeros to 32 NB.
 //   X: per chunk, the 2 NB (row half, factor block) 32 x 32 outputs are
 //      shared round-robin by the 4 waves, K = the tile's 256 columns; one
@@ -73,8 +74,12 @@ __device__ __forceinline__ void skinny_body(const uint16_t* __restrict__ S, cons
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int col0 = ct * TCB;
-  const int row0 = rt * tile_rows;
-  const int rend = min(row0 + tile_rows, n_pad);
+  // interleaved chunks: slice rt of ns takes chunks rt, rt + ns, ... (CS
+  // rows apart), so the grid streams one band of rows at a time
+  const int ns = (n_pad + tile_rows - 1) / tile_rows;
+  const int CS = ns * CRB;
+  const int row0 = rt * CRB;
+  const int rend = n_pad;
   const int l32 = lane % 32, lh = lane / 32;
   // chunk staging: thread -> rows tid / 32 + 8 i, 16-byte column group tid % 32
   const int srow = tid / 32, sgrp = tid % 32;
@@ -101,7 +106,7 @@ __device__ __forceinline__ void skinny_body(const uint16_t* __restrict__ S, cons
   };
   fetch(preA, pvA, row0);
   if constexpr (DEPTH == 2) {
-    if (row0 + CRB < rend) fetch(preB, pvB, row0 + CRB);
+    if (row0 + CS < rend) fetch(preB, pvB, row0 + CS);
   }
 
   // U_j rows of the tile's columns, transposed: sUt[c][k] = U_j[col0 + k][c]
@@ -127,7 +132,7 @@ __device__ __forceinline__ void skinny_body(const uint16_t* __restrict__ S, cons
       sVt[idx % RP][idx / RP] = bf16_rne(pv[i]);
     }
     __syncthreads();
-    if (cr0 + DEPTH * CRB < rend) fetch(pre, pv, cr0 + DEPTH * CRB);
+    if (cr0 + DEPTH * CS < rend) fetch(pre, pv, cr0 + DEPTH * CS);
 
     // X rows of the chunk
     for (int t = wave; t < 2 * NB; t += 4) {
@@ -168,12 +173,12 @@ __device__ __forceinline__ void skinny_body(const uint16_t* __restrict__ S, cons
   };
 
   if constexpr (DEPTH == 2) {
-    for (int cr0 = row0; cr0 < rend; cr0 += 2 * CRB) {
+    for (int cr0 = row0; cr0 < rend; cr0 += 2 * CS) {
       chunk(preA, pvA, cr0);
-      if (cr0 + CRB < rend) chunk(preB, pvB, cr0 + CRB);
+      if (cr0 + CS < rend) chunk(preB, pvB, cr0 + CS);
     }
   } else {
-    for (int cr0 = row0; cr0 < rend; cr0 += CRB) chunk(preA, pvA, cr0);
+    for (int cr0 = row0; cr0 < rend; cr0 += CS) chunk(preA, pvA, cr0);
   }
 
 #pragma unroll
