@@ -584,15 +584,23 @@ __device__ __forceinline__ void update_split_body(float* __restrict__ P, const i
   const int l32 = lane & 31, lh = lane >> 5;
   const int row0 = rt * TT, col0 = ct * TT;
 
+  // The old values: requested before the products (their loads overlap the
+  // products); without the shadow from R = 128 after them, so that the
+  // products run without the 64 registers they occupy (two waves per SIMD
+  // instead of one then hide the latency)
+  constexpr bool LATE_P = R >= 128 && !SH;
   float p[2][2][16];
+  auto load_p = [&]() {
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int v = 0; v < 16; ++v)
-        p[a][b][v] = __builtin_nontemporal_load(&P[(int64_t)(row0 + wm * 64 + a * 32 + 8 * (v / 4) + 4 * lh +
-                                                         (v % 4)) * ldp + col0 + wn * 64 + b * 32 + l32]);
+        for (int v = 0; v < 16; ++v)
+          p[a][b][v] = __builtin_nontemporal_load(&P[(int64_t)(row0 + wm * 64 + a * 32 + 8 * (v / 4) + 4 * lh +
+                                                           (v % 4)) * ldp + col0 + wn * 64 + b * 32 + l32]);
+  };
+  if constexpr (!LATE_P) load_p();
   v16f acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -644,6 +652,7 @@ __device__ __forceinline__ void update_split_body(float* __restrict__ P, const i
     }
   }
 
+  if constexpr (LATE_P) load_p();
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
