@@ -585,10 +585,10 @@ __device__ __forceinline__ void update_split_body(float* __restrict__ P, const i
   const int row0 = rt * TT, col0 = ct * TT;
 
   // The old values: requested before the products (their loads overlap the
-  // products); without the shadow from R = 128 after them, so that the
-  // products run without the 64 registers they occupy (two waves per SIMD
-  // instead of one then hide the latency)
-  constexpr bool LATE_P = R >= 128 && !SH;
+  // products); from R = 128 after them, so that the products run without
+  // the 64 registers they occupy (two waves per SIMD instead of one then
+  // hide the latency; see update_min_waves)
+  constexpr bool LATE_P = R >= 128;
   float p[2][2][16];
   auto load_p = [&]() {
 #pragma unroll
@@ -680,10 +680,11 @@ __device__ __forceinline__ void update_any(const UpdateDesc<T>& d, const int ct,
 }
 
 // Float matrix-core ranks: at least two waves per SIMD (the 128 x 128
-// tile's old values stay in registers while its delta is formed).  Not for
-// the split-bfloat16 products, which would spill at large ranks.
+// tile's old values stay in registers while its delta is formed).  The
+// split-bfloat16 products from R = 128 too, where the old values are loaded
+// after the products; below, their unrolled chunks fit without a bound.
 template <typename T, int R, bool SPLIT> constexpr int update_min_waves() {
-  return sizeof(T) == 4 && R >= kMfmaUpdateRank && !SPLIT ? 2 : 1;
+  return sizeof(T) == 4 && R >= kMfmaUpdateRank && (!SPLIT || R >= 128) ? 2 : 1;
 }
 
 template <typename T, int R, bool SH, bool SPLIT>
