@@ -164,3 +164,34 @@ def test_autotune_leaves_view_unchanged(pipelined):
         assert O.maxrel(host(pa), ref[p]) < 1e-4
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("mode_name,n,k,r", [("fp64", 700, 16, 1), ("bf16", 900, 8, 2), ("fp32", 600, 2, 1)])
+def test_autotune_other_modes_and_short_chains(mode_name, n, k, r):
+    """The autotuner leaves FP64 and bfloat16-shadow views unchanged bit for
+    bit (shadows included: later updates still equal the sequential order),
+    and a view with one level (k = 2, no pipeline) takes it as well."""
+    torch, lv, mode, dt, A, Us, Vs = _setup(mode_name, n, k, r, 8, seed=16)
+    Ad, Ud, Vd = dev(A, dt), dev(Us, dt), dev(Vs, dt)
+    a = lv.View(Ad, k, r_max=r, mode=mode)
+    a.update_batch(Ud[:3], Vd[:3])
+    torch.cuda.synchronize()
+    before = {p: a.read(p) for p in a.powers()}
+    rows = a.autotune(pipelined=True, trial_updates=3)
+    assert rows in range(256, 1025, 128)
+    assert a.stats()["updates"] == 3
+    for p in a.powers():
+        assert torch.equal(a.read(p), before[p]), p
+    b = lv.View(Ad, k, r_max=r, mode=mode)
+    b.set_pipeline(False)
+    b.update_batch(Ud[:3], Vd[:3])
+    b.set_tile_rows([rows] * (len(b.powers()) - 1))
+    a.update_batch(Ud[3:], Vd[3:])
+    b.update_batch(Ud[3:], Vd[3:])
+    ref = _oracle(A, Us, Vs, k)
+    for p in a.powers():
+        pa = a.read(p)
+        assert torch.equal(pa, b.read(p)), p
+        assert O.maxrel(host(pa), ref[p]) < TOL[mode_name], p
+    a.close()
+    b.close()
