@@ -420,7 +420,7 @@ __global__ void __launch_bounds__(256) k_sums_fused(const FusedDesc<T> d) {
 template <typename T, int R, int RB, bool UPD>
 __global__ void __launch_bounds__(256) k_level_fused_multi(const FusedDesc<T>* __restrict__ ds, int nd) {
   const int v = find_desc(ds, nd, (int)blockIdx.x);
-  const FusedDesc<T> d = ds[v];
+  const FusedDesc<T> d = load_desc(ds, v);
   const int local = (int)blockIdx.x - d.block_begin;
   fused_body<T, R, RB, UPD>(d.P, d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.partX, d.partY, d.partG, d.pR,
                             local % d.nct, local / d.nct);

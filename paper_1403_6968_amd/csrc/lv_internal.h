@@ -102,6 +102,24 @@ template <typename T> struct PrepDesc {
   T* slabU; T* slabV; int W; int64_t n_pad; int block_begin;   // blocks: ceil(n_pad * r_pad / 256)
 };
 
+// Descriptor v of a multi-view launch, read through the constant address
+// space.  The table is written by the host before the launch and only read
+// by it, and the compiler takes pointers loaded from constant memory to
+// address global memory: accesses through the descriptor's pointers are then
+// global instructions.  Read as ordinary (generic) memory, the pointers would
+// be generic too, and their flat accesses count against the LDS wait counter
+// as well, so that every wait for an LDS read would also wait for the HBM
+// loads in flight.
+// (The host pass of the compiler, which only declares the kernels, has no
+// address space 4.)
+template <typename D> __device__ __forceinline__ D load_desc(const D* ds, int v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return *((const __attribute__((address_space(4))) D*)ds + v);
+#else
+  return ds[v];
+#endif
+}
+
 // Tiling of the update pass.  The vector kernel covers tiles of 256 rows x
 // (64 lanes x 16 bytes); float storage with rank R >= kMfmaUpdateRank uses
 // the matrix-core kernel on 128 x 128 tiles.

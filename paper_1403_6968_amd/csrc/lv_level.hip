@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(256) k_gram(const GramDesc<T> d) {
 template <typename T, int R>
 __global__ void __launch_bounds__(256) k_gram_multi(const GramDesc<T>* __restrict__ ds, int nd) {
   const int v = find_desc(ds, nd, (int)blockIdx.x);
-  const GramDesc<T> d = ds[v];
+  const GramDesc<T> d = load_desc(ds, v);
   const int local = (int)blockIdx.x - d.block_begin;
   gram_body<T, R>(d.Uj, d.Vj, d.W, d.n_pad, d.tile_rows, d.partG, local % d.nrt, local / d.nrt);
 }
@@ -106,7 +106,7 @@ __device__ __forceinline__ void gram_sum_body(double* __restrict__ G, const int 
 __global__ void __launch_bounds__(256) k_gram_sum(const GramSumDesc d) { gram_sum_body(d.G, d.ng, d.count, blockIdx.x); }
 
 __global__ void __launch_bounds__(256) k_gram_sum_multi(const GramSumDesc* __restrict__ ds, int nd) {
-  const GramSumDesc d = ds[find_desc(ds, nd, (int)blockIdx.x)];
+  const GramSumDesc d = load_desc(ds, find_desc(ds, nd, (int)blockIdx.x));
   gram_sum_body(d.G, d.ng, d.count, (int)blockIdx.x - d.block_begin);
 }
 
@@ -270,7 +270,7 @@ __global__ void __launch_bounds__(256) k_level_tail(const TailDesc<T> d) {
 template <typename T, int R>
 __global__ void __launch_bounds__(256) k_level_tail_multi(const TailDesc<T>* __restrict__ ds, int nd) {
   const int v = find_desc(ds, nd, (int)blockIdx.x);
-  const TailDesc<T> d = ds[v];
+  const TailDesc<T> d = load_desc(ds, v);
   tail_body<T, R>(d.partX, d.partY, d.partG, d.nct, d.nrt, d.ng, d.n_pad, d.slabU, d.slabV, d.W,
                   (int)blockIdx.x - d.block_begin);
 }
@@ -696,7 +696,7 @@ template <typename T, int R, bool SH, bool SPLIT>
 __global__ void __launch_bounds__(256, (update_min_waves<T, R, SPLIT>()))
 k_level_update_multi(const UpdateDesc<T>* __restrict__ ds, int nd) {
   const int v = find_desc(ds, nd, (int)blockIdx.x);
-  const UpdateDesc<T> d = ds[v];
+  const UpdateDesc<T> d = load_desc(ds, v);
   const int local = (int)blockIdx.x - d.block_begin;
   update_any<T, R, SH, SPLIT>(d, local % d.nct, local / d.nct);
 }
@@ -736,7 +736,7 @@ __global__ void __launch_bounds__(256) k_prep(const PrepDesc<T> d) {
 template <typename T>
 __global__ void __launch_bounds__(256) k_prep_multi(const PrepDesc<T>* __restrict__ ds, int nd) {
   const int v = find_desc(ds, nd, (int)blockIdx.x);
-  const PrepDesc<T> d = ds[v];
+  const PrepDesc<T> d = load_desc(ds, v);
   prep_body<T>(d.U, d.ldu, d.V, d.ldv, d.n, d.r, d.r_pad, d.slabU, d.slabV, d.W, d.n_pad,
                (int)blockIdx.x - d.block_begin);
 }

@@ -47,6 +47,21 @@ __device__ __forceinline__ bf16x8 lds8(const uint16_t* p) {
   return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(p));
 }
 
+// Factor entries past column R are the zero padding of the factor blocks.
+// Their loads still take place, at column min(c, R - 1), which the row holds:
+// a load under a condition becomes a branch of its own, after which the
+// compiler waits for it alone, so a run of guarded loads would be served one
+// round trip at a time.  fac_clamped is the raw load (prefetches zero the
+// padding when they are staged, so that no wait follows the load), and
+// fac_or_zero the padded entry.
+__device__ __forceinline__ float fac_clamped(const float* __restrict__ row, const int c, const int R) {
+  return row[c < R ? c : R - 1];
+}
+__device__ __forceinline__ float fac_or_zero(const float* __restrict__ row, const int c, const int R) {
+  const float v = fac_clamped(row, c, R);
+  return c < R ? v : 0.f;
+}
+
 // Tile: about tile_rows x 256 columns of S (the slices of a column tile
 // interleave by 64-row chunks), walked in chunks through LDS; the next
 // chunk or two of S and of V_j are held in registers while the current one
@@ -101,7 +116,7 @@ __device__ __forceinline__ void skinny_body(const uint16_t* __restrict__ S, cons
     for (int i = 0; i < VPT; ++i) {
       const int idx = tid + 256 * i;
       const int rr = idx / RP, c = idx % RP;
-      pv[i] = c < R ? Vj[(int64_t)(r0 + rr) * W + c] : 0.f;
+      pv[i] = fac_clamped(Vj + (int64_t)(r0 + rr) * W, c, R);
     }
   };
   fetch(preA, pvA, row0);
@@ -111,7 +126,7 @@ __device__ __forceinline__ void skinny_body(const uint16_t* __restrict__ S, cons
 
   // U_j rows of the tile's columns, transposed: sUt[c][k] = U_j[col0 + k][c]
   batched_stage<RP * TCB / 256, 256, float>(
-      tid, RP * TCB, [&](int idx) { const int c = idx % RP; return c < R ? Uj[(int64_t)(col0 + idx / RP) * W + c] : 0.f; },
+      tid, RP * TCB, [&](int idx) { const int c = idx % RP; return fac_or_zero(Uj + (int64_t)(col0 + idx / RP) * W, c, R); },
       [&](int idx, float v) { sUt[idx % RP][idx / RP] = bf16_rne(v); });
 
   v16f yacc[NB][2];
@@ -129,7 +144,7 @@ __device__ __forceinline__ void skinny_body(const uint16_t* __restrict__ S, cons
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
       const int idx = tid + 256 * i;
-      sVt[idx % RP][idx / RP] = bf16_rne(pv[i]);
+      sVt[idx % RP][idx / RP] = bf16_rne(idx % RP < R ? pv[i] : 0.f);
     }
     __syncthreads();
     if (cr0 + DEPTH * CS < rend) fetch(pre, pv, cr0 + DEPTH * CS);
@@ -215,7 +230,7 @@ __device__ __forceinline__ int find_skinny(const SkinnyDesc* __restrict__ ds, in
 
 template <int NB>
 __global__ void __launch_bounds__(256, 2) k_skinny_bf16_multi(const SkinnyDesc* __restrict__ ds, int nd) {
-  const SkinnyDesc d = ds[find_skinny(ds, nd, (int)blockIdx.x)];
+  const SkinnyDesc d = load_desc(ds, find_skinny(ds, nd, (int)blockIdx.x));
   const int local = (int)blockIdx.x - d.block_begin;
   skinny_body<NB>(static_cast<const uint16_t*>(d.src), d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.R, d.partX, d.partY, d.pR,
                   local % d.nct, local / d.nct);
@@ -320,7 +335,7 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
     static_for<0, VPT>([&](auto i) {
       const int idx = tid + 256 * i;
       const int rr = idx / RP, c = idx % RP;
-      pv[i] = c < R ? Vj[(int64_t)(r0 + rr) * W + c] : 0.f;
+      pv[i] = fac_clamped(Vj + (int64_t)(r0 + rr) * W, c, R);
     });
   };
   // update waves: the chunk's U_j rows (thread t = tid - 256 holds entries t + 256 i)
@@ -329,7 +344,7 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
     static_for<0, VPT>([&](auto i) {
       const int idx = tid - 256 + 256 * i;
       const int rr = idx / RP, c = idx % RP;
-      pu[i] = c < R ? Uj[(int64_t)(r0 + rr) * W + c] : 0.f;
+      pu[i] = fac_clamped(Uj + (int64_t)(r0 + rr) * W, c, R);
     });
   };
   if (mwave) fetch(row0);
@@ -337,11 +352,11 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
 
   if (wx)
     batched_stage<RP * TCB / NT, NT, float>(
-        tid, RP * TCB, [&](int idx) { const int c = idx % RP; return c < R ? Uj[(int64_t)(col0 + idx / RP) * W + c] : 0.f; },
+        tid, RP * TCB, [&](int idx) { const int c = idx % RP; return fac_or_zero(Uj + (int64_t)(col0 + idx / RP) * W, c, R); },
         [&](int idx, float v) { sUt[idx % RP][idx / RP] = v; });
   if constexpr (UPD)
     batched_stage<RP * TCB / NT, NT, float>(
-        tid, RP * TCB, [&](int idx) { const int c = idx % RP; return c < R ? Vj[(int64_t)(col0 + idx / RP) * W + c] : 0.f; },
+        tid, RP * TCB, [&](int idx) { const int c = idx % RP; return fac_or_zero(Vj + (int64_t)(col0 + idx / RP) * W, c, R); },
         [&](int idx, float v) { sVc[idx % RP][idx / RP] = v; });
 
   v16f yacc[NB][2];
@@ -358,12 +373,12 @@ __device__ __forceinline__ void skinny_f32_body(const float* __restrict__ P, con
       static_for<0, CR / 4>([&](auto i) { *reinterpret_cast<f32x4*>(&sP[srow + 4 * i][sgrp * 4]) = pre[i]; });
       static_for<0, VPT>([&](auto i) {
         const int idx = tid + 256 * i;
-        sVt[idx % RP][idx / RP] = pv[i];
+        sVt[idx % RP][idx / RP] = idx % RP < R ? pv[i] : 0.f;
       });
     } else if constexpr (UPD) {
       static_for<0, VPT>([&](auto i) {
         const int idx = tid - 256 + 256 * i;
-        sUr[idx / RP][idx % RP] = pu[i];
+        sUr[idx / RP][idx % RP] = idx % RP < R ? pu[i] : 0.f;
       });
     }
     __syncthreads();
@@ -535,7 +550,7 @@ __device__ __forceinline__ void skinny16_f32_body(const float* __restrict__ P, c
     static_for<0, VPT>([&](auto i) {
       const int idx = tid + 256 * i;
       const int rr = idx / RP, c = idx % RP;
-      pv[i] = c < R ? Vj[(int64_t)(r0 + rr) * W + c] : 0.f;
+      pv[i] = fac_clamped(Vj + (int64_t)(r0 + rr) * W, c, R);
     });
   };
   // update waves: the chunk's U_j rows (thread t = tid - 256 holds entries t + 256 i)
@@ -544,7 +559,7 @@ __device__ __forceinline__ void skinny16_f32_body(const float* __restrict__ P, c
     static_for<0, VPT>([&](auto i) {
       const int idx = tid - 256 + 256 * i;
       const int rr = idx / RP, c = idx % RP;
-      pu[i] = c < R ? Uj[(int64_t)(r0 + rr) * W + c] : 0.f;
+      pu[i] = fac_clamped(Uj + (int64_t)(r0 + rr) * W, c, R);
     });
   };
   if (mwave) fetch(row0);
@@ -552,11 +567,11 @@ __device__ __forceinline__ void skinny16_f32_body(const float* __restrict__ P, c
 
   if (wx)
     batched_stage<RP * TCB / NT, NT, float>(
-        tid, RP * TCB, [&](int idx) { const int c = idx % RP; return c < R ? Uj[(int64_t)(col0 + idx / RP) * W + c] : 0.f; },
+        tid, RP * TCB, [&](int idx) { const int c = idx % RP; return fac_or_zero(Uj + (int64_t)(col0 + idx / RP) * W, c, R); },
         [&](int idx, float v) { sUt[idx % RP][idx / RP] = v; });
   if constexpr (UPD)
     batched_stage<RP * TCB / NT, NT, float>(
-        tid, RP * TCB, [&](int idx) { const int c = idx % RP; return c < R ? Vj[(int64_t)(col0 + idx / RP) * W + c] : 0.f; },
+        tid, RP * TCB, [&](int idx) { const int c = idx % RP; return fac_or_zero(Vj + (int64_t)(col0 + idx / RP) * W, c, R); },
         [&](int idx, float v) { sVc[idx % RP][idx / RP] = v; });
 
   v4f yacc[4];
@@ -569,12 +584,12 @@ __device__ __forceinline__ void skinny16_f32_body(const float* __restrict__ P, c
       static_for<0, CR / 4>([&](auto i) { *reinterpret_cast<f32x4*>(&sP[srow + 4 * i][sgrp * 4]) = pre[i]; });
       static_for<0, VPT>([&](auto i) {
         const int idx = tid + 256 * i;
-        sVt[idx % RP][idx / RP] = pv[i];
+        sVt[idx % RP][idx / RP] = idx % RP < R ? pv[i] : 0.f;
       });
     } else if constexpr (UPD) {
       static_for<0, VPT>([&](auto i) {
         const int idx = tid - 256 + 256 * i;
-        sUr[idx / RP][idx % RP] = pu[i];
+        sUr[idx / RP][idx % RP] = idx % RP < R ? pu[i] : 0.f;
       });
     }
     __syncthreads();
@@ -664,7 +679,7 @@ __global__ void __launch_bounds__(UPD ? 512 : 256) k_skinny16_f32(const SkinnyDe
 
 template <bool UPD>
 __global__ void __launch_bounds__(UPD ? 512 : 256) k_skinny16_f32_multi(const SkinnyDesc* __restrict__ ds, int nd) {
-  const SkinnyDesc d = ds[find_skinny(ds, nd, (int)blockIdx.x)];
+  const SkinnyDesc d = load_desc(ds, find_skinny(ds, nd, (int)blockIdx.x));
   const int local = (int)blockIdx.x - d.block_begin;
   skinny16_f32_body<UPD>(static_cast<const float*>(d.src), d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.R,
                          d.partX, d.partY, d.pR, d.want, local % d.nct, local / d.nct);
@@ -678,7 +693,7 @@ __global__ void __launch_bounds__(UPD ? 512 : 256) k_skinny_f32(const SkinnyDesc
 
 template <int NB, bool UPD>
 __global__ void __launch_bounds__(UPD ? 512 : 256) k_skinny_f32_multi(const SkinnyDesc* __restrict__ ds, int nd) {
-  const SkinnyDesc d = ds[find_skinny(ds, nd, (int)blockIdx.x)];
+  const SkinnyDesc d = load_desc(ds, find_skinny(ds, nd, (int)blockIdx.x));
   const int local = (int)blockIdx.x - d.block_begin;
   skinny_f32_body<NB, UPD>(static_cast<const float*>(d.src), d.ldp, d.n_pad, d.tile_rows, d.Uj, d.Vj, d.W, d.R,
                            d.partX, d.partY, d.pR, d.want, local % d.nct, local / d.nct);
