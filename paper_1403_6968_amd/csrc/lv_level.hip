@@ -609,14 +609,27 @@ __device__ __forceinline__ void update_split_body(float* __restrict__ P, const i
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
 
+  // The factor values of the next column group are requested before the
+  // products of the current one (registers: 8 float4 per thread).
+  constexpr int SPT = TT * KC / 4 / 256;
+  float4 nu[SPT], nw[SPT];
+  auto fetch_uv = [&](const int kc) {
+#pragma unroll
+    for (int i = 0; i < SPT; ++i) {
+      const int q = tid + 256 * i;
+      const int r = q >> 3, c4 = (q & 7) * 4;
+      nu[i] = *reinterpret_cast<const float4*>(Uj + (int64_t)(row0 + r) * W + kc + c4);
+      nw[i] = *reinterpret_cast<const float4*>(Vj + (int64_t)(col0 + r) * W + kc + c4);
+    }
+  };
+  fetch_uv(0);
   for (int kc = 0; kc < R; kc += KC) {
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < TT * KC / 4 / 256; ++i) {
+    for (int i = 0; i < SPT; ++i) {
       const int q = tid + 256 * i;
       const int r = q >> 3, c4 = (q & 7) * 4;
-      const float4 u = *reinterpret_cast<const float4*>(Uj + (int64_t)(row0 + r) * W + kc + c4);
-      const float4 w = *reinterpret_cast<const float4*>(Vj + (int64_t)(col0 + r) * W + kc + c4);
+      const float4 u = nu[i], w = nw[i];
       const float uu[4] = {u.x, u.y, u.z, u.w}, ww[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
@@ -628,6 +641,7 @@ __device__ __forceinline__ void update_split_body(float* __restrict__ P, const i
       }
     }
     __syncthreads();
+    if (kc + KC < R) fetch_uv(kc + KC);
 #pragma unroll
     for (int ks = 0; ks < KC; ks += 16) {
       bf16x8 ah[2], al[2], bh[2], bl[2];
