@@ -49,7 +49,7 @@ def parse():
     p.add_argument("--quick", action="store_true", help="timed region only (for profilers)")
     p.add_argument("--no-secondary", action="store_true",
                    help="skip the rank-4, batched and serving workloads")
-    p.add_argument("--serve-seconds", type=float, default=2.0)
+    p.add_argument("--serve-seconds", type=float, default=4.0)
     p.add_argument("--only", choices=["rank4", "batched", "serving", "sums", "general", "models", "ols", "glin", "ceiling",
                                       "fp64", "small", "serving32", "capacity", "serving_kernels"],
                    help="run one secondary workload alone and print its result (for profilers)")
@@ -605,8 +605,8 @@ def bench_batched(torch, lv, synth, dev, rounds=30):
             "autotune": tuning}
 
 
-def bench_serving(torch, lv, synth, dev, seconds=2.0, rate=20000.0, r_coalesce=16, shadow=True,
-                  hold=(16, 0.03), drift_every=100, budget_bytes=None, evict=4):
+def bench_serving(torch, lv, synth, dev, seconds=4.0, rate=20000.0, r_coalesce=32, shadow=True,
+                  hold=(32, 0.2), drift_every=100, budget_bytes=None, evict=4):
     """32 views, n log-uniform in [2048, 16384], k = 16, FP32 (with bfloat16
     shadows by default); Poisson arrivals at `rate` requests/s over views with
     Zipf(1.1) popularity; per-view coalescing, continuous batching; rounds
@@ -696,11 +696,11 @@ def bench_serving(torch, lv, synth, dev, seconds=2.0, rate=20000.0, r_coalesce=1
                 "requests_waiting_for_admission": int(st["submitted"] - st["completed"])})}
 
 
-def bench_serving_capacity(torch, lv, synth, dev, rate=20000.0, r_cap=16, shadow=True, reps=6):
+def bench_serving_capacity(torch, lv, synth, dev, rate=20000.0, r_cap=32, shadow=True, reps=6):
     """A bound for the serving workload from measured update times: every
     one of its 32 views (same orders, k = 16, same mode) applies rank-r_cap
     updates alone on the device; even if every request were coalesced into
-    a full rank-r_cap update (the widest a k = 16 view takes: k r_max <= 256),
+    a full rank-r_cap update (the widest a k = 16 view takes: k r_max <= 512),
     serving `rate` requests/s needs sum_v (rate p_v / r_cap) T_v seconds of
     device time per second.  Above 1 the offered rate cannot be sustained by
     any coalescing within the cap; rate / need is the best the device can
@@ -746,18 +746,19 @@ def bench_serving_capacity(torch, lv, synth, dev, rate=20000.0, r_cap=16, shadow
             "update_ms_by_n": {str(n): t * 1e3 for n, t in sorted(times.items())}}
 
 
-def bench_serving_kernels(torch, lv, synth, dev, reps=2):
-    """The kernels of one rank-16 update of serving views, for a kernel
-    trace: the largest serving view (n = 15278) and a middle one (n = 7022)
-    with bfloat16 shadows, and the largest in plain FP32, each applying
-    rank-16 updates one at a time (as a serving round runs a view's levels)."""
+def bench_serving_kernels(torch, lv, synth, dev, reps=2, r=32):
+    """The kernels of one rank-r update of serving views (r = 32: the
+    serving workload's coalescing width), for a kernel trace: the largest
+    serving view (n = 15278) and a middle one (n = 7022) with bfloat16
+    shadows, and the largest in plain FP32, each applying rank-r updates one
+    at a time (as a serving round runs a view's levels)."""
     out = {}
     for n, mode, tag in ((15278, lv.LV_FP32_BF16SHADOW, "shadow"), (7022, lv.LV_FP32_BF16SHADOW, "shadow"),
                          (15278, lv.LV_FP32, "fp32")):
         A = torch.from_numpy(synth.gaussian_matrix(n, seed=0, config=5, view=1).astype(np.float32)).to(dev)
-        U, V = synth.update_factors(n, 16, reps + 2, seed=0, config=5, view=1)
+        U, V = synth.update_factors(n, r, reps + 2, seed=0, config=5, view=1)
         Ud, Vd = torch.from_numpy(U.astype(np.float32)).to(dev), torch.from_numpy(V.astype(np.float32)).to(dev)
-        view = lv.View(A, 16, r_max=16, mode=mode)
+        view = lv.View(A, 16, r_max=r, mode=mode)
         del A
         view.set_pipeline(False)
         view.update_batch(Ud[:2], Vd[:2])
@@ -768,7 +769,7 @@ def bench_serving_kernels(torch, lv, synth, dev, reps=2):
         b.record()
         torch.cuda.synchronize()
         view.close()
-        out[f"n{n}_{tag}"] = {"ms_per_rank16_update": a.elapsed_time(b) / reps}
+        out[f"n{n}_{tag}"] = {"rank": r, "ms_per_update": a.elapsed_time(b) / reps}
     return out
 
 

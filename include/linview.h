@@ -109,7 +109,12 @@ size_t lv_view_footprint(int64_t n, int k, int r_max, lv_mode mode);
  *  A         n x n, leading dimension lda >= n (device).
  *  k         power of two, 1 <= k <= 1024 (the paper assumes log2 k
  *            integral, Table 1 caption).
- *  r_max     largest rank of later updates, 1 <= r_max, k * r_max <= 4096.
+ *  r_max     largest rank of later updates, 1 <= r_max; k * r_max, with
+ *            r_max rounded up to a power of two, is the width of the top
+ *            factors (App. A: the level-j factors have 2^j r columns) and
+ *            must not exceed 512 for LV_FP32 and LV_FP32_BF16SHADOW views
+ *            created without flags (level ranks up to 256, a rank-512 update
+ *            of the top power), 256 otherwise (LV_FP64, LV_WITH_SUMS).
  *  workspace device buffer of ws_bytes >= lv_view_footprint(...), 256-byte
  *            aligned; borrowed until lv_view_destroy.
  *  out       receives the new handle (host).
@@ -434,7 +439,8 @@ typedef struct {
 } lv_server_counters;
 
 /* arena: device, 256-byte aligned, >= 4 MiB (descriptor ring) plus the
- * views; r_coalesce in [1, 64] is every view's r_max. */
+ * views; r_coalesce in [1, 64] is every view's r_max (so k * r_coalesce,
+ * rounded up, obeys the width rule of lv_view_create when views are added). */
 lv_status lv_server_create(void* arena, size_t arena_bytes, lv_mode mode, int r_coalesce,
                            void* stream, lv_server** out);
 /* Arena bytes one view of order n and power k takes (0 if invalid). */

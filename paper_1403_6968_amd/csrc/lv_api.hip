@@ -749,7 +749,7 @@ const char* lv_status_str(lv_status s) {
 const char* lv_last_error(void) { return g_err; }
 
 size_t lv_view_footprint_ex(int64_t n, int k, int r_max, lv_mode mode, int flags) {
-  if (check_shape(n, k, r_max, mode) != LV_OK || (flags & ~LV_WITH_SUMS) != 0) return 0;
+  if (check_shape(n, k, r_max, mode, flags == 0) != LV_OK || (flags & ~LV_WITH_SUMS) != 0) return 0;
   return make_layout(n, k, r_max, mode, flags).total;
 }
 
@@ -774,7 +774,7 @@ lv_status create_view(const void* A, int64_t n, int64_t lda, int k, int r_max, l
   g_err[0] = 0;
   if (!out) return fail(LV_EINVAL, "out is NULL");
   *out = nullptr;
-  lv_status st = check_shape(n, k, r_max, mode);
+  lv_status st = check_shape(n, k, r_max, mode, flags == 0 && p == 0);
   if (st != LV_OK) return st;
   if ((flags & ~LV_WITH_SUMS) != 0) return fail(LV_EINVAL, "unknown creation flags 0x%x", flags);
   if (!A || !workspace) return fail(LV_EINVAL, "A or workspace is NULL");
@@ -1227,7 +1227,7 @@ void lv_view_destroy(lv_view* v) {
 
 size_t lv_reeval_footprint(int64_t n, int r_max, lv_mode mode) {
   if (mode != LV_FP64 && mode != LV_FP32) return 0;
-  if (n < 1 || n > kMaxOrder || r_max < 0 || r_max > kMaxWidth) return 0;
+  if (n < 1 || n > kMaxOrder || r_max < 0 || r_max > kMaxLevelRank) return 0;
   return reeval_bytes(round_up(n, kPadOrder), (int)next_pow2(r_max < 1 ? 1 : r_max), mode == LV_FP64 ? 8 : 4);
 }
 
@@ -1238,7 +1238,7 @@ lv_status lv_reeval(const void* A, int64_t n, int64_t lda, int k, const void* U,
   if (mode != LV_FP64 && mode != LV_FP32) return fail(LV_EINVAL, "unknown mode %d", (int)mode);
   if (n < 1 || n > kMaxOrder) return fail(LV_EINVAL, "n out of range");
   if (!is_pow2(k) || k > kMaxK) return fail(LV_EINVAL, "k = %d is not a power of two in [1, %d]", k, kMaxK);
-  if (r < 0 || r > kMaxWidth) return fail(LV_EINVAL, "r out of range");
+  if (r < 0 || r > kMaxLevelRank) return fail(LV_EINVAL, "r out of range");
   if (!A || !out || !workspace) return fail(LV_EINVAL, "NULL pointer");
   if (r > 0 && (!U || !V || ldu < r || ldv < r)) return fail(LV_EINVAL, "bad U/V");
   if (lda < n || ldo < n) return fail(LV_EINVAL, "lda/ldo < n");
@@ -1304,7 +1304,7 @@ lv_status lv_powers_update_noalloc(void* const* powers, int64_t n, int64_t ld, i
   if (n < kPadOrder || n % kPadOrder != 0 || n > kMaxOrder)
     return fail(LV_EINVAL, "n = %lld is not a positive multiple of %d up to %lld", (long long)n, kPadOrder,
                 (long long)kMaxOrder);
-  if (r < 1 || r > kMaxWidth) return fail(LV_EINVAL, "rank r = %lld outside [1, %d]", (long long)r, kMaxWidth);
+  if (r < 1 || r > kMaxLevelRank) return fail(LV_EINVAL, "rank r = %lld outside [1, %d]", (long long)r, kMaxLevelRank);
   lv_status st = check_shape(n, k, (int)r, mode);
   if (st != LV_OK) return st;
   const int elem = mode == LV_FP64 ? 8 : 4;

@@ -124,6 +124,10 @@ template <typename D> __device__ __forceinline__ D load_desc(const D* ds, int v)
 // (64 lanes x 16 bytes); float storage with rank R >= kMfmaUpdateRank uses
 // the matrix-core kernel on 128 x 128 tiles.
 constexpr int kUpdateTileRows = 256;
+// Level ranks of a plain view run up to kMaxLevelRank (the factors of the
+// level below the top; LV_RANK_SWITCH covers 1 .. kMaxLevelRank / 2), the
+// top update up to twice that.
+constexpr int kMaxLevelRank = 256;
 constexpr int kMfmaUpdateRank = 32;
 constexpr int kMfmaUpdateTile = 128;
 inline bool update_on_mfma(int R, int elem) { return elem == 4 && R >= kMfmaUpdateRank; }
@@ -233,7 +237,7 @@ hipError_t launch_level_gram(int R, const T* slabU, const T* slabV, int W, int64
                              hipStream_t s);
 hipError_t launch_gram_sum_multi(const GramSumDesc* ds, int nd, int blocks, hipStream_t s);
 
-// Skinny products of level rank R (<= 128) from the bfloat16 shadow S on the
+// Skinny products of level rank R (<= kMaxLevelRank) from the bfloat16 shadow S on the
 // matrix cores (bf16 x bf16 -> fp32): partial X = S U_j, partial Y = S^T V_j
 // over tiles of tile_rows x 256 (partials as for the fused pass, row stride R).
 hipError_t launch_skinny_bf16(int R, const uint16_t* S, int64_t ldp, int64_t n_pad, int tile_rows,
@@ -244,7 +248,7 @@ hipError_t launch_skinny_bf16_multi(int nb, const SkinnyDesc* ds, int nd, int bl
 inline int skinny_blocks_for(int R) { return R <= 32 ? 1 : 2; }   // R <= 64 per launch
 
 // The same products from the float power P (v_mfma_f32_32x32x2f32, float
-// products and accumulation), R <= 128 (32 factor columns per launch; X alone: 64).
+// products and accumulation), R <= kMaxLevelRank (32 factor columns per launch; X alone: 64).
 // update: also apply P += U_j V_j^T in the same pass (one read and one write
 // of P; R = 16 or 32, X and Y both, see skinny_fuses_update).
 hipError_t launch_skinny_f32(int R, const float* P, int64_t ldp, int64_t n_pad, int tile_rows,

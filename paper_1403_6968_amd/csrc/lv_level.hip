@@ -821,6 +821,7 @@ hipError_t launch_prep(const T* U, int64_t ldu, const T* V, int64_t ldv, int64_t
 template <typename T>
 hipError_t launch_level_tail(int R, const T* partX, const T* partY, const double* partG, int nct,
                              int nrt, int ng, int64_t n_pad, T* slabU, T* slabV, int W, hipStream_t s) {
+  if (R == kMaxLevelRank) return tail_r<T, kMaxLevelRank>(partX, partY, partG, nct, nrt, ng, n_pad, slabU, slabV, W, s);
   LV_RANK_SWITCH(R, return (tail_r<T, RR>(partX, partY, partG, nct, nrt, ng, n_pad, slabU, slabV, W, s)))
 }
 
@@ -829,7 +830,8 @@ hipError_t launch_level_update(int R, T* P, int64_t ldp, int64_t n_pad, const T*
                                const T* slabV, int W, hipStream_t s, uint16_t* S, bool split) {
   const T* Uj = slabU;
   const T* Vj = slabV + (W - R);
-  if (R == 256) return update_r<T, 256>(P, ldp, n_pad, Uj, Vj, W, s, S, split);
+  if (R == 2 * kMaxLevelRank) return update_r<T, 2 * kMaxLevelRank>(P, ldp, n_pad, Uj, Vj, W, s, S, split);
+  if (R == kMaxLevelRank) return update_r<T, kMaxLevelRank>(P, ldp, n_pad, Uj, Vj, W, s, S, split);
   LV_RANK_SWITCH(R, return (update_r<T, RR>(P, ldp, n_pad, Uj, Vj, W, s, S, split)))
 }
 
@@ -838,12 +840,17 @@ hipError_t launch_level_gram(int R, const T* slabU, const T* slabV, int W, int64
                              hipStream_t s) {
   const T* Uj = slabU;
   const T* Vj = slabV + (W - R);
+  if (R == kMaxLevelRank) return gram_r<T, kMaxLevelRank>(Uj, Vj, W, n_pad, partG, s);
   LV_RANK_SWITCH(R, return (gram_r<T, RR>(Uj, Vj, W, n_pad, partG, s)))
 }
 
 template <typename T>
 hipError_t launch_gram_multi(int R, const GramDesc<T>* ds, int nd, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
+  if (R == kMaxLevelRank) {
+    hipLaunchKernelGGL((k_gram_multi<T, kMaxLevelRank>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd);
+    return hipGetLastError();
+  }
   LV_RANK_SWITCH(R, hipLaunchKernelGGL((k_gram_multi<T, RR>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd);
                  return hipGetLastError())
 }
@@ -893,14 +900,24 @@ hipError_t launch_gram_sum_multi(const GramSumDesc* ds, int nd, int blocks, hipS
 template <typename T>
 hipError_t launch_tail_multi(int R, const TailDesc<T>* ds, int nd, int blocks, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
+  if (R == kMaxLevelRank) {
+    hipLaunchKernelGGL((k_level_tail_multi<T, kMaxLevelRank>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd);
+    return hipGetLastError();
+  }
   LV_RANK_SWITCH(R, hipLaunchKernelGGL((k_level_tail_multi<T, RR>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd);
                  return hipGetLastError())
 }
 
 template <typename T, bool SH, bool SPLIT>
 hipError_t update_multi_sh(int R, const UpdateDesc<T>* ds, int nd, int blocks, hipStream_t s) {
-  if (R == 256) {
-    hipLaunchKernelGGL((k_level_update_multi<T, 256, SH, SPLIT>), dim3((unsigned)blocks), dim3(256), 0, s, ds, nd);
+  if (R == 2 * kMaxLevelRank) {
+    hipLaunchKernelGGL((k_level_update_multi<T, 2 * kMaxLevelRank, SH, SPLIT>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       ds, nd);
+    return hipGetLastError();
+  }
+  if (R == kMaxLevelRank) {
+    hipLaunchKernelGGL((k_level_update_multi<T, kMaxLevelRank, SH, SPLIT>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       ds, nd);
     return hipGetLastError();
   }
   LV_RANK_SWITCH(R, hipLaunchKernelGGL((k_level_update_multi<T, RR, SH, SPLIT>), dim3((unsigned)blocks), dim3(256), 0,

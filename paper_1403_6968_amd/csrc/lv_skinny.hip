@@ -797,7 +797,7 @@ k_to_bf16(const float* __restrict__ P, uint16_t* __restrict__ S, int64_t count, 
 hipError_t launch_skinny_bf16(int R, const uint16_t* S, int64_t ldp, int64_t n_pad, int tile_rows,
                               const float* slabU, const float* slabV, int W, float* partX, float* partY,
                               hipStream_t s) {
-  if (R < 1 || R > 128 || (R > 64 && R % 64 != 0) || n_pad % TCB != 0 || tile_rows % CRB != 0)
+  if (R < 1 || R > kMaxLevelRank || (R > 64 && R % 64 != 0) || n_pad % TCB != 0 || tile_rows % CRB != 0)
     return hipErrorInvalidValue;
   const int nct = (int)(n_pad / TCB);
   const dim3 grid((unsigned)nct, (unsigned)((n_pad + tile_rows - 1) / tile_rows));
@@ -831,7 +831,7 @@ hipError_t launch_skinny_bf16_multi(int nb, const SkinnyDesc* ds, int nd, int bl
 hipError_t launch_skinny_f32(int R, const float* P, int64_t ldp, int64_t n_pad, int tile_rows,
                              const float* slabU, const float* slabV, int W, float* partX, float* partY,
                              hipStream_t s, int want, bool update) {
-  if (R < 1 || R > 128 || (R > 64 && R % 64 != 0) || n_pad % TCB != 0 || tile_rows % 32 != 0)
+  if (R < 1 || R > kMaxLevelRank || (R > 64 && R % 64 != 0) || n_pad % TCB != 0 || tile_rows % 32 != 0)
     return hipErrorInvalidValue;
   if (update) {
     // one launch over all R columns with the update fused (X and Y both)

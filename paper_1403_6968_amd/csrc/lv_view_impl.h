@@ -22,7 +22,7 @@ inline int64_t next_pow2(int64_t x) { int64_t p = 1; while (p < x) p <<= 1; retu
 constexpr size_t kAlign = 256;
 constexpr int64_t kMaxOrder = 65536;
 constexpr int kMaxK = 1024;
-constexpr int kMaxWidth = 256;   // k * r_pad: width of the top-level factors
+constexpr int kMaxWidth = 2 * kMaxLevelRank;   // k * r_pad: width of the top-level factors
 constexpr int kTileRows = 512;      // default rows per tile of a level pass
 constexpr int kMinTileRows = 256;   // tile rows a level pass may be set to:
 constexpr int kMaxTileRows = 1024;  //   multiples of 64 in [256, 1024]
@@ -88,15 +88,19 @@ struct Layout {
   size_t total = 0;
 };
 
-inline lv_status check_shape(int64_t n, int k, int r_max, lv_mode mode) {
+// wide: a plain float view (FP32 or BF16 shadows, no sums, no general form),
+// whose top factors may be kMaxWidth wide; other views stop at
+// kMaxLevelRank (their level passes take ranks up to kMaxLevelRank / 2).
+inline lv_status check_shape(int64_t n, int k, int r_max, lv_mode mode, bool wide = false) {
   if (mode != LV_FP64 && mode != LV_FP32 && mode != LV_FP32_BF16SHADOW)
     return fail(LV_EINVAL, "unknown mode %d", (int)mode);
   if (n < 1 || n > kMaxOrder) return fail(LV_EINVAL, "n = %lld outside [1, %lld]", (long long)n, (long long)kMaxOrder);
   if (!is_pow2(k) || k > kMaxK) return fail(LV_EINVAL, "k = %d is not a power of two in [1, %d]", k, kMaxK);
   if (r_max < 1) return fail(LV_EINVAL, "r_max = %d < 1", r_max);
   const int64_t width = (int64_t)k * next_pow2(r_max);
-  if (width > kMaxWidth)
-    return fail(LV_EINVAL, "k * r_max (rounded up to a power of two) = %lld exceeds %d", (long long)width, kMaxWidth);
+  const int cap = wide && mode != LV_FP64 ? kMaxWidth : kMaxLevelRank;
+  if (width > cap)
+    return fail(LV_EINVAL, "k * r_max (rounded up to a power of two) = %lld exceeds %d", (long long)width, cap);
   return LV_OK;
 }
 

@@ -61,6 +61,23 @@ def test_footprint_rules(lib):
     assert L.lv_reeval_footprint(0, 1, L.LV_FP32) == 0
 
 
+def test_wide_factor_rules(lib):
+    """Top factors up to 512 columns (k * r_max rounded up) for plain float
+    views only; FP64, sums and allocation-free re-evaluation stop at 256."""
+    from paper_1403_6968_amd import linview as L
+    f = L.lv_view_footprint
+    for mode in (L.LV_FP32, L.LV_FP32_BF16SHADOW):
+        assert f(1000, 16, 32, mode) > f(1000, 16, 16, mode) > 0
+        assert f(1000, 32, 16, mode) > 0
+        assert f(1000, 16, 33, mode) == 0                 # rounds up to 64: width 1024
+    assert f(1000, 16, 16, L.LV_FP64) > 0
+    assert f(1000, 16, 32, L.LV_FP64) == 0
+    assert f(1000, 16, 16, L.LV_FP32, L.LV_WITH_SUMS) > 0
+    assert f(1000, 16, 32, L.LV_FP32, L.LV_WITH_SUMS) == 0
+    assert L.lv_reeval_footprint(1000, 256, L.LV_FP32) > 0
+    assert L.lv_reeval_footprint(1000, 257, L.LV_FP32) == 0
+
+
 def test_create_validation_before_device(lib):
     from paper_1403_6968_amd import linview as L
     h = ctypes.c_void_p()
