@@ -156,14 +156,14 @@ LARGE = [(8192, 16), (4096, 16), (2048, 16), (3000, 16)]
 LARGE_PER_VIEW = (48, 40, 32, 32)
 
 
-def _serve_large(lv, subset, reqs, step_every, ids_out=None):
-    """BF16-shadow server with r_coalesce 16 over the views in subset."""
+def _serve_large(lv, subset, reqs, step_every, rc=16):
+    """BF16-shadow server with r_coalesce rc over the views in subset."""
     import torch
     mode = lv.LV_FP32_BF16SHADOW
-    probe = lv.Server(8 * MiB, mode=mode, r_coalesce=16)
+    probe = lv.Server(8 * MiB, mode=mode, r_coalesce=rc)
     total = sum(probe.view_bytes(LARGE[v][0], LARGE[v][1]) for v in subset)
     probe.close()
-    srv = lv.Server(8 * MiB + total, mode=mode, r_coalesce=16)
+    srv = lv.Server(8 * MiB + total, mode=mode, r_coalesce=rc)
     ids = {}
     for v in subset:
         n, k = LARGE[v]
@@ -187,11 +187,13 @@ def _serve_large(lv, subset, reqs, step_every, ids_out=None):
     return out, st
 
 
-def test_mix_equals_alone_and_oracle_large_shadow():
-    """The serving configuration's mode and coalescing width at realistic
-    orders: bfloat16 shadows, r_coalesce 16, views of n = 2048 .. 8192
-    served together (coalesced ranks up to 16) and each alone with another
-    cadence; both equal the FP64 oracle within 5e-3 and each other."""
+@pytest.mark.parametrize("rc", [16, 32])
+def test_mix_equals_alone_and_oracle_large_shadow(rc):
+    """The serving configuration's mode and coalescing widths at realistic
+    orders: bfloat16 shadows, r_coalesce 16 and 32 (top factors 512 wide),
+    views of n = 2048 .. 8192 served together (coalesced ranks up to rc) and
+    each alone with another cadence; both equal the FP64 oracle within 5e-3
+    and each other."""
     lv = _lv()
     reqs = []
     for v, (n, _) in enumerate(LARGE):
@@ -200,7 +202,7 @@ def test_mix_equals_alone_and_oracle_large_shadow():
             reqs.append((v, U[t, :, 0].astype(np.float32), V[t, :, 0].astype(np.float32)))
     order = synth.rng(44, 5, 9).permutation(len(reqs))
     reqs = [reqs[i] for i in order]
-    mix, st = _serve_large(lv, range(len(LARGE)), reqs, step_every=24)
+    mix, st = _serve_large(lv, range(len(LARGE)), reqs, step_every=24 * rc // 16, rc=rc)
     note(f"large mix stats {st}")
     assert st["submitted"] == st["completed"] == len(reqs)
     assert st["coalesced_updates"] < len(reqs) / 4        # wide coalesced updates
@@ -210,7 +212,7 @@ def test_mix_equals_alone_and_oracle_large_shadow():
         W = np.array([w for vv, _, w in reqs if vv == v], dtype=np.float64)
         A += U.T @ W
         ref = O.reeval(A, k)
-        alone, _ = _serve_large(lv, [v], reqs, step_every=3)
+        alone, _ = _serve_large(lv, [v], reqs, step_every=3, rc=rc)
         worst = 0.0
         for p in ref:
             mr = O.maxrel(mix[v][p], ref[p])
